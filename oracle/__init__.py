@@ -1,0 +1,239 @@
+"""CPU oracle for the DIBR view-synthesis path -- TEST INFRASTRUCTURE ONLY.
+
+Only the test suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It wraps ``fvv_oracle.c`` (plain single-threaded C, built
+with gcc, sharing no code with the HIP library) through ctypes and takes its
+inputs from :mod:`scenegen` objects and numpy arrays.
+
+Steps (see the header of ``fvv_oracle.c`` for the definitions and readings):
+O1 selection, O2 pair matrices, O3 depth decode (Eq. 1), O4 forward splat,
+O5 depth filter, O6 backward fetch + blend, O7 hole fill.  The learned-path
+reference lives in :mod:`oracle.unet`.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fvv_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle_fvv.so")
+EMPTY = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+                               "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class RefCamera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32),
+                ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float),
+                ("R", C.c_float * 9), ("t", C.c_float * 3),
+                ("depth_alpha", C.c_float), ("depth_beta", C.c_float)]
+
+
+class RefPair(C.Structure):
+    _fields_ = [("A", C.c_float * 9), ("a", C.c_float * 3), ("B", C.c_float * 9),
+                ("b", C.c_float * 3), ("sx", C.c_float), ("sy", C.c_float)]
+
+
+class RefSrc(C.Structure):
+    _fields_ = [("depth", C.c_void_p), ("depth_pitch", C.c_int64),
+                ("W", C.c_int32), ("H", C.c_int32), ("rig_index", C.c_int32),
+                ("alpha", C.c_float), ("beta", C.c_float), ("pair", C.POINTER(RefPair))]
+
+
+class RefTex(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("rgb_pitch", C.c_int64),
+                ("depth", C.c_void_p), ("depth_pitch", C.c_int64),
+                ("W", C.c_int32), ("H", C.c_int32),
+                ("alpha", C.c_float), ("beta", C.c_float),
+                ("pair", C.POINTER(RefPair)), ("weight", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        L = C.CDLL(_LIB)
+        P = C.c_void_p
+        L.fvv_ref_select.restype = C.c_int32
+        L.fvv_ref_select.argtypes = [C.POINTER(RefCamera), P, C.c_int32, C.POINTER(RefCamera),
+                                     C.c_int32, P, P]
+        L.fvv_ref_pair.restype = None
+        L.fvv_ref_pair.argtypes = [C.POINTER(RefCamera), C.POINTER(RefCamera), C.POINTER(RefPair)]
+        L.fvv_ref_decode_depth.restype = C.c_float
+        L.fvv_ref_decode_depth.argtypes = [C.c_uint16, C.c_float, C.c_float]
+        L.fvv_ref_splat.restype = None
+        L.fvv_ref_splat.argtypes = [C.POINTER(RefSrc), C.c_int32, C.c_int32, C.c_int32, C.c_float, P]
+        L.fvv_ref_filter.restype = None
+        L.fvv_ref_filter.argtypes = [P, C.c_int32, C.c_int32, C.c_float, P]
+        L.fvv_ref_blend.restype = None
+        L.fvv_ref_blend.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(RefTex), C.c_int32, C.c_float,
+                                    P, P, P]
+        L.fvv_ref_fill.restype = None
+        L.fvv_ref_fill.argtypes = [P, P, P, C.c_int32, C.c_int32, C.c_int32, P]
+        L.fvv_ref_synthesize.restype = C.c_int32
+        L.fvv_ref_synthesize.argtypes = [C.POINTER(RefCamera), C.c_int32, P, P, P, P,
+                                         C.POINTER(RefCamera), C.c_int32, C.c_float, C.c_float,
+                                         C.c_int32, P, P, P, P, P, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def ref_camera(cam) -> RefCamera:
+    w, h, fx, fy, cx, cy, R, t, al, be = cam.as_tuple()
+    return RefCamera(w, h, fx, fy, cx, cy, (C.c_float * 9)(*R), (C.c_float * 3)(*t), al, be)
+
+
+# ---------------------------------------------------------------- O1 / O2 / O3
+def select(rig: Sequence, virt, k: int, present: Optional[Sequence[bool]] = None):
+    """O1: (selected rig indices, double weights)."""
+    n = len(rig)
+    arr = (RefCamera * n)(*[ref_camera(c) for c in rig])
+    pres = None if present is None else np.asarray(present, np.int32)
+    idx = np.zeros(8, np.int32)
+    w = np.zeros(8, np.float64)
+    K = lib().fvv_ref_select(arr, _ptr(pres), n, C.byref(ref_camera(virt)), k, _ptr(idx), _ptr(w))
+    return idx[:K].copy(), w[:K].copy()
+
+
+def pair(src, virt) -> RefPair:
+    """O2: float32 pair matrices for (source, virtual)."""
+    p = RefPair()
+    lib().fvv_ref_pair(C.byref(ref_camera(src)), C.byref(ref_camera(virt)), C.byref(p))
+    return p
+
+
+def pair_arrays(src, virt):
+    p = pair(src, virt)
+    return dict(A=np.array(p.A, np.float32).reshape(3, 3), a=np.array(p.a, np.float32),
+                B=np.array(p.B, np.float32).reshape(3, 3), b=np.array(p.b, np.float32),
+                sx=np.float32(p.sx), sy=np.float32(p.sy))
+
+
+def decode_depth(d: int, alpha: float = 0.0, beta: float = 1.0) -> np.float32:
+    """O3 for one code."""
+    return np.float32(lib().fvv_ref_decode_depth(int(d), alpha, beta))
+
+
+# ---------------------------------------------------------------- O4 .. O7
+def splat(rig, depths, virt, sel, max_fp: float = 4.0) -> np.ndarray:
+    """O4: raw key map (H, W) uint64 from the selected cameras ``sel``."""
+    pairs = [pair(rig[c], virt) for c in sel]
+    depths = [np.ascontiguousarray(d, np.uint16) for d in depths]
+    srcs = (RefSrc * len(sel))()
+    for k, c in enumerate(sel):
+        d = depths[c]
+        srcs[k] = RefSrc(_ptr(d), d.shape[1], d.shape[1], d.shape[0], int(c),
+                         rig[c].depth_alpha, rig[c].depth_beta, C.pointer(pairs[k]))
+    Z = np.empty((virt.height, virt.width), np.uint64)
+    lib().fvv_ref_splat(srcs, len(sel), virt.width, virt.height, max_fp, _ptr(Z))
+    return Z
+
+
+def depth_filter(Z: np.ndarray, tau: float = 0.05) -> np.ndarray:
+    """O5: filtered key map."""
+    Z = np.ascontiguousarray(Z, np.uint64)
+    Zf = np.empty_like(Z)
+    lib().fvv_ref_filter(_ptr(Z), Z.shape[1], Z.shape[0], tau, _ptr(Zf))
+    return Zf
+
+
+def blend(Zf, rig, frames, virt, sel, weights, tau: float = 0.05):
+    """O6: (rgb (H,W,3) uint8, hole (H,W) uint8, depth (H,W) float32)."""
+    Zf = np.ascontiguousarray(Zf, np.uint64)
+    pairs = [pair(rig[c], virt) for c in sel]
+    keep = []
+    texs = (RefTex * len(sel))()
+    for k, c in enumerate(sel):
+        rgb = np.ascontiguousarray(frames[c].rgb, np.uint8)
+        dep = np.ascontiguousarray(frames[c].depth_mm, np.uint16)
+        keep += [rgb, dep]
+        texs[k] = RefTex(_ptr(rgb), rgb.shape[1] * 3, _ptr(dep), dep.shape[1],
+                         dep.shape[1], dep.shape[0], rig[c].depth_alpha, rig[c].depth_beta,
+                         C.pointer(pairs[k]), float(weights[k]))
+    H, W = Zf.shape
+    rgb = np.empty((H, W, 3), np.uint8)
+    hole = np.empty((H, W), np.uint8)
+    dep = np.empty((H, W), np.float32)
+    lib().fvv_ref_blend(_ptr(Zf), W, H, texs, len(sel), tau, _ptr(rgb), _ptr(hole), _ptr(dep))
+    return rgb, hole, dep
+
+
+def fill(rgb, hole, depth, mode: int = 0) -> np.ndarray:
+    """O7: final RGB (H,W,3)."""
+    rgb = np.ascontiguousarray(rgb, np.uint8)
+    hole = np.ascontiguousarray(hole, np.uint8)
+    depth = np.ascontiguousarray(depth, np.float32)
+    out = np.empty_like(rgb)
+    lib().fvv_ref_fill(_ptr(rgb), _ptr(hole), _ptr(depth), rgb.shape[1], rgb.shape[0], mode,
+                       _ptr(out))
+    return out
+
+
+def synthesize(rig, frames, virt, k_nearest: int = 3, tau: float = 0.05, max_fp: float = 4.0,
+               fill_mode: int = 0, taps: bool = False):
+    """O1..O7 for one virtual camera.  ``frames[c]`` may be None (absent).
+    Returns a dict with 'rgb' and, if ``taps``, the per-stage maps."""
+    n = len(rig)
+    cams = (RefCamera * n)(*[ref_camera(c) for c in rig])
+    rgbs, deps = [], []
+    for f in frames:
+        rgbs.append(None if f is None else np.ascontiguousarray(f.rgb, np.uint8))
+        deps.append(None if f is None else np.ascontiguousarray(f.depth_mm, np.uint16))
+    prgb = (C.c_void_p * n)(*[None if a is None else a.ctypes.data for a in rgbs])
+    pdep = (C.c_void_p * n)(*[None if a is None else a.ctypes.data for a in deps])
+    rp = np.array([0 if a is None else a.shape[1] * 3 for a in rgbs], np.int64)
+    dp = np.array([0 if a is None else a.shape[1] for a in deps], np.int64)
+    H, W = virt.height, virt.width
+    out = np.empty((H, W, 3), np.uint8)
+    t = {}
+    if taps:
+        t = dict(z=np.empty((H, W), np.uint64), zf=np.empty((H, W), np.uint64),
+                 blend_rgb=np.empty((H, W, 3), np.uint8), hole=np.empty((H, W), np.uint8),
+                 depth=np.empty((H, W), np.float32))
+    sel = np.zeros(8, np.int32)
+    w = np.zeros(8, np.float64)
+    K = lib().fvv_ref_synthesize(cams, n, C.cast(prgb, C.c_void_p), _ptr(rp),
+                                 C.cast(pdep, C.c_void_p), _ptr(dp),
+                                 C.byref(ref_camera(virt)), k_nearest, tau, max_fp, fill_mode,
+                                 _ptr(out), _ptr(t.get("z")), _ptr(t.get("zf")),
+                                 _ptr(t.get("blend_rgb")), _ptr(t.get("hole")),
+                                 _ptr(t.get("depth")), _ptr(sel), _ptr(w))
+    if K < 0:
+        raise ValueError("oracle rejected the arguments")
+    res = dict(rgb=out, sel=sel[:K].copy(), weights=w[:K].copy())
+    res.update(t)
+    return res
+
+
+def key_depth(Z: np.ndarray) -> np.ndarray:
+    """float32 depth held in the upper half of each key (garbage for EMPTY)."""
+    return (Z >> np.uint64(32)).astype(np.uint32).view(np.float32)
+
+
+def key_cam(Z: np.ndarray) -> np.ndarray:
+    return ((Z >> np.uint64(27)) & np.uint64(31)).astype(np.int32)
+
+
+def key_pixel(Z: np.ndarray) -> np.ndarray:
+    return (Z & np.uint64((1 << 27) - 1)).astype(np.int64)

@@ -1,0 +1,565 @@
+/*
+ * fvv_oracle.c -- TEST INFRASTRUCTURE, NOT PART OF THE PRODUCT.
+ *
+ * A plain, slow, single-threaded CPU reference of the depth-image-based
+ * rendering (DIBR) view-synthesis path of FVV Live (arXiv 2007.00558,
+ * Section VI "View synthesis").  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library; the HIP path never
+ * links, includes or calls it, and it shares no code with the HIP path.
+ *
+ * The paper describes its renderer at block-diagram level only (Section VI):
+ * each reference pixel plus its depth is a 3D point projected into the
+ * virtual camera; cracks are handled by backward warping combined with image
+ * filtering; disocclusions are covered by several reference cameras whose
+ * contributions are mixed according to their distance to the virtual camera
+ * (typically three cameras).  Every constant, tie-break and filter the paper
+ * leaves open is fixed here as an explicit reading (see the step comments);
+ * this file is the definition the GPU path must reproduce.
+ *
+ * Precision.  The paper fixes none.  Where floating point decides a discrete
+ * outcome (which pixel a point lands on, which key wins the z-buffer, whether
+ * a tap is depth-consistent, whether a pixel is a hole) the decision is taken
+ * in IEEE float32, op by op, without fused multiply-add and with correctly
+ * rounded division -- the precision of the kernels, so both sides decide
+ * identically.  Pure value arithmetic (the bilinear and view-weighted colour
+ * blend) is carried in double.  Build: gcc -O2 -ffp-contract=off
+ * -fno-fast-math.
+ *
+ * Steps (names used throughout):
+ *   O1 camera selection and view weights      (Section V-D, Section VI)
+ *   O2 pair matrices                          (Section VI, pinhole geometry)
+ *   O3 depth decode with correction           (Eq. 1, Section IV-A)
+ *   O4 forward splat into a packed-key z-buffer (Section VI, 3D warping)
+ *   O5 3x3 crack / speckle depth filter       (Section VI, "image filtering")
+ *   O6 backward colour fetch and blend        (Section VI, backward warping and mixing)
+ *   O7 background-directed hole fill          (Section VI disocclusions; the
+ *                                              paper leaves them black, Section IX)
+ *
+ * Parity status: O1-O4, O6 and O7 are pinned by closed forms, invariants and
+ * brute force in the CPU test suite.  The O5 filter rule, tau_rel, the
+ * footprint cap and the hole-fill preference are definitions of this build
+ * ("parity unpinned" for their quality: only their stated behaviour on
+ * hand-built cases is checked).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define REF_EMPTY 0xFFFFFFFFFFFFFFFFull
+#define REF_MAXK 8
+
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float R[9];   /* row-major, world -> camera: X_c = R X_w + t */
+    float t[3];
+    float depth_alpha, depth_beta;
+} ref_camera;
+
+/* pair record for one (source, virtual) camera pair, all float32:
+ *   A[9], a[3]  forward  source pixel (i,j,z) -> virtual homogeneous point
+ *   B[9], b[3]  backward virtual pixel (x,y,z) -> source homogeneous point
+ *   sx, sy      focal-length ratios virtual / source                       */
+typedef struct {
+    float A[9], a[3], B[9], b[3], sx, sy;
+} ref_pair;
+
+/* ------------------------------------------------------------------------ */
+/* O1: camera selection and view weights.
+ * The paper transmits the N_Tx cameras closest to the virtual viewpoint
+ * (Section V-D) and renders from typically three of them, mixing their
+ * contributions by distance to the virtual camera (Section VI).
+ * Reading: distance = Euclidean distance between camera centres C = -R^T t
+ * in double; stable order by (distance, rig index); weight = 1/distance; if
+ * the nearest centre is closer than 1e-6 m the virtual camera coincides with
+ * that source and only it is used, with weight 1.
+ * present[c] == 0 removes camera c from the ranking.
+ * Returns the number of selected cameras K (0 if none). */
+static void ref_center(const ref_camera *c, double C[3])
+{
+    for (int r = 0; r < 3; ++r) {
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k)
+            s += (double)c->R[k * 3 + r] * (double)c->t[k];
+        C[r] = -s;
+    }
+}
+
+int fvv_ref_select(const ref_camera *rig, const int32_t *present, int32_t n,
+                   const ref_camera *virt, int32_t k_sel,
+                   int32_t *idx_out, double *w_out)
+{
+    double Cv[3], d[64];
+    int order[64], m = 0;
+    if (n > 64) return -1;
+    ref_center(virt, Cv);
+    for (int c = 0; c < n; ++c) {
+        double Cc[3];
+        if (present && !present[c]) continue;
+        ref_center(&rig[c], Cc);
+        double dx = Cc[0] - Cv[0], dy = Cc[1] - Cv[1], dz = Cc[2] - Cv[2];
+        d[c] = sqrt(dx * dx + dy * dy + dz * dz);
+        order[m++] = c;
+    }
+    /* insertion sort: stable, ties keep the lower rig index first */
+    for (int a = 1; a < m; ++a) {
+        int v = order[a], b = a - 1;
+        while (b >= 0 && d[order[b]] > d[v]) {
+            order[b + 1] = order[b];
+            --b;
+        }
+        order[b + 1] = v;
+    }
+    int K = m < k_sel ? m : k_sel;
+    if (K > REF_MAXK) K = REF_MAXK;
+    if (K > 0 && d[order[0]] < 1e-6) {
+        idx_out[0] = order[0];
+        w_out[0] = 1.0;
+        return 1;
+    }
+    for (int k = 0; k < K; ++k) {
+        idx_out[k] = order[k];
+        w_out[k] = 1.0 / d[order[k]];
+    }
+    return K;
+}
+
+/* ------------------------------------------------------------------------ */
+/* O2: pair matrices.
+ * Pinhole model (Section VI: a pixel is a ray, its depth fixes the point).
+ * With X_c = z K_c^-1 [i,j,1]^T (z = Z-depth) and X_v = R_v R_c^T (X_c - t_c) + t_v:
+ *   K_v X_v = z A [i,j,1]^T + a,  A = K_v R_v R_c^T K_c^-1,  a = K_v (t_v - R_v R_c^T t_c)
+ * and the third component is the depth seen by the virtual camera.  The
+ * backward pair swaps the roles.  Computed in double in a fixed order
+ * (relative rotation, then times K^-1 on the right, then K on the left),
+ * each entry rounded once to float32. */
+static void ref_kmat(const ref_camera *c, double K[9])
+{
+    K[0] = c->fx; K[1] = 0.0;   K[2] = c->cx;
+    K[3] = 0.0;   K[4] = c->fy; K[5] = c->cy;
+    K[6] = 0.0;   K[7] = 0.0;   K[8] = 1.0;
+}
+
+static void ref_kinv(const ref_camera *c, double Ki[9])
+{
+    double fx = c->fx, fy = c->fy;
+    Ki[0] = 1.0 / fx; Ki[1] = 0.0;      Ki[2] = -(double)c->cx / fx;
+    Ki[3] = 0.0;      Ki[4] = 1.0 / fy; Ki[5] = -(double)c->cy / fy;
+    Ki[6] = 0.0;      Ki[7] = 0.0;      Ki[8] = 1.0;
+}
+
+static void ref_mm(const double X[9], const double Y[9], double Z[9])
+{
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k)
+                s += X[r * 3 + k] * Y[k * 3 + c];
+            Z[r * 3 + c] = s;
+        }
+}
+
+/* from camera s (source of the points) to camera d (destination image) */
+static void ref_pair_dir(const ref_camera *s, const ref_camera *d, float M[9], float m[3])
+{
+    double Rrel[9], Ks_inv[9], Kd[9], T1[9], T2[9], trel[3], out[3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; ++k)   /* (R_d R_s^T)[r][c] = sum_k R_d[r][k] R_s[c][k] */
+                acc += (double)d->R[r * 3 + k] * (double)s->R[c * 3 + k];
+            Rrel[r * 3 + c] = acc;
+        }
+    ref_kinv(s, Ks_inv);
+    ref_kmat(d, Kd);
+    ref_mm(Rrel, Ks_inv, T1);
+    ref_mm(Kd, T1, T2);
+    for (int r = 0; r < 3; ++r) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k)
+            acc += Rrel[r * 3 + k] * (double)s->t[k];
+        trel[r] = (double)d->t[r] - acc;
+    }
+    for (int r = 0; r < 3; ++r) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k)
+            acc += Kd[r * 3 + k] * trel[k];
+        out[r] = acc;
+    }
+    for (int e = 0; e < 9; ++e) M[e] = (float)T2[e];
+    for (int e = 0; e < 3; ++e) m[e] = (float)out[e];
+}
+
+void fvv_ref_pair(const ref_camera *src, const ref_camera *virt, ref_pair *p)
+{
+    ref_pair_dir(src, virt, p->A, p->a);
+    ref_pair_dir(virt, src, p->B, p->b);
+    p->sx = (float)((double)virt->fx / (double)src->fx);
+    p->sy = (float)((double)virt->fy / (double)src->fy);
+}
+
+/* ------------------------------------------------------------------------ */
+/* O3: depth decode.  Millimetres -> metres (float32 division by 1000), then
+ * the quadratic correction of Eq. 1, z_post = (alpha z + beta) z, in that
+ * operation order.  Code 0 means no depth.  (0, 1) is an exact identity. */
+float fvv_ref_decode_depth(uint16_t d, float alpha, float beta)
+{
+    float z = (float)d / 1000.0f;
+    float s = alpha * z;
+    s = s + beta;
+    return s * z;
+}
+
+static inline uint32_t ref_fbits(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    return u;
+}
+
+static inline float ref_bitsf(uint32_t u)
+{
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+/* float32 projection of one pixel: p_r = ((M_r0 i + M_r1 j) + M_r2) z + m_r */
+static inline void ref_project(const float M[9], const float m[3], float i, float j,
+                               float z, float p[3])
+{
+    for (int r = 0; r < 3; ++r) {
+        float s = M[r * 3 + 0] * i;
+        float s2 = M[r * 3 + 1] * j;
+        s = s + s2;
+        s = s + M[r * 3 + 2];
+        s = s * z;
+        p[r] = s + m[r];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* O4: forward splat (3D warping of every valid reference pixel into the
+ * virtual view, Section VI) into a z-buffer of packed 64-bit keys
+ *   key = bits32(virtual depth) << 32 | camera rig index << 27 | source pixel index
+ * Smaller key wins: nearer depth first (positive float32 bit patterns order
+ * like the values), then lower camera index, then lower source pixel index.
+ * Footprint (reading): each point covers the pixel centres x with
+ * u - mx/2 <= x < u + mx/2 (same for rows), where mx = clamp((sx z)/p2, 1,
+ * max_fp) is the point's own magnification; a fronto-parallel surface is then
+ * tiled without cracks or overlaps.  Points with p2 <= 0.01 m or non-finite
+ * image coordinates are dropped.
+ * Z must hold W*H keys; it is initialised here. */
+typedef struct {
+    const uint16_t *depth;    /* source depth, millimetres */
+    int64_t depth_pitch;      /* in elements */
+    int32_t W, H, rig_index;
+    float alpha, beta;
+    const ref_pair *pair;
+} ref_src;
+
+void fvv_ref_splat(const ref_src *src, int32_t K, int32_t W, int32_t H,
+                   float max_fp, uint64_t *Z)
+{
+    const float zclip = 0.01f;
+    for (int64_t e = 0; e < (int64_t)W * H; ++e) Z[e] = REF_EMPTY;
+    for (int k = 0; k < K; ++k) {
+        const ref_src *s = &src[k];
+        const ref_pair *p = s->pair;
+        for (int j = 0; j < s->H; ++j) {
+            for (int i = 0; i < s->W; ++i) {
+                uint16_t d = s->depth[(int64_t)j * s->depth_pitch + i];
+                if (d == 0) continue;
+                float z = fvv_ref_decode_depth(d, s->alpha, s->beta);
+                float q[3];
+                ref_project(p->A, p->a, (float)i, (float)j, z, q);
+                if (!(q[2] > zclip)) continue;
+                float u = q[0] / q[2];
+                float v = q[1] / q[2];
+                if (!isfinite(u) || !isfinite(v)) continue;
+                float mx = (p->sx * z) / q[2];
+                float my = (p->sy * z) / q[2];
+                mx = fminf(fmaxf(mx, 1.0f), max_fp);
+                my = fminf(fmaxf(my, 1.0f), max_fp);
+                float hx = 0.5f * mx, hy = 0.5f * my;
+                float x0f = ceilf(u - hx), x1f = ceilf(u + hx) - 1.0f;
+                float y0f = ceilf(v - hy), y1f = ceilf(v + hy) - 1.0f;
+                x0f = fmaxf(x0f, 0.0f);
+                y0f = fmaxf(y0f, 0.0f);
+                x1f = fminf(x1f, (float)(W - 1));
+                y1f = fminf(y1f, (float)(H - 1));
+                if (x0f > x1f || y0f > y1f) continue;
+                uint64_t key = ((uint64_t)ref_fbits(q[2]) << 32)
+                             | ((uint64_t)(uint32_t)s->rig_index << 27)
+                             | (uint64_t)((int64_t)j * s->W + i);
+                for (int y = (int)y0f; y <= (int)y1f; ++y)
+                    for (int x = (int)x0f; x <= (int)x1f; ++x) {
+                        uint64_t *cell = &Z[(int64_t)y * W + x];
+                        if (key < *cell) *cell = key;
+                    }
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* O5: 3x3 depth filter on the key map (the "image filtering" that goes with
+ * backward warping against cracks, Section VI).  Reads Z only.
+ * V = valid keys among the 8 neighbours (outside the image counts as absent),
+ * z(k) = the float32 depth in the key's upper half.
+ *  (a) crack fill: an empty pixel with |V| >= 5 takes the lower median of V
+ *      (element floor((|V|-1)/2) of V sorted by key);
+ *  (b) speckle removal: a valid pixel with |V| >= 5 none of which satisfies
+ *      |z(k) - z0| <= tau z0 takes the lower median of V;
+ *  otherwise the key is kept. */
+static uint64_t ref_lower_median(uint64_t *v, int n)
+{
+    for (int a = 1; a < n; ++a) {
+        uint64_t x = v[a];
+        int b = a - 1;
+        while (b >= 0 && v[b] > x) {
+            v[b + 1] = v[b];
+            --b;
+        }
+        v[b + 1] = x;
+    }
+    return v[(n - 1) / 2];
+}
+
+void fvv_ref_filter(const uint64_t *Z, int32_t W, int32_t H, float tau, uint64_t *Zf)
+{
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            uint64_t c = Z[(int64_t)y * W + x];
+            uint64_t v[8];
+            int n = 0;
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    if (dx == 0 && dy == 0) continue;
+                    int xx = x + dx, yy = y + dy;
+                    if (xx < 0 || yy < 0 || xx >= W || yy >= H) continue;
+                    uint64_t k = Z[(int64_t)yy * W + xx];
+                    if (k != REF_EMPTY) v[n++] = k;
+                }
+            uint64_t out = c;
+            if (n >= 5) {
+                if (c == REF_EMPTY) {
+                    out = ref_lower_median(v, n);
+                } else {
+                    float z0 = ref_bitsf((uint32_t)(c >> 32));
+                    float lim = tau * z0;
+                    int near = 0;
+                    for (int e = 0; e < n; ++e) {
+                        float zk = ref_bitsf((uint32_t)(v[e] >> 32));
+                        if (fabsf(zk - z0) <= lim) near = 1;
+                    }
+                    if (!near) out = ref_lower_median(v, n);
+                }
+            }
+            Zf[(int64_t)y * W + x] = out;
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* O6: backward colour fetch, per-camera depth consistency, view-weighted
+ * blend (backward warping, Section VI; mixing by camera distance).
+ * For each output pixel with a valid filtered key at depth zf, and each
+ * selected camera in selection order:
+ *   q = B [x,y,1] zf + b (float32, as O4), require q2 > 0.01,
+ *   u = q0/q2, v = q1/q2, require -0.5 <= u <= W_c - 0.5 and the same for v
+ *   (the sample lies on the source image's pixel area),
+ *   i0 = floor(u), j0 = floor(v), fu = u - i0, fv = v - j0;
+ *   taps (i0,j0) (i0+1,j0) (i0,j0+1) (i0+1,j0+1) with bilinear weights
+ *   (1-fu)(1-fv), fu(1-fv), (1-fu)fv, fu fv;
+ *   a tap is valid iff it lies inside the image, has depth, and its decoded
+ *   depth zs satisfies |zs - q2| <= tau q2 (float32);
+ *   col_c = sum w_n rgb_n / sum w_n over valid taps (double); the camera is
+ *   dropped when the sum of weights is 0.
+ * out = sum w_c col_c / sum w_c over surviving cameras (double), rounded
+ * half up and capped at 255; no surviving camera => hole.
+ * Outputs: rgb (W*H*3), hole flags (1 = hole), depth (zf, 0 for holes). */
+typedef struct {
+    const uint8_t *rgb;       /* source colour, 3 bytes per pixel */
+    int64_t rgb_pitch;        /* bytes */
+    const uint16_t *depth;
+    int64_t depth_pitch;      /* elements */
+    int32_t W, H;
+    float alpha, beta;
+    const ref_pair *pair;
+    double weight;
+} ref_tex;
+
+void fvv_ref_blend(const uint64_t *Zf, int32_t W, int32_t H, const ref_tex *tex,
+                   int32_t K, float tau, uint8_t *rgb, uint8_t *hole, float *depth_out)
+{
+    const float zclip = 0.01f;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            int64_t o = (int64_t)y * W + x;
+            uint64_t key = Zf[o];
+            rgb[o * 3 + 0] = rgb[o * 3 + 1] = rgb[o * 3 + 2] = 0;
+            hole[o] = 1;
+            depth_out[o] = 0.0f;
+            if (key == REF_EMPTY) continue;
+            float zf = ref_bitsf((uint32_t)(key >> 32));
+            double acc[3] = {0.0, 0.0, 0.0}, wsum = 0.0;
+            for (int k = 0; k < K; ++k) {
+                const ref_tex *t = &tex[k];
+                float q[3];
+                ref_project(t->pair->B, t->pair->b, (float)x, (float)y, zf, q);
+                if (!(q[2] > zclip)) continue;
+                float u = q[0] / q[2];
+                float v = q[1] / q[2];
+                if (!(u >= -0.5f && u <= (float)t->W - 0.5f)) continue;
+                if (!(v >= -0.5f && v <= (float)t->H - 0.5f)) continue;
+                float fi0 = floorf(u), fj0 = floorf(v);
+                float fu = u - fi0, fv = v - fj0;
+                int i0 = (int)fi0, j0 = (int)fj0;
+                float lim = tau * q[2];
+                double wt[4] = {(1.0 - fu) * (1.0 - fv), fu * (1.0 - (double)fv),
+                                (1.0 - fu) * (double)fv, (double)fu * (double)fv};
+                int ti[4] = {i0, i0 + 1, i0, i0 + 1};
+                int tj[4] = {j0, j0, j0 + 1, j0 + 1};
+                double cacc[3] = {0.0, 0.0, 0.0}, csum = 0.0;
+                for (int n = 0; n < 4; ++n) {
+                    if (ti[n] < 0 || tj[n] < 0 || ti[n] >= t->W || tj[n] >= t->H) continue;
+                    uint16_t d = t->depth[(int64_t)tj[n] * t->depth_pitch + ti[n]];
+                    if (d == 0) continue;
+                    float zs = fvv_ref_decode_depth(d, t->alpha, t->beta);
+                    if (!(fabsf(zs - q[2]) <= lim)) continue;
+                    const uint8_t *px = t->rgb + (int64_t)tj[n] * t->rgb_pitch + (int64_t)ti[n] * 3;
+                    for (int ch = 0; ch < 3; ++ch) cacc[ch] += wt[n] * (double)px[ch];
+                    csum += wt[n];
+                }
+                if (!(csum > 0.0)) continue;
+                for (int ch = 0; ch < 3; ++ch) acc[ch] += t->weight * (cacc[ch] / csum);
+                wsum += t->weight;
+            }
+            if (!(wsum > 0.0)) continue;
+            for (int ch = 0; ch < 3; ++ch) {
+                double val = floor(acc[ch] / wsum + 0.5);
+                if (val > 255.0) val = 255.0;
+                if (val < 0.0) val = 0.0;
+                rgb[o * 3 + ch] = (uint8_t)val;
+            }
+            hole[o] = 0;
+            depth_out[o] = zf;
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* O7: hole fill.  The paper leaves areas no camera sees black (Section IX);
+ * mode 1 reproduces that.  Mode 0 (reading; disocclusions uncover
+ * background): for every hole, the nearest non-hole pixel to the left,
+ * right, up and down of the blend output; the candidate with the largest
+ * depth wins, then the nearest, then the order left, right, up, down; its
+ * colour is copied.  No candidate => black.  Reads the blend output only. */
+void fvv_ref_fill(const uint8_t *rgb, const uint8_t *hole, const float *depth,
+                  int32_t W, int32_t H, int32_t mode, uint8_t *out)
+{
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            int64_t o = (int64_t)y * W + x;
+            if (!hole[o]) {
+                memcpy(out + o * 3, rgb + o * 3, 3);
+                continue;
+            }
+            out[o * 3 + 0] = out[o * 3 + 1] = out[o * 3 + 2] = 0;
+            if (mode != 0) continue;
+            int best = -1, best_dist = 0;
+            float best_z = 0.0f;
+            int64_t best_o = 0;
+            const int dxs[4] = {-1, 1, 0, 0}, dys[4] = {0, 0, -1, 1};
+            for (int dir = 0; dir < 4; ++dir) {
+                int xx = x, yy = y, dist = 0;
+                for (;;) {
+                    xx += dxs[dir];
+                    yy += dys[dir];
+                    ++dist;
+                    if (xx < 0 || yy < 0 || xx >= W || yy >= H) { dist = -1; break; }
+                    if (!hole[(int64_t)yy * W + xx]) break;
+                }
+                if (dist < 0) continue;
+                int64_t co = (int64_t)yy * W + xx;
+                float cz = depth[co];
+                int better = 0;
+                if (best < 0) better = 1;
+                else if (cz > best_z) better = 1;
+                else if (cz == best_z && dist < best_dist) better = 1;
+                if (better) {
+                    best = dir;
+                    best_z = cz;
+                    best_dist = dist;
+                    best_o = co;
+                }
+            }
+            if (best >= 0) memcpy(out + o * 3, rgb + best_o * 3, 3);
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Whole path: O1 .. O7 for one virtual view.
+ * views_rgb[c] / views_depth[c] may be NULL for a camera absent from the
+ * frame set.  Optional taps (may be NULL): Z (raw splat), Zf (filtered),
+ * blend rgb / hole / depth before the fill.  Returns K (selected cameras) or
+ * a negative number on bad arguments. */
+int32_t fvv_ref_synthesize(const ref_camera *rig, int32_t n,
+                           const uint8_t *const *views_rgb, const int64_t *rgb_pitch,
+                           const uint16_t *const *views_depth, const int64_t *depth_pitch,
+                           const ref_camera *virt, int32_t k_sel, float tau, float max_fp,
+                           int32_t fill_mode, uint8_t *out_rgb,
+                           uint64_t *tap_z, uint64_t *tap_zf, uint8_t *tap_rgb,
+                           uint8_t *tap_hole, float *tap_depth,
+                           int32_t *sel_out, double *w_out)
+{
+    if (n < 1 || n > 32 || k_sel < 1) return -1;
+    int32_t present[64], idx[REF_MAXK];
+    double w[REF_MAXK];
+    for (int c = 0; c < n; ++c) present[c] = views_rgb[c] != NULL && views_depth[c] != NULL;
+    int K = fvv_ref_select(rig, present, n, virt, k_sel, idx, w);
+    int32_t W = virt->width, H = virt->height;
+    int64_t npx = (int64_t)W * H;
+    uint64_t *Z = tap_z ? tap_z : (uint64_t *)malloc(npx * 8);
+    uint64_t *Zf = tap_zf ? tap_zf : (uint64_t *)malloc(npx * 8);
+    uint8_t *rgb = tap_rgb ? tap_rgb : (uint8_t *)malloc(npx * 3);
+    uint8_t *hole = tap_hole ? tap_hole : (uint8_t *)malloc(npx);
+    float *dep = tap_depth ? tap_depth : (float *)malloc(npx * 4);
+    ref_pair pairs[REF_MAXK];
+    ref_src srcs[REF_MAXK];
+    ref_tex texs[REF_MAXK];
+    for (int k = 0; k < K; ++k) {
+        const ref_camera *c = &rig[idx[k]];
+        fvv_ref_pair(c, virt, &pairs[k]);
+        srcs[k].depth = views_depth[idx[k]];
+        srcs[k].depth_pitch = depth_pitch[idx[k]];
+        srcs[k].W = c->width;
+        srcs[k].H = c->height;
+        srcs[k].rig_index = idx[k];
+        srcs[k].alpha = c->depth_alpha;
+        srcs[k].beta = c->depth_beta;
+        srcs[k].pair = &pairs[k];
+        texs[k].rgb = views_rgb[idx[k]];
+        texs[k].rgb_pitch = rgb_pitch[idx[k]];
+        texs[k].depth = views_depth[idx[k]];
+        texs[k].depth_pitch = depth_pitch[idx[k]];
+        texs[k].W = c->width;
+        texs[k].H = c->height;
+        texs[k].alpha = c->depth_alpha;
+        texs[k].beta = c->depth_beta;
+        texs[k].pair = &pairs[k];
+        texs[k].weight = w[k];
+        if (sel_out) sel_out[k] = idx[k];
+        if (w_out) w_out[k] = w[k];
+    }
+    fvv_ref_splat(srcs, K, W, H, max_fp, Z);
+    fvv_ref_filter(Z, W, H, tau, Zf);
+    fvv_ref_blend(Zf, W, H, texs, K, tau, rgb, hole, dep);
+    fvv_ref_fill(rgb, hole, dep, W, H, fill_mode, out_rgb);
+    if (!tap_z) free(Z);
+    if (!tap_zf) free(Zf);
+    if (!tap_rgb) free(rgb);
+    if (!tap_hole) free(hole);
+    if (!tap_depth) free(dep);
+    return K;
+}
