@@ -1,0 +1,190 @@
+/*
+ * fvv.h -- C ABI of the MI355X (gfx950) view-synthesis library libfvv.so.
+ *
+ * The library renders a virtual view from multiview-plus-depth (MVD) frames
+ * of N calibrated cameras by depth-image-based rendering, the edge-server
+ * stage of FVV Live (arXiv 2007.00558, Section VI "View synthesis"):
+ * the input is colour plus depth from calibrated cameras (Sections III-IV),
+ * the user moves a virtual camera continuously (Section VIII), and the output
+ * is the image that camera sees, built from the few nearest reference
+ * cameras (Section VI).
+ *
+ * Conventions
+ *  - Every function returns an int32_t status: FVV_OK (0) or a negative
+ *    FVV_E_* code; fvv_last_error() then describes the failure.  No C++
+ *    exception crosses this boundary.
+ *  - Pinhole cameras without distortion, OpenCV axes (x right, y down,
+ *    z forward), world -> camera X_c = R X_w + t, pixel centres at integer
+ *    coordinates, depth = Z-depth along the optical axis in millimetres
+ *    (uint16, 0 = no depth).
+ *  - Colour is packed RGB8 (3 bytes per pixel, R first).  Pitches are in
+ *    bytes and must be at least width*3 (colour) or width*2 (depth).
+ *  - Pointers marked "host or device" are interpreted according to the
+ *    mem_kind argument of the call.  Device pointers must be addresses in
+ *    the context's GPU (for example a torch tensor's data_ptr()).
+ *  - stream is a hipStream_t (NULL = the default stream).  Device-memory
+ *    calls are asynchronous on that stream: the caller keeps its buffers
+ *    alive and unchanged until the stream has passed the call.  Host-memory
+ *    calls return after the data has been consumed (upload) or written
+ *    (synthesis).
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef FVV_H
+#define FVV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FVV_ABI_VERSION 1
+
+/* status codes */
+enum {
+    FVV_OK = 0,
+    FVV_E_ARG = -1,          /* null / short / out-of-range argument */
+    FVV_E_STATE = -2,        /* call out of order: no rig, no frame, stale version */
+    FVV_E_NOMEM = -3,        /* device allocation failed or memory budget exceeded */
+    FVV_E_DEVICE = -4,       /* HIP runtime error (text in fvv_last_error) */
+    FVV_E_AGAIN = -5,        /* not ready yet / admission refused; retry later */
+    FVV_E_UNSUPPORTED = -6   /* valid request this build does not implement */
+};
+
+enum { FVV_MEM_HOST = 0, FVV_MEM_DEVICE = 1 };
+enum { FVV_FILL_BG = 0, FVV_FILL_NONE = 1 };
+enum { FVV_PATH_PLAIN = 0, FVV_PATH_LEARNED = 1 };
+
+/* limits */
+#define FVV_MAX_CAMERAS 32          /* rig size; the camera index fits 5 key bits */
+#define FVV_MAX_K 8                 /* cameras blended per view */
+#define FVV_MAX_SRC_PIXELS (1 << 27) /* width*height of a source camera (27 key bits) */
+#define FVV_MAX_OUT_DIM 8192        /* output width and height */
+
+typedef struct fvv_ctx fvv_ctx;
+
+/* One calibrated camera (Section VII: multi-camera calibration).
+ * depth_alpha / depth_beta are the per-camera depth-correction coefficients of
+ * Eq. (1), z_post = (alpha z + beta) z; (0, 1) leaves depth unchanged.  They
+ * are ignored for virtual cameras. */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float R[9];     /* row-major rotation, world -> camera */
+    float t[3];     /* translation, metres */
+    float depth_alpha, depth_beta;
+} fvv_camera;
+
+/* One camera's MVD frame.  rgb: height rows of width*3 bytes; depth_mm:
+ * height rows of width uint16 millimetres (0 = no depth).  Both NULL marks the
+ * camera as absent from this frame set: it is then never selected. */
+typedef struct {
+    const void *rgb;
+    int64_t rgb_pitch;
+    const void *depth_mm;
+    int64_t depth_pitch;
+} fvv_view;
+
+/* Synthesis parameters.  Zero-initialised fields take the defaults shown. */
+typedef struct {
+    int32_t k_nearest;      /* cameras blended per view (default 3, Section VI:
+                               typically three; at most FVV_MAX_K) */
+    float tau_rel;          /* relative depth tolerance of the consistency tests
+                               (default 0.05) */
+    float max_footprint;    /* splat footprint cap in output pixels (default 4) */
+    int32_t fill_mode;      /* FVV_FILL_BG (default) or FVV_FILL_NONE (holes
+                               stay black, as in the paper's system, Section IX) */
+    int32_t path;           /* FVV_PATH_PLAIN; FVV_PATH_LEARNED is not built
+                               (returns FVV_E_UNSUPPORTED) */
+    int32_t reserved;       /* must be 0 */
+    uint64_t frame_version; /* 0 = latest uploaded frame set, else that version
+                               if it is still resident (the two most recent) */
+} fvv_synth_params;
+
+/* ABI version of the loaded library (FVV_ABI_VERSION it was built with). */
+int32_t fvv_abi_version(void);
+
+/* Create a context on HIP device hip_device.  mem_budget_bytes caps the
+ * device memory the context may allocate (0 = no cap).  *out receives the
+ * context; it owns every device buffer it allocates (frame store, per-view
+ * workspaces). */
+int32_t fvv_create(int32_t hip_device, uint64_t mem_budget_bytes, fvv_ctx **out);
+
+/* Destroy a context; waits for its outstanding work.  NULL is a no-op. */
+void fvv_destroy(fvv_ctx *ctx);
+
+/* Text of the last failure on ctx (or of the last failed fvv_create when ctx
+ * is NULL).  Valid until the next call on ctx. */
+const char *fvv_last_error(const fvv_ctx *ctx);
+
+/* Set the camera rig: n (1..FVV_MAX_CAMERAS) calibrated cameras.  Copies the
+ * array.  Rejects non-finite values, fx/fy <= 0, R not orthonormal within
+ * 1e-4, width*height outside 1..FVV_MAX_SRC_PIXELS.  Changing the rig drops
+ * resident frame sets (FVV_E_STATE until the next upload). */
+int32_t fvv_set_rig(fvv_ctx *ctx, const fvv_camera *cams, int32_t n);
+
+/* Upload one MVD frame set: views[c] for every rig camera c (n must equal the
+ * rig size).  mem_kind says whether the view pointers are host or device
+ * memory.  The data are copied into the context's frame store (double
+ * buffered: the two most recent sets stay resident), colour repacked to
+ * 4-byte texels and depth decoded with the camera's Eq. (1) correction.
+ * *out_version (may be NULL) receives the new set's version (1, 2, ...). */
+int32_t fvv_upload_mvd(fvv_ctx *ctx, const fvv_view *views, int32_t n, int32_t mem_kind,
+                       void *stream, uint64_t *out_version);
+
+/* Render one virtual camera into out_rgb8 (height rows of width*3 bytes,
+ * pitch out_pitch; host or device per mem_kind).  Steps, all on the GPU:
+ * select the k nearest cameras and their distance weights, forward-splat
+ * their valid pixels into a z-buffer of packed (depth, camera, pixel) keys,
+ * 3x3 crack/speckle filter, depth-consistent backward colour fetch and
+ * view-weighted blend, hole fill (Section VI). */
+int32_t fvv_synthesize(fvv_ctx *ctx, const fvv_camera *virt, const fvv_synth_params *params,
+                       void *out_rgb8, int64_t out_pitch, int32_t mem_kind, void *stream);
+
+/* Render n_views virtual cameras against the same frame set in one batched
+ * launch sequence.  outs[v] / pitches[v] as out_rgb8 / out_pitch above. */
+int32_t fvv_synthesize_batch(fvv_ctx *ctx, const fvv_camera *virts, int32_t n_views,
+                             const fvv_synth_params *params, void *const *outs,
+                             const int64_t *pitches, int32_t mem_kind, void *stream);
+
+/* Host-only helpers (no device, no context): the camera selection and the
+ * float32 pair matrices the kernels use, exposed for inspection and tests.
+ * fvv_select_cameras: rank the present cameras (present may be NULL = all) by
+ * centre distance to virt, write up to k rig indices to idx and their weights
+ * 1/distance to w; a virtual camera within 1e-6 m of a source selects that
+ * source alone with weight 1.  Returns the count (>= 0) or FVV_E_ARG.
+ * fvv_pair_matrices: out[26] = A[9] a[3] B[9] b[3] sx sy, the forward
+ * (source pixel -> virtual) and backward maps of the pinhole pair. */
+int32_t fvv_select_cameras(const fvv_camera *rig, const int32_t *present, int32_t n,
+                           const fvv_camera *virt, int32_t k, int32_t *idx, float *w);
+int32_t fvv_pair_matrices(const fvv_camera *src, const fvv_camera *virt, float *out26);
+
+/* Debug taps for stage-by-stage checking.  fvv_set_debug(ctx, 1) makes the
+ * next synthesis keep, for its first view, the raw and filtered z-buffers and
+ * the blend result before hole filling; fvv_debug_read copies one of them to
+ * host memory (bytes must equal the tap's size):
+ *   FVV_TAP_Z_RAW, FVV_TAP_Z_FILT: uint64 key per output pixel,
+ *     key = float32 depth bits << 32 | camera << 27 | source pixel index,
+ *     0xFFFFFFFFFFFFFFFF = empty;
+ *   FVV_TAP_BLEND: uint32 RGBA8 per pixel, A = 255 covered, 0 hole;
+ *   FVV_TAP_DEPTH: float32 depth per pixel (0 for holes). */
+enum { FVV_TAP_Z_RAW = 0, FVV_TAP_Z_FILT = 1, FVV_TAP_BLEND = 2, FVV_TAP_DEPTH = 3 };
+int32_t fvv_set_debug(fvv_ctx *ctx, int32_t enable);
+int32_t fvv_debug_read(fvv_ctx *ctx, int32_t tap, void *host_out, int64_t bytes);
+
+/* Stage timing (tracing).  With profiling on, every kernel the context
+ * launches is bracketed by HIP events on the caller's stream (this adds a
+ * little launch overhead).  fvv_profile_read synchronises on the recorded
+ * events and writes, per stage, the summed kernel time in milliseconds and
+ * the number of launches since the last reset (n >= fvv_stage_count()).
+ * fvv_stage_name gives a stage's name (NULL if out of range). */
+int32_t fvv_set_profiling(fvv_ctx *ctx, int32_t enable);
+int32_t fvv_stage_count(void);
+const char *fvv_stage_name(int32_t stage);
+int32_t fvv_profile_read(fvv_ctx *ctx, double *total_ms, int64_t *launches, int32_t n, int32_t reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FVV_H */

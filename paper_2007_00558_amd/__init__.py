@@ -1,0 +1,272 @@
+"""Python binding of libfvv.so, the MI355X DIBR view-synthesis library.
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels (see ``include/fvv.h`` for the ABI).  Device buffers and streams come
+from PyTorch (``tensor.data_ptr()``, ``torch.cuda.current_stream()``); host
+buffers may be numpy arrays.  The library must have been built in-tree
+(``python -m paper_2007_00558_amd.build``); importing the binding without it
+raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libfvv.so")
+
+FVV_OK, FVV_E_ARG, FVV_E_STATE, FVV_E_NOMEM, FVV_E_DEVICE, FVV_E_AGAIN, FVV_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+MEM_HOST, MEM_DEVICE = 0, 1
+FILL_BG, FILL_NONE = 0, 1
+PATH_PLAIN, PATH_LEARNED = 0, 1
+TAP_Z_RAW, TAP_Z_FILT, TAP_BLEND, TAP_DEPTH = 0, 1, 2, 3
+KEY_EMPTY = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+ERROR_NAMES = {0: "FVV_OK", -1: "FVV_E_ARG", -2: "FVV_E_STATE", -3: "FVV_E_NOMEM",
+               -4: "FVV_E_DEVICE", -5: "FVV_E_AGAIN", -6: "FVV_E_UNSUPPORTED"}
+
+
+class FvvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Camera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32),
+                ("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float),
+                ("R", C.c_float * 9), ("t", C.c_float * 3),
+                ("depth_alpha", C.c_float), ("depth_beta", C.c_float)]
+
+
+class View(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("rgb_pitch", C.c_int64),
+                ("depth_mm", C.c_void_p), ("depth_pitch", C.c_int64)]
+
+
+class SynthParams(C.Structure):
+    _fields_ = [("k_nearest", C.c_int32), ("tau_rel", C.c_float), ("max_footprint", C.c_float),
+                ("fill_mode", C.c_int32), ("path", C.c_int32), ("reserved", C.c_int32),
+                ("frame_version", C.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfvv.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2007_00558_amd.build` (no fallback path exists)")
+        L = C.CDLL(LIB_PATH)
+        P, I32, I64, U64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+        sig = {
+            "fvv_abi_version": (I32, []),
+            "fvv_create": (I32, [I32, U64, C.POINTER(P)]),
+            "fvv_destroy": (None, [P]),
+            "fvv_last_error": (C.c_char_p, [P]),
+            "fvv_set_rig": (I32, [P, C.POINTER(Camera), I32]),
+            "fvv_upload_mvd": (I32, [P, C.POINTER(View), I32, I32, P, C.POINTER(U64)]),
+            "fvv_synthesize": (I32, [P, C.POINTER(Camera), C.POINTER(SynthParams), P, I64, I32, P]),
+            "fvv_synthesize_batch": (I32, [P, C.POINTER(Camera), I32, C.POINTER(SynthParams), P, P, I32, P]),
+            "fvv_select_cameras": (I32, [C.POINTER(Camera), P, I32, C.POINTER(Camera), I32, P, P]),
+            "fvv_pair_matrices": (I32, [C.POINTER(Camera), C.POINTER(Camera), P]),
+            "fvv_set_debug": (I32, [P, I32]),
+            "fvv_debug_read": (I32, [P, I32, P, I64]),
+            "fvv_set_profiling": (I32, [P, I32]),
+            "fvv_stage_count": (I32, []),
+            "fvv_stage_name": (C.c_char_p, [I32]),
+            "fvv_profile_read": (I32, [P, P, P, I32, I32]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("fvv_abi_version", "fvv_create", "fvv_destroy", "fvv_last_error", "fvv_set_rig",
+            "fvv_upload_mvd", "fvv_synthesize", "fvv_synthesize_batch", "fvv_select_cameras",
+            "fvv_pair_matrices", "fvv_set_debug", "fvv_debug_read", "fvv_set_profiling",
+            "fvv_stage_count", "fvv_stage_name", "fvv_profile_read")
+
+
+def camera(cam) -> Camera:
+    """Marshal a camera (any object with ``as_tuple()`` in boundary order, or a Camera)."""
+    if isinstance(cam, Camera):
+        return cam
+    w, h, fx, fy, cx, cy, R, t, al, be = cam.as_tuple()
+    return Camera(w, h, fx, fy, cx, cy, (C.c_float * 9)(*R), (C.c_float * 3)(*t), al, be)
+
+
+def params(k_nearest=3, tau_rel=0.05, max_footprint=4.0, fill_mode=FILL_BG, path=PATH_PLAIN,
+           frame_version=0) -> SynthParams:
+    return SynthParams(k_nearest, tau_rel, max_footprint, fill_mode, path, 0, frame_version)
+
+
+def _addr(a) -> int:
+    """Address of a numpy array or torch tensor."""
+    if a is None:
+        return 0
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()
+
+
+def _pitch(a, row_elems_bytes: int) -> int:
+    if isinstance(a, np.ndarray):
+        return a.strides[0]
+    return a.stride(0) * a.element_size()
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def select_cameras(rig: Sequence, virt, k: int, present=None):
+    """Host-only selection: (rig indices, float32 weights)."""
+    n = len(rig)
+    arr = (Camera * n)(*[camera(c) for c in rig])
+    pres = None if present is None else np.ascontiguousarray(present, np.int32)
+    idx = np.zeros(8, np.int32)
+    w = np.zeros(8, np.float32)
+    K = lib().fvv_select_cameras(arr, _addr(pres) or None, n, C.byref(camera(virt)), k,
+                                 idx.ctypes.data, w.ctypes.data)
+    if K < 0:
+        raise FvvError(K, "fvv_select_cameras rejected its arguments")
+    return idx[:K].copy(), w[:K].copy()
+
+
+def pair_matrices(src, virt):
+    out = np.zeros(26, np.float32)
+    rc = lib().fvv_pair_matrices(C.byref(camera(src)), C.byref(camera(virt)), out.ctypes.data)
+    if rc:
+        raise FvvError(rc, "fvv_pair_matrices rejected its arguments")
+    return dict(A=out[0:9].reshape(3, 3), a=out[9:12], B=out[12:21].reshape(3, 3), b=out[21:24],
+                sx=out[24], sy=out[25])
+
+
+class Context:
+    """One library context on one HIP device."""
+
+    def __init__(self, device: int = 0, mem_budget: int = 0):
+        self._L = lib()
+        h = C.c_void_p()
+        rc = self._L.fvv_create(device, mem_budget, C.byref(h))
+        if rc:
+            raise FvvError(rc, self._L.fvv_last_error(None).decode())
+        self._h = h
+        self.device = device
+        self.rig = []
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.fvv_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, rc: int):
+        if rc != FVV_OK:
+            raise FvvError(rc, self._L.fvv_last_error(self._h).decode())
+        return rc
+
+    def last_error(self) -> str:
+        return self._L.fvv_last_error(self._h).decode()
+
+    def set_rig(self, cams: Sequence):
+        arr = (Camera * len(cams))(*[camera(c) for c in cams])
+        self._check(self._L.fvv_set_rig(self._h, arr, len(cams)))
+        self.rig = list(cams)
+
+    def upload_mvd(self, frames: Sequence, mem: int = MEM_HOST, stream=None) -> int:
+        """frames[c] = (rgb (H,W,3) uint8, depth (H,W) uint16) -- numpy for
+        MEM_HOST, torch CUDA tensors for MEM_DEVICE -- or None if absent."""
+        n = len(frames)
+        views = (View * n)()
+        keep = []
+        for k, f in enumerate(frames):
+            if f is None:
+                views[k] = View(None, 0, None, 0)
+                continue
+            rgb, dep = (f.rgb, f.depth_mm) if hasattr(f, "rgb") else f
+            if mem == MEM_HOST:
+                rgb = np.ascontiguousarray(rgb, np.uint8)
+                dep = np.ascontiguousarray(dep, np.uint16)
+            keep += [rgb, dep]
+            views[k] = View(_addr(rgb), _pitch(rgb, 0), _addr(dep), _pitch(dep, 0))
+        ver = C.c_uint64(0)
+        s = None if mem == MEM_HOST and stream is None else _stream_handle(stream)
+        self._check(self._L.fvv_upload_mvd(self._h, views, n, mem, s, C.byref(ver)))
+        return ver.value
+
+    def synthesize(self, virt, out=None, p: Optional[SynthParams] = None, stream=None):
+        """Render one view.  out=None -> new numpy (H,W,3) uint8 via host mode;
+        a torch CUDA tensor -> device mode on ``stream`` (default: current)."""
+        p = p or params()
+        vc = camera(virt)
+        if out is None:
+            out = np.empty((vc.height, vc.width, 3), np.uint8)
+        if isinstance(out, np.ndarray):
+            assert out.flags.c_contiguous and out.dtype == np.uint8
+            self._check(self._L.fvv_synthesize(self._h, C.byref(vc), C.byref(p), out.ctypes.data,
+                                               out.strides[0], MEM_HOST, None))
+        else:
+            self._check(self._L.fvv_synthesize(self._h, C.byref(vc), C.byref(p), out.data_ptr(),
+                                               out.stride(0), MEM_DEVICE, _stream_handle(stream)))
+        return out
+
+    def synthesize_batch(self, virts: Sequence, outs: Sequence, p: Optional[SynthParams] = None,
+                         stream=None):
+        p = p or params()
+        n = len(virts)
+        arr = (Camera * n)(*[camera(v) for v in virts])
+        ptrs = (C.c_void_p * n)(*[_addr(o) for o in outs])
+        dev = not isinstance(outs[0], np.ndarray)
+        pitches = np.array([o.stride(0) if dev else o.strides[0] for o in outs], np.int64)
+        s = _stream_handle(stream) if dev else None
+        self._check(self._L.fvv_synthesize_batch(self._h, arr, n, C.byref(p), C.cast(ptrs, C.c_void_p),
+                                                 pitches.ctypes.data, MEM_DEVICE if dev else MEM_HOST, s))
+        return outs
+
+    def set_debug(self, on: bool = True):
+        self._check(self._L.fvv_set_debug(self._h, 1 if on else 0))
+
+    def set_profiling(self, on: bool = True):
+        self._check(self._L.fvv_set_profiling(self._h, 1 if on else 0))
+
+    def profile(self, reset: bool = True) -> dict:
+        """{stage name: (total kernel ms, launches)} since the last reset."""
+        n = self._L.fvv_stage_count()
+        ms = np.zeros(n, np.float64)
+        cnt = np.zeros(n, np.int64)
+        self._check(self._L.fvv_profile_read(self._h, ms.ctypes.data, cnt.ctypes.data, n, 1 if reset else 0))
+        return {self._L.fvv_stage_name(k).decode(): (float(ms[k]), int(cnt[k])) for k in range(n)}
+
+    def debug_read(self, tap: int, shape):
+        dtype = {TAP_Z_RAW: np.uint64, TAP_Z_FILT: np.uint64, TAP_BLEND: np.uint32,
+                 TAP_DEPTH: np.float32}[tap]
+        a = np.empty(shape, dtype)
+        self._check(self._L.fvv_debug_read(self._h, tap, a.ctypes.data, a.nbytes))
+        return a

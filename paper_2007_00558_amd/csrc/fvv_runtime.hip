@@ -1,0 +1,732 @@
+// fvv_runtime.hip -- host runtime behind the C ABI of libfvv.so (include/fvv.h).
+//
+// Owns the device state of one context: the rig, a double-buffered frame
+// store of repacked MVD frames, per-view workspaces, view descriptors and
+// debug taps.  Camera selection and the pair matrices are computed here in
+// double and handed to the kernels as float32 (Section VI: the pinhole warp
+// and the mix by camera distance).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/fvv.h"
+#include "fvv_internal.h"
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+struct FrameSlot {
+    uint64_t version = 0;                 // 0 = empty
+    std::vector<uint32_t *> rgba;         // per camera, null if absent
+    std::vector<float *> depth;
+    std::vector<int32_t> present;
+    hipEvent_t ready = nullptr;           // recorded after the repack
+    hipEvent_t last_use = nullptr;        // recorded after each synthesis reading it
+    bool used = false;
+};
+
+}  // namespace
+
+struct fvv_ctx {
+    int device = 0;
+    uint64_t budget = 0;     // 0 = unlimited
+    uint64_t allocated = 0;
+    std::string err;
+    std::vector<fvv_camera> rig;
+    FrameSlot slots[2];
+    int latest = -1;
+    uint64_t next_version = 1;
+    // upload staging: raw RGB8 + uint16 planes of all cameras
+    uint8_t *staging = nullptr;
+    size_t staging_bytes = 0;
+    hipEvent_t staging_free = nullptr;
+    // per-view workspace (keys, blend, slots, column summaries, host-mode output)
+    uint8_t *ws = nullptr;
+    size_t ws_bytes = 0;
+    // view descriptors: device array + pinned host ring
+    fvv_view_desc *d_desc = nullptr;
+    size_t desc_cap = 0;     // views
+    static constexpr int kRing = 4;
+    fvv_view_desc *h_desc[kRing] = {nullptr, nullptr, nullptr, nullptr};
+    size_t h_desc_cap = 0;
+    hipEvent_t h_desc_ev[kRing] = {nullptr, nullptr, nullptr, nullptr};
+    bool h_desc_ev_live[kRing] = {false, false, false, false};
+    int ring = 0;
+    // debug taps of view 0 of the last synthesis
+    bool debug = false;
+    unsigned long long *dbg_zf = nullptr;
+    float *dbg_depth = nullptr;
+    size_t dbg_px = 0;
+    int64_t last_px = 0;
+    unsigned long long *last_z = nullptr;
+    uint32_t *last_rgba = nullptr;
+    bool have_taps = false;
+    // stage timing
+    bool profiling = false;
+    fvv_prof prof;
+};
+
+namespace {
+
+int32_t fail(fvv_ctx *c, int32_t code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c)
+        c->err = buf;
+    else
+        g_create_error = buf;
+    return code;
+}
+
+#define HIPCHECK(ctx, expr)                                                                       \
+    do {                                                                                          \
+        hipError_t e_ = (expr);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail((ctx), FVV_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+int32_t dalloc(fvv_ctx *c, void **p, size_t bytes)
+{
+    if (c->budget && c->allocated + bytes > c->budget)
+        return fail(c, FVV_E_NOMEM, "device memory budget exceeded (%llu + %zu > %llu bytes)",
+                    (unsigned long long)c->allocated, bytes, (unsigned long long)c->budget);
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(c, FVV_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    c->allocated += bytes;
+    return FVV_OK;
+}
+
+void dfree(fvv_ctx *c, void *p, size_t bytes)
+{
+    if (p) {
+        (void)hipFree(p);
+        c->allocated -= std::min<uint64_t>(bytes, c->allocated);
+    }
+}
+
+bool finite_all(const float *v, int n)
+{
+    for (int e = 0; e < n; ++e)
+        if (!std::isfinite(v[e])) return false;
+    return true;
+}
+
+int32_t check_camera(fvv_ctx *c, const fvv_camera &cam, bool source, const char *what)
+{
+    if (cam.width < 1 || cam.height < 1 || cam.width > 65535 || cam.height > 65535)
+        return fail(c, FVV_E_ARG, "%s: bad size %dx%d", what, cam.width, cam.height);
+    if (source && (int64_t)cam.width * cam.height > FVV_MAX_SRC_PIXELS)
+        return fail(c, FVV_E_ARG, "%s: %dx%d exceeds %d pixels", what, cam.width, cam.height,
+                    FVV_MAX_SRC_PIXELS);
+    if (!source && (cam.width > FVV_MAX_OUT_DIM || cam.height > FVV_MAX_OUT_DIM))
+        return fail(c, FVV_E_ARG, "%s: output %dx%d exceeds %d", what, cam.width, cam.height, FVV_MAX_OUT_DIM);
+    const float sc[6] = {cam.fx, cam.fy, cam.cx, cam.cy, cam.depth_alpha, cam.depth_beta};
+    if (!finite_all(sc, 6) || !finite_all(cam.R, 9) || !finite_all(cam.t, 3))
+        return fail(c, FVV_E_ARG, "%s: non-finite parameter", what);
+    if (!(cam.fx > 0.f) || !(cam.fy > 0.f)) return fail(c, FVV_E_ARG, "%s: fx/fy must be > 0", what);
+    for (int r = 0; r < 3; ++r)
+        for (int q = 0; q < 3; ++q) {
+            double s = 0.0;
+            for (int k = 0; k < 3; ++k) s += (double)cam.R[r * 3 + k] * (double)cam.R[q * 3 + k];
+            if (std::fabs(s - (r == q ? 1.0 : 0.0)) > 1e-4)
+                return fail(c, FVV_E_ARG, "%s: R is not orthonormal", what);
+        }
+    return FVV_OK;
+}
+
+// camera centre C = -R^T t in double
+void centre(const fvv_camera &c, double C[3])
+{
+    for (int r = 0; r < 3; ++r) {
+        double s = 0.0;
+        for (int k = 0; k < 3; ++k) s += (double)c.R[k * 3 + r] * (double)c.t[k];
+        C[r] = -s;
+    }
+}
+
+// Rank present cameras by centre distance (stable: ties keep the lower index);
+// weights 1/d; a coincident camera (d < 1e-6 m) is used alone with weight 1.
+int select_k(const fvv_camera *rig, const int32_t *present, int n, const fvv_camera &v, int k, int32_t *idx,
+             double *w)
+{
+    double Cv[3];
+    centre(v, Cv);
+    std::vector<std::pair<double, int>> d;
+    for (int c = 0; c < n; ++c) {
+        if (present && !present[c]) continue;
+        double Cc[3];
+        centre(rig[c], Cc);
+        const double dx = Cc[0] - Cv[0], dy = Cc[1] - Cv[1], dz = Cc[2] - Cv[2];
+        d.emplace_back(std::sqrt(dx * dx + dy * dy + dz * dz), c);
+    }
+    std::stable_sort(d.begin(), d.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+    int K = std::min<int>({(int)d.size(), k, FVV_MAX_K});
+    if (K > 0 && d[0].first < 1e-6) {
+        idx[0] = d[0].second;
+        w[0] = 1.0;
+        return 1;
+    }
+    for (int e = 0; e < K; ++e) {
+        idx[e] = d[e].second;
+        w[e] = 1.0 / d[e].first;
+    }
+    return K;
+}
+
+// Pair matrices of the pinhole warp from camera s (points) to camera d
+// (image): M = K_d (R_d R_s^T) K_s^-1, m = K_d (t_d - R_d R_s^T t_s); double,
+// fixed association order, rounded once to float32.
+void pair_dir(const fvv_camera &s, const fvv_camera &d, float M[9], float m[3])
+{
+    double Rrel[9], Ksi[9], Kd[9], T1[9], T2[9], tr[3];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) {
+            double acc = 0.0;
+            for (int k = 0; k < 3; ++k) acc += (double)d.R[r * 3 + k] * (double)s.R[c * 3 + k];
+            Rrel[r * 3 + c] = acc;
+        }
+    const double fx = s.fx, fy = s.fy;
+    const double ksi[9] = {1.0 / fx, 0.0, -(double)s.cx / fx, 0.0, 1.0 / fy, -(double)s.cy / fy, 0.0, 0.0, 1.0};
+    const double kd[9] = {(double)d.fx, 0.0, (double)d.cx, 0.0, (double)d.fy, (double)d.cy, 0.0, 0.0, 1.0};
+    std::memcpy(Ksi, ksi, sizeof ksi);
+    std::memcpy(Kd, kd, sizeof kd);
+    auto mm = [](const double *X, const double *Y, double *Z) {
+        for (int r = 0; r < 3; ++r)
+            for (int c = 0; c < 3; ++c) {
+                double acc = 0.0;
+                for (int k = 0; k < 3; ++k) acc += X[r * 3 + k] * Y[k * 3 + c];
+                Z[r * 3 + c] = acc;
+            }
+    };
+    mm(Rrel, Ksi, T1);
+    mm(Kd, T1, T2);
+    for (int r = 0; r < 3; ++r) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k) acc += Rrel[r * 3 + k] * (double)s.t[k];
+        tr[r] = (double)d.t[r] - acc;
+    }
+    for (int r = 0; r < 3; ++r) {
+        double acc = 0.0;
+        for (int k = 0; k < 3; ++k) acc += Kd[r * 3 + k] * tr[k];
+        m[r] = (float)acc;
+    }
+    for (int e = 0; e < 9; ++e) M[e] = (float)T2[e];
+}
+
+int32_t ensure_frame_slot(fvv_ctx *c, FrameSlot &s)
+{
+    const int n = (int)c->rig.size();
+    if ((int)s.rgba.size() == n && s.ready) return FVV_OK;
+    s.rgba.assign(n, nullptr);
+    s.depth.assign(n, nullptr);
+    s.present.assign(n, 0);
+    for (int k = 0; k < n; ++k) {
+        const size_t px = (size_t)c->rig[k].width * c->rig[k].height;
+        int32_t rc = dalloc(c, (void **)&s.rgba[k], px * 4);
+        if (rc) return rc;
+        rc = dalloc(c, (void **)&s.depth[k], px * 4);
+        if (rc) return rc;
+    }
+    if (!s.ready) HIPCHECK(c, hipEventCreateWithFlags(&s.ready, hipEventDisableTiming));
+    if (!s.last_use) HIPCHECK(c, hipEventCreateWithFlags(&s.last_use, hipEventDisableTiming));
+    return FVV_OK;
+}
+
+void release_frames(fvv_ctx *c)
+{
+    for (auto &s : c->slots) {
+        for (size_t k = 0; k < s.rgba.size(); ++k) {
+            const size_t px = (size_t)c->rig[k].width * c->rig[k].height;
+            dfree(c, s.rgba[k], px * 4);
+            dfree(c, s.depth[k], px * 4);
+        }
+        s.rgba.clear();
+        s.depth.clear();
+        s.present.clear();
+        s.version = 0;
+        s.used = false;
+    }
+    c->latest = -1;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// bytes of workspace one view of W x H needs
+size_t view_ws_bytes(int W, int H, bool host_out)
+{
+    const size_t px = (size_t)W * H;
+    const size_t nseg = (H + FVV_FILL_SEG - 1) / FVV_FILL_SEG;
+    size_t b = align256(px * 8) + align256(px * 4) * 2 + align256(nseg * W * sizeof(int2));
+    if (host_out) b += align256(px * 3);
+    return b;
+}
+
+int32_t ensure_ws(fvv_ctx *c, size_t bytes)
+{
+    if (c->ws_bytes >= bytes) return FVV_OK;
+    HIPCHECK(c, hipDeviceSynchronize());
+    dfree(c, c->ws, c->ws_bytes);
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    int32_t rc = dalloc(c, (void **)&c->ws, bytes);
+    if (rc) return rc;
+    c->ws_bytes = bytes;
+    return FVV_OK;
+}
+
+int32_t ensure_desc(fvv_ctx *c, int n)
+{
+    if (c->desc_cap < (size_t)n) {
+        HIPCHECK(c, hipDeviceSynchronize());
+        dfree(c, c->d_desc, c->desc_cap * sizeof(fvv_view_desc));
+        c->d_desc = nullptr;
+        c->desc_cap = 0;
+        int32_t rc = dalloc(c, (void **)&c->d_desc, (size_t)n * sizeof(fvv_view_desc));
+        if (rc) return rc;
+        c->desc_cap = n;
+    }
+    if (c->h_desc_cap < (size_t)n) {
+        for (int r = 0; r < fvv_ctx::kRing; ++r) {
+            if (c->h_desc_ev_live[r]) HIPCHECK(c, hipEventSynchronize(c->h_desc_ev[r]));
+            c->h_desc_ev_live[r] = false;
+            if (c->h_desc[r]) (void)hipHostFree(c->h_desc[r]);
+            c->h_desc[r] = nullptr;
+            HIPCHECK(c, hipHostMalloc((void **)&c->h_desc[r], (size_t)n * sizeof(fvv_view_desc)));
+            if (!c->h_desc_ev[r]) HIPCHECK(c, hipEventCreateWithFlags(&c->h_desc_ev[r], hipEventDisableTiming));
+        }
+        c->h_desc_cap = n;
+    }
+    return FVV_OK;
+}
+
+int32_t resolve_params(fvv_ctx *c, const fvv_synth_params *p, fvv_synth_params &o)
+{
+    o = fvv_synth_params{3, 0.05f, 4.0f, FVV_FILL_BG, FVV_PATH_PLAIN, 0, 0};
+    if (!p) return FVV_OK;
+    o = *p;
+    if (o.k_nearest == 0) o.k_nearest = 3;
+    if (o.tau_rel == 0.f) o.tau_rel = 0.05f;
+    if (o.max_footprint == 0.f) o.max_footprint = 4.0f;
+    if (o.k_nearest < 1 || o.k_nearest > FVV_MAX_K)
+        return fail(c, FVV_E_ARG, "k_nearest %d outside 1..%d", o.k_nearest, FVV_MAX_K);
+    if (!std::isfinite(o.tau_rel) || !(o.tau_rel > 0.f))
+        return fail(c, FVV_E_ARG, "tau_rel must be finite and > 0");
+    if (!std::isfinite(o.max_footprint) || !(o.max_footprint >= 1.f) || o.max_footprint > 64.f)
+        return fail(c, FVV_E_ARG, "max_footprint must lie in [1, 64]");
+    if (o.fill_mode != FVV_FILL_BG && o.fill_mode != FVV_FILL_NONE)
+        return fail(c, FVV_E_ARG, "unknown fill_mode %d", o.fill_mode);
+    if (o.path == FVV_PATH_LEARNED) return fail(c, FVV_E_UNSUPPORTED, "learned path is not available");
+    if (o.path != FVV_PATH_PLAIN) return fail(c, FVV_E_ARG, "unknown path %d", o.path);
+    if (o.reserved != 0) return fail(c, FVV_E_ARG, "reserved field must be 0");
+    return FVV_OK;
+}
+
+int32_t synthesize_impl(fvv_ctx *c, const fvv_camera *virts, int n_views, const fvv_synth_params *params,
+                        void *const *outs, const int64_t *pitches, int32_t mem_kind, void *stream)
+{
+    if (!c) return FVV_E_ARG;
+    if (!virts || n_views < 1 || !outs || !pitches) return fail(c, FVV_E_ARG, "null argument or n_views < 1");
+    if (mem_kind != FVV_MEM_HOST && mem_kind != FVV_MEM_DEVICE) return fail(c, FVV_E_ARG, "bad mem_kind");
+    if (c->rig.empty()) return fail(c, FVV_E_STATE, "no rig set");
+    fvv_synth_params P;
+    int32_t rc = resolve_params(c, params, P);
+    if (rc) return rc;
+    int si = c->latest;
+    if (P.frame_version) {
+        si = -1;
+        for (int q = 0; q < 2; ++q)
+            if (c->slots[q].version == P.frame_version) si = q;
+        if (si < 0)
+            return fail(c, FVV_E_STATE, "frame version %llu is not resident",
+                        (unsigned long long)P.frame_version);
+    }
+    if (si < 0 || c->slots[si].version == 0) return fail(c, FVV_E_STATE, "no frame set uploaded");
+    FrameSlot &fs = c->slots[si];
+    for (int v = 0; v < n_views; ++v) {
+        rc = check_camera(c, virts[v], false, "virtual camera");
+        if (rc) return rc;
+        if (!outs[v]) return fail(c, FVV_E_ARG, "outs[%d] is null", v);
+        if (pitches[v] < (int64_t)virts[v].width * 3) return fail(c, FVV_E_ARG, "pitches[%d] too small", v);
+    }
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const bool host_out = mem_kind == FVV_MEM_HOST;
+    size_t total = 0;
+    int max_w = 0, max_h = 0;
+    for (int v = 0; v < n_views; ++v) {
+        total += view_ws_bytes(virts[v].width, virts[v].height, host_out);
+        max_w = std::max(max_w, virts[v].width);
+        max_h = std::max(max_h, virts[v].height);
+    }
+    rc = ensure_ws(c, total);
+    if (rc) return rc;
+    rc = ensure_desc(c, n_views);
+    if (rc) return rc;
+    if (c->debug) {
+        const size_t px = (size_t)virts[0].width * virts[0].height;
+        if (c->dbg_px < px) {
+            HIPCHECK(c, hipDeviceSynchronize());
+            dfree(c, c->dbg_zf, c->dbg_px * 8);
+            dfree(c, c->dbg_depth, c->dbg_px * 4);
+            c->dbg_zf = nullptr;
+            c->dbg_depth = nullptr;
+            c->dbg_px = 0;
+            if ((rc = dalloc(c, (void **)&c->dbg_zf, px * 8))) return rc;
+            if ((rc = dalloc(c, (void **)&c->dbg_depth, px * 4))) return rc;
+            c->dbg_px = px;
+        }
+    }
+    // host descriptors (pinned ring slot)
+    const int r = c->ring;
+    c->ring = (c->ring + 1) % fvv_ctx::kRing;
+    if (c->h_desc_ev_live[r]) HIPCHECK(c, hipEventSynchronize(c->h_desc_ev[r]));
+    fvv_view_desc *hd = c->h_desc[r];
+    const int n = (int)c->rig.size();
+    uint8_t *cur = c->ws;
+    int max_src = 0, max_k = 0;
+    std::vector<uint8_t *> host_stage(n_views, nullptr);
+    for (int v = 0; v < n_views; ++v) {
+        const fvv_camera &vc = virts[v];
+        fvv_view_desc &d = hd[v];
+        std::memset(&d, 0, sizeof d);
+        d.W = vc.width;
+        d.H = vc.height;
+        d.fill_mode = P.fill_mode;
+        d.tau = P.tau_rel;
+        d.max_fp = P.max_footprint;
+        d.n_seg = (vc.height + FVV_FILL_SEG - 1) / FVV_FILL_SEG;
+        const size_t px = (size_t)vc.width * vc.height;
+        d.Z = (unsigned long long *)cur;
+        cur += align256(px * 8);
+        d.rgba = (uint32_t *)cur;
+        cur += align256(px * 4);
+        d.slot = (uint32_t *)cur;
+        cur += align256(px * 4);
+        d.colsum = (int2 *)cur;
+        cur += align256((size_t)d.n_seg * vc.width * sizeof(int2));
+        if (host_out) {
+            host_stage[v] = cur;
+            d.out = cur;
+            d.out_pitch = (int64_t)vc.width * 3;
+            cur += align256(px * 3);
+        } else {
+            d.out = (uint8_t *)outs[v];
+            d.out_pitch = pitches[v];
+        }
+        if (c->debug && v == 0) {
+            d.Zf = c->dbg_zf;
+            d.dbg_depth = c->dbg_depth;
+        }
+        int32_t idx[FVV_MAX_K];
+        double w[FVV_MAX_K];
+        const int K = select_k(c->rig.data(), fs.present.data(), n, vc, P.k_nearest, idx, w);
+        if (K < 1) return fail(c, FVV_E_STATE, "no camera present in the frame set");
+        d.K = K;
+        max_k = std::max(max_k, K);
+        for (int k = 0; k < K; ++k) {
+            const fvv_camera &sc = c->rig[idx[k]];
+            fvv_src_desc &sd = d.src[k];
+            sd.rgba = fs.rgba[idx[k]];
+            sd.depth = fs.depth[idx[k]];
+            sd.W = sc.width;
+            sd.H = sc.height;
+            sd.cam = idx[k];
+            sd.wgt = (float)w[k];
+            pair_dir(sc, vc, sd.A, sd.a);
+            pair_dir(vc, sc, sd.B, sd.b);
+            sd.sx = (float)((double)vc.fx / (double)sc.fx);
+            sd.sy = (float)((double)vc.fy / (double)sc.fy);
+            max_src = std::max(max_src, sc.width * sc.height);
+        }
+    }
+    HIPCHECK(c, hipStreamWaitEvent(s, fs.ready, 0));
+    HIPCHECK(c, hipMemcpyAsync(c->d_desc, hd, (size_t)n_views * sizeof(fvv_view_desc), hipMemcpyHostToDevice, s));
+    HIPCHECK(c, hipEventRecord(c->h_desc_ev[r], s));
+    c->h_desc_ev_live[r] = true;
+    bool any_fill = P.fill_mode == FVV_FILL_BG;
+    HIPCHECK(c, fvv_launch_synthesis(c->d_desc, n_views, max_w, max_h, max_src, max_k, any_fill, s,
+                                     c->profiling ? &c->prof : nullptr));
+    HIPCHECK(c, hipEventRecord(fs.last_use, s));
+    fs.used = true;
+    c->have_taps = c->debug;
+    c->last_px = (int64_t)virts[0].width * virts[0].height;
+    c->last_z = hd[0].Z;
+    c->last_rgba = hd[0].rgba;
+    if (host_out) {
+        for (int v = 0; v < n_views; ++v)
+            HIPCHECK(c, hipMemcpy2DAsync(outs[v], pitches[v], host_stage[v], (size_t)virts[v].width * 3,
+                                         (size_t)virts[v].width * 3, virts[v].height, hipMemcpyDeviceToHost, s));
+        HIPCHECK(c, hipStreamSynchronize(s));
+    }
+    return FVV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t fvv_abi_version(void) { return FVV_ABI_VERSION; }
+
+int32_t fvv_create(int32_t hip_device, uint64_t mem_budget_bytes, fvv_ctx **out)
+{
+    if (!out) return fail(nullptr, FVV_E_ARG, "out is null");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return fail(nullptr, FVV_E_DEVICE, "hipGetDeviceCount: %s", hipGetErrorString(e));
+    if (hip_device < 0 || hip_device >= n)
+        return fail(nullptr, FVV_E_ARG, "device %d outside 0..%d", hip_device, n - 1);
+    fvv_ctx *c = new (std::nothrow) fvv_ctx();
+    if (!c) return fail(nullptr, FVV_E_NOMEM, "out of host memory");
+    c->device = hip_device;
+    c->budget = mem_budget_bytes;
+    *out = c;
+    return FVV_OK;
+}
+
+void fvv_destroy(fvv_ctx *c)
+{
+    if (!c) return;
+    {
+        DeviceGuard g(c->device);
+        (void)hipDeviceSynchronize();
+        if (!c->rig.empty()) release_frames(c);
+        for (auto &s : c->slots) {
+            if (s.ready) (void)hipEventDestroy(s.ready);
+            if (s.last_use) (void)hipEventDestroy(s.last_use);
+        }
+        dfree(c, c->staging, c->staging_bytes);
+        if (c->staging_free) (void)hipEventDestroy(c->staging_free);
+        dfree(c, c->ws, c->ws_bytes);
+        dfree(c, c->d_desc, c->desc_cap * sizeof(fvv_view_desc));
+        for (int r = 0; r < fvv_ctx::kRing; ++r) {
+            if (c->h_desc[r]) (void)hipHostFree(c->h_desc[r]);
+            if (c->h_desc_ev[r]) (void)hipEventDestroy(c->h_desc_ev[r]);
+        }
+        dfree(c, c->dbg_zf, c->dbg_px * 8);
+        dfree(c, c->dbg_depth, c->dbg_px * 4);
+        for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
+    }
+    delete c;
+}
+
+const char *fvv_last_error(const fvv_ctx *c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+int32_t fvv_set_rig(fvv_ctx *c, const fvv_camera *cams, int32_t n)
+{
+    if (!c) return FVV_E_ARG;
+    if (!cams || n < 1 || n > FVV_MAX_CAMERAS) return fail(c, FVV_E_ARG, "rig size %d outside 1..%d", n, FVV_MAX_CAMERAS);
+    for (int k = 0; k < n; ++k) {
+        int32_t rc = check_camera(c, cams[k], true, "rig camera");
+        if (rc) return rc;
+    }
+    DeviceGuard g(c->device);
+    HIPCHECK(c, hipDeviceSynchronize());
+    if (!c->rig.empty()) release_frames(c);
+    c->rig.assign(cams, cams + n);
+    return FVV_OK;
+}
+
+int32_t fvv_upload_mvd(fvv_ctx *c, const fvv_view *views, int32_t n, int32_t mem_kind, void *stream,
+                       uint64_t *out_version)
+{
+    if (!c) return FVV_E_ARG;
+    if (c->rig.empty()) return fail(c, FVV_E_STATE, "no rig set");
+    if (!views || n != (int)c->rig.size()) return fail(c, FVV_E_ARG, "need one view per rig camera (%zu)", c->rig.size());
+    if (mem_kind != FVV_MEM_HOST && mem_kind != FVV_MEM_DEVICE) return fail(c, FVV_E_ARG, "bad mem_kind");
+    size_t need = 0;
+    int n_present = 0;
+    for (int k = 0; k < n; ++k) {
+        const fvv_view &v = views[k];
+        const fvv_camera &cam = c->rig[k];
+        if (!v.rgb && !v.depth_mm) continue;
+        if (!v.rgb || !v.depth_mm) return fail(c, FVV_E_ARG, "view %d: rgb and depth must both be given", k);
+        if (v.rgb_pitch < (int64_t)cam.width * 3 || v.depth_pitch < (int64_t)cam.width * 2)
+            return fail(c, FVV_E_ARG, "view %d: pitch too small", k);
+        if (v.depth_pitch % 2) return fail(c, FVV_E_ARG, "view %d: depth pitch must be even", k);
+        need += align256((size_t)cam.width * cam.height * 3) + align256((size_t)cam.width * cam.height * 2);
+        ++n_present;
+    }
+    if (n_present == 0) return fail(c, FVV_E_ARG, "no camera present in the upload");
+    DeviceGuard g(c->device);
+    hipStream_t s = (hipStream_t)stream;
+    const int dst = c->latest < 0 ? 0 : 1 - c->latest;
+    FrameSlot &fs = c->slots[dst];
+    int32_t rc = ensure_frame_slot(c, fs);
+    if (rc) return rc;
+    if (c->staging_bytes < need) {
+        HIPCHECK(c, hipDeviceSynchronize());
+        dfree(c, c->staging, c->staging_bytes);
+        c->staging = nullptr;
+        c->staging_bytes = 0;
+        if ((rc = dalloc(c, (void **)&c->staging, need))) return rc;
+        c->staging_bytes = need;
+    }
+    if (!c->staging_free) HIPCHECK(c, hipEventCreateWithFlags(&c->staging_free, hipEventDisableTiming));
+    else HIPCHECK(c, hipStreamWaitEvent(s, c->staging_free, 0));
+    if (fs.used) HIPCHECK(c, hipStreamWaitEvent(s, fs.last_use, 0));
+    const hipMemcpyKind kind = mem_kind == FVV_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    uint8_t *cur = c->staging;
+    for (int k = 0; k < n; ++k) {
+        const fvv_view &v = views[k];
+        const fvv_camera &cam = c->rig[k];
+        fs.present[k] = (v.rgb && v.depth_mm) ? 1 : 0;
+        if (!fs.present[k]) continue;
+        const int W = cam.width, H = cam.height;
+        uint8_t *rgb = cur;
+        cur += align256((size_t)W * H * 3);
+        uint16_t *dep = (uint16_t *)cur;
+        cur += align256((size_t)W * H * 2);
+        HIPCHECK(c, hipMemcpy2DAsync(rgb, (size_t)W * 3, v.rgb, v.rgb_pitch, (size_t)W * 3, H, kind, s));
+        HIPCHECK(c, hipMemcpy2DAsync(dep, (size_t)W * 2, v.depth_mm, v.depth_pitch, (size_t)W * 2, H, kind, s));
+        HIPCHECK(c, fvv_launch_repack(rgb, (int64_t)W * 3, dep, (int64_t)W * 2, W, H, cam.depth_alpha,
+                                      cam.depth_beta, fs.rgba[k], fs.depth[k], s,
+                                      c->profiling ? &c->prof : nullptr));
+    }
+    HIPCHECK(c, hipEventRecord(c->staging_free, s));
+    HIPCHECK(c, hipEventRecord(fs.ready, s));
+    if (mem_kind == FVV_MEM_HOST) HIPCHECK(c, hipStreamSynchronize(s));
+    fs.version = c->next_version++;
+    fs.used = false;
+    c->latest = dst;
+    if (out_version) *out_version = fs.version;
+    return FVV_OK;
+}
+
+int32_t fvv_synthesize(fvv_ctx *c, const fvv_camera *virt, const fvv_synth_params *params, void *out_rgb8,
+                       int64_t out_pitch, int32_t mem_kind, void *stream)
+{
+    void *outs[1] = {out_rgb8};
+    int64_t pitches[1] = {out_pitch};
+    return synthesize_impl(c, virt, 1, params, outs, pitches, mem_kind, stream);
+}
+
+int32_t fvv_synthesize_batch(fvv_ctx *c, const fvv_camera *virts, int32_t n_views, const fvv_synth_params *params,
+                             void *const *outs, const int64_t *pitches, int32_t mem_kind, void *stream)
+{
+    return synthesize_impl(c, virts, n_views, params, outs, pitches, mem_kind, stream);
+}
+
+int32_t fvv_select_cameras(const fvv_camera *rig, const int32_t *present, int32_t n, const fvv_camera *virt,
+                           int32_t k, int32_t *idx, float *w)
+{
+    if (!rig || !virt || !idx || !w || n < 1 || n > FVV_MAX_CAMERAS || k < 1) return FVV_E_ARG;
+    int32_t id[FVV_MAX_K];
+    double wd[FVV_MAX_K];
+    const int K = select_k(rig, present, n, *virt, k, id, wd);
+    for (int e = 0; e < K; ++e) {
+        idx[e] = id[e];
+        w[e] = (float)wd[e];
+    }
+    return K;
+}
+
+int32_t fvv_pair_matrices(const fvv_camera *src, const fvv_camera *virt, float *out26)
+{
+    if (!src || !virt || !out26) return FVV_E_ARG;
+    pair_dir(*src, *virt, out26, out26 + 9);
+    pair_dir(*virt, *src, out26 + 12, out26 + 21);
+    out26[24] = (float)((double)virt->fx / (double)src->fx);
+    out26[25] = (float)((double)virt->fy / (double)src->fy);
+    return FVV_OK;
+}
+
+static const char *k_stage_names[FVV_NSTAGES] = {"repack", "zclear", "splat", "filter_blend",
+                                                  "fill_rows", "fill_colsum", "fill_resolve"};
+
+int32_t fvv_set_profiling(fvv_ctx *c, int32_t enable)
+{
+    if (!c) return FVV_E_ARG;
+    c->profiling = enable != 0;
+    return FVV_OK;
+}
+
+int32_t fvv_stage_count(void) { return FVV_NSTAGES; }
+
+const char *fvv_stage_name(int32_t stage)
+{
+    return (stage >= 0 && stage < FVV_NSTAGES) ? k_stage_names[stage] : nullptr;
+}
+
+int32_t fvv_profile_read(fvv_ctx *c, double *total_ms, int64_t *launches, int32_t n, int32_t reset)
+{
+    if (!c) return FVV_E_ARG;
+    if (!total_ms || !launches || n < FVV_NSTAGES) return fail(c, FVV_E_ARG, "need %d entries", FVV_NSTAGES);
+    DeviceGuard g(c->device);
+    for (auto &m : c->prof.marks) {
+        HIPCHECK(c, hipEventSynchronize(m.second.second));
+        float ms = 0.f;
+        HIPCHECK(c, hipEventElapsedTime(&ms, m.second.first, m.second.second));
+        c->prof.total_ms[m.first] += ms;
+        c->prof.launches[m.first] += 1;
+    }
+    c->prof.marks.clear();
+    c->prof.next = 0;
+    for (int k = 0; k < FVV_NSTAGES; ++k) {
+        total_ms[k] = c->prof.total_ms[k];
+        launches[k] = c->prof.launches[k];
+        if (reset) {
+            c->prof.total_ms[k] = 0.0;
+            c->prof.launches[k] = 0;
+        }
+    }
+    return FVV_OK;
+}
+
+int32_t fvv_set_debug(fvv_ctx *c, int32_t enable)
+{
+    if (!c) return FVV_E_ARG;
+    c->debug = enable != 0;
+    return FVV_OK;
+}
+
+int32_t fvv_debug_read(fvv_ctx *c, int32_t tap, void *host_out, int64_t bytes)
+{
+    if (!c) return FVV_E_ARG;
+    if (!host_out) return fail(c, FVV_E_ARG, "host_out is null");
+    if (!c->have_taps) return fail(c, FVV_E_STATE, "no debug taps: enable with fvv_set_debug before synthesis");
+    DeviceGuard g(c->device);
+    const void *src = nullptr;
+    int64_t need = 0;
+    switch (tap) {
+    case FVV_TAP_Z_RAW: src = c->last_z; need = c->last_px * 8; break;
+    case FVV_TAP_Z_FILT: src = c->dbg_zf; need = c->last_px * 8; break;
+    case FVV_TAP_BLEND: src = c->last_rgba; need = c->last_px * 4; break;
+    case FVV_TAP_DEPTH: src = c->dbg_depth; need = c->last_px * 4; break;
+    default: return fail(c, FVV_E_ARG, "unknown tap %d", tap);
+    }
+    if (bytes != need) return fail(c, FVV_E_ARG, "tap %d holds %lld bytes, asked %lld", tap, (long long)need, (long long)bytes);
+    HIPCHECK(c, hipDeviceSynchronize());
+    HIPCHECK(c, hipMemcpy(host_out, src, (size_t)need, hipMemcpyDeviceToHost));
+    return FVV_OK;
+}
+
+}  // extern "C"

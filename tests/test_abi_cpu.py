@@ -1,0 +1,85 @@
+"""Boundary checks that need no GPU: the library loads, exports every symbol
+the header declares, and its host-only helpers (camera selection, pair
+matrices) agree with the oracle."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+import paper_2007_00558_amd as fvv
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "fvv.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fvv_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    L = fvv.lib()
+    names = header_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(fvv.EXPORTED)
+    assert L.fvv_abi_version() == 1
+
+
+def test_header_struct_layouts_match_binding():
+    assert C.sizeof(fvv.Camera) == 80
+    assert C.sizeof(fvv.View) == 32
+    assert C.sizeof(fvv.SynthParams) == 32
+    assert fvv.SynthParams.frame_version.offset == 24
+
+
+@pytest.mark.parametrize("cfg", ["c2", "small"])
+def test_selection_matches_oracle(oracle_lib, cfg):
+    w = {"c2": sg.config2, "small": sg.config_small}[cfg](0)
+    virts = list(w.virtual) + list(w.rig) + sg.swing_trajectory(7, -40, 40, 2.1, 64, 48)
+    for v in virts:
+        for k in (1, 2, 3, 5, 8):
+            i_o, w_o = oracle_lib.select(w.rig, v, k)
+            i_f, w_f = fvv.select_cameras(w.rig, v, k)
+            assert list(i_o) == list(i_f)
+            assert np.array_equal(np.float32(w_o), w_f)
+    i_o, _ = oracle_lib.select(w.rig, w.virtual[0], 3, present=[0, 1, 1] + [1] * (len(w.rig) - 3))
+    i_f, _ = fvv.select_cameras(w.rig, w.virtual[0], 3, present=[0, 1, 1] + [1] * (len(w.rig) - 3))
+    assert list(i_o) == list(i_f)
+
+
+def test_pair_matrices_bit_exact_vs_oracle(oracle_lib):
+    for w in (sg.config1(0), sg.config2(0), sg.config_small(2)):
+        for src in w.rig:
+            for v in list(w.virtual) + list(w.rig):
+                a = oracle_lib.pair_arrays(src, v)
+                b = fvv.pair_matrices(src, v)
+                for key in ("A", "a", "B", "b"):
+                    assert np.array_equal(a[key].view(np.uint32), np.asarray(b[key], np.float32).view(np.uint32)), key
+                assert a["sx"] == b["sx"] and a["sy"] == b["sy"]
+
+
+def test_bad_arguments_are_rejected_without_a_device():
+    L = fvv.lib()
+    assert L.fvv_select_cameras(None, None, 0, None, 3, None, None) == fvv.FVV_E_ARG
+    assert L.fvv_pair_matrices(None, None, None) == fvv.FVV_E_ARG
+    h = C.c_void_p()
+    assert L.fvv_create(0, 0, None) == fvv.FVV_E_ARG
+    assert L.fvv_last_error(None)
+    L.fvv_destroy(None)
+
+
+def test_create_without_gpu_fails_cleanly():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    L = fvv.lib()
+    h = C.c_void_p()
+    rc = L.fvv_create(0, 0, C.byref(h))
+    assert rc in (fvv.FVV_E_DEVICE, fvv.FVV_E_ARG)
+    assert not h.value
+    assert len(L.fvv_last_error(None)) > 0
