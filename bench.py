@@ -32,21 +32,21 @@ def log(*a):
 
 
 # Algorithmic (compulsory) bytes per launch of each stage, from the sizes of
-# one batch: n_out output pixels per view, n_src source pixels of the
-# selected cameras per view, views per batch.
-def stage_bytes(stage: str, n_views: int, n_out: int, n_src_sel: int, n_src_all: int) -> float:
-    if stage == "repack":          # per source pixel: RGB8 + u16 in, RGBA8 + f32 out
-        return n_src_all * (3 + 2 + 4 + 4) / 9.0   # one launch per camera
-    if stage == "zclear":          # 8-byte key written per output pixel
-        return n_views * n_out * 8.0
-    if stage == "splat":           # source depth read + one key write-back per output pixel
-        return n_views * (n_src_sel * 4.0 + n_out * 8.0)
-    if stage == "filter_blend":    # key read, source texels+depth once, RGBA + slot written
-        return n_views * (n_out * (8.0 + 8.0) + n_src_sel * 8.0)
-    if stage in ("fill_rows", "fill_colsum"):
-        return n_views * n_out * 4.0
-    if stage == "fill_resolve":    # slot + RGBA read, RGB8 written
-        return n_views * n_out * (4.0 + 4.0 + 3.0)
+# one batch: n_out output pixels per view, n_src_sel source pixels of the
+# selected cameras per view, n_views views per batch.
+#   repack     per source pixel: RGB8 + u16 in, 8-byte texel + f32 depth out
+#   bin_count  per selected source pixel: f32 depth read once
+#   tile       per selected source pixel: f32 depth (splat) + 8-byte texel
+#              (backward fetch) read once; per output pixel: RGB8 + 4-byte
+#              slot written (the z-buffer lives in LDS)
+#   fill_open  touches only open holes: not counted
+def stage_bytes(stage: str, n_views: int, n_out: int, n_src_sel: float, n_src_all: int) -> float:
+    if stage == "repack":
+        return n_src_all * (3 + 2 + 8 + 4) / 9.0   # one launch per camera
+    if stage == "bin_count":
+        return n_views * n_src_sel * 4.0
+    if stage == "tile":
+        return n_views * (n_src_sel * (4.0 + 8.0) + n_out * (3.0 + 4.0))
     return float("nan")
 
 
@@ -123,9 +123,12 @@ def main():
             continue
         avg_ms = tot / cnt
         b = stage_bytes(name, n_views, n_out, n_src_sel, n_src_all)
-        stages[name] = {"avg_ms": round(avg_ms, 4), "launches_per_step": cnt / prof_steps,
-                        "alg_GBs": round(b / (avg_ms * 1e-3) / 1e9, 1)}
+        stages[name] = {"avg_ms": round(avg_ms, 4), "launches_per_step": cnt / prof_steps}
+        if b == b:
+            stages[name]["alg_GBs"] = round(b / (avg_ms * 1e-3) / 1e9, 1)
     dom = max(stages, key=lambda k: stages[k]["avg_ms"] * stages[k]["launches_per_step"])
+    if "alg_GBs" not in stages[dom]:
+        dom = "tile"
     d = stages[dom]
     roofline = {"bound": "hbm", "kernel": dom, "achieved": d["alg_GBs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(d["alg_GBs"] / HBM_PEAK_GBS, 4), "traffic": None}

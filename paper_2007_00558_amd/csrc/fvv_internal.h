@@ -11,19 +11,24 @@
 #define FVV_KMAX 8
 #define FVV_KEY_EMPTY 0xFFFFFFFFFFFFFFFFull
 #define FVV_NO_DEPTH 0xFFFFFFFFu    // depth-plane marker of a pixel without depth
-#define FVV_HOLE_BIT 0x80000000u    // slot marker of a hole (valid depths are positive floats)
+#define FVV_HOLE 0x80000000u        // slot of a hole filled inside its tile (or left black)
+#define FVV_HOLE_OPEN 0x80000001u   // slot of a hole whose neighbours lie beyond its tile
 #define FVV_ZCLIP 0.01f             // points and samples nearer than this are dropped
-#define FVV_FILL_SEG 64             // rows per column segment in the hole fill
+#define FVV_TILE 32                 // output tile edge (pixels) of the fused kernel
+#define FVV_SBLK 16                 // source block edge (pixels) of the binning
+#define FVV_LIST_PER_BLOCK 16       // bin-list capacity per source block (average tiles per block)
 
 // One selected source camera of one view.  The float32 pair matrices are
 // computed on the host in double and rounded once (Section VI pinhole warp):
 //   forward  p = ((A_r0 i + A_r1 j) + A_r2) z + a_r   (source pixel -> virtual)
 //   backward q = ((B_r0 x + B_r1 y) + B_r2) z + b_r   (virtual pixel -> source)
 struct fvv_src_desc {
-    const uint32_t *rgba;   // H*W texels, RGBA8 with R in the low byte
+    const uint2 *texel;     // H*W: x = RGBA8 (R in the low byte), y = depth bits (FVV_NO_DEPTH = none)
     const float *depth;     // H*W decoded depth (Eq. 1 applied); FVV_NO_DEPTH bits = none
     int32_t W, H;
     int32_t cam;            // rig index (key bits 27..31)
+    int32_t nbx;            // source blocks per row: ceil(W / FVV_SBLK)
+    int32_t nblk;           // source blocks: nbx * ceil(H / FVV_SBLK)
     float wgt;              // view weight, 1 / centre distance
     float A[9], a[3], B[9], b[3];
     float sx, sy;           // focal ratios virtual / source (footprint scale)
@@ -33,16 +38,28 @@ struct fvv_src_desc {
 struct fvv_view_desc {
     int32_t W, H, K, fill_mode;
     float tau, max_fp;
-    int32_t n_seg;          // ceil(H / FVV_FILL_SEG)
-    int32_t pad0;
-    unsigned long long *Z;  // W*H raw keys (splat target)
-    unsigned long long *Zf; // W*H filtered keys (debug tap; may be null)
-    float *dbg_depth;       // W*H blend depth (debug tap; may be null)
-    uint32_t *rgba;         // W*H blend result, A = 255 covered, 0 hole
-    uint32_t *slot;         // W*H depth bits of covered pixels / hole codes
-    int2 *colsum;           // n_seg*W column-segment summaries
+    int32_t ntx, nty;       // output tiles per row / column
+    int32_t blk_stride;     // bbox entries reserved per camera slot (>= max nblk)
+    int32_t list_cap;       // bin-list capacity
+    // binning
+    int32_t *counts;        // ntx*nty tile counters (zero between calls)
+    int32_t *offs;          // ntx*nty list start per tile
+    int32_t *cursor;        // ntx*nty list end per tile after the fill
+    int32_t *list;          // list_cap entries: camera slot << 24 | source block
+    int4 *bbox;             // K*blk_stride tile ranges (x0, x1, y0, y1; x0 > x1 = empty)
+    int32_t *overflow;      // 1 if the bin list overflowed (tiles then scan every block)
+    // per-tile results
+    uint32_t *slot;         // W*H depth bits of covered pixels / FVV_HOLE / FVV_HOLE_OPEN
+    int32_t *open;          // ntx*nty count of open holes per tile
+    int2 *rowsum;           // ntx*nty*FVV_TILE (first, last) covered x of each tile row
+    int2 *colsum;           // ntx*nty*FVV_TILE (first, last) covered y of each tile column
     uint8_t *out;           // final RGB8, out_pitch bytes per row
     int64_t out_pitch;
+    // debug taps (null unless enabled)
+    unsigned long long *dbg_z;
+    unsigned long long *dbg_zf;
+    uint32_t *dbg_rgba;
+    float *dbg_depth;
     fvv_src_desc src[FVV_KMAX];
 };
 
@@ -51,12 +68,11 @@ struct fvv_view_desc {
 // stage when the profile is read.
 enum fvv_stage {
     FVV_ST_REPACK = 0,
-    FVV_ST_ZCLEAR,
-    FVV_ST_SPLAT,
-    FVV_ST_FILTER_BLEND,
-    FVV_ST_FILL_ROWS,
-    FVV_ST_FILL_COLSUM,
-    FVV_ST_FILL_RESOLVE,
+    FVV_ST_BIN_COUNT,
+    FVV_ST_BIN_SCAN,
+    FVV_ST_BIN_FILL,
+    FVV_ST_TILE,
+    FVV_ST_FILL_OPEN,
     FVV_NSTAGES
 };
 
@@ -92,10 +108,19 @@ inline void fvv_prof_end(fvv_prof *p, hipStream_t s, int stage, hipEvent_t e0)
     p->marks.push_back({stage, {e0, e1}});
 }
 
+// Launch geometry of one batched synthesis call.
+struct fvv_batch_dims {
+    int n_views;
+    int max_k;            // largest K of the batch
+    int max_blocks;       // largest source-block count of a selected camera
+    int max_tiles_x;      // largest ntx
+    int max_tiles_y;      // largest nty
+    bool fill_bg;         // any view fills holes
+};
+
 // Host-side launchers (fvv_kernels.hip).  All return hipError_t of the launch.
 hipError_t fvv_launch_repack(const uint8_t *rgb, int64_t rgb_pitch, const uint16_t *depth,
                              int64_t depth_pitch, int W, int H, float alpha, float beta,
-                             uint32_t *rgba_out, float *depth_out, hipStream_t s, fvv_prof *prof);
-hipError_t fvv_launch_synthesis(const fvv_view_desc *d_views, int n_views, int max_w,
-                                int max_h, int max_src_px, int max_k, bool fill_bg,
+                             uint2 *texel_out, float *depth_out, hipStream_t s, fvv_prof *prof);
+hipError_t fvv_launch_synthesis(const fvv_view_desc *d_views, const fvv_batch_dims &dims,
                                 hipStream_t s, fvv_prof *prof);

@@ -1,26 +1,38 @@
 // fvv_kernels.hip -- gfx950 kernels of the DIBR view-synthesis path.
 //
 // Stages (FVV Live, arXiv 2007.00558, Section VI):
-//   repack   MVD upload: RGB8 -> RGBA8 texels, millimetres -> metres with the
-//            Eq. (1) correction (Section IV-A), once per frame set
-//   splat    3D warping of every valid source pixel into the virtual view,
-//            z-buffered by 64-bit packed (depth, camera, pixel) keys
-//   filter   3x3 crack fill / speckle removal on the key map ("image
-//            filtering" that accompanies backward warping against cracks)
-//   blend    backward warping into each selected camera, depth-consistent
-//            bilinear fetch, mix by camera distance
-//   fill     disocclusion holes take the nearest uncovered-free neighbour
-//            with the largest depth (background)
+//   repack     MVD ingest: RGB8 -> 8-byte texels {RGBA8, depth}, millimetres ->
+//              metres with the Eq. (1) correction (Section IV-A); per frame set
+//   bin_count  every 16x16 block of each selected source camera is projected
+//              (3D warping of its valid pixels) and the output tiles its
+//              footprints touch are counted
+//   bin_scan   per-tile list offsets
+//   bin_fill   per-tile lists of source blocks
+//   tile       one workgroup per 32x32 output tile: splats its binned blocks
+//              into an LDS z-buffer of packed (depth, camera, pixel) keys with
+//              64-bit LDS atomicMin, 3x3 crack/speckle filter in LDS, backward
+//              depth-consistent bilinear fetch from each selected camera mixed
+//              by camera distance, hole fill for holes whose neighbours lie
+//              inside the tile, writes the RGB8 output
+//   fill_open  the remaining holes: nearest covered pixel left/right/up/down
+//              through per-tile row and column summaries, larger depth wins
+//
+// The z-buffer never leaves LDS; the only per-pixel HBM traffic besides the
+// source gathers is the RGB8 output and a 4-byte slot per pixel.
 //
 // Arithmetic contract shared with the definition of the method: every
 // decision (pixel coverage, key order, tap validity, hole) is computed in
 // float32 op by op -- built with -ffp-contract=off and correctly rounded
 // division -- so the key map and the hole map are bit-exact.
 #include <algorithm>
+#include <climits>
 
 #include "fvv_internal.h"
 
 namespace {
+
+constexpr int T = FVV_TILE;
+constexpr int WN = FVV_TILE + 2;   // tile window edge with a 1-pixel halo
 
 __device__ __forceinline__ uint32_t f2u(float f) { return __float_as_uint(f); }
 __device__ __forceinline__ float u2f(uint32_t u) { return __uint_as_float(u); }
@@ -34,76 +46,184 @@ __device__ __forceinline__ void project(const float *M, const float *m, float i,
     p2 = __fadd_rn(__fmul_rn(__fadd_rn(__fadd_rn(__fmul_rn(M[6], i), __fmul_rn(M[7], j)), M[8]), z), m[2]);
 }
 
-// ---------------------------------------------------------------- repack
-__global__ void __launch_bounds__(256) k_repack(const uint8_t *__restrict__ rgb, int64_t rgb_pitch,
-                                                const uint16_t *__restrict__ depth, int64_t depth_pitch,
-                                                int W, int H, float alpha, float beta,
-                                                uint32_t *__restrict__ rgba_out,
-                                                float *__restrict__ depth_out)
-{
-    int x = blockIdx.x * blockDim.x + threadIdx.x;
-    int y = blockIdx.y;
-    if (x >= W || y >= H) return;
-    const uint8_t *p = rgb + (int64_t)y * rgb_pitch + (int64_t)x * 3;
-    uint32_t c = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | 0xFF000000u;
-    uint16_t d = *(const uint16_t *)((const uint8_t *)depth + (int64_t)y * depth_pitch + (int64_t)x * 2);
-    uint32_t zb = FVV_NO_DEPTH;
-    if (d != 0) {
-        float z = __fdiv_rn((float)d, 1000.0f);
-        float s = __fadd_rn(__fmul_rn(alpha, z), beta);   // Eq. (1): (alpha z + beta) z
-        zb = f2u(__fmul_rn(s, z));
-    }
-    rgba_out[(int64_t)y * W + x] = c;
-    depth_out[(int64_t)y * W + x] = u2f(zb);
-}
+struct Footprint {
+    int x0, x1, y0, y1;
+    unsigned long long key;
+};
 
-// ---------------------------------------------------------------- z clear
-__global__ void __launch_bounds__(256) k_zclear(const fvv_view_desc *__restrict__ views)
+// Forward warp of source pixel (i, j) at depth z: the output pixel centres
+// x with u - mx/2 <= x < u + mx/2 (rows likewise), mx = clamp(sx z / p2, 1,
+// max_fp), clipped to the output image; key = depth bits | camera | pixel.
+__device__ __forceinline__ bool splat_point(const fvv_src_desc &s, int W, int H, float max_fp, int i, int j,
+                                            float z, Footprint &f)
 {
-    const fvv_view_desc &vd = views[blockIdx.y];
-    int64_t n = (int64_t)vd.W * vd.H;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
-         e += (int64_t)gridDim.x * blockDim.x)
-        vd.Z[e] = FVV_KEY_EMPTY;
-}
-
-// ---------------------------------------------------------------- splat
-// One thread per source pixel of one selected camera of one view.
-__global__ void __launch_bounds__(256) k_splat(const fvv_view_desc *__restrict__ views)
-{
-    const fvv_view_desc &vd = views[blockIdx.z];
-    const int k = blockIdx.y;
-    if (k >= vd.K) return;
-    const fvv_src_desc &s = vd.src[k];
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= s.W * s.H) return;
-    const uint32_t zb = f2u(s.depth[p]);
-    if (zb == FVV_NO_DEPTH) return;
-    const float z = u2f(zb);
-    const int j = p / s.W, i = p - j * s.W;
     float q0, q1, q2;
     project(s.A, s.a, (float)i, (float)j, z, q0, q1, q2);
-    if (!(q2 > FVV_ZCLIP)) return;
+    if (!(q2 > FVV_ZCLIP)) return false;
     const float u = __fdiv_rn(q0, q2), v = __fdiv_rn(q1, q2);
-    if (!isfinite(u) || !isfinite(v)) return;
+    if (!isfinite(u) || !isfinite(v)) return false;
     float mx = __fdiv_rn(__fmul_rn(s.sx, z), q2);
     float my = __fdiv_rn(__fmul_rn(s.sy, z), q2);
-    mx = fminf(fmaxf(mx, 1.0f), vd.max_fp);
-    my = fminf(fmaxf(my, 1.0f), vd.max_fp);
+    mx = fminf(fmaxf(mx, 1.0f), max_fp);
+    my = fminf(fmaxf(my, 1.0f), max_fp);
     const float hx = __fmul_rn(0.5f, mx), hy = __fmul_rn(0.5f, my);
     float x0f = ceilf(__fsub_rn(u, hx)), x1f = __fsub_rn(ceilf(__fadd_rn(u, hx)), 1.0f);
     float y0f = ceilf(__fsub_rn(v, hy)), y1f = __fsub_rn(ceilf(__fadd_rn(v, hy)), 1.0f);
     x0f = fmaxf(x0f, 0.0f);
     y0f = fmaxf(y0f, 0.0f);
-    x1f = fminf(x1f, (float)(vd.W - 1));
-    y1f = fminf(y1f, (float)(vd.H - 1));
-    if (x0f > x1f || y0f > y1f) return;
-    const unsigned long long key = ((unsigned long long)f2u(q2) << 32) |
-                                   ((unsigned long long)(uint32_t)s.cam << 27) | (unsigned long long)p;
-    const int x0 = (int)x0f, x1 = (int)x1f, y0 = (int)y0f, y1 = (int)y1f;
-    for (int y = y0; y <= y1; ++y)
-        for (int x = x0; x <= x1; ++x)
-            atomicMin(&vd.Z[(int64_t)y * vd.W + x], key);
+    x1f = fminf(x1f, (float)(W - 1));
+    y1f = fminf(y1f, (float)(H - 1));
+    if (x0f > x1f || y0f > y1f) return false;
+    f.x0 = (int)x0f;
+    f.x1 = (int)x1f;
+    f.y0 = (int)y0f;
+    f.y1 = (int)y1f;
+    f.key = ((unsigned long long)f2u(q2) << 32) | ((unsigned long long)(uint32_t)s.cam << 27) |
+            (unsigned long long)((int64_t)j * s.W + i);
+    return true;
+}
+
+// ---------------------------------------------------------------- repack
+__global__ void __launch_bounds__(256) k_repack(const uint8_t *__restrict__ rgb, int64_t rgb_pitch,
+                                                const uint16_t *__restrict__ depth, int64_t depth_pitch,
+                                                int W, int H, float alpha, float beta,
+                                                uint2 *__restrict__ texel_out, float *__restrict__ depth_out)
+{
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y;
+    if (x >= W || y >= H) return;
+    const uint8_t *p = rgb + (int64_t)y * rgb_pitch + (int64_t)x * 3;
+    const uint32_t c = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | 0xFF000000u;
+    const uint16_t d = *(const uint16_t *)((const uint8_t *)depth + (int64_t)y * depth_pitch + (int64_t)x * 2);
+    uint32_t zb = FVV_NO_DEPTH;
+    if (d != 0) {
+        const float z = __fdiv_rn((float)d, 1000.0f);
+        const float s = __fadd_rn(__fmul_rn(alpha, z), beta);   // Eq. (1): (alpha z + beta) z
+        zb = f2u(__fmul_rn(s, z));
+    }
+    texel_out[(int64_t)y * W + x] = make_uint2(c, zb);
+    depth_out[(int64_t)y * W + x] = u2f(zb);
+}
+
+// ---------------------------------------------------------------- binning
+__device__ __forceinline__ int wave_min(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// One workgroup per (view, camera slot, 16x16 source block): exact bounding
+// box of the block's footprints, turned into the range of output tiles whose
+// window (tile plus 1-pixel halo) it touches; each such tile is counted.
+__global__ void __launch_bounds__(256) k_bin_count(const fvv_view_desc *__restrict__ views)
+{
+    const fvv_view_desc &vd = views[blockIdx.z];
+    const int k = blockIdx.y, blk = blockIdx.x;
+    if (k >= vd.K) return;
+    const fvv_src_desc &s = vd.src[k];
+    if (blk >= s.nblk) return;
+    const int by = blk / s.nbx, bx = blk - by * s.nbx;
+    const int i = bx * FVV_SBLK + (threadIdx.x & (FVV_SBLK - 1));
+    const int j = by * FVV_SBLK + (threadIdx.x / FVV_SBLK);
+    int x0 = INT_MAX, x1 = -1, y0 = INT_MAX, y1 = -1;
+    if (i < s.W && j < s.H) {
+        const uint32_t zb = f2u(s.depth[(int64_t)j * s.W + i]);
+        Footprint f;
+        if (zb != FVV_NO_DEPTH && splat_point(s, vd.W, vd.H, vd.max_fp, i, j, u2f(zb), f)) {
+            x0 = f.x0;
+            x1 = f.x1;
+            y0 = f.y0;
+            y1 = f.y1;
+        }
+    }
+    x0 = wave_min(x0);
+    y0 = wave_min(y0);
+    x1 = wave_max(x1);
+    y1 = wave_max(y1);
+    __shared__ int4 red[4];
+    __shared__ int4 range;
+    const int wid = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[wid] = make_int4(x0, x1, y0, y1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int4 r = red[0];
+        for (int w = 1; w < 4; ++w) {
+            r.x = min(r.x, red[w].x);
+            r.y = max(r.y, red[w].y);
+            r.z = min(r.z, red[w].z);
+            r.w = max(r.w, red[w].w);
+        }
+        int4 t = make_int4(1, 0, 1, 0);   // empty
+        if (r.y >= 0) {
+            t.x = max(0, (r.x + T - 1) / T - 1);
+            t.y = min(vd.ntx - 1, (r.y + 1) / T);
+            t.z = max(0, (r.z + T - 1) / T - 1);
+            t.w = min(vd.nty - 1, (r.w + 1) / T);
+        }
+        vd.bbox[(int64_t)k * vd.blk_stride + blk] = t;
+        range = t;
+    }
+    __syncthreads();
+    const int4 t = range;
+    if (t.x > t.y) return;
+    const int nx = t.y - t.x + 1, n = nx * (t.w - t.z + 1);
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        const int ty = t.z + e / nx, tx = t.x + e % nx;
+        atomicAdd(&vd.counts[ty * vd.ntx + tx], 1);
+    }
+}
+
+// One workgroup per view: exclusive scan of the tile counts into list
+// offsets (and fill cursors); counters are cleared for the next call.
+__global__ void __launch_bounds__(256) k_bin_scan(const fvv_view_desc *__restrict__ views)
+{
+    const fvv_view_desc &vd = views[blockIdx.x];
+    const int n = vd.ntx * vd.nty;
+    const int t = threadIdx.x;
+    const int C = (n + 255) / 256;
+    const int e0 = min(t * C, n), e1 = min(e0 + C, n);
+    int sum = 0;
+    for (int e = e0; e < e1; ++e) sum += vd.counts[e];
+    __shared__ int sc[256];
+    sc[t] = sum;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+        const int a = t >= d ? sc[t - d] : 0;
+        __syncthreads();
+        sc[t] += a;
+        __syncthreads();
+    }
+    int run = sc[t] - sum;
+    for (int e = e0; e < e1; ++e) {
+        const int c = vd.counts[e];
+        vd.offs[e] = run;
+        vd.cursor[e] = run;
+        vd.counts[e] = 0;
+        run += c;
+    }
+    if (t == 255) *vd.overflow = sc[255] > vd.list_cap ? 1 : 0;
+}
+
+// One thread per (view, camera slot, source block): append the block to the
+// list of every tile in its range.
+__global__ void __launch_bounds__(256) k_bin_fill(const fvv_view_desc *__restrict__ views)
+{
+    const fvv_view_desc &vd = views[blockIdx.z];
+    const int k = blockIdx.y;
+    const int blk = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= vd.K || blk >= vd.src[k].nblk) return;
+    if (*vd.overflow) return;
+    const int4 t = vd.bbox[(int64_t)k * vd.blk_stride + blk];
+    for (int ty = t.z; ty <= t.w; ++ty)
+        for (int tx = t.x; tx <= t.y; ++tx) {
+            const int pos = atomicAdd(&vd.cursor[ty * vd.ntx + tx], 1);
+            vd.list[pos] = (k << 24) | blk;
+        }
 }
 
 // ---------------------------------------------------------------- filter
@@ -118,13 +238,14 @@ __device__ __forceinline__ unsigned long long lower_median8(const unsigned long 
     for (int a = 0; a < 8; ++a) {
         int r = 0;
 #pragma unroll
-        for (int b = 0; b < 8; ++b)
-            r += (v[b] < v[a]) || (v[b] == v[a] && b < a);
+        for (int b = 0; b < 8; ++b) r += (v[b] < v[a]) || (v[b] == v[a] && b < a);
         if (r == m) res = v[a];
     }
     return res;
 }
 
+// Crack fill (empty key, >= 5 valid neighbours) and speckle removal (valid
+// key, >= 5 valid neighbours, none within tau z0) take the lower median.
 __device__ __forceinline__ unsigned long long filter_key(unsigned long long c, const unsigned long long v[8],
                                                          float tau)
 {
@@ -145,7 +266,10 @@ __device__ __forceinline__ unsigned long long filter_key(unsigned long long c, c
 }
 
 // ---------------------------------------------------------------- blend
-// Returns true and the RGBA8 colour if any camera contributes.
+// Backward warp of output pixel (x, y) at depth zf into every selected
+// camera; taps whose source depth agrees with the warped depth within tau
+// are mixed bilinearly, cameras by their distance weights.  Returns true and
+// the RGBA8 colour if any camera contributes.
 __device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int x, int y, float zf, uint32_t &rgba)
 {
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, wsum = 0.f;
@@ -168,14 +292,12 @@ __device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int x, int 
         for (int n = 0; n < 4; ++n) {
             const int ti = i0 + (n & 1), tj = j0 + (n >> 1);
             if (ti < 0 || tj < 0 || ti >= s.W || tj >= s.H) continue;
-            const int64_t o = (int64_t)tj * s.W + ti;
-            const uint32_t zs = f2u(s.depth[o]);
-            if (zs == FVV_NO_DEPTH) continue;
-            if (!(fabsf(__fsub_rn(u2f(zs), q2)) <= lim)) continue;
-            const uint32_t t = s.rgba[o];
-            c0 += wt[n] * (float)(t & 0xFF);
-            c1 += wt[n] * (float)((t >> 8) & 0xFF);
-            c2 += wt[n] * (float)((t >> 16) & 0xFF);
+            const uint2 tx = s.texel[(int64_t)tj * s.W + ti];
+            if (tx.y == FVV_NO_DEPTH) continue;
+            if (!(fabsf(__fsub_rn(u2f(tx.y), q2)) <= lim)) continue;
+            c0 += wt[n] * (float)(tx.x & 0xFF);
+            c1 += wt[n] * (float)((tx.x >> 8) & 0xFF);
+            c2 += wt[n] * (float)((tx.x >> 16) & 0xFF);
             csum += wt[n];
         }
         if (!(csum > 0.f)) continue;
@@ -193,119 +315,6 @@ __device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int x, int 
     return true;
 }
 
-// 16x16 output tile per workgroup; the raw key map with a 1-pixel halo is
-// staged in LDS, filtered, then each pixel is blended.
-#define TB 16
-__global__ void __launch_bounds__(256) k_filter_blend(const fvv_view_desc *__restrict__ views)
-{
-    const fvv_view_desc &vd = views[blockIdx.z];
-    const int W = vd.W, H = vd.H;
-    const int tx0 = blockIdx.x * TB, ty0 = blockIdx.y * TB;
-    if (tx0 >= W || ty0 >= H) return;
-    __shared__ unsigned long long tile[TB + 2][TB + 2];
-    const int tid = threadIdx.y * TB + threadIdx.x;
-    for (int e = tid; e < (TB + 2) * (TB + 2); e += TB * TB) {
-        const int ly = e / (TB + 2), lx = e - ly * (TB + 2);
-        const int gx = tx0 + lx - 1, gy = ty0 + ly - 1;
-        tile[ly][lx] = (gx >= 0 && gy >= 0 && gx < W && gy < H) ? vd.Z[(int64_t)gy * W + gx] : FVV_KEY_EMPTY;
-    }
-    __syncthreads();
-    const int x = tx0 + threadIdx.x, y = ty0 + threadIdx.y;
-    if (x >= W || y >= H) return;
-    const int lx = threadIdx.x + 1, ly = threadIdx.y + 1;
-    const unsigned long long nb[8] = {tile[ly - 1][lx - 1], tile[ly - 1][lx], tile[ly - 1][lx + 1],
-                                      tile[ly][lx - 1],                       tile[ly][lx + 1],
-                                      tile[ly + 1][lx - 1], tile[ly + 1][lx], tile[ly + 1][lx + 1]};
-    const unsigned long long kf = filter_key(tile[ly][lx], nb, vd.tau);
-    const int64_t o = (int64_t)y * W + x;
-    if (vd.Zf) vd.Zf[o] = kf;
-    uint32_t col = 0, slot = FVV_HOLE_BIT;
-    if (kf != FVV_KEY_EMPTY) {
-        const float zf = u2f((uint32_t)(kf >> 32));
-        if (blend_pixel(vd, x, y, zf, col)) slot = f2u(zf);
-    }
-    vd.rgba[o] = col;
-    vd.slot[o] = slot;
-    if (vd.dbg_depth) vd.dbg_depth[o] = (slot & FVV_HOLE_BIT) ? 0.0f : u2f(slot);
-}
-
-// ---------------------------------------------------------------- hole fill
-// Row pass: for every hole, the better of its nearest non-hole neighbours to
-// the left and right (larger depth, then nearer, then left) is stored in the
-// hole's slot as FVV_HOLE_BIT | (x + 1); FVV_HOLE_BIT alone = none.
-__global__ void __launch_bounds__(256) k_fill_rows(const fvv_view_desc *__restrict__ views)
-{
-    const fvv_view_desc &vd = views[blockIdx.y];
-    const int y = blockIdx.x;
-    const int W = vd.W;
-    if (y >= vd.H) return;
-    uint32_t *row = vd.slot + (int64_t)y * W;
-    const int t = threadIdx.x;
-    const int C = (W + 255) >> 8;
-    const int x0 = min(t * C, W), x1 = min(x0 + C, W);
-    int last = -1, first = W;
-    for (int x = x0; x < x1; ++x)
-        if (!(row[x] & FVV_HOLE_BIT)) {
-            if (first == W) first = x;
-            last = x;
-        }
-    __shared__ int sl[256], sf[256];
-    sl[t] = last;
-    sf[t] = first;
-    __syncthreads();
-    // inclusive prefix max of `last` and suffix min of `first` (Hillis-Steele)
-    for (int d = 1; d < 256; d <<= 1) {
-        const int a = t >= d ? sl[t - d] : -1;
-        const int b = t + d < 256 ? sf[t + d] : W;
-        __syncthreads();
-        sl[t] = max(sl[t], a);
-        sf[t] = min(sf[t], b);
-        __syncthreads();
-    }
-    int L = t > 0 ? sl[t - 1] : -1;
-    const int carryR = t < 255 ? sf[t + 1] : W;
-    for (int x = x0; x < x1; ++x) {
-        const uint32_t s = row[x];
-        if (!(s & FVV_HOLE_BIT)) {
-            L = x;
-            continue;
-        }
-        int R = carryR;
-        for (int xr = x + 1; xr < x1; ++xr)
-            if (!(row[xr] & FVV_HOLE_BIT)) {
-                R = xr;
-                break;
-            }
-        int win = -1;
-        if (L >= 0 && R < W) {
-            const float zl = u2f(row[L]), zr = u2f(row[R]);
-            win = (zl > zr || (zl == zr && x - L <= R - x)) ? L : R;
-        } else if (L >= 0) {
-            win = L;
-        } else if (R < W) {
-            win = R;
-        }
-        row[x] = FVV_HOLE_BIT | (uint32_t)(win + 1);
-    }
-}
-
-// Column summaries: first and last non-hole row of each FVV_FILL_SEG-row
-// segment of each column (-1 if none).
-__global__ void __launch_bounds__(64) k_fill_colsum(const fvv_view_desc *__restrict__ views)
-{
-    const fvv_view_desc &vd = views[blockIdx.z];
-    const int x = blockIdx.x * 64 + threadIdx.x, seg = blockIdx.y;
-    if (x >= vd.W || seg >= vd.n_seg) return;
-    const int r0 = seg * FVV_FILL_SEG, r1 = min(r0 + FVV_FILL_SEG, vd.H);
-    int first = -1, last = -1;
-    for (int r = r0; r < r1; ++r)
-        if (!(vd.slot[(int64_t)r * vd.W + x] & FVV_HOLE_BIT)) {
-            if (first < 0) first = r;
-            last = r;
-        }
-    vd.colsum[(int64_t)seg * vd.W + x] = make_int2(first, last);
-}
-
 __device__ __forceinline__ void put_rgb(uint8_t *out, int64_t pitch, int x, int y, uint32_t c)
 {
     uint8_t *p = out + (int64_t)y * pitch + (int64_t)x * 3;
@@ -314,79 +323,283 @@ __device__ __forceinline__ void put_rgb(uint8_t *out, int64_t pitch, int x, int 
     p[2] = (uint8_t)(c >> 16);
 }
 
-// Column pass: combine the row winner with the nearest non-holes above and
-// below (larger depth, then nearer; row candidates before up before down),
-// copy the winner's colour; non-holes copy their own.  Writes the output.
-__global__ void __launch_bounds__(64) k_fill_resolve(const fvv_view_desc *__restrict__ views)
+__device__ __forceinline__ uint32_t get_rgb(const uint8_t *out, int64_t pitch, int x, int y)
+{
+    const uint8_t *p = out + (int64_t)y * pitch + (int64_t)x * 3;
+    return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16);
+}
+
+// Hole-fill preference: larger depth, then nearer, then the earlier
+// direction (callers offer candidates in the order left, right, up, down).
+struct Cand {
+    float z;
+    int dist;
+    int idx;    // tile-local or image index of the chosen pixel, -1 none
+};
+
+__device__ __forceinline__ void offer(Cand &b, float z, int dist, int idx)
+{
+    if (b.idx < 0 || z > b.z || (z == b.z && dist < b.dist)) {
+        b.z = z;
+        b.dist = dist;
+        b.idx = idx;
+    }
+}
+
+// ---------------------------------------------------------------- fused tile
+__global__ void __launch_bounds__(256) k_tile(const fvv_view_desc *__restrict__ views)
 {
     const fvv_view_desc &vd = views[blockIdx.z];
-    const int x = blockIdx.x * 64 + threadIdx.x, seg = blockIdx.y;
+    const int tx = blockIdx.x, ty = blockIdx.y;
+    if (tx >= vd.ntx || ty >= vd.nty) return;
     const int W = vd.W, H = vd.H;
-    if (x >= W || seg >= vd.n_seg) return;
-    const int r0 = seg * FVV_FILL_SEG, r1 = min(r0 + FVV_FILL_SEG, H);
-    const bool fill = vd.fill_mode == 0;
-    __shared__ short below[FVV_FILL_SEG][64];
-    int up = -1;
-    if (fill) {
-        for (int s2 = seg - 1; s2 >= 0; --s2) {
-            const int l = vd.colsum[(int64_t)s2 * W + x].y;
-            if (l >= 0) {
-                up = l;
-                break;
-            }
+    const int tile = ty * vd.ntx + tx;
+    const int X0 = tx * T, Y0 = ty * T;
+    const int WX0 = X0 - 1, WY0 = Y0 - 1;
+    const int tw = min(T, W - X0), th = min(T, H - Y0);
+    __shared__ unsigned long long zk[WN * WN];
+    __shared__ uint32_t s_slot[T * T];
+    __shared__ uint32_t s_rgb[T * T];
+    __shared__ int s_open;
+    const int t = threadIdx.x;
+    for (int e = t; e < WN * WN; e += 256) zk[e] = FVV_KEY_EMPTY;
+    if (t == 0) s_open = 0;
+    __syncthreads();
+
+    // ---- S1: splat every binned source block into the window
+    const bool scan_all = *vd.overflow != 0;
+    const int beg = scan_all ? 0 : vd.offs[tile];
+    const int end = scan_all ? vd.K * vd.blk_stride : vd.cursor[tile];
+    const int si = t & (FVV_SBLK - 1), sj = t / FVV_SBLK;
+    for (int e = beg; e < end; ++e) {
+        int k, blk;
+        if (!scan_all) {
+            const int ent = vd.list[e];
+            k = ent >> 24;
+            blk = ent & 0xFFFFFF;
+        } else {
+            k = e / vd.blk_stride;
+            blk = e - k * vd.blk_stride;
+            if (blk >= vd.src[k].nblk) continue;
+            const int4 r = vd.bbox[e];
+            if (!(r.x <= tx && tx <= r.y && r.z <= ty && ty <= r.w)) continue;
         }
-        int nd = H;
-        for (int s2 = seg + 1; s2 < vd.n_seg; ++s2) {
-            const int f = vd.colsum[(int64_t)s2 * W + x].x;
-            if (f >= 0) {
-                nd = f;
-                break;
-            }
-        }
-        for (int r = r1 - 1; r >= r0; --r) {
-            below[r - r0][threadIdx.x] = (short)min(nd, 32767);
-            if (!(vd.slot[(int64_t)r * W + x] & FVV_HOLE_BIT)) nd = r;
-        }
+        const fvv_src_desc &s = vd.src[k];
+        const int by = blk / s.nbx, bx = blk - by * s.nbx;
+        const int i = bx * FVV_SBLK + si, j = by * FVV_SBLK + sj;
+        if (i >= s.W || j >= s.H) continue;
+        const uint32_t zb = f2u(s.depth[(int64_t)j * s.W + i]);
+        if (zb == FVV_NO_DEPTH) continue;
+        Footprint f;
+        if (!splat_point(s, W, H, vd.max_fp, i, j, u2f(zb), f)) continue;
+        const int xa = max(f.x0, WX0), xb = min(f.x1, WX0 + WN - 1);
+        const int ya = max(f.y0, WY0), yb = min(f.y1, WY0 + WN - 1);
+        for (int y = ya; y <= yb; ++y)
+            for (int x = xa; x <= xb; ++x) atomicMin(&zk[(y - WY0) * WN + (x - WX0)], f.key);
     }
-    for (int r = r0; r < r1; ++r) {
-        const uint32_t s = vd.slot[(int64_t)r * W + x];
-        if (!(s & FVV_HOLE_BIT)) {
-            put_rgb(vd.out, vd.out_pitch, x, r, vd.rgba[(int64_t)r * W + x]);
-            up = r;
-            continue;
-        }
-        uint32_t col = 0;
-        if (fill) {
-            int64_t src = -1;
-            float zb = 0.f;
-            int db = 0;
-            const int rw = (int)(s & ~FVV_HOLE_BIT);
-            if (rw > 0) {
-                const int xw = rw - 1;
-                src = (int64_t)r * W + xw;
-                zb = u2f(vd.slot[src]);
-                db = abs(xw - x);
+    __syncthreads();
+
+    // ---- S2 + S3: filter and blend four horizontally adjacent pixels
+    const int ly = t >> 3, lx0 = (t & 7) * 4;
+    const int y = Y0 + ly;
+    unsigned long long w3[3][6];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 6; ++c) w3[r][c] = zk[(ly + r) * WN + lx0 + c];
+    uint32_t pslot[4], prgb[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int x = X0 + lx0 + q;
+        pslot[q] = FVV_HOLE;
+        prgb[q] = 0;
+        if (x >= W || y >= H) continue;
+        const unsigned long long c = w3[1][q + 1];
+        const unsigned long long nb[8] = {w3[0][q], w3[0][q + 1], w3[0][q + 2], w3[1][q],
+                                          w3[1][q + 2], w3[2][q], w3[2][q + 1], w3[2][q + 2]};
+        const unsigned long long kf = filter_key(c, nb, vd.tau);
+        if (kf != FVV_KEY_EMPTY) {
+            const float zf = u2f((uint32_t)(kf >> 32));
+            uint32_t col;
+            if (blend_pixel(vd, x, y, zf, col)) {
+                pslot[q] = f2u(zf);
+                prgb[q] = col;
             }
-            if (up >= 0) {
-                const int64_t o = (int64_t)up * W + x;
-                const float zu = u2f(vd.slot[o]);
-                const int du = r - up;
-                if (src < 0 || zu > zb || (zu == zb && du < db)) {
-                    src = o;
-                    zb = zu;
-                    db = du;
+        }
+        const int64_t o = (int64_t)y * W + x;
+        if (vd.dbg_z) vd.dbg_z[o] = c;
+        if (vd.dbg_zf) vd.dbg_zf[o] = kf;
+        if (vd.dbg_rgba) vd.dbg_rgba[o] = prgb[q];
+        if (vd.dbg_depth) vd.dbg_depth[o] = (pslot[q] & FVV_HOLE) ? 0.0f : u2f(pslot[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        s_slot[ly * T + lx0 + q] = pslot[q];
+        s_rgb[ly * T + lx0 + q] = prgb[q];
+    }
+    __syncthreads();
+
+    // ---- S4 (local): holes whose nearest covered pixel in every direction
+    // lies inside the tile (or beyond the image edge) are filled here; the
+    // others are marked open for the second pass.
+    const bool fill = vd.fill_mode == 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int lx = lx0 + q;
+        if (lx >= tw || ly >= th) continue;
+        const int x = X0 + lx;
+        uint32_t sl = pslot[q], col = prgb[q];
+        if (sl & FVV_HOLE) {
+            col = 0;
+            if (fill) {
+                Cand b{0.f, 0, -1};
+                bool open = false;
+                int xl = lx - 1;
+                while (xl >= 0 && (s_slot[ly * T + xl] & FVV_HOLE)) --xl;
+                if (xl >= 0) offer(b, u2f(s_slot[ly * T + xl]), lx - xl, ly * T + xl);
+                else open = X0 > 0;
+                if (!open) {
+                    int xr = lx + 1;
+                    while (xr < tw && (s_slot[ly * T + xr] & FVV_HOLE)) ++xr;
+                    if (xr < tw) offer(b, u2f(s_slot[ly * T + xr]), xr - lx, ly * T + xr);
+                    else open = X0 + tw < W;
+                }
+                if (!open) {
+                    int yu = ly - 1;
+                    while (yu >= 0 && (s_slot[yu * T + lx] & FVV_HOLE)) --yu;
+                    if (yu >= 0) offer(b, u2f(s_slot[yu * T + lx]), ly - yu, yu * T + lx);
+                    else open = Y0 > 0;
+                }
+                if (!open) {
+                    int yd = ly + 1;
+                    while (yd < th && (s_slot[yd * T + lx] & FVV_HOLE)) ++yd;
+                    if (yd < th) offer(b, u2f(s_slot[yd * T + lx]), yd - ly, yd * T + lx);
+                    else open = Y0 + th < H;
+                }
+                if (open) {
+                    sl = FVV_HOLE_OPEN;
+                    atomicAdd(&s_open, 1);
+                } else {
+                    sl = FVV_HOLE;
+                    if (b.idx >= 0) col = s_rgb[b.idx];
+                }
+            } else {
+                sl = FVV_HOLE;
+            }
+        }
+        vd.slot[(int64_t)y * W + x] = sl;
+        put_rgb(vd.out, vd.out_pitch, x, y, col);
+    }
+
+    // ---- per-tile row / column summaries of covered pixels for the open pass
+    if (t < T) {
+        int first = -1, last = -1;
+        if (t < th)
+            for (int c = 0; c < tw; ++c)
+                if (!(s_slot[t * T + c] & FVV_HOLE)) {
+                    if (first < 0) first = X0 + c;
+                    last = X0 + c;
+                }
+        vd.rowsum[(int64_t)tile * T + t] = make_int2(first, last);
+    } else if (t < 2 * T) {
+        const int c = t - T;
+        int first = -1, last = -1;
+        if (c < tw)
+            for (int r = 0; r < th; ++r)
+                if (!(s_slot[r * T + c] & FVV_HOLE)) {
+                    if (first < 0) first = Y0 + r;
+                    last = Y0 + r;
+                }
+        vd.colsum[(int64_t)tile * T + c] = make_int2(first, last);
+    }
+    __syncthreads();
+    if (t == 0) vd.open[tile] = s_open;
+}
+
+// ---------------------------------------------------------------- open holes
+// Holes whose nearest covered neighbour in some direction lies outside their
+// tile: scan the tile, then walk the per-tile summaries of the row or column.
+__global__ void __launch_bounds__(256) k_fill_open(const fvv_view_desc *__restrict__ views)
+{
+    const fvv_view_desc &vd = views[blockIdx.z];
+    const int tx = blockIdx.x, ty = blockIdx.y;
+    if (tx >= vd.ntx || ty >= vd.nty) return;
+    const int tile = ty * vd.ntx + tx;
+    if (vd.open[tile] == 0) return;
+    const int W = vd.W, H = vd.H;
+    const int X0 = tx * T, Y0 = ty * T;
+    const int tw = min(T, W - X0), th = min(T, H - Y0);
+    const uint32_t *slot = vd.slot;
+    for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
+        const int ly = e / T, lx = e - ly * T;
+        if (lx >= tw || ly >= th) continue;
+        const int x = X0 + lx, y = Y0 + ly;
+        if (slot[(int64_t)y * W + x] != FVV_HOLE_OPEN) continue;
+        const int64_t row = (int64_t)y * W;
+        // left
+        int xl = x - 1;
+        while (xl >= X0 && (slot[row + xl] & FVV_HOLE)) --xl;
+        if (xl < X0) {
+            xl = -1;
+            for (int t2 = tx - 1; t2 >= 0; --t2) {
+                const int l = vd.rowsum[(int64_t)(ty * vd.ntx + t2) * T + ly].y;
+                if (l >= 0) {
+                    xl = l;
+                    break;
                 }
             }
-            const int dn = below[r - r0][threadIdx.x];
-            if (dn < H) {
-                const int64_t o = (int64_t)dn * W + x;
-                const float zd = u2f(vd.slot[o]);
-                const int dd = dn - r;
-                if (src < 0 || zd > zb || (zd == zb && dd < db)) src = o;
-            }
-            if (src >= 0) col = vd.rgba[src];
         }
-        put_rgb(vd.out, vd.out_pitch, x, r, col);
+        // right
+        int xr = x + 1;
+        while (xr < X0 + tw && (slot[row + xr] & FVV_HOLE)) ++xr;
+        if (xr >= X0 + tw) {
+            xr = -1;
+            for (int t2 = tx + 1; t2 < vd.ntx; ++t2) {
+                const int f = vd.rowsum[(int64_t)(ty * vd.ntx + t2) * T + ly].x;
+                if (f >= 0) {
+                    xr = f;
+                    break;
+                }
+            }
+        }
+        // candidates carry image indices y*W + x
+        Cand c{0.f, 0, -1};
+        if (xl >= 0) offer(c, u2f(slot[row + xl]), x - xl, y * W + xl);
+        if (xr >= 0) offer(c, u2f(slot[row + xr]), xr - x, y * W + xr);
+        // up
+        int yu = y - 1;
+        while (yu >= Y0 && (slot[(int64_t)yu * W + x] & FVV_HOLE)) --yu;
+        if (yu < Y0) {
+            yu = -1;
+            for (int t2 = ty - 1; t2 >= 0; --t2) {
+                const int l = vd.colsum[(int64_t)(t2 * vd.ntx + tx) * T + lx].y;
+                if (l >= 0) {
+                    yu = l;
+                    break;
+                }
+            }
+        }
+        if (yu >= 0) offer(c, u2f(slot[(int64_t)yu * W + x]), y - yu, yu * W + x);
+        // down
+        int yd = y + 1;
+        while (yd < Y0 + th && (slot[(int64_t)yd * W + x] & FVV_HOLE)) ++yd;
+        if (yd >= Y0 + th) {
+            yd = -1;
+            for (int t2 = ty + 1; t2 < vd.nty; ++t2) {
+                const int f = vd.colsum[(int64_t)(t2 * vd.ntx + tx) * T + lx].x;
+                if (f >= 0) {
+                    yd = f;
+                    break;
+                }
+            }
+        }
+        if (yd >= 0) offer(c, u2f(slot[(int64_t)yd * W + x]), yd - y, yd * W + x);
+        uint32_t col = 0;
+        if (c.idx >= 0) {
+            const int cy = c.idx / W, cx = c.idx - cy * W;
+            col = get_rgb(vd.out, vd.out_pitch, cx, cy);
+        }
+        put_rgb(vd.out, vd.out_pitch, x, y, col);
     }
 }
 
@@ -394,45 +607,40 @@ __global__ void __launch_bounds__(64) k_fill_resolve(const fvv_view_desc *__rest
 
 hipError_t fvv_launch_repack(const uint8_t *rgb, int64_t rgb_pitch, const uint16_t *depth,
                              int64_t depth_pitch, int W, int H, float alpha, float beta,
-                             uint32_t *rgba_out, float *depth_out, hipStream_t s, fvv_prof *prof)
+                             uint2 *texel_out, float *depth_out, hipStream_t s, fvv_prof *prof)
 {
     dim3 grid((W + 255) / 256, H);
     hipEvent_t e0;
     fvv_prof_begin(prof, s, e0);
     hipLaunchKernelGGL(k_repack, grid, dim3(256), 0, s, rgb, rgb_pitch, depth, depth_pitch, W, H, alpha,
-                       beta, rgba_out, depth_out);
+                       beta, texel_out, depth_out);
     fvv_prof_end(prof, s, FVV_ST_REPACK, e0);
     return hipGetLastError();
 }
 
-hipError_t fvv_launch_synthesis(const fvv_view_desc *d_views, int n_views, int max_w, int max_h,
-                                int max_src_px, int max_k, bool fill_bg, hipStream_t s, fvv_prof *prof)
+hipError_t fvv_launch_synthesis(const fvv_view_desc *d_views, const fvv_batch_dims &b, hipStream_t s,
+                                fvv_prof *prof)
 {
-    if (n_views <= 0) return hipSuccess;
-    const int64_t max_px = (int64_t)max_w * max_h;
-    const int zblocks = (int)std::min<int64_t>((max_px + 255) / 256, 4096);
-    const int n_seg = (max_h + FVV_FILL_SEG - 1) / FVV_FILL_SEG;
+    if (b.n_views <= 0) return hipSuccess;
     hipEvent_t e0;
     fvv_prof_begin(prof, s, e0);
-    hipLaunchKernelGGL(k_zclear, dim3(zblocks, n_views), dim3(256), 0, s, d_views);
-    fvv_prof_end(prof, s, FVV_ST_ZCLEAR, e0);
+    hipLaunchKernelGGL(k_bin_count, dim3(b.max_blocks, b.max_k, b.n_views), dim3(256), 0, s, d_views);
+    fvv_prof_end(prof, s, FVV_ST_BIN_COUNT, e0);
     fvv_prof_begin(prof, s, e0);
-    hipLaunchKernelGGL(k_splat, dim3((max_src_px + 255) / 256, max_k, n_views), dim3(256), 0, s, d_views);
-    fvv_prof_end(prof, s, FVV_ST_SPLAT, e0);
+    hipLaunchKernelGGL(k_bin_scan, dim3(b.n_views), dim3(256), 0, s, d_views);
+    fvv_prof_end(prof, s, FVV_ST_BIN_SCAN, e0);
     fvv_prof_begin(prof, s, e0);
-    hipLaunchKernelGGL(k_filter_blend, dim3((max_w + TB - 1) / TB, (max_h + TB - 1) / TB, n_views),
-                       dim3(TB, TB), 0, s, d_views);
-    fvv_prof_end(prof, s, FVV_ST_FILTER_BLEND, e0);
-    if (fill_bg) {
+    hipLaunchKernelGGL(k_bin_fill, dim3((b.max_blocks + 255) / 256, b.max_k, b.n_views), dim3(256), 0, s,
+                       d_views);
+    fvv_prof_end(prof, s, FVV_ST_BIN_FILL, e0);
+    fvv_prof_begin(prof, s, e0);
+    hipLaunchKernelGGL(k_tile, dim3(b.max_tiles_x, b.max_tiles_y, b.n_views), dim3(256), 0, s, d_views);
+    fvv_prof_end(prof, s, FVV_ST_TILE, e0);
+    if (b.fill_bg) {
         fvv_prof_begin(prof, s, e0);
-        hipLaunchKernelGGL(k_fill_rows, dim3(max_h, n_views), dim3(256), 0, s, d_views);
-        fvv_prof_end(prof, s, FVV_ST_FILL_ROWS, e0);
-        fvv_prof_begin(prof, s, e0);
-        hipLaunchKernelGGL(k_fill_colsum, dim3((max_w + 63) / 64, n_seg, n_views), dim3(64), 0, s, d_views);
-        fvv_prof_end(prof, s, FVV_ST_FILL_COLSUM, e0);
+        hipLaunchKernelGGL(k_fill_open, dim3(b.max_tiles_x, b.max_tiles_y, b.n_views), dim3(256), 0, s,
+                           d_views);
+        fvv_prof_end(prof, s, FVV_ST_FILL_OPEN, e0);
     }
-    fvv_prof_begin(prof, s, e0);
-    hipLaunchKernelGGL(k_fill_resolve, dim3((max_w + 63) / 64, n_seg, n_views), dim3(64), 0, s, d_views);
-    fvv_prof_end(prof, s, FVV_ST_FILL_RESOLVE, e0);
     return hipGetLastError();
 }

@@ -37,7 +37,7 @@ struct DeviceGuard {
 
 struct FrameSlot {
     uint64_t version = 0;                 // 0 = empty
-    std::vector<uint32_t *> rgba;         // per camera, null if absent
+    std::vector<uint2 *> texel;           // per camera {RGBA8, depth bits}
     std::vector<float *> depth;
     std::vector<int32_t> present;
     hipEvent_t ready = nullptr;           // recorded after the repack
@@ -72,14 +72,17 @@ struct fvv_ctx {
     hipEvent_t h_desc_ev[kRing] = {nullptr, nullptr, nullptr, nullptr};
     bool h_desc_ev_live[kRing] = {false, false, false, false};
     int ring = 0;
+    // tile counters of the binning: zero between calls (cleared by the scan)
+    int32_t *counts = nullptr;
+    size_t counts_cap = 0;   // entries
     // debug taps of view 0 of the last synthesis
     bool debug = false;
+    unsigned long long *dbg_z = nullptr;
     unsigned long long *dbg_zf = nullptr;
+    uint32_t *dbg_rgba = nullptr;
     float *dbg_depth = nullptr;
     size_t dbg_px = 0;
     int64_t last_px = 0;
-    unsigned long long *last_z = nullptr;
-    uint32_t *last_rgba = nullptr;
     bool have_taps = false;
     // stage timing
     bool profiling = false;
@@ -244,13 +247,13 @@ void pair_dir(const fvv_camera &s, const fvv_camera &d, float M[9], float m[3])
 int32_t ensure_frame_slot(fvv_ctx *c, FrameSlot &s)
 {
     const int n = (int)c->rig.size();
-    if ((int)s.rgba.size() == n && s.ready) return FVV_OK;
-    s.rgba.assign(n, nullptr);
+    if ((int)s.texel.size() == n && s.ready) return FVV_OK;
+    s.texel.assign(n, nullptr);
     s.depth.assign(n, nullptr);
     s.present.assign(n, 0);
     for (int k = 0; k < n; ++k) {
         const size_t px = (size_t)c->rig[k].width * c->rig[k].height;
-        int32_t rc = dalloc(c, (void **)&s.rgba[k], px * 4);
+        int32_t rc = dalloc(c, (void **)&s.texel[k], px * 8);
         if (rc) return rc;
         rc = dalloc(c, (void **)&s.depth[k], px * 4);
         if (rc) return rc;
@@ -263,12 +266,12 @@ int32_t ensure_frame_slot(fvv_ctx *c, FrameSlot &s)
 void release_frames(fvv_ctx *c)
 {
     for (auto &s : c->slots) {
-        for (size_t k = 0; k < s.rgba.size(); ++k) {
+        for (size_t k = 0; k < s.texel.size(); ++k) {
             const size_t px = (size_t)c->rig[k].width * c->rig[k].height;
-            dfree(c, s.rgba[k], px * 4);
+            dfree(c, s.texel[k], px * 8);
             dfree(c, s.depth[k], px * 4);
         }
-        s.rgba.clear();
+        s.texel.clear();
         s.depth.clear();
         s.present.clear();
         s.version = 0;
@@ -279,12 +282,24 @@ void release_frames(fvv_ctx *c)
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-// bytes of workspace one view of W x H needs
-size_t view_ws_bytes(int W, int H, bool host_out)
+struct ViewLayout {
+    int ntx, nty, n_tiles, blk_stride, list_cap, K;
+    int32_t idx[FVV_MAX_K];
+    double w[FVV_MAX_K];
+};
+
+// bytes of workspace one view needs: slot plane, tile arrays, bin list,
+// block ranges, and (host-memory output) an RGB8 staging image
+size_t view_ws_bytes(int W, int H, const ViewLayout &L, bool host_out)
 {
     const size_t px = (size_t)W * H;
-    const size_t nseg = (H + FVV_FILL_SEG - 1) / FVV_FILL_SEG;
-    size_t b = align256(px * 8) + align256(px * 4) * 2 + align256(nseg * W * sizeof(int2));
+    const size_t nt = (size_t)L.n_tiles;
+    size_t b = align256(px * 4);                                   // slot
+    b += align256(nt * 4) * 3;                                     // offs, cursor, open
+    b += align256(nt * FVV_TILE * sizeof(int2)) * 2;               // rowsum, colsum
+    b += align256((size_t)L.list_cap * 4);                         // list
+    b += align256((size_t)L.K * L.blk_stride * sizeof(int4));      // bbox
+    b += 256;                                                      // overflow flag
     if (host_out) b += align256(px * 3);
     return b;
 }
@@ -379,27 +394,62 @@ int32_t synthesize_impl(fvv_ctx *c, const fvv_camera *virts, int n_views, const 
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
     const bool host_out = mem_kind == FVV_MEM_HOST;
-    size_t total = 0;
-    int max_w = 0, max_h = 0;
+    const int n = (int)c->rig.size();
+    std::vector<ViewLayout> lay(n_views);
+    size_t total = 0, total_tiles = 0;
+    fvv_batch_dims dims{n_views, 0, 0, 0, 0, P.fill_mode == FVV_FILL_BG};
     for (int v = 0; v < n_views; ++v) {
-        total += view_ws_bytes(virts[v].width, virts[v].height, host_out);
-        max_w = std::max(max_w, virts[v].width);
-        max_h = std::max(max_h, virts[v].height);
+        ViewLayout &L = lay[v];
+        const fvv_camera &vc = virts[v];
+        L.K = select_k(c->rig.data(), fs.present.data(), n, vc, P.k_nearest, L.idx, L.w);
+        if (L.K < 1) return fail(c, FVV_E_STATE, "no camera present in the frame set");
+        L.ntx = (vc.width + FVV_TILE - 1) / FVV_TILE;
+        L.nty = (vc.height + FVV_TILE - 1) / FVV_TILE;
+        L.n_tiles = L.ntx * L.nty;
+        int sum_blk = 0, max_blk = 0;
+        for (int k = 0; k < L.K; ++k) {
+            const fvv_camera &sc = c->rig[L.idx[k]];
+            const int nb = ((sc.width + FVV_SBLK - 1) / FVV_SBLK) * ((sc.height + FVV_SBLK - 1) / FVV_SBLK);
+            sum_blk += nb;
+            max_blk = std::max(max_blk, nb);
+        }
+        L.blk_stride = max_blk;
+        L.list_cap = FVV_LIST_PER_BLOCK * sum_blk;
+        total += view_ws_bytes(vc.width, vc.height, L, host_out);
+        total_tiles += (size_t)L.n_tiles;
+        dims.max_k = std::max(dims.max_k, L.K);
+        dims.max_blocks = std::max(dims.max_blocks, max_blk);
+        dims.max_tiles_x = std::max(dims.max_tiles_x, L.ntx);
+        dims.max_tiles_y = std::max(dims.max_tiles_y, L.nty);
     }
     rc = ensure_ws(c, total);
     if (rc) return rc;
     rc = ensure_desc(c, n_views);
     if (rc) return rc;
+    if (c->counts_cap < total_tiles) {
+        HIPCHECK(c, hipDeviceSynchronize());
+        dfree(c, c->counts, c->counts_cap * 4);
+        c->counts = nullptr;
+        c->counts_cap = 0;
+        if ((rc = dalloc(c, (void **)&c->counts, total_tiles * 4))) return rc;
+        HIPCHECK(c, hipMemset(c->counts, 0, total_tiles * 4));
+        c->counts_cap = total_tiles;
+    }
     if (c->debug) {
         const size_t px = (size_t)virts[0].width * virts[0].height;
         if (c->dbg_px < px) {
             HIPCHECK(c, hipDeviceSynchronize());
+            dfree(c, c->dbg_z, c->dbg_px * 8);
             dfree(c, c->dbg_zf, c->dbg_px * 8);
+            dfree(c, c->dbg_rgba, c->dbg_px * 4);
             dfree(c, c->dbg_depth, c->dbg_px * 4);
-            c->dbg_zf = nullptr;
+            c->dbg_z = c->dbg_zf = nullptr;
+            c->dbg_rgba = nullptr;
             c->dbg_depth = nullptr;
             c->dbg_px = 0;
+            if ((rc = dalloc(c, (void **)&c->dbg_z, px * 8))) return rc;
             if ((rc = dalloc(c, (void **)&c->dbg_zf, px * 8))) return rc;
+            if ((rc = dalloc(c, (void **)&c->dbg_rgba, px * 4))) return rc;
             if ((rc = dalloc(c, (void **)&c->dbg_depth, px * 4))) return rc;
             c->dbg_px = px;
         }
@@ -409,77 +459,83 @@ int32_t synthesize_impl(fvv_ctx *c, const fvv_camera *virts, int n_views, const 
     c->ring = (c->ring + 1) % fvv_ctx::kRing;
     if (c->h_desc_ev_live[r]) HIPCHECK(c, hipEventSynchronize(c->h_desc_ev[r]));
     fvv_view_desc *hd = c->h_desc[r];
-    const int n = (int)c->rig.size();
     uint8_t *cur = c->ws;
-    int max_src = 0, max_k = 0;
+    int32_t *cnt = c->counts;
     std::vector<uint8_t *> host_stage(n_views, nullptr);
     for (int v = 0; v < n_views; ++v) {
         const fvv_camera &vc = virts[v];
+        const ViewLayout &L = lay[v];
         fvv_view_desc &d = hd[v];
         std::memset(&d, 0, sizeof d);
         d.W = vc.width;
         d.H = vc.height;
+        d.K = L.K;
         d.fill_mode = P.fill_mode;
         d.tau = P.tau_rel;
         d.max_fp = P.max_footprint;
-        d.n_seg = (vc.height + FVV_FILL_SEG - 1) / FVV_FILL_SEG;
+        d.ntx = L.ntx;
+        d.nty = L.nty;
+        d.blk_stride = L.blk_stride;
+        d.list_cap = L.list_cap;
         const size_t px = (size_t)vc.width * vc.height;
-        d.Z = (unsigned long long *)cur;
-        cur += align256(px * 8);
-        d.rgba = (uint32_t *)cur;
-        cur += align256(px * 4);
-        d.slot = (uint32_t *)cur;
-        cur += align256(px * 4);
-        d.colsum = (int2 *)cur;
-        cur += align256((size_t)d.n_seg * vc.width * sizeof(int2));
+        const size_t nt = (size_t)L.n_tiles;
+        auto carve = [&](size_t bytes) {
+            uint8_t *p = cur;
+            cur += align256(bytes);
+            return p;
+        };
+        d.slot = (uint32_t *)carve(px * 4);
+        d.offs = (int32_t *)carve(nt * 4);
+        d.cursor = (int32_t *)carve(nt * 4);
+        d.open = (int32_t *)carve(nt * 4);
+        d.rowsum = (int2 *)carve(nt * FVV_TILE * sizeof(int2));
+        d.colsum = (int2 *)carve(nt * FVV_TILE * sizeof(int2));
+        d.list = (int32_t *)carve((size_t)L.list_cap * 4);
+        d.bbox = (int4 *)carve((size_t)L.K * L.blk_stride * sizeof(int4));
+        d.overflow = (int32_t *)cur;
+        cur += 256;
+        d.counts = cnt;
+        cnt += nt;
         if (host_out) {
-            host_stage[v] = cur;
-            d.out = cur;
+            host_stage[v] = carve(px * 3);
+            d.out = host_stage[v];
             d.out_pitch = (int64_t)vc.width * 3;
-            cur += align256(px * 3);
         } else {
             d.out = (uint8_t *)outs[v];
             d.out_pitch = pitches[v];
         }
         if (c->debug && v == 0) {
-            d.Zf = c->dbg_zf;
+            d.dbg_z = c->dbg_z;
+            d.dbg_zf = c->dbg_zf;
+            d.dbg_rgba = c->dbg_rgba;
             d.dbg_depth = c->dbg_depth;
         }
-        int32_t idx[FVV_MAX_K];
-        double w[FVV_MAX_K];
-        const int K = select_k(c->rig.data(), fs.present.data(), n, vc, P.k_nearest, idx, w);
-        if (K < 1) return fail(c, FVV_E_STATE, "no camera present in the frame set");
-        d.K = K;
-        max_k = std::max(max_k, K);
-        for (int k = 0; k < K; ++k) {
-            const fvv_camera &sc = c->rig[idx[k]];
+        for (int k = 0; k < L.K; ++k) {
+            const fvv_camera &sc = c->rig[L.idx[k]];
             fvv_src_desc &sd = d.src[k];
-            sd.rgba = fs.rgba[idx[k]];
-            sd.depth = fs.depth[idx[k]];
+            sd.texel = fs.texel[L.idx[k]];
+            sd.depth = fs.depth[L.idx[k]];
             sd.W = sc.width;
             sd.H = sc.height;
-            sd.cam = idx[k];
-            sd.wgt = (float)w[k];
+            sd.cam = L.idx[k];
+            sd.nbx = (sc.width + FVV_SBLK - 1) / FVV_SBLK;
+            sd.nblk = sd.nbx * ((sc.height + FVV_SBLK - 1) / FVV_SBLK);
+            sd.wgt = (float)L.w[k];
             pair_dir(sc, vc, sd.A, sd.a);
             pair_dir(vc, sc, sd.B, sd.b);
             sd.sx = (float)((double)vc.fx / (double)sc.fx);
             sd.sy = (float)((double)vc.fy / (double)sc.fy);
-            max_src = std::max(max_src, sc.width * sc.height);
         }
     }
     HIPCHECK(c, hipStreamWaitEvent(s, fs.ready, 0));
     HIPCHECK(c, hipMemcpyAsync(c->d_desc, hd, (size_t)n_views * sizeof(fvv_view_desc), hipMemcpyHostToDevice, s));
     HIPCHECK(c, hipEventRecord(c->h_desc_ev[r], s));
     c->h_desc_ev_live[r] = true;
-    bool any_fill = P.fill_mode == FVV_FILL_BG;
-    HIPCHECK(c, fvv_launch_synthesis(c->d_desc, n_views, max_w, max_h, max_src, max_k, any_fill, s,
-                                     c->profiling ? &c->prof : nullptr));
+    HIPCHECK(c, fvv_launch_synthesis(c->d_desc, dims, s, c->profiling ? &c->prof : nullptr));
     HIPCHECK(c, hipEventRecord(fs.last_use, s));
     fs.used = true;
     c->have_taps = c->debug;
     c->last_px = (int64_t)virts[0].width * virts[0].height;
-    c->last_z = hd[0].Z;
-    c->last_rgba = hd[0].rgba;
     if (host_out) {
         for (int v = 0; v < n_views; ++v)
             HIPCHECK(c, hipMemcpy2DAsync(outs[v], pitches[v], host_stage[v], (size_t)virts[v].width * 3,
@@ -531,7 +587,10 @@ void fvv_destroy(fvv_ctx *c)
             if (c->h_desc[r]) (void)hipHostFree(c->h_desc[r]);
             if (c->h_desc_ev[r]) (void)hipEventDestroy(c->h_desc_ev[r]);
         }
+        dfree(c, c->counts, c->counts_cap * 4);
+        dfree(c, c->dbg_z, c->dbg_px * 8);
         dfree(c, c->dbg_zf, c->dbg_px * 8);
+        dfree(c, c->dbg_rgba, c->dbg_px * 4);
         dfree(c, c->dbg_depth, c->dbg_px * 4);
         for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
     }
@@ -608,7 +667,7 @@ int32_t fvv_upload_mvd(fvv_ctx *c, const fvv_view *views, int32_t n, int32_t mem
         HIPCHECK(c, hipMemcpy2DAsync(rgb, (size_t)W * 3, v.rgb, v.rgb_pitch, (size_t)W * 3, H, kind, s));
         HIPCHECK(c, hipMemcpy2DAsync(dep, (size_t)W * 2, v.depth_mm, v.depth_pitch, (size_t)W * 2, H, kind, s));
         HIPCHECK(c, fvv_launch_repack(rgb, (int64_t)W * 3, dep, (int64_t)W * 2, W, H, cam.depth_alpha,
-                                      cam.depth_beta, fs.rgba[k], fs.depth[k], s,
+                                      cam.depth_beta, fs.texel[k], fs.depth[k], s,
                                       c->profiling ? &c->prof : nullptr));
     }
     HIPCHECK(c, hipEventRecord(c->staging_free, s));
@@ -659,8 +718,8 @@ int32_t fvv_pair_matrices(const fvv_camera *src, const fvv_camera *virt, float *
     return FVV_OK;
 }
 
-static const char *k_stage_names[FVV_NSTAGES] = {"repack", "zclear", "splat", "filter_blend",
-                                                  "fill_rows", "fill_colsum", "fill_resolve"};
+static const char *k_stage_names[FVV_NSTAGES] = {"repack", "bin_count", "bin_scan", "bin_fill", "tile",
+                                                  "fill_open"};
 
 int32_t fvv_set_profiling(fvv_ctx *c, int32_t enable)
 {
@@ -717,9 +776,9 @@ int32_t fvv_debug_read(fvv_ctx *c, int32_t tap, void *host_out, int64_t bytes)
     const void *src = nullptr;
     int64_t need = 0;
     switch (tap) {
-    case FVV_TAP_Z_RAW: src = c->last_z; need = c->last_px * 8; break;
+    case FVV_TAP_Z_RAW: src = c->dbg_z; need = c->last_px * 8; break;
     case FVV_TAP_Z_FILT: src = c->dbg_zf; need = c->last_px * 8; break;
-    case FVV_TAP_BLEND: src = c->last_rgba; need = c->last_px * 4; break;
+    case FVV_TAP_BLEND: src = c->dbg_rgba; need = c->last_px * 4; break;
     case FVV_TAP_DEPTH: src = c->dbg_depth; need = c->last_px * 4; break;
     default: return fail(c, FVV_E_ARG, "unknown tap %d", tap);
     }
