@@ -50,6 +50,101 @@ def stage_bytes(stage: str, n_views: int, n_out: int, n_src_sel: float, n_src_al
     return float("nan")
 
 
+def run_serving(fvv, torch, sg, rig, raw, seconds: float, warmup_s: float, users: int = 64,
+                rate: float = 30.0, seed: int = 0, path: int = 0) -> dict:
+    """Continuous-batching load: `users` viewers, each with Poisson request
+    arrivals at `rate` per second, output sizes 640x360 / 1280x720 / 1920x1080
+    by user, a random walk of the viewpoint on the arc (angle in [-60, 60]
+    deg, radius in [2.0, 2.5] m); the frame set is re-ingested at 30 Hz from
+    device-resident raw buffers.  Latency = completion - submission, stamped
+    by the library's server."""
+    from collections import deque
+    dev = torch.device("cuda:0")
+    sizes = [(640, 360), (1280, 720), (1920, 1080)]
+    rng = np.random.default_rng(seed)
+    ctx = fvv.Context(0)
+    ctx.set_rig(rig)
+    ctx.upload_mvd(raw, mem=fvv.MEM_DEVICE)
+    torch.cuda.synchronize()
+    srv = fvv.Server(ctx, max_slots=64)
+    n_buf = 8
+    pools = [[torch.empty((sizes[u % 3][1], sizes[u % 3][0], 3), dtype=torch.uint8, device=dev)
+              for _ in range(n_buf)] for u in range(users)]
+    busy = [[False] * n_buf for _ in range(users)]
+    torch.cuda.synchronize()
+    horizon = warmup_s + seconds
+    events = []
+    for u in range(users):
+        t = rng.exponential(1.0 / rate)
+        while t < horizon:
+            events.append((t, u))
+            t += rng.exponential(1.0 / rate)
+    events.sort()
+    ang = rng.uniform(-60, 60, users)
+    rad = rng.uniform(2.0, 2.5, users)
+    cams = []
+    for _, u in events:
+        ang[u] = float(np.clip(ang[u] + rng.normal(0, 1.0), -60, 60))
+        rad[u] = float(np.clip(rad[u] + rng.normal(0, 0.005), 2.0, 2.5))
+        W, H = sizes[u % 3]
+        cams.append(fvv.camera(sg.arc_camera(ang[u], rad[u], W, H)))
+    p = fvv.params(path=path)
+    outstanding = deque()
+    done = []
+    refresh = torch.cuda.Stream()
+
+    def drain(block: bool):
+        while outstanding:
+            tk, u, b, t_sub = outstanding[0]
+            lat = srv.poll(tk)
+            if lat is None:
+                if not block:
+                    return
+                time.sleep(0.0002)
+                continue
+            outstanding.popleft()
+            busy[u][b] = False
+            done.append((t_sub, lat, sizes[u % 3][0] * sizes[u % 3][1]))
+
+    t0 = time.perf_counter()
+    next_refresh = 0.0
+    for i, (t, u) in enumerate(events):
+        while True:
+            now = time.perf_counter() - t0
+            if now >= t:
+                break
+            drain(False)
+            if t - now > 0.001:
+                time.sleep(0.0005)
+        if t >= next_refresh:
+            ctx.upload_mvd(raw, mem=fvv.MEM_DEVICE, stream=refresh)
+            next_refresh += 1.0 / 30.0
+        while all(busy[u]):
+            drain(False)
+            time.sleep(0.0002)
+        b = busy[u].index(False)
+        busy[u][b] = True
+        tk = srv.submit(cams[i], pools[u][b], p)
+        outstanding.append((tk, u, b, t))
+    drain(True)
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.stop()
+    ctx.close()
+    meas = [(ts, lat, px) for ts, lat, px in done if ts >= warmup_s]
+    lats = np.array([lat for _, lat, _ in meas]) * 1e3
+    px = sum(px for _, _, px in meas)
+    return {"users": users, "rate_per_user": rate, "path": "learned" if path else "plain",
+            "offered_req_s": round(len(events) / horizon, 1), "completed": len(done),
+            "measured_requests": len(meas), "measured_s": seconds,
+            "p50_ms": round(float(np.percentile(lats, 50)), 3),
+            "p99_ms": round(float(np.percentile(lats, 99)), 3),
+            "max_ms": round(float(lats.max()), 3),
+            "delivered_mpix_s": round(px / seconds / 1e6, 1),
+            "mean_step_requests": round(st["batch_sum"] / max(1, st["steps"]), 2),
+            "steps": st["steps"], "failed": st["failed"], "wall_s": round(wall, 2)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +154,10 @@ def main():
     ap.add_argument("--latency-reps", type=int, default=3)
     ap.add_argument("--cpu-views", type=int, default=16,
                     help="views of the oracle CPU baseline sample (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="measured seconds of the serving load (0 = skip)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run a plain device copy of this many MiB first (hardware-counter scale)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the view-synthesis "
@@ -83,6 +182,15 @@ def main():
     stream = torch.cuda.current_stream()
     n_out = w.virtual[0].width * w.virtual[0].height
     n_views = len(w.virtual)
+
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib << 20
+        a = torch.empty(n, dtype=torch.uint8, device=dev).fill_(1)
+        b = torch.empty_like(a)
+        for _ in range(2):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     def step():
         ctx.upload_mvd(raw, mem=fvv.MEM_DEVICE, stream=stream)
@@ -142,7 +250,7 @@ def main():
             ctx.synthesize(v, o, stream=stream)
             torch.cuda.synchronize()
             lat.append((time.perf_counter() - t) * 1e3)
-    lat = np.array(lat)
+    lat = np.array(lat if lat else [float("nan")])
     log(f"[bench] single-view latency p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms")
 
     cpu = None
@@ -159,6 +267,12 @@ def main():
                "sample": f"{len(sample)} of the {n_views} swing views (9x1280x720 -> 1920x1080), "
                          f"single-threaded, {dt:.1f} s on {platform.processor() or platform.machine()}"}
         log(f"[bench] cpu oracle {cpu['value']} Mpix/s")
+
+    serving = None
+    if args.serve_seconds > 0:
+        log("[bench] serving load: 64 users x 30 req/s, mixed 360p/720p/1080p")
+        serving = run_serving(fvv, torch, sg, w.rig, raw, args.serve_seconds, 1.0)
+        log(f"[bench] serving {json.dumps(serving)}")
 
     res = {
         "metric": "virtual-view Mpixel/s (9-cam 720p MVD -> 1080p) + p99 latency, plain vs learned",
@@ -182,6 +296,7 @@ def main():
                        "single_view_p99": round(float(np.percentile(lat, 99)), 3),
                        "batched_per_view": round(ms / n_views, 4)},
         "stages": stages,
+        "serving": serving,
         "path": "plain",
     }
     print(json.dumps(res), flush=True)

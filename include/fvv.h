@@ -27,7 +27,8 @@
  *    alive and unchanged until the stream has passed the call.  Host-memory
  *    calls return after the data has been consumed (upload) or written
  *    (synthesis).
- *  - A context is used by one host thread at a time.
+ *  - A context is used by one host thread at a time, except fvv_submit and
+ *    fvv_poll, which any thread may call while the server runs.
  */
 #ifndef FVV_H
 #define FVV_H
@@ -182,6 +183,44 @@ int32_t fvv_set_profiling(fvv_ctx *ctx, int32_t enable);
 int32_t fvv_stage_count(void);
 const char *fvv_stage_name(int32_t stage);
 int32_t fvv_profile_read(fvv_ctx *ctx, double *total_ms, int64_t *launches, int32_t n, int32_t reset);
+
+/* Continuous-batching server: many users' viewpoint requests of any output
+ * size rendered against the device-resident frame store (the edge server
+ * serves each client's viewpoint, Section VIII).  A scheduler thread admits
+ * pending requests in arrival order into the next step while step slots
+ * (max_slots) and step workspace memory (step_bytes; 0 = room for max_slots
+ * 1920x1080 views) last, and launches each step as one batched synthesis on
+ * one of two streams with separate workspaces, so a new step starts while the
+ * previous one still runs.  Results are written to the caller's device
+ * buffers; their content is identical to fvv_synthesize of the same request
+ * on the same frame version.  Uploads (fvv_upload_mvd) may continue while the
+ * server runs; each step reads the latest version at its launch unless the
+ * request names one.  The rig cannot change while the server runs.
+ * fvv_server_start: FVV_E_STATE without a rig or if already running;
+ *   device memory for both step workspaces is allocated here (FVV_E_NOMEM).
+ * fvv_server_pause: paused != 0 holds new steps (requests keep queueing;
+ *   steps already launched complete); 0 resumes.  Stopping ignores a pause.
+ * fvv_server_stop: drains every pending request, joins the threads.
+ * fvv_submit: thread-safe; copies the camera and parameters, stamps the
+ *   arrival time and returns a ticket; out_dev (height rows of width*3
+ *   bytes, pitch out_pitch) must have no pending work on any stream when
+ *   submitted (the server's streams do not wait for the caller's) and must
+ *   stay valid until the ticket completes;
+ *   FVV_E_AGAIN when 65536 requests are already pending.
+ * fvv_poll: FVV_OK once the request has completed (then *latency_s =
+ *   completion - submission in seconds, host clock, and the ticket is
+ *   released), FVV_E_AGAIN while pending, the request's error code if it
+ *   failed (FVV_E_NOMEM: larger than a whole step), FVV_E_ARG for an unknown
+ *   ticket.
+ * fvv_server_stats: out6 = {steps, completed, failed, output pixels, sum of
+ *   step sizes, microseconds between step launch and completion}. */
+int32_t fvv_server_start(fvv_ctx *ctx, int32_t max_slots, uint64_t step_bytes);
+int32_t fvv_server_pause(fvv_ctx *ctx, int32_t paused);
+int32_t fvv_server_stop(fvv_ctx *ctx);
+int32_t fvv_submit(fvv_ctx *ctx, const fvv_camera *virt, const fvv_synth_params *params, void *out_dev,
+                   int64_t out_pitch, uint64_t *ticket);
+int32_t fvv_poll(fvv_ctx *ctx, uint64_t ticket, double *latency_s);
+int32_t fvv_server_stats(fvv_ctx *ctx, uint64_t *out6);
 
 #ifdef __cplusplus
 }

@@ -82,6 +82,12 @@ def lib():
             "fvv_stage_count": (I32, []),
             "fvv_stage_name": (C.c_char_p, [I32]),
             "fvv_profile_read": (I32, [P, P, P, I32, I32]),
+            "fvv_server_start": (I32, [P, I32, U64]),
+            "fvv_server_stop": (I32, [P]),
+            "fvv_server_pause": (I32, [P, I32]),
+            "fvv_submit": (I32, [P, C.POINTER(Camera), C.POINTER(SynthParams), P, I64, C.POINTER(U64)]),
+            "fvv_poll": (I32, [P, U64, C.POINTER(C.c_double)]),
+            "fvv_server_stats": (I32, [P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -94,7 +100,8 @@ def lib():
 EXPORTED = ("fvv_abi_version", "fvv_create", "fvv_destroy", "fvv_last_error", "fvv_set_rig",
             "fvv_upload_mvd", "fvv_synthesize", "fvv_synthesize_batch", "fvv_select_cameras",
             "fvv_pair_matrices", "fvv_set_debug", "fvv_debug_read", "fvv_set_profiling",
-            "fvv_stage_count", "fvv_stage_name", "fvv_profile_read")
+            "fvv_stage_count", "fvv_stage_name", "fvv_profile_read", "fvv_server_start",
+            "fvv_server_stop", "fvv_server_pause", "fvv_submit", "fvv_poll", "fvv_server_stats")
 
 
 def camera(cam) -> Camera:
@@ -270,3 +277,46 @@ class Context:
         a = np.empty(shape, dtype)
         self._check(self._L.fvv_debug_read(self._h, tap, a.ctypes.data, a.nbytes))
         return a
+
+
+class Server:
+    """Continuous-batching server of one context (see ``fvv_server_start``)."""
+
+    def __init__(self, ctx: Context, max_slots: int = 64, step_bytes: int = 0):
+        self.ctx = ctx
+        ctx._check(ctx._L.fvv_server_start(ctx._h, max_slots, step_bytes))
+        self.running = True
+
+    def submit(self, virt, out, p: Optional[SynthParams] = None) -> int:
+        """Queue one view into device tensor ``out`` (H, W, 3) uint8; returns a ticket."""
+        p = p or params()
+        t = C.c_uint64(0)
+        rc = self.ctx._L.fvv_submit(self.ctx._h, C.byref(camera(virt)), C.byref(p), out.data_ptr(),
+                                    out.stride(0), C.byref(t))
+        if rc:
+            raise FvvError(rc, self.ctx.last_error())
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending, else the latency in seconds (raises on failure)."""
+        lat = C.c_double(0.0)
+        rc = self.ctx._L.fvv_poll(self.ctx._h, ticket, C.byref(lat))
+        if rc == FVV_E_AGAIN:
+            return None
+        if rc:
+            raise FvvError(rc, f"request {ticket} failed")
+        return lat.value
+
+    def stats(self) -> dict:
+        a = np.zeros(6, np.uint64)
+        self.ctx._check(self.ctx._L.fvv_server_stats(self.ctx._h, a.ctypes.data))
+        return dict(steps=int(a[0]), completed=int(a[1]), failed=int(a[2]), pixels=int(a[3]),
+                    batch_sum=int(a[4]), busy_s=float(a[5]) * 1e-6)
+
+    def pause(self, on: bool = True):
+        self.ctx._check(self.ctx._L.fvv_server_pause(self.ctx._h, 1 if on else 0))
+
+    def stop(self):
+        if self.running:
+            self.ctx._check(self.ctx._L.fvv_server_stop(self.ctx._h))
+            self.running = False

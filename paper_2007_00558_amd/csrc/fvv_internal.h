@@ -15,8 +15,9 @@
 #define FVV_HOLE_OPEN 0x80000001u   // slot of a hole whose neighbours lie beyond its tile
 #define FVV_ZCLIP 0.01f             // points and samples nearer than this are dropped
 #define FVV_TILE 32                 // output tile edge (pixels) of the fused kernel
-#define FVV_SBLK 16                 // source block edge (pixels) of the binning
-#define FVV_LIST_PER_BLOCK 16       // bin-list capacity per source block (average tiles per block)
+#define FVV_SBLK 8                  // source block edge (pixels) of the binning: one wave per block
+#define FVV_LIST_PER_BLOCK 8        // bin-list capacity per source block (average tiles per block)
+#define FVV_MAX_RIG 32              // cameras in a rig
 
 // One selected source camera of one view.  The float32 pair matrices are
 // computed on the host in double and rounded once (Section VI pinhole warp):
@@ -118,9 +119,25 @@ struct fvv_batch_dims {
     bool fill_bg;         // any view fills holes
 };
 
+// Ingest of one frame set: every present camera's caller buffers (device
+// memory, or the runtime's staging copy of host memory) in one launch.
+struct fvv_repack_cam {
+    const uint8_t *rgb;
+    int64_t rgb_pitch;      // bytes
+    const uint8_t *depth;   // uint16 millimetres
+    int64_t depth_pitch;    // bytes
+    uint2 *texel_out;
+    float *depth_out;
+    int32_t W, H;
+    float alpha, beta;      // Eq. (1)
+};
+struct fvv_repack_batch {
+    int32_t n;
+    int32_t pad;
+    fvv_repack_cam cam[FVV_MAX_RIG];
+};
+
 // Host-side launchers (fvv_kernels.hip).  All return hipError_t of the launch.
-hipError_t fvv_launch_repack(const uint8_t *rgb, int64_t rgb_pitch, const uint16_t *depth,
-                             int64_t depth_pitch, int W, int H, float alpha, float beta,
-                             uint2 *texel_out, float *depth_out, hipStream_t s, fvv_prof *prof);
+hipError_t fvv_launch_repack(const fvv_repack_batch &b, int max_w, int max_h, hipStream_t s, fvv_prof *prof);
 hipError_t fvv_launch_synthesis(const fvv_view_desc *d_views, const fvv_batch_dims &dims,
                                 hipStream_t s, fvv_prof *prof);

@@ -84,25 +84,24 @@ __device__ __forceinline__ bool splat_point(const fvv_src_desc &s, int W, int H,
 }
 
 // ---------------------------------------------------------------- repack
-__global__ void __launch_bounds__(256) k_repack(const uint8_t *__restrict__ rgb, int64_t rgb_pitch,
-                                                const uint16_t *__restrict__ depth, int64_t depth_pitch,
-                                                int W, int H, float alpha, float beta,
-                                                uint2 *__restrict__ texel_out, float *__restrict__ depth_out)
+// One launch per frame set: grid.z = camera.
+__global__ void __launch_bounds__(256) k_repack(const fvv_repack_batch b)
 {
+    const fvv_repack_cam &c = b.cam[blockIdx.z];
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
-    if (x >= W || y >= H) return;
-    const uint8_t *p = rgb + (int64_t)y * rgb_pitch + (int64_t)x * 3;
-    const uint32_t c = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | 0xFF000000u;
-    const uint16_t d = *(const uint16_t *)((const uint8_t *)depth + (int64_t)y * depth_pitch + (int64_t)x * 2);
+    if (x >= c.W || y >= c.H) return;
+    const uint8_t *p = c.rgb + (int64_t)y * c.rgb_pitch + (int64_t)x * 3;
+    const uint32_t col = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | 0xFF000000u;
+    const uint16_t d = *(const uint16_t *)(c.depth + (int64_t)y * c.depth_pitch + (int64_t)x * 2);
     uint32_t zb = FVV_NO_DEPTH;
     if (d != 0) {
         const float z = __fdiv_rn((float)d, 1000.0f);
-        const float s = __fadd_rn(__fmul_rn(alpha, z), beta);   // Eq. (1): (alpha z + beta) z
+        const float s = __fadd_rn(__fmul_rn(c.alpha, z), c.beta);   // Eq. (1): (alpha z + beta) z
         zb = f2u(__fmul_rn(s, z));
     }
-    texel_out[(int64_t)y * W + x] = make_uint2(c, zb);
-    depth_out[(int64_t)y * W + x] = u2f(zb);
+    c.texel_out[(int64_t)y * c.W + x] = make_uint2(col, zb);
+    c.depth_out[(int64_t)y * c.W + x] = u2f(zb);
 }
 
 // ---------------------------------------------------------------- binning
@@ -117,19 +116,22 @@ __device__ __forceinline__ int wave_max(int v)
     return v;
 }
 
-// One workgroup per (view, camera slot, 16x16 source block): exact bounding
-// box of the block's footprints, turned into the range of output tiles whose
-// window (tile plus 1-pixel halo) it touches; each such tile is counted.
+// One wave per (view, camera slot, 8x8 source block), four blocks per
+// workgroup: exact bounding box of the block's footprints, turned into the
+// range of output tiles whose window (tile plus 1-pixel halo) it touches;
+// each such tile is counted.
 __global__ void __launch_bounds__(256) k_bin_count(const fvv_view_desc *__restrict__ views)
 {
     const fvv_view_desc &vd = views[blockIdx.z];
-    const int k = blockIdx.y, blk = blockIdx.x;
+    const int k = blockIdx.y;
+    const int lane = threadIdx.x & 63;
+    const int blk = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (k >= vd.K) return;
     const fvv_src_desc &s = vd.src[k];
     if (blk >= s.nblk) return;
     const int by = blk / s.nbx, bx = blk - by * s.nbx;
-    const int i = bx * FVV_SBLK + (threadIdx.x & (FVV_SBLK - 1));
-    const int j = by * FVV_SBLK + (threadIdx.x / FVV_SBLK);
+    const int i = bx * FVV_SBLK + (lane & (FVV_SBLK - 1));
+    const int j = by * FVV_SBLK + (lane / FVV_SBLK);
     int x0 = INT_MAX, x1 = -1, y0 = INT_MAX, y1 = -1;
     if (i < s.W && j < s.H) {
         const uint32_t zb = f2u(s.depth[(int64_t)j * s.W + i]);
@@ -141,38 +143,22 @@ __global__ void __launch_bounds__(256) k_bin_count(const fvv_view_desc *__restri
             y1 = f.y1;
         }
     }
+    // every lane ends with the block's bounds
     x0 = wave_min(x0);
     y0 = wave_min(y0);
     x1 = wave_max(x1);
     y1 = wave_max(y1);
-    __shared__ int4 red[4];
-    __shared__ int4 range;
-    const int wid = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) red[wid] = make_int4(x0, x1, y0, y1);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int4 r = red[0];
-        for (int w = 1; w < 4; ++w) {
-            r.x = min(r.x, red[w].x);
-            r.y = max(r.y, red[w].y);
-            r.z = min(r.z, red[w].z);
-            r.w = max(r.w, red[w].w);
-        }
-        int4 t = make_int4(1, 0, 1, 0);   // empty
-        if (r.y >= 0) {
-            t.x = max(0, (r.x + T - 1) / T - 1);
-            t.y = min(vd.ntx - 1, (r.y + 1) / T);
-            t.z = max(0, (r.z + T - 1) / T - 1);
-            t.w = min(vd.nty - 1, (r.w + 1) / T);
-        }
-        vd.bbox[(int64_t)k * vd.blk_stride + blk] = t;
-        range = t;
+    int4 t = make_int4(1, 0, 1, 0);   // empty
+    if (x1 >= 0) {
+        t.x = max(0, (x0 + T - 1) / T - 1);
+        t.y = min(vd.ntx - 1, (x1 + 1) / T);
+        t.z = max(0, (y0 + T - 1) / T - 1);
+        t.w = min(vd.nty - 1, (y1 + 1) / T);
     }
-    __syncthreads();
-    const int4 t = range;
+    if (lane == 0) vd.bbox[(int64_t)k * vd.blk_stride + blk] = t;
     if (t.x > t.y) return;
     const int nx = t.y - t.x + 1, n = nx * (t.w - t.z + 1);
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    for (int e = lane; e < n; e += 64) {
         const int ty = t.z + e / nx, tx = t.x + e % nx;
         atomicAdd(&vd.counts[ty * vd.ntx + tx], 1);
     }
@@ -370,8 +356,10 @@ __global__ void __launch_bounds__(256) k_tile(const fvv_view_desc *__restrict__ 
     const bool scan_all = *vd.overflow != 0;
     const int beg = scan_all ? 0 : vd.offs[tile];
     const int end = scan_all ? vd.K * vd.blk_stride : vd.cursor[tile];
-    const int si = t & (FVV_SBLK - 1), sj = t / FVV_SBLK;
-    for (int e = beg; e < end; ++e) {
+    // each wave splats its own list entries (one 8x8 source block per entry)
+    const int lane = t & 63, wave = t >> 6;
+    const int si = lane & (FVV_SBLK - 1), sj = lane / FVV_SBLK;
+    for (int e = beg + wave; e < end; e += 4) {
         int k, blk;
         if (!scan_all) {
             const int ent = vd.list[e];
@@ -605,15 +593,13 @@ __global__ void __launch_bounds__(256) k_fill_open(const fvv_view_desc *__restri
 
 }  // namespace
 
-hipError_t fvv_launch_repack(const uint8_t *rgb, int64_t rgb_pitch, const uint16_t *depth,
-                             int64_t depth_pitch, int W, int H, float alpha, float beta,
-                             uint2 *texel_out, float *depth_out, hipStream_t s, fvv_prof *prof)
+hipError_t fvv_launch_repack(const fvv_repack_batch &b, int max_w, int max_h, hipStream_t s, fvv_prof *prof)
 {
-    dim3 grid((W + 255) / 256, H);
+    if (b.n <= 0) return hipSuccess;
+    dim3 grid((max_w + 255) / 256, max_h, b.n);
     hipEvent_t e0;
     fvv_prof_begin(prof, s, e0);
-    hipLaunchKernelGGL(k_repack, grid, dim3(256), 0, s, rgb, rgb_pitch, depth, depth_pitch, W, H, alpha,
-                       beta, texel_out, depth_out);
+    hipLaunchKernelGGL(k_repack, grid, dim3(256), 0, s, b);
     fvv_prof_end(prof, s, FVV_ST_REPACK, e0);
     return hipGetLastError();
 }
@@ -624,7 +610,7 @@ hipError_t fvv_launch_synthesis(const fvv_view_desc *d_views, const fvv_batch_di
     if (b.n_views <= 0) return hipSuccess;
     hipEvent_t e0;
     fvv_prof_begin(prof, s, e0);
-    hipLaunchKernelGGL(k_bin_count, dim3(b.max_blocks, b.max_k, b.n_views), dim3(256), 0, s, d_views);
+    hipLaunchKernelGGL(k_bin_count, dim3((b.max_blocks + 3) / 4, b.max_k, b.n_views), dim3(256), 0, s, d_views);
     fvv_prof_end(prof, s, FVV_ST_BIN_COUNT, e0);
     fvv_prof_begin(prof, s, e0);
     hipLaunchKernelGGL(k_bin_scan, dim3(b.n_views), dim3(256), 0, s, d_views);

@@ -1,23 +1,31 @@
 // fvv_runtime.hip -- host runtime behind the C ABI of libfvv.so (include/fvv.h).
 //
 // Owns the device state of one context: the rig, a double-buffered frame
-// store of repacked MVD frames, per-view workspaces, view descriptors and
-// debug taps.  Camera selection and the pair matrices are computed here in
-// double and handed to the kernels as float32 (Section VI: the pinhole warp
-// and the mix by camera distance).
+// store of repacked MVD frames, workspaces for batched synthesis, debug taps,
+// stage timing, and the continuous-batching server.  Camera selection and
+// the pair matrices are computed here in double and handed to the kernels as
+// float32 (Section VI: the pinhole warp and the mix by camera distance).
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <deque>
 #include <mutex>
 #include <string>
+#include <thread>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/fvv.h"
 #include "fvv_internal.h"
 
 namespace {
+
+using Clock = std::chrono::steady_clock;
 
 thread_local std::string g_create_error;
 
@@ -35,14 +43,81 @@ struct DeviceGuard {
     }
 };
 
+// One resident frame set.  Every stream that reads it records an event;
+// an upload into the slot waits for all of them.
 struct FrameSlot {
     uint64_t version = 0;                 // 0 = empty
     std::vector<uint2 *> texel;           // per camera {RGBA8, depth bits}
     std::vector<float *> depth;
     std::vector<int32_t> present;
     hipEvent_t ready = nullptr;           // recorded after the repack
-    hipEvent_t last_use = nullptr;        // recorded after each synthesis reading it
-    bool used = false;
+    std::vector<std::pair<hipStream_t, hipEvent_t>> readers;
+};
+
+// Device buffers of one batched launch sequence.
+struct Workspace {
+    uint8_t *ws = nullptr;
+    size_t ws_bytes = 0;
+    int32_t *counts = nullptr;            // tile counters, zero between calls
+    size_t counts_cap = 0;
+    fvv_view_desc *d_desc = nullptr;
+    size_t desc_cap = 0;
+    static constexpr int kRing = 4;       // pinned host descriptor buffers
+    fvv_view_desc *h_desc[kRing] = {};
+    hipEvent_t h_ev[kRing] = {};
+    bool h_live[kRing] = {};
+    size_t h_cap = 0;
+    int ring = 0;
+};
+
+struct ViewLayout {
+    int ntx, nty, n_tiles, blk_stride, list_cap, K;
+    int32_t idx[FVV_MAX_K];
+    double w[FVV_MAX_K];
+};
+
+struct Request {
+    uint64_t ticket;
+    fvv_camera cam;
+    fvv_synth_params P;
+    void *out;
+    int64_t pitch;
+    Clock::time_point arrive;
+    size_t bytes;     // workspace bound
+    size_t tiles;
+};
+
+struct Result {
+    bool done = false;
+    int32_t status = FVV_OK;
+    double latency = 0.0;
+};
+
+struct Server {
+    int max_slots = 0;
+    size_t step_bytes = 0;
+    size_t step_tiles = 0;
+    Workspace ws[2];
+    hipStream_t stream[2] = {nullptr, nullptr};
+    hipEvent_t done_ev[2] = {nullptr, nullptr};
+    bool busy[2] = {false, false};
+    std::vector<Request> inflight[2];
+    std::thread sched, compl_[2];
+    std::mutex qmu;                       // pending, busy, stop
+    std::condition_variable qcv;
+    std::deque<Request> pending;
+    bool stop = false;
+    bool paused = false;
+    std::mutex cmu[2];
+    std::condition_variable ccv[2];
+    bool launched[2] = {false, false};
+    Clock::time_point launch_t[2];
+    std::mutex dmu;                       // results, stats
+    std::unordered_map<uint64_t, Result> results;
+    std::atomic<uint64_t> next_ticket{1};
+    // statistics
+    uint64_t n_steps = 0, n_done = 0, n_failed = 0, pixels = 0, batch_sum = 0;
+    double busy_s = 0.0;
 };
 
 }  // namespace
@@ -51,31 +126,19 @@ struct fvv_ctx {
     int device = 0;
     uint64_t budget = 0;     // 0 = unlimited
     uint64_t allocated = 0;
+    std::mutex mu;           // guards everything below against the server thread
     std::string err;
     std::vector<fvv_camera> rig;
     FrameSlot slots[2];
     int latest = -1;
     uint64_t next_version = 1;
+    std::vector<hipEvent_t> event_pool;
     // upload staging: raw RGB8 + uint16 planes of all cameras
     uint8_t *staging = nullptr;
     size_t staging_bytes = 0;
     hipEvent_t staging_free = nullptr;
-    // per-view workspace (keys, blend, slots, column summaries, host-mode output)
-    uint8_t *ws = nullptr;
-    size_t ws_bytes = 0;
-    // view descriptors: device array + pinned host ring
-    fvv_view_desc *d_desc = nullptr;
-    size_t desc_cap = 0;     // views
-    static constexpr int kRing = 4;
-    fvv_view_desc *h_desc[kRing] = {nullptr, nullptr, nullptr, nullptr};
-    size_t h_desc_cap = 0;
-    hipEvent_t h_desc_ev[kRing] = {nullptr, nullptr, nullptr, nullptr};
-    bool h_desc_ev_live[kRing] = {false, false, false, false};
-    int ring = 0;
-    // tile counters of the binning: zero between calls (cleared by the scan)
-    int32_t *counts = nullptr;
-    size_t counts_cap = 0;   // entries
-    // debug taps of view 0 of the last synthesis
+    Workspace user;          // workspace of direct synthesis calls
+    // debug taps of view 0 of the last direct synthesis
     bool debug = false;
     unsigned long long *dbg_z = nullptr;
     unsigned long long *dbg_zf = nullptr;
@@ -87,6 +150,7 @@ struct fvv_ctx {
     // stage timing
     bool profiling = false;
     fvv_prof prof;
+    Server *server = nullptr;
 };
 
 namespace {
@@ -209,7 +273,7 @@ int select_k(const fvv_camera *rig, const int32_t *present, int n, const fvv_cam
 // fixed association order, rounded once to float32.
 void pair_dir(const fvv_camera &s, const fvv_camera &d, float M[9], float m[3])
 {
-    double Rrel[9], Ksi[9], Kd[9], T1[9], T2[9], tr[3];
+    double Rrel[9], T1[9], T2[9], tr[3];
     for (int r = 0; r < 3; ++r)
         for (int c = 0; c < 3; ++c) {
             double acc = 0.0;
@@ -217,10 +281,8 @@ void pair_dir(const fvv_camera &s, const fvv_camera &d, float M[9], float m[3])
             Rrel[r * 3 + c] = acc;
         }
     const double fx = s.fx, fy = s.fy;
-    const double ksi[9] = {1.0 / fx, 0.0, -(double)s.cx / fx, 0.0, 1.0 / fy, -(double)s.cy / fy, 0.0, 0.0, 1.0};
-    const double kd[9] = {(double)d.fx, 0.0, (double)d.cx, 0.0, (double)d.fy, (double)d.cy, 0.0, 0.0, 1.0};
-    std::memcpy(Ksi, ksi, sizeof ksi);
-    std::memcpy(Kd, kd, sizeof kd);
+    const double Ksi[9] = {1.0 / fx, 0.0, -(double)s.cx / fx, 0.0, 1.0 / fy, -(double)s.cy / fy, 0.0, 0.0, 1.0};
+    const double Kd[9] = {(double)d.fx, 0.0, (double)d.cx, 0.0, (double)d.fy, (double)d.cy, 0.0, 0.0, 1.0};
     auto mm = [](const double *X, const double *Y, double *Z) {
         for (int r = 0; r < 3; ++r)
             for (int c = 0; c < 3; ++c) {
@@ -244,49 +306,12 @@ void pair_dir(const fvv_camera &s, const fvv_camera &d, float M[9], float m[3])
     for (int e = 0; e < 9; ++e) M[e] = (float)T2[e];
 }
 
-int32_t ensure_frame_slot(fvv_ctx *c, FrameSlot &s)
+int nblocks(const fvv_camera &c)
 {
-    const int n = (int)c->rig.size();
-    if ((int)s.texel.size() == n && s.ready) return FVV_OK;
-    s.texel.assign(n, nullptr);
-    s.depth.assign(n, nullptr);
-    s.present.assign(n, 0);
-    for (int k = 0; k < n; ++k) {
-        const size_t px = (size_t)c->rig[k].width * c->rig[k].height;
-        int32_t rc = dalloc(c, (void **)&s.texel[k], px * 8);
-        if (rc) return rc;
-        rc = dalloc(c, (void **)&s.depth[k], px * 4);
-        if (rc) return rc;
-    }
-    if (!s.ready) HIPCHECK(c, hipEventCreateWithFlags(&s.ready, hipEventDisableTiming));
-    if (!s.last_use) HIPCHECK(c, hipEventCreateWithFlags(&s.last_use, hipEventDisableTiming));
-    return FVV_OK;
-}
-
-void release_frames(fvv_ctx *c)
-{
-    for (auto &s : c->slots) {
-        for (size_t k = 0; k < s.texel.size(); ++k) {
-            const size_t px = (size_t)c->rig[k].width * c->rig[k].height;
-            dfree(c, s.texel[k], px * 8);
-            dfree(c, s.depth[k], px * 4);
-        }
-        s.texel.clear();
-        s.depth.clear();
-        s.present.clear();
-        s.version = 0;
-        s.used = false;
-    }
-    c->latest = -1;
+    return ((c.width + FVV_SBLK - 1) / FVV_SBLK) * ((c.height + FVV_SBLK - 1) / FVV_SBLK);
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
-
-struct ViewLayout {
-    int ntx, nty, n_tiles, blk_stride, list_cap, K;
-    int32_t idx[FVV_MAX_K];
-    double w[FVV_MAX_K];
-};
 
 // bytes of workspace one view needs: slot plane, tile arrays, bin list,
 // block ranges, and (host-memory output) an RGB8 staging image
@@ -304,42 +329,140 @@ size_t view_ws_bytes(int W, int H, const ViewLayout &L, bool host_out)
     return b;
 }
 
-int32_t ensure_ws(fvv_ctx *c, size_t bytes)
+// Tile grid and list sizes of a view drawing on K cameras of the rig whose
+// block counts are given; used both for exact layouts and for upper bounds.
+void layout_sizes(ViewLayout &L, int W, int H, const int *nblk, int K)
 {
-    if (c->ws_bytes >= bytes) return FVV_OK;
-    HIPCHECK(c, hipDeviceSynchronize());
-    dfree(c, c->ws, c->ws_bytes);
-    c->ws = nullptr;
-    c->ws_bytes = 0;
-    int32_t rc = dalloc(c, (void **)&c->ws, bytes);
-    if (rc) return rc;
-    c->ws_bytes = bytes;
+    L.K = K;
+    L.ntx = (W + FVV_TILE - 1) / FVV_TILE;
+    L.nty = (H + FVV_TILE - 1) / FVV_TILE;
+    L.n_tiles = L.ntx * L.nty;
+    int sum = 0, mx = 0;
+    for (int k = 0; k < K; ++k) {
+        sum += nblk[k];
+        mx = std::max(mx, nblk[k]);
+    }
+    L.blk_stride = mx;
+    L.list_cap = FVV_LIST_PER_BLOCK * sum;
+}
+
+hipEvent_t take_event(fvv_ctx *c)
+{
+    if (!c->event_pool.empty()) {
+        hipEvent_t e = c->event_pool.back();
+        c->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
+    return e;
+}
+
+// record that `s` reads frame slot fs (an upload into the slot waits for it)
+int32_t note_reader(fvv_ctx *c, FrameSlot &fs, hipStream_t s)
+{
+    for (auto &r : fs.readers)
+        if (r.first == s) {
+            HIPCHECK(c, hipEventRecord(r.second, s));
+            return FVV_OK;
+        }
+    hipEvent_t e = take_event(c);
+    if (!e) return fail(c, FVV_E_DEVICE, "hipEventCreate failed");
+    HIPCHECK(c, hipEventRecord(e, s));
+    fs.readers.emplace_back(s, e);
     return FVV_OK;
 }
 
-int32_t ensure_desc(fvv_ctx *c, int n)
+int32_t ensure_frame_slot(fvv_ctx *c, FrameSlot &s)
 {
-    if (c->desc_cap < (size_t)n) {
-        HIPCHECK(c, hipDeviceSynchronize());
-        dfree(c, c->d_desc, c->desc_cap * sizeof(fvv_view_desc));
-        c->d_desc = nullptr;
-        c->desc_cap = 0;
-        int32_t rc = dalloc(c, (void **)&c->d_desc, (size_t)n * sizeof(fvv_view_desc));
+    const int n = (int)c->rig.size();
+    if ((int)s.texel.size() == n && s.ready) return FVV_OK;
+    s.texel.assign(n, nullptr);
+    s.depth.assign(n, nullptr);
+    s.present.assign(n, 0);
+    for (int k = 0; k < n; ++k) {
+        const size_t px = (size_t)c->rig[k].width * c->rig[k].height;
+        int32_t rc = dalloc(c, (void **)&s.texel[k], px * 8);
         if (rc) return rc;
-        c->desc_cap = n;
+        rc = dalloc(c, (void **)&s.depth[k], px * 4);
+        if (rc) return rc;
     }
-    if (c->h_desc_cap < (size_t)n) {
-        for (int r = 0; r < fvv_ctx::kRing; ++r) {
-            if (c->h_desc_ev_live[r]) HIPCHECK(c, hipEventSynchronize(c->h_desc_ev[r]));
-            c->h_desc_ev_live[r] = false;
-            if (c->h_desc[r]) (void)hipHostFree(c->h_desc[r]);
-            c->h_desc[r] = nullptr;
-            HIPCHECK(c, hipHostMalloc((void **)&c->h_desc[r], (size_t)n * sizeof(fvv_view_desc)));
-            if (!c->h_desc_ev[r]) HIPCHECK(c, hipEventCreateWithFlags(&c->h_desc_ev[r], hipEventDisableTiming));
+    if (!s.ready) HIPCHECK(c, hipEventCreateWithFlags(&s.ready, hipEventDisableTiming));
+    return FVV_OK;
+}
+
+void release_frames(fvv_ctx *c)
+{
+    for (auto &s : c->slots) {
+        for (size_t k = 0; k < s.texel.size(); ++k) {
+            const size_t px = (size_t)c->rig[k].width * c->rig[k].height;
+            dfree(c, s.texel[k], px * 8);
+            dfree(c, s.depth[k], px * 4);
         }
-        c->h_desc_cap = n;
+        s.texel.clear();
+        s.depth.clear();
+        s.present.clear();
+        for (auto &r : s.readers) c->event_pool.push_back(r.second);
+        s.readers.clear();
+        s.version = 0;
+    }
+    c->latest = -1;
+}
+
+// Grow a workspace (synchronising the device first) so it holds `bytes` of
+// per-view buffers, `tiles` tile counters and `n` view descriptors.
+int32_t ws_reserve(fvv_ctx *c, Workspace &W, size_t bytes, size_t tiles, size_t n)
+{
+    int32_t rc;
+    if (W.ws_bytes < bytes) {
+        HIPCHECK(c, hipDeviceSynchronize());
+        dfree(c, W.ws, W.ws_bytes);
+        W.ws = nullptr;
+        W.ws_bytes = 0;
+        if ((rc = dalloc(c, (void **)&W.ws, bytes))) return rc;
+        W.ws_bytes = bytes;
+    }
+    if (W.counts_cap < tiles) {
+        HIPCHECK(c, hipDeviceSynchronize());
+        dfree(c, W.counts, W.counts_cap * 4);
+        W.counts = nullptr;
+        W.counts_cap = 0;
+        if ((rc = dalloc(c, (void **)&W.counts, tiles * 4))) return rc;
+        HIPCHECK(c, hipMemset(W.counts, 0, tiles * 4));
+        W.counts_cap = tiles;
+    }
+    if (W.desc_cap < n) {
+        HIPCHECK(c, hipDeviceSynchronize());
+        dfree(c, W.d_desc, W.desc_cap * sizeof(fvv_view_desc));
+        W.d_desc = nullptr;
+        W.desc_cap = 0;
+        if ((rc = dalloc(c, (void **)&W.d_desc, n * sizeof(fvv_view_desc)))) return rc;
+        W.desc_cap = n;
+    }
+    if (W.h_cap < n) {
+        for (int r = 0; r < Workspace::kRing; ++r) {
+            if (W.h_live[r]) HIPCHECK(c, hipEventSynchronize(W.h_ev[r]));
+            W.h_live[r] = false;
+            if (W.h_desc[r]) (void)hipHostFree(W.h_desc[r]);
+            W.h_desc[r] = nullptr;
+            HIPCHECK(c, hipHostMalloc((void **)&W.h_desc[r], n * sizeof(fvv_view_desc)));
+            if (!W.h_ev[r]) HIPCHECK(c, hipEventCreateWithFlags(&W.h_ev[r], hipEventDisableTiming));
+        }
+        W.h_cap = n;
     }
     return FVV_OK;
+}
+
+void ws_release(fvv_ctx *c, Workspace &W)
+{
+    dfree(c, W.ws, W.ws_bytes);
+    dfree(c, W.counts, W.counts_cap * 4);
+    dfree(c, W.d_desc, W.desc_cap * sizeof(fvv_view_desc));
+    for (int r = 0; r < Workspace::kRing; ++r) {
+        if (W.h_desc[r]) (void)hipHostFree(W.h_desc[r]);
+        if (W.h_ev[r]) (void)hipEventDestroy(W.h_ev[r]);
+    }
+    W = Workspace();
 }
 
 int32_t resolve_params(fvv_ctx *c, const fvv_synth_params *p, fvv_synth_params &o)
@@ -364,78 +487,56 @@ int32_t resolve_params(fvv_ctx *c, const fvv_synth_params *p, fvv_synth_params &
     return FVV_OK;
 }
 
-int32_t synthesize_impl(fvv_ctx *c, const fvv_camera *virts, int n_views, const fvv_synth_params *params,
-                        void *const *outs, const int64_t *pitches, int32_t mem_kind, void *stream)
+int32_t find_slot(fvv_ctx *c, uint64_t version, int &si)
 {
-    if (!c) return FVV_E_ARG;
-    if (!virts || n_views < 1 || !outs || !pitches) return fail(c, FVV_E_ARG, "null argument or n_views < 1");
-    if (mem_kind != FVV_MEM_HOST && mem_kind != FVV_MEM_DEVICE) return fail(c, FVV_E_ARG, "bad mem_kind");
-    if (c->rig.empty()) return fail(c, FVV_E_STATE, "no rig set");
-    fvv_synth_params P;
-    int32_t rc = resolve_params(c, params, P);
-    if (rc) return rc;
-    int si = c->latest;
-    if (P.frame_version) {
+    si = c->latest;
+    if (version) {
         si = -1;
         for (int q = 0; q < 2; ++q)
-            if (c->slots[q].version == P.frame_version) si = q;
-        if (si < 0)
-            return fail(c, FVV_E_STATE, "frame version %llu is not resident",
-                        (unsigned long long)P.frame_version);
+            if (c->slots[q].version == version) si = q;
+        if (si < 0) return fail(c, FVV_E_STATE, "frame version %llu is not resident", (unsigned long long)version);
     }
     if (si < 0 || c->slots[si].version == 0) return fail(c, FVV_E_STATE, "no frame set uploaded");
-    FrameSlot &fs = c->slots[si];
-    for (int v = 0; v < n_views; ++v) {
-        rc = check_camera(c, virts[v], false, "virtual camera");
-        if (rc) return rc;
-        if (!outs[v]) return fail(c, FVV_E_ARG, "outs[%d] is null", v);
-        if (pitches[v] < (int64_t)virts[v].width * 3) return fail(c, FVV_E_ARG, "pitches[%d] too small", v);
-    }
-    DeviceGuard g(c->device);
-    hipStream_t s = (hipStream_t)stream;
-    const bool host_out = mem_kind == FVV_MEM_HOST;
+    return FVV_OK;
+}
+
+// One batched launch sequence over n views (caller holds c->mu, has checked
+// the arguments and resolved each view's parameters).  grow: the workspace
+// may be enlarged; otherwise the caller guarantees it fits.
+int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const fvv_synth_params *Ps, int n_views,
+                     void *const *outs, const int64_t *pitches, bool host_out, hipStream_t s, bool grow,
+                     bool taps)
+{
     const int n = (int)c->rig.size();
     std::vector<ViewLayout> lay(n_views);
+    std::vector<int> slot_of(n_views);
     size_t total = 0, total_tiles = 0;
-    fvv_batch_dims dims{n_views, 0, 0, 0, 0, P.fill_mode == FVV_FILL_BG};
+    fvv_batch_dims dims{n_views, 0, 0, 0, 0, false};
+    int32_t rc;
     for (int v = 0; v < n_views; ++v) {
+        if ((rc = find_slot(c, Ps[v].frame_version, slot_of[v]))) return rc;
+        const FrameSlot &fs = c->slots[slot_of[v]];
         ViewLayout &L = lay[v];
         const fvv_camera &vc = virts[v];
-        L.K = select_k(c->rig.data(), fs.present.data(), n, vc, P.k_nearest, L.idx, L.w);
-        if (L.K < 1) return fail(c, FVV_E_STATE, "no camera present in the frame set");
-        L.ntx = (vc.width + FVV_TILE - 1) / FVV_TILE;
-        L.nty = (vc.height + FVV_TILE - 1) / FVV_TILE;
-        L.n_tiles = L.ntx * L.nty;
-        int sum_blk = 0, max_blk = 0;
-        for (int k = 0; k < L.K; ++k) {
-            const fvv_camera &sc = c->rig[L.idx[k]];
-            const int nb = ((sc.width + FVV_SBLK - 1) / FVV_SBLK) * ((sc.height + FVV_SBLK - 1) / FVV_SBLK);
-            sum_blk += nb;
-            max_blk = std::max(max_blk, nb);
-        }
-        L.blk_stride = max_blk;
-        L.list_cap = FVV_LIST_PER_BLOCK * sum_blk;
+        const int K = select_k(c->rig.data(), fs.present.data(), n, vc, Ps[v].k_nearest, L.idx, L.w);
+        if (K < 1) return fail(c, FVV_E_STATE, "no camera present in the frame set");
+        int nb[FVV_MAX_K];
+        for (int k = 0; k < K; ++k) nb[k] = nblocks(c->rig[L.idx[k]]);
+        layout_sizes(L, vc.width, vc.height, nb, K);
         total += view_ws_bytes(vc.width, vc.height, L, host_out);
         total_tiles += (size_t)L.n_tiles;
         dims.max_k = std::max(dims.max_k, L.K);
-        dims.max_blocks = std::max(dims.max_blocks, max_blk);
+        dims.max_blocks = std::max(dims.max_blocks, L.blk_stride);
         dims.max_tiles_x = std::max(dims.max_tiles_x, L.ntx);
         dims.max_tiles_y = std::max(dims.max_tiles_y, L.nty);
+        dims.fill_bg = dims.fill_bg || Ps[v].fill_mode == FVV_FILL_BG;
     }
-    rc = ensure_ws(c, total);
-    if (rc) return rc;
-    rc = ensure_desc(c, n_views);
-    if (rc) return rc;
-    if (c->counts_cap < total_tiles) {
-        HIPCHECK(c, hipDeviceSynchronize());
-        dfree(c, c->counts, c->counts_cap * 4);
-        c->counts = nullptr;
-        c->counts_cap = 0;
-        if ((rc = dalloc(c, (void **)&c->counts, total_tiles * 4))) return rc;
-        HIPCHECK(c, hipMemset(c->counts, 0, total_tiles * 4));
-        c->counts_cap = total_tiles;
+    if (grow) {
+        if ((rc = ws_reserve(c, Wk, total, total_tiles, n_views))) return rc;
+    } else if (Wk.ws_bytes < total || Wk.counts_cap < total_tiles || Wk.desc_cap < (size_t)n_views) {
+        return fail(c, FVV_E_NOMEM, "step does not fit its workspace");
     }
-    if (c->debug) {
+    if (taps) {
         const size_t px = (size_t)virts[0].width * virts[0].height;
         if (c->dbg_px < px) {
             HIPCHECK(c, hipDeviceSynchronize());
@@ -454,25 +555,25 @@ int32_t synthesize_impl(fvv_ctx *c, const fvv_camera *virts, int n_views, const 
             c->dbg_px = px;
         }
     }
-    // host descriptors (pinned ring slot)
-    const int r = c->ring;
-    c->ring = (c->ring + 1) % fvv_ctx::kRing;
-    if (c->h_desc_ev_live[r]) HIPCHECK(c, hipEventSynchronize(c->h_desc_ev[r]));
-    fvv_view_desc *hd = c->h_desc[r];
-    uint8_t *cur = c->ws;
-    int32_t *cnt = c->counts;
+    const int r = Wk.ring;
+    Wk.ring = (Wk.ring + 1) % Workspace::kRing;
+    if (Wk.h_live[r]) HIPCHECK(c, hipEventSynchronize(Wk.h_ev[r]));
+    fvv_view_desc *hd = Wk.h_desc[r];
+    uint8_t *cur = Wk.ws;
+    int32_t *cnt = Wk.counts;
     std::vector<uint8_t *> host_stage(n_views, nullptr);
     for (int v = 0; v < n_views; ++v) {
         const fvv_camera &vc = virts[v];
         const ViewLayout &L = lay[v];
+        const FrameSlot &fs = c->slots[slot_of[v]];
         fvv_view_desc &d = hd[v];
         std::memset(&d, 0, sizeof d);
         d.W = vc.width;
         d.H = vc.height;
         d.K = L.K;
-        d.fill_mode = P.fill_mode;
-        d.tau = P.tau_rel;
-        d.max_fp = P.max_footprint;
+        d.fill_mode = Ps[v].fill_mode;
+        d.tau = Ps[v].tau_rel;
+        d.max_fp = Ps[v].max_footprint;
         d.ntx = L.ntx;
         d.nty = L.nty;
         d.blk_stride = L.blk_stride;
@@ -504,7 +605,7 @@ int32_t synthesize_impl(fvv_ctx *c, const fvv_camera *virts, int n_views, const 
             d.out = (uint8_t *)outs[v];
             d.out_pitch = pitches[v];
         }
-        if (c->debug && v == 0) {
+        if (taps && v == 0) {
             d.dbg_z = c->dbg_z;
             d.dbg_zf = c->dbg_zf;
             d.dbg_rgba = c->dbg_rgba;
@@ -519,7 +620,7 @@ int32_t synthesize_impl(fvv_ctx *c, const fvv_camera *virts, int n_views, const 
             sd.H = sc.height;
             sd.cam = L.idx[k];
             sd.nbx = (sc.width + FVV_SBLK - 1) / FVV_SBLK;
-            sd.nblk = sd.nbx * ((sc.height + FVV_SBLK - 1) / FVV_SBLK);
+            sd.nblk = nblocks(sc);
             sd.wgt = (float)L.w[k];
             pair_dir(sc, vc, sd.A, sd.a);
             pair_dir(vc, sc, sd.B, sd.b);
@@ -527,15 +628,18 @@ int32_t synthesize_impl(fvv_ctx *c, const fvv_camera *virts, int n_views, const 
             sd.sy = (float)((double)vc.fy / (double)sc.fy);
         }
     }
-    HIPCHECK(c, hipStreamWaitEvent(s, fs.ready, 0));
-    HIPCHECK(c, hipMemcpyAsync(c->d_desc, hd, (size_t)n_views * sizeof(fvv_view_desc), hipMemcpyHostToDevice, s));
-    HIPCHECK(c, hipEventRecord(c->h_desc_ev[r], s));
-    c->h_desc_ev_live[r] = true;
-    HIPCHECK(c, fvv_launch_synthesis(c->d_desc, dims, s, c->profiling ? &c->prof : nullptr));
-    HIPCHECK(c, hipEventRecord(fs.last_use, s));
-    fs.used = true;
-    c->have_taps = c->debug;
-    c->last_px = (int64_t)virts[0].width * virts[0].height;
+    bool waited[2] = {false, false};
+    for (int v = 0; v < n_views; ++v)
+        if (!waited[slot_of[v]]) {
+            HIPCHECK(c, hipStreamWaitEvent(s, c->slots[slot_of[v]].ready, 0));
+            waited[slot_of[v]] = true;
+        }
+    HIPCHECK(c, hipMemcpyAsync(Wk.d_desc, hd, (size_t)n_views * sizeof(fvv_view_desc), hipMemcpyHostToDevice, s));
+    HIPCHECK(c, hipEventRecord(Wk.h_ev[r], s));
+    Wk.h_live[r] = true;
+    HIPCHECK(c, fvv_launch_synthesis(Wk.d_desc, dims, s, c->profiling ? &c->prof : nullptr));
+    for (int q = 0; q < 2; ++q)
+        if (waited[q] && (rc = note_reader(c, c->slots[q], s))) return rc;
     if (host_out) {
         for (int v = 0; v < n_views; ++v)
             HIPCHECK(c, hipMemcpy2DAsync(outs[v], pitches[v], host_stage[v], (size_t)virts[v].width * 3,
@@ -543,6 +647,223 @@ int32_t synthesize_impl(fvv_ctx *c, const fvv_camera *virts, int n_views, const 
         HIPCHECK(c, hipStreamSynchronize(s));
     }
     return FVV_OK;
+}
+
+int32_t synthesize_impl(fvv_ctx *c, const fvv_camera *virts, int n_views, const fvv_synth_params *params,
+                        void *const *outs, const int64_t *pitches, int32_t mem_kind, void *stream)
+{
+    if (!c) return FVV_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (!virts || n_views < 1 || !outs || !pitches) return fail(c, FVV_E_ARG, "null argument or n_views < 1");
+    if (mem_kind != FVV_MEM_HOST && mem_kind != FVV_MEM_DEVICE) return fail(c, FVV_E_ARG, "bad mem_kind");
+    if (c->rig.empty()) return fail(c, FVV_E_STATE, "no rig set");
+    fvv_synth_params P;
+    int32_t rc = resolve_params(c, params, P);
+    if (rc) return rc;
+    int si;
+    if ((rc = find_slot(c, P.frame_version, si))) return rc;
+    for (int v = 0; v < n_views; ++v) {
+        if ((rc = check_camera(c, virts[v], false, "virtual camera"))) return rc;
+        if (!outs[v]) return fail(c, FVV_E_ARG, "outs[%d] is null", v);
+        if (pitches[v] < (int64_t)virts[v].width * 3) return fail(c, FVV_E_ARG, "pitches[%d] too small", v);
+    }
+    DeviceGuard g(c->device);
+    std::vector<fvv_synth_params> Ps(n_views, P);
+    rc = launch_views(c, c->user, virts, Ps.data(), n_views, outs, pitches, mem_kind == FVV_MEM_HOST,
+                      (hipStream_t)stream, true, c->debug);
+    if (rc) return rc;
+    c->have_taps = c->debug;
+    c->last_px = (int64_t)virts[0].width * virts[0].height;
+    return FVV_OK;
+}
+
+// ---------------------------------------------------------------- server
+// Upper bound of the workspace one request can need (any K cameras of the rig).
+void request_bounds(const fvv_ctx *c, const fvv_camera &v, int k, size_t &bytes, size_t &tiles)
+{
+    std::vector<int> nb;
+    for (const auto &cam : c->rig) nb.push_back(nblocks(cam));
+    std::sort(nb.rbegin(), nb.rend());
+    const int K = std::min<int>({k, (int)nb.size(), FVV_MAX_K});
+    ViewLayout L;
+    layout_sizes(L, v.width, v.height, nb.data(), K);
+    bytes = view_ws_bytes(v.width, v.height, L, false);
+    tiles = (size_t)L.n_tiles;
+}
+
+void finish(Server *S, const Request &r, int32_t status, double latency)
+{
+    std::lock_guard<std::mutex> lk(S->dmu);
+    Result &res = S->results[r.ticket];
+    res.done = true;
+    res.status = status;
+    res.latency = latency;
+    if (status == FVV_OK) {
+        ++S->n_done;
+        S->pixels += (uint64_t)r.cam.width * r.cam.height;
+    } else {
+        ++S->n_failed;
+    }
+}
+
+// Continuous batching: whenever one of the two step workspaces is free, the
+// pending requests are admitted in arrival order while step slots and
+// workspace memory last, and launched as one batch on that workspace's
+// stream; the other workspace's step may still be running.
+void scheduler(fvv_ctx *c)
+{
+    Server *S = c->server;
+    for (;;) {
+        std::vector<Request> batch;
+        int w = -1;
+        {
+            std::unique_lock<std::mutex> lk(S->qmu);
+            S->qcv.wait(lk, [&] { return (S->stop && S->pending.empty()) ||
+                                         (!S->pending.empty() && (!S->paused || S->stop) &&
+                                          (!S->busy[0] || !S->busy[1])); });
+            if (S->pending.empty()) break;
+            w = S->busy[0] ? 1 : 0;
+            size_t bytes = 0, tiles = 0;
+            while (!S->pending.empty() && (int)batch.size() < S->max_slots) {
+                Request &r = S->pending.front();
+                if (r.bytes > S->step_bytes || r.tiles > S->step_tiles) {
+                    Request bad = r;
+                    S->pending.pop_front();
+                    lk.unlock();
+                    finish(S, bad, FVV_E_NOMEM, 0.0);
+                    lk.lock();
+                    continue;
+                }
+                if (bytes + r.bytes > S->step_bytes || tiles + r.tiles > S->step_tiles) break;
+                bytes += r.bytes;
+                tiles += r.tiles;
+                batch.push_back(r);
+                S->pending.pop_front();
+            }
+            if (batch.empty()) continue;
+            S->busy[w] = true;
+        }
+        int32_t rc;
+        {
+            std::lock_guard<std::mutex> lk(c->mu);
+            DeviceGuard g(c->device);
+            std::vector<fvv_camera> cams;
+            std::vector<fvv_synth_params> Ps;
+            std::vector<void *> outs;
+            std::vector<int64_t> pitches;
+            for (auto &r : batch) {
+                cams.push_back(r.cam);
+                Ps.push_back(r.P);
+                outs.push_back(r.out);
+                pitches.push_back(r.pitch);
+            }
+            rc = launch_views(c, S->ws[w], cams.data(), Ps.data(), (int)batch.size(), outs.data(), pitches.data(),
+                              false, S->stream[w], false, false);
+            if (rc == FVV_OK && hipEventRecord(S->done_ev[w], S->stream[w]) != hipSuccess) rc = FVV_E_DEVICE;
+        }
+        if (rc != FVV_OK) {
+            for (auto &r : batch) finish(S, r, rc, 0.0);
+            std::lock_guard<std::mutex> lk(S->qmu);
+            S->busy[w] = false;
+            S->qcv.notify_all();
+            continue;
+        }
+        {
+            std::lock_guard<std::mutex> lk(S->cmu[w]);
+            S->inflight[w] = std::move(batch);
+            S->launched[w] = true;
+            S->launch_t[w] = Clock::now();
+        }
+        S->ccv[w].notify_all();
+    }
+    for (int w = 0; w < 2; ++w) {
+        std::lock_guard<std::mutex> lk(S->cmu[w]);
+        S->ccv[w].notify_all();
+    }
+}
+
+// Completion of workspace w's steps: wait for the step's event, stamp every
+// request of the step (latency = completion - submission, host clock) and
+// hand the workspace back to the scheduler.
+void completer(fvv_ctx *c, int w)
+{
+    Server *S = c->server;
+    for (;;) {
+        std::vector<Request> batch;
+        Clock::time_point t0;
+        {
+            std::unique_lock<std::mutex> lk(S->cmu[w]);
+            S->ccv[w].wait(lk, [&] {
+                if (S->launched[w]) return true;
+                std::lock_guard<std::mutex> q(S->qmu);
+                return S->stop && S->pending.empty() && !S->busy[w];
+            });
+            if (!S->launched[w]) break;
+            batch = std::move(S->inflight[w]);
+            S->launched[w] = false;
+            t0 = S->launch_t[w];
+        }
+        int32_t status = FVV_OK;
+        {
+            DeviceGuard g(c->device);
+            if (hipEventSynchronize(S->done_ev[w]) != hipSuccess) status = FVV_E_DEVICE;
+        }
+        const Clock::time_point t = Clock::now();
+        for (auto &r : batch) finish(S, r, status, std::chrono::duration<double>(t - r.arrive).count());
+        {
+            std::lock_guard<std::mutex> lk(S->dmu);
+            ++S->n_steps;
+            S->batch_sum += batch.size();
+            S->busy_s += std::chrono::duration<double>(t - t0).count();
+        }
+        {
+            std::lock_guard<std::mutex> lk(S->qmu);
+            S->busy[w] = false;
+        }
+        S->qcv.notify_all();
+        for (int o = 0; o < 2; ++o) S->ccv[o].notify_all();
+    }
+}
+
+void server_teardown(fvv_ctx *c)
+{
+    Server *S = c->server;
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->qmu);
+        S->stop = true;
+    }
+    S->qcv.notify_all();
+    if (S->sched.joinable()) S->sched.join();
+    for (int w = 0; w < 2; ++w) {
+        {
+            std::lock_guard<std::mutex> lk(S->cmu[w]);
+        }
+        S->ccv[w].notify_all();
+        if (S->compl_[w].joinable()) S->compl_[w].join();
+    }
+    std::lock_guard<std::mutex> lk(c->mu);
+    DeviceGuard g(c->device);
+    for (int w = 0; w < 2; ++w) {
+        if (S->stream[w]) {
+            (void)hipStreamSynchronize(S->stream[w]);
+            for (auto &slot : c->slots) {
+                auto &rd = slot.readers;
+                for (size_t e = 0; e < rd.size();)
+                    if (rd[e].first == S->stream[w]) {
+                        c->event_pool.push_back(rd[e].second);
+                        rd.erase(rd.begin() + e);
+                    } else {
+                        ++e;
+                    }
+            }
+            (void)hipStreamDestroy(S->stream[w]);
+        }
+        if (S->done_ev[w]) (void)hipEventDestroy(S->done_ev[w]);
+        ws_release(c, S->ws[w]);
+    }
+    delete S;
+    c->server = nullptr;
 }
 
 }  // namespace
@@ -571,28 +892,23 @@ int32_t fvv_create(int32_t hip_device, uint64_t mem_budget_bytes, fvv_ctx **out)
 void fvv_destroy(fvv_ctx *c)
 {
     if (!c) return;
+    server_teardown(c);
     {
+        std::lock_guard<std::mutex> lk(c->mu);
         DeviceGuard g(c->device);
         (void)hipDeviceSynchronize();
         if (!c->rig.empty()) release_frames(c);
-        for (auto &s : c->slots) {
+        for (auto &s : c->slots)
             if (s.ready) (void)hipEventDestroy(s.ready);
-            if (s.last_use) (void)hipEventDestroy(s.last_use);
-        }
         dfree(c, c->staging, c->staging_bytes);
         if (c->staging_free) (void)hipEventDestroy(c->staging_free);
-        dfree(c, c->ws, c->ws_bytes);
-        dfree(c, c->d_desc, c->desc_cap * sizeof(fvv_view_desc));
-        for (int r = 0; r < fvv_ctx::kRing; ++r) {
-            if (c->h_desc[r]) (void)hipHostFree(c->h_desc[r]);
-            if (c->h_desc_ev[r]) (void)hipEventDestroy(c->h_desc_ev[r]);
-        }
-        dfree(c, c->counts, c->counts_cap * 4);
+        ws_release(c, c->user);
         dfree(c, c->dbg_z, c->dbg_px * 8);
         dfree(c, c->dbg_zf, c->dbg_px * 8);
         dfree(c, c->dbg_rgba, c->dbg_px * 4);
         dfree(c, c->dbg_depth, c->dbg_px * 4);
         for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
+        for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
     }
     delete c;
 }
@@ -602,6 +918,8 @@ const char *fvv_last_error(const fvv_ctx *c) { return c ? c->err.c_str() : g_cre
 int32_t fvv_set_rig(fvv_ctx *c, const fvv_camera *cams, int32_t n)
 {
     if (!c) return FVV_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->server) return fail(c, FVV_E_STATE, "stop the server before changing the rig");
     if (!cams || n < 1 || n > FVV_MAX_CAMERAS) return fail(c, FVV_E_ARG, "rig size %d outside 1..%d", n, FVV_MAX_CAMERAS);
     for (int k = 0; k < n; ++k) {
         int32_t rc = check_camera(c, cams[k], true, "rig camera");
@@ -618,6 +936,7 @@ int32_t fvv_upload_mvd(fvv_ctx *c, const fvv_view *views, int32_t n, int32_t mem
                        uint64_t *out_version)
 {
     if (!c) return FVV_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
     if (c->rig.empty()) return fail(c, FVV_E_STATE, "no rig set");
     if (!views || n != (int)c->rig.size()) return fail(c, FVV_E_ARG, "need one view per rig camera (%zu)", c->rig.size());
     if (mem_kind != FVV_MEM_HOST && mem_kind != FVV_MEM_DEVICE) return fail(c, FVV_E_ARG, "bad mem_kind");
@@ -630,18 +949,20 @@ int32_t fvv_upload_mvd(fvv_ctx *c, const fvv_view *views, int32_t n, int32_t mem
         if (!v.rgb || !v.depth_mm) return fail(c, FVV_E_ARG, "view %d: rgb and depth must both be given", k);
         if (v.rgb_pitch < (int64_t)cam.width * 3 || v.depth_pitch < (int64_t)cam.width * 2)
             return fail(c, FVV_E_ARG, "view %d: pitch too small", k);
-        if (v.depth_pitch % 2) return fail(c, FVV_E_ARG, "view %d: depth pitch must be even", k);
+        if (v.depth_pitch % 2 || ((uintptr_t)v.depth_mm & 1))
+            return fail(c, FVV_E_ARG, "view %d: depth must be 2-byte aligned (pointer and pitch)", k);
         need += align256((size_t)cam.width * cam.height * 3) + align256((size_t)cam.width * cam.height * 2);
         ++n_present;
     }
     if (n_present == 0) return fail(c, FVV_E_ARG, "no camera present in the upload");
     DeviceGuard g(c->device);
     hipStream_t s = (hipStream_t)stream;
+    const bool host = mem_kind == FVV_MEM_HOST;
     const int dst = c->latest < 0 ? 0 : 1 - c->latest;
     FrameSlot &fs = c->slots[dst];
     int32_t rc = ensure_frame_slot(c, fs);
     if (rc) return rc;
-    if (c->staging_bytes < need) {
+    if (host && c->staging_bytes < need) {
         HIPCHECK(c, hipDeviceSynchronize());
         dfree(c, c->staging, c->staging_bytes);
         c->staging = nullptr;
@@ -650,9 +971,12 @@ int32_t fvv_upload_mvd(fvv_ctx *c, const fvv_view *views, int32_t n, int32_t mem
         c->staging_bytes = need;
     }
     if (!c->staging_free) HIPCHECK(c, hipEventCreateWithFlags(&c->staging_free, hipEventDisableTiming));
-    else HIPCHECK(c, hipStreamWaitEvent(s, c->staging_free, 0));
-    if (fs.used) HIPCHECK(c, hipStreamWaitEvent(s, fs.last_use, 0));
-    const hipMemcpyKind kind = mem_kind == FVV_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+    else if (host) HIPCHECK(c, hipStreamWaitEvent(s, c->staging_free, 0));
+    for (auto &r : fs.readers) HIPCHECK(c, hipStreamWaitEvent(s, r.second, 0));
+    // device memory is read in place by the repack kernel; host memory is
+    // first copied into the staging buffer
+    fvv_repack_batch b{};
+    int max_w = 0, max_h = 0;
     uint8_t *cur = c->staging;
     for (int k = 0; k < n; ++k) {
         const fvv_view &v = views[k];
@@ -660,21 +984,40 @@ int32_t fvv_upload_mvd(fvv_ctx *c, const fvv_view *views, int32_t n, int32_t mem
         fs.present[k] = (v.rgb && v.depth_mm) ? 1 : 0;
         if (!fs.present[k]) continue;
         const int W = cam.width, H = cam.height;
-        uint8_t *rgb = cur;
-        cur += align256((size_t)W * H * 3);
-        uint16_t *dep = (uint16_t *)cur;
-        cur += align256((size_t)W * H * 2);
-        HIPCHECK(c, hipMemcpy2DAsync(rgb, (size_t)W * 3, v.rgb, v.rgb_pitch, (size_t)W * 3, H, kind, s));
-        HIPCHECK(c, hipMemcpy2DAsync(dep, (size_t)W * 2, v.depth_mm, v.depth_pitch, (size_t)W * 2, H, kind, s));
-        HIPCHECK(c, fvv_launch_repack(rgb, (int64_t)W * 3, dep, (int64_t)W * 2, W, H, cam.depth_alpha,
-                                      cam.depth_beta, fs.texel[k], fs.depth[k], s,
-                                      c->profiling ? &c->prof : nullptr));
+        fvv_repack_cam &rc_ = b.cam[b.n++];
+        if (host) {
+            uint8_t *rgb = cur;
+            cur += align256((size_t)W * H * 3);
+            uint8_t *dep = cur;
+            cur += align256((size_t)W * H * 2);
+            HIPCHECK(c, hipMemcpy2DAsync(rgb, (size_t)W * 3, v.rgb, v.rgb_pitch, (size_t)W * 3, H,
+                                         hipMemcpyHostToDevice, s));
+            HIPCHECK(c, hipMemcpy2DAsync(dep, (size_t)W * 2, v.depth_mm, v.depth_pitch, (size_t)W * 2, H,
+                                         hipMemcpyHostToDevice, s));
+            rc_.rgb = rgb;
+            rc_.rgb_pitch = (int64_t)W * 3;
+            rc_.depth = dep;
+            rc_.depth_pitch = (int64_t)W * 2;
+        } else {
+            rc_.rgb = (const uint8_t *)v.rgb;
+            rc_.rgb_pitch = v.rgb_pitch;
+            rc_.depth = (const uint8_t *)v.depth_mm;
+            rc_.depth_pitch = v.depth_pitch;
+        }
+        rc_.texel_out = fs.texel[k];
+        rc_.depth_out = fs.depth[k];
+        rc_.W = W;
+        rc_.H = H;
+        rc_.alpha = cam.depth_alpha;
+        rc_.beta = cam.depth_beta;
+        max_w = std::max(max_w, W);
+        max_h = std::max(max_h, H);
     }
-    HIPCHECK(c, hipEventRecord(c->staging_free, s));
+    HIPCHECK(c, fvv_launch_repack(b, max_w, max_h, s, c->profiling ? &c->prof : nullptr));
+    if (host) HIPCHECK(c, hipEventRecord(c->staging_free, s));
     HIPCHECK(c, hipEventRecord(fs.ready, s));
     if (mem_kind == FVV_MEM_HOST) HIPCHECK(c, hipStreamSynchronize(s));
     fs.version = c->next_version++;
-    fs.used = false;
     c->latest = dst;
     if (out_version) *out_version = fs.version;
     return FVV_OK;
@@ -724,6 +1067,7 @@ static const char *k_stage_names[FVV_NSTAGES] = {"repack", "bin_count", "bin_sca
 int32_t fvv_set_profiling(fvv_ctx *c, int32_t enable)
 {
     if (!c) return FVV_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
     c->profiling = enable != 0;
     return FVV_OK;
 }
@@ -738,6 +1082,7 @@ const char *fvv_stage_name(int32_t stage)
 int32_t fvv_profile_read(fvv_ctx *c, double *total_ms, int64_t *launches, int32_t n, int32_t reset)
 {
     if (!c) return FVV_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
     if (!total_ms || !launches || n < FVV_NSTAGES) return fail(c, FVV_E_ARG, "need %d entries", FVV_NSTAGES);
     DeviceGuard g(c->device);
     for (auto &m : c->prof.marks) {
@@ -763,6 +1108,7 @@ int32_t fvv_profile_read(fvv_ctx *c, double *total_ms, int64_t *launches, int32_
 int32_t fvv_set_debug(fvv_ctx *c, int32_t enable)
 {
     if (!c) return FVV_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
     c->debug = enable != 0;
     return FVV_OK;
 }
@@ -770,6 +1116,7 @@ int32_t fvv_set_debug(fvv_ctx *c, int32_t enable)
 int32_t fvv_debug_read(fvv_ctx *c, int32_t tap, void *host_out, int64_t bytes)
 {
     if (!c) return FVV_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
     if (!host_out) return fail(c, FVV_E_ARG, "host_out is null");
     if (!c->have_taps) return fail(c, FVV_E_STATE, "no debug taps: enable with fvv_set_debug before synthesis");
     DeviceGuard g(c->device);
@@ -785,6 +1132,139 @@ int32_t fvv_debug_read(fvv_ctx *c, int32_t tap, void *host_out, int64_t bytes)
     if (bytes != need) return fail(c, FVV_E_ARG, "tap %d holds %lld bytes, asked %lld", tap, (long long)need, (long long)bytes);
     HIPCHECK(c, hipDeviceSynchronize());
     HIPCHECK(c, hipMemcpy(host_out, src, (size_t)need, hipMemcpyDeviceToHost));
+    return FVV_OK;
+}
+
+int32_t fvv_server_start(fvv_ctx *c, int32_t max_slots, uint64_t step_bytes)
+{
+    if (!c) return FVV_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->server) return fail(c, FVV_E_STATE, "server already running");
+    if (c->rig.empty()) return fail(c, FVV_E_STATE, "no rig set");
+    if (max_slots < 1 || max_slots > 4096) return fail(c, FVV_E_ARG, "max_slots %d outside 1..4096", max_slots);
+    DeviceGuard g(c->device);
+    Server *S = new (std::nothrow) Server();
+    if (!S) return fail(c, FVV_E_NOMEM, "out of host memory");
+    S->max_slots = max_slots;
+    if (step_bytes == 0) {
+        // default: room for max_slots 1920x1080 views drawing on three cameras
+        fvv_camera v1080{};
+        v1080.width = 1920;
+        v1080.height = 1080;
+        size_t b, t;
+        request_bounds(c, v1080, 3, b, t);
+        step_bytes = (uint64_t)b * max_slots;
+    }
+    S->step_bytes = step_bytes;
+    // tile counters: a 1920x1080 view has 2040 tiles in under 9 MB of workspace
+    S->step_tiles = std::max<size_t>(4096, step_bytes / 2048);
+    int32_t rc = FVV_OK;
+    for (int w = 0; w < 2 && rc == FVV_OK; ++w) {
+        rc = ws_reserve(c, S->ws[w], S->step_bytes, S->step_tiles, (size_t)max_slots);
+        if (rc == FVV_OK && hipStreamCreateWithFlags(&S->stream[w], hipStreamNonBlocking) != hipSuccess)
+            rc = fail(c, FVV_E_DEVICE, "hipStreamCreate failed");
+        if (rc == FVV_OK &&
+            hipEventCreateWithFlags(&S->done_ev[w], hipEventDisableTiming | hipEventBlockingSync) != hipSuccess)
+            rc = fail(c, FVV_E_DEVICE, "hipEventCreate failed");
+    }
+    if (rc != FVV_OK) {
+        for (int w = 0; w < 2; ++w) {
+            if (S->stream[w]) (void)hipStreamDestroy(S->stream[w]);
+            if (S->done_ev[w]) (void)hipEventDestroy(S->done_ev[w]);
+            ws_release(c, S->ws[w]);
+        }
+        delete S;
+        return rc;
+    }
+    c->server = S;
+    S->sched = std::thread(scheduler, c);
+    for (int w = 0; w < 2; ++w) S->compl_[w] = std::thread(completer, c, w);
+    return FVV_OK;
+}
+
+int32_t fvv_server_pause(fvv_ctx *c, int32_t paused)
+{
+    if (!c) return FVV_E_ARG;
+    Server *S = c->server;
+    if (!S) return fail(c, FVV_E_STATE, "server not running");
+    {
+        std::lock_guard<std::mutex> lk(S->qmu);
+        S->paused = paused != 0;
+    }
+    S->qcv.notify_all();
+    return FVV_OK;
+}
+
+int32_t fvv_server_stop(fvv_ctx *c)
+{
+    if (!c) return FVV_E_ARG;
+    if (!c->server) return fail(c, FVV_E_STATE, "server not running");
+    server_teardown(c);
+    return FVV_OK;
+}
+
+int32_t fvv_submit(fvv_ctx *c, const fvv_camera *virt, const fvv_synth_params *params, void *out_dev,
+                   int64_t out_pitch, uint64_t *ticket)
+{
+    if (!c || !virt || !out_dev || !ticket) return FVV_E_ARG;
+    Request r;
+    Server *S;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        S = c->server;
+        if (!S) return fail(c, FVV_E_STATE, "server not running");
+        int32_t rc = resolve_params(c, params, r.P);
+        if (rc) return rc;
+        if ((rc = check_camera(c, *virt, false, "virtual camera"))) return rc;
+        if (out_pitch < (int64_t)virt->width * 3) return fail(c, FVV_E_ARG, "out_pitch too small");
+        request_bounds(c, *virt, r.P.k_nearest, r.bytes, r.tiles);
+    }
+    r.cam = *virt;
+    r.out = out_dev;
+    r.pitch = out_pitch;
+    r.arrive = Clock::now();
+    {
+        std::lock_guard<std::mutex> lk(S->qmu);
+        if (S->stop) return FVV_E_STATE;
+        if (S->pending.size() >= 65536) return FVV_E_AGAIN;
+        r.ticket = S->next_ticket++;
+        {
+            std::lock_guard<std::mutex> d(S->dmu);
+            S->results[r.ticket] = Result();
+        }
+        S->pending.push_back(r);
+    }
+    S->qcv.notify_all();
+    *ticket = r.ticket;
+    return FVV_OK;
+}
+
+int32_t fvv_poll(fvv_ctx *c, uint64_t ticket, double *latency_s)
+{
+    if (!c || !c->server) return FVV_E_STATE;
+    Server *S = c->server;
+    std::lock_guard<std::mutex> lk(S->dmu);
+    auto it = S->results.find(ticket);
+    if (it == S->results.end()) return FVV_E_ARG;
+    if (!it->second.done) return FVV_E_AGAIN;
+    const int32_t st = it->second.status;
+    if (latency_s) *latency_s = it->second.latency;
+    S->results.erase(it);
+    return st;
+}
+
+int32_t fvv_server_stats(fvv_ctx *c, uint64_t *out6)
+{
+    if (!c || !out6) return FVV_E_ARG;
+    if (!c->server) return FVV_E_STATE;
+    Server *S = c->server;
+    std::lock_guard<std::mutex> lk(S->dmu);
+    out6[0] = S->n_steps;
+    out6[1] = S->n_done;
+    out6[2] = S->n_failed;
+    out6[3] = S->pixels;
+    out6[4] = S->batch_sum;
+    out6[5] = (uint64_t)(S->busy_s * 1e6);
     return FVV_OK;
 }
 

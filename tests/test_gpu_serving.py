@@ -1,0 +1,198 @@
+"""GPU tests of the continuous-batching server: every result served in a mix
+of concurrent requests of different output sizes equals the same request
+rendered alone (plain path: bit-exact), admission by step memory, frame
+refreshes while serving, draining on stop."""
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def fvv():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2007_00558_amd as m
+    m.lib()
+    return m
+
+
+def _mixed_views(w, n, seed):
+    rng = np.random.default_rng(seed)
+    sizes = [(96, 54), (160, 90), (200, 120), (33, 17)]
+    out = []
+    for q in range(n):
+        a = rng.uniform(-20, 20)
+        W, H = sizes[q % len(sizes)]
+        out.append(sg.arc_camera(a, rng.uniform(2.0, 2.4), W, H))
+    return out
+
+
+def _wait(srv, tickets, timeout=60.0):
+    lat = {}
+    t_end = time.time() + timeout
+    pending = set(tickets)
+    while pending:
+        assert time.time() < t_end, f"{len(pending)} requests did not complete"
+        for t in list(pending):
+            r = srv.poll(t)
+            if r is not None:
+                lat[t] = r
+                pending.discard(t)
+        time.sleep(0.001)
+    return lat
+
+
+def test_served_mix_equals_alone(fvv):
+    import torch
+    say("[gpu] serving mix vs alone")
+    w = sg.config_small(11, n_cams=5, w=120, h=80)
+    ctx = fvv.Context(0)
+    ctx.set_rig(w.rig)
+    ctx.upload_mvd(w.frames)
+    views = _mixed_views(w, 48, 0)
+    alone = [ctx.synthesize(v) for v in views]
+    srv = fvv.Server(ctx, max_slots=8)
+    outs = [torch.full((v.height, v.width, 3), 7, dtype=torch.uint8, device="cuda") for v in views]
+    torch.cuda.synchronize()   # output buffers must be idle before submission
+    tickets = [None] * len(views)
+    # phase 1: held while submitting, so the steps must batch 8 at a time
+    srv.pause(True)
+    first = [srv.submit(views[q], outs[q]) for q in range(16)]
+    srv.pause(False)
+    _wait(srv, first)
+    st1 = srv.stats()
+    assert st1["steps"] == 2 and st1["batch_sum"] == 16
+    for q in range(16):
+        tickets[q] = first[q]
+    # phase 2: two submitting threads racing the scheduler
+
+    def submitter(idx):
+        for q in idx:
+            tickets[q] = srv.submit(views[q], outs[q])
+            time.sleep(0.0005)
+
+    th = [threading.Thread(target=submitter, args=(list(range(s, len(views), 2)),)) for s in (16, 17)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    lat = _wait(srv, tickets[16:])
+    st = srv.stats()
+    srv.stop()
+    torch.cuda.synchronize()
+    for a, o in zip(alone, outs):
+        assert np.array_equal(a, o.cpu().numpy())
+    assert st["completed"] == len(views) and st["failed"] == 0
+    assert all(v > 0 for v in lat.values())
+    ctx.close()
+
+
+def test_admission_by_memory_and_oversized_request(fvv):
+    import torch
+    say("[gpu] serving admission")
+    w = sg.config_small(12, n_cams=3, w=96, h=64)
+    ctx = fvv.Context(0)
+    ctx.set_rig(w.rig)
+    ctx.upload_mvd(w.frames)
+    small = [sg.arc_camera(a, 2.2, 64, 40) for a in (-5.0, 0.0, 5.0, 8.0)]
+    alone = [ctx.synthesize(v) for v in small]
+    # a step holds one 64x40 view but not two, and never a 640x400 one
+    srv = fvv.Server(ctx, max_slots=16, step_bytes=30_000)
+    outs = [torch.zeros((v.height, v.width, 3), dtype=torch.uint8, device="cuda") for v in small]
+    big = sg.arc_camera(0.0, 2.2, 640, 400)
+    big_out = torch.zeros((400, 640, 3), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    tickets = [srv.submit(v, o) for v, o in zip(small, outs)]
+    tb = srv.submit(big, big_out)
+    _wait(srv, tickets)
+    t_end = time.time() + 30
+    while True:
+        try:
+            r = srv.poll(tb)
+        except fvv.FvvError as e:
+            assert e.code == fvv.FVV_E_NOMEM
+            break
+        assert r is None and time.time() < t_end
+        time.sleep(0.001)
+    st = srv.stats()
+    srv.stop()
+    torch.cuda.synchronize()
+    assert st["steps"] == len(small) and st["failed"] == 1
+    for a, o in zip(alone, outs):
+        assert np.array_equal(a, o.cpu().numpy())
+    ctx.close()
+
+
+def test_refresh_while_serving(fvv):
+    import torch
+    say("[gpu] serving with refreshes")
+    w1 = sg.config_small(13, n_cams=3, w=96, h=64)
+    w2 = sg.config_small(14, n_cams=3, w=96, h=64)   # same rig geometry, new scene
+    ctx = fvv.Context(0)
+    ctx.set_rig(w1.rig)
+    v1 = ctx.upload_mvd(w1.frames)
+    views = _mixed_views(w1, 24, 1)
+    ref1 = [ctx.synthesize(v) for v in views]
+    v2 = ctx.upload_mvd(w2.frames)
+    ref2 = [ctx.synthesize(v) for v in views]
+    ctx.upload_mvd(w1.frames)   # version 3 == scene 1; v2 stays resident
+    srv = fvv.Server(ctx, max_slots=4)
+    outs = [torch.zeros((v.height, v.width, 3), dtype=torch.uint8, device="cuda") for v in views]
+    outs2 = [torch.zeros_like(o) for o in outs]
+    torch.cuda.synchronize()
+    tickets = []
+    for q, (v, o) in enumerate(zip(views, outs)):
+        tickets.append(srv.submit(v, o, fvv.params(frame_version=v2 if q % 2 else 0)))
+    _wait(srv, tickets)
+    # keep serving while new frame sets arrive
+    more = []
+    for q, (v, o) in enumerate(zip(views, outs2)):
+        more.append(srv.submit(v, o))
+        if q % 6 == 0:
+            ctx.upload_mvd(w1.frames)
+    _wait(srv, more)
+    srv.stop()
+    torch.cuda.synchronize()
+    for q, o in enumerate(outs):
+        assert np.array_equal((ref2 if q % 2 else ref1)[q], o.cpu().numpy()), q
+    for q, o in enumerate(outs2):
+        assert np.array_equal(ref1[q], o.cpu().numpy()), q
+    assert v1 == 1
+    ctx.close()
+
+
+def test_stop_drains_pending(fvv):
+    import torch
+    say("[gpu] serving drain")
+    w = sg.config_small(15, n_cams=3, w=96, h=64)
+    ctx = fvv.Context(0)
+    ctx.set_rig(w.rig)
+    ctx.upload_mvd(w.frames)
+    views = _mixed_views(w, 40, 2)
+    srv = fvv.Server(ctx, max_slots=2)
+    outs = [torch.zeros((v.height, v.width, 3), dtype=torch.uint8, device="cuda") for v in views]
+    torch.cuda.synchronize()
+    for v, o in zip(views, outs):
+        srv.submit(v, o)
+    st_before = srv.stats()
+    srv.stop()
+    torch.cuda.synchronize()
+    ref = [ctx.synthesize(v) for v in views]
+    for a, o in zip(ref, outs):
+        assert np.array_equal(a, o.cpu().numpy())
+    assert st_before["completed"] <= len(views)
+    with pytest.raises(fvv.FvvError):
+        srv.ctx._check(ctx._L.fvv_server_stop(ctx._h))
+    ctx.close()
