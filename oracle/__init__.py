@@ -85,6 +85,8 @@ def lib():
         L.fvv_ref_blend.restype = None
         L.fvv_ref_blend.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(RefTex), C.c_int32, C.c_float,
                                     P, P, P]
+        L.fvv_ref_stack.restype = None
+        L.fvv_ref_stack.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(RefTex), C.c_int32, C.c_float, P]
         L.fvv_ref_fill.restype = None
         L.fvv_ref_fill.argtypes = [P, P, P, C.c_int32, C.c_int32, C.c_int32, P]
         L.fvv_ref_synthesize.restype = C.c_int32
@@ -177,6 +179,50 @@ def blend(Zf, rig, frames, virt, sel, weights, tau: float = 0.05):
     dep = np.empty((H, W), np.float32)
     lib().fvv_ref_blend(_ptr(Zf), W, H, texs, len(sel), tau, _ptr(rgb), _ptr(hole), _ptr(dep))
     return rgb, hole, dep
+
+
+def _texs(rig, frames, virt, sel, weights):
+    pairs = [pair(rig[c], virt) for c in sel]
+    keep = [pairs]
+    texs = (RefTex * max(1, len(sel)))()
+    for k, c in enumerate(sel):
+        rgb = np.ascontiguousarray(frames[c].rgb, np.uint8)
+        dep = np.ascontiguousarray(frames[c].depth_mm, np.uint16)
+        keep += [rgb, dep]
+        texs[k] = RefTex(_ptr(rgb), rgb.shape[1] * 3, _ptr(dep), dep.shape[1],
+                         dep.shape[1], dep.shape[0], rig[c].depth_alpha, rig[c].depth_beta,
+                         C.pointer(pairs[k]), float(weights[k]))
+    return texs, keep
+
+
+def stack(Zf, rig, frames, virt, sel, weights, tau: float = 0.05, pad_rows: int = 0,
+          pad_cols: int = 0) -> np.ndarray:
+    """O6': network input, float64 (H + pad_rows, W + pad_cols, 16): 15
+    per-camera channels (R, G, B, inverse depth, validity for up to three
+    cameras in selection order) and a zero channel; padding is zero.  Values
+    are not rounded; the network rounds them to bfloat16."""
+    Zf = np.ascontiguousarray(Zf, np.uint64)
+    H, W = Zf.shape
+    texs, keep = _texs(rig, frames, virt, sel, weights)
+    st = np.zeros((H, W, 15), np.float64)
+    lib().fvv_ref_stack(_ptr(Zf), W, H, texs, len(sel), tau, _ptr(st))
+    out = np.zeros((H + pad_rows, W + pad_cols, 16), np.float64)
+    out[:H, :W, :15] = st
+    return out
+
+
+def synthesize_learned(rig, frames, virt, net_params, k_nearest: int = 3, tau: float = 0.05,
+                       max_fp: float = 4.0, widths=None):
+    """Learned path for one view: O1..O5, the O6' stack on the padded grid
+    (multiples of 8), the network (oracle.unet, bfloat16 points as on the
+    device), RGB8 of the image area.  Returns (rgb, s, stack)."""
+    from . import unet
+    r = synthesize(rig, frames, virt, k_nearest=k_nearest, tau=tau, max_fp=max_fp, taps=True)
+    H, W = virt.height, virt.width
+    Hp, Wp = -(-H // 8) * 8, -(-W // 8) * 8
+    st = stack(r["zf"], rig, frames, virt, r["sel"], r["weights"], tau, Hp - H, Wp - W)
+    s, _ = unet.forward(net_params, st, widths or unet.WIDTHS)
+    return unet.to_rgb8(s)[:H, :W], s, st
 
 
 def fill(rgb, hole, depth, mode: int = 0) -> np.ndarray:

@@ -449,6 +449,64 @@ void fvv_ref_blend(const uint64_t *Zf, int32_t W, int32_t H, const ref_tex *tex,
 }
 
 /* ------------------------------------------------------------------------ */
+/* O6': input of the learned blend/inpaint network (reading: the paper mixes
+ * the warped cameras with fixed distance weights, Section VI; the learned
+ * path hands the same per-camera evidence to a network instead).  For every
+ * pixel whose filtered z-buffer holds a point, and for each selected camera
+ * slot k (selection order), the depth-consistent bilinear colour of that
+ * camera -- the same sample O6 mixes -- gives five values: R, G, B divided
+ * by 255, the inverse source-camera depth 0.5 / q_z (fp32, capped at 1) and
+ * a validity flag 1.  Cameras that give no sample, unused slots and pixels
+ * without a point give zeros.  Output: H*W*15 doubles, pixel-major. */
+void fvv_ref_stack(const uint64_t *Zf, int32_t W, int32_t H, const ref_tex *tex,
+                   int32_t K, float tau, double *stack)
+{
+    const float zclip = 0.01f;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            int64_t o = (int64_t)y * W + x;
+            double *st = stack + o * 15;
+            for (int c = 0; c < 15; ++c) st[c] = 0.0;
+            uint64_t key = Zf[o];
+            if (key == REF_EMPTY) continue;
+            float zf = ref_bitsf((uint32_t)(key >> 32));
+            for (int k = 0; k < K && k < 3; ++k) {
+                const ref_tex *t = &tex[k];
+                float q[3];
+                ref_project(t->pair->B, t->pair->b, (float)x, (float)y, zf, q);
+                if (!(q[2] > zclip)) continue;
+                float u = q[0] / q[2];
+                float v = q[1] / q[2];
+                if (!(u >= -0.5f && u <= (float)t->W - 0.5f)) continue;
+                if (!(v >= -0.5f && v <= (float)t->H - 0.5f)) continue;
+                float fi0 = floorf(u), fj0 = floorf(v);
+                float fu = u - fi0, fv = v - fj0;
+                int i0 = (int)fi0, j0 = (int)fj0;
+                float lim = tau * q[2];
+                double wt[4] = {(1.0 - fu) * (1.0 - fv), fu * (1.0 - (double)fv),
+                                (1.0 - fu) * (double)fv, (double)fu * (double)fv};
+                double cacc[3] = {0.0, 0.0, 0.0}, csum = 0.0;
+                for (int n = 0; n < 4; ++n) {
+                    int ii = i0 + (n & 1), jj = j0 + (n >> 1);
+                    if (ii < 0 || jj < 0 || ii >= t->W || jj >= t->H) continue;
+                    uint16_t d = t->depth[(int64_t)jj * t->depth_pitch + ii];
+                    if (d == 0) continue;
+                    float zs = fvv_ref_decode_depth(d, t->alpha, t->beta);
+                    if (!(fabsf(zs - q[2]) <= lim)) continue;
+                    const uint8_t *px = t->rgb + (int64_t)jj * t->rgb_pitch + (int64_t)ii * 3;
+                    for (int ch = 0; ch < 3; ++ch) cacc[ch] += wt[n] * (double)px[ch];
+                    csum += wt[n];
+                }
+                if (!(csum > 0.0)) continue;
+                for (int ch = 0; ch < 3; ++ch) st[5 * k + ch] = cacc[ch] / csum / 255.0;
+                float inv = 0.5f / q[2];
+                st[5 * k + 3] = inv < 1.0f ? (double)inv : 1.0;
+                st[5 * k + 4] = 1.0;
+            }
+        }
+}
+
+/* ------------------------------------------------------------------------ */
 /* O7: hole fill.  The paper leaves areas no camera sees black (Section IX);
  * mode 1 reproduces that.  Mode 0 (reading; disocclusions uncover
  * background): for every hole, the nearest non-hole pixel to the left,

@@ -492,3 +492,75 @@ def test_absent_camera_is_not_used(oracle_lib):
     frames[1] = None
     r = o.synthesize(w.rig, frames, w.virtual[1])
     assert 1 not in list(r["sel"])
+
+
+# ------------------------------------------------------------------ O6' (network input)
+def test_stack_identity_view_holds_source(oracle_lib):
+    """Virtual camera == rig camera 0 (selected alone): wherever the identity
+    fetch keeps the pixel, the first camera slot holds the source colour / 255,
+    0.5 / source depth (float32) and a validity flag; other slots are zero."""
+    o = oracle_lib
+    w = sg.config1(0)
+    r = o.synthesize(w.rig, w.frames, w.rig[0], k_nearest=3, taps=True, fill_mode=1)
+    assert list(r["sel"]) == [0]
+    st = o.stack(r["zf"], w.rig, w.frames, w.rig[0], r["sel"], r["weights"], pad_rows=5)
+    H, W = r["zf"].shape
+    assert st.shape == (H + 5, W, 16)
+    assert np.all(st[H:] == 0) and np.all(st[..., 15] == 0) and np.all(st[..., 5:] == 0)
+    st = st[:H]
+    valid = w.frames[0].depth_mm > 0
+    kept = valid & (r["z"] == r["zf"])
+    assert kept.sum() > 0.6 * valid.size
+    src = w.frames[0].rgb.astype(np.float64)
+    # the float32 identity warp lands within ~1e-5 px of the integer pixel
+    assert np.abs(st[..., 0:3][kept] * 255.0 - src[kept]).max() < 0.01
+    z = np.array([o.decode_depth(int(d)) for d in w.frames[0].depth_mm[kept][:2000]], np.float32)
+    inv = np.minimum(np.float32(0.5) / z, np.float32(1.0))
+    assert np.array_equal(st[..., 3][kept][:2000].astype(np.float32), inv)
+    assert np.all(st[..., 4][kept] == 1.0)
+
+
+def test_stack_two_cameras_keep_their_own_colours(oracle_lib):
+    """Two cameras at equal distance see a constant-colour plane each: the
+    two slots hold the two colours unmixed, in selection order, and the
+    inverse depth of the plane (0.5 / 2 m)."""
+    o = oracle_lib
+    W, H, fx, D = 40, 30, 60.0, 2.0
+    left = plain_cam(W, H, fx, t=(0.1, 0, 0))
+    right = plain_cam(W, H, fx, t=(-0.1, 0, 0))
+    virt = plain_cam(W, H, fx)
+    ca, cb = np.uint8([0, 100, 255]), np.uint8([50, 0, 255])
+    fa = plane_frame(left, D, lambda i, j: np.zeros(i.shape + (3,), np.uint8) + ca)
+    fb = plane_frame(right, D, lambda i, j: np.zeros(i.shape + (3,), np.uint8) + cb)
+    rig, frames = [left, right], [fa, fb]
+    r = o.synthesize(rig, frames, virt, k_nearest=2, taps=True, fill_mode=1)
+    st = o.stack(r["zf"], rig, frames, virt, r["sel"], r["weights"])
+    both = (st[..., 4] == 1) & (st[..., 9] == 1)
+    assert both[:, 4:W - 4].all()
+    cols = {0: ca, 1: cb}
+    for slot, cam in enumerate(r["sel"]):
+        got = st[..., 5 * slot:5 * slot + 3][both] * 255.0
+        assert np.abs(got - cols[int(cam)]).max() < 1e-9
+        assert np.all(st[..., 5 * slot + 3][both] == 0.25)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_stack_recombines_to_the_blend(oracle_lib, seed):
+    """Mixing the stack's valid camera colours with the selection weights
+    reproduces the blend (O6) pixel for pixel, and a pixel is a hole of the
+    blend exactly when no camera slot is valid."""
+    o = oracle_lib
+    w = sg.config_small(seed, n_cams=4)
+    for v in w.virtual[:2]:
+        r = o.synthesize(w.rig, w.frames, v, k_nearest=3, taps=True, fill_mode=1)
+        st = o.stack(r["zf"], w.rig, w.frames, v, r["sel"], r["weights"])
+        K = len(r["sel"])
+        valid = np.stack([st[..., 5 * k + 4] for k in range(K)], -1)
+        assert np.array_equal(valid.any(-1), r["hole"] == 0)
+        wk = np.asarray(r["weights"])[None, None, :] * valid
+        num = sum(wk[..., k, None] * st[..., 5 * k:5 * k + 3] * 255.0 for k in range(K))
+        den = wk.sum(-1)[..., None]
+        ok = r["hole"] == 0
+        mix = np.clip(np.floor(num[ok] / den[ok] + 0.5), 0, 255)
+        diff = np.abs(mix - r["blend_rgb"][ok].astype(np.float64))
+        assert diff.max() <= 1 and np.mean(diff > 0) < 1e-3
