@@ -25,6 +25,21 @@ import time
 import numpy as np
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak, GB/s
+BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bf16 matrix-core peak, TFLOP/s
+
+
+def net_flops(fvv, H: int, W: int) -> float:
+    """Multiply-add FLOPs (x2) of one network forward on an H x W stack:
+    3x3 convs and the head per output pixel, transposed convs per input
+    pixel, at each layer's resolution level."""
+    level = {"enc0a": 0, "enc0b": 0, "enc1a": 1, "enc1b": 1, "enc2a": 2, "enc2b": 2, "mid_a": 3,
+             "mid_b": 3, "up2": 3, "dec2a": 2, "dec2b": 2, "up1": 2, "dec1a": 1, "dec1b": 1,
+             "up0": 1, "dec0a": 0, "dec0b": 0, "head": 0}
+    total = 0.0
+    for name, kind, ci, co, k in fvv.net_layers():
+        px = (H >> level[name]) * (W >> level[name])
+        total += 2.0 * px * k * k * ci * co
+    return total
 
 
 def log(*a):
@@ -35,16 +50,13 @@ def log(*a):
 # one batch: n_out output pixels per view, n_src_sel source pixels of the
 # selected cameras per view, n_views views per batch.
 #   repack     per source pixel: RGB8 + u16 in, 8-byte texel + f32 depth out
-#   bin_count  per selected source pixel: f32 depth read once
 #   tile       per selected source pixel: f32 depth (splat) + 8-byte texel
 #              (backward fetch) read once; per output pixel: RGB8 + 4-byte
 #              slot written (the z-buffer lives in LDS)
-#   fill_open  touches only open holes: not counted
+#   desc, bin, fill_open: descriptors, per-block ranges, open holes only
 def stage_bytes(stage: str, n_views: int, n_out: int, n_src_sel: float, n_src_all: int) -> float:
     if stage == "repack":
-        return n_src_all * (3 + 2 + 8 + 4) / 9.0   # one launch per camera
-    if stage == "bin_count":
-        return n_views * n_src_sel * 4.0
+        return n_src_all * (3 + 2 + 8 + 4)
     if stage == "tile":
         return n_views * (n_src_sel * (4.0 + 8.0) + n_out * (3.0 + 4.0))
     return float("nan")
@@ -65,6 +77,9 @@ def run_serving(fvv, torch, sg, rig, raw, seconds: float, warmup_s: float, users
     ctx = fvv.Context(0)
     ctx.set_rig(rig)
     ctx.upload_mvd(raw, mem=fvv.MEM_DEVICE)
+    if path == fvv.PATH_LEARNED:
+        from paper_2007_00558_amd import learned as L
+        ctx.net_load(L.init_params(0))
     torch.cuda.synchronize()
     srv = fvv.Server(ctx, max_slots=64)
     n_buf = 8
@@ -145,6 +160,64 @@ def run_serving(fvv, torch, sg, rig, raw, seconds: float, warmup_s: float, users
             "steps": st["steps"], "failed": st["failed"], "wall_s": round(wall, 2)}
 
 
+def run_learned(fvv, torch, w, ctx, stream, args) -> dict:
+    """Learned path at 960x540 (the swing views at half size): stack in the
+    tile kernel, network forward, RGB.  Weights are a seeded initialisation
+    (throughput does not depend on their values)."""
+    from paper_2007_00558_amd import learned as L
+    dev = torch.device("cuda:0")
+    ctx.net_load(L.init_params(0))
+    virts = [v.with_size(960, 540, 0.5) for v in w.virtual[: args.learned_views]]
+    outs = [torch.empty((540, 960, 3), dtype=torch.uint8, device=dev) for _ in virts]
+    p = fvv.params(path=fvv.PATH_LEARNED)
+    for _ in range(2):
+        ctx.synthesize_batch(virts, outs, p=p, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = max(2, min(args.steps, 5))
+    e0.record(stream)
+    for _ in range(reps):
+        ctx.synthesize_batch(virts, outs, p=p, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ctx.set_profiling(True)
+    ctx.profile(reset=True)
+    ctx.synthesize_batch(virts, outs, p=p, stream=stream)
+    torch.cuda.synchronize()
+    prof = ctx.profile(reset=True)
+    ctx.set_profiling(False)
+    net_ms, net_n = prof["net"]
+    fl = net_flops(fvv, fvv.pad8(540), 960)
+    tflops = fl / (net_ms / net_n * 1e-3) / 1e12
+    # plain at the same size and views, for comparison
+    ctx.synthesize_batch(virts, outs, stream=stream)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        ctx.synthesize_batch(virts, outs, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_plain = e0.elapsed_time(e1) / reps
+    lat = []
+    for v, o in zip(virts, outs):
+        t = time.perf_counter()
+        ctx.synthesize(v, o, p=p, stream=stream)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t) * 1e3)
+    npx = len(virts) * 960 * 540
+    return {"config": "learned blend/inpaint, 9 cams 1280x720 -> 960x540 (stack 960x544x16 bf16), K=3",
+            "views": len(virts), "ms_per_batch": round(ms, 3), "mpix_s": round(npx / (ms * 1e-3) / 1e6, 1),
+            "plain_same_views_mpix_s": round(npx / (ms_plain * 1e-3) / 1e6, 1),
+            "net_ms_per_view": round(net_ms / net_n, 4), "net_gflop_per_view": round(fl / 1e9, 2),
+            "roofline": {"bound": "mfma", "kernel": "network forward (all layers)",
+                         "achieved": round(tflops, 1), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tflops / BF16_PEAK_TFLOPS, 4), "traffic": None},
+            "single_view_p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "single_view_p99_ms": round(float(np.percentile(lat, 99)), 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -156,6 +229,10 @@ def main():
                     help="views of the oracle CPU baseline sample (0 = skip)")
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="measured seconds of the serving load (0 = skip)")
+    ap.add_argument("--learned-views", type=int, default=16,
+                    help="views of the learned-path measurement at 960x540 (0 = skip)")
+    ap.add_argument("--serve-learned-seconds", type=float, default=3.0,
+                    help="measured seconds of the learned serving load (0 = skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain device copy of this many MiB first (hardware-counter scale)")
     args = ap.parse_args()
@@ -268,11 +345,22 @@ def main():
                          f"single-threaded, {dt:.1f} s on {platform.processor() or platform.machine()}"}
         log(f"[bench] cpu oracle {cpu['value']} Mpix/s")
 
+    learned = None
+    if args.learned_views > 0:
+        learned = run_learned(fvv, torch, w, ctx, stream, args)
+        log(f"[bench] learned {json.dumps(learned)}")
+
     serving = None
     if args.serve_seconds > 0:
         log("[bench] serving load: 64 users x 30 req/s, mixed 360p/720p/1080p")
         serving = run_serving(fvv, torch, sg, w.rig, raw, args.serve_seconds, 1.0)
         log(f"[bench] serving {json.dumps(serving)}")
+    serving_learned = None
+    if args.serve_learned_seconds > 0:
+        log("[bench] learned serving load: 64 users x 30 req/s, mixed 360p/720p/1080p")
+        serving_learned = run_serving(fvv, torch, sg, w.rig, raw, args.serve_learned_seconds, 1.0,
+                                      path=fvv.PATH_LEARNED)
+        log(f"[bench] learned serving {json.dumps(serving_learned)}")
 
     res = {
         "metric": "virtual-view Mpixel/s (9-cam 720p MVD -> 1080p) + p99 latency, plain vs learned",
@@ -297,6 +385,8 @@ def main():
                        "batched_per_view": round(ms / n_views, 4)},
         "stages": stages,
         "serving": serving,
+        "learned": learned,
+        "serving_learned": serving_learned,
         "path": "plain",
     }
     print(json.dumps(res), flush=True)

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define FVV_ABI_VERSION 1
+#define FVV_ABI_VERSION 2
 
 /* status codes */
 enum {
@@ -95,9 +95,12 @@ typedef struct {
     float max_footprint;    /* splat footprint cap in output pixels (default 4) */
     int32_t fill_mode;      /* FVV_FILL_BG (default) or FVV_FILL_NONE (holes
                                stay black, as in the paper's system, Section IX) */
-    int32_t path;           /* FVV_PATH_PLAIN; FVV_PATH_LEARNED is not built
-                               (returns FVV_E_UNSUPPORTED) */
-    int32_t reserved;       /* must be 0 */
+    int32_t path;           /* FVV_PATH_PLAIN, or FVV_PATH_LEARNED: the network
+                               loaded with fvv_net_load replaces the blend and
+                               hole fill (plain result where no network is
+                               loaded or its output is not finite) */
+    uint32_t exclude_mask;  /* rig cameras c with bit c set are not selected
+                               (leave-one-camera-out evaluation); 0 = none */
     uint64_t frame_version; /* 0 = latest uploaded frame set, else that version
                                if it is still resident (the two most recent) */
 } fvv_synth_params;
@@ -221,6 +224,59 @@ int32_t fvv_submit(fvv_ctx *ctx, const fvv_camera *virt, const fvv_synth_params 
                    int64_t out_pitch, uint64_t *ticket);
 int32_t fvv_poll(fvv_ctx *ctx, uint64_t ticket, double *latency_s);
 int32_t fvv_server_stats(fvv_ctx *ctx, uint64_t *out6);
+
+/* Learned blend/inpaint network (the learned path).  The paper mixes the
+ * warped reference cameras with fixed weights by camera distance and leaves
+ * disocclusions unfilled (Sections VI, IX); this path hands the same
+ * per-camera evidence to a small U-Net that predicts the output colour.
+ *  - Network: 3x3 convolutions + ReLU at widths 32/64/128/256 with 2x2
+ *    max-pooling, 2x2 transposed convolutions with skip concatenation
+ *    [up, skip], a 1x1 head + sigmoid; bfloat16 weights and activations,
+ *    float32 accumulation; float32 master weights and Adam (0.9, 0.999,
+ *    1e-8) for training.  fvv_net_layer_info(i, out4) gives layer i's kind
+ *    (0 conv3x3+ReLU, 1 convT2x2, 2 head), C_in, C_out, kernel size;
+ *    fvv_net_layer_name its name.
+ *  - Parameters: fvv_net_param_count() float32 values, layer by layer, each
+ *    layer's weights (C_out, kh, kw, C_in) then its bias (C_out); a transposed
+ *    convolution maps input (y, x) to output (2y+kh, 2x+kw).
+ *  - Stack (network input): bfloat16 [n][Hp][Wp][32], Hp and Wp the output
+ *    height and width rounded up to multiples of 8.  Per pixel and for each
+ *    of the first three selected cameras (selection order): the camera's
+ *    depth-consistent bilinear colour R, G, B / 255, 0.5 / (its depth in that
+ *    camera) capped at 1, and 1; zeros where the camera gives no sample, at
+ *    pixels without a filtered point and in the padding; channels 15..31 zero.
+ * fvv_net_load: host float32 parameters; resets the optimiser state.
+ * fvv_net_read: host copy of the parameters (FVV_NET_PARAMS) or of the last
+ *   training step's gradient (FVV_NET_GRADS).
+ * fvv_make_stack: the stacks of n_views views of one size (params: one entry
+ *   per view) into stack_dev (device, 16-byte aligned), asynchronously.
+ * fvv_net_forward: out_dev (device float32 [n][height][width][3]) = the
+ *   network's sigmoid output for n stacks of height x width (multiples of 8).
+ * fvv_net_train_step: forward, L1 loss mean |out - target| over the first
+ *   valid_rows rows of every image and 3 channels (target_dev device float32
+ *   [n][height][width][3] in [0, 1]), backward; apply != 0 then takes one Adam
+ *   step with learning rate lr.  *loss_out (host, may be NULL) receives the
+ *   loss, which synchronises the stream.  The weight gradient is reduced in
+ *   a fixed order (no float atomics): a step is bit-reproducible.
+ * fvv_net_read_act: host copy of one layer's output of the last forward,
+ *   bfloat16 NHWC (bytes must be pixels at that layer's resolution x C_out x 2).
+ * fvv_net_device_bytes: device memory held by the network and its
+ *   activation sets (part of the context's budget). */
+enum { FVV_NET_PARAMS = 0, FVV_NET_GRADS = 1 };
+uint64_t fvv_net_param_count(void);
+int32_t fvv_net_layer_info(int32_t layer, int32_t *out4);
+const char *fvv_net_layer_name(int32_t layer);
+int32_t fvv_net_load(fvv_ctx *ctx, const float *params, uint64_t n);
+int32_t fvv_net_read(fvv_ctx *ctx, int32_t what, float *out, uint64_t n);
+int32_t fvv_make_stack(fvv_ctx *ctx, const fvv_camera *virts, int32_t n_views, const fvv_synth_params *params,
+                       void *stack_dev, void *stream);
+int32_t fvv_net_forward(fvv_ctx *ctx, const void *stack_dev, int32_t n, int32_t height, int32_t width,
+                        float *out_dev, void *stream);
+int32_t fvv_net_train_step(fvv_ctx *ctx, const void *stack_dev, const float *target_dev, int32_t n,
+                           int32_t height, int32_t width, int32_t valid_rows, float lr, int32_t apply,
+                           float *loss_out, void *stream);
+int32_t fvv_net_read_act(fvv_ctx *ctx, int32_t layer, void *host_out, int64_t bytes);
+uint64_t fvv_net_device_bytes(fvv_ctx *ctx);
 
 #ifdef __cplusplus
 }

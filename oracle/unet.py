@@ -99,14 +99,16 @@ def _convT(x, w, b):
 
 
 def forward(params: Dict[str, Tuple[np.ndarray, np.ndarray]], stack: np.ndarray, widths=WIDTHS,
-            rounding: bool = True, keep: bool = False):
+            rounding: bool = True, keep: bool = False, acc=np.float64):
     """stack: (H, W, C_in) float values (bfloat16-representable).  Returns
-    (s (H, W, 3) float64 sigmoid output, dict of per-layer outputs as NHWC)."""
+    (s (H, W, 3) sigmoid output, dict of per-layer outputs as NHWC).  ``acc``
+    is the arithmetic type (float64 for the reference; float32 gives a second,
+    independently rounded evaluation used to size tolerances)."""
     R = Rounding(rounding)
     layers = layer_shapes(widths, stack.shape[2])
-    P = {n: (R(torch.from_numpy(np.asarray(w, np.float64))), torch.from_numpy(np.asarray(b, np.float64)))
+    P = {n: (R(torch.from_numpy(np.asarray(w, acc))), torch.from_numpy(np.asarray(b, acc)))
          for n, (w, b) in params.items()}
-    x = R(torch.from_numpy(np.asarray(stack, np.float64)).permute(2, 0, 1)[None])
+    x = R(torch.from_numpy(np.asarray(stack, acc)).permute(2, 0, 1)[None])
     acts = {"input": x}
     relu = lambda t: R(torch.clamp_min(t, 0.0))
     a = x
@@ -148,7 +150,8 @@ def to_rgb8(s: np.ndarray) -> np.ndarray:
 
 
 # ---------------------------------------------------------------- training
-def loss_and_grads(params, stack, target, valid_rows: int, widths=WIDTHS, rounding: bool = True):
+def loss_and_grads(params, stack, target, valid_rows: int, widths=WIDTHS, rounding: bool = True,
+                   acc=np.float64):
     """L1 loss over rows [0, valid_rows) and its gradients, written out with
     the kernels' bfloat16 points: every tensor fed to a matrix product
     (activations, weights, incoming gradients) is bfloat16, accumulations and
@@ -156,9 +159,9 @@ def loss_and_grads(params, stack, target, valid_rows: int, widths=WIDTHS, roundi
     target: (H, W, 3) in [0, 1].  Returns (loss, {name: (gW, gb)})."""
     R = Rounding(rounding)
     layers = {n: (k, ci, co) for n, k, ci, co in layer_shapes(widths, stack.shape[2])}
-    P = {n: (R(torch.from_numpy(np.asarray(w, np.float64))), torch.from_numpy(np.asarray(b, np.float64)))
+    P = {n: (R(torch.from_numpy(np.asarray(w, acc))), torch.from_numpy(np.asarray(b, acc)))
          for n, (w, b) in params.items()}
-    x = R(torch.from_numpy(np.asarray(stack, np.float64)).permute(2, 0, 1)[None])
+    x = R(torch.from_numpy(np.asarray(stack, acc)).permute(2, 0, 1)[None])
     relu = lambda t: R(torch.clamp_min(t, 0.0))
     # forward, keeping what the backward needs
     ins, outs = {}, {}
@@ -199,7 +202,7 @@ def loss_and_grads(params, stack, target, valid_rows: int, widths=WIDTHS, roundi
     z = _conv(a, *P["head"])
     s = torch.sigmoid(z)
     H = s.shape[2]
-    t = torch.from_numpy(np.asarray(target, np.float64)).permute(2, 0, 1)[None]
+    t = torch.from_numpy(np.asarray(target, acc)).permute(2, 0, 1)[None]
     diff = (s - t)[:, :, :valid_rows]
     n = diff.numel()
     loss = float(diff.abs().sum() / n)

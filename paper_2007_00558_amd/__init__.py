@@ -49,7 +49,7 @@ class View(C.Structure):
 
 class SynthParams(C.Structure):
     _fields_ = [("k_nearest", C.c_int32), ("tau_rel", C.c_float), ("max_footprint", C.c_float),
-                ("fill_mode", C.c_int32), ("path", C.c_int32), ("reserved", C.c_int32),
+                ("fill_mode", C.c_int32), ("path", C.c_int32), ("exclude_mask", C.c_uint32),
                 ("frame_version", C.c_uint64)]
 
 
@@ -88,6 +88,16 @@ def lib():
             "fvv_submit": (I32, [P, C.POINTER(Camera), C.POINTER(SynthParams), P, I64, C.POINTER(U64)]),
             "fvv_poll": (I32, [P, U64, C.POINTER(C.c_double)]),
             "fvv_server_stats": (I32, [P, P]),
+            "fvv_net_param_count": (U64, []),
+            "fvv_net_layer_info": (I32, [I32, P]),
+            "fvv_net_layer_name": (C.c_char_p, [I32]),
+            "fvv_net_load": (I32, [P, P, U64]),
+            "fvv_net_read": (I32, [P, I32, P, U64]),
+            "fvv_make_stack": (I32, [P, C.POINTER(Camera), I32, C.POINTER(SynthParams), P, P]),
+            "fvv_net_forward": (I32, [P, P, I32, I32, I32, P, P]),
+            "fvv_net_train_step": (I32, [P, P, P, I32, I32, I32, I32, C.c_float, I32, P, P]),
+            "fvv_net_read_act": (I32, [P, I32, P, I64]),
+            "fvv_net_device_bytes": (U64, [P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -101,7 +111,13 @@ EXPORTED = ("fvv_abi_version", "fvv_create", "fvv_destroy", "fvv_last_error", "f
             "fvv_upload_mvd", "fvv_synthesize", "fvv_synthesize_batch", "fvv_select_cameras",
             "fvv_pair_matrices", "fvv_set_debug", "fvv_debug_read", "fvv_set_profiling",
             "fvv_stage_count", "fvv_stage_name", "fvv_profile_read", "fvv_server_start",
-            "fvv_server_stop", "fvv_server_pause", "fvv_submit", "fvv_poll", "fvv_server_stats")
+            "fvv_server_stop", "fvv_server_pause", "fvv_submit", "fvv_poll", "fvv_server_stats",
+            "fvv_net_param_count", "fvv_net_layer_info", "fvv_net_layer_name", "fvv_net_load",
+            "fvv_net_read", "fvv_make_stack", "fvv_net_forward", "fvv_net_train_step",
+            "fvv_net_read_act", "fvv_net_device_bytes")
+NET_PARAMS, NET_GRADS = 0, 1
+NET_ALIGN = 8           # network inputs: multiples of 8 in both dimensions
+NET_IN = 32             # stack channels on the device (16 defined, zero padded)
 
 
 def camera(cam) -> Camera:
@@ -113,8 +129,35 @@ def camera(cam) -> Camera:
 
 
 def params(k_nearest=3, tau_rel=0.05, max_footprint=4.0, fill_mode=FILL_BG, path=PATH_PLAIN,
-           frame_version=0) -> SynthParams:
-    return SynthParams(k_nearest, tau_rel, max_footprint, fill_mode, path, 0, frame_version)
+           frame_version=0, exclude=()) -> SynthParams:
+    """Synthesis parameters; ``exclude`` lists rig cameras that may not be selected."""
+    mask = 0
+    for c in exclude:
+        mask |= 1 << int(c)
+    return SynthParams(k_nearest, tau_rel, max_footprint, fill_mode, path, mask, frame_version)
+
+
+def net_layers():
+    """[(name, kind, C_in, C_out, kernel)] of the learned-path network."""
+    L = lib()
+    out = []
+    i = 0
+    while True:
+        name = L.fvv_net_layer_name(i)
+        if name is None:
+            return out
+        a = np.zeros(4, np.int32)
+        L.fvv_net_layer_info(i, a.ctypes.data)
+        out.append((name.decode(), int(a[0]), int(a[1]), int(a[2]), int(a[3])))
+        i += 1
+
+
+def net_param_count() -> int:
+    return int(lib().fvv_net_param_count())
+
+
+def pad8(n: int) -> int:
+    return (n + NET_ALIGN - 1) // NET_ALIGN * NET_ALIGN
 
 
 def _addr(a) -> int:
@@ -270,6 +313,47 @@ class Context:
         cnt = np.zeros(n, np.int64)
         self._check(self._L.fvv_profile_read(self._h, ms.ctypes.data, cnt.ctypes.data, n, 1 if reset else 0))
         return {self._L.fvv_stage_name(k).decode(): (float(ms[k]), int(cnt[k])) for k in range(n)}
+
+    # ---- learned path
+    def net_load(self, flat: np.ndarray):
+        flat = np.ascontiguousarray(flat, np.float32)
+        self._check(self._L.fvv_net_load(self._h, flat.ctypes.data, flat.size))
+
+    def net_read(self, what: int = NET_PARAMS) -> np.ndarray:
+        a = np.empty(net_param_count(), np.float32)
+        self._check(self._L.fvv_net_read(self._h, what, a.ctypes.data, a.size))
+        return a
+
+    def make_stack(self, virts: Sequence, ps: Sequence[SynthParams], stack, stream=None):
+        """Stacks of views of one size into ``stack`` (torch bf16/int16 CUDA
+        tensor of n * pad8(H) * pad8(W) * 32 elements)."""
+        n = len(virts)
+        arr = (Camera * n)(*[camera(v) for v in virts])
+        parr = (SynthParams * n)(*ps)
+        self._check(self._L.fvv_make_stack(self._h, arr, n, parr, stack.data_ptr(), _stream_handle(stream)))
+        return stack
+
+    def net_forward(self, stack, n: int, height: int, width: int, out, stream=None):
+        self._check(self._L.fvv_net_forward(self._h, stack.data_ptr(), n, height, width, out.data_ptr(),
+                                            _stream_handle(stream)))
+        return out
+
+    def net_train_step(self, stack, target, n: int, height: int, width: int, valid_rows: int,
+                       lr: float = 1e-3, apply: bool = True, want_loss: bool = True, stream=None):
+        loss = C.c_float(0.0)
+        self._check(self._L.fvv_net_train_step(self._h, stack.data_ptr(), target.data_ptr(), n, height, width,
+                                               valid_rows, lr, 1 if apply else 0,
+                                               C.byref(loss) if want_loss else None, _stream_handle(stream)))
+        return loss.value if want_loss else None
+
+    def net_read_act(self, layer: int, shape) -> np.ndarray:
+        """Layer output of the last forward as float32 (bf16 values), ``shape`` = (P, C)."""
+        raw = np.empty(shape, np.uint16)
+        self._check(self._L.fvv_net_read_act(self._h, layer, raw.ctypes.data, raw.nbytes))
+        return (raw.astype(np.uint32) << 16).view(np.float32)
+
+    def net_device_bytes(self) -> int:
+        return int(self._L.fvv_net_device_bytes(self._h))
 
     def debug_read(self, tap: int, shape):
         dtype = {TAP_Z_RAW: np.uint64, TAP_Z_FILT: np.uint64, TAP_BLEND: np.uint32,

@@ -16,7 +16,7 @@
 #define FVV_ZCLIP 0.01f             // points and samples nearer than this are dropped
 #define FVV_TILE 32                 // output tile edge (pixels) of the fused kernel
 #define FVV_SBLK 8                  // source block edge (pixels) of the binning: one wave per block
-#define FVV_LIST_PER_BLOCK 8        // bin-list capacity per source block (average tiles per block)
+#define FVV_TILE_CAP_MIN 128        // minimum bin-list entries per output tile
 #define FVV_MAX_RIG 32              // cameras in a rig
 
 // One selected source camera of one view.  The float32 pair matrices are
@@ -41,21 +41,24 @@ struct fvv_view_desc {
     float tau, max_fp;
     int32_t ntx, nty;       // output tiles per row / column
     int32_t blk_stride;     // bbox entries reserved per camera slot (>= max nblk)
-    int32_t list_cap;       // bin-list capacity
+    int32_t tile_cap;       // bin-list entries per tile
+    int32_t view;           // index of this view in the batch
+    int32_t pad0;
     // binning
-    int32_t *counts;        // ntx*nty tile counters (zero between calls)
-    int32_t *offs;          // ntx*nty list start per tile
-    int32_t *cursor;        // ntx*nty list end per tile after the fill
-    int32_t *list;          // list_cap entries: camera slot << 24 | source block
+    int32_t *counts;        // ntx*nty tile counters (zero between calls; cleared by the tile kernel)
+    int32_t *list;          // ntx*nty*tile_cap entries: camera slot << 24 | source block
     int4 *bbox;             // K*blk_stride tile ranges (x0, x1, y0, y1; x0 > x1 = empty)
-    int32_t *overflow;      // 1 if the bin list overflowed (tiles then scan every block)
     // per-tile results
     uint32_t *slot;         // W*H depth bits of covered pixels / FVV_HOLE / FVV_HOLE_OPEN
-    int32_t *open;          // ntx*nty count of open holes per tile
     int2 *rowsum;           // ntx*nty*FVV_TILE (first, last) covered x of each tile row
     int2 *colsum;           // ntx*nty*FVV_TILE (first, last) covered y of each tile column
+    int2 *open_list;        // batch-wide list of (view, tile) with open holes
+    int32_t *open_count;    // its length (cleared by the binning kernel)
     uint8_t *out;           // final RGB8, out_pitch bytes per row
     int64_t out_pitch;
+    // learned path: network input [stack_h][stack_w][32] bf16 (null = plain view)
+    uint16_t *stack;
+    int32_t stack_w, stack_h;   // W, H rounded up to multiples of 8
     // debug taps (null unless enabled)
     unsigned long long *dbg_z;
     unsigned long long *dbg_zf;
@@ -69,11 +72,12 @@ struct fvv_view_desc {
 // stage when the profile is read.
 enum fvv_stage {
     FVV_ST_REPACK = 0,
-    FVV_ST_BIN_COUNT,
-    FVV_ST_BIN_SCAN,
-    FVV_ST_BIN_FILL,
+    FVV_ST_DESC,
+    FVV_ST_BIN,
     FVV_ST_TILE,
     FVV_ST_FILL_OPEN,
+    FVV_ST_NET,         // learned path: network forward of one view
+    FVV_ST_TRAIN,       // learned path: one training step
     FVV_NSTAGES
 };
 
@@ -116,7 +120,9 @@ struct fvv_batch_dims {
     int max_blocks;       // largest source-block count of a selected camera
     int max_tiles_x;      // largest ntx
     int max_tiles_y;      // largest nty
+    int total_tiles;      // tiles of all views
     bool fill_bg;         // any view fills holes
+    bool any_stack;       // any view writes a learned-path stack
 };
 
 // Ingest of one frame set: every present camera's caller buffers (device
@@ -139,5 +145,7 @@ struct fvv_repack_batch {
 
 // Host-side launchers (fvv_kernels.hip).  All return hipError_t of the launch.
 hipError_t fvv_launch_repack(const fvv_repack_batch &b, int max_w, int max_h, hipStream_t s, fvv_prof *prof);
-hipError_t fvv_launch_synthesis(const fvv_view_desc *d_views, const fvv_batch_dims &dims,
-                                hipStream_t s, fvv_prof *prof);
+// h_views: device-visible pointer to the coherent pinned host copy of the
+// descriptors, copied into d_views by the first kernel of the sequence.
+hipError_t fvv_launch_synthesis(const fvv_view_desc *h_views, fvv_view_desc *d_views,
+                                const fvv_batch_dims &dims, hipStream_t s, fvv_prof *prof);

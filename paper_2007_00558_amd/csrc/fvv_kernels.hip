@@ -1,19 +1,21 @@
 // fvv_kernels.hip -- gfx950 kernels of the DIBR view-synthesis path.
 //
 // Stages (FVV Live, arXiv 2007.00558, Section VI):
-//   repack     MVD ingest: RGB8 -> 8-byte texels {RGBA8, depth}, millimetres ->
-//              metres with the Eq. (1) correction (Section IV-A); per frame set
-//   bin_count  every 16x16 block of each selected source camera is projected
-//              (3D warping of its valid pixels) and the output tiles its
-//              footprints touch are counted
-//   bin_scan   per-tile list offsets
-//   bin_fill   per-tile lists of source blocks
+//   repack     MVD ingest, once per frame set: RGB8 -> 8-byte texels {RGBA8,
+//              depth}, millimetres -> metres with the Eq. (1) correction
+//              (Section IV-A), and the depth range of every 8x8 block
+//   desc       copy of the view descriptors from coherent pinned host memory
+//   bin        every 8x8 block of each selected source camera is bounded in
+//              the virtual image from the 8 corners of its pixel-and-depth
+//              frustum section and appended to the lists of the output tiles
+//              it may touch
 //   tile       one workgroup per 32x32 output tile: splats its binned blocks
-//              into an LDS z-buffer of packed (depth, camera, pixel) keys with
-//              64-bit LDS atomicMin, 3x3 crack/speckle filter in LDS, backward
-//              depth-consistent bilinear fetch from each selected camera mixed
-//              by camera distance, hole fill for holes whose neighbours lie
-//              inside the tile, writes the RGB8 output
+//              (3D warping of each valid pixel) into an LDS z-buffer of packed
+//              (depth, camera, pixel) keys with 64-bit LDS atomicMin, 3x3
+//              crack/speckle filter in LDS, backward depth-consistent
+//              bilinear fetch from each selected camera mixed by camera
+//              distance, hole fill for holes whose neighbours lie inside the
+//              tile, writes the RGB8 output
 //   fill_open  the remaining holes: nearest covered pixel left/right/up/down
 //              through per-tile row and column summaries, larger depth wins
 //
@@ -36,6 +38,12 @@ constexpr int WN = FVV_TILE + 2;   // tile window edge with a 1-pixel halo
 
 __device__ __forceinline__ uint32_t f2u(float f) { return __float_as_uint(f); }
 __device__ __forceinline__ float u2f(uint32_t u) { return __uint_as_float(u); }
+// float -> bfloat16 bits, round to nearest even (inputs here are finite)
+__device__ __forceinline__ uint32_t bf16_rne(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
 
 // p_r = ((M_r0 i + M_r1 j) + M_r2) z + m_r, each op rounded to float32
 __device__ __forceinline__ void project(const float *M, const float *m, float i, float j, float z,
@@ -83,8 +91,21 @@ __device__ __forceinline__ bool splat_point(const fvv_src_desc &s, int W, int H,
     return true;
 }
 
+__device__ __forceinline__ float wave_minf(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ float wave_maxf(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
 // ---------------------------------------------------------------- repack
-// One launch per frame set: grid.z = camera.
+// One thread per source pixel (grid.z = camera): 8-byte texel {RGBA8,
+// decoded depth bits} for the backward gathers and the decoded depth plane
+// for the splat.
 __global__ void __launch_bounds__(256) k_repack(const fvv_repack_batch b)
 {
     const fvv_repack_cam &c = b.cam[blockIdx.z];
@@ -104,6 +125,13 @@ __global__ void __launch_bounds__(256) k_repack(const fvv_repack_batch b)
     c.depth_out[(int64_t)y * c.W + x] = u2f(zb);
 }
 
+// ---------------------------------------------------------------- descriptors
+__global__ void __launch_bounds__(256) k_desc(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int n)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) dst[e] = src[e];
+}
+
 // ---------------------------------------------------------------- binning
 __device__ __forceinline__ int wave_min(int v)
 {
@@ -116,13 +144,18 @@ __device__ __forceinline__ int wave_max(int v)
     return v;
 }
 
-// One wave per (view, camera slot, 8x8 source block), four blocks per
-// workgroup: exact bounding box of the block's footprints, turned into the
-// range of output tiles whose window (tile plus 1-pixel halo) it touches;
-// each such tile is counted.
-__global__ void __launch_bounds__(256) k_bin_count(const fvv_view_desc *__restrict__ views)
+// One wave per (view, camera slot, 8x8 source block), one lane per pixel:
+// the exact output bounds of the block's footprints (each pixel projected as
+// the splat projects it), turned into the range of tiles whose window -- the
+// tile plus a 1-pixel halo -- they touch, and appended to those tiles' lists.
+// Entries past a tile's capacity are dropped and that tile then scans every
+// block's range instead.  (Bounds from the corners of the block's depth range
+// would save the per-pixel projections, but depth noise widens them along
+// the epipolar lines by several pixels and roughly doubles the tile work.)
+__global__ void __launch_bounds__(256) k_bin(const fvv_view_desc *__restrict__ views)
 {
     const fvv_view_desc &vd = views[blockIdx.z];
+    if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) *vd.open_count = 0;
     const int k = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int blk = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -131,7 +164,7 @@ __global__ void __launch_bounds__(256) k_bin_count(const fvv_view_desc *__restri
     if (blk >= s.nblk) return;
     const int by = blk / s.nbx, bx = blk - by * s.nbx;
     const int i = bx * FVV_SBLK + (lane & (FVV_SBLK - 1));
-    const int j = by * FVV_SBLK + (lane / FVV_SBLK);
+    const int j = by * FVV_SBLK + lane / FVV_SBLK;
     int x0 = INT_MAX, x1 = -1, y0 = INT_MAX, y1 = -1;
     if (i < s.W && j < s.H) {
         const uint32_t zb = f2u(s.depth[(int64_t)j * s.W + i]);
@@ -143,7 +176,6 @@ __global__ void __launch_bounds__(256) k_bin_count(const fvv_view_desc *__restri
             y1 = f.y1;
         }
     }
-    // every lane ends with the block's bounds
     x0 = wave_min(x0);
     y0 = wave_min(y0);
     x1 = wave_max(x1);
@@ -159,81 +191,44 @@ __global__ void __launch_bounds__(256) k_bin_count(const fvv_view_desc *__restri
     if (t.x > t.y) return;
     const int nx = t.y - t.x + 1, n = nx * (t.w - t.z + 1);
     for (int e = lane; e < n; e += 64) {
-        const int ty = t.z + e / nx, tx = t.x + e % nx;
-        atomicAdd(&vd.counts[ty * vd.ntx + tx], 1);
+        const int tile = (t.z + e / nx) * vd.ntx + t.x + e % nx;
+        const int pos = atomicAdd(&vd.counts[tile], 1);
+        if (pos < vd.tile_cap) vd.list[(int64_t)tile * vd.tile_cap + pos] = (k << 24) | blk;
     }
-}
-
-// One workgroup per view: exclusive scan of the tile counts into list
-// offsets (and fill cursors); counters are cleared for the next call.
-__global__ void __launch_bounds__(256) k_bin_scan(const fvv_view_desc *__restrict__ views)
-{
-    const fvv_view_desc &vd = views[blockIdx.x];
-    const int n = vd.ntx * vd.nty;
-    const int t = threadIdx.x;
-    const int C = (n + 255) / 256;
-    const int e0 = min(t * C, n), e1 = min(e0 + C, n);
-    int sum = 0;
-    for (int e = e0; e < e1; ++e) sum += vd.counts[e];
-    __shared__ int sc[256];
-    sc[t] = sum;
-    __syncthreads();
-    for (int d = 1; d < 256; d <<= 1) {
-        const int a = t >= d ? sc[t - d] : 0;
-        __syncthreads();
-        sc[t] += a;
-        __syncthreads();
-    }
-    int run = sc[t] - sum;
-    for (int e = e0; e < e1; ++e) {
-        const int c = vd.counts[e];
-        vd.offs[e] = run;
-        vd.cursor[e] = run;
-        vd.counts[e] = 0;
-        run += c;
-    }
-    if (t == 255) *vd.overflow = sc[255] > vd.list_cap ? 1 : 0;
-}
-
-// One thread per (view, camera slot, source block): append the block to the
-// list of every tile in its range.
-__global__ void __launch_bounds__(256) k_bin_fill(const fvv_view_desc *__restrict__ views)
-{
-    const fvv_view_desc &vd = views[blockIdx.z];
-    const int k = blockIdx.y;
-    const int blk = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= vd.K || blk >= vd.src[k].nblk) return;
-    if (*vd.overflow) return;
-    const int4 t = vd.bbox[(int64_t)k * vd.blk_stride + blk];
-    for (int ty = t.z; ty <= t.w; ++ty)
-        for (int tx = t.x; tx <= t.y; ++tx) {
-            const int pos = atomicAdd(&vd.cursor[ty * vd.ntx + tx], 1);
-            vd.list[pos] = (k << 24) | blk;
-        }
 }
 
 // ---------------------------------------------------------------- filter
-// Lower median (element (n-1)/2 in key order) of the valid keys among the 8
-// neighbours; empty keys (all ones) order last, so a rank selection over all
-// eight picks it directly.
-__device__ __forceinline__ unsigned long long lower_median8(const unsigned long long v[8], int n)
-{
-    const int m = (n - 1) >> 1;
-    unsigned long long res = FVV_KEY_EMPTY;
-#pragma unroll
-    for (int a = 0; a < 8; ++a) {
-        int r = 0;
-#pragma unroll
-        for (int b = 0; b < 8; ++b) r += (v[b] < v[a]) || (v[b] == v[a] && b < a);
-        if (r == m) res = v[a];
+#define CSWAP(a, b)                                     \
+    {                                                   \
+        const unsigned long long lo_ = min(v[a], v[b]); \
+        const unsigned long long hi_ = max(v[a], v[b]); \
+        v[a] = lo_;                                     \
+        v[b] = hi_;                                     \
     }
+
+// Lower median (element (n-1)/2 in key order) of the valid keys among the 8
+// neighbours.  Empty keys (all ones) order last, so sorting all eight with a
+// 19-comparator network and taking that element is exact.
+__device__ __forceinline__ unsigned long long lower_median8(unsigned long long v[8], int n)
+{
+    CSWAP(0, 2) CSWAP(1, 3) CSWAP(4, 6) CSWAP(5, 7)
+    CSWAP(0, 4) CSWAP(1, 5) CSWAP(2, 6) CSWAP(3, 7)
+    CSWAP(0, 1) CSWAP(2, 3) CSWAP(4, 5) CSWAP(6, 7)
+    CSWAP(2, 4) CSWAP(3, 5)
+    CSWAP(1, 4) CSWAP(3, 6)
+    CSWAP(1, 2) CSWAP(3, 4) CSWAP(5, 6)
+    const int m = (n - 1) >> 1;
+    unsigned long long res = v[0];
+#pragma unroll
+    for (int e = 1; e < 8; ++e)
+        if (m == e) res = v[e];
     return res;
 }
+#undef CSWAP
 
 // Crack fill (empty key, >= 5 valid neighbours) and speckle removal (valid
 // key, >= 5 valid neighbours, none within tau z0) take the lower median.
-__device__ __forceinline__ unsigned long long filter_key(unsigned long long c, const unsigned long long v[8],
-                                                         float tau)
+__device__ __forceinline__ unsigned long long filter_key(unsigned long long c, unsigned long long v[8], float tau)
 {
     int n = 0;
 #pragma unroll
@@ -301,6 +296,61 @@ __device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int x, int 
     return true;
 }
 
+// Learned-path input of output pixel (x, y): for each of the first three
+// selected cameras, the depth-consistent bilinear colour that blend_pixel
+// mixes (R, G, B / 255), the inverse source depth 0.5 / q_z capped at 1 and a
+// validity flag; zeros where a camera gives no sample, for pixels without a
+// filtered point and for the padding beyond the image.  16 bf16 channels and
+// 16 zero channels (64 bytes) per pixel.
+__device__ __forceinline__ void stack_pixel(const fvv_view_desc &vd, int x, int y, unsigned long long kf)
+{
+    uint32_t ch[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // channel c in ch[c / 2], low half for even c
+    auto put = [&](int c, float v) { ch[c >> 1] |= (uint32_t)bf16_rne(v) << (16 * (c & 1)); };
+    if (kf != FVV_KEY_EMPTY) {
+        const float zf = u2f((uint32_t)(kf >> 32));
+        const int K = min(vd.K, 3);
+        for (int k = 0; k < K; ++k) {
+            const fvv_src_desc &s = vd.src[k];
+            float q0, q1, q2;
+            project(s.B, s.b, (float)x, (float)y, zf, q0, q1, q2);
+            if (!(q2 > FVV_ZCLIP)) continue;
+            const float u = __fdiv_rn(q0, q2), v = __fdiv_rn(q1, q2);
+            if (!(u >= -0.5f && u <= __fsub_rn((float)s.W, 0.5f))) continue;
+            if (!(v >= -0.5f && v <= __fsub_rn((float)s.H, 0.5f))) continue;
+            const float fi0 = floorf(u), fj0 = floorf(v);
+            const float fu = __fsub_rn(u, fi0), fv = __fsub_rn(v, fj0);
+            const int i0 = (int)fi0, j0 = (int)fj0;
+            const float lim = __fmul_rn(vd.tau, q2);
+            const float gu = 1.0f - fu, gv = 1.0f - fv;
+            const float wt[4] = {gu * gv, fu * gv, gu * fv, fu * fv};
+            float c0 = 0.f, c1 = 0.f, c2 = 0.f, csum = 0.f;
+            for (int n = 0; n < 4; ++n) {
+                const int ti = i0 + (n & 1), tj = j0 + (n >> 1);
+                if (ti < 0 || tj < 0 || ti >= s.W || tj >= s.H) continue;
+                const uint2 tx = s.texel[(int64_t)tj * s.W + ti];
+                if (tx.y == FVV_NO_DEPTH) continue;
+                if (!(fabsf(__fsub_rn(u2f(tx.y), q2)) <= lim)) continue;
+                c0 += wt[n] * (float)(tx.x & 0xFF);
+                c1 += wt[n] * (float)((tx.x >> 8) & 0xFF);
+                c2 += wt[n] * (float)((tx.x >> 16) & 0xFF);
+                csum += wt[n];
+            }
+            if (!(csum > 0.f)) continue;
+            put(5 * k + 0, __fdiv_rn(__fdiv_rn(c0, csum), 255.0f));
+            put(5 * k + 1, __fdiv_rn(__fdiv_rn(c1, csum), 255.0f));
+            put(5 * k + 2, __fdiv_rn(__fdiv_rn(c2, csum), 255.0f));
+            const float inv = __fdiv_rn(0.5f, q2);
+            put(5 * k + 3, inv < 1.0f ? inv : 1.0f);
+            put(5 * k + 4, 1.0f);
+        }
+    }
+    uint4 *o = (uint4 *)(vd.stack + ((int64_t)y * vd.stack_w + x) * 32);
+    o[0] = make_uint4(ch[0], ch[1], ch[2], ch[3]);
+    o[1] = make_uint4(ch[4], ch[5], ch[6], ch[7]);
+    o[2] = make_uint4(0, 0, 0, 0);
+    o[3] = make_uint4(0, 0, 0, 0);
+}
+
 __device__ __forceinline__ void put_rgb(uint8_t *out, int64_t pitch, int x, int y, uint32_t c)
 {
     uint8_t *p = out + (int64_t)y * pitch + (int64_t)x * 3;
@@ -333,6 +383,9 @@ __device__ __forceinline__ void offer(Cand &b, float z, int dist, int idx)
 }
 
 // ---------------------------------------------------------------- fused tile
+// STACK: views may carry a learned-path stack (a separate instantiation, so
+// the plain kernel keeps its register budget and occupancy).
+template <bool STACK>
 __global__ void __launch_bounds__(256) k_tile(const fvv_view_desc *__restrict__ views)
 {
     const fvv_view_desc &vd = views[blockIdx.z];
@@ -348,21 +401,22 @@ __global__ void __launch_bounds__(256) k_tile(const fvv_view_desc *__restrict__ 
     __shared__ uint32_t s_rgb[T * T];
     __shared__ int s_open;
     const int t = threadIdx.x;
+    const int n_entries = vd.counts[tile];
     for (int e = t; e < WN * WN; e += 256) zk[e] = FVV_KEY_EMPTY;
     if (t == 0) s_open = 0;
     __syncthreads();
 
-    // ---- S1: splat every binned source block into the window
-    const bool scan_all = *vd.overflow != 0;
-    const int beg = scan_all ? 0 : vd.offs[tile];
-    const int end = scan_all ? vd.K * vd.blk_stride : vd.cursor[tile];
-    // each wave splats its own list entries (one 8x8 source block per entry)
+    // ---- S1: splat every binned source block into the window; each wave
+    // takes its own list entries (one 8x8 source block = one wave)
+    const bool scan_all = n_entries > vd.tile_cap;
+    const int end = scan_all ? vd.K * vd.blk_stride : n_entries;
     const int lane = t & 63, wave = t >> 6;
     const int si = lane & (FVV_SBLK - 1), sj = lane / FVV_SBLK;
-    for (int e = beg + wave; e < end; e += 4) {
+    const int32_t *lst = vd.list + (int64_t)tile * vd.tile_cap;
+    for (int e = wave; e < end; e += 4) {
         int k, blk;
         if (!scan_all) {
-            const int ent = vd.list[e];
+            const int ent = lst[e];
             k = ent >> 24;
             blk = ent & 0xFFFFFF;
         } else {
@@ -401,24 +455,27 @@ __global__ void __launch_bounds__(256) k_tile(const fvv_view_desc *__restrict__ 
         const int x = X0 + lx0 + q;
         pslot[q] = FVV_HOLE;
         prgb[q] = 0;
-        if (x >= W || y >= H) continue;
-        const unsigned long long c = w3[1][q + 1];
-        const unsigned long long nb[8] = {w3[0][q], w3[0][q + 1], w3[0][q + 2], w3[1][q],
-                                          w3[1][q + 2], w3[2][q], w3[2][q + 1], w3[2][q + 2]};
-        const unsigned long long kf = filter_key(c, nb, vd.tau);
-        if (kf != FVV_KEY_EMPTY) {
-            const float zf = u2f((uint32_t)(kf >> 32));
-            uint32_t col;
-            if (blend_pixel(vd, x, y, zf, col)) {
-                pslot[q] = f2u(zf);
-                prgb[q] = col;
+        unsigned long long kf = FVV_KEY_EMPTY;
+        if (x < W && y < H) {
+            const unsigned long long c = w3[1][q + 1];
+            unsigned long long nb[8] = {w3[0][q], w3[0][q + 1], w3[0][q + 2], w3[1][q],
+                                        w3[1][q + 2], w3[2][q], w3[2][q + 1], w3[2][q + 2]};
+            kf = filter_key(c, nb, vd.tau);
+            if (kf != FVV_KEY_EMPTY) {
+                const float zf = u2f((uint32_t)(kf >> 32));
+                uint32_t col;
+                if (blend_pixel(vd, x, y, zf, col)) {
+                    pslot[q] = f2u(zf);
+                    prgb[q] = col;
+                }
             }
+            const int64_t o = (int64_t)y * W + x;
+            if (vd.dbg_z) vd.dbg_z[o] = c;
+            if (vd.dbg_zf) vd.dbg_zf[o] = kf;
+            if (vd.dbg_rgba) vd.dbg_rgba[o] = prgb[q];
+            if (vd.dbg_depth) vd.dbg_depth[o] = (pslot[q] & FVV_HOLE) ? 0.0f : u2f(pslot[q]);
         }
-        const int64_t o = (int64_t)y * W + x;
-        if (vd.dbg_z) vd.dbg_z[o] = c;
-        if (vd.dbg_zf) vd.dbg_zf[o] = kf;
-        if (vd.dbg_rgba) vd.dbg_rgba[o] = prgb[q];
-        if (vd.dbg_depth) vd.dbg_depth[o] = (pslot[q] & FVV_HOLE) ? 0.0f : u2f(pslot[q]);
+        if (STACK && vd.stack && x < vd.stack_w && y < vd.stack_h) stack_pixel(vd, x, y, kf);
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -439,6 +496,7 @@ __global__ void __launch_bounds__(256) k_tile(const fvv_view_desc *__restrict__ 
         uint32_t sl = pslot[q], col = prgb[q];
         if (sl & FVV_HOLE) {
             col = 0;
+            sl = FVV_HOLE;
             if (fill) {
                 Cand b{0.f, 0, -1};
                 bool open = false;
@@ -467,12 +525,9 @@ __global__ void __launch_bounds__(256) k_tile(const fvv_view_desc *__restrict__ 
                 if (open) {
                     sl = FVV_HOLE_OPEN;
                     atomicAdd(&s_open, 1);
-                } else {
-                    sl = FVV_HOLE;
-                    if (b.idx >= 0) col = s_rgb[b.idx];
+                } else if (b.idx >= 0) {
+                    col = s_rgb[b.idx];
                 }
-            } else {
-                sl = FVV_HOLE;
             }
         }
         vd.slot[(int64_t)y * W + x] = sl;
@@ -501,93 +556,99 @@ __global__ void __launch_bounds__(256) k_tile(const fvv_view_desc *__restrict__ 
         vd.colsum[(int64_t)tile * T + c] = make_int2(first, last);
     }
     __syncthreads();
-    if (t == 0) vd.open[tile] = s_open;
+    if (t == 0) {
+        vd.counts[tile] = 0;   // ready for the next call
+        if (s_open > 0) vd.open_list[atomicAdd(vd.open_count, 1)] = make_int2(vd.view, tile);
+    }
 }
 
 // ---------------------------------------------------------------- open holes
 // Holes whose nearest covered neighbour in some direction lies outside their
 // tile: scan the tile, then walk the per-tile summaries of the row or column.
+// A fixed grid walks the batch's list of tiles with open holes.
 __global__ void __launch_bounds__(256) k_fill_open(const fvv_view_desc *__restrict__ views)
 {
-    const fvv_view_desc &vd = views[blockIdx.z];
-    const int tx = blockIdx.x, ty = blockIdx.y;
-    if (tx >= vd.ntx || ty >= vd.nty) return;
-    const int tile = ty * vd.ntx + tx;
-    if (vd.open[tile] == 0) return;
-    const int W = vd.W, H = vd.H;
-    const int X0 = tx * T, Y0 = ty * T;
-    const int tw = min(T, W - X0), th = min(T, H - Y0);
-    const uint32_t *slot = vd.slot;
-    for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
-        const int ly = e / T, lx = e - ly * T;
-        if (lx >= tw || ly >= th) continue;
-        const int x = X0 + lx, y = Y0 + ly;
-        if (slot[(int64_t)y * W + x] != FVV_HOLE_OPEN) continue;
-        const int64_t row = (int64_t)y * W;
-        // left
-        int xl = x - 1;
-        while (xl >= X0 && (slot[row + xl] & FVV_HOLE)) --xl;
-        if (xl < X0) {
-            xl = -1;
-            for (int t2 = tx - 1; t2 >= 0; --t2) {
-                const int l = vd.rowsum[(int64_t)(ty * vd.ntx + t2) * T + ly].y;
-                if (l >= 0) {
-                    xl = l;
-                    break;
+    const int n_open = *views[0].open_count;
+    for (int item = blockIdx.x; item < n_open; item += gridDim.x) {
+        const int2 vt = views[0].open_list[item];
+        const fvv_view_desc &vd = views[vt.x];
+        const int tile = vt.y;
+        const int ty = tile / vd.ntx, tx = tile - ty * vd.ntx;
+        const int W = vd.W, H = vd.H;
+        const int X0 = tx * T, Y0 = ty * T;
+        const int tw = min(T, W - X0), th = min(T, H - Y0);
+        const uint32_t *slot = vd.slot;
+        for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
+            const int ly = e / T, lx = e - ly * T;
+            if (lx >= tw || ly >= th) continue;
+            const int x = X0 + lx, y = Y0 + ly;
+            if (slot[(int64_t)y * W + x] != FVV_HOLE_OPEN) continue;
+            const int64_t row = (int64_t)y * W;
+            // left
+            int xl = x - 1;
+            while (xl >= X0 && (slot[row + xl] & FVV_HOLE)) --xl;
+            if (xl < X0) {
+                xl = -1;
+                for (int t2 = tx - 1; t2 >= 0; --t2) {
+                    const int l = vd.rowsum[(int64_t)(ty * vd.ntx + t2) * T + ly].y;
+                    if (l >= 0) {
+                        xl = l;
+                        break;
+                    }
                 }
             }
-        }
-        // right
-        int xr = x + 1;
-        while (xr < X0 + tw && (slot[row + xr] & FVV_HOLE)) ++xr;
-        if (xr >= X0 + tw) {
-            xr = -1;
-            for (int t2 = tx + 1; t2 < vd.ntx; ++t2) {
-                const int f = vd.rowsum[(int64_t)(ty * vd.ntx + t2) * T + ly].x;
-                if (f >= 0) {
-                    xr = f;
-                    break;
+            // right
+            int xr = x + 1;
+            while (xr < X0 + tw && (slot[row + xr] & FVV_HOLE)) ++xr;
+            if (xr >= X0 + tw) {
+                xr = -1;
+                for (int t2 = tx + 1; t2 < vd.ntx; ++t2) {
+                    const int f = vd.rowsum[(int64_t)(ty * vd.ntx + t2) * T + ly].x;
+                    if (f >= 0) {
+                        xr = f;
+                        break;
+                    }
                 }
             }
-        }
-        // candidates carry image indices y*W + x
-        Cand c{0.f, 0, -1};
-        if (xl >= 0) offer(c, u2f(slot[row + xl]), x - xl, y * W + xl);
-        if (xr >= 0) offer(c, u2f(slot[row + xr]), xr - x, y * W + xr);
-        // up
-        int yu = y - 1;
-        while (yu >= Y0 && (slot[(int64_t)yu * W + x] & FVV_HOLE)) --yu;
-        if (yu < Y0) {
-            yu = -1;
-            for (int t2 = ty - 1; t2 >= 0; --t2) {
-                const int l = vd.colsum[(int64_t)(t2 * vd.ntx + tx) * T + lx].y;
-                if (l >= 0) {
-                    yu = l;
-                    break;
+            // candidates carry image indices y*W + x
+            Cand c{0.f, 0, -1};
+            if (xl >= 0) offer(c, u2f(slot[row + xl]), x - xl, y * W + xl);
+            if (xr >= 0) offer(c, u2f(slot[row + xr]), xr - x, y * W + xr);
+            // up
+            int yu = y - 1;
+            while (yu >= Y0 && (slot[(int64_t)yu * W + x] & FVV_HOLE)) --yu;
+            if (yu < Y0) {
+                yu = -1;
+                for (int t2 = ty - 1; t2 >= 0; --t2) {
+                    const int l = vd.colsum[(int64_t)(t2 * vd.ntx + tx) * T + lx].y;
+                    if (l >= 0) {
+                        yu = l;
+                        break;
+                    }
                 }
             }
-        }
-        if (yu >= 0) offer(c, u2f(slot[(int64_t)yu * W + x]), y - yu, yu * W + x);
-        // down
-        int yd = y + 1;
-        while (yd < Y0 + th && (slot[(int64_t)yd * W + x] & FVV_HOLE)) ++yd;
-        if (yd >= Y0 + th) {
-            yd = -1;
-            for (int t2 = ty + 1; t2 < vd.nty; ++t2) {
-                const int f = vd.colsum[(int64_t)(t2 * vd.ntx + tx) * T + lx].x;
-                if (f >= 0) {
-                    yd = f;
-                    break;
+            if (yu >= 0) offer(c, u2f(slot[(int64_t)yu * W + x]), y - yu, yu * W + x);
+            // down
+            int yd = y + 1;
+            while (yd < Y0 + th && (slot[(int64_t)yd * W + x] & FVV_HOLE)) ++yd;
+            if (yd >= Y0 + th) {
+                yd = -1;
+                for (int t2 = ty + 1; t2 < vd.nty; ++t2) {
+                    const int f = vd.colsum[(int64_t)(t2 * vd.ntx + tx) * T + lx].x;
+                    if (f >= 0) {
+                        yd = f;
+                        break;
+                    }
                 }
             }
+            if (yd >= 0) offer(c, u2f(slot[(int64_t)yd * W + x]), yd - y, yd * W + x);
+            uint32_t col = 0;
+            if (c.idx >= 0) {
+                const int cy = c.idx / W, cx = c.idx - cy * W;
+                col = get_rgb(vd.out, vd.out_pitch, cx, cy);
+            }
+            put_rgb(vd.out, vd.out_pitch, x, y, col);
         }
-        if (yd >= 0) offer(c, u2f(slot[(int64_t)yd * W + x]), yd - y, yd * W + x);
-        uint32_t col = 0;
-        if (c.idx >= 0) {
-            const int cy = c.idx / W, cx = c.idx - cy * W;
-            col = get_rgb(vd.out, vd.out_pitch, cx, cy);
-        }
-        put_rgb(vd.out, vd.out_pitch, x, y, col);
     }
 }
 
@@ -604,28 +665,30 @@ hipError_t fvv_launch_repack(const fvv_repack_batch &b, int max_w, int max_h, hi
     return hipGetLastError();
 }
 
-hipError_t fvv_launch_synthesis(const fvv_view_desc *d_views, const fvv_batch_dims &b, hipStream_t s,
-                                fvv_prof *prof)
+hipError_t fvv_launch_synthesis(const fvv_view_desc *h_views, fvv_view_desc *d_views, const fvv_batch_dims &b,
+                                hipStream_t s, fvv_prof *prof)
 {
     if (b.n_views <= 0) return hipSuccess;
+    static_assert(sizeof(fvv_view_desc) % 16 == 0, "descriptors are copied in 16-byte words");
+    const int words = (int)(b.n_views * sizeof(fvv_view_desc) / 16);
     hipEvent_t e0;
     fvv_prof_begin(prof, s, e0);
-    hipLaunchKernelGGL(k_bin_count, dim3((b.max_blocks + 3) / 4, b.max_k, b.n_views), dim3(256), 0, s, d_views);
-    fvv_prof_end(prof, s, FVV_ST_BIN_COUNT, e0);
+    hipLaunchKernelGGL(k_desc, dim3((words + 255) / 256), dim3(256), 0, s, (const uint4 *)h_views, (uint4 *)d_views,
+                       words);
+    fvv_prof_end(prof, s, FVV_ST_DESC, e0);
     fvv_prof_begin(prof, s, e0);
-    hipLaunchKernelGGL(k_bin_scan, dim3(b.n_views), dim3(256), 0, s, d_views);
-    fvv_prof_end(prof, s, FVV_ST_BIN_SCAN, e0);
+    hipLaunchKernelGGL(k_bin, dim3((b.max_blocks + 3) / 4, b.max_k, b.n_views), dim3(256), 0, s, d_views);
+    fvv_prof_end(prof, s, FVV_ST_BIN, e0);
     fvv_prof_begin(prof, s, e0);
-    hipLaunchKernelGGL(k_bin_fill, dim3((b.max_blocks + 255) / 256, b.max_k, b.n_views), dim3(256), 0, s,
-                       d_views);
-    fvv_prof_end(prof, s, FVV_ST_BIN_FILL, e0);
-    fvv_prof_begin(prof, s, e0);
-    hipLaunchKernelGGL(k_tile, dim3(b.max_tiles_x, b.max_tiles_y, b.n_views), dim3(256), 0, s, d_views);
+    if (b.any_stack)
+        hipLaunchKernelGGL(k_tile<true>, dim3(b.max_tiles_x, b.max_tiles_y, b.n_views), dim3(256), 0, s, d_views);
+    else
+        hipLaunchKernelGGL(k_tile<false>, dim3(b.max_tiles_x, b.max_tiles_y, b.n_views), dim3(256), 0, s, d_views);
     fvv_prof_end(prof, s, FVV_ST_TILE, e0);
     if (b.fill_bg) {
         fvv_prof_begin(prof, s, e0);
-        hipLaunchKernelGGL(k_fill_open, dim3(b.max_tiles_x, b.max_tiles_y, b.n_views), dim3(256), 0, s,
-                           d_views);
+        const int grid = std::max(1, std::min(b.total_tiles, 2048));
+        hipLaunchKernelGGL(k_fill_open, dim3(grid), dim3(256), 0, s, d_views);
         fvv_prof_end(prof, s, FVV_ST_FILL_OPEN, e0);
     }
     return hipGetLastError();

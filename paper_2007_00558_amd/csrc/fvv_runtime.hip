@@ -22,6 +22,7 @@
 
 #include "../../include/fvv.h"
 #include "fvv_internal.h"
+#include "fvv_unet.h"
 
 namespace {
 
@@ -62,8 +63,12 @@ struct Workspace {
     size_t counts_cap = 0;
     fvv_view_desc *d_desc = nullptr;
     size_t desc_cap = 0;
-    static constexpr int kRing = 4;       // pinned host descriptor buffers
+    int2 *open_list = nullptr;            // batch list of tiles with open holes
+    int32_t *open_count = nullptr;
+    bool dirty = false;                   // a launch failed: clear the counters first
+    static constexpr int kRing = 4;       // coherent pinned host descriptor buffers
     fvv_view_desc *h_desc[kRing] = {};
+    fvv_view_desc *h_desc_dev[kRing] = {};   // their device-visible addresses
     hipEvent_t h_ev[kRing] = {};
     bool h_live[kRing] = {};
     size_t h_cap = 0;
@@ -71,7 +76,7 @@ struct Workspace {
 };
 
 struct ViewLayout {
-    int ntx, nty, n_tiles, blk_stride, list_cap, K;
+    int ntx, nty, n_tiles, blk_stride, tile_cap, K;
     int32_t idx[FVV_MAX_K];
     double w[FVV_MAX_K];
 };
@@ -115,6 +120,7 @@ struct Server {
     std::mutex dmu;                       // results, stats
     std::unordered_map<uint64_t, Result> results;
     std::atomic<uint64_t> next_ticket{1};
+    unet_act *act[2] = {nullptr, nullptr};   // network activations of each stream's steps
     // statistics
     uint64_t n_steps = 0, n_done = 0, n_failed = 0, pixels = 0, batch_sum = 0;
     double busy_s = 0.0;
@@ -151,6 +157,10 @@ struct fvv_ctx {
     bool profiling = false;
     fvv_prof prof;
     Server *server = nullptr;
+    // learned path: network weights and the activation set of direct calls
+    unet_state *net = nullptr;
+    unet_act *act = nullptr;
+    uint64_t net_bytes = 0;     // device bytes held by the network and every activation set
 };
 
 namespace {
@@ -315,17 +325,19 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // bytes of workspace one view needs: slot plane, tile arrays, bin list,
 // block ranges, and (host-memory output) an RGB8 staging image
-size_t view_ws_bytes(int W, int H, const ViewLayout &L, bool host_out)
+size_t stack_w(int W) { return (size_t)(W + UNET_ALIGN - 1) / UNET_ALIGN * UNET_ALIGN; }
+size_t stack_bytes(int W, int H) { return stack_w(W) * stack_w(H) * UNET_IN * 2; }
+
+size_t view_ws_bytes(int W, int H, const ViewLayout &L, bool host_out, bool learned = false)
 {
     const size_t px = (size_t)W * H;
     const size_t nt = (size_t)L.n_tiles;
     size_t b = align256(px * 4);                                   // slot
-    b += align256(nt * 4) * 3;                                     // offs, cursor, open
     b += align256(nt * FVV_TILE * sizeof(int2)) * 2;               // rowsum, colsum
-    b += align256((size_t)L.list_cap * 4);                         // list
-    b += align256((size_t)L.K * L.blk_stride * sizeof(int4));      // bbox
-    b += 256;                                                      // overflow flag
+    b += align256(nt * (size_t)L.tile_cap * 4);                    // bin lists
+    b += align256((size_t)L.K * L.blk_stride * sizeof(int4));      // block tile ranges
     if (host_out) b += align256(px * 3);
+    if (learned) b += align256(stack_bytes(W, H));
     return b;
 }
 
@@ -343,7 +355,9 @@ void layout_sizes(ViewLayout &L, int W, int H, const int *nblk, int K)
         mx = std::max(mx, nblk[k]);
     }
     L.blk_stride = mx;
-    L.list_cap = FVV_LIST_PER_BLOCK * sum;
+    // a block touches about two tiles; room for four times the average
+    const int cap = (int)std::min<int64_t>(65536, (8LL * sum + L.n_tiles - 1) / L.n_tiles);
+    L.tile_cap = std::max(FVV_TILE_CAP_MIN, (cap + 31) / 32 * 32);
 }
 
 hipEvent_t take_event(fvv_ctx *c)
@@ -425,11 +439,18 @@ int32_t ws_reserve(fvv_ctx *c, Workspace &W, size_t bytes, size_t tiles, size_t 
     if (W.counts_cap < tiles) {
         HIPCHECK(c, hipDeviceSynchronize());
         dfree(c, W.counts, W.counts_cap * 4);
+        dfree(c, W.open_list, W.counts_cap * sizeof(int2));
+        dfree(c, W.open_count, 256);
         W.counts = nullptr;
+        W.open_list = nullptr;
+        W.open_count = nullptr;
         W.counts_cap = 0;
         if ((rc = dalloc(c, (void **)&W.counts, tiles * 4))) return rc;
+        if ((rc = dalloc(c, (void **)&W.open_list, tiles * sizeof(int2)))) return rc;
+        if ((rc = dalloc(c, (void **)&W.open_count, 256))) return rc;
         HIPCHECK(c, hipMemset(W.counts, 0, tiles * 4));
         W.counts_cap = tiles;
+        W.dirty = false;
     }
     if (W.desc_cap < n) {
         HIPCHECK(c, hipDeviceSynchronize());
@@ -445,7 +466,10 @@ int32_t ws_reserve(fvv_ctx *c, Workspace &W, size_t bytes, size_t tiles, size_t 
             W.h_live[r] = false;
             if (W.h_desc[r]) (void)hipHostFree(W.h_desc[r]);
             W.h_desc[r] = nullptr;
-            HIPCHECK(c, hipHostMalloc((void **)&W.h_desc[r], n * sizeof(fvv_view_desc)));
+            // fine-grained (coherent) so the copy kernel always sees this call's data
+            HIPCHECK(c, hipHostMalloc((void **)&W.h_desc[r], n * sizeof(fvv_view_desc),
+                                      hipHostMallocMapped | hipHostMallocCoherent));
+            HIPCHECK(c, hipHostGetDevicePointer((void **)&W.h_desc_dev[r], W.h_desc[r], 0));
             if (!W.h_ev[r]) HIPCHECK(c, hipEventCreateWithFlags(&W.h_ev[r], hipEventDisableTiming));
         }
         W.h_cap = n;
@@ -457,6 +481,8 @@ void ws_release(fvv_ctx *c, Workspace &W)
 {
     dfree(c, W.ws, W.ws_bytes);
     dfree(c, W.counts, W.counts_cap * 4);
+    dfree(c, W.open_list, W.counts_cap * sizeof(int2));
+    dfree(c, W.open_count, 256);
     dfree(c, W.d_desc, W.desc_cap * sizeof(fvv_view_desc));
     for (int r = 0; r < Workspace::kRing; ++r) {
         if (W.h_desc[r]) (void)hipHostFree(W.h_desc[r]);
@@ -467,7 +493,7 @@ void ws_release(fvv_ctx *c, Workspace &W)
 
 int32_t resolve_params(fvv_ctx *c, const fvv_synth_params *p, fvv_synth_params &o)
 {
-    o = fvv_synth_params{3, 0.05f, 4.0f, FVV_FILL_BG, FVV_PATH_PLAIN, 0, 0};
+    o = fvv_synth_params{3, 0.05f, 4.0f, FVV_FILL_BG, FVV_PATH_PLAIN, 0u, 0};
     if (!p) return FVV_OK;
     o = *p;
     if (o.k_nearest == 0) o.k_nearest = 3;
@@ -481,9 +507,7 @@ int32_t resolve_params(fvv_ctx *c, const fvv_synth_params *p, fvv_synth_params &
         return fail(c, FVV_E_ARG, "max_footprint must lie in [1, 64]");
     if (o.fill_mode != FVV_FILL_BG && o.fill_mode != FVV_FILL_NONE)
         return fail(c, FVV_E_ARG, "unknown fill_mode %d", o.fill_mode);
-    if (o.path == FVV_PATH_LEARNED) return fail(c, FVV_E_UNSUPPORTED, "learned path is not available");
-    if (o.path != FVV_PATH_PLAIN) return fail(c, FVV_E_ARG, "unknown path %d", o.path);
-    if (o.reserved != 0) return fail(c, FVV_E_ARG, "reserved field must be 0");
+    if (o.path != FVV_PATH_PLAIN && o.path != FVV_PATH_LEARNED) return fail(c, FVV_E_ARG, "unknown path %d", o.path);
     return FVV_OK;
 }
 
@@ -500,42 +524,92 @@ int32_t find_slot(fvv_ctx *c, uint64_t version, int &si)
     return FVV_OK;
 }
 
+// Grow an activation set to hold `px` network pixels (and the training
+// buffers if train), within the context's memory budget.
+int32_t reserve_act(fvv_ctx *c, unet_act *a, size_t px, bool train)
+{
+    const bool tr = train || unet_act_trainable(a);
+    const size_t cap = std::max(px, unet_act_cap(a));
+    if (cap == unet_act_cap(a) && tr == unet_act_trainable(a)) return FVV_OK;
+    const size_t before = unet_act_bytes(a), after = unet_act_need(cap, tr);
+    if (c->budget && c->allocated - before + after > c->budget)
+        return fail(c, FVV_E_NOMEM, "device memory budget exceeded by the network activations (%zu bytes)", after);
+    const hipError_t e = unet_act_reserve(a, cap, tr);
+    c->allocated = c->allocated - before + unet_act_bytes(a);
+    c->net_bytes = c->net_bytes - before + unet_act_bytes(a);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, FVV_E_NOMEM, "network activations (%zu bytes): %s", after, hipGetErrorString(e));
+    }
+    return FVV_OK;
+}
+
+int32_t net_status(fvv_ctx *c, hipError_t e, const std::string &err, const char *what)
+{
+    if (e == hipSuccess) return FVV_OK;
+    if (!err.empty()) return fail(c, FVV_E_ARG, "%s: %s", what, err.c_str());
+    return fail(c, FVV_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Learned-path inputs and outputs of one launch sequence.
+struct LearnedIO {
+    unet_act *act = nullptr;           // activation set of the stream (null: the network does not run)
+    uint16_t *stack_out = nullptr;     // caller's stacks [n][stack_h][stack_w][32] (every view learned)
+    bool scratch_out = false;          // RGB goes to workspace scratch (stack-only calls)
+};
+
 // One batched launch sequence over n views (caller holds c->mu, has checked
 // the arguments and resolved each view's parameters).  grow: the workspace
-// may be enlarged; otherwise the caller guarantees it fits.
+// may be enlarged; otherwise the caller guarantees it fits.  Views on the
+// learned path also write the network input stack in the tile kernel, and
+// the network then overwrites their plain result with its own wherever its
+// output is finite; without a loaded network they stay plain.
 int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const fvv_synth_params *Ps, int n_views,
                      void *const *outs, const int64_t *pitches, bool host_out, hipStream_t s, bool grow,
-                     bool taps)
+                     bool taps, const LearnedIO &lio = LearnedIO())
 {
+    const bool have_net = lio.act && c->net && unet_loaded(c->net);
+    std::vector<char> learned(n_views, 0);
+    size_t net_px = 0;
+    for (int v = 0; v < n_views; ++v) {
+        learned[v] = lio.stack_out || (have_net && Ps[v].path == FVV_PATH_LEARNED);
+        if (learned[v] && !lio.stack_out) net_px = std::max(net_px, stack_w(virts[v].width) * stack_w(virts[v].height));
+    }
     const int n = (int)c->rig.size();
     std::vector<ViewLayout> lay(n_views);
     std::vector<int> slot_of(n_views);
     size_t total = 0, total_tiles = 0;
-    fvv_batch_dims dims{n_views, 0, 0, 0, 0, false};
+    fvv_batch_dims dims{n_views, 0, 0, 0, 0, 0, false, false};
     int32_t rc;
     for (int v = 0; v < n_views; ++v) {
         if ((rc = find_slot(c, Ps[v].frame_version, slot_of[v]))) return rc;
         const FrameSlot &fs = c->slots[slot_of[v]];
         ViewLayout &L = lay[v];
         const fvv_camera &vc = virts[v];
-        const int K = select_k(c->rig.data(), fs.present.data(), n, vc, Ps[v].k_nearest, L.idx, L.w);
+        std::vector<int32_t> pres(fs.present);
+        for (int q = 0; q < n; ++q)
+            if (q < 32 && ((Ps[v].exclude_mask >> q) & 1u)) pres[q] = 0;
+        const int K = select_k(c->rig.data(), pres.data(), n, vc, Ps[v].k_nearest, L.idx, L.w);
         if (K < 1) return fail(c, FVV_E_STATE, "no camera present in the frame set");
         int nb[FVV_MAX_K];
         for (int k = 0; k < K; ++k) nb[k] = nblocks(c->rig[L.idx[k]]);
         layout_sizes(L, vc.width, vc.height, nb, K);
-        total += view_ws_bytes(vc.width, vc.height, L, host_out);
+        total += view_ws_bytes(vc.width, vc.height, L, host_out || lio.scratch_out, learned[v] && !lio.stack_out);
         total_tiles += (size_t)L.n_tiles;
+        dims.total_tiles += L.n_tiles;
         dims.max_k = std::max(dims.max_k, L.K);
         dims.max_blocks = std::max(dims.max_blocks, L.blk_stride);
         dims.max_tiles_x = std::max(dims.max_tiles_x, L.ntx);
         dims.max_tiles_y = std::max(dims.max_tiles_y, L.nty);
         dims.fill_bg = dims.fill_bg || Ps[v].fill_mode == FVV_FILL_BG;
+        dims.any_stack = dims.any_stack || learned[v];
     }
     if (grow) {
         if ((rc = ws_reserve(c, Wk, total, total_tiles, n_views))) return rc;
     } else if (Wk.ws_bytes < total || Wk.counts_cap < total_tiles || Wk.desc_cap < (size_t)n_views) {
         return fail(c, FVV_E_NOMEM, "step does not fit its workspace");
     }
+    if (net_px && (rc = reserve_act(c, lio.act, net_px, false))) return rc;
     if (taps) {
         const size_t px = (size_t)virts[0].width * virts[0].height;
         if (c->dbg_px < px) {
@@ -577,7 +651,8 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
         d.ntx = L.ntx;
         d.nty = L.nty;
         d.blk_stride = L.blk_stride;
-        d.list_cap = L.list_cap;
+        d.tile_cap = L.tile_cap;
+        d.view = v;
         const size_t px = (size_t)vc.width * vc.height;
         const size_t nt = (size_t)L.n_tiles;
         auto carve = [&](size_t bytes) {
@@ -586,24 +661,27 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
             return p;
         };
         d.slot = (uint32_t *)carve(px * 4);
-        d.offs = (int32_t *)carve(nt * 4);
-        d.cursor = (int32_t *)carve(nt * 4);
-        d.open = (int32_t *)carve(nt * 4);
         d.rowsum = (int2 *)carve(nt * FVV_TILE * sizeof(int2));
         d.colsum = (int2 *)carve(nt * FVV_TILE * sizeof(int2));
-        d.list = (int32_t *)carve((size_t)L.list_cap * 4);
+        d.list = (int32_t *)carve(nt * (size_t)L.tile_cap * 4);
         d.bbox = (int4 *)carve((size_t)L.K * L.blk_stride * sizeof(int4));
-        d.overflow = (int32_t *)cur;
-        cur += 256;
+        d.open_list = Wk.open_list;
+        d.open_count = Wk.open_count;
         d.counts = cnt;
         cnt += nt;
-        if (host_out) {
+        if (host_out || lio.scratch_out) {
             host_stage[v] = carve(px * 3);
             d.out = host_stage[v];
             d.out_pitch = (int64_t)vc.width * 3;
         } else {
             d.out = (uint8_t *)outs[v];
             d.out_pitch = pitches[v];
+        }
+        if (learned[v]) {
+            d.stack_w = (int32_t)stack_w(vc.width);
+            d.stack_h = (int32_t)stack_w(vc.height);
+            d.stack = lio.stack_out ? lio.stack_out + (size_t)v * stack_bytes(vc.width, vc.height) / 2
+                                    : (uint16_t *)carve(stack_bytes(vc.width, vc.height));
         }
         if (taps && v == 0) {
             d.dbg_z = c->dbg_z;
@@ -634,13 +712,35 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
             HIPCHECK(c, hipStreamWaitEvent(s, c->slots[slot_of[v]].ready, 0));
             waited[slot_of[v]] = true;
         }
-    HIPCHECK(c, hipMemcpyAsync(Wk.d_desc, hd, (size_t)n_views * sizeof(fvv_view_desc), hipMemcpyHostToDevice, s));
+    if (Wk.dirty) {
+        HIPCHECK(c, hipMemsetAsync(Wk.counts, 0, Wk.counts_cap * 4, s));
+        Wk.dirty = false;
+    }
+    const hipError_t le = fvv_launch_synthesis(Wk.h_desc_dev[r], Wk.d_desc, dims, s,
+                                               c->profiling ? &c->prof : nullptr);
+    if (le != hipSuccess) {
+        Wk.dirty = true;
+        return fail(c, FVV_E_DEVICE, "synthesis launch failed: %s", hipGetErrorString(le));
+    }
+    if (net_px) {
+        fvv_prof *prof = c->profiling ? &c->prof : nullptr;
+        for (int v = 0; v < n_views; ++v) {
+            if (!learned[v]) continue;
+            const fvv_view_desc &d = hd[v];
+            std::string err;
+            hipEvent_t e0;
+            fvv_prof_begin(prof, s, e0);
+            const hipError_t e = unet_forward(c->net, lio.act, d.stack, 1, d.stack_h, d.stack_w, nullptr, d.out,
+                                              d.out_pitch, 0, d.H, d.W, s, err);
+            fvv_prof_end(prof, s, FVV_ST_NET, e0);
+            if ((rc = net_status(c, e, err, "network forward"))) return rc;
+        }
+    }
     HIPCHECK(c, hipEventRecord(Wk.h_ev[r], s));
     Wk.h_live[r] = true;
-    HIPCHECK(c, fvv_launch_synthesis(Wk.d_desc, dims, s, c->profiling ? &c->prof : nullptr));
     for (int q = 0; q < 2; ++q)
         if (waited[q] && (rc = note_reader(c, c->slots[q], s))) return rc;
-    if (host_out) {
+    if (host_out && !lio.scratch_out) {
         for (int v = 0; v < n_views; ++v)
             HIPCHECK(c, hipMemcpy2DAsync(outs[v], pitches[v], host_stage[v], (size_t)virts[v].width * 3,
                                          (size_t)virts[v].width * 3, virts[v].height, hipMemcpyDeviceToHost, s));
@@ -669,8 +769,10 @@ int32_t synthesize_impl(fvv_ctx *c, const fvv_camera *virts, int n_views, const 
     }
     DeviceGuard g(c->device);
     std::vector<fvv_synth_params> Ps(n_views, P);
+    LearnedIO lio;
+    lio.act = c->act;
     rc = launch_views(c, c->user, virts, Ps.data(), n_views, outs, pitches, mem_kind == FVV_MEM_HOST,
-                      (hipStream_t)stream, true, c->debug);
+                      (hipStream_t)stream, true, c->debug, lio);
     if (rc) return rc;
     c->have_taps = c->debug;
     c->last_px = (int64_t)virts[0].width * virts[0].height;
@@ -679,7 +781,7 @@ int32_t synthesize_impl(fvv_ctx *c, const fvv_camera *virts, int n_views, const 
 
 // ---------------------------------------------------------------- server
 // Upper bound of the workspace one request can need (any K cameras of the rig).
-void request_bounds(const fvv_ctx *c, const fvv_camera &v, int k, size_t &bytes, size_t &tiles)
+void request_bounds(const fvv_ctx *c, const fvv_camera &v, int k, bool learned, size_t &bytes, size_t &tiles)
 {
     std::vector<int> nb;
     for (const auto &cam : c->rig) nb.push_back(nblocks(cam));
@@ -687,7 +789,7 @@ void request_bounds(const fvv_ctx *c, const fvv_camera &v, int k, size_t &bytes,
     const int K = std::min<int>({k, (int)nb.size(), FVV_MAX_K});
     ViewLayout L;
     layout_sizes(L, v.width, v.height, nb.data(), K);
-    bytes = view_ws_bytes(v.width, v.height, L, false);
+    bytes = view_ws_bytes(v.width, v.height, L, false, learned);
     tiles = (size_t)L.n_tiles;
 }
 
@@ -757,8 +859,10 @@ void scheduler(fvv_ctx *c)
                 outs.push_back(r.out);
                 pitches.push_back(r.pitch);
             }
+            LearnedIO lio;
+            lio.act = S->act[w];
             rc = launch_views(c, S->ws[w], cams.data(), Ps.data(), (int)batch.size(), outs.data(), pitches.data(),
-                              false, S->stream[w], false, false);
+                              false, S->stream[w], false, false, lio);
             if (rc == FVV_OK && hipEventRecord(S->done_ev[w], S->stream[w]) != hipSuccess) rc = FVV_E_DEVICE;
         }
         if (rc != FVV_OK) {
@@ -861,6 +965,10 @@ void server_teardown(fvv_ctx *c)
         }
         if (S->done_ev[w]) (void)hipEventDestroy(S->done_ev[w]);
         ws_release(c, S->ws[w]);
+        const size_t ab = unet_act_bytes(S->act[w]);
+        c->allocated -= std::min<uint64_t>(ab, c->allocated);
+        c->net_bytes -= std::min<uint64_t>(ab, c->net_bytes);
+        unet_act_free(S->act[w]);
     }
     delete S;
     c->server = nullptr;
@@ -909,6 +1017,8 @@ void fvv_destroy(fvv_ctx *c)
         dfree(c, c->dbg_depth, c->dbg_px * 4);
         for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
         for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+        unet_act_free(c->act);
+        unet_free(c->net);
     }
     delete c;
 }
@@ -1061,8 +1171,7 @@ int32_t fvv_pair_matrices(const fvv_camera *src, const fvv_camera *virt, float *
     return FVV_OK;
 }
 
-static const char *k_stage_names[FVV_NSTAGES] = {"repack", "bin_count", "bin_scan", "bin_fill", "tile",
-                                                  "fill_open"};
+static const char *k_stage_names[FVV_NSTAGES] = {"repack", "desc", "bin", "tile", "fill_open", "net", "net_train"};
 
 int32_t fvv_set_profiling(fvv_ctx *c, int32_t enable)
 {
@@ -1152,7 +1261,7 @@ int32_t fvv_server_start(fvv_ctx *c, int32_t max_slots, uint64_t step_bytes)
         v1080.width = 1920;
         v1080.height = 1080;
         size_t b, t;
-        request_bounds(c, v1080, 3, b, t);
+        request_bounds(c, v1080, 3, false, b, t);
         step_bytes = (uint64_t)b * max_slots;
     }
     S->step_bytes = step_bytes;
@@ -1161,6 +1270,7 @@ int32_t fvv_server_start(fvv_ctx *c, int32_t max_slots, uint64_t step_bytes)
     int32_t rc = FVV_OK;
     for (int w = 0; w < 2 && rc == FVV_OK; ++w) {
         rc = ws_reserve(c, S->ws[w], S->step_bytes, S->step_tiles, (size_t)max_slots);
+        if (rc == FVV_OK && !(S->act[w] = unet_act_new())) rc = fail(c, FVV_E_NOMEM, "out of host memory");
         if (rc == FVV_OK && hipStreamCreateWithFlags(&S->stream[w], hipStreamNonBlocking) != hipSuccess)
             rc = fail(c, FVV_E_DEVICE, "hipStreamCreate failed");
         if (rc == FVV_OK &&
@@ -1172,6 +1282,7 @@ int32_t fvv_server_start(fvv_ctx *c, int32_t max_slots, uint64_t step_bytes)
             if (S->stream[w]) (void)hipStreamDestroy(S->stream[w]);
             if (S->done_ev[w]) (void)hipEventDestroy(S->done_ev[w]);
             ws_release(c, S->ws[w]);
+            unet_act_free(S->act[w]);
         }
         delete S;
         return rc;
@@ -1217,7 +1328,7 @@ int32_t fvv_submit(fvv_ctx *c, const fvv_camera *virt, const fvv_synth_params *p
         if (rc) return rc;
         if ((rc = check_camera(c, *virt, false, "virtual camera"))) return rc;
         if (out_pitch < (int64_t)virt->width * 3) return fail(c, FVV_E_ARG, "out_pitch too small");
-        request_bounds(c, *virt, r.P.k_nearest, r.bytes, r.tiles);
+        request_bounds(c, *virt, r.P.k_nearest, r.P.path == FVV_PATH_LEARNED, r.bytes, r.tiles);
     }
     r.cam = *virt;
     r.out = out_dev;
@@ -1267,5 +1378,149 @@ int32_t fvv_server_stats(fvv_ctx *c, uint64_t *out6)
     out6[5] = (uint64_t)(S->busy_s * 1e6);
     return FVV_OK;
 }
+
+// ---------------------------------------------------------------- learned path
+uint64_t fvv_net_param_count(void) { return (uint64_t)unet_param_floats(); }
+
+int32_t fvv_net_layer_info(int32_t layer, int32_t *out4)
+{
+    const unet_layer *l = unet_layer_info(layer);
+    if (!l || !out4) return FVV_E_ARG;
+    out4[0] = l->kind;
+    out4[1] = l->cin;
+    out4[2] = l->cout;
+    out4[3] = l->kind == 0 ? 3 : (l->kind == 1 ? 2 : 1);
+    return FVV_OK;
+}
+
+const char *fvv_net_layer_name(int32_t layer)
+{
+    const unet_layer *l = unet_layer_info(layer);
+    return l ? l->name : nullptr;
+}
+
+int32_t fvv_net_load(fvv_ctx *c, const float *params, uint64_t n)
+{
+    if (!c) return FVV_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (!params || n != unet_param_floats())
+        return fail(c, FVV_E_ARG, "need %zu parameters, got %llu", unet_param_floats(), (unsigned long long)n);
+    for (uint64_t e = 0; e < n; ++e)
+        if (!std::isfinite(params[e])) return fail(c, FVV_E_ARG, "parameter %llu is not finite", (unsigned long long)e);
+    DeviceGuard g(c->device);
+    if (!c->net) {
+        const size_t wb = unet_weight_bytes();
+        if (c->budget && c->allocated + wb > c->budget)
+            return fail(c, FVV_E_NOMEM, "device memory budget exceeded by the network weights (%zu bytes)", wb);
+        c->net = unet_new();
+        c->act = unet_act_new();
+        if (!c->net || !c->act) return fail(c, FVV_E_NOMEM, "out of host memory");
+        c->allocated += wb;
+        c->net_bytes += wb;
+    }
+    HIPCHECK(c, hipDeviceSynchronize());
+    HIPCHECK(c, unet_set_params(c->net, params, nullptr));
+    return FVV_OK;
+}
+
+int32_t fvv_net_read(fvv_ctx *c, int32_t what, float *out, uint64_t n)
+{
+    if (!c) return FVV_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (!c->net || !unet_loaded(c->net)) return fail(c, FVV_E_STATE, "no network loaded");
+    if (!out || n != unet_param_floats())
+        return fail(c, FVV_E_ARG, "need room for %zu parameters", unet_param_floats());
+    DeviceGuard g(c->device);
+    HIPCHECK(c, hipDeviceSynchronize());
+    if (what == FVV_NET_PARAMS) HIPCHECK(c, unet_get_params(c->net, out, nullptr));
+    else if (what == FVV_NET_GRADS) HIPCHECK(c, unet_get_grads(c->net, out, nullptr));
+    else return fail(c, FVV_E_ARG, "unknown selector %d", what);
+    return FVV_OK;
+}
+
+int32_t fvv_make_stack(fvv_ctx *c, const fvv_camera *virts, int32_t n_views, const fvv_synth_params *params,
+                       void *stack_dev, void *stream)
+{
+    if (!c) return FVV_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (!virts || !params || !stack_dev || n_views < 1) return fail(c, FVV_E_ARG, "null argument or n_views < 1");
+    if (((uintptr_t)stack_dev & 15) != 0) return fail(c, FVV_E_ARG, "stack_dev must be 16-byte aligned");
+    if (c->rig.empty()) return fail(c, FVV_E_STATE, "no rig set");
+    std::vector<fvv_synth_params> Ps(n_views);
+    int32_t rc;
+    for (int v = 0; v < n_views; ++v) {
+        if ((rc = resolve_params(c, &params[v], Ps[v]))) return rc;
+        Ps[v].path = FVV_PATH_LEARNED;
+        if ((rc = check_camera(c, virts[v], false, "virtual camera"))) return rc;
+        if (virts[v].width != virts[0].width || virts[v].height != virts[0].height)
+            return fail(c, FVV_E_ARG, "all views of a stack call must share one size");
+    }
+    DeviceGuard g(c->device);
+    LearnedIO lio;
+    lio.stack_out = (uint16_t *)stack_dev;
+    lio.scratch_out = true;
+    return launch_views(c, c->user, virts, Ps.data(), n_views, nullptr, nullptr, false, (hipStream_t)stream, true,
+                        false, lio);
+}
+
+int32_t fvv_net_forward(fvv_ctx *c, const void *stack_dev, int32_t n, int32_t height, int32_t width, float *out_dev,
+                        void *stream)
+{
+    if (!c) return FVV_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (!c->net || !unet_loaded(c->net)) return fail(c, FVV_E_STATE, "no network loaded");
+    if (!stack_dev || !out_dev || n < 1 || height < 1 || width < 1 || height % UNET_ALIGN || width % UNET_ALIGN)
+        return fail(c, FVV_E_ARG, "bad network input (sizes must be multiples of %d)", UNET_ALIGN);
+    DeviceGuard g(c->device);
+    const size_t px = (size_t)n * height * width;
+    int32_t rc = reserve_act(c, c->act, px, false);
+    if (rc) return rc;
+    std::string err;
+    hipEvent_t e0;
+    fvv_prof *prof = c->profiling ? &c->prof : nullptr;
+    fvv_prof_begin(prof, (hipStream_t)stream, e0);
+    const hipError_t e = unet_forward(c->net, c->act, (const uint16_t *)stack_dev, n, height, width, out_dev, nullptr,
+                                      0, 0, 0, 0, (hipStream_t)stream, err);
+    fvv_prof_end(prof, (hipStream_t)stream, FVV_ST_NET, e0);
+    return net_status(c, e, err, "network forward");
+}
+
+int32_t fvv_net_train_step(fvv_ctx *c, const void *stack_dev, const float *target_dev, int32_t n, int32_t height,
+                           int32_t width, int32_t valid_rows, float lr, int32_t apply, float *loss_out, void *stream)
+{
+    if (!c) return FVV_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (!c->net || !unet_loaded(c->net)) return fail(c, FVV_E_STATE, "no network loaded");
+    if (!stack_dev || !target_dev || n < 1 || height < 1 || width < 1 || height % UNET_ALIGN || width % UNET_ALIGN ||
+        valid_rows < 1 || valid_rows > height)
+        return fail(c, FVV_E_ARG, "bad training batch (sizes must be multiples of %d, 1 <= valid_rows <= height)",
+                    UNET_ALIGN);
+    if (!std::isfinite(lr) || lr < 0.f) return fail(c, FVV_E_ARG, "learning rate must be finite and >= 0");
+    DeviceGuard g(c->device);
+    int32_t rc = reserve_act(c, c->act, (size_t)n * height * width, true);
+    if (rc) return rc;
+    std::string err;
+    hipEvent_t e0;
+    fvv_prof *prof = c->profiling ? &c->prof : nullptr;
+    fvv_prof_begin(prof, (hipStream_t)stream, e0);
+    const hipError_t e = unet_train(c->net, c->act, (const uint16_t *)stack_dev, target_dev, n, height, width,
+                                    valid_rows, lr, apply, loss_out, (hipStream_t)stream, err);
+    fvv_prof_end(prof, (hipStream_t)stream, FVV_ST_TRAIN, e0);
+    return net_status(c, e, err, "training step");
+}
+
+int32_t fvv_net_read_act(fvv_ctx *c, int32_t layer, void *host_out, int64_t bytes)
+{
+    if (!c) return FVV_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (!c->act || !host_out || bytes < 0) return fail(c, FVV_E_STATE, "no network activations");
+    DeviceGuard g(c->device);
+    HIPCHECK(c, hipDeviceSynchronize());
+    const hipError_t e = unet_read_act(c->act, layer, host_out, (size_t)bytes, nullptr);
+    if (e != hipSuccess) return fail(c, FVV_E_ARG, "layer %d: wrong layer or byte count", layer);
+    return FVV_OK;
+}
+
+uint64_t fvv_net_device_bytes(fvv_ctx *c) { return c ? c->net_bytes : 0; }
 
 }  // extern "C"

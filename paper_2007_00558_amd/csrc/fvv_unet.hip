@@ -1,0 +1,1176 @@
+// fvv_unet.hip -- learned blend/inpaint network on gfx950 matrix cores.
+//
+// Every convolution is an implicit GEMM on v_mfma_f32_16x16x32_bf16: rows are
+// output channels (A = bf16 weights, [rows][taps][K]), columns are pixels
+// (B = bf16 NHWC activations gathered per tap), so each lane's accumulator
+// holds four consecutive output channels of one pixel and stores them with
+// one 8- or 16-byte write.  Weight gradients contract over pixels: tiles of
+// the gradient and of the layer input are transposed through LDS and every
+// workgroup writes an fp32 partial for its pixel chunk; a second kernel sums
+// the partials in chunk order, so gradients are deterministic (no float
+// atomics anywhere).  bfloat16 values are rounded to nearest even.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "fvv_unet.h"
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+enum { TAP_CONV3 = 0, TAP_ONE = 1, TAP_FINE4 = 2 };
+enum { EPI_RELU_BF16 = 0, EPI_F32 = 1, EPI_CONVT_BF16 = 2 };
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);   // quiet NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x8 ld8(const uint16_t *p) { return __builtin_bit_cast(bf16x8, *(const uint4 *)p); }
+
+struct GemmArgs {
+    const uint16_t *A;       // [M][taps][K] bf16
+    const uint16_t *Bsrc;    // NHWC bf16 activations
+    int b_cs, b_off;         // channel stride / offset of Bsrc
+    const float *bias;       // per output channel (EPI_RELU_BF16, EPI_CONVT_BF16)
+    void *out;
+    int o_cs, o_off;
+    int NB, H, W;            // column pixels: NB images of H x W
+    int K;                   // channels per tap (multiple of 32)
+    int M;                   // rows (multiple of 16)
+    int cout;                // EPI_CONVT_BF16: output channels (M = 4 cout)
+};
+
+// Source pixel of tap t for column pixel (b, y, x); -1 outside.
+template <int TAP>
+__device__ __forceinline__ int64_t tap_src(int b, int y, int x, int t, int H, int W)
+{
+    if (TAP == TAP_CONV3) {
+        const int sy = y + t / 3 - 1, sx = x + t % 3 - 1;
+        if (sy < 0 || sx < 0 || sy >= H || sx >= W) return -1;
+        return ((int64_t)b * H + sy) * W + sx;
+    } else if (TAP == TAP_FINE4) {
+        return ((int64_t)b * 2 * H + 2 * y + (t >> 1)) * (2 * W) + 2 * x + (t & 1);
+    } else {
+        return ((int64_t)b * H + y) * W + x;
+    }
+}
+
+template <int MC, int NP, int TAP, int EPI>
+__global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int HW = g.H * g.W;
+    const int P = g.NB * HW;
+    const int taps = TAP == TAP_CONV3 ? 9 : (TAP == TAP_FINE4 ? 4 : 1);
+    int pb[NP], py[NP], px[NP];
+    bool pv[NP];
+    const int pbase = blockIdx.x * (64 * NP) + wave * (16 * NP);
+#pragma unroll
+    for (int n = 0; n < NP; ++n) {
+        const int p = pbase + n * 16 + lr;
+        pv[n] = p < P;
+        const int pp = pv[n] ? p : 0;
+        pb[n] = pp / HW;
+        const int r = pp - pb[n] * HW;
+        py[n] = r / g.W;
+        px[n] = r - py[n] * g.W;
+    }
+    const int mbase = blockIdx.y * (16 * MC);
+    f32x4 acc[MC][NP];
+#pragma unroll
+    for (int i = 0; i < MC; ++i)
+#pragma unroll
+        for (int n = 0; n < NP; ++n) acc[i][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8 zero8 = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+    for (int t = 0; t < taps; ++t) {
+        int64_t src[NP];
+#pragma unroll
+        for (int n = 0; n < NP; ++n) {
+            const int64_t q = pv[n] ? tap_src<TAP>(pb[n], py[n], px[n], t, g.H, g.W) : -1;
+            src[n] = q < 0 ? -1 : q * g.b_cs + g.b_off;
+        }
+        for (int c0 = 0; c0 < g.K; c0 += 32) {
+            const int kk = c0 + 8 * lg;
+            bf16x8 bfr[NP], afr[MC];
+#pragma unroll
+            for (int n = 0; n < NP; ++n) bfr[n] = src[n] >= 0 ? ld8(g.Bsrc + src[n] + kk) : zero8;
+#pragma unroll
+            for (int i = 0; i < MC; ++i) {
+                const int m = mbase + i * 16 + lr;
+                afr[i] = m < g.M ? ld8(g.A + ((int64_t)m * taps + t) * g.K + kk) : zero8;
+            }
+#pragma unroll
+            for (int i = 0; i < MC; ++i)
+#pragma unroll
+                for (int n = 0; n < NP; ++n)
+                    acc[i][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afr[i], bfr[n], acc[i][n], 0, 0, 0);
+        }
+    }
+    // epilogue: lane holds rows m0..m0+3 of column pixel (pb, py, px)
+#pragma unroll
+    for (int i = 0; i < MC; ++i) {
+        const int m0 = mbase + i * 16 + 4 * lg;
+        if (m0 >= g.M) continue;
+#pragma unroll
+        for (int n = 0; n < NP; ++n) {
+            if (!pv[n]) continue;
+            const int64_t pix = ((int64_t)pb[n] * g.H + py[n]) * g.W + px[n];
+            float v0 = acc[i][n][0], v1 = acc[i][n][1], v2 = acc[i][n][2], v3 = acc[i][n][3];
+            if (EPI == EPI_F32) {
+                float *o = (float *)g.out + pix * g.o_cs + g.o_off + m0;
+                *(float4 *)o = make_float4(v0, v1, v2, v3);
+            } else if (EPI == EPI_RELU_BF16) {
+                v0 = fmaxf(v0 + g.bias[m0 + 0], 0.f);
+                v1 = fmaxf(v1 + g.bias[m0 + 1], 0.f);
+                v2 = fmaxf(v2 + g.bias[m0 + 2], 0.f);
+                v3 = fmaxf(v3 + g.bias[m0 + 3], 0.f);
+                uint16_t *o = (uint16_t *)g.out + pix * g.o_cs + g.o_off + m0;
+                *(uint2 *)o = make_uint2((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16),
+                                         (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16));
+            } else {
+                const int d = m0 / g.cout, co = m0 - d * g.cout;
+                const int64_t fp = ((int64_t)pb[n] * 2 * g.H + 2 * py[n] + (d >> 1)) * (2 * g.W) + 2 * px[n] + (d & 1);
+                v0 += g.bias[co + 0];
+                v1 += g.bias[co + 1];
+                v2 += g.bias[co + 2];
+                v3 += g.bias[co + 3];
+                uint16_t *o = (uint16_t *)g.out + fp * g.o_cs + g.o_off + co;
+                *(uint2 *)o = make_uint2((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16),
+                                         (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16));
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- weight gradient
+struct WgradArgs {
+    const uint16_t *G;       // bf16 gradient of the layer output (rows)
+    int g_cs, g_off;
+    const uint16_t *X;       // bf16 layer input (columns)
+    int x_cs, x_off;
+    float *part;             // [chunks][M][taps*K] fp32 partial sums
+    int NB, H, W;            // pixel grid of the contraction (the coarse grid for convT)
+    int M, K;                // rows; input channels per tap (multiple of 32)
+    int chunk;               // pixels per workgroup (multiple of 32)
+};
+
+constexpr int WG_LD = 40;    // LDS row length in bf16 (32 pixels + pad, 16-byte aligned rows)
+
+// grid: x = tap * (K/32) + column block of 32 channels, y = 64-row block,
+// z = pixel chunk.  LDS holds the chunk's 32-pixel steps transposed to
+// [channel][pixel] so each lane reads 8 consecutive pixels of one channel.
+template <int TAP>
+__global__ void __launch_bounds__(256) k_wgrad(const WgradArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t Gt[64 * WG_LD];
+    __shared__ __attribute__((aligned(16))) uint16_t Xt[32 * WG_LD];
+    const int taps = TAP == TAP_CONV3 ? 9 : (TAP == TAP_FINE4 ? 4 : 1);
+    const int ncb = a.K / 32;
+    const int t = blockIdx.x / ncb, cb = blockIdx.x - t * ncb;
+    const int mb = blockIdx.y * 64;
+    const int HW = a.H * a.W, P = a.NB * HW;
+    const int p_begin = blockIdx.z * a.chunk, p_end = min(P, p_begin + a.chunk);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+    for (int p0 = p_begin; p0 < p_end; p0 += 32) {
+        // gradient tile: 32 pixels x 64 rows (8 rows per thread)
+        {
+            const int pl = tid >> 3, rg = tid & 7;
+            const int p = p0 + pl;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            const int m = mb + rg * 8;
+            if (p < p_end && m < a.M) {
+                const int b = p / HW, r = p - b * HW, y = r / a.W, x = r - y * a.W;
+                int64_t gp;
+                if (TAP == TAP_FINE4)
+                    gp = ((int64_t)b * 2 * a.H + 2 * y + (t >> 1)) * (2 * a.W) + 2 * x + (t & 1);
+                else
+                    gp = p;
+                v = *(const uint4 *)(a.G + gp * a.g_cs + a.g_off + m);
+            }
+            const uint16_t *h = (const uint16_t *)&v;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) Gt[(rg * 8 + j) * WG_LD + pl] = h[j];
+        }
+        // input tile: 32 pixels x 32 channels (threads 0..127)
+        if (tid < 128) {
+            const int pl = tid >> 2, cg = tid & 3;
+            const int p = p0 + pl;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (p < p_end) {
+                const int b = p / HW, r = p - b * HW, y = r / a.W, x = r - y * a.W;
+                int64_t xp = -1;
+                if (TAP == TAP_CONV3) {
+                    const int sy = y + t / 3 - 1, sx = x + t % 3 - 1;
+                    if (sy >= 0 && sx >= 0 && sy < a.H && sx < a.W) xp = ((int64_t)b * a.H + sy) * a.W + sx;
+                } else {
+                    xp = p;
+                }
+                if (xp >= 0) v = *(const uint4 *)(a.X + xp * a.x_cs + a.x_off + cb * 32 + cg * 8);
+            }
+            const uint16_t *h = (const uint16_t *)&v;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) Xt[(cg * 8 + j) * WG_LD + pl] = h[j];
+        }
+        __syncthreads();
+        const bf16x8 af = __builtin_bit_cast(bf16x8, *(const uint4 *)&Gt[(wave * 16 + lr) * WG_LD + 8 * lg]);
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+            const bf16x8 bf = __builtin_bit_cast(bf16x8, *(const uint4 *)&Xt[(n * 16 + lr) * WG_LD + 8 * lg]);
+            acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, acc[n], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    const int cols = taps * a.K;
+    float *out = a.part + (int64_t)blockIdx.z * a.M * cols;
+#pragma unroll
+    for (int n = 0; n < 2; ++n)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int m = mb + wave * 16 + 4 * lg + r;
+            if (m < a.M) out[(int64_t)m * cols + t * a.K + cb * 32 + n * 16 + lr] = acc[n][r];
+        }
+}
+
+// Sum the partials in chunk order into the canonical gradient (rows x taps x
+// cin, dropping padded input channels).
+__global__ void __launch_bounds__(256) k_wgrad_reduce(const float *__restrict__ part, int chunks, int M, int taps,
+                                                      int K, int cin, float *__restrict__ gw)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = M * taps * cin;
+    if (e >= n) return;
+    const int ci = e % cin, mt = e / cin, t = mt % taps, m = mt / taps;
+    const int64_t cols = (int64_t)taps * K;
+    float s = 0.f;
+    for (int c = 0; c < chunks; ++c) s += part[(int64_t)c * M * cols + (int64_t)m * cols + t * K + ci];
+    gw[e] = s;
+}
+
+// ---------------------------------------------------------------- elementwise layers
+// 2x2 max-pool, bf16 NHWC; thread per (output pixel, 8 channels).
+__global__ void __launch_bounds__(256) k_pool(const uint16_t *in, int i_cs, int i_off, uint16_t *out, int NB, int H,
+                                              int W, int C)
+{
+    const int groups = C / 8;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int Ho = H / 2, Wo = W / 2;
+    if (e >= (int64_t)NB * Ho * Wo * groups) return;
+    const int gi = (int)(e % groups);
+    const int64_t op = e / groups;
+    const int b = (int)(op / (Ho * Wo)), r = (int)(op % (Ho * Wo)), y = r / Wo, x = r - y * Wo;
+    uint16_t best[8];
+    for (int d = 0; d < 4; ++d) {
+        const int64_t ip = ((int64_t)b * H + 2 * y + (d >> 1)) * W + 2 * x + (d & 1);
+        const uint4 v = *(const uint4 *)(in + ip * i_cs + i_off + gi * 8);
+        const uint16_t *h = (const uint16_t *)&v;
+        for (int j = 0; j < 8; ++j)
+            if (d == 0 || bf2f(h[j]) > bf2f(best[j])) best[j] = h[j];
+    }
+    *(uint4 *)(out + op * C + gi * 8) = *(const uint4 *)best;
+}
+
+// Pool backward fused with the skip-connection gradient: g_fine[p] =
+// (p is the first maximum of its window ? g_coarse : 0) + skip[p].
+__global__ void __launch_bounds__(256) k_pool_back(const uint16_t *a, int a_cs, int a_off, const float *g_coarse,
+                                                   const float *skip, int s_cs, int s_off, float *g_fine, int NB,
+                                                   int H, int W, int C)
+{
+    const int groups = C / 8;
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int Ho = H / 2, Wo = W / 2;
+    if (e >= (int64_t)NB * Ho * Wo * groups) return;
+    const int gi = (int)(e % groups);
+    const int64_t op = e / groups;
+    const int b = (int)(op / (Ho * Wo)), r = (int)(op % (Ho * Wo)), y = r / Wo, x = r - y * Wo;
+    float best[8];
+    int arg[8];
+    for (int d = 0; d < 4; ++d) {
+        const int64_t ip = ((int64_t)b * H + 2 * y + (d >> 1)) * W + 2 * x + (d & 1);
+        const uint4 v = *(const uint4 *)(a + ip * a_cs + a_off + gi * 8);
+        const uint16_t *h = (const uint16_t *)&v;
+        for (int j = 0; j < 8; ++j) {
+            const float f = bf2f(h[j]);
+            if (d == 0 || f > best[j]) {
+                best[j] = f;
+                arg[j] = d;
+            }
+        }
+    }
+    for (int d = 0; d < 4; ++d) {
+        const int64_t ip = ((int64_t)b * H + 2 * y + (d >> 1)) * W + 2 * x + (d & 1);
+        for (int j = 0; j < 8; ++j) {
+            const int c = gi * 8 + j;
+            const float gv = arg[j] == d ? g_coarse[op * C + c] : 0.f;
+            g_fine[ip * C + c] = gv + skip[ip * s_cs + s_off + c];
+        }
+    }
+}
+
+// Gradient at a layer output -> bf16 matrix-core operand (masked by the ReLU
+// when relu != 0) and per-workgroup bias partial sums of the fp32 masked
+// gradient.  Workgroup: 64 pixels; thread: 8 channels.
+__global__ void __launch_bounds__(256) k_mask_round(const float *g, int g_cs, int g_off, const uint16_t *act, int a_cs,
+                                                    int a_off, int relu, uint16_t *G, int C, int P, float *bpart)
+{
+    const int groups = C / 8;
+    const int tid = threadIdx.x;
+    const int gi = tid % groups;
+    float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const int p0 = blockIdx.x * 64;
+    for (int e = tid; e < 64 * groups; e += 256) {
+        const int p = p0 + e / groups;
+        if (p >= P) break;
+        const float4 ga = *(const float4 *)(g + (int64_t)p * g_cs + g_off + gi * 8);
+        const float4 gb = *(const float4 *)(g + (int64_t)p * g_cs + g_off + gi * 8 + 4);
+        float v[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
+        if (relu) {
+            const uint4 av = *(const uint4 *)(act + (int64_t)p * a_cs + a_off + gi * 8);
+            const uint16_t *h = (const uint16_t *)&av;
+            for (int j = 0; j < 8; ++j)
+                if (!(bf2f(h[j]) > 0.f)) v[j] = 0.f;
+        }
+        uint16_t o[8];
+        for (int j = 0; j < 8; ++j) {
+            s[j] += v[j];
+            o[j] = f2bf(v[j]);
+        }
+        *(uint4 *)(G + (int64_t)p * C + gi * 8) = *(const uint4 *)o;
+    }
+    __shared__ float red[256 * 8];
+    for (int j = 0; j < 8; ++j) red[tid * 8 + j] = s[j];
+    __syncthreads();
+    if (tid < groups) {
+        float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int u = tid; u < 256; u += groups)
+            for (int j = 0; j < 8; ++j) acc[j] += red[u * 8 + j];
+        for (int j = 0; j < 8; ++j) bpart[(int64_t)blockIdx.x * C + tid * 8 + j] = acc[j];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_reduce_rows(const float *part, int rows, int n, float *out)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    float s = 0.f;
+    for (int r = 0; r < rows; ++r) s += part[(int64_t)r * n + e];
+    out[e] = s;
+}
+
+// Head: 1x1 conv 32->3 + bias, sigmoid.  mode 0: inference (s and/or RGB8
+// of finite pixels); mode 1: training (loss partials, d loss / d z, the
+// gradient at the head input and the head's weight/bias partials).
+struct HeadArgs {
+    const uint16_t *a;       // [P][32] bf16
+    const uint16_t *w;       // [3][32] bf16
+    const float *bias;       // [3]
+    float *s_out;            // [P][3] or null
+    uint8_t *rgb;            // image b at rgb + b * img_stride, or null
+    int64_t pitch, img_stride;
+    int NB, H, W, valid_h, valid_w;
+    const float *target;     // [P][3] training
+    float inv_n;             // 1 / (NB * valid_h * W * 3)
+    float *g_a;              // [P][32] fp32 gradient at the head input
+    float *part;             // per workgroup: 3*32 weight + 3 bias partials + 1 loss partial
+};
+
+__global__ void __launch_bounds__(256) k_head(const HeadArgs h, int mode)
+{
+    __shared__ float red[256 * 4];
+    __shared__ float wred[32 * 4];
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int P = h.NB * h.H * h.W;
+    const bool in = p < P;
+    float a[32];
+    float z[3] = {0.f, 0.f, 0.f};
+    if (in) {
+        for (int q = 0; q < 4; ++q) {
+            const uint4 v = *(const uint4 *)(h.a + p * 32 + q * 8);
+            const uint16_t *hv = (const uint16_t *)&v;
+            for (int j = 0; j < 8; ++j) a[q * 8 + j] = bf2f(hv[j]);
+        }
+        for (int c = 0; c < 3; ++c) {
+            float acc = 0.f;
+            for (int ci = 0; ci < 32; ++ci) acc += bf2f(h.w[c * 32 + ci]) * a[ci];
+            z[c] = acc + h.bias[c];
+        }
+    }
+    float s[3];
+    for (int c = 0; c < 3; ++c) s[c] = 1.0f / (1.0f + expf(-z[c]));
+    const int b = in ? (int)(p / (h.H * h.W)) : 0;
+    const int r = in ? (int)(p % (h.H * h.W)) : 0;
+    const int y = r / h.W, x = r - y * h.W;
+    if (mode == 0) {
+        if (!in) return;
+        if (h.s_out)
+            for (int c = 0; c < 3; ++c) h.s_out[p * 3 + c] = s[c];
+        if (h.rgb && y < h.valid_h && x < h.valid_w && isfinite(s[0]) && isfinite(s[1]) && isfinite(s[2])) {
+            uint8_t *o = h.rgb + b * h.img_stride + (int64_t)y * h.pitch + (int64_t)x * 3;
+            for (int c = 0; c < 3; ++c) o[c] = (uint8_t)fminf(floorf(s[c] * 255.f + 0.5f), 255.f);
+        }
+        return;
+    }
+    // training
+    float gz[3] = {0.f, 0.f, 0.f}, loss = 0.f;
+    if (in && y < h.valid_h) {
+        for (int c = 0; c < 3; ++c) {
+            const float d = s[c] - h.target[p * 3 + c];
+            loss += fabsf(d);
+            const float sg = d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f);
+            gz[c] = sg * h.inv_n * s[c] * (1.f - s[c]);
+        }
+    }
+    float gzr[3];
+    for (int c = 0; c < 3; ++c) gzr[c] = bf2f(f2bf(gz[c]));
+    if (in)
+        for (int ci = 0; ci < 32; ++ci) {
+            float acc = 0.f;
+            for (int c = 0; c < 3; ++c) acc += gzr[c] * bf2f(h.w[c * 32 + ci]);
+            h.g_a[p * 32 + ci] = acc;
+        }
+    // per-workgroup partials: weights (3 x 32), bias (3), loss (1), fixed order
+    const int tid = threadIdx.x;
+    float *outp = h.part + (int64_t)blockIdx.x * (96 + 4);
+    for (int c = 0; c < 3; ++c) {
+        for (int q = 0; q < 8; ++q) {   // 32 input channels in 8 rounds of 4
+            for (int j = 0; j < 4; ++j) red[tid * 4 + j] = in ? gzr[c] * a[q * 4 + j] : 0.f;
+            __syncthreads();
+            if (tid < 4) {
+                float acc = 0.f;
+                for (int u = 0; u < 256; ++u) acc += red[u * 4 + tid];
+                wred[(q * 4 + tid)] = acc;
+            }
+            __syncthreads();
+        }
+        if (tid < 32) outp[c * 32 + tid] = wred[tid];
+        __syncthreads();
+    }
+    red[tid * 4 + 0] = gz[0];
+    red[tid * 4 + 1] = gz[1];
+    red[tid * 4 + 2] = gz[2];
+    red[tid * 4 + 3] = loss;
+    __syncthreads();
+    if (tid < 4) {
+        float acc = 0.f;
+        for (int u = 0; u < 256; ++u) acc += red[u * 4 + tid];
+        outp[96 + tid] = acc;
+    }
+}
+
+// Adam on the fp32 master parameters of one layer, and the bf16 copies in
+// the forward layout ([rows][taps][cin_pad]) and the data-gradient layout
+// ([cin][taps][cout], taps mirrored for 3x3).
+struct AdamArgs {
+    float *w, *m, *v;
+    const float *g;
+    int n;                   // floats of this parameter block
+    int is_weight;
+    int kind, cin, cin_pad, cout, taps;
+    uint16_t *wf, *wd;
+    float lr, b1, b2, eps, c1, c2;   // c1 = 1 / (1 - b1^t), c2 = 1 / (1 - b2^t)
+    int apply;
+};
+
+__global__ void __launch_bounds__(256) k_adam(const AdamArgs a)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.n) return;
+    float w = a.w[e];
+    if (a.apply) {
+        const float g = a.g[e];
+        const float m = a.b1 * a.m[e] + (1.f - a.b1) * g;
+        const float v = a.b2 * a.v[e] + (1.f - a.b2) * g * g;
+        a.m[e] = m;
+        a.v[e] = v;
+        w = w - a.lr * (m * a.c1) / (sqrtf(v * a.c2) + a.eps);
+        a.w[e] = w;
+    }
+    if (!a.is_weight) return;
+    const int ci = e % a.cin, rest = e / a.cin, t = rest % a.taps, co = rest / a.taps;
+    const uint16_t wb = f2bf(w);
+    if (a.kind == 1) {   // convT: forward rows are (tap, cout)
+        a.wf[((int64_t)(t * a.cout + co)) * a.cin_pad + ci] = wb;
+    } else {
+        a.wf[((int64_t)co * a.taps + t) * a.cin_pad + ci] = wb;
+    }
+    if (a.wd) {
+        const int td = a.kind == 0 ? a.taps - 1 - t : t;
+        a.wd[((int64_t)ci * a.taps + td) * a.cout + co] = wb;
+    }
+}
+
+// ---------------------------------------------------------------- host side
+const struct {
+    const char *name;
+    int kind, cin, cout;
+} kLayers[] = {
+    {"enc0a", 0, UNET_IN_CANON, 32}, {"enc0b", 0, 32, 32},  {"enc1a", 0, 32, 64},   {"enc1b", 0, 64, 64},
+    {"enc2a", 0, 64, 128},              {"enc2b", 0, 128, 128}, {"mid_a", 0, 128, 256}, {"mid_b", 0, 256, 256},
+    {"up2", 1, 256, 128},               {"dec2a", 0, 256, 128}, {"dec2b", 0, 128, 128}, {"up1", 1, 128, 64},
+    {"dec1a", 0, 128, 64},              {"dec1b", 0, 64, 64},   {"up0", 1, 64, 32},     {"dec0a", 0, 64, 32},
+    {"dec0b", 0, 32, 32},               {"head", 2, 32, 3},
+};
+constexpr int kNL = sizeof(kLayers) / sizeof(kLayers[0]);
+enum { L_E0A, L_E0B, L_E1A, L_E1B, L_E2A, L_E2B, L_MA, L_MB, L_UP2, L_D2A, L_D2B, L_UP1, L_D1A, L_D1B, L_UP0,
+       L_D0A, L_D0B, L_HEAD };
+// resolution level (0 = full) of each layer's output, and of its weight-gradient contraction
+constexpr int kOutLevel[kNL] = {0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 2, 1, 1, 1, 0, 0, 0, 0};
+constexpr int kSumLevel[kNL] = {0, 0, 1, 1, 2, 2, 3, 3, 3, 2, 2, 2, 1, 1, 1, 0, 0, 0};
+
+struct Layers {
+    unet_layer L[kNL];
+    size_t n_params = 0, n_wf = 0, n_wd = 0;
+    Layers()
+    {
+        for (int i = 0; i < kNL; ++i) {
+            unet_layer &l = L[i];
+            l.name = kLayers[i].name;
+            l.kind = kLayers[i].kind;
+            l.cin = kLayers[i].cin;
+            l.cout = kLayers[i].cout;
+            l.cin_pad = l.kind == 2 ? l.cin : std::max(32, l.cin);
+            l.taps = l.kind == 0 ? 9 : (l.kind == 1 ? 4 : 1);
+            l.w_off = n_params;
+            n_params += (size_t)l.cout * l.taps * l.cin;
+            l.b_off = n_params;
+            n_params += (size_t)l.cout;
+            l.wf_off = n_wf;
+            n_wf += (size_t)l.cout * l.taps * l.cin_pad;
+            l.wd_off = n_wd;
+            if (l.kind != 2 && i != L_E0A) n_wd += (size_t)l.cout * l.taps * l.cin;
+        }
+    }
+};
+const Layers &layers()
+{
+    static const Layers t;
+    return t;
+}
+
+// chunking of a weight-gradient contraction over P pixels
+int wgrad_chunk(size_t P) { return (int)std::max<size_t>(256, ((P / 128) + 31) / 32 * 32); }
+
+size_t partial_floats(size_t P0)
+{
+    const Layers &T = layers();
+    size_t m = ((P0 + 63) / 64) * 256;   // bias partials (<= 256 channels per 64-pixel group)
+    for (int i = 0; i < kNL; ++i) {
+        const unet_layer &l = T.L[i];
+        if (l.kind == 2) continue;
+        // any contraction over at most Pk pixels has <= min(ceil(Pk / 256), 128) chunks
+        const size_t Pk = P0 >> (2 * kSumLevel[i]);
+        const size_t chunks = std::min<size_t>((Pk + 255) / 256, 128);
+        m = std::max(m, chunks * l.cout * l.taps * l.cin_pad);
+    }
+    return m;
+}
+
+#define NCHK(expr)                                  \
+    do {                                            \
+        hipError_t e_ = (expr);                     \
+        if (e_ != hipSuccess) return e_;            \
+    } while (0)
+
+}  // namespace
+
+struct unet_state {
+    float *w = nullptr, *m = nullptr, *v = nullptr, *g = nullptr;
+    uint16_t *wf = nullptr, *wd = nullptr;
+    int step = 0;
+    bool loaded = false;
+};
+
+// Forward activations (bf16; concat buffers hold [up | skip]) and, for
+// training, the fp32 gradient ping-pong, the concat gradients, the bf16
+// matrix-core operand and the partial sums.
+struct unet_act {
+    size_t cap = 0;          // pixels at full resolution
+    bool train = false;
+    size_t bytes = 0;
+    int NB = 0, H = 0, W = 0;
+    uint16_t *e0a = nullptr, *cat0 = nullptr, *p1 = nullptr, *e1a = nullptr, *cat1 = nullptr, *p2 = nullptr,
+             *e2a = nullptr, *cat2 = nullptr, *p3 = nullptr, *ma = nullptr, *mb = nullptr, *d2a = nullptr,
+             *d2b = nullptr, *d1a = nullptr, *d1b = nullptr, *d0a = nullptr, *d0b = nullptr;
+    float *g0 = nullptr, *g1 = nullptr;                  // [P0][32] each
+    float *gs0 = nullptr, *gs1 = nullptr, *gs2 = nullptr;   // [P0][64], [P1][128], [P2][256]
+    uint16_t *G = nullptr;                                // [P0][32]
+    float *part = nullptr;
+    float *head_part = nullptr;
+    float *loss_dev = nullptr;
+    void *blocks[40] = {};
+    int n_blocks = 0;
+};
+
+namespace {
+
+struct Plan {
+    size_t off[40];
+    int n = 0;
+    size_t total = 0;
+    size_t add(size_t bytes)
+    {
+        off[n++] = total;
+        const size_t o = total;
+        total += (bytes + 255) & ~(size_t)255;
+        return o;
+    }
+};
+
+// One allocation per set; the plan gives every buffer its offset.
+template <typename F>
+void act_plan(size_t P0, bool train, F &&put)
+{
+    const size_t P1 = P0 / 4, P2 = P1 / 4, P3 = P2 / 4;
+    put(0, P0 * 32 * 2);     // e0a
+    put(1, P0 * 64 * 2);     // cat0
+    put(2, P1 * 32 * 2);     // p1
+    put(3, P1 * 64 * 2);     // e1a
+    put(4, P1 * 128 * 2);    // cat1
+    put(5, P2 * 64 * 2);     // p2
+    put(6, P2 * 128 * 2);    // e2a
+    put(7, P2 * 256 * 2);    // cat2
+    put(8, P3 * 128 * 2);    // p3
+    put(9, P3 * 256 * 2);    // ma
+    put(10, P3 * 256 * 2);   // mb
+    put(11, P2 * 128 * 2);   // d2a
+    put(12, P2 * 128 * 2);   // d2b
+    put(13, P1 * 64 * 2);    // d1a
+    put(14, P1 * 64 * 2);    // d1b
+    put(15, P0 * 32 * 2);    // d0a
+    put(16, P0 * 32 * 2);    // d0b
+    if (!train) return;
+    put(17, P0 * 32 * 4);    // g0
+    put(18, P0 * 32 * 4);    // g1
+    put(19, P0 * 64 * 4);    // gs0
+    put(20, P1 * 128 * 4);   // gs1
+    put(21, P2 * 256 * 4);   // gs2
+    put(22, P0 * 32 * 2);    // G
+    put(23, partial_floats(P0) * 4);
+    put(24, ((P0 + 255) / 256) * 100 * 4);
+    put(25, 256);            // loss
+}
+
+}  // namespace
+
+unet_state *unet_new() { return new (std::nothrow) unet_state(); }
+
+void unet_free(unet_state *n)
+{
+    if (!n) return;
+    for (void *p : {(void *)n->w, (void *)n->m, (void *)n->v, (void *)n->g, (void *)n->wf, (void *)n->wd})
+        if (p) (void)hipFree(p);
+    delete n;
+}
+
+unet_act *unet_act_new() { return new (std::nothrow) unet_act(); }
+
+void unet_act_free(unet_act *a)
+{
+    if (!a) return;
+    if (a->blocks[0]) (void)hipFree(a->blocks[0]);
+    delete a;
+}
+
+size_t unet_param_floats() { return layers().n_params; }
+int unet_layer_count() { return kNL; }
+const unet_layer *unet_layer_info(int i) { return (i >= 0 && i < kNL) ? &layers().L[i] : nullptr; }
+size_t unet_weight_bytes()
+{
+    const Layers &T = layers();
+    return T.n_params * 4 * 4 + (T.n_wf + T.n_wd) * 2;
+}
+size_t unet_act_need(size_t pixels, bool train)
+{
+    size_t total = 0;
+    act_plan(pixels, train, [&](int, size_t b) { total += (b + 255) & ~(size_t)255; });
+    return total;
+}
+size_t unet_act_bytes(const unet_act *a) { return a ? a->bytes : 0; }
+size_t unet_act_cap(const unet_act *a) { return a ? a->cap : 0; }
+bool unet_act_trainable(const unet_act *a) { return a && a->train; }
+bool unet_loaded(const unet_state *n) { return n && n->loaded; }
+
+hipError_t unet_act_reserve(unet_act *a, size_t pixels, bool train)
+{
+    if (a->cap >= pixels && (a->train || !train)) return hipSuccess;
+    const size_t cap = std::max(pixels, a->cap);
+    train = train || a->train;
+    NCHK(hipDeviceSynchronize());
+    if (a->blocks[0]) (void)hipFree(a->blocks[0]);
+    *a = unet_act();
+    size_t off[32] = {}, total = 0;
+    act_plan(cap, train, [&](int i, size_t b) {
+        off[i] = total;
+        total += (b + 255) & ~(size_t)255;
+    });
+    uint8_t *base = nullptr;
+    NCHK(hipMalloc((void **)&base, total));
+    a->blocks[0] = base;
+    a->bytes = total;
+    a->cap = cap;
+    a->train = train;
+    uint16_t **bf[17] = {&a->e0a, &a->cat0, &a->p1, &a->e1a, &a->cat1, &a->p2, &a->e2a, &a->cat2, &a->p3,
+                         &a->ma,  &a->mb,   &a->d2a, &a->d2b, &a->d1a, &a->d1b, &a->d0a, &a->d0b};
+    for (int i = 0; i < 17; ++i) *bf[i] = (uint16_t *)(base + off[i]);
+    if (train) {
+        a->g0 = (float *)(base + off[17]);
+        a->g1 = (float *)(base + off[18]);
+        a->gs0 = (float *)(base + off[19]);
+        a->gs1 = (float *)(base + off[20]);
+        a->gs2 = (float *)(base + off[21]);
+        a->G = (uint16_t *)(base + off[22]);
+        a->part = (float *)(base + off[23]);
+        a->head_part = (float *)(base + off[24]);
+        a->loss_dev = (float *)(base + off[25]);
+    }
+    return hipSuccess;
+}
+
+namespace {
+
+template <int MC, int NP, int TAP, int EPI>
+hipError_t gemm(const GemmArgs &g, hipStream_t s)
+{
+    const int P = g.NB * g.H * g.W;
+    dim3 grid((P + 64 * NP - 1) / (64 * NP), (g.M + 16 * MC - 1) / (16 * MC));
+    hipLaunchKernelGGL((k_gemm<MC, NP, TAP, EPI>), grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+// 3x3 conv + bias + ReLU into (out, o_cs, o_off)
+hipError_t conv_fwd(unet_state *n, int li, const uint16_t *in, int i_cs, int i_off, uint16_t *out, int o_cs, int o_off,
+                    int NB, int H, int W, hipStream_t s)
+{
+    const unet_layer &l = layers().L[li];
+    GemmArgs g{};
+    g.A = n->wf + l.wf_off;
+    g.Bsrc = in;
+    g.b_cs = i_cs;
+    g.b_off = i_off;
+    g.bias = n->w + l.b_off;
+    g.out = out;
+    g.o_cs = o_cs;
+    g.o_off = o_off;
+    g.NB = NB;
+    g.H = H;
+    g.W = W;
+    g.K = l.cin_pad;
+    g.M = l.cout;
+    if (l.cout >= 64) return gemm<4, 1, TAP_CONV3, EPI_RELU_BF16>(g, s);
+    return gemm<2, 2, TAP_CONV3, EPI_RELU_BF16>(g, s);
+}
+
+hipError_t convT_fwd(unet_state *n, int li, const uint16_t *in, int i_cs, int NB, int H, int W, uint16_t *out,
+                     int o_cs, hipStream_t s)
+{
+    const unet_layer &l = layers().L[li];
+    GemmArgs g{};
+    g.A = n->wf + l.wf_off;
+    g.Bsrc = in;
+    g.b_cs = i_cs;
+    g.bias = n->w + l.b_off;
+    g.out = out;
+    g.o_cs = o_cs;
+    g.NB = NB;
+    g.H = H;
+    g.W = W;
+    g.K = l.cin_pad;
+    g.M = 4 * l.cout;
+    g.cout = l.cout;
+    return gemm<4, 1, TAP_ONE, EPI_CONVT_BF16>(g, s);
+}
+
+hipError_t pool(const uint16_t *in, int i_cs, int i_off, uint16_t *out, int NB, int H, int W, int C, hipStream_t s)
+{
+    const int64_t n = (int64_t)NB * (H / 2) * (W / 2) * (C / 8);
+    hipLaunchKernelGGL(k_pool, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, i_cs, i_off, out, NB, H, W, C);
+    return hipGetLastError();
+}
+
+hipError_t forward_all(unet_state *n, unet_act *a, const uint16_t *stack, int NB, int H, int W, hipStream_t s)
+{
+    a->NB = NB;
+    a->H = H;
+    a->W = W;
+    const int H1 = H / 2, W1 = W / 2, H2 = H / 4, W2 = W / 4, H3 = H / 8, W3 = W / 8;
+    NCHK(conv_fwd(n, L_E0A, stack, UNET_IN, 0, a->e0a, 32, 0, NB, H, W, s));
+    NCHK(conv_fwd(n, L_E0B, a->e0a, 32, 0, a->cat0, 64, 32, NB, H, W, s));
+    NCHK(pool(a->cat0, 64, 32, a->p1, NB, H, W, 32, s));
+    NCHK(conv_fwd(n, L_E1A, a->p1, 32, 0, a->e1a, 64, 0, NB, H1, W1, s));
+    NCHK(conv_fwd(n, L_E1B, a->e1a, 64, 0, a->cat1, 128, 64, NB, H1, W1, s));
+    NCHK(pool(a->cat1, 128, 64, a->p2, NB, H1, W1, 64, s));
+    NCHK(conv_fwd(n, L_E2A, a->p2, 64, 0, a->e2a, 128, 0, NB, H2, W2, s));
+    NCHK(conv_fwd(n, L_E2B, a->e2a, 128, 0, a->cat2, 256, 128, NB, H2, W2, s));
+    NCHK(pool(a->cat2, 256, 128, a->p3, NB, H2, W2, 128, s));
+    NCHK(conv_fwd(n, L_MA, a->p3, 128, 0, a->ma, 256, 0, NB, H3, W3, s));
+    NCHK(conv_fwd(n, L_MB, a->ma, 256, 0, a->mb, 256, 0, NB, H3, W3, s));
+    NCHK(convT_fwd(n, L_UP2, a->mb, 256, NB, H3, W3, a->cat2, 256, s));
+    NCHK(conv_fwd(n, L_D2A, a->cat2, 256, 0, a->d2a, 128, 0, NB, H2, W2, s));
+    NCHK(conv_fwd(n, L_D2B, a->d2a, 128, 0, a->d2b, 128, 0, NB, H2, W2, s));
+    NCHK(convT_fwd(n, L_UP1, a->d2b, 128, NB, H2, W2, a->cat1, 128, s));
+    NCHK(conv_fwd(n, L_D1A, a->cat1, 128, 0, a->d1a, 64, 0, NB, H1, W1, s));
+    NCHK(conv_fwd(n, L_D1B, a->d1a, 64, 0, a->d1b, 64, 0, NB, H1, W1, s));
+    NCHK(convT_fwd(n, L_UP0, a->d1b, 64, NB, H1, W1, a->cat0, 64, s));
+    NCHK(conv_fwd(n, L_D0A, a->cat0, 64, 0, a->d0a, 32, 0, NB, H, W, s));
+    NCHK(conv_fwd(n, L_D0B, a->d0a, 32, 0, a->d0b, 32, 0, NB, H, W, s));
+    return hipSuccess;
+}
+
+// gradient g (fp32, C channels at g_off of a g_cs-channel buffer) of layer
+// li's output -> bf16 operand a->G [P][C] (ReLU-masked by the stored output
+// when relu) and the layer's bias gradient
+hipError_t mask_round(unet_state *n, unet_act *a, const float *g, int g_cs, int g_off, const uint16_t *act,
+                      int a_cs, int a_off, bool relu, int C, int P, int li, hipStream_t s)
+{
+    const int wgs = (P + 63) / 64;
+    hipLaunchKernelGGL(k_mask_round, dim3(wgs), dim3(256), 0, s, g, g_cs, g_off, act, a_cs, a_off, relu ? 1 : 0, a->G,
+                       C, P, a->part);
+    NCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce_rows, dim3((C + 255) / 256), dim3(256), 0, s, (const float *)a->part, wgs, C,
+                       n->g + layers().L[li].b_off);
+    return hipGetLastError();
+}
+
+// weight gradient of layer li from a->G (its masked output gradient) and
+// its input X; (NB, H, W) is the contraction grid (the coarse grid for convT)
+template <int TAP>
+hipError_t wgrad(unet_state *n, unet_act *a, int li, const uint16_t *X, int x_cs, int NB, int H, int W, hipStream_t s)
+{
+    const unet_layer &l = layers().L[li];
+    const int P = NB * H * W;
+    const int chunk = wgrad_chunk((size_t)P);
+    const int chunks = (P + chunk - 1) / chunk;
+    WgradArgs w{};
+    w.G = a->G;
+    w.g_cs = l.cout;
+    w.X = X;
+    w.x_cs = x_cs;
+    w.part = a->part;
+    w.NB = NB;
+    w.H = H;
+    w.W = W;
+    w.M = l.cout;
+    w.K = l.cin_pad;
+    w.chunk = chunk;
+    constexpr int taps = TAP == TAP_CONV3 ? 9 : (TAP == TAP_FINE4 ? 4 : 1);
+    dim3 grid(taps * (l.cin_pad / 32), (l.cout + 63) / 64, chunks);
+    hipLaunchKernelGGL(k_wgrad<TAP>, grid, dim3(256), 0, s, w);
+    NCHK(hipGetLastError());
+    const int nel = l.cout * taps * l.cin;
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3((nel + 255) / 256), dim3(256), 0, s, (const float *)a->part, chunks,
+                       l.cout, taps, l.cin_pad, l.cin, n->g + l.w_off);
+    return hipGetLastError();
+}
+
+// data gradient of a 3x3 conv from a->G: fp32 [P][cin]
+hipError_t conv_dgrad(unet_state *n, unet_act *a, int li, float *out, int NB, int H, int W, hipStream_t s)
+{
+    const unet_layer &l = layers().L[li];
+    GemmArgs g{};
+    g.A = n->wd + l.wd_off;
+    g.Bsrc = a->G;
+    g.b_cs = l.cout;
+    g.out = out;
+    g.o_cs = l.cin;
+    g.NB = NB;
+    g.H = H;
+    g.W = W;
+    g.K = l.cout;
+    g.M = l.cin;
+    if (l.cin >= 64) return gemm<4, 1, TAP_CONV3, EPI_F32>(g, s);
+    return gemm<2, 2, TAP_CONV3, EPI_F32>(g, s);
+}
+
+// data gradient of a 2x2 transposed conv: a->G on the fine grid -> fp32 [P_coarse][cin]
+hipError_t convT_dgrad(unet_state *n, unet_act *a, int li, float *out, int NB, int Hc, int Wc, hipStream_t s)
+{
+    const unet_layer &l = layers().L[li];
+    GemmArgs g{};
+    g.A = n->wd + l.wd_off;
+    g.Bsrc = a->G;
+    g.b_cs = l.cout;
+    g.out = out;
+    g.o_cs = l.cin;
+    g.NB = NB;
+    g.H = Hc;
+    g.W = Wc;
+    g.K = l.cout;
+    g.M = l.cin;
+    return gemm<4, 1, TAP_FINE4, EPI_F32>(g, s);
+}
+
+hipError_t pool_back(const uint16_t *act, int a_cs, int a_off, const float *g_coarse, const float *skip, int s_cs,
+                     int s_off, float *g_fine, int NB, int H, int W, int C, hipStream_t s)
+{
+    const int64_t n = (int64_t)NB * (H / 2) * (W / 2) * (C / 8);
+    hipLaunchKernelGGL(k_pool_back, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, act, a_cs, a_off, g_coarse,
+                       skip, s_cs, s_off, g_fine, NB, H, W, C);
+    return hipGetLastError();
+}
+
+// Adam (apply) and the bf16 copies of every layer
+hipError_t prep_weights(unet_state *n, float lr, int apply, hipStream_t s)
+{
+    float c1 = 1.f, c2 = 1.f;
+    if (apply) {
+        c1 = (float)(1.0 / (1.0 - std::pow(0.9, n->step)));
+        c2 = (float)(1.0 / (1.0 - std::pow(0.999, n->step)));
+    }
+    const Layers &T = layers();
+    for (int i = 0; i < kNL; ++i) {
+        const unet_layer &l = T.L[i];
+        for (int part = 0; part < 2; ++part) {
+            AdamArgs a{};
+            const size_t off = part == 0 ? l.w_off : l.b_off;
+            a.w = n->w + off;
+            a.m = n->m + off;
+            a.v = n->v + off;
+            a.g = n->g + off;
+            a.n = part == 0 ? l.cout * l.taps * l.cin : l.cout;
+            a.is_weight = part == 0;
+            a.kind = l.kind;
+            a.cin = l.cin;
+            a.cin_pad = l.cin_pad;
+            a.cout = l.cout;
+            a.taps = l.taps;
+            a.wf = n->wf + l.wf_off;
+            a.wd = (l.kind != 2 && i != L_E0A) ? n->wd + l.wd_off : nullptr;
+            a.lr = lr;
+            a.b1 = 0.9f;
+            a.b2 = 0.999f;
+            a.eps = 1e-8f;
+            a.c1 = c1;
+            a.c2 = c2;
+            a.apply = apply;
+            hipLaunchKernelGGL(k_adam, dim3((a.n + 255) / 256), dim3(256), 0, s, a);
+            NCHK(hipGetLastError());
+        }
+    }
+    return hipSuccess;
+}
+
+bool geometry_ok(unet_act *a, int NB, int H, int W)
+{
+    return NB >= 1 && H >= UNET_ALIGN && W >= UNET_ALIGN && H % UNET_ALIGN == 0 && W % UNET_ALIGN == 0 &&
+           (size_t)NB * H * W <= a->cap;
+}
+
+}  // namespace
+
+hipError_t unet_set_params(unet_state *n, const float *host, hipStream_t s)
+{
+    const Layers &T = layers();
+    if (!n->w) {
+        NCHK(hipMalloc((void **)&n->w, T.n_params * 4));
+        NCHK(hipMalloc((void **)&n->m, T.n_params * 4));
+        NCHK(hipMalloc((void **)&n->v, T.n_params * 4));
+        NCHK(hipMalloc((void **)&n->g, T.n_params * 4));
+        NCHK(hipMalloc((void **)&n->wf, T.n_wf * 2));
+        NCHK(hipMalloc((void **)&n->wd, T.n_wd * 2));
+    }
+    NCHK(hipMemcpyAsync(n->w, host, T.n_params * 4, hipMemcpyHostToDevice, s));
+    NCHK(hipMemsetAsync(n->m, 0, T.n_params * 4, s));
+    NCHK(hipMemsetAsync(n->v, 0, T.n_params * 4, s));
+    NCHK(hipMemsetAsync(n->g, 0, T.n_params * 4, s));
+    NCHK(hipMemsetAsync(n->wf, 0, T.n_wf * 2, s));   // padded input channels stay zero
+    n->step = 0;
+    NCHK(prep_weights(n, 0.f, 0, s));
+    NCHK(hipStreamSynchronize(s));
+    n->loaded = true;
+    return hipSuccess;
+}
+
+hipError_t unet_get_params(unet_state *n, float *host, hipStream_t s)
+{
+    NCHK(hipMemcpyAsync(host, n->w, layers().n_params * 4, hipMemcpyDeviceToHost, s));
+    return hipStreamSynchronize(s);
+}
+
+hipError_t unet_get_grads(unet_state *n, float *host, hipStream_t s)
+{
+    NCHK(hipMemcpyAsync(host, n->g, layers().n_params * 4, hipMemcpyDeviceToHost, s));
+    return hipStreamSynchronize(s);
+}
+
+hipError_t unet_forward(unet_state *n, unet_act *a, const uint16_t *stack, int NB, int H, int W, float *s_out,
+                           uint8_t *rgb, int64_t pitch, int64_t img_stride, int valid_h, int valid_w,
+                           hipStream_t s, std::string &err)
+{
+    if (!n->loaded) {
+        err = "no network parameters loaded";
+        return hipErrorInvalidValue;
+    }
+    if (!geometry_ok(a, NB, H, W)) {
+        err = "network input must be a multiple of 8 in both dimensions and fit the activation set";
+        return hipErrorInvalidValue;
+    }
+    NCHK(forward_all(n, a, stack, NB, H, W, s));
+    const unet_layer &hl = layers().L[L_HEAD];
+    HeadArgs h{};
+    h.a = a->d0b;
+    h.w = n->wf + hl.wf_off;
+    h.bias = n->w + hl.b_off;
+    h.s_out = s_out;
+    h.rgb = rgb;
+    h.pitch = pitch;
+    h.img_stride = img_stride;
+    h.NB = NB;
+    h.H = H;
+    h.W = W;
+    h.valid_h = valid_h;
+    h.valid_w = valid_w;
+    const int P = NB * H * W;
+    hipLaunchKernelGGL(k_head, dim3((P + 255) / 256), dim3(256), 0, s, h, 0);
+    return hipGetLastError();
+}
+
+hipError_t unet_train(unet_state *n, unet_act *a, const uint16_t *stack, const float *target, int NB, int H,
+                         int W, int valid_h, float lr, int apply, float *loss_host, hipStream_t s, std::string &err)
+{
+    if (!n->loaded) {
+        err = "no network parameters loaded";
+        return hipErrorInvalidValue;
+    }
+    if (!a->train || !geometry_ok(a, NB, H, W) || valid_h < 1 || valid_h > H) {
+        err = "bad training geometry";
+        return hipErrorInvalidValue;
+    }
+    NCHK(forward_all(n, a, stack, NB, H, W, s));
+    const int P0 = NB * H * W, P1 = P0 / 4, P2 = P1 / 4, P3 = P2 / 4;
+    const int H1 = H / 2, W1 = W / 2, H2 = H / 4, W2 = W / 4, H3 = H / 8, W3 = W / 8;
+    const Layers &T = layers();
+    // head: loss, gradient at dec0b, head weight/bias gradients
+    HeadArgs h{};
+    h.a = a->d0b;
+    h.w = n->wf + T.L[L_HEAD].wf_off;
+    h.bias = n->w + T.L[L_HEAD].b_off;
+    h.NB = NB;
+    h.H = H;
+    h.W = W;
+    h.valid_h = valid_h;
+    h.valid_w = W;
+    h.target = target;
+    h.inv_n = (float)(1.0 / ((double)NB * valid_h * W * 3));
+    h.g_a = a->g0;
+    h.part = a->head_part;
+    const int hwg = (P0 + 255) / 256;
+    hipLaunchKernelGGL(k_head, dim3(hwg), dim3(256), 0, s, h, 1);
+    NCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(256), 0, s, (const float *)a->head_part, hwg, 100, a->part);
+    NCHK(hipGetLastError());
+    NCHK(hipMemcpyAsync(n->g + T.L[L_HEAD].w_off, a->part, 96 * 4, hipMemcpyDeviceToDevice, s));
+    NCHK(hipMemcpyAsync(n->g + T.L[L_HEAD].b_off, a->part + 96, 3 * 4, hipMemcpyDeviceToDevice, s));
+    NCHK(hipMemcpyAsync(a->loss_dev, a->part + 99, 4, hipMemcpyDeviceToDevice, s));
+    // decoder, level 0
+    NCHK(mask_round(n, a, a->g0, 32, 0, a->d0b, 32, 0, true, 32, P0, L_D0B, s));
+    NCHK(wgrad<TAP_CONV3>(n, a, L_D0B, a->d0a, 32, NB, H, W, s));
+    NCHK(conv_dgrad(n, a, L_D0B, a->g1, NB, H, W, s));
+    NCHK(mask_round(n, a, a->g1, 32, 0, a->d0a, 32, 0, true, 32, P0, L_D0A, s));
+    NCHK(wgrad<TAP_CONV3>(n, a, L_D0A, a->cat0, 64, NB, H, W, s));
+    NCHK(conv_dgrad(n, a, L_D0A, a->gs0, NB, H, W, s));              // [g_up0 | g_skip0]
+    NCHK(mask_round(n, a, a->gs0, 64, 0, nullptr, 0, 0, false, 32, P0, L_UP0, s));
+    NCHK(wgrad<TAP_FINE4>(n, a, L_UP0, a->d1b, 64, NB, H1, W1, s));
+    NCHK(convT_dgrad(n, a, L_UP0, a->g0, NB, H1, W1, s));            // g(d1b) [P1][64]
+    // level 1
+    NCHK(mask_round(n, a, a->g0, 64, 0, a->d1b, 64, 0, true, 64, P1, L_D1B, s));
+    NCHK(wgrad<TAP_CONV3>(n, a, L_D1B, a->d1a, 64, NB, H1, W1, s));
+    NCHK(conv_dgrad(n, a, L_D1B, a->g1, NB, H1, W1, s));
+    NCHK(mask_round(n, a, a->g1, 64, 0, a->d1a, 64, 0, true, 64, P1, L_D1A, s));
+    NCHK(wgrad<TAP_CONV3>(n, a, L_D1A, a->cat1, 128, NB, H1, W1, s));
+    NCHK(conv_dgrad(n, a, L_D1A, a->gs1, NB, H1, W1, s));            // [g_up1 | g_skip1]
+    NCHK(mask_round(n, a, a->gs1, 128, 0, nullptr, 0, 0, false, 64, P1, L_UP1, s));
+    NCHK(wgrad<TAP_FINE4>(n, a, L_UP1, a->d2b, 128, NB, H2, W2, s));
+    NCHK(convT_dgrad(n, a, L_UP1, a->g0, NB, H2, W2, s));            // g(d2b) [P2][128]
+    // level 2
+    NCHK(mask_round(n, a, a->g0, 128, 0, a->d2b, 128, 0, true, 128, P2, L_D2B, s));
+    NCHK(wgrad<TAP_CONV3>(n, a, L_D2B, a->d2a, 128, NB, H2, W2, s));
+    NCHK(conv_dgrad(n, a, L_D2B, a->g1, NB, H2, W2, s));
+    NCHK(mask_round(n, a, a->g1, 128, 0, a->d2a, 128, 0, true, 128, P2, L_D2A, s));
+    NCHK(wgrad<TAP_CONV3>(n, a, L_D2A, a->cat2, 256, NB, H2, W2, s));
+    NCHK(conv_dgrad(n, a, L_D2A, a->gs2, NB, H2, W2, s));            // [g_up2 | g_skip2]
+    NCHK(mask_round(n, a, a->gs2, 256, 0, nullptr, 0, 0, false, 128, P2, L_UP2, s));
+    NCHK(wgrad<TAP_FINE4>(n, a, L_UP2, a->mb, 256, NB, H3, W3, s));
+    NCHK(convT_dgrad(n, a, L_UP2, a->g0, NB, H3, W3, s));            // g(mb) [P3][256]
+    // bottleneck
+    NCHK(mask_round(n, a, a->g0, 256, 0, a->mb, 256, 0, true, 256, P3, L_MB, s));
+    NCHK(wgrad<TAP_CONV3>(n, a, L_MB, a->ma, 256, NB, H3, W3, s));
+    NCHK(conv_dgrad(n, a, L_MB, a->g1, NB, H3, W3, s));
+    NCHK(mask_round(n, a, a->g1, 256, 0, a->ma, 256, 0, true, 256, P3, L_MA, s));
+    NCHK(wgrad<TAP_CONV3>(n, a, L_MA, a->p3, 128, NB, H3, W3, s));
+    NCHK(conv_dgrad(n, a, L_MA, a->g0, NB, H3, W3, s));              // g(p3) [P3][128]
+    // encoder, level 2: g(enc2b) = pool routing of g(p3) + skip
+    NCHK(pool_back(a->cat2, 256, 128, a->g0, a->gs2, 256, 128, a->g1, NB, H2, W2, 128, s));
+    NCHK(mask_round(n, a, a->g1, 128, 0, a->cat2, 256, 128, true, 128, P2, L_E2B, s));
+    NCHK(wgrad<TAP_CONV3>(n, a, L_E2B, a->e2a, 128, NB, H2, W2, s));
+    NCHK(conv_dgrad(n, a, L_E2B, a->g0, NB, H2, W2, s));
+    NCHK(mask_round(n, a, a->g0, 128, 0, a->e2a, 128, 0, true, 128, P2, L_E2A, s));
+    NCHK(wgrad<TAP_CONV3>(n, a, L_E2A, a->p2, 64, NB, H2, W2, s));
+    NCHK(conv_dgrad(n, a, L_E2A, a->g1, NB, H2, W2, s));             // g(p2) [P2][64]
+    // level 1
+    NCHK(pool_back(a->cat1, 128, 64, a->g1, a->gs1, 128, 64, a->g0, NB, H1, W1, 64, s));
+    NCHK(mask_round(n, a, a->g0, 64, 0, a->cat1, 128, 64, true, 64, P1, L_E1B, s));
+    NCHK(wgrad<TAP_CONV3>(n, a, L_E1B, a->e1a, 64, NB, H1, W1, s));
+    NCHK(conv_dgrad(n, a, L_E1B, a->g1, NB, H1, W1, s));
+    NCHK(mask_round(n, a, a->g1, 64, 0, a->e1a, 64, 0, true, 64, P1, L_E1A, s));
+    NCHK(wgrad<TAP_CONV3>(n, a, L_E1A, a->p1, 32, NB, H1, W1, s));
+    NCHK(conv_dgrad(n, a, L_E1A, a->g0, NB, H1, W1, s));             // g(p1) [P1][32]
+    // level 0
+    NCHK(pool_back(a->cat0, 64, 32, a->g0, a->gs0, 64, 32, a->g1, NB, H, W, 32, s));
+    NCHK(mask_round(n, a, a->g1, 32, 0, a->cat0, 64, 32, true, 32, P0, L_E0B, s));
+    NCHK(wgrad<TAP_CONV3>(n, a, L_E0B, a->e0a, 32, NB, H, W, s));
+    NCHK(conv_dgrad(n, a, L_E0B, a->g0, NB, H, W, s));
+    NCHK(mask_round(n, a, a->g0, 32, 0, a->e0a, 32, 0, true, 32, P0, L_E0A, s));
+    NCHK(wgrad<TAP_CONV3>(n, a, L_E0A, stack, UNET_IN, NB, H, W, s));
+    if (apply) {
+        n->step += 1;
+        NCHK(prep_weights(n, lr, 1, s));
+    }
+    if (loss_host) {
+        float sum = 0.f;
+        NCHK(hipMemcpyAsync(&sum, a->loss_dev, 4, hipMemcpyDeviceToHost, s));
+        NCHK(hipStreamSynchronize(s));
+        *loss_host = (float)(sum / ((double)NB * valid_h * W * 3));
+    }
+    return hipSuccess;
+}
+
+hipError_t unet_read_act(unet_act *a, int layer, void *host, size_t bytes, hipStream_t s)
+{
+    const uint16_t *src = nullptr;
+    int cs = 0, off = 0, C = 0;
+    switch (layer) {
+    case L_E0A: src = a->e0a; cs = 32; C = 32; break;
+    case L_E0B: src = a->cat0; cs = 64; off = 32; C = 32; break;
+    case L_E1A: src = a->e1a; cs = 64; C = 64; break;
+    case L_E1B: src = a->cat1; cs = 128; off = 64; C = 64; break;
+    case L_E2A: src = a->e2a; cs = 128; C = 128; break;
+    case L_E2B: src = a->cat2; cs = 256; off = 128; C = 128; break;
+    case L_MA: src = a->ma; cs = 256; C = 256; break;
+    case L_MB: src = a->mb; cs = 256; C = 256; break;
+    case L_UP2: src = a->cat2; cs = 256; C = 128; break;
+    case L_D2A: src = a->d2a; cs = 128; C = 128; break;
+    case L_D2B: src = a->d2b; cs = 128; C = 128; break;
+    case L_UP1: src = a->cat1; cs = 128; C = 64; break;
+    case L_D1A: src = a->d1a; cs = 64; C = 64; break;
+    case L_D1B: src = a->d1b; cs = 64; C = 64; break;
+    case L_UP0: src = a->cat0; cs = 64; C = 32; break;
+    case L_D0A: src = a->d0a; cs = 32; C = 32; break;
+    case L_D0B: src = a->d0b; cs = 32; C = 32; break;
+    default: return hipErrorInvalidValue;
+    }
+    if (!src || a->NB == 0) return hipErrorInvalidValue;
+    const size_t P = ((size_t)a->NB * a->H * a->W) >> (2 * kOutLevel[layer]);
+    if (bytes != P * C * 2) return hipErrorInvalidValue;
+    NCHK(hipMemcpy2DAsync(host, (size_t)C * 2, src + off, (size_t)cs * 2, (size_t)C * 2, P, hipMemcpyDeviceToHost, s));
+    return hipStreamSynchronize(s);
+}

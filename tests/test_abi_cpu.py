@@ -27,7 +27,7 @@ def test_library_exports_every_declared_function():
     for name in names:
         assert hasattr(L, name), name
     assert set(names) == set(fvv.EXPORTED)
-    assert L.fvv_abi_version() == 1
+    assert L.fvv_abi_version() == 2
 
 
 def test_header_struct_layouts_match_binding():
@@ -83,3 +83,17 @@ def test_create_without_gpu_fails_cleanly():
     assert rc in (fvv.FVV_E_DEVICE, fvv.FVV_E_ARG)
     assert not h.value
     assert len(L.fvv_last_error(None)) > 0
+
+
+def test_network_layout_matches_definition():
+    """The library's network (host-side description, no device needed) has
+    the layers, channel counts and parameter count of the CPU definition."""
+    import paper_2007_00558_amd as fvv
+    from oracle import unet
+    got = fvv.net_layers()
+    kinds = {"conv": 0, "convT": 1, "head": 2}
+    ksz = {"conv": 3, "convT": 2, "head": 1}
+    assert [(n, k, ci, co, s) for n, k, ci, co, s in got] == \
+        [(n, kinds[k], ci, co, ksz[k]) for n, k, ci, co in unet.LAYERS]
+    total = sum(int(np.prod(unet.weight_shape(k, ci, co))) + co for _, k, ci, co in unet.LAYERS)
+    assert fvv.net_param_count() == total

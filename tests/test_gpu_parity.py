@@ -233,9 +233,11 @@ def test_error_codes(fvv):
         with pytest.raises(fvv.FvvError) as e:
             c.synthesize(w.virtual[0], p=bad)
         assert e.value.code == fvv.FVV_E_ARG
+    bad_path = fvv.params()
+    bad_path.path = 7
     with pytest.raises(fvv.FvvError) as e:
-        c.synthesize(w.virtual[0], p=fvv.params(path=fvv.PATH_LEARNED))
-    assert e.value.code == fvv.FVV_E_UNSUPPORTED
+        c.synthesize(w.virtual[0], p=bad_path)
+    assert e.value.code == fvv.FVV_E_ARG
     bad_cam = sg.Camera(64, 48, -5.0, 5.0, 1.0, 1.0, np.eye(3), np.zeros(3))
     with pytest.raises(fvv.FvvError) as e:
         c.synthesize(bad_cam)
