@@ -63,6 +63,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2007_00558_amd.build` (no fallback path exists)")
+        # PyTorch ships its own HIP runtime; loading torch first makes the
+        # library bind to that same runtime (one HIP runtime per process,
+        # so torch's device buffers and streams are valid for the library)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P, I32, I64, U64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
         sig = {

@@ -56,7 +56,8 @@ def held_out_views(cams):
 
 class SceneSet:
     """One scene on the device: its frame set uploaded to the context, the
-    nine leave-one-out stacks and the ray-cast targets."""
+    nine leave-one-out stacks and the ray-cast targets (RGB8, padded rows
+    zero)."""
 
     def __init__(self, ctx: Context, seed: int, device="cuda"):
         import torch
@@ -69,7 +70,6 @@ class SceneSet:
         for c in self.cams:
             rgb, d = sgg.capture(self.scene, c, gen, noise_k=0.003, invalid_frac=0.10, device=device)
             frames.append((rgb.contiguous(), d.to(torch.int16).contiguous()))
-        self.frames = frames
         ctx.upload_mvd(frames, mem=MEM_DEVICE)
         self.views = held_out_views(self.cams)
         self.ps = [params(exclude=(j,)) for j in range(len(self.cams))]
@@ -77,13 +77,11 @@ class SceneSet:
         n = len(self.views)
         self.stack = torch.empty((n, self.Hp, self.Wp, 32), dtype=torch.int16, device=device)
         ctx.make_stack(self.views, self.ps, self.stack)
-        tgt = torch.zeros((n, self.Hp, self.Wp, 3), dtype=torch.float32, device=device)
-        self.target8 = []
+        self.target8 = torch.zeros((n, self.Hp, self.Wp, 3), dtype=torch.uint8, device=device)
         for j, v in enumerate(self.views):
             rgb, _ = sgg.render(self.scene, v, device)
-            self.target8.append(rgb)
-            tgt[j, :OUT_H, :OUT_W] = rgb.to(torch.float32) / 255.0
-        self.target = tgt
+            self.target8[j, :OUT_H, :OUT_W] = rgb
+        torch.cuda.synchronize()
 
 
 def psnr(a, b) -> float:
@@ -101,25 +99,39 @@ def evaluate(ctx: Context, seeds, device="cuda"):
         for j, v in enumerate(S.views):
             for name, path in (("plain", PATH_PLAIN), ("learned", PATH_LEARNED)):
                 out = torch.empty((OUT_H, OUT_W, 3), dtype=torch.uint8, device=device)
-                p = params(exclude=(j,), path=path)
-                ctx.synthesize(v, out, p)
-                res[name].append(psnr(out, S.target8[j]))
+                ctx.synthesize(v, out, params(exclude=(j,), path=path))
+                res[name].append(psnr(out, S.target8[j, :OUT_H, :OUT_W]))
         torch.cuda.synchronize()
     return {k: float(np.mean(v)) for k, v in res.items()}, res
 
 
-def train(ctx: Context, train_seeds, steps: int, lr: float = 1e-3, log_every: int = 50, log=print):
+def train(ctx: Context, train_seeds, steps: int, lr: float = 1e-3, log_every: int = 50, cache: int = 0,
+          log=print):
+    """Adam with a cosine learning-rate decay; one scene (nine held-out
+    views) per step.  Up to ``cache`` scenes stay on the device after their
+    first use (stacks + RGB8 targets, about 0.3 GB each)."""
     import torch
     losses = []
+    store = {}
+    tgt = None
     t0 = time.time()
     for it in range(steps):
-        S = SceneSet(ctx, train_seeds[it % len(train_seeds)])
+        seed = train_seeds[it % len(train_seeds)]
+        S = store.get(seed)
+        if S is None:
+            S = SceneSet(ctx, seed)
+            if len(store) < cache:
+                store[seed] = S
+        if tgt is None:
+            tgt = torch.empty(S.target8.shape, dtype=torch.float32, device=S.target8.device)
+        tgt.copy_(S.target8)
+        tgt.mul_(1.0 / 255.0)
         lr_t = lr * 0.5 * (1.0 + math.cos(math.pi * it / max(1, steps)))
-        loss = ctx.net_train_step(S.stack, S.target, len(S.views), S.Hp, S.Wp, OUT_H, lr=lr_t, apply=True,
+        loss = ctx.net_train_step(S.stack, tgt, len(S.views), S.Hp, S.Wp, OUT_H, lr=lr_t, apply=True,
                                   want_loss=(it % log_every == 0 or it == steps - 1))
         if loss is not None:
             losses.append((it, loss))
-            log(f"step {it} loss {loss:.5f} lr {lr_t:.2e} {time.time() - t0:.1f}s")
+            log(f"step {it} loss {loss:.5f} lr {lr_t:.2e} cached {len(store)} {time.time() - t0:.1f}s", flush=True)
     torch.cuda.synchronize()
     return losses
 
@@ -131,17 +143,20 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cache", type=int, default=0, help="training scenes kept on the device")
     ap.add_argument("--init", default="", help="float32 .npy parameters to start from")
     ap.add_argument("--save", default="", help="write the trained parameters here (.npy)")
     ap.add_argument("--json", default="", help="write the summary here")
     a = ap.parse_args(argv)
+    import torch
+    torch.cuda.init()
     ctx = Context(0)
     ctx.set_rig(rig())
     p0 = np.load(a.init) if a.init else init_params(a.seed)
     ctx.net_load(p0)
     test = list(range(TEST_SEED0, TEST_SEED0 + a.test_scenes))
     t0 = time.time()
-    losses = train(ctx, list(range(a.train_scenes)), a.steps, a.lr)
+    losses = train(ctx, list(range(a.train_scenes)), a.steps, a.lr, cache=a.cache)
     t_train = time.time() - t0
     if a.save:
         np.save(a.save, ctx.net_read())
