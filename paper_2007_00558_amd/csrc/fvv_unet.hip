@@ -20,6 +20,7 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 enum { TAP_CONV3 = 0, TAP_ONE = 1, TAP_FINE4 = 2 };
 enum { EPI_RELU_BF16 = 0, EPI_F32 = 1, EPI_CONVT_BF16 = 2 };
@@ -148,6 +149,124 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
                                          (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16));
             }
         }
+    }
+}
+
+// ---------------------------------------------------------------- 3x3 convolution, LDS-staged
+// 3x3 convolution (forward, or the data gradient with the mirrored weights)
+// as an implicit GEMM on v_mfma_f32_32x32x16_bf16.  A block computes 32*MT
+// output channels of a TH x 16 pixel patch of one image; for each 32-channel
+// chunk of the input it stages the (TH+2) x 18 input patch and the weight
+// slice (32*MT rows x 9 taps x 32 channels) in LDS once, and all nine taps
+// read them from there.  Four waves split the patch's rows; each wave holds
+// MT x NT tiles of 32 channels x 32 pixels (2 rows x 16 columns).
+// Per-pixel and per-row LDS strides are padded by 16 bytes so the 16-byte
+// fragment reads of 8 consecutive lanes fall in distinct banks.
+constexpr int C3_PXS = 80;             // bytes per staged pixel (32 bf16 + pad)
+constexpr int C3_RS = 9 * 64 + 16;     // bytes per staged weight row
+
+template <int MT, int TH>
+constexpr int c3_lds_bytes() { return (TH + 2) * 18 * C3_PXS + 32 * MT * C3_RS; }
+
+template <int MT, int TH, int EPI>
+__global__ void __launch_bounds__(256) k_conv3(const GemmArgs g)
+{
+    static_assert(TH % 8 == 0, "each wave takes TH/4 rows, two per 32-pixel tile");
+    constexpr int NT = TH / 8;         // 32-pixel tiles per wave (TH/4 rows of 16)
+    constexpr int PW = 18;             // staged patch width
+    constexpr int PH = TH + 2;
+    extern __shared__ __attribute__((aligned(16))) uint8_t c3_smem[];
+    uint8_t *patch = c3_smem;
+    uint8_t *wts = c3_smem + PH * PW * C3_PXS;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tiles_x = (g.W + 15) / 16, tiles_y = (g.H + TH - 1) / TH;
+    int t = blockIdx.x;
+    const int txi = t % tiles_x;
+    t /= tiles_x;
+    const int tyi = t % tiles_y;
+    const int b = t / tiles_y;
+    const int x0 = txi * 16, y0 = tyi * TH;
+    const int mbase = blockIdx.y * 32 * MT;
+    const int lc = lane & 31, lh = lane >> 5;
+    f32x16 acc[MT][NT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][n][r] = 0.f;
+    for (int c0 = 0; c0 < g.K; c0 += 32) {
+        // stage the input patch: PH x PW pixels x 4 quarters of 8 channels
+        for (int e = tid; e < PH * PW * 4; e += 256) {
+            const int px = e >> 2, q = e & 3;
+            const int pr = px / PW, pc = px - pr * PW;
+            const int gy = y0 - 1 + pr, gx = x0 - 1 + pc;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (gy >= 0 && gy < g.H && gx >= 0 && gx < g.W)
+                v = *(const uint4 *)(g.Bsrc + (((int64_t)b * g.H + gy) * g.W + gx) * g.b_cs + g.b_off + c0 + q * 8);
+            *(uint4 *)(patch + px * C3_PXS + q * 16) = v;
+        }
+        // stage the weights: 32*MT rows x 9 taps x 4 quarters
+        for (int e = tid; e < 32 * MT * 36; e += 256) {
+            const int r = e / 36, rem = e - r * 36, tap = rem >> 2, q = rem & 3;
+            const int m = mbase + r;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (m < g.M) v = *(const uint4 *)(g.A + ((int64_t)m * 9 + tap) * g.K + c0 + q * 8);
+            *(uint4 *)(wts + r * C3_RS + tap * 64 + q * 16) = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            const int dy = tap / 3, dx = tap - dy * 3;
+#pragma unroll
+            for (int kk = 0; kk < 2; ++kk) {
+                const int koff = (kk * 16 + 8 * lh) * 2;
+                bf16x8 af[MT], bfr[NT];
+#pragma unroll
+                for (int i = 0; i < MT; ++i)
+                    af[i] = __builtin_bit_cast(bf16x8, *(const uint4 *)(wts + (i * 32 + lc) * C3_RS + tap * 64 + koff));
+#pragma unroll
+                for (int n = 0; n < NT; ++n) {
+                    const int pr = wave * (TH / 4) + 2 * n + (lc >> 4) + dy;
+                    const int pc = (lc & 15) + dx;
+                    bfr[n] = __builtin_bit_cast(bf16x8, *(const uint4 *)(patch + (pr * PW + pc) * C3_PXS + koff));
+                }
+#pragma unroll
+                for (int i = 0; i < MT; ++i)
+#pragma unroll
+                    for (int n = 0; n < NT; ++n)
+                        acc[i][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[n], acc[i][n], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // epilogue: lane holds, for pixel lc of each tile, channels
+    // 8*j + 4*lh + {0..3} (j = 0..3) of each 32-row tile
+#pragma unroll
+    for (int n = 0; n < NT; ++n) {
+        const int py = y0 + wave * (TH / 4) + 2 * n + (lc >> 4), px = x0 + (lc & 15);
+        if (py >= g.H || px >= g.W) continue;
+        const int64_t pix = ((int64_t)b * g.H + py) * g.W + px;
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int m0 = mbase + i * 32 + 8 * j + 4 * lh;
+                if (m0 >= g.M) continue;
+                float v0 = acc[i][n][4 * j + 0], v1 = acc[i][n][4 * j + 1];
+                float v2 = acc[i][n][4 * j + 2], v3 = acc[i][n][4 * j + 3];
+                if (EPI == EPI_F32) {
+                    *(float4 *)((float *)g.out + pix * g.o_cs + g.o_off + m0) = make_float4(v0, v1, v2, v3);
+                } else {
+                    v0 = fmaxf(v0 + g.bias[m0 + 0], 0.f);
+                    v1 = fmaxf(v1 + g.bias[m0 + 1], 0.f);
+                    v2 = fmaxf(v2 + g.bias[m0 + 2], 0.f);
+                    v3 = fmaxf(v3 + g.bias[m0 + 3], 0.f);
+                    *(uint2 *)((uint16_t *)g.out + pix * g.o_cs + g.o_off + m0) =
+                        make_uint2((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16),
+                                   (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16));
+                }
+            }
     }
 }
 
@@ -747,6 +866,29 @@ hipError_t gemm(const GemmArgs &g, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int MT, int TH, int EPI>
+hipError_t conv3_launch(const GemmArgs &g, hipStream_t s)
+{
+    constexpr int lds = c3_lds_bytes<MT, TH>();
+    static_assert(lds <= 65536, "staged patch and weights must fit 64 KB");
+    const int tiles = ((g.W + 15) / 16) * ((g.H + TH - 1) / TH) * g.NB;
+    dim3 grid(tiles, (g.M + 32 * MT - 1) / (32 * MT));
+    hipLaunchKernelGGL((k_conv3<MT, TH, EPI>), grid, dim3(256), lds, s, g);
+    return hipGetLastError();
+}
+
+// 3x3 convolution shapes: 32 rows x 24-row patches for 32-channel outputs,
+// else 64 rows x 16-row patches (8-row patches on small grids so more
+// blocks exist)
+template <int EPI>
+hipError_t conv3(const GemmArgs &g, hipStream_t s)
+{
+    if (g.K % 32 != 0) return hipErrorInvalidValue;
+    if (g.M <= 32) return conv3_launch<1, 24, EPI>(g, s);
+    if ((int64_t)g.NB * g.H * g.W >= 65536) return conv3_launch<2, 16, EPI>(g, s);
+    return conv3_launch<2, 8, EPI>(g, s);
+}
+
 // 3x3 conv + bias + ReLU into (out, o_cs, o_off)
 hipError_t conv_fwd(unet_state *n, int li, const uint16_t *in, int i_cs, int i_off, uint16_t *out, int o_cs, int o_off,
                     int NB, int H, int W, hipStream_t s)
@@ -766,8 +908,7 @@ hipError_t conv_fwd(unet_state *n, int li, const uint16_t *in, int i_cs, int i_o
     g.W = W;
     g.K = l.cin_pad;
     g.M = l.cout;
-    if (l.cout >= 64) return gemm<4, 1, TAP_CONV3, EPI_RELU_BF16>(g, s);
-    return gemm<2, 2, TAP_CONV3, EPI_RELU_BF16>(g, s);
+    return conv3<EPI_RELU_BF16>(g, s);
 }
 
 hipError_t convT_fwd(unet_state *n, int li, const uint16_t *in, int i_cs, int NB, int H, int W, uint16_t *out,
@@ -887,8 +1028,7 @@ hipError_t conv_dgrad(unet_state *n, unet_act *a, int li, float *out, int NB, in
     g.W = W;
     g.K = l.cout;
     g.M = l.cin;
-    if (l.cin >= 64) return gemm<4, 1, TAP_CONV3, EPI_F32>(g, s);
-    return gemm<2, 2, TAP_CONV3, EPI_F32>(g, s);
+    return conv3<EPI_F32>(g, s);
 }
 
 // data gradient of a 2x2 transposed conv: a->G on the fine grid -> fp32 [P_coarse][cin]
