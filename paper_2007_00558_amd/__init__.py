@@ -298,7 +298,7 @@ class Context:
                          stream=None):
         p = p or params()
         n = len(virts)
-        arr = (Camera * n)(*[camera(v) for v in virts])
+        arr = virts if isinstance(virts, C.Array) else (Camera * n)(*[camera(v) for v in virts])
         ptrs = (C.c_void_p * n)(*[_addr(o) for o in outs])
         dev = not isinstance(outs[0], np.ndarray)
         pitches = np.array([o.stride(0) if dev else o.strides[0] for o in outs], np.int64)

@@ -62,16 +62,18 @@ struct Footprint {
 // Forward warp of source pixel (i, j) at depth z: the output pixel centres
 // x with u - mx/2 <= x < u + mx/2 (rows likewise), mx = clamp(sx z / p2, 1,
 // max_fp), clipped to the output image; key = depth bits | camera | pixel.
+// In float32 with one division: r = 1/p2, u = p0 r, v = p1 r, mx = (sx z) r.
 __device__ __forceinline__ bool splat_point(const fvv_src_desc &s, int W, int H, float max_fp, int i, int j,
                                             float z, Footprint &f)
 {
     float q0, q1, q2;
     project(s.A, s.a, (float)i, (float)j, z, q0, q1, q2);
     if (!(q2 > FVV_ZCLIP)) return false;
-    const float u = __fdiv_rn(q0, q2), v = __fdiv_rn(q1, q2);
+    const float r = __fdiv_rn(1.0f, q2);   // one correctly rounded division per point
+    const float u = __fmul_rn(q0, r), v = __fmul_rn(q1, r);
     if (!isfinite(u) || !isfinite(v)) return false;
-    float mx = __fdiv_rn(__fmul_rn(s.sx, z), q2);
-    float my = __fdiv_rn(__fmul_rn(s.sy, z), q2);
+    float mx = __fmul_rn(__fmul_rn(s.sx, z), r);
+    float my = __fmul_rn(__fmul_rn(s.sy, z), r);
     mx = fminf(fmaxf(mx, 1.0f), max_fp);
     my = fminf(fmaxf(my, 1.0f), max_fp);
     const float hx = __fmul_rn(0.5f, mx), hy = __fmul_rn(0.5f, my);
@@ -259,7 +261,8 @@ __device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int x, int 
         float q0, q1, q2;
         project(s.B, s.b, (float)x, (float)y, zf, q0, q1, q2);
         if (!(q2 > FVV_ZCLIP)) continue;
-        const float u = __fdiv_rn(q0, q2), v = __fdiv_rn(q1, q2);
+        const float r = __fdiv_rn(1.0f, q2);
+        const float u = __fmul_rn(q0, r), v = __fmul_rn(q1, r);
         if (!(u >= -0.5f && u <= __fsub_rn((float)s.W, 0.5f))) continue;
         if (!(v >= -0.5f && v <= __fsub_rn((float)s.H, 0.5f))) continue;
         const float fi0 = floorf(u), fj0 = floorf(v);
@@ -314,7 +317,8 @@ __device__ __forceinline__ void stack_pixel(const fvv_view_desc &vd, int x, int 
             float q0, q1, q2;
             project(s.B, s.b, (float)x, (float)y, zf, q0, q1, q2);
             if (!(q2 > FVV_ZCLIP)) continue;
-            const float u = __fdiv_rn(q0, q2), v = __fdiv_rn(q1, q2);
+            const float r = __fdiv_rn(1.0f, q2);
+            const float u = __fmul_rn(q0, r), v = __fmul_rn(q1, r);
             if (!(u >= -0.5f && u <= __fsub_rn((float)s.W, 0.5f))) continue;
             if (!(v >= -0.5f && v <= __fsub_rn((float)s.H, 0.5f))) continue;
             const float fi0 = floorf(u), fj0 = floorf(v);
@@ -409,35 +413,77 @@ __global__ void __launch_bounds__(256) k_tile(const fvv_view_desc *__restrict__ 
     // ---- S1: splat every binned source block into the window; each wave
     // takes its own list entries (one 8x8 source block = one wave)
     const bool scan_all = n_entries > vd.tile_cap;
-    const int end = scan_all ? vd.K * vd.blk_stride : n_entries;
     const int lane = t & 63, wave = t >> 6;
     const int si = lane & (FVV_SBLK - 1), sj = lane / FVV_SBLK;
-    const int32_t *lst = vd.list + (int64_t)tile * vd.tile_cap;
-    for (int e = wave; e < end; e += 4) {
-        int k, blk;
-        if (!scan_all) {
-            const int ent = lst[e];
-            k = ent >> 24;
-            blk = ent & 0xFFFFFF;
-        } else {
-            k = e / vd.blk_stride;
-            blk = e - k * vd.blk_stride;
-            if (blk >= vd.src[k].nblk) continue;
-            const int4 r = vd.bbox[e];
-            if (!(r.x <= tx && tx <= r.y && r.z <= ty && ty <= r.w)) continue;
-        }
-        const fvv_src_desc &s = vd.src[k];
+    // depth bits of this lane's pixel of block `ent` (FVV_NO_DEPTH outside)
+    auto block_depth = [&](int ent) -> uint32_t {
+        const fvv_src_desc &s = vd.src[ent >> 24];
+        const int blk = ent & 0xFFFFFF;
         const int by = blk / s.nbx, bx = blk - by * s.nbx;
         const int i = bx * FVV_SBLK + si, j = by * FVV_SBLK + sj;
-        if (i >= s.W || j >= s.H) continue;
-        const uint32_t zb = f2u(s.depth[(int64_t)j * s.W + i]);
-        if (zb == FVV_NO_DEPTH) continue;
+        if (i >= s.W || j >= s.H) return FVV_NO_DEPTH;
+        return f2u(s.depth[(int64_t)j * s.W + i]);
+    };
+    auto splat_entry = [&](int ent, uint32_t zb) {
+        if (zb == FVV_NO_DEPTH) return;
+        const fvv_src_desc &s = vd.src[ent >> 24];
+        const int blk = ent & 0xFFFFFF;
+        const int by = blk / s.nbx, bx = blk - by * s.nbx;
+        const int i = bx * FVV_SBLK + si, j = by * FVV_SBLK + sj;
         Footprint f;
-        if (!splat_point(s, W, H, vd.max_fp, i, j, u2f(zb), f)) continue;
+        if (!splat_point(s, W, H, vd.max_fp, i, j, u2f(zb), f)) return;
         const int xa = max(f.x0, WX0), xb = min(f.x1, WX0 + WN - 1);
         const int ya = max(f.y0, WY0), yb = min(f.y1, WY0 + WN - 1);
         for (int y = ya; y <= yb; ++y)
             for (int x = xa; x <= xb; ++x) atomicMin(&zk[(y - WY0) * WN + (x - WX0)], f.key);
+    };
+    if (!scan_all) {
+        // The wave's entries are e = wave + 4 q.  They are read 64 at a time
+        // (one per lane) and the depths of the next two entries are in
+        // flight while the current one is splatted, so the dependent loads
+        // of consecutive entries overlap instead of queueing.
+        const int32_t *lst = vd.list + (int64_t)tile * vd.tile_cap;
+        const int nq = n_entries > wave ? (n_entries - wave + 3) / 4 : 0;
+        int base = 0;
+        int ents = lane < nq ? lst[wave + 4 * lane] : 0;
+        auto entry = [&](int q) -> int {
+            if (q - base >= 64) {
+                base = q;
+                ents = q + lane < nq ? lst[wave + 4 * (q + lane)] : 0;
+            }
+            return __shfl(ents, q - base, 64);
+        };
+        int e0 = 0, e1 = 0;
+        uint32_t z0 = FVV_NO_DEPTH, z1 = FVV_NO_DEPTH;
+        if (nq > 0) {
+            e0 = entry(0);
+            z0 = block_depth(e0);
+        }
+        if (nq > 1) {
+            e1 = entry(1);
+            z1 = block_depth(e1);
+        }
+        for (int q = 0; q < nq; ++q) {
+            const int ec = e0;
+            const uint32_t zc = z0;
+            e0 = e1;
+            z0 = z1;
+            if (q + 2 < nq) {
+                e1 = entry(q + 2);
+                z1 = block_depth(e1);
+            }
+            splat_entry(ec, zc);
+        }
+    } else {
+        // more entries than the list holds: test every block's tile range
+        for (int e = wave; e < vd.K * vd.blk_stride; e += 4) {
+            const int k = e / vd.blk_stride, blk = e - k * vd.blk_stride;
+            if (blk >= vd.src[k].nblk) continue;
+            const int4 r = vd.bbox[e];
+            if (!(r.x <= tx && tx <= r.y && r.z <= ty && ty <= r.w)) continue;
+            const int ent = (k << 24) | blk;
+            splat_entry(ent, block_depth(ent));
+        }
     }
     __syncthreads();
 
