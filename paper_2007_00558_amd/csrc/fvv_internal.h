@@ -18,6 +18,7 @@
 #define FVV_SBLK 8                  // source block edge (pixels) of the binning: one wave per block
 #define FVV_TILE_CAP_MIN 128        // minimum bin-list entries per output tile
 #define FVV_MAX_RIG 32              // cameras in a rig
+#define FVV_XCDS 8                  // XCDs of an MI355X: workgroup i runs on XCD i mod 8
 
 // One selected source camera of one view.  The float32 pair matrices are
 // computed on the host in double and rounded once (Section VI pinhole warp):

@@ -390,10 +390,21 @@ __device__ __forceinline__ void offer(Cand &b, float z, int dist, int idx)
 // STACK: views may carry a learned-path stack (a separate instantiation, so
 // the plain kernel keeps its register budget and occupancy).
 template <bool STACK>
-__global__ void __launch_bounds__(256) k_tile(const fvv_view_desc *__restrict__ views)
+__global__ void __launch_bounds__(256) k_tile(const fvv_view_desc *__restrict__ views, int mtx, int mty, int n_views)
 {
-    const fvv_view_desc &vd = views[blockIdx.z];
-    const int tx = blockIdx.x, ty = blockIdx.y;
+    // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin, so
+    // dispatch index b runs on XCD b % 8.  Each XCD takes a contiguous
+    // eighth of the (view, tile) sequence in raster order; neighbouring
+    // tiles, which splat many of the same source blocks, then share one L2.
+    const int per_view = mtx * mty;
+    const int total = per_view * n_views;
+    const int per_xcd = (total + FVV_XCDS - 1) / FVV_XCDS;
+    const int b = blockIdx.x;
+    const int w = (b % FVV_XCDS) * per_xcd + b / FVV_XCDS;
+    if (w >= total) return;
+    const int view = w / per_view, rem = w - view * per_view;
+    const int ty = rem / mtx, tx = rem - ty * mtx;
+    const fvv_view_desc &vd = views[view];
     if (tx >= vd.ntx || ty >= vd.nty) return;
     const int W = vd.W, H = vd.H;
     const int tile = ty * vd.ntx + tx;
@@ -726,10 +737,15 @@ hipError_t fvv_launch_synthesis(const fvv_view_desc *h_views, fvv_view_desc *d_v
     hipLaunchKernelGGL(k_bin, dim3((b.max_blocks + 3) / 4, b.max_k, b.n_views), dim3(256), 0, s, d_views);
     fvv_prof_end(prof, s, FVV_ST_BIN, e0);
     fvv_prof_begin(prof, s, e0);
-    if (b.any_stack)
-        hipLaunchKernelGGL(k_tile<true>, dim3(b.max_tiles_x, b.max_tiles_y, b.n_views), dim3(256), 0, s, d_views);
-    else
-        hipLaunchKernelGGL(k_tile<false>, dim3(b.max_tiles_x, b.max_tiles_y, b.n_views), dim3(256), 0, s, d_views);
+    {
+        // 1-D dispatch of every (view, tile), rounded up to whole XCD rounds
+        const int total = b.max_tiles_x * b.max_tiles_y * b.n_views;
+        const dim3 grid((total + FVV_XCDS - 1) / FVV_XCDS * FVV_XCDS);
+        if (b.any_stack)
+            hipLaunchKernelGGL(k_tile<true>, grid, dim3(256), 0, s, d_views, b.max_tiles_x, b.max_tiles_y, b.n_views);
+        else
+            hipLaunchKernelGGL(k_tile<false>, grid, dim3(256), 0, s, d_views, b.max_tiles_x, b.max_tiles_y, b.n_views);
+    }
     fvv_prof_end(prof, s, FVV_ST_TILE, e0);
     if (b.fill_bg) {
         fvv_prof_begin(prof, s, e0);
