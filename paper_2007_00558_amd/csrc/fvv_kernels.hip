@@ -625,80 +625,88 @@ __global__ void __launch_bounds__(256) k_tile(const fvv_view_desc *__restrict__ 
 // A fixed grid walks the batch's list of tiles with open holes.
 __global__ void __launch_bounds__(256) k_fill_open(const fvv_view_desc *__restrict__ views)
 {
+    // the tile's slots are staged in LDS: the scans inside the tile (most of
+    // the work) then cost no dependent global loads
+    __shared__ uint32_t s_slot[T * T];
     const int n_open = *views[0].open_count;
     for (int item = blockIdx.x; item < n_open; item += gridDim.x) {
         const int2 vt = views[0].open_list[item];
         const fvv_view_desc &vd = views[vt.x];
         const int tile = vt.y;
         const int ty = tile / vd.ntx, tx = tile - ty * vd.ntx;
-        const int W = vd.W, H = vd.H;
+        const int W = vd.W;
         const int X0 = tx * T, Y0 = ty * T;
-        const int tw = min(T, W - X0), th = min(T, H - Y0);
+        const int tw = min(T, W - X0), th = min(T, vd.H - Y0);
         const uint32_t *slot = vd.slot;
+        __syncthreads();   // the previous item's readers are done
         for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
             const int ly = e / T, lx = e - ly * T;
-            if (lx >= tw || ly >= th) continue;
+            s_slot[e] = (lx < tw && ly < th) ? slot[(int64_t)(Y0 + ly) * W + X0 + lx] : FVV_HOLE;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
+            const int ly = e / T, lx = e - ly * T;
+            if (lx >= tw || ly >= th || s_slot[e] != FVV_HOLE_OPEN) continue;
             const int x = X0 + lx, y = Y0 + ly;
-            if (slot[(int64_t)y * W + x] != FVV_HOLE_OPEN) continue;
             const int64_t row = (int64_t)y * W;
+            // candidates carry image indices y*W + x; depths from the slots
+            Cand c{0.f, 0, -1};
             // left
-            int xl = x - 1;
-            while (xl >= X0 && (slot[row + xl] & FVV_HOLE)) --xl;
-            if (xl < X0) {
-                xl = -1;
+            int l = lx - 1;
+            while (l >= 0 && (s_slot[ly * T + l] & FVV_HOLE)) --l;
+            if (l >= 0) {
+                offer(c, u2f(s_slot[ly * T + l]), lx - l, y * W + X0 + l);
+            } else {
                 for (int t2 = tx - 1; t2 >= 0; --t2) {
-                    const int l = vd.rowsum[(int64_t)(ty * vd.ntx + t2) * T + ly].y;
-                    if (l >= 0) {
-                        xl = l;
+                    const int xl = vd.rowsum[(int64_t)(ty * vd.ntx + t2) * T + ly].y;
+                    if (xl >= 0) {
+                        offer(c, u2f(slot[row + xl]), x - xl, y * W + xl);
                         break;
                     }
                 }
             }
             // right
-            int xr = x + 1;
-            while (xr < X0 + tw && (slot[row + xr] & FVV_HOLE)) ++xr;
-            if (xr >= X0 + tw) {
-                xr = -1;
+            int r = lx + 1;
+            while (r < tw && (s_slot[ly * T + r] & FVV_HOLE)) ++r;
+            if (r < tw) {
+                offer(c, u2f(s_slot[ly * T + r]), r - lx, y * W + X0 + r);
+            } else {
                 for (int t2 = tx + 1; t2 < vd.ntx; ++t2) {
-                    const int f = vd.rowsum[(int64_t)(ty * vd.ntx + t2) * T + ly].x;
-                    if (f >= 0) {
-                        xr = f;
+                    const int xr = vd.rowsum[(int64_t)(ty * vd.ntx + t2) * T + ly].x;
+                    if (xr >= 0) {
+                        offer(c, u2f(slot[row + xr]), xr - x, y * W + xr);
                         break;
                     }
                 }
             }
-            // candidates carry image indices y*W + x
-            Cand c{0.f, 0, -1};
-            if (xl >= 0) offer(c, u2f(slot[row + xl]), x - xl, y * W + xl);
-            if (xr >= 0) offer(c, u2f(slot[row + xr]), xr - x, y * W + xr);
             // up
-            int yu = y - 1;
-            while (yu >= Y0 && (slot[(int64_t)yu * W + x] & FVV_HOLE)) --yu;
-            if (yu < Y0) {
-                yu = -1;
+            int u = ly - 1;
+            while (u >= 0 && (s_slot[u * T + lx] & FVV_HOLE)) --u;
+            if (u >= 0) {
+                offer(c, u2f(s_slot[u * T + lx]), ly - u, (Y0 + u) * W + x);
+            } else {
                 for (int t2 = ty - 1; t2 >= 0; --t2) {
-                    const int l = vd.colsum[(int64_t)(t2 * vd.ntx + tx) * T + lx].y;
-                    if (l >= 0) {
-                        yu = l;
+                    const int yu = vd.colsum[(int64_t)(t2 * vd.ntx + tx) * T + lx].y;
+                    if (yu >= 0) {
+                        offer(c, u2f(slot[(int64_t)yu * W + x]), y - yu, yu * W + x);
                         break;
                     }
                 }
             }
-            if (yu >= 0) offer(c, u2f(slot[(int64_t)yu * W + x]), y - yu, yu * W + x);
             // down
-            int yd = y + 1;
-            while (yd < Y0 + th && (slot[(int64_t)yd * W + x] & FVV_HOLE)) ++yd;
-            if (yd >= Y0 + th) {
-                yd = -1;
+            int d = ly + 1;
+            while (d < th && (s_slot[d * T + lx] & FVV_HOLE)) ++d;
+            if (d < th) {
+                offer(c, u2f(s_slot[d * T + lx]), d - ly, (Y0 + d) * W + x);
+            } else {
                 for (int t2 = ty + 1; t2 < vd.nty; ++t2) {
-                    const int f = vd.colsum[(int64_t)(t2 * vd.ntx + tx) * T + lx].x;
-                    if (f >= 0) {
-                        yd = f;
+                    const int yd = vd.colsum[(int64_t)(t2 * vd.ntx + tx) * T + lx].x;
+                    if (yd >= 0) {
+                        offer(c, u2f(slot[(int64_t)yd * W + x]), yd - y, yd * W + x);
                         break;
                     }
                 }
             }
-            if (yd >= 0) offer(c, u2f(slot[(int64_t)yd * W + x]), yd - y, yd * W + x);
             uint32_t col = 0;
             if (c.idx >= 0) {
                 const int cy = c.idx / W, cx = c.idx - cy * W;
