@@ -222,6 +222,24 @@ def run_learned(fvv, torch, w, ctx, stream, args) -> dict:
         ctx.synthesize(v, o, p=p, stream=stream)
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t) * 1e3)
+    # one training step on a batch of stacks of the same views (targets: the
+    # plain renders; lr 0 keeps the weights) -> samples/s
+    nb = min(4, len(virts))
+    Hp, Wp = fvv.pad8(540), fvv.pad8(960)
+    stack = torch.empty((nb, Hp, Wp, 32), dtype=torch.int16, device=dev)
+    ctx.make_stack(virts[:nb], [fvv.params()] * nb, stack, stream=stream)
+    target = torch.zeros((nb, Hp, Wp, 3), dtype=torch.float32, device=dev)
+    for q in range(nb):
+        target[q, :540] = outs[q].to(torch.float32) / 255.0
+    ctx.net_train_step(stack, target, nb, Hp, Wp, 540, lr=0.0, want_loss=False, stream=stream)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(reps):
+        ctx.net_train_step(stack, target, nb, Hp, Wp, 540, lr=0.0, want_loss=False, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_train = e0.elapsed_time(e1) / reps
+    train_tflops = 3.0 * fl * nb / (ms_train * 1e-3) / 1e12
     npx = len(virts) * 960 * 540
     return {"config": "learned blend/inpaint, 9 cams 1280x720 -> 960x540 (stack 960x544x16 bf16), K=3",
             "views": len(virts), "ms_per_batch": round(ms, 3), "mpix_s": round(npx / (ms * 1e-3) / 1e6, 1),
@@ -231,7 +249,10 @@ def run_learned(fvv, torch, w, ctx, stream, args) -> dict:
                          "achieved": round(tflops, 1), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": round(tflops / BF16_PEAK_TFLOPS, 4), "traffic": None},
             "single_view_p50_ms": round(float(np.percentile(lat, 50)), 3),
-            "single_view_p99_ms": round(float(np.percentile(lat, 99)), 3)}
+            "single_view_p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "train_step_ms": round(ms_train, 3), "train_batch": nb,
+            "train_samples_s": round(nb / (ms_train * 1e-3), 1),
+            "train_tflops_approx": round(train_tflops, 1)}
 
 
 def main():

@@ -361,6 +361,74 @@ __global__ void __launch_bounds__(256) k_wgrad(const WgradArgs a)
         }
 }
 
+// Weight gradient of a 3x3 convolution with all nine taps in one workgroup:
+// the 32-pixel gradient tile is staged once per step and reused by the
+// nine shifted input tiles (9 x 2 MFMAs per wave per step).  grid: x = input
+// channel block of 32, y = 64-row block, z = pixel chunk.
+__global__ void __launch_bounds__(256) k_wgrad3(const WgradArgs a)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t Gt[64 * WG_LD];
+    __shared__ __attribute__((aligned(16))) uint16_t Xt[9 * 32 * WG_LD];
+    const int cb = blockIdx.x;
+    const int mb = blockIdx.y * 64;
+    const int HW = a.H * a.W, P = a.NB * HW;
+    const int p_begin = blockIdx.z * a.chunk, p_end = min(P, p_begin + a.chunk);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    f32x4 acc[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t][0] = acc[t][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int p0 = p_begin; p0 < p_end; p0 += 32) {
+        {   // gradient tile: 32 pixels x 64 rows
+            const int pl = tid >> 3, rg = tid & 7;
+            const int p = p0 + pl, m = mb + rg * 8;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (p < p_end && m < a.M) v = *(const uint4 *)(a.G + (int64_t)p * a.g_cs + a.g_off + m);
+            const uint16_t *h = (const uint16_t *)&v;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) Gt[(rg * 8 + j) * WG_LD + pl] = h[j];
+        }
+        // nine input tiles: 32 pixels x 32 channels each, shifted by the tap
+        for (int e = tid; e < 9 * 128; e += 256) {
+            const int t = e >> 7, rem = e & 127, pl = rem >> 2, cg = rem & 3;
+            const int p = p0 + pl;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (p < p_end) {
+                const int b = p / HW, r = p - b * HW, y = r / a.W, x = r - y * a.W;
+                const int sy = y + t / 3 - 1, sx = x + t % 3 - 1;
+                if (sy >= 0 && sx >= 0 && sy < a.H && sx < a.W)
+                    v = *(const uint4 *)(a.X + (((int64_t)b * a.H + sy) * a.W + sx) * a.x_cs + a.x_off + cb * 32 +
+                                         cg * 8);
+            }
+            const uint16_t *h = (const uint16_t *)&v;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) Xt[(t * 32 + cg * 8 + j) * WG_LD + pl] = h[j];
+        }
+        __syncthreads();
+        const bf16x8 af = __builtin_bit_cast(bf16x8, *(const uint4 *)&Gt[(wave * 16 + lr) * WG_LD + 8 * lg]);
+#pragma unroll
+        for (int t = 0; t < 9; ++t)
+#pragma unroll
+            for (int n = 0; n < 2; ++n) {
+                const bf16x8 bf =
+                    __builtin_bit_cast(bf16x8, *(const uint4 *)&Xt[(t * 32 + n * 16 + lr) * WG_LD + 8 * lg]);
+                acc[t][n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, acc[t][n], 0, 0, 0);
+            }
+        __syncthreads();
+    }
+    const int cols = 9 * a.K;
+    float *out = a.part + (int64_t)blockIdx.z * a.M * cols;
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int m = mb + wave * 16 + 4 * lg + r;
+                if (m < a.M) out[(int64_t)m * cols + t * a.K + cb * 32 + n * 16 + lr] = acc[t][n][r];
+            }
+}
+
 // Sum the partials in chunk order into the canonical gradient (rows x taps x
 // cin, dropping padded input channels).
 __global__ void __launch_bounds__(256) k_wgrad_reduce(const float *__restrict__ part, int chunks, int M, int taps,
@@ -477,13 +545,22 @@ __global__ void __launch_bounds__(256) k_mask_round(const float *g, int g_cs, in
     }
 }
 
+// Column sums of a rows x n matrix of partials: one workgroup per column,
+// thread t adds rows t, t+256, ... in order, then a fixed tree combines the
+// 256 sums -- the same result on every run.
 __global__ void __launch_bounds__(256) k_reduce_rows(const float *part, int rows, int n, float *out)
 {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    float s = 0.f;
-    for (int r = 0; r < rows; ++r) s += part[(int64_t)r * n + e];
-    out[e] = s;
+    __shared__ float red[256];
+    const int col = blockIdx.x;
+    float acc = 0.f;
+    for (int r = threadIdx.x; r < rows; r += 256) acc += part[(int64_t)r * n + col];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[col] = red[0];
 }
 
 // Head: 1x1 conv 32->3 + bias, sigmoid.  mode 0: inference (s and/or RGB8
@@ -677,7 +754,24 @@ const Layers &layers()
 }
 
 // chunking of a weight-gradient contraction over P pixels
-int wgrad_chunk(size_t P) { return (int)std::max<size_t>(256, ((P / 128) + 31) / 32 * 32); }
+// Pixel chunking of a weight-gradient contraction over P pixels for a
+// layer whose grid has `wgs` workgroups per chunk: about 1024 workgroups in
+// all, chunks of at least 256 pixels (multiples of 32).
+int wgrad_chunks(size_t P, int wgs)
+{
+    const size_t want = std::max<size_t>(1, 1024 / (size_t)std::max(1, wgs));
+    return (int)std::max<size_t>(1, std::min<size_t>((P + 255) / 256, want));
+}
+int wgrad_chunk(size_t P, int wgs)
+{
+    const size_t c = (P + wgrad_chunks(P, wgs) - 1) / wgrad_chunks(P, wgs);
+    return (int)((c + 31) / 32 * 32);
+}
+int wgrad_wgs(const unet_layer &l)
+{
+    const int mblk = (l.cout + 63) / 64, kblk = l.cin_pad / 32;
+    return l.kind == 0 ? mblk * kblk : mblk * kblk * l.taps;
+}
 
 size_t partial_floats(size_t P0)
 {
@@ -686,9 +780,10 @@ size_t partial_floats(size_t P0)
     for (int i = 0; i < kNL; ++i) {
         const unet_layer &l = T.L[i];
         if (l.kind == 2) continue;
-        // any contraction over at most Pk pixels has <= min(ceil(Pk / 256), 128) chunks
+        // a contraction over P <= Pk pixels has ceil(P / chunk) <= wgrad_chunks(P)
+        // <= wgrad_chunks(Pk) chunks (chunk >= P / wgrad_chunks(P), monotone in P)
         const size_t Pk = P0 >> (2 * kSumLevel[i]);
-        const size_t chunks = std::min<size_t>((Pk + 255) / 256, 128);
+        const size_t chunks = (size_t)wgrad_chunks(Pk, wgrad_wgs(l));
         m = std::max(m, chunks * l.cout * l.taps * l.cin_pad);
     }
     return m;
@@ -977,7 +1072,7 @@ hipError_t mask_round(unet_state *n, unet_act *a, const float *g, int g_cs, int 
     hipLaunchKernelGGL(k_mask_round, dim3(wgs), dim3(256), 0, s, g, g_cs, g_off, act, a_cs, a_off, relu ? 1 : 0, a->G,
                        C, P, a->part);
     NCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_reduce_rows, dim3((C + 255) / 256), dim3(256), 0, s, (const float *)a->part, wgs, C,
+    hipLaunchKernelGGL(k_reduce_rows, dim3(C), dim3(256), 0, s, (const float *)a->part, wgs, C,
                        n->g + layers().L[li].b_off);
     return hipGetLastError();
 }
@@ -989,7 +1084,7 @@ hipError_t wgrad(unet_state *n, unet_act *a, int li, const uint16_t *X, int x_cs
 {
     const unet_layer &l = layers().L[li];
     const int P = NB * H * W;
-    const int chunk = wgrad_chunk((size_t)P);
+    const int chunk = wgrad_chunk((size_t)P, wgrad_wgs(l));
     const int chunks = (P + chunk - 1) / chunk;
     WgradArgs w{};
     w.G = a->G;
@@ -1004,8 +1099,13 @@ hipError_t wgrad(unet_state *n, unet_act *a, int li, const uint16_t *X, int x_cs
     w.K = l.cin_pad;
     w.chunk = chunk;
     constexpr int taps = TAP == TAP_CONV3 ? 9 : (TAP == TAP_FINE4 ? 4 : 1);
-    dim3 grid(taps * (l.cin_pad / 32), (l.cout + 63) / 64, chunks);
-    hipLaunchKernelGGL(k_wgrad<TAP>, grid, dim3(256), 0, s, w);
+    if (TAP == TAP_CONV3) {
+        dim3 grid(l.cin_pad / 32, (l.cout + 63) / 64, chunks);
+        hipLaunchKernelGGL(k_wgrad3, grid, dim3(256), 0, s, w);
+    } else {
+        dim3 grid(taps * (l.cin_pad / 32), (l.cout + 63) / 64, chunks);
+        hipLaunchKernelGGL(k_wgrad<TAP>, grid, dim3(256), 0, s, w);
+    }
     NCHK(hipGetLastError());
     const int nel = l.cout * taps * l.cin;
     hipLaunchKernelGGL(k_wgrad_reduce, dim3((nel + 255) / 256), dim3(256), 0, s, (const float *)a->part, chunks,
@@ -1206,7 +1306,7 @@ hipError_t unet_train(unet_state *n, unet_act *a, const uint16_t *stack, const f
     const int hwg = (P0 + 255) / 256;
     hipLaunchKernelGGL(k_head, dim3(hwg), dim3(256), 0, s, h, 1);
     NCHK(hipGetLastError());
-    hipLaunchKernelGGL(k_reduce_rows, dim3(1), dim3(256), 0, s, (const float *)a->head_part, hwg, 100, a->part);
+    hipLaunchKernelGGL(k_reduce_rows, dim3(100), dim3(256), 0, s, (const float *)a->head_part, hwg, 100, a->part);
     NCHK(hipGetLastError());
     NCHK(hipMemcpyAsync(n->g + T.L[L_HEAD].w_off, a->part, 96 * 4, hipMemcpyDeviceToDevice, s));
     NCHK(hipMemcpyAsync(n->g + T.L[L_HEAD].b_off, a->part + 96, 3 * 4, hipMemcpyDeviceToDevice, s));
