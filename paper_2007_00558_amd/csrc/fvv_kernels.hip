@@ -390,7 +390,7 @@ __device__ __forceinline__ void offer(Cand &b, float z, int dist, int idx)
 // STACK: views may carry a learned-path stack (a separate instantiation, so
 // the plain kernel keeps its register budget and occupancy).
 template <bool STACK>
-__global__ void __launch_bounds__(256) k_tile(const fvv_view_desc *__restrict__ views, int mtx, int mty, int n_views)
+__device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ views, int mtx, int mty, int n_views)
 {
     // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin, so
     // dispatch index b runs on XCD b % 8.  Each XCD takes a contiguous
@@ -619,6 +619,20 @@ __global__ void __launch_bounds__(256) k_tile(const fvv_view_desc *__restrict__ 
     }
 }
 
+// The plain kernel is held to 64 VGPRs (8 waves per SIMD: it is latency-
+// bound, so occupancy pays); the stack variant keeps its registers.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
+k_tile_plain(const fvv_view_desc *__restrict__ views, int mtx, int mty, int n_views)
+{
+    tile_body<false>(views, mtx, mty, n_views);
+}
+
+__global__ void __launch_bounds__(256) k_tile_stack(const fvv_view_desc *__restrict__ views, int mtx, int mty,
+                                                    int n_views)
+{
+    tile_body<true>(views, mtx, mty, n_views);
+}
+
 // ---------------------------------------------------------------- open holes
 // Holes whose nearest covered neighbour in some direction lies outside their
 // tile: scan the tile, then walk the per-tile summaries of the row or column.
@@ -750,9 +764,9 @@ hipError_t fvv_launch_synthesis(const fvv_view_desc *h_views, fvv_view_desc *d_v
         const int total = b.max_tiles_x * b.max_tiles_y * b.n_views;
         const dim3 grid((total + FVV_XCDS - 1) / FVV_XCDS * FVV_XCDS);
         if (b.any_stack)
-            hipLaunchKernelGGL(k_tile<true>, grid, dim3(256), 0, s, d_views, b.max_tiles_x, b.max_tiles_y, b.n_views);
+            hipLaunchKernelGGL(k_tile_stack, grid, dim3(256), 0, s, d_views, b.max_tiles_x, b.max_tiles_y, b.n_views);
         else
-            hipLaunchKernelGGL(k_tile<false>, grid, dim3(256), 0, s, d_views, b.max_tiles_x, b.max_tiles_y, b.n_views);
+            hipLaunchKernelGGL(k_tile_plain, grid, dim3(256), 0, s, d_views, b.max_tiles_x, b.max_tiles_y, b.n_views);
     }
     fvv_prof_end(prof, s, FVV_ST_TILE, e0);
     if (b.fill_bg) {
