@@ -196,3 +196,34 @@ def test_stop_drains_pending(fvv):
     with pytest.raises(fvv.FvvError):
         srv.ctx._check(ctx._L.fvv_server_stop(ctx._h))
     ctx.close()
+
+
+def test_learned_requests_in_mix_equal_alone(fvv):
+    """Learned-path requests served in a mix of sizes and paths equal the
+    same requests rendered alone (the network runs per view, so a result does
+    not depend on what else shares its step)."""
+    import torch
+    from paper_2007_00558_amd import learned as L
+    say("[gpu] serving learned mix vs alone")
+    w = sg.config_small(16, n_cams=5, w=120, h=80)
+    ctx = fvv.Context(0)
+    ctx.set_rig(w.rig)
+    ctx.upload_mvd(w.frames)
+    ctx.net_load(L.init_params(3))
+    views = _mixed_views(w, 24, 3)
+    paths = [fvv.PATH_LEARNED if q % 3 else fvv.PATH_PLAIN for q in range(len(views))]
+    alone = [ctx.synthesize(v, p=fvv.params(path=pa)) for v, pa in zip(views, paths)]
+    srv = fvv.Server(ctx, max_slots=6)
+    outs = [torch.zeros((v.height, v.width, 3), dtype=torch.uint8, device="cuda") for v in views]
+    torch.cuda.synchronize()
+    srv.pause(True)
+    tickets = [srv.submit(v, o, fvv.params(path=pa)) for v, o, pa in zip(views, outs, paths)]
+    srv.pause(False)
+    _wait(srv, tickets)
+    st = srv.stats()
+    srv.stop()
+    torch.cuda.synchronize()
+    assert st["failed"] == 0 and st["steps"] < len(views)
+    for a, o in zip(alone, outs):
+        assert np.array_equal(a, o.cpu().numpy())
+    ctx.close()
