@@ -270,6 +270,88 @@ __global__ void __launch_bounds__(256) k_conv3(const GemmArgs g)
     }
 }
 
+// ---------------------------------------------------------------- 1x1 GEMM, LDS-staged
+// out[p][m] = sum_k A[m][k] B[p][k] for the transposed convolutions (rows
+// m = tap * C_out + co, scattered to the four fine pixels by the epilogue):
+// 128 rows x 128 pixels per block, 32-channel chunks of A and B staged in
+// LDS, four waves of 64 x 64 on v_mfma_f32_32x32x16_bf16.
+template <int EPI>
+__global__ void __launch_bounds__(256) k_gemm1(const GemmArgs g)
+{
+    __shared__ __attribute__((aligned(16))) uint8_t As[128 * C3_PXS];
+    __shared__ __attribute__((aligned(16))) uint8_t Bs[128 * C3_PXS];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lc = lane & 31, lh = lane >> 5;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int P = g.NB * g.H * g.W;
+    const int pbase = blockIdx.x * 128, mbase = blockIdx.y * 128;
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int n = 0; n < 2; ++n)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][n][r] = 0.f;
+    for (int c0 = 0; c0 < g.K; c0 += 32) {
+        for (int e = tid; e < 512; e += 256) {
+            const int r = e >> 2, q = e & 3;
+            const int m = mbase + r, p = pbase + r;
+            uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
+            if (m < g.M) va = *(const uint4 *)(g.A + (int64_t)m * g.K + c0 + q * 8);
+            if (p < P) vb = *(const uint4 *)(g.Bsrc + (int64_t)p * g.b_cs + g.b_off + c0 + q * 8);
+            *(uint4 *)(As + r * C3_PXS + q * 16) = va;
+            *(uint4 *)(Bs + r * C3_PXS + q * 16) = vb;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < 2; ++kk) {
+            const int koff = (kk * 16 + 8 * lh) * 2;
+            bf16x8 af[2], bfr[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                af[i] = __builtin_bit_cast(bf16x8, *(const uint4 *)(As + (wm * 64 + i * 32 + lc) * C3_PXS + koff));
+#pragma unroll
+            for (int n = 0; n < 2; ++n)
+                bfr[n] = __builtin_bit_cast(bf16x8, *(const uint4 *)(Bs + (wn * 64 + n * 32 + lc) * C3_PXS + koff));
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+                for (int n = 0; n < 2; ++n)
+                    acc[i][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[n], acc[i][n], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    const int HW = g.H * g.W;
+#pragma unroll
+    for (int n = 0; n < 2; ++n) {
+        const int p = pbase + wn * 64 + n * 32 + lc;
+        if (p >= P) continue;
+        const int b = p / HW, rr = p - b * HW, y = rr / g.W, x = rr - y * g.W;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int m0 = mbase + wm * 64 + i * 32 + 8 * j + 4 * lh;
+                if (m0 >= g.M) continue;
+                float v0 = acc[i][n][4 * j + 0], v1 = acc[i][n][4 * j + 1];
+                float v2 = acc[i][n][4 * j + 2], v3 = acc[i][n][4 * j + 3];
+                if (EPI == EPI_CONVT_BF16) {
+                    const int d = m0 / g.cout, co = m0 - d * g.cout;
+                    const int64_t fp = ((int64_t)b * 2 * g.H + 2 * y + (d >> 1)) * (2 * g.W) + 2 * x + (d & 1);
+                    v0 += g.bias[co + 0];
+                    v1 += g.bias[co + 1];
+                    v2 += g.bias[co + 2];
+                    v3 += g.bias[co + 3];
+                    *(uint2 *)((uint16_t *)g.out + fp * g.o_cs + g.o_off + co) =
+                        make_uint2((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16),
+                                   (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16));
+                } else {
+                    *(float4 *)((float *)g.out + (int64_t)p * g.o_cs + g.o_off + m0) = make_float4(v0, v1, v2, v3);
+                }
+            }
+    }
+}
+
 // ---------------------------------------------------------------- weight gradient
 struct WgradArgs {
     const uint16_t *G;       // bf16 gradient of the layer output (rows)
@@ -972,14 +1054,14 @@ hipError_t conv3_launch(const GemmArgs &g, hipStream_t s)
     return hipGetLastError();
 }
 
-// 3x3 convolution shapes: 32 rows x 24-row patches for 32-channel outputs,
+// 3x3 convolution shapes: 32 rows x 16-row patches for 32-channel outputs,
 // else 64 rows x 16-row patches (8-row patches on small grids so more
 // blocks exist)
 template <int EPI>
 hipError_t conv3(const GemmArgs &g, hipStream_t s)
 {
     if (g.K % 32 != 0) return hipErrorInvalidValue;
-    if (g.M <= 32) return conv3_launch<1, 24, EPI>(g, s);
+    if (g.M <= 32) return conv3_launch<1, 16, EPI>(g, s);
     if ((int64_t)g.NB * g.H * g.W >= 65536) return conv3_launch<2, 16, EPI>(g, s);
     return conv3_launch<2, 8, EPI>(g, s);
 }
@@ -1023,7 +1105,10 @@ hipError_t convT_fwd(unet_state *n, int li, const uint16_t *in, int i_cs, int NB
     g.K = l.cin_pad;
     g.M = 4 * l.cout;
     g.cout = l.cout;
-    return gemm<4, 1, TAP_ONE, EPI_CONVT_BF16>(g, s);
+    const int P = NB * H * W;
+    dim3 grid((P + 127) / 128, (g.M + 127) / 128);
+    hipLaunchKernelGGL(k_gemm1<EPI_CONVT_BF16>, grid, dim3(256), 0, s, g);
+    return hipGetLastError();
 }
 
 hipError_t pool(const uint16_t *in, int i_cs, int i_off, uint16_t *out, int NB, int H, int W, int C, hipStream_t s)
