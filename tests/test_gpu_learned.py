@@ -302,3 +302,30 @@ def test_learned_errors(fvv):
         c.net_forward(st, 1, 12, 16, out)    # 12 is not a multiple of 8
     assert e.value.code == fvv.FVV_E_ARG
     c.close()
+
+
+@pytest.mark.parametrize("case", ["tiny", "ragged", "one_camera"])
+def test_learned_synthesis_edge_cases(fvv, oracle_lib, case):
+    """Outputs smaller than the network's 8-pixel grain (padded to 8x8, the
+    coarsest level is 1x1), ragged sizes, and a rig of one camera (one valid
+    stack slot) against the oracle; excluding every camera is an error."""
+    say(f"[gpu] learned edge case {case}")
+    c = fvv.Context(0)
+    if case == "one_camera":
+        w = sg.config1(1)
+        v = w.virtual[0]
+    else:
+        w = sg.config_small(80, n_cams=4, w=96, h=64)
+        v = sg.arc_camera(3.0, 2.2, *((5, 3) if case == "tiny" else (33, 17)))
+    c.set_rig(w.rig)
+    c.upload_mvd(w.frames)
+    P = rand_params(81)
+    c.net_load(flat(P))
+    got = c.synthesize(v, p=fvv.params(path=fvv.PATH_LEARNED, k_nearest=w.k_nearest))
+    ref, _, _ = oracle_lib.synthesize_learned(w.rig, w.frames, v, P, k_nearest=w.k_nearest)
+    d = np.abs(got.astype(int) - ref.astype(int))
+    assert np.mean(d <= 2) >= 0.999 and d.max() <= 8, (np.mean(d <= 2), d.max())
+    with pytest.raises(fvv.FvvError) as e:
+        c.synthesize(v, p=fvv.params(path=fvv.PATH_LEARNED, exclude=range(len(w.rig))))
+    assert e.value.code == fvv.FVV_E_STATE
+    c.close()
