@@ -35,6 +35,10 @@ namespace {
 
 constexpr int T = FVV_TILE;
 constexpr int WN = FVV_TILE + 2;   // tile window edge with a 1-pixel halo
+constexpr int TNT = T * T / 4;     // threads of a tile workgroup: four pixels each
+constexpr int TNW = TNT / 64;      // its waves
+constexpr int TPR = T / 4;         // threads per tile row
+static_assert(T % 4 == 0 && TNT % 64 == 0 && TNT >= 2 * T && TNT <= 1024, "tile workgroup shape");
 
 __device__ __forceinline__ uint32_t f2u(float f) { return __float_as_uint(f); }
 __device__ __forceinline__ float u2f(uint32_t u) { return __uint_as_float(u); }
@@ -432,7 +436,7 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
     __shared__ int s_open;
     const int t = threadIdx.x;
     const int n_entries = vd.counts[tile];
-    for (int e = t; e < WN * WN; e += 256) zk[e] = FVV_KEY_EMPTY;
+    for (int e = t; e < WN * WN; e += TNT) zk[e] = FVV_KEY_EMPTY;
     if (t == 0) s_open = 0;
     __syncthreads();
 
@@ -464,18 +468,18 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
             for (int x = xa; x <= xb; ++x) atomicMin(&zk[(y - WY0) * WN + (x - WX0)], f.key);
     };
     if (!scan_all) {
-        // The wave's entries are e = wave + 4 q.  They are read 64 at a time
+        // The wave's entries are e = wave + TNW q.  They are read 64 at a time
         // (one per lane) and the depths of the next two entries are in
         // flight while the current one is splatted, so the dependent loads
         // of consecutive entries overlap instead of queueing.
         const int32_t *lst = vd.list + (int64_t)tile * vd.tile_cap;
-        const int nq = n_entries > wave ? (n_entries - wave + 3) / 4 : 0;
+        const int nq = n_entries > wave ? (n_entries - wave + TNW - 1) / TNW : 0;
         int base = 0;
-        int ents = lane < nq ? lst[wave + 4 * lane] : 0;
+        int ents = lane < nq ? lst[wave + TNW * lane] : 0;
         auto entry = [&](int q) -> int {
             if (q - base >= 64) {
                 base = q;
-                ents = q + lane < nq ? lst[wave + 4 * (q + lane)] : 0;
+                ents = q + lane < nq ? lst[wave + TNW * (q + lane)] : 0;
             }
             return __shfl(ents, q - base, 64);
         };
@@ -502,7 +506,7 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
         }
     } else {
         // more entries than the list holds: test every block's tile range
-        for (int e = wave; e < vd.K * vd.blk_stride; e += 4) {
+        for (int e = wave; e < vd.K * vd.blk_stride; e += TNW) {
             const int k = e / vd.blk_stride, blk = e - k * vd.blk_stride;
             if (blk >= vd.src[k].nblk) continue;
             const int4 r = vd.bbox[e];
@@ -514,7 +518,7 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
     __syncthreads();
 
     // ---- S2 + S3: filter and blend four horizontally adjacent pixels
-    const int ly = t >> 3, lx0 = (t & 7) * 4;
+    const int ly = t / TPR, lx0 = (t % TPR) * 4;
     const int y = Y0 + ly;
     unsigned long long w3[3][6];
 #pragma unroll
@@ -636,13 +640,13 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
 
 // The plain kernel is held to 64 VGPRs (8 waves per SIMD: it is latency-
 // bound, so occupancy pays); the stack variant keeps its registers.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
+__global__ void __launch_bounds__(TNT) __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_tile_plain(const fvv_view_desc *__restrict__ views, int mtx, int mty, int n_views)
 {
     tile_body<false>(views, mtx, mty, n_views);
 }
 
-__global__ void __launch_bounds__(256) k_tile_stack(const fvv_view_desc *__restrict__ views, int mtx, int mty,
+__global__ void __launch_bounds__(TNT) k_tile_stack(const fvv_view_desc *__restrict__ views, int mtx, int mty,
                                                     int n_views)
 {
     tile_body<true>(views, mtx, mty, n_views);
@@ -779,9 +783,9 @@ hipError_t fvv_launch_synthesis(const fvv_view_desc *h_views, fvv_view_desc *d_v
         const int total = b.max_tiles_x * b.max_tiles_y * b.n_views;
         const dim3 grid((total + FVV_XCDS - 1) / FVV_XCDS * FVV_XCDS);
         if (b.any_stack)
-            hipLaunchKernelGGL(k_tile_stack, grid, dim3(256), 0, s, d_views, b.max_tiles_x, b.max_tiles_y, b.n_views);
+            hipLaunchKernelGGL(k_tile_stack, grid, dim3(TNT), 0, s, d_views, b.max_tiles_x, b.max_tiles_y, b.n_views);
         else
-            hipLaunchKernelGGL(k_tile_plain, grid, dim3(256), 0, s, d_views, b.max_tiles_x, b.max_tiles_y, b.n_views);
+            hipLaunchKernelGGL(k_tile_plain, grid, dim3(TNT), 0, s, d_views, b.max_tiles_x, b.max_tiles_y, b.n_views);
     }
     fvv_prof_end(prof, s, FVV_ST_TILE, e0);
     if (b.fill_bg) {
