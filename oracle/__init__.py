@@ -87,6 +87,18 @@ def lib():
                                     P, P, P]
         L.fvv_ref_stack.restype = None
         L.fvv_ref_stack.argtypes = [P, C.c_int32, C.c_int32, C.POINTER(RefTex), C.c_int32, C.c_float, P]
+        L.fvv_ref_depth_code.restype = C.c_uint16
+        L.fvv_ref_depth_code.argtypes = [C.c_uint16, C.c_float, C.c_float]
+        L.fvv_ref_code_depth.restype = C.c_uint16
+        L.fvv_ref_code_depth.argtypes = [C.c_uint16, C.c_float, C.c_float]
+        L.fvv_ref_depth_codes.restype = None
+        L.fvv_ref_depth_codes.argtypes = [P, C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_float, P]
+        L.fvv_ref_codes_depth.restype = None
+        L.fvv_ref_codes_depth.argtypes = [P, C.c_int32, C.c_int32, C.c_float, C.c_float, P]
+        L.fvv_ref_pack_y12.restype = None
+        L.fvv_ref_pack_y12.argtypes = [P, C.c_int32, C.c_int32, P, P, P]
+        L.fvv_ref_unpack_y12.restype = None
+        L.fvv_ref_unpack_y12.argtypes = [P, P, P, C.c_int32, C.c_int32, P]
         L.fvv_ref_fill.restype = None
         L.fvv_ref_fill.argtypes = [P, P, P, C.c_int32, C.c_int32, C.c_int32, P]
         L.fvv_ref_synthesize.restype = C.c_int32
@@ -283,3 +295,59 @@ def key_cam(Z: np.ndarray) -> np.ndarray:
 
 def key_pixel(Z: np.ndarray) -> np.ndarray:
     return (Z & np.uint64((1 << 27) - 1)).astype(np.int64)
+
+
+# ---------------------------------------------------------------- OC: depth codec
+# Section V-A: 12-bit quantisation (Eq. 2) and the bit re-arrangement onto an
+# 8-bit I420 image (Eq. 3 plus the U/V interleave); the C functions carry the
+# readings.
+def depth_codes(depth_mm: np.ndarray, z_near: float, z_far: float) -> np.ndarray:
+    """Eq. 2 quantisation of a millimetre depth map to 12-bit codes (1 = none)."""
+    d = np.ascontiguousarray(depth_mm, np.uint16)
+    H, W = d.shape
+    out = np.empty((H, W), np.uint16)
+    lib().fvv_ref_depth_codes(_ptr(d), W, W, H, z_near, z_far, _ptr(out))
+    return out
+
+
+def codes_depth(codes: np.ndarray, z_near: float, z_far: float) -> np.ndarray:
+    """Inverse of Eq. 2 to whole millimetres (0 for codes 0 and 1)."""
+    c = np.ascontiguousarray(codes, np.uint16)
+    H, W = c.shape
+    out = np.empty((H, W), np.uint16)
+    lib().fvv_ref_codes_depth(_ptr(c), W, H, z_near, z_far, _ptr(out))
+    return out
+
+
+def pack_y12(codes: np.ndarray):
+    """12-bit codes (H, W even) -> I420 planes (Y (H,W), U (H/2,W/2), V)."""
+    c = np.ascontiguousarray(codes, np.uint16)
+    H, W = c.shape
+    assert H % 2 == 0 and W % 2 == 0
+    Y = np.empty((H, W), np.uint8)
+    U = np.empty((H // 2, W // 2), np.uint8)
+    V = np.empty((H // 2, W // 2), np.uint8)
+    lib().fvv_ref_pack_y12(_ptr(c), W, H, _ptr(Y), _ptr(U), _ptr(V))
+    return Y, U, V
+
+
+def unpack_y12(Y, U, V) -> np.ndarray:
+    """I420 planes -> 12-bit codes."""
+    Y = np.ascontiguousarray(Y, np.uint8)
+    U = np.ascontiguousarray(U, np.uint8)
+    V = np.ascontiguousarray(V, np.uint8)
+    H, W = Y.shape
+    assert U.shape == V.shape == (H // 2, W // 2)
+    codes = np.empty((H, W), np.uint16)
+    lib().fvv_ref_unpack_y12(_ptr(Y), _ptr(U), _ptr(V), W, H, _ptr(codes))
+    return codes
+
+
+def encode_depth_y12(depth_mm, z_near: float, z_far: float):
+    """Capture side: millimetre depth -> I420 planes (Y, U, V)."""
+    return pack_y12(depth_codes(depth_mm, z_near, z_far))
+
+
+def decode_depth_y12(Y, U, V, z_near: float, z_far: float) -> np.ndarray:
+    """Receiving side: I420 planes -> whole-millimetre depth (0 = none)."""
+    return codes_depth(unpack_y12(Y, U, V), z_near, z_far)

@@ -626,3 +626,100 @@ int32_t fvv_ref_synthesize(const ref_camera *rig, int32_t n,
     if (!tap_depth) free(dep);
     return K;
 }
+
+/* ------------------------------------------------------------------------ */
+/* OC: 12-bit depth coding for 8-bit YUV420 codecs (Section V-A).
+ * Quantisation, Eq. 2: Y = (2^12 - 3)(1/z - 1/z_far)/(1/z_near - 1/z_far) + 2
+ * (reading: double precision in that operation order, rounded half up);
+ * code 1 = no depth, or out of range, read as a rounded value outside
+ * 2..4095 (so a depth within half a code of a clipping plane keeps the end
+ * code whatever the float32 rounding of the plane); code 0 = the background
+ * signal of the paper's layered synthesis (never produced here, decoded as
+ * no depth).
+ * Bit re-arrangement of each 2x2 block (p11 p12 / p21 p22) onto I420 planes:
+ * Y of each pixel = its 8 LSBs, flipped to 255 - LSBs when its 4 MSBs are
+ * odd (Eq. 3); U = the MSBs of p11 and p12 bit-interleaved, V = those of p21
+ * and p22.  Reading of the missing figure: bit 2k of U is bit k of p11's
+ * MSBs, bit 2k+1 is bit k of p12's (the most variable bits, the low ones,
+ * land lowest).
+ * Decoding inverts both steps; a code >= 2 becomes
+ * z = 1 / ((Y - 2)/4093 (1/z_near - 1/z_far) + 1/z_far) (double) and then
+ * whole millimetres, floor(1000 z + 0.5) clamped to [1, 65535]. */
+static inline uint8_t ref_interleave4(uint32_t a, uint32_t b)
+{
+    uint32_t v = 0;
+    for (int k = 0; k < 4; ++k) v |= ((a >> k) & 1u) << (2 * k) | ((b >> k) & 1u) << (2 * k + 1);
+    return (uint8_t)v;
+}
+
+uint16_t fvv_ref_depth_code(uint16_t mm, float z_near, float z_far)
+{
+    if (mm == 0) return 1;
+    double z = (double)mm / 1000.0;
+    double zn = (double)z_near, zf = (double)z_far;
+    double a = 1.0 / z - 1.0 / zf;
+    double b = 1.0 / zn - 1.0 / zf;
+    double y = 4093.0 * a / b + 2.0;
+    double r = floor(y + 0.5);
+    if (!(r >= 2.0 && r <= 4095.0)) return 1;
+    return (uint16_t)r;
+}
+
+uint16_t fvv_ref_code_depth(uint16_t code, float z_near, float z_far)
+{
+    if (code < 2) return 0;
+    double zn = (double)z_near, zf = (double)z_far;
+    double t = (double)(code - 2) / 4093.0;
+    double inv = t * (1.0 / zn - 1.0 / zf) + 1.0 / zf;
+    double z = 1.0 / inv;
+    double mm = floor(z * 1000.0 + 0.5);
+    if (mm < 1.0) mm = 1.0;
+    if (mm > 65535.0) mm = 65535.0;
+    return (uint16_t)mm;
+}
+
+/* Eq. 2 over a plane: mm (pitch in elements) -> codes (W per row) */
+void fvv_ref_depth_codes(const uint16_t *mm, int64_t pitch, int32_t W, int32_t H, float z_near, float z_far,
+                         uint16_t *codes)
+{
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x)
+            codes[(int64_t)y * W + x] = fvv_ref_depth_code(mm[(int64_t)y * pitch + x], z_near, z_far);
+}
+
+void fvv_ref_codes_depth(const uint16_t *codes, int32_t W, int32_t H, float z_near, float z_far, uint16_t *mm)
+{
+    for (int64_t i = 0; i < (int64_t)W * H; ++i) mm[i] = fvv_ref_code_depth(codes[i], z_near, z_far);
+}
+
+/* codes (H x W, W and H even) -> I420 planes */
+void fvv_ref_pack_y12(const uint16_t *codes, int32_t W, int32_t H, uint8_t *Y, uint8_t *U, uint8_t *V)
+{
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            uint32_t c = codes[(int64_t)y * W + x] & 0xFFFu;
+            uint32_t msb = c >> 8, lsb = c & 0xFFu;
+            Y[(int64_t)y * W + x] = (uint8_t)((msb & 1u) ? 255u - lsb : lsb);
+        }
+    for (int r = 0; r < H / 2; ++r)
+        for (int c = 0; c < W / 2; ++c) {
+            const uint16_t *p1 = codes + (int64_t)(2 * r) * W + 2 * c;
+            const uint16_t *p2 = p1 + W;
+            U[(int64_t)r * (W / 2) + c] = ref_interleave4(p1[0] >> 8, p1[1] >> 8);
+            V[(int64_t)r * (W / 2) + c] = ref_interleave4(p2[0] >> 8, p2[1] >> 8);
+        }
+}
+
+/* I420 planes -> codes */
+void fvv_ref_unpack_y12(const uint8_t *Y, const uint8_t *U, const uint8_t *V, int32_t W, int32_t H, uint16_t *codes)
+{
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            uint32_t uv = (y & 1) ? V[(int64_t)(y / 2) * (W / 2) + x / 2] : U[(int64_t)(y / 2) * (W / 2) + x / 2];
+            uint32_t msb = 0;
+            for (int k = 0; k < 4; ++k) msb |= ((uv >> (2 * k + (x & 1))) & 1u) << k;
+            uint32_t yv = Y[(int64_t)y * W + x];
+            uint32_t lsb = (msb & 1u) ? 255u - yv : yv;
+            codes[(int64_t)y * W + x] = (uint16_t)(msb << 8 | lsb);
+        }
+}
