@@ -255,6 +255,66 @@ def run_learned(fvv, torch, w, ctx, stream, args) -> dict:
             "train_tflops_approx": round(train_tflops, 1)}
 
 
+def run_codec(fvv, torch, w, raw, virt_c, outs, stream, reps: int) -> dict:
+    """12-bit depth coding (Section V-A) on the 9-camera 1280x720 rig: the
+    capture-side encoder and the standalone decoder (one launch per camera,
+    HIP events on the stream), and a step whose ingest decodes the coded
+    depth inside the repack kernel."""
+    zn, zf = 1.0, 8.0           # clipping planes enclosing the scene's 1.4..7.4 m
+    dev = raw[0][1].device
+    yuv = [torch.empty((d.shape[0] * 3 // 2, d.shape[1]), dtype=torch.uint8, device=dev) for _, d in raw]
+    back = [torch.empty_like(d) for _, d in raw]
+    px = sum(d.numel() for _, d in raw)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def enc():
+        for (_, d), y in zip(raw, yuv):
+            fvv.depth_encode_y12(d, zn, zf, out=y, stream=stream)
+
+    def dec():
+        for y, (_, d), b in zip(yuv, raw, back):
+            fvv.depth_decode_y12(y, d.shape[1], d.shape[0], zn, zf, out=b, stream=stream)
+
+    enc_ms = timed(enc)
+    dec_ms = timed(dec)
+    coded = [(rgb, y) for (rgb, _), y in zip(raw, yuv)]
+    c2 = fvv.Context(0)
+    c2.set_rig(w.rig)
+    c2.set_depth_format(fvv.DEPTH_Y12, zn, zf)
+
+    def step():
+        c2.upload_mvd(coded, mem=fvv.MEM_DEVICE, stream=stream)
+        c2.synthesize_batch(virt_c, outs, stream=stream)
+
+    step_ms = timed(step)
+    c2.set_profiling(True)
+    c2.profile(reset=True)
+    for _ in range(5):
+        step()
+    torch.cuda.synchronize()
+    prof = c2.profile(reset=True)
+    c2.close()
+    stages = {k: round(t / n, 4) for k, (t, n) in prof.items() if n}
+    b_codec = 3.5 * px          # 2 B of millimetres <-> 1.5 B of I420 per pixel
+    return {"planes_m": [zn, zf], "pixels": px,
+            "encode_ms": round(enc_ms, 4), "encode_alg_GBs": round(b_codec / (enc_ms * 1e-3) / 1e9, 1),
+            "decode_ms": round(dec_ms, 4), "decode_alg_GBs": round(b_codec / (dec_ms * 1e-3) / 1e9, 1),
+            "launches": 2 * len(raw),
+            "coded_step_ms": round(step_ms, 4), "coded_step_stage_ms": stages}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,6 +330,8 @@ def main():
                     help="views of the learned-path measurement at 960x540 (0 = skip)")
     ap.add_argument("--serve-learned-seconds", type=float, default=3.0,
                     help="measured seconds of the learned serving load (0 = skip)")
+    ap.add_argument("--codec-reps", type=int, default=20,
+                    help="repetitions of the 12-bit depth codec timing (0 = skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain device copy of this many MiB first (hardware-counter scale)")
     args = ap.parse_args()
@@ -400,6 +462,11 @@ def main():
                          f"single-threaded, {dt:.1f} s on {platform.processor() or platform.machine()}"}
         log(f"[bench] cpu oracle {cpu['value']} Mpix/s")
 
+    codec = None
+    if args.codec_reps > 0:
+        codec = run_codec(fvv, torch, w, raw, virt_c, outs, stream, args.codec_reps)
+        log(f"[bench] depth codec {json.dumps(codec)}")
+
     learned = None
     if args.learned_views > 0:
         learned = run_learned(fvv, torch, w, ctx, stream, args)
@@ -444,6 +511,7 @@ def main():
         "serving": serving,
         "learned": learned,
         "serving_learned": serving_learned,
+        "depth_codec": codec,
         "path": "plain",
     }
     print(json.dumps(res), flush=True)

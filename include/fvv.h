@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define FVV_ABI_VERSION 2
+#define FVV_ABI_VERSION 3
 
 /* status codes */
 enum {
@@ -77,8 +77,10 @@ typedef struct {
 } fvv_camera;
 
 /* One camera's MVD frame.  rgb: height rows of width*3 bytes; depth_mm:
- * height rows of width uint16 millimetres (0 = no depth).  Both NULL marks the
- * camera as absent from this frame set: it is then never selected. */
+ * height rows of width uint16 millimetres (0 = no depth), or, once the
+ * context's depth format is FVV_DEPTH_Y12, the 12-bit coded I420 image of
+ * fvv_depth_encode_y12 with depth_pitch as its luma pitch.  Both NULL marks
+ * the camera as absent from this frame set: it is then never selected. */
 typedef struct {
     const void *rgb;
     int64_t rgb_pitch;
@@ -117,8 +119,9 @@ int32_t fvv_create(int32_t hip_device, uint64_t mem_budget_bytes, fvv_ctx **out)
 /* Destroy a context; waits for its outstanding work.  NULL is a no-op. */
 void fvv_destroy(fvv_ctx *ctx);
 
-/* Text of the last failure on ctx (or of the last failed fvv_create when ctx
- * is NULL).  Valid until the next call on ctx. */
+/* Text of the last failure on ctx (or, when ctx is NULL, of the calling
+ * thread's last failed fvv_create or codec call).  Valid until the next call
+ * on ctx. */
 const char *fvv_last_error(const fvv_ctx *ctx);
 
 /* Set the camera rig: n (1..FVV_MAX_CAMERAS) calibrated cameras.  Copies the
@@ -135,6 +138,42 @@ int32_t fvv_set_rig(fvv_ctx *ctx, const fvv_camera *cams, int32_t n);
  * *out_version (may be NULL) receives the new set's version (1, 2, ...). */
 int32_t fvv_upload_mvd(fvv_ctx *ctx, const fvv_view *views, int32_t n, int32_t mem_kind,
                        void *stream, uint64_t *out_version);
+
+/* 12-bit depth coding for 8-bit YUV420 video codecs (Section V-A).
+ * The capture side quantises depth to 12-bit codes (Eq. 2, linear in 1/z
+ * between the clipping planes z_near and z_far, metres):
+ *   code = round(4093 (1/z - 1/z_far) / (1/z_near - 1/z_far) + 2),
+ * evaluated in double precision and rounded half up; 1 = no depth (0 mm) or
+ * a rounded code outside 2..4095; 0 is reserved for background pixels (it
+ * decodes as no depth).  Each 2x2 block p11 p12 / p21 p22 of codes becomes
+ * one 2x2 block of an I420 image: Y = the code's 8 LSBs, mirrored to
+ * 255 - LSBs when its 4 MSBs are odd (Eq. 3); U = the MSBs of p11 on the
+ * even bits and of p12 on the odd bits; V = the same for p21 and p22.
+ * Decoding inverts both steps and returns whole millimetres,
+ * round(1000 / ((code - 2)/4093 (1/z_near - 1/z_far) + 1/z_far)), 0 for
+ * codes 0 and 1.
+ *
+ * I420 layout (yuv): height rows of y_pitch bytes (Y), then U and V, each
+ * height/2 rows of y_pitch/2 bytes.  y_pitch even and >= width; width and
+ * height even, >= 2, width*height <= FVV_MAX_SRC_PIXELS, height <= 65536.
+ * depth rows: depth_pitch bytes (even, >= 2*width), 2-byte aligned.
+ * Both buffers are device memory; the work is enqueued on stream (HIP
+ * stream, NULL = default) of the current device and the call returns at
+ * once.  FVV_E_ARG for bad sizes, pitches or planes (0 < z_near < z_far,
+ * finite); FVV_E_DEVICE if the launch fails. */
+int32_t fvv_depth_encode_y12(const void *depth_mm, int64_t depth_pitch, int32_t width, int32_t height,
+                             float z_near, float z_far, void *yuv, int64_t y_pitch, void *stream);
+int32_t fvv_depth_decode_y12(const void *yuv, int64_t y_pitch, int32_t width, int32_t height, float z_near,
+                             float z_far, void *depth_mm, int64_t depth_pitch, void *stream);
+
+/* Depth format of the following uploads on ctx: FVV_DEPTH_MM16 (default,
+ * uint16 millimetres) or FVV_DEPTH_Y12 (the I420 image above, decoded to
+ * millimetres by the ingest kernel; every camera's width and height even).
+ * Eq. (1) is then applied to the decoded millimetres as for the 16-bit
+ * format.  z_near / z_far are read for FVV_DEPTH_Y12 only.  Resident frame
+ * sets are not affected. */
+enum { FVV_DEPTH_MM16 = 0, FVV_DEPTH_Y12 = 1 };
+int32_t fvv_set_depth_format(fvv_ctx *ctx, int32_t format, float z_near, float z_far);
 
 /* Render one virtual camera into out_rgb8 (height rows of width*3 bytes,
  * pitch out_pitch; host or device per mem_kind).  Steps, all on the GPU:

@@ -105,6 +105,9 @@ def lib():
             "fvv_net_train_step": (I32, [P, P, P, I32, I32, I32, I32, C.c_float, I32, P, P]),
             "fvv_net_read_act": (I32, [P, I32, P, I64]),
             "fvv_net_device_bytes": (U64, [P]),
+            "fvv_depth_encode_y12": (I32, [P, I64, I32, I32, C.c_float, C.c_float, P, I64, P]),
+            "fvv_depth_decode_y12": (I32, [P, I64, I32, I32, C.c_float, C.c_float, P, I64, P]),
+            "fvv_set_depth_format": (I32, [P, I32, C.c_float, C.c_float]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -121,7 +124,9 @@ EXPORTED = ("fvv_abi_version", "fvv_create", "fvv_destroy", "fvv_last_error", "f
             "fvv_server_stop", "fvv_server_pause", "fvv_submit", "fvv_poll", "fvv_server_stats",
             "fvv_net_param_count", "fvv_net_layer_info", "fvv_net_layer_name", "fvv_net_load",
             "fvv_net_read", "fvv_make_stack", "fvv_net_forward", "fvv_net_train_step",
-            "fvv_net_read_act", "fvv_net_device_bytes")
+            "fvv_net_read_act", "fvv_net_device_bytes", "fvv_depth_encode_y12",
+            "fvv_depth_decode_y12", "fvv_set_depth_format")
+DEPTH_MM16, DEPTH_Y12 = 0, 1
 NET_PARAMS, NET_GRADS = 0, 1
 NET_ALIGN = 8           # network inputs: multiples of 8 in both dimensions
 NET_IN = 32             # stack channels on the device (16 defined, zero padded)
@@ -214,6 +219,37 @@ def pair_matrices(src, virt):
                 sx=out[24], sy=out[25])
 
 
+def _codec_check(rc: int, what: str):
+    if rc != FVV_OK:
+        raise FvvError(rc, f"{what}: " + lib().fvv_last_error(None).decode())
+
+
+def depth_encode_y12(depth, z_near: float, z_far: float, out=None, stream=None):
+    """12-bit depth coding (Section V-A) of a device depth map (H, W) of
+    2-byte millimetres into an I420 image; out (H*3/2, W) uint8 device tensor
+    (a new one if None), rows of out.stride(0) bytes."""
+    import torch
+    H, W = depth.shape
+    if out is None:
+        out = torch.empty((H * 3 // 2, W), dtype=torch.uint8, device=depth.device)
+    _codec_check(lib().fvv_depth_encode_y12(depth.data_ptr(), _pitch(depth, 0), W, H, z_near, z_far,
+                                            out.data_ptr(), _pitch(out, 0), _stream_handle(stream)),
+                 "fvv_depth_encode_y12")
+    return out
+
+
+def depth_decode_y12(yuv, width: int, height: int, z_near: float, z_far: float, out=None, stream=None):
+    """Inverse of depth_encode_y12: I420 device image -> (H, W) int16 tensor
+    holding the uint16 millimetres (0 = no depth)."""
+    import torch
+    if out is None:
+        out = torch.empty((height, width), dtype=torch.int16, device=yuv.device)
+    _codec_check(lib().fvv_depth_decode_y12(yuv.data_ptr(), _pitch(yuv, 0), width, height, z_near, z_far,
+                                            out.data_ptr(), _pitch(out, 0), _stream_handle(stream)),
+                 "fvv_depth_decode_y12")
+    return out
+
+
 class Context:
     """One library context on one HIP device."""
 
@@ -226,6 +262,7 @@ class Context:
         self._h = h
         self.device = device
         self.rig = []
+        self.depth_format = DEPTH_MM16
 
     def close(self):
         if getattr(self, "_h", None):
@@ -257,9 +294,17 @@ class Context:
         self._check(self._L.fvv_set_rig(self._h, arr, len(cams)))
         self.rig = list(cams)
 
+    def set_depth_format(self, fmt: int, z_near: float = 0.0, z_far: float = 0.0):
+        """DEPTH_MM16 (uint16 millimetres) or DEPTH_Y12 (12-bit coded I420
+        images, (H*3/2, W) uint8) for the following uploads."""
+        self._check(self._L.fvv_set_depth_format(self._h, fmt, z_near, z_far))
+        self.depth_format = fmt
+
     def upload_mvd(self, frames: Sequence, mem: int = MEM_HOST, stream=None) -> int:
-        """frames[c] = (rgb (H,W,3) uint8, depth (H,W) uint16) -- numpy for
-        MEM_HOST, torch CUDA tensors for MEM_DEVICE -- or None if absent."""
+        """frames[c] = (rgb (H,W,3) uint8, depth) -- numpy for MEM_HOST, torch
+        CUDA tensors for MEM_DEVICE -- or None if absent.  depth is (H,W)
+        uint16 millimetres, or the (H*3/2, W) uint8 I420 image in the 12-bit
+        depth format."""
         n = len(frames)
         views = (View * n)()
         keep = []
@@ -270,7 +315,7 @@ class Context:
             rgb, dep = (f.rgb, f.depth_mm) if hasattr(f, "rgb") else f
             if mem == MEM_HOST:
                 rgb = np.ascontiguousarray(rgb, np.uint8)
-                dep = np.ascontiguousarray(dep, np.uint16)
+                dep = np.ascontiguousarray(dep, np.uint8 if self.depth_format == DEPTH_Y12 else np.uint16)
             keep += [rgb, dep]
             views[k] = View(_addr(rgb), _pitch(rgb, 0), _addr(dep), _pitch(dep, 0))
         ver = C.c_uint64(0)

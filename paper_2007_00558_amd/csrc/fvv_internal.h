@@ -131,7 +131,9 @@ struct fvv_batch_dims {
 struct fvv_repack_cam {
     const uint8_t *rgb;
     int64_t rgb_pitch;      // bytes
-    const uint8_t *depth;   // uint16 millimetres
+    const uint8_t *depth;   // uint16 millimetres, or (12-bit coding) an I420 image:
+                            // Y rows of depth_pitch bytes, then the U and V
+                            // planes, H/2 rows of depth_pitch/2 bytes each
     int64_t depth_pitch;    // bytes
     uint2 *texel_out;
     float *depth_out;
@@ -140,9 +142,18 @@ struct fvv_repack_cam {
 };
 struct fvv_repack_batch {
     int32_t n;
-    int32_t pad;
+    int32_t y12;            // depth arrives 12-bit coded (Section V-A)
+    float z_near, z_far;    // clipping planes of that coding, metres
     fvv_repack_cam cam[FVV_MAX_RIG];
 };
+
+// 12-bit depth coding (fvv_codec.hip): millimetres (pitch dpitch) <-> an
+// I420 image at yuv (Y rows of ypitch bytes, then U and V of H/2 rows of
+// ypitch/2 bytes).  W and H even.
+hipError_t fvv_launch_y12_encode(const uint8_t *dep, int64_t dpitch, int W, int H, float zn, float zf, uint8_t *yuv,
+                                 int64_t ypitch, hipStream_t s);
+hipError_t fvv_launch_y12_decode(const uint8_t *yuv, int64_t ypitch, int W, int H, float zn, float zf, uint8_t *dep,
+                                 int64_t dpitch, hipStream_t s);
 
 // Host-side launchers (fvv_kernels.hip).  All return hipError_t of the launch.
 hipError_t fvv_launch_repack(const fvv_repack_batch &b, int max_w, int max_h, hipStream_t s, fvv_prof *prof);

@@ -2,8 +2,9 @@
 //
 // Stages (FVV Live, arXiv 2007.00558, Section VI):
 //   repack     MVD ingest, once per frame set: RGB8 -> 8-byte texels {RGBA8,
-//              depth}, millimetres -> metres with the Eq. (1) correction
-//              (Section IV-A), and the depth range of every 8x8 block
+//              depth}, millimetres (or 12-bit coded depth, Section V-A,
+//              decoded to millimetres) -> metres with the Eq. (1) correction
+//              (Section IV-A)
 //   desc       copy of the view descriptors from coherent pinned host memory
 //   bin        every 8x8 block of each selected source camera is bounded in
 //              the virtual image from the 8 corners of its pixel-and-depth
@@ -30,6 +31,7 @@
 #include <climits>
 
 #include "fvv_internal.h"
+#include "fvv_y12.h"
 
 namespace {
 
@@ -120,7 +122,17 @@ __global__ void __launch_bounds__(256) k_repack(const fvv_repack_batch b)
     if (x >= c.W || y >= c.H) return;
     const uint8_t *p = c.rgb + (int64_t)y * c.rgb_pitch + (int64_t)x * 3;
     const uint32_t col = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | 0xFF000000u;
-    const uint16_t d = *(const uint16_t *)(c.depth + (int64_t)y * c.depth_pitch + (int64_t)x * 2);
+    uint32_t d;
+    if (b.y12) {
+        // I420 12-bit coding: Y, then U (even rows' MSBs), then V (odd rows')
+        const int64_t uvp = c.depth_pitch >> 1;
+        const uint8_t *pl = c.depth + (int64_t)c.H * c.depth_pitch + ((y & 1) ? (int64_t)(c.H >> 1) * uvp : 0);
+        const uint32_t uv = pl[(int64_t)(y >> 1) * uvp + (x >> 1)];
+        d = y12_dequantise(y12_unfold(c.depth[(int64_t)y * c.depth_pitch + x], y12_msb(uv, x & 1)), b.z_near,
+                           b.z_far);
+    } else {
+        d = *(const uint16_t *)(c.depth + (int64_t)y * c.depth_pitch + (int64_t)x * 2);
+    }
     uint32_t zb = FVV_NO_DEPTH;
     if (d != 0) {
         const float z = __fdiv_rn((float)d, 1000.0f);

@@ -139,7 +139,11 @@ struct fvv_ctx {
     int latest = -1;
     uint64_t next_version = 1;
     std::vector<hipEvent_t> event_pool;
-    // upload staging: raw RGB8 + uint16 planes of all cameras
+    // depth format of uploads (FVV_DEPTH_*) and the clipping planes of the
+    // 12-bit coding
+    int32_t depth_format = FVV_DEPTH_MM16;
+    float z_near = 0.f, z_far = 0.f;
+    // upload staging: raw RGB8 + depth planes of all cameras
     uint8_t *staging = nullptr;
     size_t staging_bytes = 0;
     hipEvent_t staging_free = nullptr;
@@ -1050,6 +1054,9 @@ int32_t fvv_upload_mvd(fvv_ctx *c, const fvv_view *views, int32_t n, int32_t mem
     if (c->rig.empty()) return fail(c, FVV_E_STATE, "no rig set");
     if (!views || n != (int)c->rig.size()) return fail(c, FVV_E_ARG, "need one view per rig camera (%zu)", c->rig.size());
     if (mem_kind != FVV_MEM_HOST && mem_kind != FVV_MEM_DEVICE) return fail(c, FVV_E_ARG, "bad mem_kind");
+    const bool y12 = c->depth_format == FVV_DEPTH_Y12;
+    // staged depth plane: uint16 rows, or an I420 image (Y, then U and V)
+    auto depth_bytes = [y12](int W, int H) { return y12 ? (size_t)W * H * 3 / 2 : (size_t)W * H * 2; };
     size_t need = 0;
     int n_present = 0;
     for (int k = 0; k < n; ++k) {
@@ -1057,11 +1064,18 @@ int32_t fvv_upload_mvd(fvv_ctx *c, const fvv_view *views, int32_t n, int32_t mem
         const fvv_camera &cam = c->rig[k];
         if (!v.rgb && !v.depth_mm) continue;
         if (!v.rgb || !v.depth_mm) return fail(c, FVV_E_ARG, "view %d: rgb and depth must both be given", k);
-        if (v.rgb_pitch < (int64_t)cam.width * 3 || v.depth_pitch < (int64_t)cam.width * 2)
-            return fail(c, FVV_E_ARG, "view %d: pitch too small", k);
-        if (v.depth_pitch % 2 || ((uintptr_t)v.depth_mm & 1))
-            return fail(c, FVV_E_ARG, "view %d: depth must be 2-byte aligned (pointer and pitch)", k);
-        need += align256((size_t)cam.width * cam.height * 3) + align256((size_t)cam.width * cam.height * 2);
+        if (y12) {
+            if (cam.width % 2 || cam.height % 2)
+                return fail(c, FVV_E_ARG, "view %d: 12-bit coded depth needs even width and height", k);
+            if (v.rgb_pitch < (int64_t)cam.width * 3 || v.depth_pitch < (int64_t)cam.width || v.depth_pitch % 2)
+                return fail(c, FVV_E_ARG, "view %d: pitch too small (or odd I420 luma pitch)", k);
+        } else {
+            if (v.rgb_pitch < (int64_t)cam.width * 3 || v.depth_pitch < (int64_t)cam.width * 2)
+                return fail(c, FVV_E_ARG, "view %d: pitch too small", k);
+            if (v.depth_pitch % 2 || ((uintptr_t)v.depth_mm & 1))
+                return fail(c, FVV_E_ARG, "view %d: depth must be 2-byte aligned (pointer and pitch)", k);
+        }
+        need += align256((size_t)cam.width * cam.height * 3) + align256(depth_bytes(cam.width, cam.height));
         ++n_present;
     }
     if (n_present == 0) return fail(c, FVV_E_ARG, "no camera present in the upload");
@@ -1099,15 +1113,25 @@ int32_t fvv_upload_mvd(fvv_ctx *c, const fvv_view *views, int32_t n, int32_t mem
             uint8_t *rgb = cur;
             cur += align256((size_t)W * H * 3);
             uint8_t *dep = cur;
-            cur += align256((size_t)W * H * 2);
+            cur += align256(depth_bytes(W, H));
             HIPCHECK(c, hipMemcpy2DAsync(rgb, (size_t)W * 3, v.rgb, v.rgb_pitch, (size_t)W * 3, H,
                                          hipMemcpyHostToDevice, s));
-            HIPCHECK(c, hipMemcpy2DAsync(dep, (size_t)W * 2, v.depth_mm, v.depth_pitch, (size_t)W * 2, H,
-                                         hipMemcpyHostToDevice, s));
+            if (y12) {
+                // Y rows, then the U and V planes at half the pitch
+                const uint8_t *src = (const uint8_t *)v.depth_mm;
+                const int64_t sp = v.depth_pitch, up = sp / 2;
+                HIPCHECK(c, hipMemcpy2DAsync(dep, (size_t)W, src, sp, (size_t)W, H, hipMemcpyHostToDevice, s));
+                HIPCHECK(c, hipMemcpy2DAsync(dep + (size_t)W * H, (size_t)W / 2, src + (int64_t)H * sp, up,
+                                             (size_t)W / 2, H, hipMemcpyHostToDevice, s));
+                rc_.depth_pitch = W;
+            } else {
+                HIPCHECK(c, hipMemcpy2DAsync(dep, (size_t)W * 2, v.depth_mm, v.depth_pitch, (size_t)W * 2, H,
+                                             hipMemcpyHostToDevice, s));
+                rc_.depth_pitch = (int64_t)W * 2;
+            }
             rc_.rgb = rgb;
             rc_.rgb_pitch = (int64_t)W * 3;
             rc_.depth = dep;
-            rc_.depth_pitch = (int64_t)W * 2;
         } else {
             rc_.rgb = (const uint8_t *)v.rgb;
             rc_.rgb_pitch = v.rgb_pitch;
@@ -1123,6 +1147,9 @@ int32_t fvv_upload_mvd(fvv_ctx *c, const fvv_view *views, int32_t n, int32_t mem
         max_w = std::max(max_w, W);
         max_h = std::max(max_h, H);
     }
+    b.y12 = y12;
+    b.z_near = c->z_near;
+    b.z_far = c->z_far;
     HIPCHECK(c, fvv_launch_repack(b, max_w, max_h, s, c->profiling ? &c->prof : nullptr));
     if (host) HIPCHECK(c, hipEventRecord(c->staging_free, s));
     HIPCHECK(c, hipEventRecord(fs.ready, s));
@@ -1130,6 +1157,65 @@ int32_t fvv_upload_mvd(fvv_ctx *c, const fvv_view *views, int32_t n, int32_t mem
     fs.version = c->next_version++;
     c->latest = dst;
     if (out_version) *out_version = fs.version;
+    return FVV_OK;
+}
+
+int32_t fvv_set_depth_format(fvv_ctx *c, int32_t format, float z_near, float z_far)
+{
+    if (!c) return FVV_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (format == FVV_DEPTH_MM16) {
+        c->depth_format = format;
+        return FVV_OK;
+    }
+    if (format != FVV_DEPTH_Y12) return fail(c, FVV_E_ARG, "unknown depth format %d", format);
+    if (!(std::isfinite(z_near) && std::isfinite(z_far) && z_near > 0.f && z_near < z_far))
+        return fail(c, FVV_E_ARG, "clipping planes need 0 < z_near < z_far (finite)");
+    c->depth_format = format;
+    c->z_near = z_near;
+    c->z_far = z_far;
+    return FVV_OK;
+}
+
+namespace {
+
+// arguments shared by the standalone encoder and decoder
+int32_t check_y12_args(const void *a, const void *b, int32_t W, int32_t H, float zn, float zf, int64_t ypitch,
+                       int64_t dpitch)
+{
+    if (!a || !b) return fail(nullptr, FVV_E_ARG, "null buffer");
+    if (W < 2 || H < 2 || W % 2 || H % 2 || (int64_t)W * H > FVV_MAX_SRC_PIXELS || H > 65536)
+        return fail(nullptr, FVV_E_ARG, "width and height must be even, >= 2, with width*height <= %d",
+                    FVV_MAX_SRC_PIXELS);
+    if (ypitch < W || ypitch % 2) return fail(nullptr, FVV_E_ARG, "I420 luma pitch must be even and >= width");
+    if (dpitch < 2 * (int64_t)W || dpitch % 2 || ((uintptr_t)b & 1))
+        return fail(nullptr, FVV_E_ARG, "depth rows must be 2-byte aligned and hold width values");
+    if (!(std::isfinite(zn) && std::isfinite(zf) && zn > 0.f && zn < zf))
+        return fail(nullptr, FVV_E_ARG, "clipping planes need 0 < z_near < z_far (finite)");
+    return FVV_OK;
+}
+
+}  // namespace
+
+int32_t fvv_depth_encode_y12(const void *depth_mm, int64_t depth_pitch, int32_t width, int32_t height, float z_near,
+                             float z_far, void *yuv, int64_t y_pitch, void *stream)
+{
+    int32_t rc = check_y12_args(yuv, depth_mm, width, height, z_near, z_far, y_pitch, depth_pitch);
+    if (rc) return rc;
+    hipError_t e = fvv_launch_y12_encode((const uint8_t *)depth_mm, depth_pitch, width, height, z_near, z_far,
+                                         (uint8_t *)yuv, y_pitch, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(nullptr, FVV_E_DEVICE, "encode launch: %s", hipGetErrorString(e));
+    return FVV_OK;
+}
+
+int32_t fvv_depth_decode_y12(const void *yuv, int64_t y_pitch, int32_t width, int32_t height, float z_near,
+                             float z_far, void *depth_mm, int64_t depth_pitch, void *stream)
+{
+    int32_t rc = check_y12_args(yuv, depth_mm, width, height, z_near, z_far, y_pitch, depth_pitch);
+    if (rc) return rc;
+    hipError_t e = fvv_launch_y12_decode((const uint8_t *)yuv, y_pitch, width, height, z_near, z_far,
+                                         (uint8_t *)depth_mm, depth_pitch, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(nullptr, FVV_E_DEVICE, "decode launch: %s", hipGetErrorString(e));
     return FVV_OK;
 }
 

@@ -1,0 +1,66 @@
+// fvv_y12.h -- device helpers of the 12-bit depth coding for 8-bit YUV420
+// video codecs (Section V-A), shared by the codec kernels and the frame-store
+// ingest.  Internal to the library.
+//
+// Codes: 0 = background (layered synthesis; decoded as no depth), 1 = no
+// depth or out of range, 2..4095 = Eq. 2 of the depth, which is linear in
+// 1/z between the clipping planes.  Eq. 2 and its inverse run in double
+// precision op by op (the library is built without contraction), rounded
+// half up; "out of range" means the rounded code leaves 2..4095.
+//
+// I420 placement of each 2x2 block p11 p12 / p21 p22: every pixel's Y is its
+// 8 LSBs, mirrored to 255 - LSBs when its 4 MSBs are odd (Eq. 3), so that
+// consecutive codes never jump in Y; U carries the MSBs of p11 on its even
+// bits and those of p12 on its odd bits (bit 2k = bit k of p11, bit 2k+1 =
+// bit k of p12), V the same for p21 and p22.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+// Eq. 2: millimetres -> code
+__device__ __forceinline__ uint32_t y12_quantise(uint32_t mm, double zn, double zf)
+{
+    if (mm == 0) return 1u;
+    const double z = (double)mm / 1000.0;
+    const double a = 1.0 / z - 1.0 / zf;
+    const double b = 1.0 / zn - 1.0 / zf;
+    const double r = floor(4093.0 * a / b + 2.0 + 0.5);
+    return (r >= 2.0 && r <= 4095.0) ? (uint32_t)r : 1u;
+}
+
+// inverse of Eq. 2 -> whole millimetres in 1..65535 (0 for codes 0 and 1)
+__device__ __forceinline__ uint32_t y12_dequantise(uint32_t code, double zn, double zf)
+{
+    if (code < 2u) return 0u;
+    const double t = (double)(code - 2u) / 4093.0;
+    const double inv = t * (1.0 / zn - 1.0 / zf) + 1.0 / zf;
+    const double mm = floor(1.0 / inv * 1000.0 + 0.5);
+    return mm < 1.0 ? 1u : mm > 65535.0 ? 65535u : (uint32_t)mm;
+}
+
+// Eq. 3 and its inverse
+__device__ __forceinline__ uint32_t y12_fold(uint32_t code)
+{
+    return ((code >> 8) & 1u) ? 255u - (code & 0xFFu) : (code & 0xFFu);
+}
+__device__ __forceinline__ uint32_t y12_unfold(uint32_t yv, uint32_t msb)
+{
+    return msb << 8 | ((msb & 1u) ? 255u - yv : yv);
+}
+
+// 4 bits b3..b0 -> the even bits of a byte, and back
+__device__ __forceinline__ uint32_t y12_spread4(uint32_t m)
+{
+    m = (m | m << 2) & 0x33u;
+    return (m | m << 1) & 0x55u;
+}
+__device__ __forceinline__ uint32_t y12_gather4(uint32_t v)
+{
+    v &= 0x55u;
+    v = (v | v >> 1) & 0x33u;
+    return (v | v >> 2) & 0x0Fu;
+}
+
+// MSBs of pixel column `odd` (0 = left, 1 = right) of a U or V byte
+__device__ __forceinline__ uint32_t y12_msb(uint32_t uv, uint32_t odd) { return y12_gather4(uv >> odd); }

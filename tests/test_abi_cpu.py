@@ -27,7 +27,7 @@ def test_library_exports_every_declared_function():
     for name in names:
         assert hasattr(L, name), name
     assert set(names) == set(fvv.EXPORTED)
-    assert L.fvv_abi_version() == 2
+    assert L.fvv_abi_version() == 3
 
 
 def test_header_struct_layouts_match_binding():
@@ -97,3 +97,28 @@ def test_network_layout_matches_definition():
         [(n, kinds[k], ci, co, ksz[k]) for n, k, ci, co in unet.LAYERS]
     total = sum(int(np.prod(unet.weight_shape(k, ci, co))) + co for _, k, ci, co in unet.LAYERS)
     assert fvv.net_param_count() == total
+
+
+def test_codec_argument_checks_need_no_device():
+    """The 12-bit depth codec rejects bad shapes, pitches and clipping planes
+    on the host, before anything reaches a device (the pointers here are
+    never dereferenced)."""
+    L = fvv.lib()
+    fake = 4096
+    cases = [
+        (fake, 12, 5, 4, 0.5, 10.0, fake, 6),       # odd width
+        (fake, 12, 6, 3, 0.5, 10.0, fake, 6),       # odd height
+        (fake, 10, 6, 4, 0.5, 10.0, fake, 6),       # depth rows too short
+        (fake + 1, 12, 6, 4, 0.5, 10.0, fake, 6),   # depth not 2-byte aligned
+        (fake, 12, 6, 4, 0.5, 10.0, fake, 5),       # odd luma pitch
+        (fake, 12, 6, 4, 0.5, 10.0, fake, 4),       # luma pitch below the width
+        (fake, 12, 6, 4, 10.0, 0.5, fake, 6),       # planes swapped
+        (fake, 12, 6, 4, 0.0, 1.0, fake, 6),        # z_near = 0
+        (fake, 12, 6, 4, 0.5, float("inf"), fake, 6),
+        (None, 12, 6, 4, 0.5, 10.0, fake, 6),
+        (fake, 1 << 16, 1 << 15, 1 << 13, 0.5, 10.0, fake, 1 << 15),   # beyond FVV_MAX_SRC_PIXELS
+    ]
+    for d, dp, W, H, zn, zf, y, yp in cases:
+        assert L.fvv_depth_encode_y12(d, dp, W, H, zn, zf, y, yp, None) == fvv.FVV_E_ARG
+        assert L.fvv_depth_decode_y12(y, yp, W, H, zn, zf, d, dp, None) == fvv.FVV_E_ARG
+        assert L.fvv_last_error(None)
