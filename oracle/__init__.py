@@ -284,6 +284,68 @@ def synthesize(rig, frames, virt, k_nearest: int = 3, tau: float = 0.05, max_fp:
     return res
 
 
+# ---------------------------------------------------------------- OL: layered synthesis
+BG_MM = 0xFFFF      # background signal in live millimetre maps (O3)
+
+
+class _LayerFrame:
+    def __init__(self, rgb, depth_mm):
+        self.rgb = rgb
+        self.depth_mm = depth_mm
+
+
+class _IdentityDepthCamera:
+    """A rig camera whose Eq. 1 correction is the identity (0, 1)."""
+    def __init__(self, cam):
+        self._t = cam.as_tuple()[:8] + (0.0, 1.0)
+
+    def as_tuple(self):
+        return self._t
+
+
+def layer_frames(rig, frames, bg_models):
+    """Per-camera contributions to the two layers (Section VI, the per-camera
+    process): the foreground keeps the live colour and live depth where the
+    depth is not the background signal; the background keeps the live colour
+    with the background model's depth where the live depth is the background
+    signal.  The background model is calibration geometry, so the Eq. 1
+    correction of the live stereo depth is not applied to it (reading).
+    Returns (fg_frames, bg_rig, bg_frames)."""
+    fg, bg = [], []
+    for f, m in zip(frames, bg_models):
+        if f is None:
+            fg.append(None)
+            bg.append(None)
+            continue
+        d = np.asarray(f.depth_mm, np.uint16)
+        is_bg = d == BG_MM
+        fg.append(_LayerFrame(f.rgb, np.where(is_bg, 0, d).astype(np.uint16)))
+        bgd = np.zeros_like(d) if m is None else np.where(is_bg, np.asarray(m, np.uint16), 0).astype(np.uint16)
+        bg.append(_LayerFrame(f.rgb, bgd))
+    return fg, [_IdentityDepthCamera(c) for c in rig], bg
+
+
+def synthesize_layered(rig, frames, bg_models, virt, k_nearest: int = 3, tau: float = 0.05,
+                       max_fp: float = 4.0, fill_mode: int = 0):
+    """Layered FG/BG synthesis (Section VI): each layer is warped, filtered
+    and mixed over the same selected cameras by their distance weights (O1-O6
+    on that layer's frames), the foreground layer is stacked over the
+    background layer wherever it has a blended colour, and the hole fill (O7)
+    runs on the composite.  Returns a dict with 'rgb', the composite 'hole',
+    'depth' and 'blend_rgb', and each layer's taps under 'fg' and 'bg'."""
+    fg_frames, bg_rig, bg_frames = layer_frames(rig, frames, bg_models)
+    rf = synthesize(rig, fg_frames, virt, k_nearest=k_nearest, tau=tau, max_fp=max_fp, fill_mode=1, taps=True)
+    rb = synthesize(bg_rig, bg_frames, virt, k_nearest=k_nearest, tau=tau, max_fp=max_fp, fill_mode=1, taps=True)
+    fg_on = rf["hole"] == 0
+    comp = np.where(fg_on[..., None], rf["blend_rgb"], rb["blend_rgb"]).astype(np.uint8)
+    hole = (~fg_on & (rb["hole"] != 0)).astype(np.uint8)
+    depth = np.where(fg_on, rf["depth"], rb["depth"]).astype(np.float32)
+    comp[hole == 1] = 0
+    depth[hole == 1] = 0
+    return dict(rgb=fill(comp, hole, depth, fill_mode), hole=hole, depth=depth, blend_rgb=comp, fg=rf, bg=rb,
+                sel=rf["sel"], weights=rf["weights"])
+
+
 def key_depth(Z: np.ndarray) -> np.ndarray:
     """float32 depth held in the upper half of each key (garbage for EMPTY)."""
     return (Z >> np.uint64(32)).astype(np.uint32).view(np.float32)

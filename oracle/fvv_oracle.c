@@ -202,7 +202,13 @@ void fvv_ref_pair(const ref_camera *src, const ref_camera *virt, ref_pair *p)
 /* ------------------------------------------------------------------------ */
 /* O3: depth decode.  Millimetres -> metres (float32 division by 1000), then
  * the quadratic correction of Eq. 1, z_post = (alpha z + beta) z, in that
- * operation order.  Code 0 means no depth.  (0, 1) is an exact identity. */
+ * operation order.  (0, 1) is an exact identity.  Two values carry no live
+ * depth: 0 (no depth, e.g. object boundaries) and 0xFFFF, the background
+ * signal (the capture side removes background depth from the live stream,
+ * Section IV-B; the layered synthesis takes it from the background model). */
+#define REF_BG_MM 0xFFFFu
+static inline int ref_has_depth(uint16_t d) { return d != 0 && d != REF_BG_MM; }
+
 float fvv_ref_decode_depth(uint16_t d, float alpha, float beta)
 {
     float z = (float)d / 1000.0f;
@@ -271,7 +277,7 @@ void fvv_ref_splat(const ref_src *src, int32_t K, int32_t W, int32_t H,
         for (int j = 0; j < s->H; ++j) {
             for (int i = 0; i < s->W; ++i) {
                 uint16_t d = s->depth[(int64_t)j * s->depth_pitch + i];
-                if (d == 0) continue;
+                if (!ref_has_depth(d)) continue;
                 float z = fvv_ref_decode_depth(d, s->alpha, s->beta);
                 float q[3];
                 ref_project(p->A, p->a, (float)i, (float)j, z, q);
@@ -429,7 +435,7 @@ void fvv_ref_blend(const uint64_t *Zf, int32_t W, int32_t H, const ref_tex *tex,
                 for (int n = 0; n < 4; ++n) {
                     if (ti[n] < 0 || tj[n] < 0 || ti[n] >= t->W || tj[n] >= t->H) continue;
                     uint16_t d = t->depth[(int64_t)tj[n] * t->depth_pitch + ti[n]];
-                    if (d == 0) continue;
+                    if (!ref_has_depth(d)) continue;
                     float zs = fvv_ref_decode_depth(d, t->alpha, t->beta);
                     if (!(fabsf(zs - q[2]) <= lim)) continue;
                     const uint8_t *px = t->rgb + (int64_t)tj[n] * t->rgb_pitch + (int64_t)ti[n] * 3;
@@ -495,7 +501,7 @@ void fvv_ref_stack(const uint64_t *Zf, int32_t W, int32_t H, const ref_tex *tex,
                     int ii = i0 + (n & 1), jj = j0 + (n >> 1);
                     if (ii < 0 || jj < 0 || ii >= t->W || jj >= t->H) continue;
                     uint16_t d = t->depth[(int64_t)jj * t->depth_pitch + ii];
-                    if (d == 0) continue;
+                    if (!ref_has_depth(d)) continue;
                     float zs = fvv_ref_decode_depth(d, t->alpha, t->beta);
                     if (!(fabsf(zs - q[2]) <= lim)) continue;
                     const uint8_t *px = t->rgb + (int64_t)jj * t->rgb_pitch + (int64_t)ii * 3;
@@ -634,15 +640,15 @@ int32_t fvv_ref_synthesize(const ref_camera *rig, int32_t n,
  * code 1 = no depth, or out of range, read as a rounded value outside
  * 2..4095 (so a depth within half a code of a clipping plane keeps the end
  * code whatever the float32 rounding of the plane); code 0 = the background
- * signal of the paper's layered synthesis (never produced here, decoded as
- * no depth).
+ * signal, 0xFFFF in millimetre maps (O3).
  * Bit re-arrangement of each 2x2 block (p11 p12 / p21 p22) onto I420 planes:
  * Y of each pixel = its 8 LSBs, flipped to 255 - LSBs when its 4 MSBs are
  * odd (Eq. 3); U = the MSBs of p11 and p12 bit-interleaved, V = those of p21
  * and p22.  Reading of the missing figure: bit 2k of U is bit k of p11's
  * MSBs, bit 2k+1 is bit k of p12's (the most variable bits, the low ones,
  * land lowest).
- * Decoding inverts both steps; a code >= 2 becomes
+ * Decoding inverts both steps; code 0 becomes 0xFFFF, code 1 becomes 0, and
+ * a code >= 2 becomes
  * z = 1 / ((Y - 2)/4093 (1/z_near - 1/z_far) + 1/z_far) (double) and then
  * whole millimetres, floor(1000 z + 0.5) clamped to [1, 65535]. */
 static inline uint8_t ref_interleave4(uint32_t a, uint32_t b)
@@ -654,6 +660,7 @@ static inline uint8_t ref_interleave4(uint32_t a, uint32_t b)
 
 uint16_t fvv_ref_depth_code(uint16_t mm, float z_near, float z_far)
 {
+    if (mm == REF_BG_MM) return 0;
     if (mm == 0) return 1;
     double z = (double)mm / 1000.0;
     double zn = (double)z_near, zf = (double)z_far;
@@ -667,7 +674,8 @@ uint16_t fvv_ref_depth_code(uint16_t mm, float z_near, float z_far)
 
 uint16_t fvv_ref_code_depth(uint16_t code, float z_near, float z_far)
 {
-    if (code < 2) return 0;
+    if (code == 0) return REF_BG_MM;
+    if (code == 1) return 0;
     double zn = (double)z_near, zf = (double)z_far;
     double t = (double)(code - 2) / 4093.0;
     double inv = t * (1.0 / zn - 1.0 / zf) + 1.0 / zf;

@@ -33,7 +33,7 @@ import numpy as np
 __all__ = [
     "Camera", "look_at", "arc_camera", "Scene", "Frame", "Workload",
     "random_scene", "config1", "config2", "config3", "config_small",
-    "swing_trajectory",
+    "swing_trajectory", "BG_MM", "capture_layered", "background_model", "background_scene",
 ]
 
 
@@ -321,10 +321,44 @@ def _disc_mask(rng, H, W, frac, rmin, rmax):
     return m
 
 
+# background signal in millimetre depth maps: the capture side of the layered
+# system removes background depth from the live stream (Section IV-B)
+BG_MM = 0xFFFF
+
+
 def capture(scene: Scene, cam: Camera, seed: int, cam_index: int, noise_k=0.0,
             invalid_frac=0.0, invalid_blobs=False, zrange=None) -> Frame:
     """Colour + millimetre depth of one source camera."""
-    rgb, z, _ = scene.render(cam)
+    return _capture(scene, cam, seed, cam_index, noise_k, invalid_frac, invalid_blobs, zrange)[0]
+
+
+def background_scene(scene: Scene) -> Scene:
+    """The static part of a scene (ground and backdrop): the world the
+    background model of each camera is computed from."""
+    return replace(scene, spheres=[], boxes=[])
+
+
+def background_model(scene: Scene, cam: Camera) -> np.ndarray:
+    """Exact millimetre depth of the static background seen by ``cam``
+    (0 where nothing is hit), as a calibration-time model would give it."""
+    _, z, _ = background_scene(scene).render(cam)
+    mm = np.clip(np.floor(np.where(np.isfinite(z), z, 0.0) * 1000.0 + 0.5), 1, BG_MM - 1)
+    return np.where(np.isfinite(z), mm, 0).astype(np.uint16)
+
+
+def capture_layered(scene: Scene, cam: Camera, seed: int, cam_index: int, noise_k=0.0,
+                    invalid_frac=0.0, invalid_blobs=False) -> Frame:
+    """Live frame of the layered system: colour everywhere; depth only on
+    foreground pixels (objects), with the same noise and dropouts as
+    ``capture``; pixels whose colour shows the background (ground, backdrop,
+    sky) carry BG_MM.  The foreground/background classification is exact."""
+    f, pid = _capture(scene, cam, seed, cam_index, noise_k, invalid_frac, invalid_blobs, None)
+    depth = np.where(pid >= 2, f.depth_mm, BG_MM).astype(np.uint16)
+    return Frame(f.rgb, depth)
+
+
+def _capture(scene, cam, seed, cam_index, noise_k, invalid_frac, invalid_blobs, zrange):
+    rgb, z, pid = scene.render(cam)
     rng = np.random.Generator(np.random.Philox(key=[seed & 0xFFFFFFFF, 0x5EED0000 + cam_index]))
     valid = np.isfinite(z)
     zn = np.where(valid, z, 0.0)
@@ -339,7 +373,7 @@ def capture(scene: Scene, cam: Camera, seed: int, cam_index: int, noise_k=0.0,
             valid &= rng.random(z.shape) >= invalid_frac
     mm = np.clip(np.floor(zn * 1000.0 + 0.5), 1, 65535)
     depth = np.where(valid, mm, 0).astype(np.uint16)
-    return Frame(rgb, depth)
+    return Frame(rgb, depth), pid
 
 
 @dataclass
@@ -351,6 +385,7 @@ class Workload:
     virtual: List[Camera]
     scene: Scene
     k_nearest: int = 3
+    bg_models: Optional[List[np.ndarray]] = None   # layered workloads: per-camera background depth (mm)
 
 
 def config1(seed: int = 0) -> Workload:
@@ -398,32 +433,39 @@ def config2(seed: int = 0) -> Workload:
 
 
 def config3(seed: int = 0, n_frames: int = 60, out_w: int = 1920, out_h: int = 1080,
-            src_w: int = 1280, src_h: int = 720) -> Workload:
+            src_w: int = 1280, src_h: int = 720, layered: bool = False) -> Workload:
     """9 cameras 1280x720 (hFOV 60 deg) on a 2.5 m arc, -60..+60 deg every
     15 deg, sigma = 0.003 z^2, 10% invalid as discs of radius 4-24 px; a
     60-frame swing trajectory from -60 to +60 deg rendered at 1920x1080 with
-    the same field of view (1.5x magnification)."""
+    the same field of view (1.5x magnification).  layered: live depth on the
+    objects only (background signalled) plus exact background models."""
     rng = np.random.default_rng(3000 + seed)
     scene = random_scene(rng, n_spheres=4, n_boxes=4, salt=seed)
     angles = [-60.0 + 15.0 * k for k in range(9)]
     rig = [arc_camera(a, 2.5, src_w, src_h) for a in angles]
-    frames = [capture(scene, c, seed, k, noise_k=0.003, invalid_frac=0.10, invalid_blobs=True)
+    cap = capture_layered if layered else capture
+    frames = [cap(scene, c, seed, k, noise_k=0.003, invalid_frac=0.10, invalid_blobs=True)
               for k, c in enumerate(rig)]
     virt = swing_trajectory(n_frames, -60.0, 60.0, 2.5, out_w, out_h)
-    return Workload("c3_9cam_1280x720_to_1920x1080", rig, frames, virt, scene)
+    bgm = [background_model(scene, c) for c in rig] if layered else None
+    return Workload("c3_9cam_1280x720_to_1920x1080" + ("_layered" if layered else ""), rig, frames, virt,
+                    scene, bg_models=bgm)
 
 
 def config_small(seed: int = 0, n_cams: int = 3, w: int = 96, h: int = 64,
                  out_w: int = 128, out_h: int = 80, n_virtual: int = 3,
-                 noise_k: float = 0.002, invalid_frac: float = 0.05) -> Workload:
+                 noise_k: float = 0.002, invalid_frac: float = 0.05, layered: bool = False) -> Workload:
     """A scaled-down config-3-like rig for fast tests (several tiles and a
     ragged tail at small sizes)."""
     rng = np.random.default_rng(5000 + seed)
     scene = random_scene(rng, salt=seed)
     angles = [(-15.0 * (n_cams - 1) / 2.0) + 15.0 * k for k in range(n_cams)]
     rig = [arc_camera(a, 2.2, w, h) for a in angles]
-    frames = [capture(scene, c, seed, k, noise_k=noise_k, invalid_frac=invalid_frac)
+    cap = capture_layered if layered else capture
+    frames = [cap(scene, c, seed, k, noise_k=noise_k, invalid_frac=invalid_frac)
               for k, c in enumerate(rig)]
     virt = [arc_camera(a, 2.2, out_w, out_h) for a in
             np.linspace(angles[0] - 3.0, angles[-1] + 3.0, n_virtual)]
-    return Workload(f"small_{n_cams}cam_{w}x{h}", rig, frames, virt, scene)
+    bgm = [background_model(scene, c) for c in rig] if layered else None
+    return Workload(f"small_{n_cams}cam_{w}x{h}" + ("_layered" if layered else ""), rig, frames, virt, scene,
+                    bg_models=bgm)

@@ -83,7 +83,8 @@ def exact_code(mm, zn, zf):
 def test_quantiser_range_monotone_and_rounding(zn, zf):
     mm = np.arange(0, 65536, dtype=np.uint16).reshape(256, 256)
     codes = oracle.depth_codes(mm, zn, zf).reshape(-1).astype(int)
-    assert codes[0] == 1
+    assert codes[0] == 1 and codes[65535] == 0
+    codes[65535] = 1            # the background signal; beyond z_far otherwise
     lo, hi = int(np.ceil(zn * 1000)), int(np.floor(zf * 1000))
     # the clipping planes and everything between them take codes 2..4095
     c = codes[lo:hi + 1]
@@ -111,7 +112,7 @@ def test_quantiser_range_monotone_and_rounding(zn, zf):
 def test_dequantiser_inverts_the_quantiser(zn, zf):
     codes = np.arange(4096, dtype=np.uint16).reshape(64, 64)
     mm = oracle.codes_depth(codes, zn, zf).reshape(-1).astype(int)
-    assert mm[0] == 0 and mm[1] == 0
+    assert mm[0] == 65535 and mm[1] == 0
     d = mm[2:]
     assert np.all(np.diff(d) <= 0)
     assert d.min() == round(zn * 1000) and d.max() == round(zf * 1000)
