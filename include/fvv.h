@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define FVV_ABI_VERSION 3
+#define FVV_ABI_VERSION 4
 
 /* status codes */
 enum {
@@ -54,7 +54,9 @@ enum {
 
 enum { FVV_MEM_HOST = 0, FVV_MEM_DEVICE = 1 };
 enum { FVV_FILL_BG = 0, FVV_FILL_NONE = 1 };
-enum { FVV_PATH_PLAIN = 0, FVV_PATH_LEARNED = 1 };
+enum { FVV_PATH_PLAIN = 0, FVV_PATH_LEARNED = 1, FVV_PATH_LAYERED = 2 };
+
+#define FVV_BG_MM 0xFFFF             /* background signal in millimetre depth maps */
 
 /* limits */
 #define FVV_MAX_CAMERAS 32          /* rig size; the camera index fits 5 key bits */
@@ -77,7 +79,9 @@ typedef struct {
 } fvv_camera;
 
 /* One camera's MVD frame.  rgb: height rows of width*3 bytes; depth_mm:
- * height rows of width uint16 millimetres (0 = no depth), or, once the
+ * height rows of width uint16 millimetres (0 = no depth; FVV_BG_MM = the
+ * background signal: the pixel shows the static background, whose depth
+ * the layered synthesis takes from the background model), or, once the
  * context's depth format is FVV_DEPTH_Y12, the 12-bit coded I420 image of
  * fvv_depth_encode_y12 with depth_pitch as its luma pitch.  Both NULL marks
  * the camera as absent from this frame set: it is then never selected. */
@@ -97,10 +101,12 @@ typedef struct {
     float max_footprint;    /* splat footprint cap in output pixels (default 4) */
     int32_t fill_mode;      /* FVV_FILL_BG (default) or FVV_FILL_NONE (holes
                                stay black, as in the paper's system, Section IX) */
-    int32_t path;           /* FVV_PATH_PLAIN, or FVV_PATH_LEARNED: the network
+    int32_t path;           /* FVV_PATH_PLAIN; FVV_PATH_LEARNED: the network
                                loaded with fvv_net_load replaces the blend and
                                hole fill (plain result where no network is
-                               loaded or its output is not finite) */
+                               loaded or its output is not finite);
+                               FVV_PATH_LAYERED: foreground and background
+                               layers (fvv_set_bg_model), k_nearest <= 4 */
     uint32_t exclude_mask;  /* rig cameras c with bit c set are not selected
                                (leave-one-camera-out evaluation); 0 = none */
     uint64_t frame_version; /* 0 = latest uploaded frame set, else that version
@@ -144,14 +150,14 @@ int32_t fvv_upload_mvd(fvv_ctx *ctx, const fvv_view *views, int32_t n, int32_t m
  * between the clipping planes z_near and z_far, metres):
  *   code = round(4093 (1/z - 1/z_far) / (1/z_near - 1/z_far) + 2),
  * evaluated in double precision and rounded half up; 1 = no depth (0 mm) or
- * a rounded code outside 2..4095; 0 is reserved for background pixels (it
- * decodes as no depth).  Each 2x2 block p11 p12 / p21 p22 of codes becomes
+ * a rounded code outside 2..4095; 0 = the background signal (FVV_BG_MM).
+ * Each 2x2 block p11 p12 / p21 p22 of codes becomes
  * one 2x2 block of an I420 image: Y = the code's 8 LSBs, mirrored to
  * 255 - LSBs when its 4 MSBs are odd (Eq. 3); U = the MSBs of p11 on the
  * even bits and of p12 on the odd bits; V = the same for p21 and p22.
  * Decoding inverts both steps and returns whole millimetres,
- * round(1000 / ((code - 2)/4093 (1/z_near - 1/z_far) + 1/z_far)), 0 for
- * codes 0 and 1.
+ * round(1000 / ((code - 2)/4093 (1/z_near - 1/z_far) + 1/z_far)),
+ * FVV_BG_MM for code 0 and 0 for code 1.
  *
  * I420 layout (yuv): height rows of y_pitch bytes (Y), then U and V, each
  * height/2 rows of y_pitch/2 bytes.  y_pitch even and >= width; width and
@@ -174,6 +180,24 @@ int32_t fvv_depth_decode_y12(const void *yuv, int64_t y_pitch, int32_t width, in
  * sets are not affected. */
 enum { FVV_DEPTH_MM16 = 0, FVV_DEPTH_Y12 = 1 };
 int32_t fvv_set_depth_format(fvv_ctx *ctx, int32_t format, float z_near, float z_far);
+
+/* Background models of the layered synthesis (Section VI): per rig camera,
+ * the depth of the static background in uint16 millimetres (height rows of
+ * width values, pitches[c] bytes per row; 0 = no background there), computed
+ * at calibration; depth_mm[c] NULL = no model for camera c (its background
+ * layer stays empty); depth_mm NULL clears every model.  Copied into the
+ * context (host or device memory per mem_kind; the call returns when the
+ * copy is done).  The models are calibrated geometry: Eq. (1) is not
+ * applied to them.  Frame sets uploaded afterwards carry, per camera, a
+ * foreground layer (live depth where it is not FVV_BG_MM) and a background
+ * layer (the model's depth under the live colour of FVV_BG_MM pixels); the
+ * call drops resident frame sets (FVV_E_STATE until the next upload).  The
+ * layered synthesis warps, filters and mixes each layer over the same
+ * selected cameras and stacks the foreground layer over the background
+ * layer before the hole fill.  FVV_E_STATE while the server runs or
+ * without a rig; a rig change clears the models. */
+int32_t fvv_set_bg_model(fvv_ctx *ctx, const void *const *depth_mm, const int64_t *pitches, int32_t n,
+                         int32_t mem_kind, void *stream);
 
 /* Render one virtual camera into out_rgb8 (height rows of width*3 bytes,
  * pitch out_pitch; host or device per mem_kind).  Steps, all on the GPU:
@@ -210,8 +234,12 @@ int32_t fvv_pair_matrices(const fvv_camera *src, const fvv_camera *virt, float *
  *     key = float32 depth bits << 32 | camera << 27 | source pixel index,
  *     0xFFFFFFFFFFFFFFFF = empty;
  *   FVV_TAP_BLEND: uint32 RGBA8 per pixel, A = 255 covered, 0 hole;
- *   FVV_TAP_DEPTH: float32 depth per pixel (0 for holes). */
-enum { FVV_TAP_Z_RAW = 0, FVV_TAP_Z_FILT = 1, FVV_TAP_BLEND = 2, FVV_TAP_DEPTH = 3 };
+ *   FVV_TAP_DEPTH: float32 depth per pixel (0 for holes);
+ *   FVV_TAP_BG_Z_RAW, FVV_TAP_BG_Z_FILT (layered synthesis only): the
+ *     background layer's key maps; the first two taps then hold the
+ *     foreground layer's, BLEND and DEPTH the composite. */
+enum { FVV_TAP_Z_RAW = 0, FVV_TAP_Z_FILT = 1, FVV_TAP_BLEND = 2, FVV_TAP_DEPTH = 3, FVV_TAP_BG_Z_RAW = 4,
+       FVV_TAP_BG_Z_FILT = 5 };
 int32_t fvv_set_debug(fvv_ctx *ctx, int32_t enable);
 int32_t fvv_debug_read(fvv_ctx *ctx, int32_t tap, void *host_out, int64_t bytes);
 

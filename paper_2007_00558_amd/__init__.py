@@ -21,8 +21,9 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libfvv.so")
 FVV_OK, FVV_E_ARG, FVV_E_STATE, FVV_E_NOMEM, FVV_E_DEVICE, FVV_E_AGAIN, FVV_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 MEM_HOST, MEM_DEVICE = 0, 1
 FILL_BG, FILL_NONE = 0, 1
-PATH_PLAIN, PATH_LEARNED = 0, 1
-TAP_Z_RAW, TAP_Z_FILT, TAP_BLEND, TAP_DEPTH = 0, 1, 2, 3
+PATH_PLAIN, PATH_LEARNED, PATH_LAYERED = 0, 1, 2
+TAP_Z_RAW, TAP_Z_FILT, TAP_BLEND, TAP_DEPTH, TAP_BG_Z_RAW, TAP_BG_Z_FILT = 0, 1, 2, 3, 4, 5
+BG_MM = 0xFFFF          # background signal in millimetre depth maps
 KEY_EMPTY = np.uint64(0xFFFFFFFFFFFFFFFF)
 
 ERROR_NAMES = {0: "FVV_OK", -1: "FVV_E_ARG", -2: "FVV_E_STATE", -3: "FVV_E_NOMEM",
@@ -108,6 +109,7 @@ def lib():
             "fvv_depth_encode_y12": (I32, [P, I64, I32, I32, C.c_float, C.c_float, P, I64, P]),
             "fvv_depth_decode_y12": (I32, [P, I64, I32, I32, C.c_float, C.c_float, P, I64, P]),
             "fvv_set_depth_format": (I32, [P, I32, C.c_float, C.c_float]),
+            "fvv_set_bg_model": (I32, [P, P, P, I32, I32, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -125,7 +127,7 @@ EXPORTED = ("fvv_abi_version", "fvv_create", "fvv_destroy", "fvv_last_error", "f
             "fvv_net_param_count", "fvv_net_layer_info", "fvv_net_layer_name", "fvv_net_load",
             "fvv_net_read", "fvv_make_stack", "fvv_net_forward", "fvv_net_train_step",
             "fvv_net_read_act", "fvv_net_device_bytes", "fvv_depth_encode_y12",
-            "fvv_depth_decode_y12", "fvv_set_depth_format")
+            "fvv_depth_decode_y12", "fvv_set_depth_format", "fvv_set_bg_model")
 DEPTH_MM16, DEPTH_Y12 = 0, 1
 NET_PARAMS, NET_GRADS = 0, 1
 NET_ALIGN = 8           # network inputs: multiples of 8 in both dimensions
@@ -300,6 +302,29 @@ class Context:
         self._check(self._L.fvv_set_depth_format(self._h, fmt, z_near, z_far))
         self.depth_format = fmt
 
+    def set_bg_model(self, models: Optional[Sequence], mem: int = MEM_HOST, stream=None):
+        """Background depth models (layered synthesis): models[c] a (H,W)
+        uint16 millimetre map (numpy for MEM_HOST, torch CUDA tensor for
+        MEM_DEVICE) or None; models=None clears them.  Drops resident frame
+        sets."""
+        if models is None:
+            self._check(self._L.fvv_set_bg_model(self._h, None, None, 0, mem, None))
+            return
+        n = len(models)
+        keep = []
+        ptrs = (C.c_void_p * n)()
+        pitches = np.zeros(n, np.int64)
+        for k, m in enumerate(models):
+            if m is None:
+                continue
+            if mem == MEM_HOST:
+                m = np.ascontiguousarray(m, np.uint16)
+            keep.append(m)
+            ptrs[k] = _addr(m)
+            pitches[k] = _pitch(m, 0)
+        s = None if mem == MEM_HOST and stream is None else _stream_handle(stream)
+        self._check(self._L.fvv_set_bg_model(self._h, ptrs, pitches.ctypes.data, n, mem, s))
+
     def upload_mvd(self, frames: Sequence, mem: int = MEM_HOST, stream=None) -> int:
         """frames[c] = (rgb (H,W,3) uint8, depth) -- numpy for MEM_HOST, torch
         CUDA tensors for MEM_DEVICE -- or None if absent.  depth is (H,W)
@@ -409,7 +434,7 @@ class Context:
 
     def debug_read(self, tap: int, shape):
         dtype = {TAP_Z_RAW: np.uint64, TAP_Z_FILT: np.uint64, TAP_BLEND: np.uint32,
-                 TAP_DEPTH: np.float32}[tap]
+                 TAP_DEPTH: np.float32, TAP_BG_Z_RAW: np.uint64, TAP_BG_Z_FILT: np.uint64}[tap]
         a = np.empty(shape, dtype)
         self._check(self._L.fvv_debug_read(self._h, tap, a.ctypes.data, a.nbytes))
         return a

@@ -11,6 +11,7 @@
 #define FVV_KMAX 8
 #define FVV_KEY_EMPTY 0xFFFFFFFFFFFFFFFFull
 #define FVV_NO_DEPTH 0xFFFFFFFFu    // depth-plane marker of a pixel without depth
+#define FVV_BG_MM 0xFFFFu           // background signal of live millimetre maps (no live depth)
 #define FVV_HOLE 0x80000000u        // slot of a hole filled inside its tile (or left black)
 #define FVV_HOLE_OPEN 0x80000001u   // slot of a hole whose neighbours lie beyond its tile
 #define FVV_ZCLIP 0.01f             // points and samples nearer than this are dropped
@@ -38,17 +39,18 @@ struct fvv_src_desc {
 
 // One virtual view of a batched synthesis call.
 struct fvv_view_desc {
-    int32_t W, H, K, fill_mode;
+    int32_t W, H, K, fill_mode;     // K selected cameras
     float tau, max_fp;
     int32_t ntx, nty;       // output tiles per row / column
     int32_t blk_stride;     // bbox entries reserved per camera slot (>= max nblk)
     int32_t tile_cap;       // bin-list entries per tile
     int32_t view;           // index of this view in the batch
-    int32_t pad0;
+    int32_t layered;        // layered synthesis: src[0..K) foreground layers,
+                            // src[K..2K) background layers of the same cameras
     // binning
     int32_t *counts;        // ntx*nty tile counters (zero between calls; cleared by the tile kernel)
-    int32_t *list;          // ntx*nty*tile_cap entries: camera slot << 24 | source block
-    int4 *bbox;             // K*blk_stride tile ranges (x0, x1, y0, y1; x0 > x1 = empty)
+    int32_t *list;          // ntx*nty*tile_cap entries: source slot << 24 | source block
+    int4 *bbox;             // nsrc*blk_stride tile ranges (x0, x1, y0, y1; x0 > x1 = empty)
     // per-tile results
     uint32_t *slot;         // W*H depth bits of covered pixels / FVV_HOLE / FVV_HOLE_OPEN
     int2 *rowsum;           // ntx*nty*FVV_TILE (first, last) covered x of each tile row
@@ -60,13 +62,18 @@ struct fvv_view_desc {
     // learned path: network input [stack_h][stack_w][32] bf16 (null = plain view)
     uint16_t *stack;
     int32_t stack_w, stack_h;   // W, H rounded up to multiples of 8
-    // debug taps (null unless enabled)
+    // debug taps (null unless enabled); dbg_bz / dbg_bzf: background layer
     unsigned long long *dbg_z;
     unsigned long long *dbg_zf;
+    unsigned long long *dbg_bz;
+    unsigned long long *dbg_bzf;
     uint32_t *dbg_rgba;
     float *dbg_depth;
     fvv_src_desc src[FVV_KMAX];
 };
+
+// source slots of a view: one per selected camera, two when layered
+__host__ __device__ inline int fvv_nsrc(const fvv_view_desc &d) { return d.layered ? 2 * d.K : d.K; }
 
 // Stage timing: when a context has profiling on, every kernel launch is
 // bracketed by a pair of HIP events on its stream; durations are summed per
@@ -117,13 +124,14 @@ inline void fvv_prof_end(fvv_prof *p, hipStream_t s, int stage, hipEvent_t e0)
 // Launch geometry of one batched synthesis call.
 struct fvv_batch_dims {
     int n_views;
-    int max_k;            // largest K of the batch
+    int max_k;            // largest source-slot count of the batch
     int max_blocks;       // largest source-block count of a selected camera
     int max_tiles_x;      // largest ntx
     int max_tiles_y;      // largest nty
     int total_tiles;      // tiles of all views
     bool fill_bg;         // any view fills holes
     bool any_stack;       // any view writes a learned-path stack
+    bool any_layered;     // any view is layered (no view is both)
 };
 
 // Ingest of one frame set: every present camera's caller buffers (device
@@ -139,6 +147,11 @@ struct fvv_repack_cam {
     float *depth_out;
     int32_t W, H;
     float alpha, beta;      // Eq. (1)
+    // layered frame sets: the camera's background model (uint16 mm, W per
+    // row; null = none) and the background-layer planes it fills
+    const uint16_t *bg_model;
+    uint2 *bg_texel_out;
+    float *bg_depth_out;
 };
 struct fvv_repack_batch {
     int32_t n;

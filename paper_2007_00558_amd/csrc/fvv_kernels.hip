@@ -113,7 +113,9 @@ __device__ __forceinline__ float wave_maxf(float v)
 // ---------------------------------------------------------------- repack
 // One thread per source pixel (grid.z = camera): 8-byte texel {RGBA8,
 // decoded depth bits} for the backward gathers and the decoded depth plane
-// for the splat.
+// for the splat.  Millimetres 0 and 0xFFFF (the background signal) carry no
+// live depth.  With a background model the background layer's texel and
+// depth planes are written too (layered synthesis, Section VI).
 __global__ void __launch_bounds__(256) k_repack(const fvv_repack_batch b)
 {
     const fvv_repack_cam &c = b.cam[blockIdx.z];
@@ -134,13 +136,23 @@ __global__ void __launch_bounds__(256) k_repack(const fvv_repack_batch b)
         d = *(const uint16_t *)(c.depth + (int64_t)y * c.depth_pitch + (int64_t)x * 2);
     }
     uint32_t zb = FVV_NO_DEPTH;
-    if (d != 0) {
+    if (d != 0 && d != FVV_BG_MM) {
         const float z = __fdiv_rn((float)d, 1000.0f);
         const float s = __fadd_rn(__fmul_rn(c.alpha, z), c.beta);   // Eq. (1): (alpha z + beta) z
         zb = f2u(__fmul_rn(s, z));
     }
-    c.texel_out[(int64_t)y * c.W + x] = make_uint2(col, zb);
-    c.depth_out[(int64_t)y * c.W + x] = u2f(zb);
+    const int64_t o = (int64_t)y * c.W + x;
+    c.texel_out[o] = make_uint2(col, zb);
+    c.depth_out[o] = u2f(zb);
+    if (c.bg_texel_out) {
+        // background layer: the model's depth (calibrated geometry, no Eq. 1)
+        // under the live colour of pixels that carry the background signal
+        uint32_t bz = FVV_NO_DEPTH;
+        const uint32_t m = c.bg_model ? c.bg_model[o] : 0u;
+        if (d == FVV_BG_MM && m != 0 && m != FVV_BG_MM) bz = f2u(__fdiv_rn((float)m, 1000.0f));
+        c.bg_texel_out[o] = make_uint2(col, bz);
+        c.bg_depth_out[o] = u2f(bz);
+    }
 }
 
 // ---------------------------------------------------------------- descriptors
@@ -192,7 +204,7 @@ __global__ void __launch_bounds__(256) k_bin(const fvv_view_desc *__restrict__ v
     const int k = blockIdx.y;
     const int lane = threadIdx.x & 63;
     const int blk = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (k >= vd.K) return;
+    if (k >= fvv_nsrc(vd)) return;
     const fvv_src_desc &s = vd.src[k];
     if (blk >= s.nblk) return;
     const int by = blk / s.nbx, bx = blk - by * s.nbx;
@@ -280,14 +292,15 @@ __device__ __forceinline__ unsigned long long filter_key(unsigned long long c, u
 }
 
 // ---------------------------------------------------------------- blend
-// Backward warp of output pixel (x, y) at depth zf into every selected
-// camera; taps whose source depth agrees with the warped depth within tau
-// are mixed bilinearly, cameras by their distance weights.  Returns true and
-// the RGBA8 colour if any camera contributes.
-__device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int x, int y, float zf, uint32_t &rgba)
+// Backward warp of output pixel (x, y) at depth zf into the K source slots
+// from k0 (one layer's selected cameras); taps whose source depth agrees with
+// the warped depth within tau are mixed bilinearly, cameras by their
+// distance weights.  Returns true and the RGBA8 colour if any camera
+// contributes.
+__device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int k0, int x, int y, float zf, uint32_t &rgba)
 {
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, wsum = 0.f;
-    for (int k = 0; k < vd.K; ++k) {
+    for (int k = k0; k < k0 + vd.K; ++k) {
         const fvv_src_desc &s = vd.src[k];
         float q0, q1, q2;
         project(s.B, s.b, (float)x, (float)y, zf, q0, q1, q2);
@@ -420,7 +433,7 @@ __device__ __forceinline__ void offer(Cand &b, float z, int dist, int idx)
 // ---------------------------------------------------------------- fused tile
 // STACK: views may carry a learned-path stack (a separate instantiation, so
 // the plain kernel keeps its register budget and occupancy).
-template <bool STACK>
+template <bool STACK, bool LAYERED>
 __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ views, int mtx, int mty, int n_views)
 {
     // XCD-aware order: workgroups are dealt to the 8 XCDs round-robin, so
@@ -442,13 +455,16 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
     const int X0 = tx * T, Y0 = ty * T;
     const int WX0 = X0 - 1, WY0 = Y0 - 1;
     const int tw = min(T, W - X0), th = min(T, H - Y0);
-    __shared__ unsigned long long zk[WN * WN];
+    // z-buffer window(s): layered views keep the foreground layer in the
+    // first and the background layer in the second
+    constexpr int NZ = LAYERED ? 2 * WN * WN : WN * WN;
+    __shared__ unsigned long long zk[NZ];
     __shared__ uint32_t s_slot[T * T];
     __shared__ uint32_t s_rgb[T * T];
     __shared__ int s_open;
     const int t = threadIdx.x;
     const int n_entries = vd.counts[tile];
-    for (int e = t; e < WN * WN; e += TNT) zk[e] = FVV_KEY_EMPTY;
+    for (int e = t; e < NZ; e += TNT) zk[e] = FVV_KEY_EMPTY;
     if (t == 0) s_open = 0;
     __syncthreads();
 
@@ -476,8 +492,9 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
         if (!splat_point(s, W, H, vd.max_fp, i, j, u2f(zb), f)) return;
         const int xa = max(f.x0, WX0), xb = min(f.x1, WX0 + WN - 1);
         const int ya = max(f.y0, WY0), yb = min(f.y1, WY0 + WN - 1);
+        unsigned long long *zl = (LAYERED && (ent >> 24) >= vd.K) ? zk + WN * WN : zk;
         for (int y = ya; y <= yb; ++y)
-            for (int x = xa; x <= xb; ++x) atomicMin(&zk[(y - WY0) * WN + (x - WX0)], f.key);
+            for (int x = xa; x <= xb; ++x) atomicMin(&zl[(y - WY0) * WN + (x - WX0)], f.key);
     };
     if (!scan_all) {
         // The wave's entries are e = wave + TNW q.  They are read 64 at a time
@@ -518,7 +535,7 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
         }
     } else {
         // more entries than the list holds: test every block's tile range
-        for (int e = wave; e < vd.K * vd.blk_stride; e += TNW) {
+        for (int e = wave; e < fvv_nsrc(vd) * vd.blk_stride; e += TNW) {
             const int k = e / vd.blk_stride, blk = e - k * vd.blk_stride;
             if (blk >= vd.src[k].nblk) continue;
             const int4 r = vd.bbox[e];
@@ -552,12 +569,36 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
             if (kf != FVV_KEY_EMPTY) {
                 const float zf = u2f((uint32_t)(kf >> 32));
                 uint32_t col;
-                if (blend_pixel(vd, x, y, zf, col)) {
+                if (blend_pixel(vd, 0, x, y, zf, col)) {
                     pslot[q] = f2u(zf);
                     prgb[q] = col;
                 }
             }
             const int64_t o = (int64_t)y * W + x;
+            if (LAYERED) {
+                // the background layer shows wherever the foreground layer
+                // has no colour (the foreground is stacked over it)
+                const bool tap = vd.dbg_bz != nullptr;
+                if ((pslot[q] & FVV_HOLE) || tap) {
+                    const unsigned long long *zb = zk + WN * WN + ly * WN + lx0 + q;
+                    const unsigned long long cb = zb[WN + 1];
+                    unsigned long long nbb[8] = {zb[0], zb[1], zb[2], zb[WN], zb[WN + 2], zb[2 * WN], zb[2 * WN + 1],
+                                                 zb[2 * WN + 2]};
+                    const unsigned long long kb = filter_key(cb, nbb, vd.tau);
+                    if ((pslot[q] & FVV_HOLE) && kb != FVV_KEY_EMPTY) {
+                        const float zf = u2f((uint32_t)(kb >> 32));
+                        uint32_t col;
+                        if (blend_pixel(vd, vd.K, x, y, zf, col)) {
+                            pslot[q] = f2u(zf);
+                            prgb[q] = col;
+                        }
+                    }
+                    if (tap) {
+                        vd.dbg_bz[o] = cb;
+                        vd.dbg_bzf[o] = kb;
+                    }
+                }
+            }
             if (vd.dbg_z) vd.dbg_z[o] = c;
             if (vd.dbg_zf) vd.dbg_zf[o] = kf;
             if (vd.dbg_rgba) vd.dbg_rgba[o] = prgb[q];
@@ -655,13 +696,31 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
 __global__ void __launch_bounds__(TNT) __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_tile_plain(const fvv_view_desc *__restrict__ views, int mtx, int mty, int n_views)
 {
-    tile_body<false>(views, mtx, mty, n_views);
+    tile_body<false, false>(views, mtx, mty, n_views);
 }
 
 __global__ void __launch_bounds__(TNT) k_tile_stack(const fvv_view_desc *__restrict__ views, int mtx, int mty,
                                                     int n_views)
 {
-    tile_body<true>(views, mtx, mty, n_views);
+    tile_body<true, false>(views, mtx, mty, n_views);
+}
+
+// Layered synthesis (Section VI): foreground and background layers splatted
+// into their own LDS z-buffers, each filtered and mixed over its own source
+// slots, the foreground stacked over the background.  Plain views of a batch
+// that also holds layered views run here too (their second window stays
+// empty), and a batch that also holds learned views takes the variant that
+// writes their stacks.  The two windows bound occupancy to 5 workgroups per
+// CU through LDS, so registers are not capped.
+__global__ void __launch_bounds__(TNT) k_tile_layered(const fvv_view_desc *__restrict__ views, int mtx, int mty, int n_views)
+{
+    tile_body<false, true>(views, mtx, mty, n_views);
+}
+
+__global__ void __launch_bounds__(TNT) k_tile_stack_layered(const fvv_view_desc *__restrict__ views, int mtx,
+                                                            int mty, int n_views)
+{
+    tile_body<true, true>(views, mtx, mty, n_views);
 }
 
 // ---------------------------------------------------------------- open holes
@@ -794,7 +853,13 @@ hipError_t fvv_launch_synthesis(const fvv_view_desc *h_views, fvv_view_desc *d_v
         // 1-D dispatch of every (view, tile), rounded up to whole XCD rounds
         const int total = b.max_tiles_x * b.max_tiles_y * b.n_views;
         const dim3 grid((total + FVV_XCDS - 1) / FVV_XCDS * FVV_XCDS);
-        if (b.any_stack)
+        if (b.any_layered && b.any_stack)
+            hipLaunchKernelGGL(k_tile_stack_layered, grid, dim3(TNT), 0, s, d_views, b.max_tiles_x, b.max_tiles_y,
+                               b.n_views);
+        else if (b.any_layered)
+            hipLaunchKernelGGL(k_tile_layered, grid, dim3(TNT), 0, s, d_views, b.max_tiles_x, b.max_tiles_y,
+                               b.n_views);
+        else if (b.any_stack)
             hipLaunchKernelGGL(k_tile_stack, grid, dim3(TNT), 0, s, d_views, b.max_tiles_x, b.max_tiles_y, b.n_views);
         else
             hipLaunchKernelGGL(k_tile_plain, grid, dim3(TNT), 0, s, d_views, b.max_tiles_x, b.max_tiles_y, b.n_views);

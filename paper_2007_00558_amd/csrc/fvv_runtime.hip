@@ -50,6 +50,9 @@ struct FrameSlot {
     uint64_t version = 0;                 // 0 = empty
     std::vector<uint2 *> texel;           // per camera {RGBA8, depth bits}
     std::vector<float *> depth;
+    std::vector<uint2 *> bg_texel;        // layered sets: background layer of each camera
+    std::vector<float *> bg_depth;
+    bool layered = false;                 // holds background layers
     std::vector<int32_t> present;
     hipEvent_t ready = nullptr;           // recorded after the repack
     std::vector<std::pair<hipStream_t, hipEvent_t>> readers;
@@ -77,6 +80,7 @@ struct Workspace {
 
 struct ViewLayout {
     int ntx, nty, n_tiles, blk_stride, tile_cap, K;
+    int nsrc;             // source slots: K, or 2K when layered
     int32_t idx[FVV_MAX_K];
     double w[FVV_MAX_K];
 };
@@ -139,6 +143,10 @@ struct fvv_ctx {
     int latest = -1;
     uint64_t next_version = 1;
     std::vector<hipEvent_t> event_pool;
+    // background models of the layered synthesis: uint16 mm per camera
+    // (width per row; null = none), set while has_bg
+    std::vector<uint16_t *> bg_model;
+    bool has_bg = false;
     // depth format of uploads (FVV_DEPTH_*) and the clipping planes of the
     // 12-bit coding
     int32_t depth_format = FVV_DEPTH_MM16;
@@ -152,6 +160,9 @@ struct fvv_ctx {
     bool debug = false;
     unsigned long long *dbg_z = nullptr;
     unsigned long long *dbg_zf = nullptr;
+    unsigned long long *dbg_bz = nullptr;     // background layer (layered views)
+    unsigned long long *dbg_bzf = nullptr;
+    bool last_layered = false;
     uint32_t *dbg_rgba = nullptr;
     float *dbg_depth = nullptr;
     size_t dbg_px = 0;
@@ -339,24 +350,26 @@ size_t view_ws_bytes(int W, int H, const ViewLayout &L, bool host_out, bool lear
     size_t b = align256(px * 4);                                   // slot
     b += align256(nt * FVV_TILE * sizeof(int2)) * 2;               // rowsum, colsum
     b += align256(nt * (size_t)L.tile_cap * 4);                    // bin lists
-    b += align256((size_t)L.K * L.blk_stride * sizeof(int4));      // block tile ranges
+    b += align256((size_t)L.nsrc * L.blk_stride * sizeof(int4));   // block tile ranges
     if (host_out) b += align256(px * 3);
     if (learned) b += align256(stack_bytes(W, H));
     return b;
 }
 
 // Tile grid and list sizes of a view drawing on K cameras of the rig whose
-// block counts are given; used both for exact layouts and for upper bounds.
-void layout_sizes(ViewLayout &L, int W, int H, const int *nblk, int K)
+// block counts are given (each twice when layered); used both for exact
+// layouts and for upper bounds.
+void layout_sizes(ViewLayout &L, int W, int H, const int *nblk, int K, bool layered)
 {
     L.K = K;
+    L.nsrc = layered ? 2 * K : K;
     L.ntx = (W + FVV_TILE - 1) / FVV_TILE;
     L.nty = (H + FVV_TILE - 1) / FVV_TILE;
     L.n_tiles = L.ntx * L.nty;
     int sum = 0, mx = 0;
-    for (int k = 0; k < K; ++k) {
-        sum += nblk[k];
-        mx = std::max(mx, nblk[k]);
+    for (int k = 0; k < L.nsrc; ++k) {
+        sum += nblk[k % K];
+        mx = std::max(mx, nblk[k % K]);
     }
     L.blk_stride = mx;
     // a block touches about two tiles; room for four times the average
@@ -394,9 +407,13 @@ int32_t note_reader(fvv_ctx *c, FrameSlot &fs, hipStream_t s)
 int32_t ensure_frame_slot(fvv_ctx *c, FrameSlot &s)
 {
     const int n = (int)c->rig.size();
-    if ((int)s.texel.size() == n && s.ready) return FVV_OK;
+    if ((int)s.texel.size() == n && s.layered == c->has_bg && s.ready) return FVV_OK;
+    if (!s.texel.empty()) return fail(c, FVV_E_STATE, "frame slot layout out of date");
     s.texel.assign(n, nullptr);
     s.depth.assign(n, nullptr);
+    s.bg_texel.assign(n, nullptr);
+    s.bg_depth.assign(n, nullptr);
+    s.layered = c->has_bg;
     s.present.assign(n, 0);
     for (int k = 0; k < n; ++k) {
         const size_t px = (size_t)c->rig[k].width * c->rig[k].height;
@@ -404,9 +421,21 @@ int32_t ensure_frame_slot(fvv_ctx *c, FrameSlot &s)
         if (rc) return rc;
         rc = dalloc(c, (void **)&s.depth[k], px * 4);
         if (rc) return rc;
+        if (s.layered) {
+            if ((rc = dalloc(c, (void **)&s.bg_texel[k], px * 8))) return rc;
+            if ((rc = dalloc(c, (void **)&s.bg_depth[k], px * 4))) return rc;
+        }
     }
     if (!s.ready) HIPCHECK(c, hipEventCreateWithFlags(&s.ready, hipEventDisableTiming));
     return FVV_OK;
+}
+
+void release_bg(fvv_ctx *c)
+{
+    for (size_t k = 0; k < c->bg_model.size(); ++k)
+        if (c->bg_model[k]) dfree(c, c->bg_model[k], (size_t)c->rig[k].width * c->rig[k].height * 2);
+    c->bg_model.clear();
+    c->has_bg = false;
 }
 
 void release_frames(fvv_ctx *c)
@@ -416,9 +445,16 @@ void release_frames(fvv_ctx *c)
             const size_t px = (size_t)c->rig[k].width * c->rig[k].height;
             dfree(c, s.texel[k], px * 8);
             dfree(c, s.depth[k], px * 4);
+            if (s.layered) {
+                dfree(c, s.bg_texel[k], px * 8);
+                dfree(c, s.bg_depth[k], px * 4);
+            }
         }
         s.texel.clear();
         s.depth.clear();
+        s.bg_texel.clear();
+        s.bg_depth.clear();
+        s.layered = false;
         s.present.clear();
         for (auto &r : s.readers) c->event_pool.push_back(r.second);
         s.readers.clear();
@@ -511,7 +547,10 @@ int32_t resolve_params(fvv_ctx *c, const fvv_synth_params *p, fvv_synth_params &
         return fail(c, FVV_E_ARG, "max_footprint must lie in [1, 64]");
     if (o.fill_mode != FVV_FILL_BG && o.fill_mode != FVV_FILL_NONE)
         return fail(c, FVV_E_ARG, "unknown fill_mode %d", o.fill_mode);
-    if (o.path != FVV_PATH_PLAIN && o.path != FVV_PATH_LEARNED) return fail(c, FVV_E_ARG, "unknown path %d", o.path);
+    if (o.path != FVV_PATH_PLAIN && o.path != FVV_PATH_LEARNED && o.path != FVV_PATH_LAYERED)
+        return fail(c, FVV_E_ARG, "unknown path %d", o.path);
+    if (o.path == FVV_PATH_LAYERED && o.k_nearest > FVV_MAX_K / 2)
+        return fail(c, FVV_E_ARG, "layered synthesis blends at most %d cameras", FVV_MAX_K / 2);
     return FVV_OK;
 }
 
@@ -583,11 +622,14 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
     std::vector<ViewLayout> lay(n_views);
     std::vector<int> slot_of(n_views);
     size_t total = 0, total_tiles = 0;
-    fvv_batch_dims dims{n_views, 0, 0, 0, 0, 0, false, false};
+    fvv_batch_dims dims{n_views, 0, 0, 0, 0, 0, false, false, false};
     int32_t rc;
     for (int v = 0; v < n_views; ++v) {
         if ((rc = find_slot(c, Ps[v].frame_version, slot_of[v]))) return rc;
         const FrameSlot &fs = c->slots[slot_of[v]];
+        const bool layered = Ps[v].path == FVV_PATH_LAYERED;
+        if (layered && !fs.layered)
+            return fail(c, FVV_E_STATE, "layered synthesis needs a frame set uploaded with background models");
         ViewLayout &L = lay[v];
         const fvv_camera &vc = virts[v];
         std::vector<int32_t> pres(fs.present);
@@ -597,11 +639,12 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
         if (K < 1) return fail(c, FVV_E_STATE, "no camera present in the frame set");
         int nb[FVV_MAX_K];
         for (int k = 0; k < K; ++k) nb[k] = nblocks(c->rig[L.idx[k]]);
-        layout_sizes(L, vc.width, vc.height, nb, K);
+        layout_sizes(L, vc.width, vc.height, nb, K, layered);
         total += view_ws_bytes(vc.width, vc.height, L, host_out || lio.scratch_out, learned[v] && !lio.stack_out);
         total_tiles += (size_t)L.n_tiles;
         dims.total_tiles += L.n_tiles;
-        dims.max_k = std::max(dims.max_k, L.K);
+        dims.max_k = std::max(dims.max_k, L.nsrc);
+        dims.any_layered = dims.any_layered || layered;
         dims.max_blocks = std::max(dims.max_blocks, L.blk_stride);
         dims.max_tiles_x = std::max(dims.max_tiles_x, L.ntx);
         dims.max_tiles_y = std::max(dims.max_tiles_y, L.nty);
@@ -620,14 +663,18 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
             HIPCHECK(c, hipDeviceSynchronize());
             dfree(c, c->dbg_z, c->dbg_px * 8);
             dfree(c, c->dbg_zf, c->dbg_px * 8);
+            dfree(c, c->dbg_bz, c->dbg_px * 8);
+            dfree(c, c->dbg_bzf, c->dbg_px * 8);
             dfree(c, c->dbg_rgba, c->dbg_px * 4);
             dfree(c, c->dbg_depth, c->dbg_px * 4);
-            c->dbg_z = c->dbg_zf = nullptr;
+            c->dbg_z = c->dbg_zf = c->dbg_bz = c->dbg_bzf = nullptr;
             c->dbg_rgba = nullptr;
             c->dbg_depth = nullptr;
             c->dbg_px = 0;
             if ((rc = dalloc(c, (void **)&c->dbg_z, px * 8))) return rc;
             if ((rc = dalloc(c, (void **)&c->dbg_zf, px * 8))) return rc;
+            if ((rc = dalloc(c, (void **)&c->dbg_bz, px * 8))) return rc;
+            if ((rc = dalloc(c, (void **)&c->dbg_bzf, px * 8))) return rc;
             if ((rc = dalloc(c, (void **)&c->dbg_rgba, px * 4))) return rc;
             if ((rc = dalloc(c, (void **)&c->dbg_depth, px * 4))) return rc;
             c->dbg_px = px;
@@ -657,6 +704,7 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
         d.blk_stride = L.blk_stride;
         d.tile_cap = L.tile_cap;
         d.view = v;
+        d.layered = L.nsrc > L.K;
         const size_t px = (size_t)vc.width * vc.height;
         const size_t nt = (size_t)L.n_tiles;
         auto carve = [&](size_t bytes) {
@@ -668,7 +716,7 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
         d.rowsum = (int2 *)carve(nt * FVV_TILE * sizeof(int2));
         d.colsum = (int2 *)carve(nt * FVV_TILE * sizeof(int2));
         d.list = (int32_t *)carve(nt * (size_t)L.tile_cap * 4);
-        d.bbox = (int4 *)carve((size_t)L.K * L.blk_stride * sizeof(int4));
+        d.bbox = (int4 *)carve((size_t)L.nsrc * L.blk_stride * sizeof(int4));
         d.open_list = Wk.open_list;
         d.open_count = Wk.open_count;
         d.counts = cnt;
@@ -690,6 +738,10 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
         if (taps && v == 0) {
             d.dbg_z = c->dbg_z;
             d.dbg_zf = c->dbg_zf;
+            if (d.layered) {
+                d.dbg_bz = c->dbg_bz;
+                d.dbg_bzf = c->dbg_bzf;
+            }
             d.dbg_rgba = c->dbg_rgba;
             d.dbg_depth = c->dbg_depth;
         }
@@ -708,6 +760,13 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
             pair_dir(vc, sc, sd.B, sd.b);
             sd.sx = (float)((double)vc.fx / (double)sc.fx);
             sd.sy = (float)((double)vc.fy / (double)sc.fy);
+            if (d.layered) {
+                // the camera's background layer: same geometry and weight
+                fvv_src_desc &bd = d.src[L.K + k];
+                bd = sd;
+                bd.texel = fs.bg_texel[L.idx[k]];
+                bd.depth = fs.bg_depth[L.idx[k]];
+            }
         }
     }
     bool waited[2] = {false, false};
@@ -780,19 +839,21 @@ int32_t synthesize_impl(fvv_ctx *c, const fvv_camera *virts, int n_views, const 
     if (rc) return rc;
     c->have_taps = c->debug;
     c->last_px = (int64_t)virts[0].width * virts[0].height;
+    c->last_layered = P.path == FVV_PATH_LAYERED;
     return FVV_OK;
 }
 
 // ---------------------------------------------------------------- server
 // Upper bound of the workspace one request can need (any K cameras of the rig).
-void request_bounds(const fvv_ctx *c, const fvv_camera &v, int k, bool learned, size_t &bytes, size_t &tiles)
+void request_bounds(const fvv_ctx *c, const fvv_camera &v, int k, bool learned, bool layered, size_t &bytes,
+                    size_t &tiles)
 {
     std::vector<int> nb;
     for (const auto &cam : c->rig) nb.push_back(nblocks(cam));
     std::sort(nb.rbegin(), nb.rend());
     const int K = std::min<int>({k, (int)nb.size(), FVV_MAX_K});
     ViewLayout L;
-    layout_sizes(L, v.width, v.height, nb.data(), K);
+    layout_sizes(L, v.width, v.height, nb.data(), K, layered);
     bytes = view_ws_bytes(v.width, v.height, L, false, learned);
     tiles = (size_t)L.n_tiles;
 }
@@ -1017,8 +1078,11 @@ void fvv_destroy(fvv_ctx *c)
         ws_release(c, c->user);
         dfree(c, c->dbg_z, c->dbg_px * 8);
         dfree(c, c->dbg_zf, c->dbg_px * 8);
+        dfree(c, c->dbg_bz, c->dbg_px * 8);
+        dfree(c, c->dbg_bzf, c->dbg_px * 8);
         dfree(c, c->dbg_rgba, c->dbg_px * 4);
         dfree(c, c->dbg_depth, c->dbg_px * 4);
+        release_bg(c);
         for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
         for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
         unet_act_free(c->act);
@@ -1042,7 +1106,45 @@ int32_t fvv_set_rig(fvv_ctx *c, const fvv_camera *cams, int32_t n)
     DeviceGuard g(c->device);
     HIPCHECK(c, hipDeviceSynchronize());
     if (!c->rig.empty()) release_frames(c);
+    release_bg(c);
     c->rig.assign(cams, cams + n);
+    return FVV_OK;
+}
+
+int32_t fvv_set_bg_model(fvv_ctx *c, const void *const *depth_mm, const int64_t *pitches, int32_t n,
+                         int32_t mem_kind, void *stream)
+{
+    if (!c) return FVV_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (c->server) return fail(c, FVV_E_STATE, "stop the server before changing the background models");
+    if (c->rig.empty()) return fail(c, FVV_E_STATE, "no rig set");
+    if (mem_kind != FVV_MEM_HOST && mem_kind != FVV_MEM_DEVICE) return fail(c, FVV_E_ARG, "bad mem_kind");
+    if (depth_mm && (n != (int)c->rig.size() || !pitches))
+        return fail(c, FVV_E_ARG, "need one model (or NULL) per rig camera (%zu) and their pitches", c->rig.size());
+    if (depth_mm)
+        for (int k = 0; k < n; ++k) {
+            if (!depth_mm[k]) continue;
+            if (pitches[k] < 2 * (int64_t)c->rig[k].width || pitches[k] % 2 || ((uintptr_t)depth_mm[k] & 1))
+                return fail(c, FVV_E_ARG, "model %d: rows must be 2-byte aligned and hold width values", k);
+        }
+    DeviceGuard g(c->device);
+    HIPCHECK(c, hipDeviceSynchronize());
+    // resident frame sets lose their layers: the next upload rebuilds them
+    release_frames(c);
+    release_bg(c);
+    if (!depth_mm) return FVV_OK;
+    c->bg_model.assign(n, nullptr);
+    c->has_bg = true;
+    hipStream_t s = (hipStream_t)stream;
+    for (int k = 0; k < n; ++k) {
+        if (!depth_mm[k]) continue;
+        const int W = c->rig[k].width, H = c->rig[k].height;
+        int32_t rc = dalloc(c, (void **)&c->bg_model[k], (size_t)W * H * 2);
+        if (rc) return rc;
+        HIPCHECK(c, hipMemcpy2DAsync(c->bg_model[k], (size_t)W * 2, depth_mm[k], pitches[k], (size_t)W * 2, H,
+                                     mem_kind == FVV_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+    }
+    HIPCHECK(c, hipStreamSynchronize(s));
     return FVV_OK;
 }
 
@@ -1140,6 +1242,11 @@ int32_t fvv_upload_mvd(fvv_ctx *c, const fvv_view *views, int32_t n, int32_t mem
         }
         rc_.texel_out = fs.texel[k];
         rc_.depth_out = fs.depth[k];
+        if (fs.layered) {
+            rc_.bg_model = c->bg_model[k];
+            rc_.bg_texel_out = fs.bg_texel[k];
+            rc_.bg_depth_out = fs.bg_depth[k];
+        }
         rc_.W = W;
         rc_.H = H;
         rc_.alpha = cam.depth_alpha;
@@ -1322,6 +1429,12 @@ int32_t fvv_debug_read(fvv_ctx *c, int32_t tap, void *host_out, int64_t bytes)
     case FVV_TAP_Z_FILT: src = c->dbg_zf; need = c->last_px * 8; break;
     case FVV_TAP_BLEND: src = c->dbg_rgba; need = c->last_px * 4; break;
     case FVV_TAP_DEPTH: src = c->dbg_depth; need = c->last_px * 4; break;
+    case FVV_TAP_BG_Z_RAW:
+    case FVV_TAP_BG_Z_FILT:
+        if (!c->last_layered) return fail(c, FVV_E_STATE, "background-layer taps need a layered synthesis");
+        src = tap == FVV_TAP_BG_Z_RAW ? c->dbg_bz : c->dbg_bzf;
+        need = c->last_px * 8;
+        break;
     default: return fail(c, FVV_E_ARG, "unknown tap %d", tap);
     }
     if (bytes != need) return fail(c, FVV_E_ARG, "tap %d holds %lld bytes, asked %lld", tap, (long long)need, (long long)bytes);
@@ -1347,7 +1460,7 @@ int32_t fvv_server_start(fvv_ctx *c, int32_t max_slots, uint64_t step_bytes)
         v1080.width = 1920;
         v1080.height = 1080;
         size_t b, t;
-        request_bounds(c, v1080, 3, false, b, t);
+        request_bounds(c, v1080, 3, false, false, b, t);
         step_bytes = (uint64_t)b * max_slots;
     }
     S->step_bytes = step_bytes;
@@ -1414,7 +1527,10 @@ int32_t fvv_submit(fvv_ctx *c, const fvv_camera *virt, const fvv_synth_params *p
         if (rc) return rc;
         if ((rc = check_camera(c, *virt, false, "virtual camera"))) return rc;
         if (out_pitch < (int64_t)virt->width * 3) return fail(c, FVV_E_ARG, "out_pitch too small");
-        request_bounds(c, *virt, r.P.k_nearest, r.P.path == FVV_PATH_LEARNED, r.bytes, r.tiles);
+        if (r.P.path == FVV_PATH_LAYERED && !c->has_bg)
+            return fail(c, FVV_E_STATE, "layered synthesis needs background models");
+        request_bounds(c, *virt, r.P.k_nearest, r.P.path == FVV_PATH_LEARNED, r.P.path == FVV_PATH_LAYERED,
+                       r.bytes, r.tiles);
     }
     r.cam = *virt;
     r.out = out_dev;

@@ -2,8 +2,9 @@
 // video codecs (Section V-A), shared by the codec kernels and the frame-store
 // ingest.  Internal to the library.
 //
-// Codes: 0 = background (layered synthesis; decoded as no depth), 1 = no
-// depth or out of range, 2..4095 = Eq. 2 of the depth, which is linear in
+// Codes: 0 = background (0xFFFF in millimetre maps, the background signal of
+// the layered transmission), 1 = no depth (0 mm) or out of range,
+// 2..4095 = Eq. 2 of the depth, which is linear in
 // 1/z between the clipping planes.  Eq. 2 and its inverse run in double
 // precision op by op (the library is built without contraction), rounded
 // half up; "out of range" means the rounded code leaves 2..4095.
@@ -21,6 +22,7 @@
 // Eq. 2: millimetres -> code
 __device__ __forceinline__ uint32_t y12_quantise(uint32_t mm, double zn, double zf)
 {
+    if (mm == 0xFFFFu) return 0u;
     if (mm == 0) return 1u;
     const double z = (double)mm / 1000.0;
     const double a = 1.0 / z - 1.0 / zf;
@@ -29,10 +31,12 @@ __device__ __forceinline__ uint32_t y12_quantise(uint32_t mm, double zn, double 
     return (r >= 2.0 && r <= 4095.0) ? (uint32_t)r : 1u;
 }
 
-// inverse of Eq. 2 -> whole millimetres in 1..65535 (0 for codes 0 and 1)
+// inverse of Eq. 2 -> whole millimetres in 1..65535 (0xFFFF for code 0, 0 for
+// code 1)
 __device__ __forceinline__ uint32_t y12_dequantise(uint32_t code, double zn, double zf)
 {
-    if (code < 2u) return 0u;
+    if (code == 0u) return 0xFFFFu;
+    if (code == 1u) return 0u;
     const double t = (double)(code - 2u) / 4093.0;
     const double inv = t * (1.0 / zn - 1.0 / zf) + 1.0 / zf;
     const double mm = floor(1.0 / inv * 1000.0 + 0.5);
