@@ -95,6 +95,9 @@ def lib():
         L.fvv_ref_depth_codes.argtypes = [P, C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_float, P]
         L.fvv_ref_codes_depth.restype = None
         L.fvv_ref_codes_depth.argtypes = [P, C.c_int32, C.c_int32, C.c_float, C.c_float, P]
+        L.fvv_ref_prefilter.restype = None
+        L.fvv_ref_prefilter.argtypes = [P, C.c_int64, P, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+                                        C.c_float, C.c_float, C.c_int32, P]
         L.fvv_ref_pack_y12.restype = None
         L.fvv_ref_pack_y12.argtypes = [P, C.c_int32, C.c_int32, P, P, P]
         L.fvv_ref_unpack_y12.restype = None
@@ -284,14 +287,34 @@ def synthesize(rig, frames, virt, k_nearest: int = 3, tau: float = 0.05, max_fp:
     return res
 
 
-# ---------------------------------------------------------------- OL: layered synthesis
-BG_MM = 0xFFFF      # background signal in live millimetre maps (O3)
-
-
 class _LayerFrame:
     def __init__(self, rgb, depth_mm):
         self.rgb = rgb
         self.depth_mm = depth_mm
+
+
+# ---------------------------------------------------------------- OJ: joint bilateral pre-filter
+JBF_DEFAULTS = dict(radius=2, sigma_s=1.5, sigma_c=24.0, min_valid=5)
+
+
+def prefilter(rgb, depth_mm, radius: int = 2, sigma_s: float = 1.5, sigma_c: float = 24.0,
+              min_valid: int = 5) -> np.ndarray:
+    """Hole-filling joint bilateral filter of one live depth map (readings in
+    the C source)."""
+    rgb = np.ascontiguousarray(rgb, np.uint8)
+    d = np.ascontiguousarray(depth_mm, np.uint16)
+    H, W = d.shape
+    out = np.empty((H, W), np.uint16)
+    lib().fvv_ref_prefilter(_ptr(rgb), W * 3, _ptr(d), W, W, H, radius, sigma_s, sigma_c, min_valid, _ptr(out))
+    return out
+
+
+def prefilter_frames(frames, **kw):
+    return [None if f is None else _LayerFrame(f.rgb, prefilter(f.rgb, f.depth_mm, **kw)) for f in frames]
+
+
+# ---------------------------------------------------------------- OL: layered synthesis
+BG_MM = 0xFFFF      # background signal in live millimetre maps (O3)
 
 
 class _IdentityDepthCamera:

@@ -731,3 +731,71 @@ void fvv_ref_unpack_y12(const uint8_t *Y, const uint8_t *U, const uint8_t *V, in
             codes[(int64_t)y * W + x] = (uint16_t)(msb << 8 | lsb);
         }
 }
+
+/* ------------------------------------------------------------------------ */
+/* OJ: joint bilateral pre-filter of the live depth (Section VI: small holes
+ * and gaps at object edges are closed before warping with a joint bilateral
+ * filter; the paper states no parameters).  Readings:
+ *  - it fills holes only: a pixel without depth (0) takes the bilateral
+ *    mean of the valid depths in its (2r+1)^2 window, guided by the live
+ *    colour; measured depths are left as they are, and background-signalled
+ *    pixels (0xFFFF) are neither filled nor used;
+ *  - weights are a spatial Gaussian (sigma_s, pixels) times a range Gaussian
+ *    of the L1 colour distance (sigma_c, 8-bit levels), each rounded to a
+ *    12-bit integer, exp in double: ws = floor(4096 exp(-(dx^2+dy^2) /
+ *    (2 sigma_s^2)) + 0.5), wc = floor(4096 exp(-d^2 / (2 sigma_c^2)) + 0.5),
+ *    w = ws wc;
+ *  - a hole is filled when at least min_valid neighbours have w > 0; the
+ *    filled depth is floor((sum w D + floor(sum w / 2)) / sum w) in integer
+ *    arithmetic, millimetres;
+ *  - one pass over the original map (filled values are not reused);
+ *  - it runs on the transmitted millimetres, before the Eq. 1 decode. */
+static void ref_jbf_tables(int32_t radius, float sigma_s, float sigma_c, uint32_t *ws, uint32_t *wc)
+{
+    const int n = 2 * radius + 1;
+    for (int dy = -radius; dy <= radius; ++dy)
+        for (int dx = -radius; dx <= radius; ++dx) {
+            double e = exp(-(double)(dx * dx + dy * dy) / (2.0 * (double)sigma_s * (double)sigma_s));
+            ws[(dy + radius) * n + dx + radius] = (uint32_t)floor(4096.0 * e + 0.5);
+        }
+    for (int d = 0; d <= 765; ++d) {
+        double e = exp(-(double)d * (double)d / (2.0 * (double)sigma_c * (double)sigma_c));
+        wc[d] = (uint32_t)floor(4096.0 * e + 0.5);
+    }
+}
+
+void fvv_ref_prefilter(const uint8_t *rgb, int64_t rgb_pitch, const uint16_t *depth, int64_t depth_pitch,
+                       int32_t W, int32_t H, int32_t radius, float sigma_s, float sigma_c, int32_t min_valid,
+                       uint16_t *out)
+{
+    uint32_t ws[49], wc[766];
+    ref_jbf_tables(radius, sigma_s, sigma_c, ws, wc);
+    const int n = 2 * radius + 1;
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            const uint16_t d = depth[(int64_t)y * depth_pitch + x];
+            uint16_t res = d;
+            if (d == 0) {
+                const uint8_t *cp = rgb + (int64_t)y * rgb_pitch + (int64_t)x * 3;
+                uint64_t sw = 0, swd = 0;
+                int cnt = 0;
+                for (int dy = -radius; dy <= radius; ++dy)
+                    for (int dx = -radius; dx <= radius; ++dx) {
+                        const int xx = x + dx, yy = y + dy;
+                        if ((dx == 0 && dy == 0) || xx < 0 || yy < 0 || xx >= W || yy >= H) continue;
+                        const uint16_t q = depth[(int64_t)yy * depth_pitch + xx];
+                        if (!ref_has_depth(q)) continue;
+                        const uint8_t *cq = rgb + (int64_t)yy * rgb_pitch + (int64_t)xx * 3;
+                        const int dist = abs((int)cp[0] - (int)cq[0]) + abs((int)cp[1] - (int)cq[1]) +
+                                         abs((int)cp[2] - (int)cq[2]);
+                        const uint64_t w = (uint64_t)ws[(dy + radius) * n + dx + radius] * wc[dist];
+                        if (w == 0) continue;
+                        sw += w;
+                        swd += w * q;
+                        ++cnt;
+                    }
+                if (cnt >= min_valid && sw > 0) res = (uint16_t)((swd + sw / 2) / sw);
+            }
+            out[(int64_t)y * W + x] = res;
+        }
+}
