@@ -315,6 +315,51 @@ def run_codec(fvv, torch, w, raw, virt_c, outs, stream, reps: int) -> dict:
             "coded_step_ms": round(step_ms, 4), "coded_step_stage_ms": stages}
 
 
+def run_layered_step(fvv, torch, sg, args, stream) -> dict:
+    """Layered FG/BG synthesis (Section VI) on the same rig and trajectory:
+    live depth on the objects only, exact background models; a step is the
+    two-layer re-ingest plus the batched 60-view layered synthesis."""
+    w = sg.config3(0, n_frames=args.views, layered=True)
+    dev = torch.device("cuda:0")
+    raw = [(torch.from_numpy(f.rgb).to(dev), torch.from_numpy(f.depth_mm.view(np.int16)).to(dev))
+           for f in w.frames]
+    c = fvv.Context(0)
+    c.set_rig(w.rig)
+    c.set_bg_model(w.bg_models)
+    outs = [torch.empty((v.height, v.width, 3), dtype=torch.uint8, device=dev) for v in w.virtual]
+    virt_c = (fvv.Camera * len(w.virtual))(*[fvv.camera(v) for v in w.virtual])
+    p = fvv.params(path=fvv.PATH_LAYERED)
+
+    def step():
+        c.upload_mvd(raw, mem=fvv.MEM_DEVICE, stream=stream)
+        c.synthesize_batch(virt_c, outs, p=p, stream=stream)
+
+    for _ in range(max(5, args.warmup // 4)):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = max(5, args.steps // 2)
+    e0.record(stream)
+    for _ in range(reps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    c.set_profiling(True)
+    c.profile(reset=True)
+    for _ in range(5):
+        step()
+    torch.cuda.synchronize()
+    prof = c.profile(reset=True)
+    c.close()
+    n_out = w.virtual[0].width * w.virtual[0].height
+    fg = float(np.mean([np.mean(f.depth_mm != sg.BG_MM) for f in w.frames]))
+    return {"ms_per_step": round(ms, 4), "Mpix_per_s": round(len(w.virtual) * n_out / (ms * 1e-3) / 1e6, 1),
+            "views": len(w.virtual), "foreground_fraction_of_source_pixels": round(fg, 3),
+            "stage_ms": {k: round(t / n, 4) for k, (t, n) in prof.items() if n}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -330,6 +375,7 @@ def main():
                     help="views of the learned-path measurement at 960x540 (0 = skip)")
     ap.add_argument("--serve-learned-seconds", type=float, default=3.0,
                     help="measured seconds of the learned serving load (0 = skip)")
+    ap.add_argument("--layered", type=int, default=1, help="measure the layered FG/BG step (0 = skip)")
     ap.add_argument("--codec-reps", type=int, default=20,
                     help="repetitions of the 12-bit depth codec timing (0 = skip)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -462,6 +508,12 @@ def main():
                          f"single-threaded, {dt:.1f} s on {platform.processor() or platform.machine()}"}
         log(f"[bench] cpu oracle {cpu['value']} Mpix/s")
 
+    layered = None
+    if args.layered:
+        log("[bench] layered FG/BG step (generating background models)")
+        layered = run_layered_step(fvv, torch, sg, args, stream)
+        log(f"[bench] layered {json.dumps(layered)}")
+
     codec = None
     if args.codec_reps > 0:
         codec = run_codec(fvv, torch, w, raw, virt_c, outs, stream, args.codec_reps)
@@ -512,6 +564,7 @@ def main():
         "learned": learned,
         "serving_learned": serving_learned,
         "depth_codec": codec,
+        "layered": layered,
         "path": "plain",
     }
     print(json.dumps(res), flush=True)

@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define FVV_ABI_VERSION 4
+#define FVV_ABI_VERSION 5
 
 /* status codes */
 enum {
@@ -198,6 +198,33 @@ int32_t fvv_set_depth_format(fvv_ctx *ctx, int32_t format, float z_near, float z
  * without a rig; a rig change clears the models. */
 int32_t fvv_set_bg_model(fvv_ctx *ctx, const void *const *depth_mm, const int64_t *pitches, int32_t n,
                          int32_t mem_kind, void *stream);
+
+/* Joint bilateral pre-filter of the live depth at ingest (Section VI: small
+ * holes and gaps around object edges are closed before warping; the paper
+ * gives no parameters).  With enable != 0, following uploads fill every
+ * pixel without depth (0 mm; background-signalled pixels are neither filled
+ * nor used) with the bilateral mean of the valid depths in its
+ * (2 radius + 1)^2 window: weight = ws * wc with
+ *   ws = floor(4096 exp(-(dx^2 + dy^2) / (2 sigma_s^2)) + 0.5)   (pixels)
+ *   wc = floor(4096 exp(-d^2 / (2 sigma_c^2)) + 0.5)              (d = L1
+ *        distance of the two RGB8 colours),
+ * depth = floor((sum w D + floor(sum w / 2)) / sum w) millimetres, when at
+ * least min_valid neighbours have w > 0 (else the pixel stays a hole).  One
+ * pass over the transmitted millimetres (coded depth decoded first), before
+ * the Eq. (1) decode.  radius 1..3, sigmas finite and > 0, min_valid in
+ * 1..(2 radius + 1)^2 - 1 (suggested: 2, 1.5, 24, 5); enable == 0 turns the
+ * filter off.  Resident frame sets are not affected. */
+int32_t fvv_set_prefilter(fvv_ctx *ctx, int32_t enable, int32_t radius, float sigma_s, float sigma_c,
+                          int32_t min_valid);
+
+/* Copy camera cam's decoded depth plane of a resident frame set (version 0 =
+ * latest) to host memory: width*height float32 metres after the pre-filter
+ * and Eq. (1), bits 0xFFFFFFFF where there is no depth; layer 0 = live
+ * (foreground) depth, 1 = the background layer of a layered frame set.
+ * bytes must equal width*height*4.  For inspection and tests; synchronises
+ * the device. */
+int32_t fvv_read_frame_depth(fvv_ctx *ctx, int32_t cam, int32_t layer, uint64_t version, void *host_out,
+                             int64_t bytes);
 
 /* Render one virtual camera into out_rgb8 (height rows of width*3 bytes,
  * pitch out_pitch; host or device per mem_kind).  Steps, all on the GPU:

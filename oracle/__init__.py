@@ -95,6 +95,8 @@ def lib():
         L.fvv_ref_depth_codes.argtypes = [P, C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_float, P]
         L.fvv_ref_codes_depth.restype = None
         L.fvv_ref_codes_depth.argtypes = [P, C.c_int32, C.c_int32, C.c_float, C.c_float, P]
+        L.fvv_ref_decode_plane.restype = None
+        L.fvv_ref_decode_plane.argtypes = [P, C.c_int64, C.c_float, C.c_float, P]
         L.fvv_ref_prefilter.restype = None
         L.fvv_ref_prefilter.argtypes = [P, C.c_int64, P, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                                         C.c_float, C.c_float, C.c_int32, P]
@@ -285,6 +287,14 @@ def synthesize(rig, frames, virt, k_nearest: int = 3, tau: float = 0.05, max_fp:
     res = dict(rgb=out, sel=sel[:K].copy(), weights=w[:K].copy())
     res.update(t)
     return res
+
+
+def decode_plane_bits(depth_mm, alpha: float = 0.0, beta: float = 1.0) -> np.ndarray:
+    """O3 over a millimetre map: uint32 float32 bits, 0xFFFFFFFF = no depth."""
+    d = np.ascontiguousarray(depth_mm, np.uint16)
+    out = np.empty(d.shape, np.uint32)
+    lib().fvv_ref_decode_plane(_ptr(d), d.size, alpha, beta, _ptr(out))
+    return out
 
 
 class _LayerFrame:

@@ -217,6 +217,20 @@ float fvv_ref_decode_depth(uint16_t d, float alpha, float beta)
     return s * z;
 }
 
+/* O3 over a plane: float32 bits of the decoded depth, 0xFFFFFFFF where the
+ * millimetre value carries no depth */
+void fvv_ref_decode_plane(const uint16_t *mm, int64_t n, float alpha, float beta, uint32_t *out)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        uint32_t b = 0xFFFFFFFFu;
+        if (ref_has_depth(mm[i])) {
+            float z = fvv_ref_decode_depth(mm[i], alpha, beta);
+            memcpy(&b, &z, 4);
+        }
+        out[i] = b;
+    }
+}
+
 static inline uint32_t ref_fbits(float f)
 {
     uint32_t u;

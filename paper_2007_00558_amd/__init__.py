@@ -110,6 +110,8 @@ def lib():
             "fvv_depth_decode_y12": (I32, [P, I64, I32, I32, C.c_float, C.c_float, P, I64, P]),
             "fvv_set_depth_format": (I32, [P, I32, C.c_float, C.c_float]),
             "fvv_set_bg_model": (I32, [P, P, P, I32, I32, P]),
+            "fvv_set_prefilter": (I32, [P, I32, I32, C.c_float, C.c_float, I32]),
+            "fvv_read_frame_depth": (I32, [P, I32, I32, U64, P, I64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -127,7 +129,8 @@ EXPORTED = ("fvv_abi_version", "fvv_create", "fvv_destroy", "fvv_last_error", "f
             "fvv_net_param_count", "fvv_net_layer_info", "fvv_net_layer_name", "fvv_net_load",
             "fvv_net_read", "fvv_make_stack", "fvv_net_forward", "fvv_net_train_step",
             "fvv_net_read_act", "fvv_net_device_bytes", "fvv_depth_encode_y12",
-            "fvv_depth_decode_y12", "fvv_set_depth_format", "fvv_set_bg_model")
+            "fvv_depth_decode_y12", "fvv_set_depth_format", "fvv_set_bg_model", "fvv_set_prefilter",
+            "fvv_read_frame_depth")
 DEPTH_MM16, DEPTH_Y12 = 0, 1
 NET_PARAMS, NET_GRADS = 0, 1
 NET_ALIGN = 8           # network inputs: multiples of 8 in both dimensions
@@ -301,6 +304,18 @@ class Context:
         images, (H*3/2, W) uint8) for the following uploads."""
         self._check(self._L.fvv_set_depth_format(self._h, fmt, z_near, z_far))
         self.depth_format = fmt
+
+    def set_prefilter(self, enable: bool = True, radius: int = 2, sigma_s: float = 1.5, sigma_c: float = 24.0,
+                      min_valid: int = 5):
+        """Hole-filling joint bilateral pre-filter of the live depth at ingest."""
+        self._check(self._L.fvv_set_prefilter(self._h, 1 if enable else 0, radius, sigma_s, sigma_c, min_valid))
+
+    def read_frame_depth(self, cam: int, layer: int = 0, version: int = 0) -> np.ndarray:
+        """Decoded depth plane (float32 metres; NaN-pattern bits 0xFFFFFFFF = none)."""
+        c = self.rig[cam]
+        out = np.empty((c.height, c.width), np.float32)
+        self._check(self._L.fvv_read_frame_depth(self._h, cam, layer, version, out.ctypes.data, out.nbytes))
+        return out
 
     def set_bg_model(self, models: Optional[Sequence], mem: int = MEM_HOST, stream=None):
         """Background depth models (layered synthesis): models[c] a (H,W)

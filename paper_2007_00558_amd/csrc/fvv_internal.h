@@ -153,10 +153,17 @@ struct fvv_repack_cam {
     uint2 *bg_texel_out;
     float *bg_depth_out;
 };
+// Joint bilateral pre-filter tables: FVV_JBF_WS spatial weights (a
+// (2r+1)^2 window, row-major, padded to 7x7) then FVV_JBF_WC range weights
+// by L1 colour distance, 12-bit integers.
+#define FVV_JBF_WS 49
+#define FVV_JBF_WC 766
 struct fvv_repack_batch {
     int32_t n;
     int32_t y12;            // depth arrives 12-bit coded (Section V-A)
     float z_near, z_far;    // clipping planes of that coding, metres
+    const uint32_t *jbf;    // pre-filter weight tables (null = filter off)
+    int32_t jbf_radius, jbf_min;
     fvv_repack_cam cam[FVV_MAX_RIG];
 };
 

@@ -114,8 +114,53 @@ __device__ __forceinline__ float wave_maxf(float v)
 // One thread per source pixel (grid.z = camera): 8-byte texel {RGBA8,
 // decoded depth bits} for the backward gathers and the decoded depth plane
 // for the splat.  Millimetres 0 and 0xFFFF (the background signal) carry no
-// live depth.  With a background model the background layer's texel and
+// live depth; holes (0) may first be closed by the pre-filter.  With a background model the background layer's texel and
 // depth planes are written too (layered synthesis, Section VI).
+// live millimetres of source pixel (x, y): uint16, or decoded from the I420
+// 12-bit coding (Y, then U with the even rows' MSBs, then V with the odd rows')
+__device__ __forceinline__ uint32_t live_mm(const fvv_repack_batch &b, const fvv_repack_cam &c, int x, int y)
+{
+    if (b.y12) {
+        const int64_t uvp = c.depth_pitch >> 1;
+        const uint8_t *pl = c.depth + (int64_t)c.H * c.depth_pitch + ((y & 1) ? (int64_t)(c.H >> 1) * uvp : 0);
+        const uint32_t uv = pl[(int64_t)(y >> 1) * uvp + (x >> 1)];
+        return y12_dequantise(y12_unfold(c.depth[(int64_t)y * c.depth_pitch + x], y12_msb(uv, x & 1)), b.z_near,
+                              b.z_far);
+    }
+    return *(const uint16_t *)(c.depth + (int64_t)y * c.depth_pitch + (int64_t)x * 2);
+}
+
+// Hole-filling joint bilateral pre-filter (Section VI pre-processing of the
+// live depth): the integer bilateral mean of the valid depths around a hole,
+// spatial weight times the weight of the L1 colour distance, when at least
+// jbf_min neighbours carry weight; 0 (still a hole) otherwise.
+__device__ __noinline__ uint32_t jbf_fill(const fvv_repack_batch &b, const fvv_repack_cam &c, int x, int y,
+                                          const uint8_t *p)
+{
+    const int r = b.jbf_radius, n = 2 * r + 1;
+    const uint32_t *ws = b.jbf, *wc = b.jbf + FVV_JBF_WS;
+    uint64_t sw = 0, swd = 0;
+    int cnt = 0;
+    for (int dy = -r; dy <= r; ++dy) {
+        const int yy = y + dy;
+        if (yy < 0 || yy >= c.H) continue;
+        for (int dx = -r; dx <= r; ++dx) {
+            const int xx = x + dx;
+            if ((dx | dy) == 0 || xx < 0 || xx >= c.W) continue;
+            const uint32_t q = live_mm(b, c, xx, yy);
+            if (q == 0 || q == FVV_BG_MM) continue;
+            const uint8_t *pq = c.rgb + (int64_t)yy * c.rgb_pitch + (int64_t)xx * 3;
+            const int dist = abs((int)p[0] - (int)pq[0]) + abs((int)p[1] - (int)pq[1]) + abs((int)p[2] - (int)pq[2]);
+            const uint64_t w = (uint64_t)(ws[(dy + r) * n + dx + r] * wc[dist]);
+            if (w == 0) continue;
+            sw += w;
+            swd += w * q;
+            ++cnt;
+        }
+    }
+    return (cnt >= b.jbf_min && sw > 0) ? (uint32_t)((swd + sw / 2) / sw) : 0u;
+}
+
 __global__ void __launch_bounds__(256) k_repack(const fvv_repack_batch b)
 {
     const fvv_repack_cam &c = b.cam[blockIdx.z];
@@ -124,17 +169,8 @@ __global__ void __launch_bounds__(256) k_repack(const fvv_repack_batch b)
     if (x >= c.W || y >= c.H) return;
     const uint8_t *p = c.rgb + (int64_t)y * c.rgb_pitch + (int64_t)x * 3;
     const uint32_t col = (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | 0xFF000000u;
-    uint32_t d;
-    if (b.y12) {
-        // I420 12-bit coding: Y, then U (even rows' MSBs), then V (odd rows')
-        const int64_t uvp = c.depth_pitch >> 1;
-        const uint8_t *pl = c.depth + (int64_t)c.H * c.depth_pitch + ((y & 1) ? (int64_t)(c.H >> 1) * uvp : 0);
-        const uint32_t uv = pl[(int64_t)(y >> 1) * uvp + (x >> 1)];
-        d = y12_dequantise(y12_unfold(c.depth[(int64_t)y * c.depth_pitch + x], y12_msb(uv, x & 1)), b.z_near,
-                           b.z_far);
-    } else {
-        d = *(const uint16_t *)(c.depth + (int64_t)y * c.depth_pitch + (int64_t)x * 2);
-    }
+    uint32_t d = live_mm(b, c, x, y);
+    if (d == 0 && b.jbf) d = jbf_fill(b, c, x, y, p);
     uint32_t zb = FVV_NO_DEPTH;
     if (d != 0 && d != FVV_BG_MM) {
         const float z = __fdiv_rn((float)d, 1000.0f);

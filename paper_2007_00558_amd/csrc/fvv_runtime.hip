@@ -147,6 +147,10 @@ struct fvv_ctx {
     // (width per row; null = none), set while has_bg
     std::vector<uint16_t *> bg_model;
     bool has_bg = false;
+    // joint bilateral pre-filter of live depth at ingest (null tables = off)
+    uint32_t *jbf = nullptr;
+    int32_t jbf_radius = 0, jbf_min = 0;
+    bool jbf_on = false;
     // depth format of uploads (FVV_DEPTH_*) and the clipping planes of the
     // 12-bit coding
     int32_t depth_format = FVV_DEPTH_MM16;
@@ -1083,6 +1087,7 @@ void fvv_destroy(fvv_ctx *c)
         dfree(c, c->dbg_rgba, c->dbg_px * 4);
         dfree(c, c->dbg_depth, c->dbg_px * 4);
         release_bg(c);
+        dfree(c, c->jbf, (FVV_JBF_WS + FVV_JBF_WC) * 4);
         for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
         for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
         unet_act_free(c->act);
@@ -1257,6 +1262,11 @@ int32_t fvv_upload_mvd(fvv_ctx *c, const fvv_view *views, int32_t n, int32_t mem
     b.y12 = y12;
     b.z_near = c->z_near;
     b.z_far = c->z_far;
+    if (c->jbf_on) {
+        b.jbf = c->jbf;
+        b.jbf_radius = c->jbf_radius;
+        b.jbf_min = c->jbf_min;
+    }
     HIPCHECK(c, fvv_launch_repack(b, max_w, max_h, s, c->profiling ? &c->prof : nullptr));
     if (host) HIPCHECK(c, hipEventRecord(c->staging_free, s));
     HIPCHECK(c, hipEventRecord(fs.ready, s));
@@ -1264,6 +1274,66 @@ int32_t fvv_upload_mvd(fvv_ctx *c, const fvv_view *views, int32_t n, int32_t mem
     fs.version = c->next_version++;
     c->latest = dst;
     if (out_version) *out_version = fs.version;
+    return FVV_OK;
+}
+
+int32_t fvv_set_prefilter(fvv_ctx *c, int32_t enable, int32_t radius, float sigma_s, float sigma_c,
+                          int32_t min_valid)
+{
+    if (!c) return FVV_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (!enable) {
+        c->jbf_on = false;
+        return FVV_OK;
+    }
+    if (radius < 1 || radius > 3) return fail(c, FVV_E_ARG, "pre-filter radius %d outside 1..3", radius);
+    if (!(std::isfinite(sigma_s) && sigma_s > 0.f && std::isfinite(sigma_c) && sigma_c > 0.f))
+        return fail(c, FVV_E_ARG, "pre-filter sigmas must be finite and > 0");
+    const int n = 2 * radius + 1;
+    if (min_valid < 1 || min_valid > n * n - 1)
+        return fail(c, FVV_E_ARG, "pre-filter min_valid %d outside 1..%d", min_valid, n * n - 1);
+    // weight tables: 12-bit integers of the spatial and range Gaussians
+    uint32_t t[FVV_JBF_WS + FVV_JBF_WC] = {};
+    for (int dy = -radius; dy <= radius; ++dy)
+        for (int dx = -radius; dx <= radius; ++dx) {
+            const double e = std::exp(-(double)(dx * dx + dy * dy) / (2.0 * (double)sigma_s * (double)sigma_s));
+            t[(dy + radius) * n + dx + radius] = (uint32_t)std::floor(4096.0 * e + 0.5);
+        }
+    for (int d = 0; d < FVV_JBF_WC; ++d) {
+        const double e = std::exp(-(double)d * (double)d / (2.0 * (double)sigma_c * (double)sigma_c));
+        t[FVV_JBF_WS + d] = (uint32_t)std::floor(4096.0 * e + 0.5);
+    }
+    DeviceGuard g(c->device);
+    int32_t rc;
+    if (!c->jbf && (rc = dalloc(c, (void **)&c->jbf, sizeof t))) return rc;
+    HIPCHECK(c, hipDeviceSynchronize());
+    HIPCHECK(c, hipMemcpy(c->jbf, t, sizeof t, hipMemcpyHostToDevice));
+    c->jbf_radius = radius;
+    c->jbf_min = min_valid;
+    c->jbf_on = true;
+    return FVV_OK;
+}
+
+int32_t fvv_read_frame_depth(fvv_ctx *c, int32_t cam, int32_t layer, uint64_t version, void *host_out,
+                             int64_t bytes)
+{
+    if (!c) return FVV_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (!host_out) return fail(c, FVV_E_ARG, "host_out is null");
+    if (cam < 0 || cam >= (int)c->rig.size()) return fail(c, FVV_E_ARG, "camera %d outside the rig", cam);
+    if (layer != 0 && layer != 1) return fail(c, FVV_E_ARG, "layer must be 0 (live / foreground) or 1 (background)");
+    int si;
+    int32_t rc = find_slot(c, version, si);
+    if (rc) return rc;
+    const FrameSlot &fs = c->slots[si];
+    if (!fs.present[cam]) return fail(c, FVV_E_STATE, "camera %d is absent from that frame set", cam);
+    if (layer == 1 && !fs.layered) return fail(c, FVV_E_STATE, "that frame set has no background layers");
+    const int64_t need = (int64_t)c->rig[cam].width * c->rig[cam].height * 4;
+    if (bytes != need) return fail(c, FVV_E_ARG, "the plane holds %lld bytes, asked %lld", (long long)need,
+                                   (long long)bytes);
+    DeviceGuard g(c->device);
+    HIPCHECK(c, hipDeviceSynchronize());
+    HIPCHECK(c, hipMemcpy(host_out, layer ? fs.bg_depth[cam] : fs.depth[cam], (size_t)need, hipMemcpyDeviceToHost));
     return FVV_OK;
 }
 

@@ -227,3 +227,35 @@ def test_learned_requests_in_mix_equal_alone(fvv):
     for a, o in zip(alone, outs):
         assert np.array_equal(a, o.cpu().numpy())
     ctx.close()
+
+
+def test_layered_requests_in_mix_equal_alone(fvv):
+    """Layered, learned and plain requests served together (one step can hold
+    all three: its tile launch then takes the two-window variant that also
+    writes the network stacks) equal the same requests rendered alone."""
+    import torch
+    from paper_2007_00558_amd import learned as L
+    say("[gpu] serving layered/learned/plain mix vs alone")
+    w = sg.config_small(17, n_cams=5, w=120, h=80, layered=True)
+    ctx = fvv.Context(0)
+    ctx.set_rig(w.rig)
+    ctx.set_bg_model(w.bg_models)
+    ctx.upload_mvd(w.frames)
+    ctx.net_load(L.init_params(4))
+    views = _mixed_views(w, 24, 5)
+    paths = [(fvv.PATH_PLAIN, fvv.PATH_LAYERED, fvv.PATH_LEARNED)[q % 3] for q in range(len(views))]
+    alone = [ctx.synthesize(v, p=fvv.params(path=pa)) for v, pa in zip(views, paths)]
+    srv = fvv.Server(ctx, max_slots=6)
+    outs = [torch.zeros((v.height, v.width, 3), dtype=torch.uint8, device="cuda") for v in views]
+    torch.cuda.synchronize()
+    srv.pause(True)
+    tickets = [srv.submit(v, o, fvv.params(path=pa)) for v, o, pa in zip(views, outs, paths)]
+    srv.pause(False)
+    _wait(srv, tickets)
+    st = srv.stats()
+    srv.stop()
+    torch.cuda.synchronize()
+    assert st["failed"] == 0 and st["steps"] < len(views)
+    for a, o in zip(alone, outs):
+        assert np.array_equal(a, o.cpu().numpy())
+    ctx.close()
