@@ -95,6 +95,8 @@ def lib():
         L.fvv_ref_depth_codes.argtypes = [P, C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_float, P]
         L.fvv_ref_codes_depth.restype = None
         L.fvv_ref_codes_depth.argtypes = [P, C.c_int32, C.c_int32, C.c_float, C.c_float, P]
+        L.fvv_ref_tx_cameras.restype = C.c_int32
+        L.fvv_ref_tx_cameras.argtypes = [P, C.c_int32, P, C.c_int32, C.c_int32, P]
         L.fvv_ref_decode_plane.restype = None
         L.fvv_ref_decode_plane.argtypes = [P, C.c_int64, C.c_float, C.c_float, P]
         L.fvv_ref_prefilter.restype = None
@@ -287,6 +289,19 @@ def synthesize(rig, frames, virt, k_nearest: int = 3, tau: float = 0.05, max_fp:
     res = dict(rgb=out, sel=sel[:K].copy(), weights=w[:K].copy())
     res.update(t)
     return res
+
+
+def tx_cameras(rig, viewpoints, n_tx: int = 5):
+    """OT: bit mask of the cameras to transmit for these client viewpoints."""
+    n = len(rig)
+    arr = (RefCamera * n)(*[ref_camera(c) for c in rig])
+    nv = len(viewpoints)
+    va = (RefCamera * max(nv, 1))(*[ref_camera(v) for v in viewpoints])
+    mask = C.c_uint32(0)
+    cnt = lib().fvv_ref_tx_cameras(C.cast(arr, C.c_void_p), n, C.cast(va, C.c_void_p), nv, n_tx, C.byref(mask))
+    if cnt < 0:
+        raise ValueError("oracle rejected the arguments")
+    return mask.value
 
 
 def decode_plane_bits(depth_mm, alpha: float = 0.0, beta: float = 1.0) -> np.ndarray:

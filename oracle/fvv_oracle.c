@@ -125,6 +125,44 @@ int fvv_ref_select(const ref_camera *rig, const int32_t *present, int32_t n,
     return K;
 }
 
+/* OT: adaptive view transmission (Section V-C).  Only the N_Tx cameras
+ * closest to a client's viewpoint are transmitted; with several clients the
+ * edge server needs the union over their viewpoints.  Reading: the ranking
+ * is O1's (centre distance in double, ties to the lower rig index) without
+ * the coincident-camera shortcut, since the spare cameras are there for
+ * viewpoints that move.  mask bit c = transmit camera c; returns the count. */
+int32_t fvv_ref_tx_cameras(const ref_camera *rig, int32_t n, const ref_camera *views, int32_t n_views,
+                           int32_t n_tx, uint32_t *mask)
+{
+    if (n > 32 || n < 1 || n_tx < 1) return -1;
+    uint32_t m = 0;
+    for (int v = 0; v < n_views; ++v) {
+        double Cv[3], d[32];
+        int order[32];
+        ref_center(&views[v], Cv);
+        for (int c = 0; c < n; ++c) {
+            double Cc[3];
+            ref_center(&rig[c], Cc);
+            double dx = Cc[0] - Cv[0], dy = Cc[1] - Cv[1], dz = Cc[2] - Cv[2];
+            d[c] = sqrt(dx * dx + dy * dy + dz * dz);
+            order[c] = c;
+        }
+        for (int a = 1; a < n; ++a) {
+            int x = order[a], b = a - 1;
+            while (b >= 0 && d[order[b]] > d[x]) {
+                order[b + 1] = order[b];
+                --b;
+            }
+            order[b + 1] = x;
+        }
+        for (int e = 0; e < n_tx && e < n; ++e) m |= 1u << order[e];
+    }
+    *mask = m;
+    int cnt = 0;
+    for (int c = 0; c < n; ++c) cnt += (m >> c) & 1u;
+    return cnt;
+}
+
 /* ------------------------------------------------------------------------ */
 /* O2: pair matrices.
  * Pinhole model (Section VI: a pixel is a ray, its depth fixes the point).
