@@ -360,6 +360,36 @@ def run_layered_step(fvv, torch, sg, args, stream) -> dict:
             "stage_ms": {k: round(t / n, 4) for k, (t, n) in prof.items() if n}}
 
 
+def run_tx_policy(fvv, torch, w, reps: int = 5) -> dict:
+    """Adaptive view transmission (Section V-C) for one client at the middle
+    of the swing: host uploads (pageable numpy frames, PCIe included) of the
+    N_Tx = 5 nearest cameras against all nine."""
+    v = w.virtual[len(w.virtual) // 2]
+    mask = fvv.tx_cameras(w.rig, [v], 5)
+    sub = [f if mask >> k & 1 else None for k, f in enumerate(w.frames)]
+    c = fvv.Context(0)
+    c.set_rig(w.rig)
+
+    def timed(frames):
+        c.upload_mvd(frames)
+        t = time.perf_counter()
+        for _ in range(reps):
+            c.upload_mvd(frames)
+        return (time.perf_counter() - t) * 1e3 / reps
+
+    all_ms = timed(w.frames)
+    sub_ms = timed(sub)
+    out_sub = c.synthesize(v)
+    c.upload_mvd(w.frames)
+    same = bool(np.array_equal(out_sub, c.synthesize(v)))
+    c.close()
+    per_cam = [f.rgb.nbytes + f.depth_mm.nbytes for f in w.frames]
+    sent = sum(b for k, b in enumerate(per_cam) if mask >> k & 1)
+    return {"n_tx": 5, "cameras_sent": bin(mask).count("1"), "cameras": len(w.rig),
+            "bytes_sent_frac": round(sent / sum(per_cam), 4), "host_upload_ms_all": round(all_ms, 3),
+            "host_upload_ms_subset": round(sub_ms, 3), "view_identical_to_full_upload": same}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -508,6 +538,9 @@ def main():
                          f"single-threaded, {dt:.1f} s on {platform.processor() or platform.machine()}"}
         log(f"[bench] cpu oracle {cpu['value']} Mpix/s")
 
+    tx = run_tx_policy(fvv, torch, w)
+    log(f"[bench] transmission policy {json.dumps(tx)}")
+
     layered = None
     if args.layered:
         log("[bench] layered FG/BG step (generating background models)")
@@ -565,6 +598,7 @@ def main():
         "serving_learned": serving_learned,
         "depth_codec": codec,
         "layered": layered,
+        "tx_policy": tx,
         "path": "plain",
     }
     print(json.dumps(res), flush=True)

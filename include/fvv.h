@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define FVV_ABI_VERSION 5
+#define FVV_ABI_VERSION 6
 
 /* status codes */
 enum {
@@ -253,6 +253,19 @@ int32_t fvv_select_cameras(const fvv_camera *rig, const int32_t *present, int32_
                            const fvv_camera *virt, int32_t k, int32_t *idx, float *w);
 int32_t fvv_pair_matrices(const fvv_camera *src, const fvv_camera *virt, float *out26);
 
+/* Adaptive view transmission (Section V-C): only the n_tx cameras nearest
+ * to a client's viewpoint are transmitted (five for one client, two more
+ * than the three rendered, so a moving viewpoint always finds its cameras);
+ * with several clients, the union.  Writes the set as a bit mask (bit c =
+ * rig camera c) to *mask and returns its size, or FVV_E_ARG.  The ranking is
+ * that of fvv_select_cameras (centre distance, ties to the lower index)
+ * without the coincident-camera shortcut, so for n_tx >= k every camera the
+ * synthesis selects for these viewpoints is in the set, and uploading only
+ * the set renders those viewpoints exactly as uploading every camera.
+ * Host-only. */
+int32_t fvv_tx_cameras(const fvv_camera *rig, int32_t n, const fvv_camera *views, int32_t n_views,
+                       int32_t n_tx, uint32_t *mask);
+
 /* Debug taps for stage-by-stage checking.  fvv_set_debug(ctx, 1) makes the
  * next synthesis keep, for its first view, the raw and filtered z-buffers and
  * the blend result before hole filling; fvv_debug_read copies one of them to
@@ -280,6 +293,12 @@ int32_t fvv_set_profiling(fvv_ctx *ctx, int32_t enable);
 int32_t fvv_stage_count(void);
 const char *fvv_stage_name(int32_t stage);
 int32_t fvv_profile_read(fvv_ctx *ctx, double *total_ms, int64_t *launches, int32_t n, int32_t reset);
+
+/* Transmission set of the served clients: fvv_tx_cameras over the
+ * viewpoints of the requests submitted in the last window_s seconds (at most
+ * the last 4096 requests).  The edge server asks the capture side for these
+ * cameras and uploads only them.  FVV_E_STATE if the server is not running. */
+int32_t fvv_server_tx_cameras(fvv_ctx *ctx, int32_t n_tx, double window_s, uint32_t *mask);
 
 /* Continuous-batching server: many users' viewpoint requests of any output
  * size rendered against the device-resident frame store (the edge server

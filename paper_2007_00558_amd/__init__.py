@@ -112,6 +112,8 @@ def lib():
             "fvv_set_bg_model": (I32, [P, P, P, I32, I32, P]),
             "fvv_set_prefilter": (I32, [P, I32, I32, C.c_float, C.c_float, I32]),
             "fvv_read_frame_depth": (I32, [P, I32, I32, U64, P, I64]),
+            "fvv_tx_cameras": (I32, [C.POINTER(Camera), I32, C.POINTER(Camera), I32, I32, C.POINTER(C.c_uint32)]),
+            "fvv_server_tx_cameras": (I32, [P, I32, C.c_double, C.POINTER(C.c_uint32)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -130,7 +132,7 @@ EXPORTED = ("fvv_abi_version", "fvv_create", "fvv_destroy", "fvv_last_error", "f
             "fvv_net_read", "fvv_make_stack", "fvv_net_forward", "fvv_net_train_step",
             "fvv_net_read_act", "fvv_net_device_bytes", "fvv_depth_encode_y12",
             "fvv_depth_decode_y12", "fvv_set_depth_format", "fvv_set_bg_model", "fvv_set_prefilter",
-            "fvv_read_frame_depth")
+            "fvv_read_frame_depth", "fvv_tx_cameras", "fvv_server_tx_cameras")
 DEPTH_MM16, DEPTH_Y12 = 0, 1
 NET_PARAMS, NET_GRADS = 0, 1
 NET_ALIGN = 8           # network inputs: multiples of 8 in both dimensions
@@ -213,6 +215,18 @@ def select_cameras(rig: Sequence, virt, k: int, present=None):
     if K < 0:
         raise FvvError(K, "fvv_select_cameras rejected its arguments")
     return idx[:K].copy(), w[:K].copy()
+
+
+def tx_cameras(rig: Sequence, viewpoints: Sequence, n_tx: int = 5) -> int:
+    """Bit mask of the cameras to transmit for these client viewpoints."""
+    n, nv = len(rig), len(viewpoints)
+    arr = (Camera * n)(*[camera(c) for c in rig])
+    va = (Camera * max(nv, 1))(*[camera(v) for v in viewpoints])
+    m = C.c_uint32(0)
+    rc = lib().fvv_tx_cameras(arr, n, va, nv, n_tx, C.byref(m))
+    if rc < 0:
+        raise FvvError(rc, "fvv_tx_cameras rejected its arguments")
+    return m.value
 
 
 def pair_matrices(src, virt):
@@ -491,6 +505,14 @@ class Server:
 
     def pause(self, on: bool = True):
         self.ctx._check(self.ctx._L.fvv_server_pause(self.ctx._h, 1 if on else 0))
+
+    def tx_cameras(self, n_tx: int = 5, window_s: float = 1.0) -> int:
+        """Bit mask of the cameras the recent clients need (adaptive transmission)."""
+        m = C.c_uint32(0)
+        rc = self.ctx._L.fvv_server_tx_cameras(self.ctx._h, n_tx, window_s, C.byref(m))
+        if rc < 0:
+            self.ctx._check(rc)
+        return m.value
 
     def stop(self):
         if self.running:

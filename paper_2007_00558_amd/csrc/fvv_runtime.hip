@@ -115,6 +115,9 @@ struct Server {
     std::mutex qmu;                       // pending, busy, stop
     std::condition_variable qcv;
     std::deque<Request> pending;
+    // viewpoints of recent requests (arrival time, camera) for the
+    // transmission set; bounded
+    std::deque<std::pair<Clock::time_point, fvv_camera>> recent;
     bool stop = false;
     bool paused = false;
     std::mutex cmu[2];
@@ -266,6 +269,30 @@ void centre(const fvv_camera &c, double C[3])
         for (int k = 0; k < 3; ++k) s += (double)c.R[k * 3 + r] * (double)c.t[k];
         C[r] = -s;
     }
+}
+
+// Adaptive view transmission (Section V-C): OR into m the n_tx rig cameras
+// nearest to viewpoint v (centre distance, ties to the lower index).
+void tx_union(const fvv_camera *rig, int n, const fvv_camera &v, int n_tx, uint32_t &m)
+{
+    double Cv[3];
+    centre(v, Cv);
+    std::vector<std::pair<double, int>> d;
+    for (int c = 0; c < n; ++c) {
+        double Cc[3];
+        centre(rig[c], Cc);
+        const double dx = Cc[0] - Cv[0], dy = Cc[1] - Cv[1], dz = Cc[2] - Cv[2];
+        d.emplace_back(std::sqrt(dx * dx + dy * dy + dz * dz), c);
+    }
+    std::stable_sort(d.begin(), d.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
+    for (int e = 0; e < n_tx && e < n; ++e) m |= 1u << d[e].second;
+}
+
+int popcount32(uint32_t m)
+{
+    int c = 0;
+    for (; m; m &= m - 1) ++c;
+    return c;
 }
 
 // Rank present cameras by centre distance (stable: ties keep the lower index);
@@ -1424,6 +1451,17 @@ int32_t fvv_select_cameras(const fvv_camera *rig, const int32_t *present, int32_
     return K;
 }
 
+int32_t fvv_tx_cameras(const fvv_camera *rig, int32_t n, const fvv_camera *views, int32_t n_views, int32_t n_tx,
+                       uint32_t *mask)
+{
+    if (!rig || !mask || n < 1 || n > FVV_MAX_CAMERAS || n_tx < 1 || n_views < 0 || (n_views > 0 && !views))
+        return FVV_E_ARG;
+    uint32_t m = 0;
+    for (int v = 0; v < n_views; ++v) tx_union(rig, n, views[v], n_tx, m);
+    *mask = m;
+    return popcount32(m);
+}
+
 int32_t fvv_pair_matrices(const fvv_camera *src, const fvv_camera *virt, float *out26)
 {
     if (!src || !virt || !out26) return FVV_E_ARG;
@@ -1608,6 +1646,8 @@ int32_t fvv_submit(fvv_ctx *c, const fvv_camera *virt, const fvv_synth_params *p
     r.arrive = Clock::now();
     {
         std::lock_guard<std::mutex> lk(S->qmu);
+        S->recent.emplace_back(r.arrive, *virt);
+        if (S->recent.size() > 4096) S->recent.pop_front();
         if (S->stop) return FVV_E_STATE;
         if (S->pending.size() >= 65536) return FVV_E_AGAIN;
         r.ticket = S->next_ticket++;
@@ -1634,6 +1674,25 @@ int32_t fvv_poll(fvv_ctx *c, uint64_t ticket, double *latency_s)
     if (latency_s) *latency_s = it->second.latency;
     S->results.erase(it);
     return st;
+}
+
+int32_t fvv_server_tx_cameras(fvv_ctx *c, int32_t n_tx, double window_s, uint32_t *mask)
+{
+    if (!c || !mask || n_tx < 1 || !(window_s >= 0.0)) return FVV_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (!c->server) return fail(c, FVV_E_STATE, "server not running");
+    Server *S = c->server;
+    std::vector<fvv_camera> views;
+    {
+        std::lock_guard<std::mutex> q(S->qmu);
+        const Clock::time_point now = Clock::now();
+        for (const auto &e : S->recent)
+            if (std::chrono::duration<double>(now - e.first).count() <= window_s) views.push_back(e.second);
+    }
+    uint32_t m = 0;
+    for (const auto &v : views) tx_union(c->rig.data(), (int)c->rig.size(), v, n_tx, m);
+    *mask = m;
+    return popcount32(m);
 }
 
 int32_t fvv_server_stats(fvv_ctx *c, uint64_t *out6)

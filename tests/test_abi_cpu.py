@@ -27,7 +27,7 @@ def test_library_exports_every_declared_function():
     for name in names:
         assert hasattr(L, name), name
     assert set(names) == set(fvv.EXPORTED)
-    assert L.fvv_abi_version() == 5
+    assert L.fvv_abi_version() == 6
 
 
 def test_header_struct_layouts_match_binding():
@@ -122,3 +122,21 @@ def test_codec_argument_checks_need_no_device():
         assert L.fvv_depth_encode_y12(d, dp, W, H, zn, zf, y, yp, None) == fvv.FVV_E_ARG
         assert L.fvv_depth_decode_y12(y, yp, W, H, zn, zf, d, dp, None) == fvv.FVV_E_ARG
         assert L.fvv_last_error(None)
+
+
+def test_tx_cameras_bit_exact_vs_oracle(oracle_lib):
+    """Adaptive transmission set (host-only) against the oracle."""
+    rng = np.random.default_rng(0)
+    rigs = [sg.config3(0, n_frames=2, src_w=64, src_h=36).rig, sg.config_small(1, n_cams=5).rig]
+    for rig in rigs:
+        for _ in range(40):
+            nv = int(rng.integers(1, 4))
+            views = [sg.arc_camera(rng.uniform(-80, 80), rng.uniform(1.8, 3.2), 64, 36) for _ in range(nv)]
+            for n_tx in (1, 3, 5, len(rig)):
+                assert fvv.tx_cameras(rig, views, n_tx) == oracle_lib.tx_cameras(rig, views, n_tx)
+    L = fvv.lib()
+    m = C.c_uint32(0)
+    arr = (fvv.Camera * 1)(fvv.camera(rigs[1][0]))
+    assert L.fvv_tx_cameras(arr, 1, arr, 1, 0, C.byref(m)) == fvv.FVV_E_ARG
+    assert L.fvv_tx_cameras(arr, 0, arr, 1, 1, C.byref(m)) == fvv.FVV_E_ARG
+    assert L.fvv_tx_cameras(arr, 1, None, 0, 1, C.byref(m)) == 0 and m.value == 0
