@@ -35,7 +35,7 @@ def counted_traffic(kernel: str, n_views: int):
     if kernel != "tile" or n_views != 60 or not os.path.exists(path):
         return None
     for line in open(path):
-        if line.startswith("traffic_bytes_per_launch k_tile<false> 60 views:"):
+        if line.startswith("traffic_bytes_per_launch k_tile_plain 60 views:"):
             return int(line.split(":")[1])
     return None
 

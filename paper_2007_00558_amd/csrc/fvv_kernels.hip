@@ -133,9 +133,10 @@ __device__ __forceinline__ uint32_t live_mm(const fvv_repack_batch &b, const fvv
 // Hole-filling joint bilateral pre-filter (Section VI pre-processing of the
 // live depth): the integer bilateral mean of the valid depths around a hole,
 // spatial weight times the weight of the L1 colour distance, when at least
-// jbf_min neighbours carry weight; 0 (still a hole) otherwise.
-__device__ __noinline__ uint32_t jbf_fill(const fvv_repack_batch &b, const fvv_repack_cam &c, int x, int y,
-                                          const uint8_t *p)
+// jbf_min neighbours carry weight; 0 (still a hole) otherwise.  Inlined: the
+// batch lives in the kernel arguments, and a call would copy it to scratch.
+__device__ __forceinline__ uint32_t jbf_fill(const fvv_repack_batch &b, const fvv_repack_cam &c, int x, int y,
+                                             const uint8_t *p)
 {
     const int r = b.jbf_radius, n = 2 * r + 1;
     const uint32_t *ws = b.jbf, *wc = b.jbf + FVV_JBF_WS;

@@ -835,10 +835,19 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
     for (int q = 0; q < 2; ++q)
         if (waited[q] && (rc = note_reader(c, c->slots[q], s))) return rc;
     if (host_out && !lio.scratch_out) {
-        for (int v = 0; v < n_views; ++v)
-            HIPCHECK(c, hipMemcpy2DAsync(outs[v], pitches[v], host_stage[v], (size_t)virts[v].width * 3,
-                                         (size_t)virts[v].width * 3, virts[v].height, hipMemcpyDeviceToHost, s));
+        // caller's pageable host memory: blocking copies once the views are
+        // done (an asynchronous copy into pageable memory is not guaranteed
+        // to have landed by the stream synchronisation under every runtime
+        // configuration, e.g. with a tracing tool attached)
         HIPCHECK(c, hipStreamSynchronize(s));
+        for (int v = 0; v < n_views; ++v) {
+            const size_t row = (size_t)virts[v].width * 3;
+            if (pitches[v] == (int64_t)row)
+                HIPCHECK(c, hipMemcpy(outs[v], host_stage[v], row * virts[v].height, hipMemcpyDeviceToHost));
+            else
+                HIPCHECK(c, hipMemcpy2D(outs[v], pitches[v], host_stage[v], row, row, virts[v].height,
+                                        hipMemcpyDeviceToHost));
+        }
     }
     return FVV_OK;
 }
@@ -1173,8 +1182,12 @@ int32_t fvv_set_bg_model(fvv_ctx *c, const void *const *depth_mm, const int64_t 
         const int W = c->rig[k].width, H = c->rig[k].height;
         int32_t rc = dalloc(c, (void **)&c->bg_model[k], (size_t)W * H * 2);
         if (rc) return rc;
-        HIPCHECK(c, hipMemcpy2DAsync(c->bg_model[k], (size_t)W * 2, depth_mm[k], pitches[k], (size_t)W * 2, H,
-                                     mem_kind == FVV_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s));
+        if (mem_kind == FVV_MEM_HOST)
+            HIPCHECK(c, hipMemcpy2D(c->bg_model[k], (size_t)W * 2, depth_mm[k], pitches[k], (size_t)W * 2, H,
+                                    hipMemcpyHostToDevice));
+        else
+            HIPCHECK(c, hipMemcpy2DAsync(c->bg_model[k], (size_t)W * 2, depth_mm[k], pitches[k], (size_t)W * 2, H,
+                                         hipMemcpyDeviceToDevice, s));
     }
     HIPCHECK(c, hipStreamSynchronize(s));
     return FVV_OK;
@@ -1232,7 +1245,9 @@ int32_t fvv_upload_mvd(fvv_ctx *c, const fvv_view *views, int32_t n, int32_t mem
     else if (host) HIPCHECK(c, hipStreamWaitEvent(s, c->staging_free, 0));
     for (auto &r : fs.readers) HIPCHECK(c, hipStreamWaitEvent(s, r.second, 0));
     // device memory is read in place by the repack kernel; host memory is
-    // first copied into the staging buffer
+    // first copied into the staging buffer, with blocking copies from the
+    // caller's pageable memory once the stream is idle
+    if (host) HIPCHECK(c, hipStreamSynchronize(s));
     fvv_repack_batch b{};
     int max_w = 0, max_h = 0;
     uint8_t *cur = c->staging;
@@ -1248,19 +1263,19 @@ int32_t fvv_upload_mvd(fvv_ctx *c, const fvv_view *views, int32_t n, int32_t mem
             cur += align256((size_t)W * H * 3);
             uint8_t *dep = cur;
             cur += align256(depth_bytes(W, H));
-            HIPCHECK(c, hipMemcpy2DAsync(rgb, (size_t)W * 3, v.rgb, v.rgb_pitch, (size_t)W * 3, H,
-                                         hipMemcpyHostToDevice, s));
+            HIPCHECK(c, hipMemcpy2D(rgb, (size_t)W * 3, v.rgb, v.rgb_pitch, (size_t)W * 3, H,
+                                    hipMemcpyHostToDevice));
             if (y12) {
                 // Y rows, then the U and V planes at half the pitch
                 const uint8_t *src = (const uint8_t *)v.depth_mm;
                 const int64_t sp = v.depth_pitch, up = sp / 2;
-                HIPCHECK(c, hipMemcpy2DAsync(dep, (size_t)W, src, sp, (size_t)W, H, hipMemcpyHostToDevice, s));
-                HIPCHECK(c, hipMemcpy2DAsync(dep + (size_t)W * H, (size_t)W / 2, src + (int64_t)H * sp, up,
-                                             (size_t)W / 2, H, hipMemcpyHostToDevice, s));
+                HIPCHECK(c, hipMemcpy2D(dep, (size_t)W, src, sp, (size_t)W, H, hipMemcpyHostToDevice));
+                HIPCHECK(c, hipMemcpy2D(dep + (size_t)W * H, (size_t)W / 2, src + (int64_t)H * sp, up, (size_t)W / 2,
+                                        H, hipMemcpyHostToDevice));
                 rc_.depth_pitch = W;
             } else {
-                HIPCHECK(c, hipMemcpy2DAsync(dep, (size_t)W * 2, v.depth_mm, v.depth_pitch, (size_t)W * 2, H,
-                                             hipMemcpyHostToDevice, s));
+                HIPCHECK(c, hipMemcpy2D(dep, (size_t)W * 2, v.depth_mm, v.depth_pitch, (size_t)W * 2, H,
+                                        hipMemcpyHostToDevice));
                 rc_.depth_pitch = (int64_t)W * 2;
             }
             rc_.rgb = rgb;

@@ -1303,7 +1303,10 @@ hipError_t unet_set_params(unet_state *n, const float *host, hipStream_t s)
         NCHK(hipMalloc((void **)&n->wf, T.n_wf * 2));
         NCHK(hipMalloc((void **)&n->wd, T.n_wd * 2));
     }
-    NCHK(hipMemcpyAsync(n->w, host, T.n_params * 4, hipMemcpyHostToDevice, s));
+    // host buffers are the caller's pageable memory: blocking copies with the
+    // stream idle
+    NCHK(hipStreamSynchronize(s));
+    NCHK(hipMemcpy(n->w, host, T.n_params * 4, hipMemcpyHostToDevice));
     NCHK(hipMemsetAsync(n->m, 0, T.n_params * 4, s));
     NCHK(hipMemsetAsync(n->v, 0, T.n_params * 4, s));
     NCHK(hipMemsetAsync(n->g, 0, T.n_params * 4, s));
@@ -1317,14 +1320,14 @@ hipError_t unet_set_params(unet_state *n, const float *host, hipStream_t s)
 
 hipError_t unet_get_params(unet_state *n, float *host, hipStream_t s)
 {
-    NCHK(hipMemcpyAsync(host, n->w, layers().n_params * 4, hipMemcpyDeviceToHost, s));
-    return hipStreamSynchronize(s);
+    NCHK(hipStreamSynchronize(s));
+    return hipMemcpy(host, n->w, layers().n_params * 4, hipMemcpyDeviceToHost);
 }
 
 hipError_t unet_get_grads(unet_state *n, float *host, hipStream_t s)
 {
-    NCHK(hipMemcpyAsync(host, n->g, layers().n_params * 4, hipMemcpyDeviceToHost, s));
-    return hipStreamSynchronize(s);
+    NCHK(hipStreamSynchronize(s));
+    return hipMemcpy(host, n->g, layers().n_params * 4, hipMemcpyDeviceToHost);
 }
 
 hipError_t unet_forward(unet_state *n, unet_act *a, const uint16_t *stack, int NB, int H, int W, float *s_out,
@@ -1462,8 +1465,8 @@ hipError_t unet_train(unet_state *n, unet_act *a, const uint16_t *stack, const f
     }
     if (loss_host) {
         float sum = 0.f;
-        NCHK(hipMemcpyAsync(&sum, a->loss_dev, 4, hipMemcpyDeviceToHost, s));
         NCHK(hipStreamSynchronize(s));
+        NCHK(hipMemcpy(&sum, a->loss_dev, 4, hipMemcpyDeviceToHost));
         *loss_host = (float)(sum / ((double)NB * valid_h * W * 3));
     }
     return hipSuccess;
@@ -1496,6 +1499,6 @@ hipError_t unet_read_act(unet_act *a, int layer, void *host, size_t bytes, hipSt
     if (!src || a->NB == 0) return hipErrorInvalidValue;
     const size_t P = ((size_t)a->NB * a->H * a->W) >> (2 * kOutLevel[layer]);
     if (bytes != P * C * 2) return hipErrorInvalidValue;
-    NCHK(hipMemcpy2DAsync(host, (size_t)C * 2, src + off, (size_t)cs * 2, (size_t)C * 2, P, hipMemcpyDeviceToHost, s));
-    return hipStreamSynchronize(s);
+    NCHK(hipStreamSynchronize(s));
+    return hipMemcpy2D(host, (size_t)C * 2, src + off, (size_t)cs * 2, (size_t)C * 2, P, hipMemcpyDeviceToHost);
 }
