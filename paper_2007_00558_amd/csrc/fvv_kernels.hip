@@ -508,7 +508,10 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
     // ---- S1: splat every binned source block into the window; each wave
     // takes its own list entries (one 8x8 source block = one wave)
     const bool scan_all = n_entries > vd.tile_cap;
-    const int lane = t & 63, wave = t >> 6;
+    // the wave index and every list entry are wave-uniform: kept in scalar
+    // registers, the source descriptor of an entry is read with scalar loads
+    // and its block arithmetic runs on the scalar unit
+    const int lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int si = lane & (FVV_SBLK - 1), sj = lane / FVV_SBLK;
     // depth bits of this lane's pixel of block `ent` (FVV_NO_DEPTH outside)
     auto block_depth = [&](int ent) -> uint32_t {
@@ -547,7 +550,7 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
                 base = q;
                 ents = q + lane < nq ? lst[wave + TNW * (q + lane)] : 0;
             }
-            return __shfl(ents, q - base, 64);
+            return __builtin_amdgcn_readlane(ents, q - base);
         };
         int e0 = 0, e1 = 0;
         uint32_t z0 = FVV_NO_DEPTH, z1 = FVV_NO_DEPTH;
