@@ -336,6 +336,9 @@ __device__ __forceinline__ unsigned long long filter_key(unsigned long long c, u
 // contributes.
 __device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int k0, int x, int y, float zf, uint32_t &rgba)
 {
+    // Decisions (sample in range, tap valid and depth-consistent, camera
+    // survives) in float32 op by op; the colour mix is value arithmetic and
+    // uses fused multiply-adds and hardware reciprocals.
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, wsum = 0.f;
     for (int k = k0; k < k0 + vd.K; ++k) {
         const fvv_src_desc &s = vd.src[k];
@@ -352,30 +355,34 @@ __device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int k0, int
         const float lim = __fmul_rn(vd.tau, q2);
         const float gu = 1.0f - fu, gv = 1.0f - fv;
         const float wt[4] = {gu * gv, fu * gv, gu * fv, fu * fv};
+        // i0 >= -1 and i0 <= W - 1 (likewise j0): only the outer taps can fall off
+        const bool okc[2] = {i0 >= 0, i0 + 1 < s.W};
+        const bool okr[2] = {j0 >= 0, j0 + 1 < s.H};
+        const int64_t o = (int64_t)j0 * s.W + i0;
         float c0 = 0.f, c1 = 0.f, c2 = 0.f, csum = 0.f;
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
-            const int ti = i0 + (n & 1), tj = j0 + (n >> 1);
-            if (ti < 0 || tj < 0 || ti >= s.W || tj >= s.H) continue;
-            const uint2 tx = s.texel[(int64_t)tj * s.W + ti];
+            if (!(okc[n & 1] && okr[n >> 1])) continue;
+            const uint2 tx = s.texel[o + (n >> 1) * s.W + (n & 1)];
             if (tx.y == FVV_NO_DEPTH) continue;
             if (!(fabsf(__fsub_rn(u2f(tx.y), q2)) <= lim)) continue;
-            c0 += wt[n] * (float)(tx.x & 0xFF);
-            c1 += wt[n] * (float)((tx.x >> 8) & 0xFF);
-            c2 += wt[n] * (float)((tx.x >> 16) & 0xFF);
+            c0 = fmaf(wt[n], (float)(tx.x & 0xFF), c0);
+            c1 = fmaf(wt[n], (float)((tx.x >> 8) & 0xFF), c1);
+            c2 = fmaf(wt[n], (float)((tx.x >> 16) & 0xFF), c2);
             csum += wt[n];
         }
         if (!(csum > 0.f)) continue;
-        const float inv = s.wgt / csum;
-        acc0 += c0 * inv;
-        acc1 += c1 * inv;
-        acc2 += c2 * inv;
+        const float inv = s.wgt * __builtin_amdgcn_rcpf(csum);
+        acc0 = fmaf(c0, inv, acc0);
+        acc1 = fmaf(c1, inv, acc1);
+        acc2 = fmaf(c2, inv, acc2);
         wsum += s.wgt;
     }
     if (!(wsum > 0.f)) return false;
-    const float r = fminf(floorf(acc0 / wsum + 0.5f), 255.f);
-    const float g = fminf(floorf(acc1 / wsum + 0.5f), 255.f);
-    const float b = fminf(floorf(acc2 / wsum + 0.5f), 255.f);
+    const float iw = __builtin_amdgcn_rcpf(wsum);
+    const float r = fminf(floorf(fmaf(acc0, iw, 0.5f)), 255.f);
+    const float g = fminf(floorf(fmaf(acc1, iw, 0.5f)), 255.f);
+    const float b = fminf(floorf(fmaf(acc2, iw, 0.5f)), 255.f);
     rgba = (uint32_t)r | ((uint32_t)g << 8) | ((uint32_t)b << 16) | 0xFF000000u;
     return true;
 }
