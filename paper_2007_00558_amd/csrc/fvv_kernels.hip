@@ -522,6 +522,7 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
     const int si = lane & (FVV_SBLK - 1), sj = lane / FVV_SBLK;
     // depth bits of this lane's pixel of block `ent` (FVV_NO_DEPTH outside)
     auto block_depth = [&](int ent) -> uint32_t {
+        ent = __builtin_amdgcn_readfirstlane(ent);   // uniform (see above)
         const fvv_src_desc &s = vd.src[ent >> 24];
         const int blk = ent & 0xFFFFFF;
         const int by = blk / s.nbx, bx = blk - by * s.nbx;
@@ -530,6 +531,7 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
         return f2u(s.depth[(int64_t)j * s.W + i]);
     };
     auto splat_entry = [&](int ent, uint32_t zb) {
+        ent = __builtin_amdgcn_readfirstlane(ent);   // uniform; the pipeline's copies lose that
         if (zb == FVV_NO_DEPTH) return;
         const fvv_src_desc &s = vd.src[ent >> 24];
         const int blk = ent & 0xFFFFFF;
