@@ -99,6 +99,32 @@ __device__ __forceinline__ bool splat_point(const fvv_src_desc &s, int W, int H,
     return true;
 }
 
+// Wave-wide min / max of (y << 16 | x) pairs with DPP lane moves (packed
+// u16 min / max, both halves at once): pairs, quads, half rows and rows
+// inside each 16-lane row, then the row broadcasts carry rows 0 -> 1, 2 -> 3
+// and 1 -> 2, 3; lane 63 then holds the result for the whole wave.  Lanes a
+// move does not write keep their own value (old = v), the identity of min
+// and max.
+typedef unsigned short fvv_u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ fvv_u16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(fvv_u16x2, v); }
+__device__ __forceinline__ uint32_t as_u32(fvv_u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+template <bool MIN>
+__device__ __forceinline__ uint32_t wave_reduce_u16x2(uint32_t v)
+{
+    auto op = [](uint32_t a, uint32_t b) {
+        return as_u32(MIN ? __builtin_elementwise_min(as_u16x2(a), as_u16x2(b))
+                          : __builtin_elementwise_max(as_u16x2(a), as_u16x2(b)));
+    };
+    int w = (int)v;
+    w = (int)op((uint32_t)w, (uint32_t)__builtin_amdgcn_update_dpp(w, w, 0xB1, 0xF, 0xF, false));
+    w = (int)op((uint32_t)w, (uint32_t)__builtin_amdgcn_update_dpp(w, w, 0x4E, 0xF, 0xF, false));
+    w = (int)op((uint32_t)w, (uint32_t)__builtin_amdgcn_update_dpp(w, w, 0x141, 0xF, 0xF, false));
+    w = (int)op((uint32_t)w, (uint32_t)__builtin_amdgcn_update_dpp(w, w, 0x140, 0xF, 0xF, false));
+    w = (int)op((uint32_t)w, (uint32_t)__builtin_amdgcn_update_dpp(w, w, 0x142, 0xA, 0xF, false));
+    w = (int)op((uint32_t)w, (uint32_t)__builtin_amdgcn_update_dpp(w, w, 0x143, 0xC, 0xF, false));
+    return (uint32_t)__builtin_amdgcn_readlane(w, 63);
+}
+
 __device__ __forceinline__ float wave_minf(float v)
 {
     for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
@@ -200,32 +226,6 @@ __global__ void __launch_bounds__(256) k_desc(const uint4 *__restrict__ src, uin
 }
 
 // ---------------------------------------------------------------- binning
-// Wave-wide min / max with DPP lane moves: pairs, quads, half rows and rows
-// inside each 16-lane row, then the row broadcasts carry rows 0 -> 1,
-// 2 -> 3 and 1 -> 2, 3; lane 63 then holds the result for the whole wave.
-// Lanes a move does not write keep their own value (old = v), the identity
-// of min and max.
-__device__ __forceinline__ int wave_min(int v)
-{
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));    // quad_perm [1,0,3,2]
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));    // quad_perm [2,3,0,1]
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));   // row_half_mirror
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));   // row_mirror
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));   // row_bcast:15
-    v = min(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));   // row_bcast:31
-    return __builtin_amdgcn_readlane(v, 63);
-}
-__device__ __forceinline__ int wave_max(int v)
-{
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));
-    return __builtin_amdgcn_readlane(v, 63);
-}
-
 // One wave per (view, camera slot, 8x8 source block), one lane per pixel:
 // the exact output bounds of the block's footprints (each pixel projected as
 // the splat projects it), turned into the range of tiles whose window -- the
@@ -240,30 +240,30 @@ __global__ void __launch_bounds__(256) k_bin(const fvv_view_desc *__restrict__ v
     if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) *vd.open_count = 0;
     const int k = blockIdx.y;
     const int lane = threadIdx.x & 63;
-    const int blk = blockIdx.x * 4 + (threadIdx.x >> 6);
+    // wave-uniform block index: the block arithmetic stays on the scalar unit
+    const int blk = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (k >= fvv_nsrc(vd)) return;
     const fvv_src_desc &s = vd.src[k];
     if (blk >= s.nblk) return;
     const int by = blk / s.nbx, bx = blk - by * s.nbx;
     const int i = bx * FVV_SBLK + (lane & (FVV_SBLK - 1));
     const int j = by * FVV_SBLK + lane / FVV_SBLK;
-    int x0 = INT_MAX, x1 = -1, y0 = INT_MAX, y1 = -1;
+    // footprint bounds as (y << 16 | x) pairs; clipped to the output
+    // (< 8192), so 15 bits each; 0x7FFF in the low pair marks "none"
+    uint32_t lo = 0x7FFF7FFFu, hi = 0u;
     if (i < s.W && j < s.H) {
         const uint32_t zb = f2u(s.depth[(int64_t)j * s.W + i]);
         Footprint f;
         if (zb != FVV_NO_DEPTH && splat_point(s, vd.W, vd.H, vd.max_fp, i, j, u2f(zb), f)) {
-            x0 = f.x0;
-            x1 = f.x1;
-            y0 = f.y0;
-            y1 = f.y1;
+            lo = (uint32_t)f.y0 << 16 | (uint32_t)f.x0;
+            hi = (uint32_t)f.y1 << 16 | (uint32_t)f.x1;
         }
     }
-    x0 = wave_min(x0);
-    y0 = wave_min(y0);
-    x1 = wave_max(x1);
-    y1 = wave_max(y1);
+    lo = wave_reduce_u16x2<true>(lo);
+    hi = wave_reduce_u16x2<false>(hi);
+    const int x0 = (int)(lo & 0xFFFF), y0 = (int)(lo >> 16), x1 = (int)(hi & 0xFFFF), y1 = (int)(hi >> 16);
     int4 t = make_int4(1, 0, 1, 0);   // empty
-    if (x1 >= 0) {
+    if (x0 != 0x7FFF) {
         t.x = max(0, (x0 + T - 1) / T - 1);
         t.y = min(vd.ntx - 1, (x1 + 1) / T);
         t.z = max(0, (y0 + T - 1) / T - 1);
