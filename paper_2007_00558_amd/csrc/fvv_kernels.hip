@@ -778,9 +778,19 @@ __global__ void __launch_bounds__(TNT) k_tile_stack_layered(const fvv_view_desc 
 // A fixed grid walks the batch's list of tiles with open holes.
 __global__ void __launch_bounds__(256) k_fill_open(const fvv_view_desc *__restrict__ views)
 {
-    // the tile's slots are staged in LDS: the scans inside the tile (most of
-    // the work) then cost no dependent global loads
+    // The tile's slots are staged in LDS (the scans inside the tile then
+    // cost no dependent global loads), and the walks beyond the tile, which
+    // every hole of a tile row (or column) would repeat, are done once per
+    // row and direction: s_ox[d][q] = the nearest covered image coordinate
+    // outside the tile (x for left / right of row q, y for up / down of
+    // column q; -1 = none) and s_oz[d][q] its depth bits.
     __shared__ uint32_t s_slot[T * T];
+    __shared__ int s_ox[4][T];
+    __shared__ uint32_t s_oz[4][T];
+    // nearest covered pixel inside the tile in each direction (tile-local
+    // column for left / right, row for up / down; -1 = none), one scan per
+    // row or column instead of one per hole
+    __shared__ int8_t s_in[4][T * T];
     const int n_open = *views[0].open_count;
     for (int item = blockIdx.x; item < n_open; item += gridDim.x) {
         const int2 vt = views[0].open_list[item];
@@ -796,70 +806,79 @@ __global__ void __launch_bounds__(256) k_fill_open(const fvv_view_desc *__restri
             const int ly = e / T, lx = e - ly * T;
             s_slot[e] = (lx < tw && ly < th) ? slot[(int64_t)(Y0 + ly) * W + X0 + lx] : FVV_HOLE;
         }
+        if (threadIdx.x < 4 * T) {
+            const int d = threadIdx.x / T, q = threadIdx.x - d * T;
+            int pos = -1;
+            if (d < 2 && q < th) {
+                const int y = Y0 + q;
+                if (d == 0) {
+                    for (int t2 = tx - 1; t2 >= 0 && pos < 0; --t2) pos = vd.rowsum[(int64_t)(ty * vd.ntx + t2) * T + q].y;
+                } else {
+                    for (int t2 = tx + 1; t2 < vd.ntx && pos < 0; ++t2)
+                        pos = vd.rowsum[(int64_t)(ty * vd.ntx + t2) * T + q].x;
+                }
+                s_oz[d][q] = pos >= 0 ? slot[(int64_t)y * W + pos] : 0u;
+            } else if (d >= 2 && q < tw) {
+                const int x = X0 + q;
+                if (d == 2) {
+                    for (int t2 = ty - 1; t2 >= 0 && pos < 0; --t2) pos = vd.colsum[(int64_t)(t2 * vd.ntx + tx) * T + q].y;
+                } else {
+                    for (int t2 = ty + 1; t2 < vd.nty && pos < 0; ++t2)
+                        pos = vd.colsum[(int64_t)(t2 * vd.ntx + tx) * T + q].x;
+                }
+                s_oz[d][q] = pos >= 0 ? slot[(int64_t)pos * W + x] : 0u;
+            }
+            s_ox[d][q] = pos;
+        }
+        __syncthreads();
+        if (threadIdx.x < 4 * T) {
+            const int d = threadIdx.x / T, q = threadIdx.x - d * T;
+            int last = -1;
+            if (d == 0 && q < th) {
+                for (int lx = 0; lx < tw; ++lx) {
+                    s_in[0][q * T + lx] = (int8_t)last;
+                    if (!(s_slot[q * T + lx] & FVV_HOLE)) last = lx;
+                }
+            } else if (d == 1 && q < th) {
+                for (int lx = tw - 1; lx >= 0; --lx) {
+                    s_in[1][q * T + lx] = (int8_t)last;
+                    if (!(s_slot[q * T + lx] & FVV_HOLE)) last = lx;
+                }
+            } else if (d == 2 && q < tw) {
+                for (int ly = 0; ly < th; ++ly) {
+                    s_in[2][ly * T + q] = (int8_t)last;
+                    if (!(s_slot[ly * T + q] & FVV_HOLE)) last = ly;
+                }
+            } else if (d == 3 && q < tw) {
+                for (int ly = th - 1; ly >= 0; --ly) {
+                    s_in[3][ly * T + q] = (int8_t)last;
+                    if (!(s_slot[ly * T + q] & FVV_HOLE)) last = ly;
+                }
+            }
+        }
         __syncthreads();
         for (int e = threadIdx.x; e < T * T; e += blockDim.x) {
             const int ly = e / T, lx = e - ly * T;
             if (lx >= tw || ly >= th || s_slot[e] != FVV_HOLE_OPEN) continue;
             const int x = X0 + lx, y = Y0 + ly;
-            const int64_t row = (int64_t)y * W;
             // candidates carry image indices y*W + x; depths from the slots
             Cand c{0.f, 0, -1};
             // left
-            int l = lx - 1;
-            while (l >= 0 && (s_slot[ly * T + l] & FVV_HOLE)) --l;
-            if (l >= 0) {
-                offer(c, u2f(s_slot[ly * T + l]), lx - l, y * W + X0 + l);
-            } else {
-                for (int t2 = tx - 1; t2 >= 0; --t2) {
-                    const int xl = vd.rowsum[(int64_t)(ty * vd.ntx + t2) * T + ly].y;
-                    if (xl >= 0) {
-                        offer(c, u2f(slot[row + xl]), x - xl, y * W + xl);
-                        break;
-                    }
-                }
-            }
+            const int l = s_in[0][e];
+            if (l >= 0) offer(c, u2f(s_slot[ly * T + l]), lx - l, y * W + X0 + l);
+            else if (s_ox[0][ly] >= 0) offer(c, u2f(s_oz[0][ly]), x - s_ox[0][ly], y * W + s_ox[0][ly]);
             // right
-            int r = lx + 1;
-            while (r < tw && (s_slot[ly * T + r] & FVV_HOLE)) ++r;
-            if (r < tw) {
-                offer(c, u2f(s_slot[ly * T + r]), r - lx, y * W + X0 + r);
-            } else {
-                for (int t2 = tx + 1; t2 < vd.ntx; ++t2) {
-                    const int xr = vd.rowsum[(int64_t)(ty * vd.ntx + t2) * T + ly].x;
-                    if (xr >= 0) {
-                        offer(c, u2f(slot[row + xr]), xr - x, y * W + xr);
-                        break;
-                    }
-                }
-            }
+            const int r = s_in[1][e];
+            if (r >= 0) offer(c, u2f(s_slot[ly * T + r]), r - lx, y * W + X0 + r);
+            else if (s_ox[1][ly] >= 0) offer(c, u2f(s_oz[1][ly]), s_ox[1][ly] - x, y * W + s_ox[1][ly]);
             // up
-            int u = ly - 1;
-            while (u >= 0 && (s_slot[u * T + lx] & FVV_HOLE)) --u;
-            if (u >= 0) {
-                offer(c, u2f(s_slot[u * T + lx]), ly - u, (Y0 + u) * W + x);
-            } else {
-                for (int t2 = ty - 1; t2 >= 0; --t2) {
-                    const int yu = vd.colsum[(int64_t)(t2 * vd.ntx + tx) * T + lx].y;
-                    if (yu >= 0) {
-                        offer(c, u2f(slot[(int64_t)yu * W + x]), y - yu, yu * W + x);
-                        break;
-                    }
-                }
-            }
+            const int u = s_in[2][e];
+            if (u >= 0) offer(c, u2f(s_slot[u * T + lx]), ly - u, (Y0 + u) * W + x);
+            else if (s_ox[2][lx] >= 0) offer(c, u2f(s_oz[2][lx]), y - s_ox[2][lx], s_ox[2][lx] * W + x);
             // down
-            int d = ly + 1;
-            while (d < th && (s_slot[d * T + lx] & FVV_HOLE)) ++d;
-            if (d < th) {
-                offer(c, u2f(s_slot[d * T + lx]), d - ly, (Y0 + d) * W + x);
-            } else {
-                for (int t2 = ty + 1; t2 < vd.nty; ++t2) {
-                    const int yd = vd.colsum[(int64_t)(t2 * vd.ntx + tx) * T + lx].x;
-                    if (yd >= 0) {
-                        offer(c, u2f(slot[(int64_t)yd * W + x]), yd - y, yd * W + x);
-                        break;
-                    }
-                }
-            }
+            const int d = s_in[3][e];
+            if (d >= 0) offer(c, u2f(s_slot[d * T + lx]), d - ly, (Y0 + d) * W + x);
+            else if (s_ox[3][lx] >= 0) offer(c, u2f(s_oz[3][lx]), s_ox[3][lx] - y, s_ox[3][lx] * W + x);
             uint32_t col = 0;
             if (c.idx >= 0) {
                 const int cy = c.idx / W, cx = c.idx - cy * W;
