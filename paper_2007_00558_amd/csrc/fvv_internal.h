@@ -11,7 +11,9 @@
 #define FVV_KMAX 8
 #define FVV_KEY_EMPTY 0xFFFFFFFFFFFFFFFFull
 #define FVV_NO_DEPTH 0xFFFFFFFFu    // depth-plane marker of a pixel without depth
-#define FVV_BG_MM 0xFFFFu           // background signal of live millimetre maps (no live depth)
+#ifndef FVV_BG_MM
+#define FVV_BG_MM 0xFFFF            // background signal of live millimetre maps (no live depth), as in fvv.h
+#endif
 #define FVV_HOLE 0x80000000u        // slot of a hole filled inside its tile (or left black)
 #define FVV_HOLE_OPEN 0x80000001u   // slot of a hole whose neighbours lie beyond its tile
 #define FVV_ZCLIP 0.01f             // points and samples nearer than this are dropped
