@@ -35,6 +35,12 @@
 
 namespace {
 
+// Pointers the kernels read from global memory, as global-address-space
+// pointers: loads then compile to global_load (not flat_load, which also
+// waits on the LDS counter).
+template <typename V> using gmem = __attribute__((address_space(1))) const V;
+template <typename V> __device__ __forceinline__ gmem<V> *gptr(const V *p) { return (gmem<V> *)p; }
+
 constexpr int T = FVV_TILE;
 constexpr int WN = FVV_TILE + 2;   // tile window edge with a 1-pixel halo
 constexpr int TNT = T * T / 4;     // threads of a tile workgroup: four pixels each
@@ -252,7 +258,7 @@ __global__ void __launch_bounds__(256) k_bin(const fvv_view_desc *__restrict__ v
     // (< 8192), so 15 bits each; 0x7FFF in the low pair marks "none"
     uint32_t lo = 0x7FFF7FFFu, hi = 0u;
     if (i < s.W && j < s.H) {
-        const uint32_t zb = f2u(s.depth[(int64_t)j * s.W + i]);
+        const uint32_t zb = f2u(gptr(s.depth)[(int64_t)j * s.W + i]);
         Footprint f;
         if (zb != FVV_NO_DEPTH && splat_point(s, vd.W, vd.H, vd.max_fp, i, j, u2f(zb), f)) {
             lo = (uint32_t)f.y0 << 16 | (uint32_t)f.x0;
@@ -355,21 +361,31 @@ __device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int k0, int
         const float lim = __fmul_rn(vd.tau, q2);
         const float gu = 1.0f - fu, gv = 1.0f - fv;
         const float wt[4] = {gu * gv, fu * gv, gu * fv, fu * fv};
-        // i0 >= -1 and i0 <= W - 1 (likewise j0): only the outer taps can fall off
+        // i0 >= -1 and i0 <= W - 1 (likewise j0): only the outer taps can fall
+        // off.  The four taps are read together from clamped coordinates and
+        // an invalid or inconsistent tap gets weight 0 (adding 0 * colour and
+        // 0 to the sums leaves them unchanged, as skipping it would).
         const bool okc[2] = {i0 >= 0, i0 + 1 < s.W};
         const bool okr[2] = {j0 >= 0, j0 + 1 < s.H};
-        const int64_t o = (int64_t)j0 * s.W + i0;
+        const int ic[2] = {max(i0, 0), min(i0 + 1, s.W - 1)};
+        const int64_t jr[2] = {(int64_t)max(j0, 0) * s.W, (int64_t)min(j0 + 1, s.H - 1) * s.W};
+        const gmem<unsigned long long> *tex = gptr((const unsigned long long *)s.texel);
+        uint2 tx[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const unsigned long long t = tex[jr[n >> 1] + ic[n & 1]];
+            tx[n] = make_uint2((uint32_t)t, (uint32_t)(t >> 32));
+        }
         float c0 = 0.f, c1 = 0.f, c2 = 0.f, csum = 0.f;
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
-            if (!(okc[n & 1] && okr[n >> 1])) continue;
-            const uint2 tx = s.texel[o + (n >> 1) * s.W + (n & 1)];
-            if (tx.y == FVV_NO_DEPTH) continue;
-            if (!(fabsf(__fsub_rn(u2f(tx.y), q2)) <= lim)) continue;
-            c0 = fmaf(wt[n], (float)(tx.x & 0xFF), c0);
-            c1 = fmaf(wt[n], (float)((tx.x >> 8) & 0xFF), c1);
-            c2 = fmaf(wt[n], (float)((tx.x >> 16) & 0xFF), c2);
-            csum += wt[n];
+            const bool ok = okc[n & 1] && okr[n >> 1] && tx[n].y != FVV_NO_DEPTH &&
+                            fabsf(__fsub_rn(u2f(tx[n].y), q2)) <= lim;
+            const float w = ok ? wt[n] : 0.0f;
+            c0 = fmaf(w, (float)(tx[n].x & 0xFF), c0);
+            c1 = fmaf(w, (float)((tx[n].x >> 8) & 0xFF), c1);
+            c2 = fmaf(w, (float)((tx[n].x >> 16) & 0xFF), c2);
+            csum += w;
         }
         if (!(csum > 0.f)) continue;
         const float inv = s.wgt * __builtin_amdgcn_rcpf(csum);
@@ -528,7 +544,7 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
         const int by = blk / s.nbx, bx = blk - by * s.nbx;
         const int i = bx * FVV_SBLK + si, j = by * FVV_SBLK + sj;
         if (i >= s.W || j >= s.H) return FVV_NO_DEPTH;
-        return f2u(s.depth[(int64_t)j * s.W + i]);
+        return f2u(gptr(s.depth)[(int64_t)j * s.W + i]);
     };
     auto splat_entry = [&](int ent, uint32_t zb) {
         ent = __builtin_amdgcn_readfirstlane(ent);   // uniform; the pipeline's copies lose that
@@ -598,11 +614,6 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
     // ---- S2 + S3: filter and blend four horizontally adjacent pixels
     const int ly = t / TPR, lx0 = (t % TPR) * 4;
     const int y = Y0 + ly;
-    unsigned long long w3[3][6];
-#pragma unroll
-    for (int r = 0; r < 3; ++r)
-#pragma unroll
-        for (int c = 0; c < 6; ++c) w3[r][c] = zk[(ly + r) * WN + lx0 + c];
     uint32_t pslot[4], prgb[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -611,9 +622,12 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
         prgb[q] = 0;
         unsigned long long kf = FVV_KEY_EMPTY;
         if (x < W && y < H) {
-            const unsigned long long c = w3[1][q + 1];
-            unsigned long long nb[8] = {w3[0][q], w3[0][q + 1], w3[0][q + 2], w3[1][q],
-                                        w3[1][q + 2], w3[2][q], w3[2][q + 1], w3[2][q + 2]};
+            // the pixel's 3x3 window, read from LDS per pixel (holding the
+            // 3x6 window of all four would cost 36 registers)
+            const unsigned long long *w3 = zk + ly * WN + lx0 + q;
+            const unsigned long long c = w3[WN + 1];
+            unsigned long long nb[8] = {w3[0], w3[1], w3[2], w3[WN], w3[WN + 2], w3[2 * WN], w3[2 * WN + 1],
+                                        w3[2 * WN + 2]};
             kf = filter_key(c, nb, vd.tau);
             if (kf != FVV_KEY_EMPTY) {
                 const float zf = u2f((uint32_t)(kf >> 32));
