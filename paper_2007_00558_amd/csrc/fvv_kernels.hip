@@ -101,7 +101,7 @@ __device__ __forceinline__ bool splat_point(const fvv_src_desc &s, int W, int H,
     f.y0 = (int)y0f;
     f.y1 = (int)y1f;
     f.key = ((unsigned long long)f2u(q2) << 32) | ((unsigned long long)(uint32_t)s.cam << 27) |
-            (unsigned long long)((int64_t)j * s.W + i);
+            (unsigned long long)(uint32_t)(j * s.W + i);   // < 2^27 pixels
     return true;
 }
 
@@ -258,7 +258,7 @@ __global__ void __launch_bounds__(256) k_bin(const fvv_view_desc *__restrict__ v
     // (< 8192), so 15 bits each; 0x7FFF in the low pair marks "none"
     uint32_t lo = 0x7FFF7FFFu, hi = 0u;
     if (i < s.W && j < s.H) {
-        const uint32_t zb = f2u(gptr(s.depth)[(int64_t)j * s.W + i]);
+        const uint32_t zb = f2u(gptr(s.depth)[(uint32_t)(j * s.W + i)]);
         Footprint f;
         if (zb != FVV_NO_DEPTH && splat_point(s, vd.W, vd.H, vd.max_fp, i, j, u2f(zb), f)) {
             lo = (uint32_t)f.y0 << 16 | (uint32_t)f.x0;
@@ -368,12 +368,14 @@ __device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int k0, int
         const bool okc[2] = {i0 >= 0, i0 + 1 < s.W};
         const bool okr[2] = {j0 >= 0, j0 + 1 < s.H};
         const int ic[2] = {max(i0, 0), min(i0 + 1, s.W - 1)};
-        const int64_t jr[2] = {(int64_t)max(j0, 0) * s.W, (int64_t)min(j0 + 1, s.H - 1) * s.W};
+        // 32-bit texel indices (a source has < 2^27 pixels): a uniform base
+        // plus a 32-bit offset needs no 64-bit address arithmetic
+        const uint32_t jr[2] = {(uint32_t)(max(j0, 0) * s.W), (uint32_t)(min(j0 + 1, s.H - 1) * s.W)};
         const gmem<unsigned long long> *tex = gptr((const unsigned long long *)s.texel);
         uint2 tx[4];
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
-            const unsigned long long t = tex[jr[n >> 1] + ic[n & 1]];
+            const unsigned long long t = tex[jr[n >> 1] + (uint32_t)ic[n & 1]];
             tx[n] = make_uint2((uint32_t)t, (uint32_t)(t >> 32));
         }
         float c0 = 0.f, c1 = 0.f, c2 = 0.f, csum = 0.f;
@@ -544,7 +546,7 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
         const int by = blk / s.nbx, bx = blk - by * s.nbx;
         const int i = bx * FVV_SBLK + si, j = by * FVV_SBLK + sj;
         if (i >= s.W || j >= s.H) return FVV_NO_DEPTH;
-        return f2u(gptr(s.depth)[(int64_t)j * s.W + i]);
+        return f2u(gptr(s.depth)[(uint32_t)(j * s.W + i)]);
     };
     auto splat_entry = [&](int ent, uint32_t zb) {
         ent = __builtin_amdgcn_readfirstlane(ent);   // uniform; the pipeline's copies lose that
