@@ -1054,16 +1054,17 @@ hipError_t conv3_launch(const GemmArgs &g, hipStream_t s)
     return hipGetLastError();
 }
 
-// 3x3 convolution shapes: 32 rows x 16-row patches for 32-channel outputs,
-// else 64 rows x 16-row patches (8-row patches on small grids so more
-// blocks exist)
+// 3x3 convolution shapes (measured on the 960x544 network): 32 output
+// channels x 8-row patches for 32-channel outputs and for grids under 64 K
+// pixels (more blocks where there are few pixels), else 64 channels x
+// 16-row patches
 template <int EPI>
 hipError_t conv3(const GemmArgs &g, hipStream_t s)
 {
     if (g.K % 32 != 0) return hipErrorInvalidValue;
-    if (g.M <= 32) return conv3_launch<1, 16, EPI>(g, s);
+    if (g.M <= 32) return conv3_launch<1, 8, EPI>(g, s);
     if ((int64_t)g.NB * g.H * g.W >= 65536) return conv3_launch<2, 16, EPI>(g, s);
-    return conv3_launch<2, 8, EPI>(g, s);
+    return conv3_launch<1, 8, EPI>(g, s);
 }
 
 // 3x3 conv + bias + ReLU into (out, o_cs, o_off)
