@@ -451,8 +451,12 @@ def main():
         ctx.upload_mvd(raw, mem=fvv.MEM_DEVICE, stream=stream)
         ctx.synthesize_batch(virt_c, outs, stream=stream)
 
-    for _ in range(args.warmup):
+    # warm-up: at least W steps and at least one second (clocks settle)
+    t_w = time.perf_counter()
+    n_w = 0
+    while n_w < args.warmup or time.perf_counter() - t_w < 1.0:
         step()
+        n_w += 1
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
@@ -593,6 +597,7 @@ def main():
                        "single_view_p99": round(float(np.percentile(lat, 99)), 3),
                        "batched_per_view": round(ms / n_views, 4)},
         "stages": stages,
+        "kernel_ms_per_step": round(sum(v["avg_ms"] * v["launches_per_step"] for v in stages.values()), 4),
         "serving": serving,
         "learned": learned,
         "serving_learned": serving_learned,
