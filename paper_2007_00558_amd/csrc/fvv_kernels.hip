@@ -523,11 +523,14 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
     __shared__ unsigned long long zk[NZ];
     __shared__ uint32_t s_slot[T * T];
     __shared__ uint32_t s_rgb[T * T];
-    __shared__ int s_open;
+    __shared__ int s_open, s_hole;
     const int t = threadIdx.x;
     const int n_entries = vd.counts[tile];
     for (int e = t; e < NZ; e += TNT) zk[e] = FVV_KEY_EMPTY;
-    if (t == 0) s_open = 0;
+    if (t == 0) {
+        s_open = 0;
+        s_hole = 0;
+    }
     __syncthreads();
 
     // ---- S1: splat every binned source block into the window; each wave
@@ -671,61 +674,110 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
         }
         if (STACK && vd.stack && x < vd.stack_w && y < vd.stack_h) stack_pixel(vd, x, y, kf);
     }
+    bool any_hole = false;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         s_slot[ly * T + lx0 + q] = pslot[q];
         s_rgb[ly * T + lx0 + q] = prgb[q];
+        any_hole |= (pslot[q] & FVV_HOLE) && lx0 + q < tw && ly < th;
     }
+    if (any_hole) s_hole = 1;
     __syncthreads();
 
     // ---- S4 (local): holes whose nearest covered pixel in every direction
     // lies inside the tile (or beyond the image edge) are filled here; the
     // others are marked open for the second pass.
     const bool fill = vd.fill_mode == 0;
+    // nearest covered pixel inside the tile in each direction for every
+    // pixel (tile-local column for left / right, row for up / down; -1 =
+    // none): one scan per row and column, in the z-buffer's LDS, which is
+    // dead by now; only tiles with holes
+    int8_t *s_in = (int8_t *)zk;
+    static_assert(4 * T * T <= WN * WN * 8, "the scan arrays fit the key window");
+    if (fill && s_hole) {
+        if (t < 4 * T) {
+            const int d = t / T, q = t - d * T;
+            int last = -1;
+            if (d == 0 && q < th) {
+                for (int lx = 0; lx < tw; ++lx) {
+                    s_in[q * T + lx] = (int8_t)last;
+                    if (!(s_slot[q * T + lx] & FVV_HOLE)) last = lx;
+                }
+            } else if (d == 1 && q < th) {
+                for (int lx = tw - 1; lx >= 0; --lx) {
+                    s_in[T * T + q * T + lx] = (int8_t)last;
+                    if (!(s_slot[q * T + lx] & FVV_HOLE)) last = lx;
+                }
+            } else if (d == 2 && q < tw) {
+                for (int ly2 = 0; ly2 < th; ++ly2) {
+                    s_in[2 * T * T + ly2 * T + q] = (int8_t)last;
+                    if (!(s_slot[ly2 * T + q] & FVV_HOLE)) last = ly2;
+                }
+            } else if (d == 3 && q < tw) {
+                for (int ly2 = th - 1; ly2 >= 0; --ly2) {
+                    s_in[3 * T * T + ly2 * T + q] = (int8_t)last;
+                    if (!(s_slot[ly2 * T + q] & FVV_HOLE)) last = ly2;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    uint32_t osl[4], ocol[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int lx = lx0 + q;
+        osl[q] = FVV_HOLE;
+        ocol[q] = 0;
         if (lx >= tw || ly >= th) continue;
-        const int x = X0 + lx;
         uint32_t sl = pslot[q], col = prgb[q];
         if (sl & FVV_HOLE) {
             col = 0;
             sl = FVV_HOLE;
             if (fill) {
                 Cand b{0.f, 0, -1};
-                bool open = false;
-                int xl = lx - 1;
-                while (xl >= 0 && (s_slot[ly * T + xl] & FVV_HOLE)) --xl;
-                if (xl >= 0) offer(b, u2f(s_slot[ly * T + xl]), lx - xl, ly * T + xl);
-                else open = X0 > 0;
+                const int e = ly * T + lx;
+                const int xl = s_in[e], xr = s_in[T * T + e], yu = s_in[2 * T * T + e], yd = s_in[3 * T * T + e];
+                // open: some direction has no covered pixel inside the tile
+                // and the tile does not end at the image edge there
+                const bool open = (xl < 0 && X0 > 0) || (xr < 0 && X0 + tw < W) || (yu < 0 && Y0 > 0) ||
+                                  (yd < 0 && Y0 + th < H);
                 if (!open) {
-                    int xr = lx + 1;
-                    while (xr < tw && (s_slot[ly * T + xr] & FVV_HOLE)) ++xr;
-                    if (xr < tw) offer(b, u2f(s_slot[ly * T + xr]), xr - lx, ly * T + xr);
-                    else open = X0 + tw < W;
-                }
-                if (!open) {
-                    int yu = ly - 1;
-                    while (yu >= 0 && (s_slot[yu * T + lx] & FVV_HOLE)) --yu;
+                    if (xl >= 0) offer(b, u2f(s_slot[ly * T + xl]), lx - xl, ly * T + xl);
+                    if (xr >= 0) offer(b, u2f(s_slot[ly * T + xr]), xr - lx, ly * T + xr);
                     if (yu >= 0) offer(b, u2f(s_slot[yu * T + lx]), ly - yu, yu * T + lx);
-                    else open = Y0 > 0;
-                }
-                if (!open) {
-                    int yd = ly + 1;
-                    while (yd < th && (s_slot[yd * T + lx] & FVV_HOLE)) ++yd;
-                    if (yd < th) offer(b, u2f(s_slot[yd * T + lx]), yd - ly, yd * T + lx);
-                    else open = Y0 + th < H;
+                    if (yd >= 0) offer(b, u2f(s_slot[yd * T + lx]), yd - ly, yd * T + lx);
                 }
                 if (open) {
                     sl = FVV_HOLE_OPEN;
-                    atomicAdd(&s_open, 1);
+                    s_open = 1;
                 } else if (b.idx >= 0) {
                     col = s_rgb[b.idx];
                 }
             }
         }
-        vd.slot[(int64_t)y * W + x] = sl;
-        put_rgb(vd.out, vd.out_pitch, x, y, col);
+        osl[q] = sl;
+        ocol[q] = col;
+    }
+    // the thread's four pixels are adjacent: one 16-byte slot store and
+    // three 4-byte colour stores where alignment allows, else per pixel
+    if (ly < th) {
+        const int x = X0 + lx0;
+        const int64_t so = (int64_t)y * W + x;
+        uint8_t *po = vd.out + (int64_t)y * vd.out_pitch + (int64_t)x * 3;
+        if (lx0 + 3 < tw && (so & 3) == 0 && ((uintptr_t)po & 3) == 0) {
+            *(uint4 *)(vd.slot + so) = make_uint4(osl[0], osl[1], osl[2], osl[3]);
+            uint32_t *pw = (uint32_t *)po;
+            pw[0] = (ocol[0] & 0xFFFFFFu) | (ocol[1] << 24);
+            pw[1] = ((ocol[1] >> 8) & 0xFFFFu) | (ocol[2] << 16);
+            pw[2] = ((ocol[2] >> 16) & 0xFFu) | ((ocol[3] & 0xFFFFFFu) << 8);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (lx0 + q >= tw) continue;
+                vd.slot[so + q] = osl[q];
+                put_rgb(vd.out, vd.out_pitch, x + q, y, ocol[q]);
+            }
+        }
     }
 
     // ---- per-tile row / column summaries of covered pixels for the open pass
