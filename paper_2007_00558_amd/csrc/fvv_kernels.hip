@@ -781,9 +781,14 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
     }
 
     // ---- per-tile row / column summaries of covered pixels for the open pass
+    // (a tile without holes is covered edge to edge)
+    const bool holes = s_hole != 0;
     if (t < T) {
         int first = -1, last = -1;
-        if (t < th)
+        if (t < th && !holes) {
+            first = X0;
+            last = X0 + tw - 1;
+        } else if (t < th)
             for (int c = 0; c < tw; ++c)
                 if (!(s_slot[t * T + c] & FVV_HOLE)) {
                     if (first < 0) first = X0 + c;
@@ -793,7 +798,10 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
     } else if (t < 2 * T) {
         const int c = t - T;
         int first = -1, last = -1;
-        if (c < tw)
+        if (c < tw && !holes) {
+            first = Y0;
+            last = Y0 + th - 1;
+        } else if (c < tw)
             for (int r = 0; r < th; ++r)
                 if (!(s_slot[r * T + c] & FVV_HOLE)) {
                     if (first < 0) first = Y0 + r;
@@ -808,8 +816,9 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
     }
 }
 
-// The plain kernel is held to 64 VGPRs (8 waves per SIMD: it is latency-
-// bound, so occupancy pays); the stack variant keeps its registers.
+// The plain kernel is held to 64 VGPRs (8 waves per SIMD; it uses 52), so
+// the waves of eight workgroups share each SIMD; the stack variant keeps
+// its registers.
 __global__ void __launch_bounds__(TNT) __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_tile_plain(const fvv_view_desc *__restrict__ views, int mtx, int mty, int n_views)
 {
