@@ -40,6 +40,18 @@ def counted_traffic(kernel: str, n_views: int):
     return None
 
 
+def counted_valu_issue(kernel: str):
+    """VALU issue utilisation of the tile kernel from the committed
+    instruction-issue counter summary (fraction of the issue slots), or None."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "tile_bin_fill_c3_issue_counters.md")
+    if kernel != "tile" or not os.path.exists(path):
+        return None
+    for line in open(path):
+        if line.startswith("| `k_tile_plain` |"):
+            return float(line.split("|")[7])
+    return None
+
+
 def net_flops(fvv, H: int, W: int) -> float:
     """Multiply-add FLOPs (x2) of one network forward on an H x W stack:
     3x3 convs and the head per output pixel, transposed convs per input
@@ -513,6 +525,7 @@ def main():
     roofline = {"bound": "hbm", "kernel": dom, "achieved": d["alg_GBs"], "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(d["alg_GBs"] / HBM_PEAK_GBS, 4),
                 "traffic": counted_traffic(dom, n_views),
+                "valu_issue_frac": counted_valu_issue(dom),
                 "alg_bytes": round(stage_bytes(dom, n_views, n_out, n_src_sel, n_src_all))}
     log(f"[bench] stages: {json.dumps(stages)}")
 
