@@ -273,65 +273,72 @@ __global__ void __launch_bounds__(256) k_conv3(const GemmArgs g)
 // ---------------------------------------------------------------- 1x1 GEMM, LDS-staged
 // out[p][m] = sum_k A[m][k] B[p][k] for the transposed convolutions (rows
 // m = tap * C_out + co, scattered to the four fine pixels by the epilogue):
-// 128 rows x 128 pixels per block, 32-channel chunks of A and B staged in
-// LDS, four waves of 64 x 64 on v_mfma_f32_32x32x16_bf16.
-template <int EPI>
+// TM rows x TN pixels per block (128 x 128, or 64 x 64 on small grids),
+// 32-channel chunks of A and B staged in LDS, four waves of TM/2 x TN/2 on
+// v_mfma_f32_32x32x16_bf16.
+template <int EPI, int TM, int TN>
 __global__ void __launch_bounds__(256) k_gemm1(const GemmArgs g)
 {
-    __shared__ __attribute__((aligned(16))) uint8_t As[128 * C3_PXS];
-    __shared__ __attribute__((aligned(16))) uint8_t Bs[128 * C3_PXS];
+    constexpr int MI = TM / 64, NI = TN / 64;   // 32x32 tiles per wave in each direction
+    __shared__ __attribute__((aligned(16))) uint8_t As[TM * C3_PXS];
+    __shared__ __attribute__((aligned(16))) uint8_t Bs[TN * C3_PXS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int lc = lane & 31, lh = lane >> 5;
     const int wm = wave >> 1, wn = wave & 1;
     const int P = g.NB * g.H * g.W;
-    const int pbase = blockIdx.x * 128, mbase = blockIdx.y * 128;
-    f32x16 acc[2][2];
+    const int pbase = blockIdx.x * TN, mbase = blockIdx.y * TM;
+    f32x16 acc[MI][NI];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int n = 0; n < 2; ++n)
+        for (int n = 0; n < NI; ++n)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][n][r] = 0.f;
     for (int c0 = 0; c0 < g.K; c0 += 32) {
-        for (int e = tid; e < 512; e += 256) {
+        for (int e = tid; e < TM * 4; e += 256) {
             const int r = e >> 2, q = e & 3;
-            const int m = mbase + r, p = pbase + r;
-            uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
+            const int m = mbase + r;
+            uint4 va = make_uint4(0, 0, 0, 0);
             if (m < g.M) va = *(const uint4 *)(g.A + (int64_t)m * g.K + c0 + q * 8);
-            if (p < P) vb = *(const uint4 *)(g.Bsrc + (int64_t)p * g.b_cs + g.b_off + c0 + q * 8);
             *(uint4 *)(As + r * C3_PXS + q * 16) = va;
+        }
+        for (int e = tid; e < TN * 4; e += 256) {
+            const int r = e >> 2, q = e & 3;
+            const int p = pbase + r;
+            uint4 vb = make_uint4(0, 0, 0, 0);
+            if (p < P) vb = *(const uint4 *)(g.Bsrc + (int64_t)p * g.b_cs + g.b_off + c0 + q * 8);
             *(uint4 *)(Bs + r * C3_PXS + q * 16) = vb;
         }
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < 2; ++kk) {
             const int koff = (kk * 16 + 8 * lh) * 2;
-            bf16x8 af[2], bfr[2];
+            bf16x8 af[MI], bfr[NI];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-                af[i] = __builtin_bit_cast(bf16x8, *(const uint4 *)(As + (wm * 64 + i * 32 + lc) * C3_PXS + koff));
+            for (int i = 0; i < MI; ++i)
+                af[i] = __builtin_bit_cast(bf16x8, *(const uint4 *)(As + (wm * 32 * MI + i * 32 + lc) * C3_PXS + koff));
 #pragma unroll
-            for (int n = 0; n < 2; ++n)
-                bfr[n] = __builtin_bit_cast(bf16x8, *(const uint4 *)(Bs + (wn * 64 + n * 32 + lc) * C3_PXS + koff));
+            for (int n = 0; n < NI; ++n)
+                bfr[n] = __builtin_bit_cast(bf16x8, *(const uint4 *)(Bs + (wn * 32 * NI + n * 32 + lc) * C3_PXS + koff));
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
+            for (int i = 0; i < MI; ++i)
 #pragma unroll
-                for (int n = 0; n < 2; ++n)
+                for (int n = 0; n < NI; ++n)
                     acc[i][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[n], acc[i][n], 0, 0, 0);
         }
         __syncthreads();
     }
     const int HW = g.H * g.W;
 #pragma unroll
-    for (int n = 0; n < 2; ++n) {
-        const int p = pbase + wn * 64 + n * 32 + lc;
+    for (int n = 0; n < NI; ++n) {
+        const int p = pbase + wn * 32 * NI + n * 32 + lc;
         if (p >= P) continue;
         const int b = p / HW, rr = p - b * HW, y = rr / g.W, x = rr - y * g.W;
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < MI; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int m0 = mbase + wm * 64 + i * 32 + 8 * j + 4 * lh;
+                const int m0 = mbase + wm * 32 * MI + i * 32 + 8 * j + 4 * lh;
                 if (m0 >= g.M) continue;
                 float v0 = acc[i][n][4 * j + 0], v1 = acc[i][n][4 * j + 1];
                 float v2 = acc[i][n][4 * j + 2], v3 = acc[i][n][4 * j + 3];
@@ -1107,8 +1114,16 @@ hipError_t convT_fwd(unet_state *n, int li, const uint16_t *in, int i_cs, int NB
     g.M = 4 * l.cout;
     g.cout = l.cout;
     const int P = NB * H * W;
-    dim3 grid((P + 127) / 128, (g.M + 127) / 128);
-    hipLaunchKernelGGL(k_gemm1<EPI_CONVT_BF16>, grid, dim3(256), 0, s, g);
+    // 128 x 128 blocks where they number a thousand or more, else 64 x 64
+    // (small grids are latency-bound: more, shorter blocks)
+    const int64_t big = (int64_t)((P + 127) / 128) * ((g.M + 127) / 128);
+    if (big >= 1024) {
+        dim3 grid((P + 127) / 128, (g.M + 127) / 128);
+        hipLaunchKernelGGL((k_gemm1<EPI_CONVT_BF16, 128, 128>), grid, dim3(256), 0, s, g);
+    } else {
+        dim3 grid((P + 63) / 64, (g.M + 63) / 64);
+        hipLaunchKernelGGL((k_gemm1<EPI_CONVT_BF16, 64, 64>), grid, dim3(256), 0, s, g);
+    }
     return hipGetLastError();
 }
 
