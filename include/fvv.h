@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define FVV_ABI_VERSION 6
+#define FVV_ABI_VERSION 7
 
 /* status codes */
 enum {
@@ -171,6 +171,19 @@ int32_t fvv_depth_encode_y12(const void *depth_mm, int64_t depth_pitch, int32_t 
                              float z_near, float z_far, void *yuv, int64_t y_pitch, void *stream);
 int32_t fvv_depth_decode_y12(const void *yuv, int64_t y_pitch, int32_t width, int32_t height, float z_near,
                              float z_far, void *depth_mm, int64_t depth_pitch, void *stream);
+
+/* The same coding for n (1..FVV_MAX_CAMERAS) images of one size and one pair
+ * of clipping planes in a single launch (a capture server coding all of its
+ * cameras' depth maps).  depth_mm, depth_pitch, yuv and y_pitch are host
+ * arrays of n entries (read during the call only); entry i follows the
+ * single-image rules above.  The images must not overlap.  Same errors; on
+ * any bad entry nothing is enqueued. */
+int32_t fvv_depth_encode_y12_batch(int32_t n, const void *const *depth_mm, const int64_t *depth_pitch,
+                                   int32_t width, int32_t height, float z_near, float z_far, void *const *yuv,
+                                   const int64_t *y_pitch, void *stream);
+int32_t fvv_depth_decode_y12_batch(int32_t n, const void *const *yuv, const int64_t *y_pitch, int32_t width,
+                                   int32_t height, float z_near, float z_far, void *const *depth_mm,
+                                   const int64_t *depth_pitch, void *stream);
 
 /* Depth format of the following uploads on ctx: FVV_DEPTH_MM16 (default,
  * uint16 millimetres) or FVV_DEPTH_Y12 (the I420 image above, decoded to

@@ -108,6 +108,8 @@ def lib():
             "fvv_net_device_bytes": (U64, [P]),
             "fvv_depth_encode_y12": (I32, [P, I64, I32, I32, C.c_float, C.c_float, P, I64, P]),
             "fvv_depth_decode_y12": (I32, [P, I64, I32, I32, C.c_float, C.c_float, P, I64, P]),
+            "fvv_depth_encode_y12_batch": (I32, [I32, P, P, I32, I32, C.c_float, C.c_float, P, P, P]),
+            "fvv_depth_decode_y12_batch": (I32, [I32, P, P, I32, I32, C.c_float, C.c_float, P, P, P]),
             "fvv_set_depth_format": (I32, [P, I32, C.c_float, C.c_float]),
             "fvv_set_bg_model": (I32, [P, P, P, I32, I32, P]),
             "fvv_set_prefilter": (I32, [P, I32, I32, C.c_float, C.c_float, I32]),
@@ -132,7 +134,8 @@ EXPORTED = ("fvv_abi_version", "fvv_create", "fvv_destroy", "fvv_last_error", "f
             "fvv_net_read", "fvv_make_stack", "fvv_net_forward", "fvv_net_train_step",
             "fvv_net_read_act", "fvv_net_device_bytes", "fvv_depth_encode_y12",
             "fvv_depth_decode_y12", "fvv_set_depth_format", "fvv_set_bg_model", "fvv_set_prefilter",
-            "fvv_read_frame_depth", "fvv_tx_cameras", "fvv_server_tx_cameras")
+            "fvv_read_frame_depth", "fvv_tx_cameras", "fvv_server_tx_cameras",
+            "fvv_depth_encode_y12_batch", "fvv_depth_decode_y12_batch")
 DEPTH_MM16, DEPTH_Y12 = 0, 1
 NET_PARAMS, NET_GRADS = 0, 1
 NET_ALIGN = 8           # network inputs: multiples of 8 in both dimensions
@@ -267,6 +270,40 @@ def depth_decode_y12(yuv, width: int, height: int, z_near: float, z_far: float, 
                                             out.data_ptr(), _pitch(out, 0), _stream_handle(stream)),
                  "fvv_depth_decode_y12")
     return out
+
+
+def _y12_batch(fn, what, srcs, dsts, width, height, z_near, z_far, stream):
+    n = len(srcs)
+    if n != len(dsts):
+        raise ValueError(f"{what}: {n} sources but {len(dsts)} destinations")
+    ptr = C.c_void_p * max(n, 1)
+    pit = C.c_int64 * max(n, 1)
+    sp, spp = ptr(*[t.data_ptr() for t in srcs]), pit(*[_pitch(t, 0) for t in srcs])
+    dp, dpp = ptr(*[t.data_ptr() for t in dsts]), pit(*[_pitch(t, 0) for t in dsts])
+    _codec_check(fn(n, sp, spp, width, height, z_near, z_far, dp, dpp, _stream_handle(stream)), what)
+
+
+def depth_encode_y12_batch(depths, z_near: float, z_far: float, outs=None, stream=None):
+    """depth_encode_y12 of several equal-sized device depth maps in one
+    launch; returns the list of I420 images."""
+    import torch
+    H, W = depths[0].shape
+    if outs is None:
+        outs = [torch.empty((H * 3 // 2, W), dtype=torch.uint8, device=d.device) for d in depths]
+    _y12_batch(lib().fvv_depth_encode_y12_batch, "fvv_depth_encode_y12_batch", depths, outs, W, H,
+               z_near, z_far, stream)
+    return outs
+
+
+def depth_decode_y12_batch(yuvs, width: int, height: int, z_near: float, z_far: float, outs=None, stream=None):
+    """depth_decode_y12 of several equal-sized I420 device images in one
+    launch; returns the list of (H, W) int16 depth maps."""
+    import torch
+    if outs is None:
+        outs = [torch.empty((height, width), dtype=torch.int16, device=y.device) for y in yuvs]
+    _y12_batch(lib().fvv_depth_decode_y12_batch, "fvv_depth_decode_y12_batch", yuvs, outs, width, height,
+               z_near, z_far, stream)
+    return outs
 
 
 class Context:

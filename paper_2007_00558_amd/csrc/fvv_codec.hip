@@ -3,23 +3,27 @@
 // interleave) and the standalone decoder.  The frame-store ingest decodes
 // the same format inside its repack kernel.
 //
-// One thread per 2x2 block: a wave covers 128 columns of two rows, so every
-// plane is read and written in contiguous runs.  Memory bound (HBM): the
-// encoder moves 2 + 1.5 bytes per pixel, the decoder 1.5 + 2.
+// One thread per 2x2 block (grid.z = image of a batch of equal-sized
+// images): a wave covers 128 columns of two rows, so every plane is read and
+// written in contiguous runs.  Memory bound (HBM): the encoder moves 2 + 1.5
+// bytes per pixel, the decoder 1.5 + 2.
 #include "fvv_internal.h"
 #include "fvv_y12.h"
 
 namespace {
 
-__global__ void __launch_bounds__(256) k_y12_encode(const uint8_t *__restrict__ dep, int64_t dpitch, int bw,
-                                                      float z_near, float z_far, uint8_t *__restrict__ Y,
-                                                      int64_t ypitch, uint8_t *__restrict__ U,
-                                                      uint8_t *__restrict__ V, int64_t uvpitch)
+__global__ void __launch_bounds__(256) k_y12_encode(const fvv_y12_batch b)
 {
     const int c = blockIdx.x * 256 + threadIdx.x;
     const int r = blockIdx.y;
+    const int bw = b.W / 2;
     if (c >= bw) return;
-    const double zn = z_near, zf = z_far;
+    const uint8_t *dep = b.mm[blockIdx.z];
+    const int64_t dpitch = b.mm_pitch[blockIdx.z], ypitch = b.yuv_pitch[blockIdx.z], uvpitch = ypitch / 2;
+    uint8_t *Y = b.yuv[blockIdx.z];
+    uint8_t *U = Y + (int64_t)b.H * ypitch;
+    uint8_t *V = U + (int64_t)(b.H / 2) * uvpitch;
+    const double zn = b.z_near, zf = b.z_far;
     const uint16_t *d0 = (const uint16_t *)(dep + (int64_t)(2 * r) * dpitch) + 2 * c;
     const uint16_t *d1 = (const uint16_t *)(dep + (int64_t)(2 * r + 1) * dpitch) + 2 * c;
     const uint32_t p11 = y12_quantise(d0[0], zn, zf), p12 = y12_quantise(d0[1], zn, zf);
@@ -34,15 +38,18 @@ __global__ void __launch_bounds__(256) k_y12_encode(const uint8_t *__restrict__ 
     V[(int64_t)r * uvpitch + c] = (uint8_t)(y12_spread4(p21 >> 8) | y12_spread4(p22 >> 8) << 1);
 }
 
-__global__ void __launch_bounds__(256) k_y12_decode(const uint8_t *__restrict__ Y, int64_t ypitch,
-                                                      const uint8_t *__restrict__ U, const uint8_t *__restrict__ V,
-                                                      int64_t uvpitch, int bw, float z_near, float z_far,
-                                                      uint8_t *__restrict__ dep, int64_t dpitch)
+__global__ void __launch_bounds__(256) k_y12_decode(const fvv_y12_batch b)
 {
     const int c = blockIdx.x * 256 + threadIdx.x;
     const int r = blockIdx.y;
+    const int bw = b.W / 2;
     if (c >= bw) return;
-    const double zn = z_near, zf = z_far;
+    const int64_t ypitch = b.yuv_pitch[blockIdx.z], uvpitch = ypitch / 2, dpitch = b.mm_pitch[blockIdx.z];
+    const uint8_t *Y = b.yuv[blockIdx.z];
+    const uint8_t *U = Y + (int64_t)b.H * ypitch;
+    const uint8_t *V = U + (int64_t)(b.H / 2) * uvpitch;
+    uint8_t *dep = (uint8_t *)b.mm[blockIdx.z];
+    const double zn = b.z_near, zf = b.z_far;
     const uint8_t *y0 = Y + (int64_t)(2 * r) * ypitch + 2 * c;
     const uint8_t *y1 = y0 + ypitch;
     const uint32_t u = U[(int64_t)r * uvpitch + c], v = V[(int64_t)r * uvpitch + c];
@@ -56,24 +63,13 @@ __global__ void __launch_bounds__(256) k_y12_decode(const uint8_t *__restrict__ 
 
 }  // namespace
 
-hipError_t fvv_launch_y12_encode(const uint8_t *dep, int64_t dpitch, int W, int H, float zn, float zf, uint8_t *yuv,
-                                 int64_t ypitch, hipStream_t s)
+hipError_t fvv_launch_y12(const fvv_y12_batch &b, bool encode, hipStream_t s)
 {
-    const int bw = W / 2, bh = H / 2;
-    uint8_t *U = yuv + (int64_t)H * ypitch;
-    uint8_t *V = U + (int64_t)bh * (ypitch / 2);
-    hipLaunchKernelGGL(k_y12_encode, dim3((bw + 255) / 256, bh), dim3(256), 0, s, dep, dpitch, bw, zn, zf, yuv,
-                       ypitch, U, V, ypitch / 2);
-    return hipGetLastError();
-}
-
-hipError_t fvv_launch_y12_decode(const uint8_t *yuv, int64_t ypitch, int W, int H, float zn, float zf, uint8_t *dep,
-                                 int64_t dpitch, hipStream_t s)
-{
-    const int bw = W / 2, bh = H / 2;
-    const uint8_t *U = yuv + (int64_t)H * ypitch;
-    const uint8_t *V = U + (int64_t)bh * (ypitch / 2);
-    hipLaunchKernelGGL(k_y12_decode, dim3((bw + 255) / 256, bh), dim3(256), 0, s, yuv, ypitch, U, V, ypitch / 2, bw,
-                       zn, zf, dep, dpitch);
+    if (b.n <= 0) return hipSuccess;
+    const dim3 grid((b.W / 2 + 255) / 256, b.H / 2, b.n);
+    if (encode)
+        hipLaunchKernelGGL(k_y12_encode, grid, dim3(256), 0, s, b);
+    else
+        hipLaunchKernelGGL(k_y12_decode, grid, dim3(256), 0, s, b);
     return hipGetLastError();
 }

@@ -169,13 +169,19 @@ struct fvv_repack_batch {
     fvv_repack_cam cam[FVV_MAX_RIG];
 };
 
-// 12-bit depth coding (fvv_codec.hip): millimetres (pitch dpitch) <-> an
-// I420 image at yuv (Y rows of ypitch bytes, then U and V of H/2 rows of
-// ypitch/2 bytes).  W and H even.
-hipError_t fvv_launch_y12_encode(const uint8_t *dep, int64_t dpitch, int W, int H, float zn, float zf, uint8_t *yuv,
-                                 int64_t ypitch, hipStream_t s);
-hipError_t fvv_launch_y12_decode(const uint8_t *yuv, int64_t ypitch, int W, int H, float zn, float zf, uint8_t *dep,
-                                 int64_t dpitch, hipStream_t s);
+// 12-bit depth coding (fvv_codec.hip) of n equal-sized images in one
+// launch: millimetres (mm[i], rows of mm_pitch[i] bytes) <-> an I420 image
+// (yuv[i]: Y rows of yuv_pitch[i] bytes, then U and V of H/2 rows of
+// yuv_pitch[i]/2 bytes).  W and H even.
+struct fvv_y12_batch {
+    int32_t n, W, H;
+    float z_near, z_far;
+    const uint8_t *mm[FVV_MAX_RIG];
+    int64_t mm_pitch[FVV_MAX_RIG];
+    uint8_t *yuv[FVV_MAX_RIG];
+    int64_t yuv_pitch[FVV_MAX_RIG];
+};
+hipError_t fvv_launch_y12(const fvv_y12_batch &b, bool encode, hipStream_t s);
 
 // Host-side launchers (fvv_kernels.hip).  All return hipError_t of the launch.
 hipError_t fvv_launch_repack(const fvv_repack_batch &b, int max_w, int max_h, hipStream_t s, fvv_prof *prof);

@@ -1416,26 +1416,61 @@ int32_t check_y12_args(const void *a, const void *b, int32_t W, int32_t H, float
 
 }  // namespace
 
+namespace {
+
+int32_t y12_batch(int32_t n, const void *const *depth_mm, const int64_t *depth_pitch, int32_t W, int32_t H,
+                  float zn, float zf, void *const *yuv, const int64_t *y_pitch, bool encode, void *stream)
+{
+    if (n < 1 || n > FVV_MAX_RIG || !depth_mm || !depth_pitch || !yuv || !y_pitch)
+        return fail(nullptr, FVV_E_ARG, "need 1..%d images and their pointer and pitch arrays", FVV_MAX_RIG);
+    fvv_y12_batch b{};
+    b.n = n;
+    b.W = W;
+    b.H = H;
+    b.z_near = zn;
+    b.z_far = zf;
+    for (int i = 0; i < n; ++i) {
+        int32_t rc = check_y12_args(yuv[i], depth_mm[i], W, H, zn, zf, y_pitch[i], depth_pitch[i]);
+        if (rc) return rc;
+        b.mm[i] = (const uint8_t *)depth_mm[i];
+        b.mm_pitch[i] = depth_pitch[i];
+        b.yuv[i] = (uint8_t *)yuv[i];
+        b.yuv_pitch[i] = y_pitch[i];
+    }
+    hipError_t e = fvv_launch_y12(b, encode, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(nullptr, FVV_E_DEVICE, "coding launch: %s", hipGetErrorString(e));
+    return FVV_OK;
+}
+
+}  // namespace
+
 int32_t fvv_depth_encode_y12(const void *depth_mm, int64_t depth_pitch, int32_t width, int32_t height, float z_near,
                              float z_far, void *yuv, int64_t y_pitch, void *stream)
 {
-    int32_t rc = check_y12_args(yuv, depth_mm, width, height, z_near, z_far, y_pitch, depth_pitch);
-    if (rc) return rc;
-    hipError_t e = fvv_launch_y12_encode((const uint8_t *)depth_mm, depth_pitch, width, height, z_near, z_far,
-                                         (uint8_t *)yuv, y_pitch, (hipStream_t)stream);
-    if (e != hipSuccess) return fail(nullptr, FVV_E_DEVICE, "encode launch: %s", hipGetErrorString(e));
-    return FVV_OK;
+    return y12_batch(1, &depth_mm, &depth_pitch, width, height, z_near, z_far, &yuv, &y_pitch, true, stream);
 }
 
 int32_t fvv_depth_decode_y12(const void *yuv, int64_t y_pitch, int32_t width, int32_t height, float z_near,
                              float z_far, void *depth_mm, int64_t depth_pitch, void *stream)
 {
-    int32_t rc = check_y12_args(yuv, depth_mm, width, height, z_near, z_far, y_pitch, depth_pitch);
-    if (rc) return rc;
-    hipError_t e = fvv_launch_y12_decode((const uint8_t *)yuv, y_pitch, width, height, z_near, z_far,
-                                         (uint8_t *)depth_mm, depth_pitch, (hipStream_t)stream);
-    if (e != hipSuccess) return fail(nullptr, FVV_E_DEVICE, "decode launch: %s", hipGetErrorString(e));
-    return FVV_OK;
+    const void *mm = depth_mm;
+    void *y = const_cast<void *>(yuv);
+    return y12_batch(1, &mm, &depth_pitch, width, height, z_near, z_far, &y, &y_pitch, false, stream);
+}
+
+int32_t fvv_depth_encode_y12_batch(int32_t n, const void *const *depth_mm, const int64_t *depth_pitch, int32_t width,
+                                   int32_t height, float z_near, float z_far, void *const *yuv, const int64_t *y_pitch,
+                                   void *stream)
+{
+    return y12_batch(n, depth_mm, depth_pitch, width, height, z_near, z_far, yuv, y_pitch, true, stream);
+}
+
+int32_t fvv_depth_decode_y12_batch(int32_t n, const void *const *yuv, const int64_t *y_pitch, int32_t width,
+                                   int32_t height, float z_near, float z_far, void *const *depth_mm,
+                                   const int64_t *depth_pitch, void *stream)
+{
+    return y12_batch(n, (const void *const *)depth_mm, depth_pitch, width, height, z_near, z_far,
+                     (void *const *)yuv, y_pitch, false, stream);
 }
 
 int32_t fvv_synthesize(fvv_ctx *c, const fvv_camera *virt, const fvv_synth_params *params, void *out_rgb8,

@@ -27,7 +27,7 @@ def test_library_exports_every_declared_function():
     for name in names:
         assert hasattr(L, name), name
     assert set(names) == set(fvv.EXPORTED)
-    assert L.fvv_abi_version() == 6
+    assert L.fvv_abi_version() == 7
 
 
 def test_header_struct_layouts_match_binding():
@@ -122,6 +122,25 @@ def test_codec_argument_checks_need_no_device():
         assert L.fvv_depth_encode_y12(d, dp, W, H, zn, zf, y, yp, None) == fvv.FVV_E_ARG
         assert L.fvv_depth_decode_y12(y, yp, W, H, zn, zf, d, dp, None) == fvv.FVV_E_ARG
         assert L.fvv_last_error(None)
+
+
+def test_codec_batch_argument_checks_need_no_device():
+    """The batched coder checks its count and every entry on the host; one
+    bad entry rejects the whole batch (pointers never dereferenced)."""
+    L = fvv.lib()
+    ptr, pit = C.c_void_p * 3, C.c_int64 * 3
+    good_d, good_y = ptr(4096, 8192, 12288), ptr(16384, 20480, 24576)
+    dp, yp = pit(12, 12, 12), pit(6, 6, 6)
+    for n in (0, -1, 33):
+        assert L.fvv_depth_encode_y12_batch(n, good_d, dp, 6, 4, 0.5, 10.0, good_y, yp, None) == fvv.FVV_E_ARG
+        assert L.fvv_depth_decode_y12_batch(n, good_y, yp, 6, 4, 0.5, 10.0, good_d, dp, None) == fvv.FVV_E_ARG
+    assert L.fvv_depth_encode_y12_batch(3, None, dp, 6, 4, 0.5, 10.0, good_y, yp, None) == fvv.FVV_E_ARG
+    bad_pitch = pit(12, 12, 5)           # third luma pitch odd
+    assert L.fvv_depth_encode_y12_batch(3, good_d, dp, 6, 4, 0.5, 10.0, good_y, bad_pitch, None) == fvv.FVV_E_ARG
+    bad_ptr = ptr(4096, 8193, 12288)     # second depth map not 2-byte aligned
+    assert L.fvv_depth_encode_y12_batch(3, bad_ptr, dp, 6, 4, 0.5, 10.0, good_y, yp, None) == fvv.FVV_E_ARG
+    assert L.fvv_depth_decode_y12_batch(3, good_y, yp, 6, 4, 0.5, 10.0, bad_ptr, dp, None) == fvv.FVV_E_ARG
+    assert L.fvv_last_error(None)
 
 
 def test_tx_cameras_bit_exact_vs_oracle(oracle_lib):

@@ -77,6 +77,50 @@ def test_decode_bit_exact(fvv, oracle_lib, zn, zf, H, W):
     assert np.array_equal(got, want), np.argwhere(got != want)[:5]
 
 
+@pytest.mark.parametrize("n", [1, 3, 9])
+def test_batch_bit_exact(fvv, oracle_lib, n):
+    """Batched coding of n equal-sized maps, some of them views with padded
+    rows, against the oracle image by image; the batched decoder returns
+    what the oracle decodes."""
+    import torch
+    H, W = 66, 130
+    zn, zf = 0.5, 10.0
+    say(f"[gpu] y12 batch n={n} {W}x{H}")
+    rng = np.random.default_rng(100 + n)
+    maps = [noisy_depth(rng, H, W) for _ in range(n)]
+    devs = []
+    for i, d in enumerate(maps):
+        if i % 2:
+            big = torch.zeros((H, W + 6), dtype=torch.int16, device="cuda")
+            big[:, :W] = torch.from_numpy(d.view(np.int16)).cuda()
+            devs.append(big[:, :W])
+        else:
+            devs.append(torch.from_numpy(d.view(np.int16)).cuda())
+    outs = [torch.full((H * 3 // 2, W + 2 * (i % 3)), 7, dtype=torch.uint8, device="cuda")[:, :W]
+            for i in range(n)]
+    fvv.depth_encode_y12_batch(devs, zn, zf, outs=outs)
+    torch.cuda.synchronize()
+    for i, d in enumerate(maps):
+        Y, U, V = oracle_lib.encode_depth_y12(d, zn, zf)
+        o = outs[i]
+        p = o.stride(0)
+        flat = o.contiguous().cpu().numpy()
+        base = torch.as_strided(o, (H * 3 // 2 * p,), (1,)).cpu().numpy() if p != W else flat.reshape(-1)
+        got_y = base[:H * p].reshape(H, p)[:, :W]
+        got_u = base[H * p:H * p + (H // 2) * (p // 2)].reshape(H // 2, p // 2)[:, :W // 2]
+        got_v = base[H * p + (H // 2) * (p // 2):H * p + H * (p // 2)].reshape(H // 2, p // 2)[:, :W // 2]
+        assert np.array_equal(got_y, Y) and np.array_equal(got_u, U) and np.array_equal(got_v, V), i
+    imgs = [torch.from_numpy(rng.integers(0, 256, size=(H * 3 // 2, W), dtype=np.uint8)).cuda() for _ in range(n)]
+    back = fvv.depth_decode_y12_batch(imgs, W, H, zn, zf)
+    torch.cuda.synchronize()
+    for img, b in zip(imgs, back):
+        a = img.cpu().numpy()
+        uv = a[H:].reshape(-1)
+        want = oracle_lib.decode_depth_y12(a[:H], uv[:H * W // 4].reshape(H // 2, W // 2),
+                                           uv[H * W // 4:].reshape(H // 2, W // 2), zn, zf)
+        assert np.array_equal(b.cpu().numpy().view(np.uint16), want)
+
+
 def test_every_code_round_trips_on_device(fvv, oracle_lib):
     """All 4096 codes through the oracle's packing, the device decoder and
     the device encoder: the bit re-arrangement is lossless and the
