@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fvv_y12.h"
+
 #include <utility>
 #include <vector>
 
@@ -163,7 +165,7 @@ struct fvv_repack_cam {
 struct fvv_repack_batch {
     int32_t n;
     int32_t y12;            // depth arrives 12-bit coded (Section V-A)
-    float z_near, z_far;    // clipping planes of that coding, metres
+    y12_planes planes;      // plane terms of that coding (clipping planes in metres)
     const uint32_t *jbf;    // pre-filter weight tables (null = filter off)
     int32_t jbf_radius, jbf_min;
     fvv_repack_cam cam[FVV_MAX_RIG];
@@ -175,7 +177,7 @@ struct fvv_repack_batch {
 // yuv_pitch[i]/2 bytes).  W and H even.
 struct fvv_y12_batch {
     int32_t n, W, H;
-    float z_near, z_far;
+    y12_planes planes;      // of the clipping planes z_near, z_far
     const uint8_t *mm[FVV_MAX_RIG];
     int64_t mm_pitch[FVV_MAX_RIG];
     uint8_t *yuv[FVV_MAX_RIG];

@@ -156,8 +156,7 @@ __device__ __forceinline__ uint32_t live_mm(const fvv_repack_batch &b, const fvv
         const int64_t uvp = c.depth_pitch >> 1;
         const uint8_t *pl = c.depth + (int64_t)c.H * c.depth_pitch + ((y & 1) ? (int64_t)(c.H >> 1) * uvp : 0);
         const uint32_t uv = pl[(int64_t)(y >> 1) * uvp + (x >> 1)];
-        return y12_dequantise(y12_unfold(c.depth[(int64_t)y * c.depth_pitch + x], y12_msb(uv, x & 1)), b.z_near,
-                              b.z_far);
+        return y12_dequantise(y12_unfold(c.depth[(int64_t)y * c.depth_pitch + x], y12_msb(uv, x & 1)), b.planes);
     }
     return *(const uint16_t *)(c.depth + (int64_t)y * c.depth_pitch + (int64_t)x * 2);
 }

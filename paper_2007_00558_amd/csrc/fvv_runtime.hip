@@ -1302,8 +1302,7 @@ int32_t fvv_upload_mvd(fvv_ctx *c, const fvv_view *views, int32_t n, int32_t mem
         max_h = std::max(max_h, H);
     }
     b.y12 = y12;
-    b.z_near = c->z_near;
-    b.z_far = c->z_far;
+    if (y12) b.planes = y12_make_planes(c->z_near, c->z_far);
     if (c->jbf_on) {
         b.jbf = c->jbf;
         b.jbf_radius = c->jbf_radius;
@@ -1427,8 +1426,7 @@ int32_t y12_batch(int32_t n, const void *const *depth_mm, const int64_t *depth_p
     b.n = n;
     b.W = W;
     b.H = H;
-    b.z_near = zn;
-    b.z_far = zf;
+    b.planes = y12_make_planes(zn, zf);
     for (int i = 0; i < n; ++i) {
         int32_t rc = check_y12_args(yuv[i], depth_mm[i], W, H, zn, zf, y_pitch[i], depth_pitch[i]);
         if (rc) return rc;

@@ -19,26 +19,37 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// The two plane terms of Eq. 2, 1/z_far and 1/z_near - 1/z_far, each one
+// correctly rounded double operation; the host evaluates them once per call
+// (the same IEEE operations give the same bits there).
+struct y12_planes {
+    double inv_zf, span;
+};
+__host__ __device__ inline y12_planes y12_make_planes(float z_near, float z_far)
+{
+    const double zn = z_near, zf = z_far;
+    return {1.0 / zf, 1.0 / zn - 1.0 / zf};
+}
+
 // Eq. 2: millimetres -> code
-__device__ __forceinline__ uint32_t y12_quantise(uint32_t mm, double zn, double zf)
+__device__ __forceinline__ uint32_t y12_quantise(uint32_t mm, y12_planes p)
 {
     if (mm == 0xFFFFu) return 0u;
     if (mm == 0) return 1u;
     const double z = (double)mm / 1000.0;
-    const double a = 1.0 / z - 1.0 / zf;
-    const double b = 1.0 / zn - 1.0 / zf;
-    const double r = floor(4093.0 * a / b + 2.0 + 0.5);
+    const double a = 1.0 / z - p.inv_zf;
+    const double r = floor(4093.0 * a / p.span + 2.0 + 0.5);
     return (r >= 2.0 && r <= 4095.0) ? (uint32_t)r : 1u;
 }
 
 // inverse of Eq. 2 -> whole millimetres in 1..65535 (0xFFFF for code 0, 0 for
 // code 1)
-__device__ __forceinline__ uint32_t y12_dequantise(uint32_t code, double zn, double zf)
+__device__ __forceinline__ uint32_t y12_dequantise(uint32_t code, y12_planes p)
 {
     if (code == 0u) return 0xFFFFu;
     if (code == 1u) return 0u;
     const double t = (double)(code - 2u) / 4093.0;
-    const double inv = t * (1.0 / zn - 1.0 / zf) + 1.0 / zf;
+    const double inv = t * p.span + p.inv_zf;
     const double mm = floor(1.0 / inv * 1000.0 + 0.5);
     return mm < 1.0 ? 1u : mm > 65535.0 ? 65535u : (uint32_t)mm;
 }
