@@ -20,7 +20,8 @@
 #define FVV_HOLE_OPEN 0x80000001u   // slot of a hole whose neighbours lie beyond its tile
 #define FVV_ZCLIP 0.01f             // points and samples nearer than this are dropped
 #define FVV_TILE 32                 // output tile edge (pixels) of the fused kernel
-#define FVV_SBLK 8                  // source block edge (pixels) of the binning: one wave per block
+#define FVV_SBLK 8                  // source block edge (pixels) of the binning
+#define FVV_BIN_BPW 4               // source blocks per wave of the binning
 #define FVV_TILE_CAP_MIN 128        // minimum bin-list entries per output tile
 #define FVV_MAX_RIG 32              // cameras in a rig
 #define FVV_XCDS 8                  // XCDs of an MI355X: workgroup i runs on XCD i mod 8

@@ -105,30 +105,23 @@ __device__ __forceinline__ bool splat_point(const fvv_src_desc &s, int W, int H,
     return true;
 }
 
-// Wave-wide min / max of (y << 16 | x) pairs with DPP lane moves (packed
-// u16 min / max, both halves at once): pairs, quads, half rows and rows
-// inside each 16-lane row, then the row broadcasts carry rows 0 -> 1, 2 -> 3
-// and 1 -> 2, 3; lane 63 then holds the result for the whole wave.  Lanes a
-// move does not write keep their own value (old = v), the identity of min
-// and max.
-typedef unsigned short fvv_u16x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ fvv_u16x2 as_u16x2(uint32_t v) { return __builtin_bit_cast(fvv_u16x2, v); }
-__device__ __forceinline__ uint32_t as_u32(fvv_u16x2 v) { return __builtin_bit_cast(uint32_t, v); }
+// Wave-wide min / max of a u32 with DPP lane moves: pairs, quads, half rows
+// and rows inside each 16-lane row, then the row broadcasts carry rows
+// 0 -> 1, 2 -> 3 and 1 -> 2, 3; lane 63 then holds the result for the whole
+// wave.  Each step folds into one v_min_u32_dpp / v_max_u32_dpp: lanes a
+// move does not write keep their own value, the identity of min and max.
 template <bool MIN>
-__device__ __forceinline__ uint32_t wave_reduce_u16x2(uint32_t v)
+__device__ __forceinline__ uint32_t wave_reduce_u32(uint32_t v)
 {
-    auto op = [](uint32_t a, uint32_t b) {
-        return as_u32(MIN ? __builtin_elementwise_min(as_u16x2(a), as_u16x2(b))
-                          : __builtin_elementwise_max(as_u16x2(a), as_u16x2(b)));
-    };
-    int w = (int)v;
-    w = (int)op((uint32_t)w, (uint32_t)__builtin_amdgcn_update_dpp(w, w, 0xB1, 0xF, 0xF, false));
-    w = (int)op((uint32_t)w, (uint32_t)__builtin_amdgcn_update_dpp(w, w, 0x4E, 0xF, 0xF, false));
-    w = (int)op((uint32_t)w, (uint32_t)__builtin_amdgcn_update_dpp(w, w, 0x141, 0xF, 0xF, false));
-    w = (int)op((uint32_t)w, (uint32_t)__builtin_amdgcn_update_dpp(w, w, 0x140, 0xF, 0xF, false));
-    w = (int)op((uint32_t)w, (uint32_t)__builtin_amdgcn_update_dpp(w, w, 0x142, 0xA, 0xF, false));
-    w = (int)op((uint32_t)w, (uint32_t)__builtin_amdgcn_update_dpp(w, w, 0x143, 0xC, 0xF, false));
-    return (uint32_t)__builtin_amdgcn_readlane(w, 63);
+    constexpr int id = MIN ? (int)0xFFFFFFFF : 0;
+    auto op = [](uint32_t a, int b) { return MIN ? min(a, (uint32_t)b) : max(a, (uint32_t)b); };
+    v = op(v, __builtin_amdgcn_update_dpp(id, (int)v, 0xB1, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp(id, (int)v, 0x4E, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp(id, (int)v, 0x141, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp(id, (int)v, 0x140, 0xF, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp(id, (int)v, 0x142, 0xA, 0xF, false));
+    v = op(v, __builtin_amdgcn_update_dpp(id, (int)v, 0x143, 0xC, 0xF, false));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 __device__ __forceinline__ float wave_minf(float v)
@@ -245,42 +238,77 @@ __global__ void __launch_bounds__(256) k_bin(const fvv_view_desc *__restrict__ v
     if (blockIdx.x == 0 && blockIdx.y == 0 && blockIdx.z == 0 && threadIdx.x == 0) *vd.open_count = 0;
     const int k = blockIdx.y;
     const int lane = threadIdx.x & 63;
-    // wave-uniform block index: the block arithmetic stays on the scalar unit
-    const int blk = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (threadIdx.x >> 6));
     if (k >= fvv_nsrc(vd)) return;
     const fvv_src_desc &s = vd.src[k];
-    if (blk >= s.nblk) return;
-    const int by = blk / s.nbx, bx = blk - by * s.nbx;
-    const int i = bx * FVV_SBLK + (lane & (FVV_SBLK - 1));
-    const int j = by * FVV_SBLK + lane / FVV_SBLK;
-    // footprint bounds as (y << 16 | x) pairs; clipped to the output
-    // (< 8192), so 15 bits each; 0x7FFF in the low pair marks "none"
-    uint32_t lo = 0x7FFF7FFFu, hi = 0u;
-    if (i < s.W && j < s.H) {
-        const uint32_t zb = f2u(gptr(s.depth)[(uint32_t)(j * s.W + i)]);
+    // FVV_BIN_BPW consecutive blocks per wave (wave-uniform indices: the
+    // block arithmetic stays on the scalar unit).  A wave is bound by the
+    // latency of its depth loads and list atomics, so each wave carries
+    // independent blocks whose loads, reductions and atomics overlap.
+    const int blk0 = __builtin_amdgcn_readfirstlane((blockIdx.x * 4 + (threadIdx.x >> 6)) * FVV_BIN_BPW);
+    if (blk0 >= s.nblk) return;
+    uint32_t zb[FVV_BIN_BPW];
+    int pi[FVV_BIN_BPW], pj[FVV_BIN_BPW];
+#pragma unroll
+    for (int q = 0; q < FVV_BIN_BPW; ++q) {
+        const int by = (blk0 + q) / s.nbx, bx = blk0 + q - by * s.nbx;
+        pi[q] = bx * FVV_SBLK + (lane & (FVV_SBLK - 1));
+        pj[q] = by * FVV_SBLK + lane / FVV_SBLK;
+        zb[q] = FVV_NO_DEPTH;
+        if (blk0 + q < s.nblk && pi[q] < s.W && pj[q] < s.H) zb[q] = f2u(gptr(s.depth)[(uint32_t)(pj[q] * s.W + pi[q])]);
+    }
+    // footprint bounds, clipped to the output (< 8192); 0x7FFF as the
+    // smallest x0 marks "none"
+    int4 t[FVV_BIN_BPW];
+#pragma unroll
+    for (int q = 0; q < FVV_BIN_BPW; ++q) {
+        uint32_t x0 = 0x7FFFu, y0 = 0x7FFFu, x1 = 0u, y1 = 0u;
         Footprint f;
-        if (zb != FVV_NO_DEPTH && splat_point(s, vd.W, vd.H, vd.max_fp, i, j, u2f(zb), f)) {
-            lo = (uint32_t)f.y0 << 16 | (uint32_t)f.x0;
-            hi = (uint32_t)f.y1 << 16 | (uint32_t)f.x1;
+        if (zb[q] != FVV_NO_DEPTH && splat_point(s, vd.W, vd.H, vd.max_fp, pi[q], pj[q], u2f(zb[q]), f)) {
+            x0 = (uint32_t)f.x0;
+            y0 = (uint32_t)f.y0;
+            x1 = (uint32_t)f.x1;
+            y1 = (uint32_t)f.y1;
         }
+        const int fx0 = (int)wave_reduce_u32<true>(x0), fy0 = (int)wave_reduce_u32<true>(y0);
+        const int fx1 = (int)wave_reduce_u32<false>(x1), fy1 = (int)wave_reduce_u32<false>(y1);
+        t[q] = make_int4(1, 0, 1, 0);   // empty
+        if (fx0 != 0x7FFF) {
+            t[q].x = max(0, (fx0 + T - 1) / T - 1);
+            t[q].y = min(vd.ntx - 1, (fx1 + 1) / T);
+            t[q].z = max(0, (fy0 + T - 1) / T - 1);
+            t[q].w = min(vd.nty - 1, (fy1 + 1) / T);
+        }
+        if (lane == 0 && blk0 + q < s.nblk) vd.bbox[(int64_t)k * vd.blk_stride + blk0 + q] = t[q];
     }
-    lo = wave_reduce_u16x2<true>(lo);
-    hi = wave_reduce_u16x2<false>(hi);
-    const int x0 = (int)(lo & 0xFFFF), y0 = (int)(lo >> 16), x1 = (int)(hi & 0xFFFF), y1 = (int)(hi >> 16);
-    int4 t = make_int4(1, 0, 1, 0);   // empty
-    if (x0 != 0x7FFF) {
-        t.x = max(0, (x0 + T - 1) / T - 1);
-        t.y = min(vd.ntx - 1, (x1 + 1) / T);
-        t.z = max(0, (y0 + T - 1) / T - 1);
-        t.w = min(vd.nty - 1, (y1 + 1) / T);
-    }
-    if (lane == 0) vd.bbox[(int64_t)k * vd.blk_stride + blk] = t;
-    if (t.x > t.y) return;
-    const int nx = t.y - t.x + 1, n = nx * (t.w - t.z + 1);
-    for (int e = lane; e < n; e += 64) {
-        const int tile = (t.z + e / nx) * vd.ntx + t.x + e % nx;
-        const int pos = atomicAdd(&vd.counts[tile], 1);
-        if (pos < vd.tile_cap) vd.list[(int64_t)tile * vd.tile_cap + pos] = (k << 24) | blk;
+    auto append = [&](int tile, int blk) {
+        const int pos = __hip_atomic_fetch_add((__attribute__((address_space(1))) int32_t *)(vd.counts + tile), 1,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (pos < vd.tile_cap)
+            ((__attribute__((address_space(1))) int32_t *)vd.list)[(uint64_t)(uint32_t)tile * (uint32_t)vd.tile_cap +
+                                                                   (uint32_t)pos] = (k << 24) | blk;
+    };
+    // the usual case, every range within 8 x (64 / 8 / FVV_BIN_BPW) tiles:
+    // one atomic instruction appends all blocks of the wave, lane group q
+    // (64 / FVV_BIN_BPW lanes) taking block q's tiles
+    constexpr int GL = 64 / FVV_BIN_BPW, GY = GL / 8;
+    bool small = true;
+#pragma unroll
+    for (int q = 0; q < FVV_BIN_BPW; ++q)
+        small = small && (t[q].x > t[q].y || (t[q].y - t[q].x < 8 && t[q].w - t[q].z < GY));
+    if (small) {
+        const int g = lane / GL, ex = lane & 7, ey = (lane % GL) >> 3;
+        int4 r = t[0];
+#pragma unroll
+        for (int q = 1; q < FVV_BIN_BPW; ++q)
+            if (g == q) r = t[q];
+        if (r.x + ex <= r.y && r.z + ey <= r.w) append((r.z + ey) * vd.ntx + r.x + ex, blk0 + g);
+    } else {
+#pragma unroll
+        for (int q = 0; q < FVV_BIN_BPW; ++q) {
+            if (t[q].x > t[q].y) continue;
+            const int nx = t[q].y - t[q].x + 1, n = nx * (t[q].w - t[q].z + 1);
+            for (int e = lane; e < n; e += 64) append((t[q].z + e / nx) * vd.ntx + t[q].x + e % nx, blk0 + q);
+        }
     }
 }
 
@@ -990,7 +1018,8 @@ hipError_t fvv_launch_synthesis(const fvv_view_desc *h_views, fvv_view_desc *d_v
                        words);
     fvv_prof_end(prof, s, FVV_ST_DESC, e0);
     fvv_prof_begin(prof, s, e0);
-    hipLaunchKernelGGL(k_bin, dim3((b.max_blocks + 3) / 4, b.max_k, b.n_views), dim3(256), 0, s, d_views);
+    const int bin_waves = (b.max_blocks + FVV_BIN_BPW - 1) / FVV_BIN_BPW;
+    hipLaunchKernelGGL(k_bin, dim3((bin_waves + 3) / 4, b.max_k, b.n_views), dim3(256), 0, s, d_views);
     fvv_prof_end(prof, s, FVV_ST_BIN, e0);
     fvv_prof_begin(prof, s, e0);
     {
