@@ -19,6 +19,7 @@
 #define FVV_HOLE 0x80000000u        // slot of a hole filled inside its tile (or left black)
 #define FVV_HOLE_OPEN 0x80000001u   // slot of a hole whose neighbours lie beyond its tile
 #define FVV_ZCLIP 0.01f             // points and samples nearer than this are dropped
+#define FVV_SPL_RECOMPUTE 0xFFFFFFFFu   // splat record whose footprint does not pack (x0 = 8191 with x1 > x0)
 #define FVV_TILE 32                 // output tile edge (pixels) of the fused kernel
 #define FVV_SBLK 8                  // source block edge (pixels) of the binning
 #define FVV_BIN_BPW 4               // source blocks per wave of the binning
@@ -56,6 +57,12 @@ struct fvv_view_desc {
     int32_t *counts;        // ntx*nty tile counters (zero between calls; cleared by the tile kernel)
     int32_t *list;          // ntx*nty*tile_cap entries: source slot << 24 | source block
     int4 *bbox;             // nsrc*blk_stride tile ranges (x0, x1, y0, y1; x0 > x1 = empty)
+    // per-pixel splat records written by the binning, nsrc*blk_stride*64
+    // (slot, block, lane): x = depth bits of the projected point
+    // (FVV_NO_DEPTH = no splat), y = footprint x0 | y0 << 13 | (x1 - x0) << 26
+    // | (y1 - y0) << 29, or FVV_SPL_RECOMPUTE when an extent exceeds 7
+    unsigned long long *spl;
+    uint64_t pad16;         // keeps the descriptor a whole number of 16-byte words
     // per-tile results
     uint32_t *slot;         // W*H depth bits of covered pixels / FVV_HOLE / FVV_HOLE_OPEN
     int2 *rowsum;           // ntx*nty*FVV_TILE (first, last) covered x of each tile row

@@ -263,12 +263,20 @@ __global__ void __launch_bounds__(256) k_bin(const fvv_view_desc *__restrict__ v
     for (int q = 0; q < FVV_BIN_BPW; ++q) {
         uint32_t x0 = 0x7FFFu, y0 = 0x7FFFu, x1 = 0u, y1 = 0u;
         Footprint f;
+        uint32_t rz = FVV_NO_DEPTH, rf = 0u;   // this pixel's splat record
         if (zb[q] != FVV_NO_DEPTH && splat_point(s, vd.W, vd.H, vd.max_fp, pi[q], pj[q], u2f(zb[q]), f)) {
             x0 = (uint32_t)f.x0;
             y0 = (uint32_t)f.y0;
             x1 = (uint32_t)f.x1;
             y1 = (uint32_t)f.y1;
+            rz = (uint32_t)(f.key >> 32);
+            rf = (x1 - x0 <= 7u && y1 - y0 <= 7u) ? (x0 | y0 << 13 | (x1 - x0) << 26 | (y1 - y0) << 29)
+                                                  : FVV_SPL_RECOMPUTE;
         }
+        if (blk0 + q < s.nblk)
+            ((__attribute__((address_space(1))) unsigned long long *)
+                 vd.spl)[((uint32_t)(k * vd.blk_stride + blk0 + q) << 6) + (uint32_t)lane] =
+                (unsigned long long)rf << 32 | rz;
         const int fx0 = (int)wave_reduce_u32<true>(x0), fy0 = (int)wave_reduce_u32<true>(y0);
         const int fx1 = (int)wave_reduce_u32<false>(x1), fy1 = (int)wave_reduce_u32<false>(y1);
         t[q] = make_int4(1, 0, 1, 0);   // empty
@@ -568,25 +576,32 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
     // and its block arithmetic runs on the scalar unit
     const int lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int si = lane & (FVV_SBLK - 1), sj = lane / FVV_SBLK;
-    // depth bits of this lane's pixel of block `ent` (FVV_NO_DEPTH outside)
-    auto block_depth = [&](int ent) -> uint32_t {
+    // this lane's splat record of block `ent`, written by the binning
+    // (the same projection and footprint as splat_point, computed once per
+    // block instead of once per tile that lists it)
+    auto block_rec = [&](int ent) -> unsigned long long {
         ent = __builtin_amdgcn_readfirstlane(ent);   // uniform (see above)
-        const fvv_src_desc &s = vd.src[ent >> 24];
-        const int blk = ent & 0xFFFFFF;
-        const int by = blk / s.nbx, bx = blk - by * s.nbx;
-        const int i = bx * FVV_SBLK + si, j = by * FVV_SBLK + sj;
-        if (i >= s.W || j >= s.H) return FVV_NO_DEPTH;
-        return f2u(gptr(s.depth)[(uint32_t)(j * s.W + i)]);
+        return gptr(vd.spl)[((uint32_t)((ent >> 24) * vd.blk_stride + (ent & 0xFFFFFF)) << 6) + (uint32_t)lane];
     };
-    auto splat_entry = [&](int ent, uint32_t zb) {
+    auto splat_entry = [&](int ent, unsigned long long rec) {
         ent = __builtin_amdgcn_readfirstlane(ent);   // uniform; the pipeline's copies lose that
-        if (zb == FVV_NO_DEPTH) return;
+        const uint32_t rz = (uint32_t)rec, rf = (uint32_t)(rec >> 32);
+        if (rz == FVV_NO_DEPTH) return;
         const fvv_src_desc &s = vd.src[ent >> 24];
         const int blk = ent & 0xFFFFFF;
         const int by = blk / s.nbx, bx = blk - by * s.nbx;
         const int i = bx * FVV_SBLK + si, j = by * FVV_SBLK + sj;
         Footprint f;
-        if (!splat_point(s, W, H, vd.max_fp, i, j, u2f(zb), f)) return;
+        if (rf != FVV_SPL_RECOMPUTE) {
+            f.x0 = (int)(rf & 0x1FFFu);
+            f.y0 = (int)((rf >> 13) & 0x1FFFu);
+            f.x1 = f.x0 + (int)((rf >> 26) & 7u);
+            f.y1 = f.y0 + (int)(rf >> 29);
+            f.key = ((unsigned long long)rz << 32) | ((unsigned long long)(uint32_t)s.cam << 27) |
+                    (unsigned long long)(uint32_t)(j * s.W + i);
+        } else if (!splat_point(s, W, H, vd.max_fp, i, j, gptr(s.depth)[(uint32_t)(j * s.W + i)], f)) {
+            return;
+        }
         const int xa = max(f.x0, WX0), xb = min(f.x1, WX0 + WN - 1);
         const int ya = max(f.y0, WY0), yb = min(f.y1, WY0 + WN - 1);
         unsigned long long *zl = (LAYERED && (ent >> 24) >= vd.K) ? zk + WN * WN : zk;
@@ -595,9 +610,9 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
     };
     if (!scan_all) {
         // The wave's entries are e = wave + TNW q.  They are read 64 at a time
-        // (one per lane) and the depths of the next two entries are in
-        // flight while the current one is splatted, so the dependent loads
-        // of consecutive entries overlap instead of queueing.
+        // (one per lane) and the splat records of the next two entries are
+        // in flight while the current one is splatted, so the dependent
+        // loads of consecutive entries overlap instead of queueing.
         const int32_t *lst = vd.list + (int64_t)tile * vd.tile_cap;
         const int nq = n_entries > wave ? (n_entries - wave + TNW - 1) / TNW : 0;
         int base = 0;
@@ -610,23 +625,23 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
             return __builtin_amdgcn_readlane(ents, q - base);
         };
         int e0 = 0, e1 = 0;
-        uint32_t z0 = FVV_NO_DEPTH, z1 = FVV_NO_DEPTH;
+        unsigned long long z0 = 0, z1 = 0;
         if (nq > 0) {
             e0 = entry(0);
-            z0 = block_depth(e0);
+            z0 = block_rec(e0);
         }
         if (nq > 1) {
             e1 = entry(1);
-            z1 = block_depth(e1);
+            z1 = block_rec(e1);
         }
         for (int q = 0; q < nq; ++q) {
             const int ec = e0;
-            const uint32_t zc = z0;
+            const unsigned long long zc = z0;
             e0 = e1;
             z0 = z1;
             if (q + 2 < nq) {
                 e1 = entry(q + 2);
-                z1 = block_depth(e1);
+                z1 = block_rec(e1);
             }
             splat_entry(ec, zc);
         }
@@ -638,7 +653,7 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
             const int4 r = vd.bbox[e];
             if (!(r.x <= tx && tx <= r.y && r.z <= ty && ty <= r.w)) continue;
             const int ent = (k << 24) | blk;
-            splat_entry(ent, block_depth(ent));
+            splat_entry(ent, block_rec(ent));
         }
     }
     __syncthreads();

@@ -382,6 +382,7 @@ size_t view_ws_bytes(int W, int H, const ViewLayout &L, bool host_out, bool lear
     b += align256(nt * FVV_TILE * sizeof(int2)) * 2;               // rowsum, colsum
     b += align256(nt * (size_t)L.tile_cap * 4);                    // bin lists
     b += align256((size_t)L.nsrc * L.blk_stride * sizeof(int4));   // block tile ranges
+    b += align256((size_t)L.nsrc * L.blk_stride * 64 * 8);         // splat records
     if (host_out) b += align256(px * 3);
     if (learned) b += align256(stack_bytes(W, H));
     return b;
@@ -748,6 +749,7 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
         d.colsum = (int2 *)carve(nt * FVV_TILE * sizeof(int2));
         d.list = (int32_t *)carve(nt * (size_t)L.tile_cap * 4);
         d.bbox = (int4 *)carve((size_t)L.nsrc * L.blk_stride * sizeof(int4));
+        d.spl = (unsigned long long *)carve((size_t)L.nsrc * L.blk_stride * 64 * 8);
         d.open_list = Wk.open_list;
         d.open_count = Wk.open_count;
         d.counts = cnt;

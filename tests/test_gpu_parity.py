@@ -111,6 +111,18 @@ def test_parameter_variants_parity(fvv, ctx, oracle_lib, max_fp, tau):
         compare(oracle_lib, w, v, out, taps, max_fp=max_fp, tau=tau)
 
 
+@pytest.mark.parametrize("max_fp", [6.0, 16.0, 64.0])
+def test_large_footprint_parity(fvv, ctx, oracle_lib, max_fp):
+    """Views magnified about 12x: splat footprints up to max_fp pixels, so
+    with 16 and 64 many exceed the 7-pixel extent that a packed per-pixel
+    splat record holds and the tile kernel recomputes those points; source
+    blocks then also cover more tiles than one binning atomic serves."""
+    w = sg.config_small(5, n_cams=3, w=24, h=16, out_w=300, out_h=200, n_virtual=2)
+    for v in w.virtual:
+        out, taps = gpu_run(fvv, ctx, w, v, max_fp=max_fp)
+        compare(oracle_lib, w, v, out, taps, max_fp=max_fp)
+
+
 def test_fill_none_parity(fvv, ctx, oracle_lib):
     w = sg.config_small(2)
     out, taps = gpu_run(fvv, ctx, w, w.virtual[0], fill=1)

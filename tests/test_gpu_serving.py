@@ -108,8 +108,9 @@ def test_admission_by_memory_and_oversized_request(fvv):
     ctx.upload_mvd(w.frames)
     small = [sg.arc_camera(a, 2.2, 64, 40) for a in (-5.0, 0.0, 5.0, 8.0)]
     alone = [ctx.synthesize(v) for v in small]
-    # a step holds one 64x40 view but not two, and never a 640x400 one
-    srv = fvv.Server(ctx, max_slots=16, step_bytes=30_000)
+    # a step holds one 64x40 view (about 166 KB of workspace with its
+    # per-pixel splat records) but not two, and never a 640x400 one
+    srv = fvv.Server(ctx, max_slots=16, step_bytes=250_000)
     outs = [torch.zeros((v.height, v.width, 3), dtype=torch.uint8, device="cuda") for v in small]
     big = sg.arc_camera(0.0, 2.2, 640, 400)
     big_out = torch.zeros((400, 640, 3), dtype=torch.uint8, device="cuda")
