@@ -74,15 +74,19 @@ def log(*a):
 # one batch: n_out output pixels per view, n_src_sel source pixels of the
 # selected cameras per view, n_views views per batch.
 #   repack     per source pixel: RGB8 + u16 in, 8-byte texel + f32 depth out
-#   tile       per selected source pixel: f32 depth (splat) + 8-byte texel
+#   bin        per selected source pixel: f32 depth in, 8-byte splat record
+#              (projected depth + packed footprint) out
+#   tile       per selected source pixel: 8-byte splat record + 8-byte texel
 #              (backward fetch) read once; per output pixel: RGB8 + 4-byte
 #              slot written (the z-buffer lives in LDS)
-#   desc, bin, fill_open: descriptors, per-block ranges, open holes only
+#   desc, fill_open: descriptors, open holes only
 def stage_bytes(stage: str, n_views: int, n_out: int, n_src_sel: float, n_src_all: int) -> float:
     if stage == "repack":
         return n_src_all * (3 + 2 + 8 + 4)
+    if stage == "bin":
+        return n_views * n_src_sel * (4.0 + 8.0)
     if stage == "tile":
-        return n_views * (n_src_sel * (4.0 + 8.0) + n_out * (3.0 + 4.0))
+        return n_views * (n_src_sel * (8.0 + 8.0) + n_out * (3.0 + 4.0))
     return float("nan")
 
 
