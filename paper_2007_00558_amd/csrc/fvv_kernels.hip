@@ -605,8 +605,20 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
         const int xa = max(f.x0, WX0), xb = min(f.x1, WX0 + WN - 1);
         const int ya = max(f.y0, WY0), yb = min(f.y1, WY0 + WN - 1);
         unsigned long long *zl = (LAYERED && (ent >> 24) >= vd.K) ? zk + WN * WN : zk;
-        for (int y = ya; y <= yb; ++y)
-            for (int x = xa; x <= xb; ++x) atomicMin(&zl[(y - WY0) * WN + (x - WX0)], f.key);
+        if (xa > xb || ya > yb) return;
+        // the first 2 x 2 pixels of the footprint (all of it at the usual
+        // magnifications) as predicated atomics, the rest in a loop
+        unsigned long long *z0 = zl + (ya - WY0) * WN + (xa - WX0);
+        const bool wx = xa < xb, wy = ya < yb;
+        atomicMin(z0, f.key);
+        if (wx) atomicMin(z0 + 1, f.key);
+        if (wy) atomicMin(z0 + WN, f.key);
+        if (wx && wy) atomicMin(z0 + WN + 1, f.key);
+        if (xb - xa > 1 || yb - ya > 1) {
+            for (int y = ya; y <= yb; ++y)
+                for (int x = xa; x <= xb; ++x)
+                    if (x - xa > 1 || y - ya > 1) atomicMin(&zl[(y - WY0) * WN + (x - WX0)], f.key);
+        }
     };
     if (!scan_all) {
         // The wave's entries are e = wave + TNW q.  They are read 64 at a time
