@@ -123,6 +123,18 @@ def test_large_footprint_parity(fvv, ctx, oracle_lib, max_fp):
         compare(oracle_lib, w, v, out, taps, max_fp=max_fp)
 
 
+@pytest.mark.parametrize("ow,oh,max_fp", [(8192, 40, 4.0), (48, 8192, 4.0), (8192, 40, 64.0)])
+def test_maximum_output_size_parity(fvv, ctx, oracle_lib, ow, oh, max_fp):
+    """Output edges at the maximum (8192): covered pixels reach x = 8189,
+    next to the largest coordinate a packed splat record holds; 256 tiles
+    per row or column; with max_fp 64 the footprints take the recompute
+    path."""
+    w = sg.config_small(9, n_cams=3, w=96, h=64, out_w=ow, out_h=oh, n_virtual=1)
+    v = w.virtual[0]
+    out, taps = gpu_run(fvv, ctx, w, v, max_fp=max_fp)
+    compare(oracle_lib, w, v, out, taps, max_fp=max_fp)
+
+
 def test_fill_none_parity(fvv, ctx, oracle_lib):
     w = sg.config_small(2)
     out, taps = gpu_run(fvv, ctx, w, w.virtual[0], fill=1)
