@@ -363,7 +363,7 @@ __device__ __forceinline__ unsigned long long filter_key(unsigned long long c, u
         bool near = false;
 #pragma unroll
         for (int e = 0; e < 8; ++e)
-            if (v[e] != FVV_KEY_EMPTY && fabsf(__fsub_rn(u2f((uint32_t)(v[e] >> 32)), z0)) <= lim) near = true;
+            if (fabsf(__fsub_rn(u2f((uint32_t)(v[e] >> 32)), z0)) <= lim) near = true;   // empty: NaN, false
         if (near) return c;
     }
     return lower_median8(v, n);
@@ -416,8 +416,9 @@ __device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int k0, int
         float c0 = 0.f, c1 = 0.f, c2 = 0.f, csum = 0.f;
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
-            const bool ok = okc[n & 1] && okr[n >> 1] && tx[n].y != FVV_NO_DEPTH &&
-                            fabsf(__fsub_rn(u2f(tx[n].y), q2)) <= lim;
+            // a texel without depth holds FVV_NO_DEPTH, a NaN as float32,
+            // so the consistency test alone rejects it (NaN <= lim is false)
+            const bool ok = okc[n & 1] && okr[n >> 1] && fabsf(__fsub_rn(u2f(tx[n].y), q2)) <= lim;
             const float w = ok ? wt[n] : 0.0f;
             c0 = fmaf(w, (float)(tx[n].x & 0xFF), c0);
             c1 = fmaf(w, (float)((tx[n].x >> 8) & 0xFF), c1);
