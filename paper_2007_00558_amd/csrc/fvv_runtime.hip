@@ -1192,6 +1192,9 @@ int32_t fvv_set_bg_model(fvv_ctx *c, const void *const *depth_mm, const int64_t 
                                          hipMemcpyDeviceToDevice, s));
     }
     HIPCHECK(c, hipStreamSynchronize(s));
+    // models are set rarely: finish every copy (a pageable host copy may
+    // still be in flight on return) before any stream's ingest reads them
+    HIPCHECK(c, hipDeviceSynchronize());
     return FVV_OK;
 }
 
