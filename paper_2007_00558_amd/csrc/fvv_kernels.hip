@@ -908,7 +908,11 @@ __global__ void __launch_bounds__(TNT) k_tile_stack_layered(const fvv_view_desc 
 // Holes whose nearest covered neighbour in some direction lies outside their
 // tile: scan the tile, then walk the per-tile summaries of the row or column.
 // A fixed grid walks the batch's list of tiles with open holes.
-__global__ void __launch_bounds__(256) k_fill_open(const fvv_view_desc *__restrict__ views)
+// threads per open tile: one per row and direction of the walks and scans
+// (4 x 32), every thread busy in those serial phases; twice the tiles in
+// flight of a 256-thread block
+constexpr int FILL_NT = 4 * T;
+__global__ void __launch_bounds__(FILL_NT) k_fill_open(const fvv_view_desc *__restrict__ views)
 {
     // The tile's slots are staged in LDS (the scans inside the tile then
     // cost no dependent global loads), and the walks beyond the tile, which
@@ -1068,8 +1072,8 @@ hipError_t fvv_launch_synthesis(const fvv_view_desc *h_views, fvv_view_desc *d_v
     fvv_prof_end(prof, s, FVV_ST_TILE, e0);
     if (b.fill_bg) {
         fvv_prof_begin(prof, s, e0);
-        const int grid = std::max(1, std::min(b.total_tiles, 2048));
-        hipLaunchKernelGGL(k_fill_open, dim3(grid), dim3(256), 0, s, d_views);
+        const int grid = std::max(1, std::min(b.total_tiles, 2048 * 256 / FILL_NT));
+        hipLaunchKernelGGL(k_fill_open, dim3(grid), dim3(FILL_NT), 0, s, d_views);
         fvv_prof_end(prof, s, FVV_ST_FILL_OPEN, e0);
     }
     return hipGetLastError();
