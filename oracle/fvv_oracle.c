@@ -306,9 +306,9 @@ static inline void ref_project(const float M[9], const float m[3], float i, floa
  * Footprint (reading): each point covers the pixel centres x with
  * u - mx/2 <= x < u + mx/2 (same for rows), where mx = clamp((sx z)/p2, 1,
  * max_fp) is the point's own magnification; a fronto-parallel surface is then
- * tiled without cracks or overlaps.  In float32: r = 1/p2, u = p0 r,
- * v = p1 r, mx = (sx z) r (one division per point).  Points with p2 <= 0.01 m
- * or non-finite image coordinates are dropped.
+ * tiled without cracks or overlaps.  In float32 with correctly rounded
+ * division: u = p0/p2, v = p1/p2, mx = (sx z)/p2, my = (sy z)/p2.  Points
+ * with p2 <= 0.01 m or non-finite image coordinates are dropped.
  * Z must hold W*H keys; it is initialised here. */
 typedef struct {
     const uint16_t *depth;    /* source depth, millimetres */
@@ -334,12 +334,11 @@ void fvv_ref_splat(const ref_src *src, int32_t K, int32_t W, int32_t H,
                 float q[3];
                 ref_project(p->A, p->a, (float)i, (float)j, z, q);
                 if (!(q[2] > zclip)) continue;
-                float r = 1.0f / q[2];
-                float u = q[0] * r;
-                float v = q[1] * r;
+                float u = q[0] / q[2];
+                float v = q[1] / q[2];
                 if (!isfinite(u) || !isfinite(v)) continue;
-                float mx = (p->sx * z) * r;
-                float my = (p->sy * z) * r;
+                float mx = (p->sx * z) / q[2];
+                float my = (p->sy * z) / q[2];
                 mx = fminf(fmaxf(mx, 1.0f), max_fp);
                 my = fminf(fmaxf(my, 1.0f), max_fp);
                 float hx = 0.5f * mx, hy = 0.5f * my;
@@ -427,8 +426,8 @@ void fvv_ref_filter(const uint64_t *Z, int32_t W, int32_t H, float tau, uint64_t
  * For each output pixel with a valid filtered key at depth zf, and each
  * selected camera in selection order:
  *   q = B [x,y,1] zf + b (float32, as O4), require q2 > 0.01,
- *   r = 1/q2, u = q0 r, v = q1 r (float32), require -0.5 <= u <= W_c - 0.5
- *   and the same for v
+ *   u = q0/q2, v = q1/q2 (float32), require -0.5 <= u <= W_c - 0.5 and the
+ *   same for v
  *   (the sample lies on the source image's pixel area),
  *   i0 = floor(u), j0 = floor(v), fu = u - i0, fv = v - j0;
  *   taps (i0,j0) (i0+1,j0) (i0,j0+1) (i0+1,j0+1) with bilinear weights
@@ -470,9 +469,8 @@ void fvv_ref_blend(const uint64_t *Zf, int32_t W, int32_t H, const ref_tex *tex,
                 float q[3];
                 ref_project(t->pair->B, t->pair->b, (float)x, (float)y, zf, q);
                 if (!(q[2] > zclip)) continue;
-                float r = 1.0f / q[2];
-                float u = q[0] * r;
-                float v = q[1] * r;
+                float u = q[0] / q[2];
+                float v = q[1] / q[2];
                 if (!(u >= -0.5f && u <= (float)t->W - 0.5f)) continue;
                 if (!(v >= -0.5f && v <= (float)t->H - 0.5f)) continue;
                 float fi0 = floorf(u), fj0 = floorf(v);
@@ -537,9 +535,8 @@ void fvv_ref_stack(const uint64_t *Zf, int32_t W, int32_t H, const ref_tex *tex,
                 float q[3];
                 ref_project(t->pair->B, t->pair->b, (float)x, (float)y, zf, q);
                 if (!(q[2] > zclip)) continue;
-                float r = 1.0f / q[2];
-                float u = q[0] * r;
-                float v = q[1] * r;
+                float u = q[0] / q[2];
+                float v = q[1] / q[2];
                 if (!(u >= -0.5f && u <= (float)t->W - 0.5f)) continue;
                 if (!(v >= -0.5f && v <= (float)t->H - 0.5f)) continue;
                 float fi0 = floorf(u), fj0 = floorf(v);

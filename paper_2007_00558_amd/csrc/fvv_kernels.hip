@@ -66,6 +66,19 @@ __device__ __forceinline__ void project(const float *M, const float *m, float i,
     p2 = __fadd_rn(__fmul_rn(__fadd_rn(__fadd_rn(__fmul_rn(M[6], i), __fmul_rn(M[7], j)), M[8]), z), m[2]);
 }
 
+// a / b rounded to nearest from y = RN(1/b), bit for bit what a correctly
+// rounded division gives (Markstein's theorem: q = RN(a y) is within one ulp
+// of a/b, the remainder a - b q is exact in one fused multiply-add, and
+// RN(q + rem y) = RN(a/b); no overflow or underflow for the magnitudes of
+// image coordinates and depths).  Lets one division serve every quotient by
+// the same projected depth at three instructions per extra quotient.
+__device__ __forceinline__ float div_by(float a, float b, float y)
+{
+    const float q = __fmul_rn(a, y);
+    const float rem = __fmaf_rn(-b, q, a);
+    return __fmaf_rn(rem, y, q);
+}
+
 struct Footprint {
     int x0, x1, y0, y1;
     unsigned long long key;
@@ -74,7 +87,8 @@ struct Footprint {
 // Forward warp of source pixel (i, j) at depth z: the output pixel centres
 // x with u - mx/2 <= x < u + mx/2 (rows likewise), mx = clamp(sx z / p2, 1,
 // max_fp), clipped to the output image; key = depth bits | camera | pixel.
-// In float32 with one division: r = 1/p2, u = p0 r, v = p1 r, mx = (sx z) r.
+// In float32 with correctly rounded quotients u = p0/p2, v = p1/p2,
+// mx = (sx z)/p2, my = (sy z)/p2 (one division, see div_by).
 __device__ __forceinline__ bool splat_point(const fvv_src_desc &s, int W, int H, float max_fp, int i, int j,
                                             float z, Footprint &f)
 {
@@ -82,10 +96,10 @@ __device__ __forceinline__ bool splat_point(const fvv_src_desc &s, int W, int H,
     project(s.A, s.a, (float)i, (float)j, z, q0, q1, q2);
     if (!(q2 > FVV_ZCLIP)) return false;
     const float r = __fdiv_rn(1.0f, q2);   // one correctly rounded division per point
-    const float u = __fmul_rn(q0, r), v = __fmul_rn(q1, r);
+    const float u = div_by(q0, q2, r), v = div_by(q1, q2, r);
     if (!isfinite(u) || !isfinite(v)) return false;
-    float mx = __fmul_rn(__fmul_rn(s.sx, z), r);
-    float my = __fmul_rn(__fmul_rn(s.sy, z), r);
+    float mx = div_by(__fmul_rn(s.sx, z), q2, r);
+    float my = div_by(__fmul_rn(s.sy, z), q2, r);
     mx = fminf(fmaxf(mx, 1.0f), max_fp);
     my = fminf(fmaxf(my, 1.0f), max_fp);
     const float hx = __fmul_rn(0.5f, mx), hy = __fmul_rn(0.5f, my);
@@ -387,7 +401,7 @@ __device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int k0, int
         project(s.B, s.b, (float)x, (float)y, zf, q0, q1, q2);
         if (!(q2 > FVV_ZCLIP)) continue;
         const float r = __fdiv_rn(1.0f, q2);
-        const float u = __fmul_rn(q0, r), v = __fmul_rn(q1, r);
+        const float u = div_by(q0, q2, r), v = div_by(q1, q2, r);
         if (!(u >= -0.5f && u <= __fsub_rn((float)s.W, 0.5f))) continue;
         if (!(v >= -0.5f && v <= __fsub_rn((float)s.H, 0.5f))) continue;
         const float fi0 = floorf(u), fj0 = floorf(v);
@@ -460,7 +474,7 @@ __device__ __forceinline__ void stack_pixel(const fvv_view_desc &vd, int x, int 
             project(s.B, s.b, (float)x, (float)y, zf, q0, q1, q2);
             if (!(q2 > FVV_ZCLIP)) continue;
             const float r = __fdiv_rn(1.0f, q2);
-            const float u = __fmul_rn(q0, r), v = __fmul_rn(q1, r);
+            const float u = div_by(q0, q2, r), v = div_by(q1, q2, r);
             if (!(u >= -0.5f && u <= __fsub_rn((float)s.W, 0.5f))) continue;
             if (!(v >= -0.5f && v <= __fsub_rn((float)s.H, 0.5f))) continue;
             const float fi0 = floorf(u), fj0 = floorf(v);

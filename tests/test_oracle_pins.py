@@ -233,10 +233,9 @@ def _brute_force_splat(o, rig, depths, virt, sel, max_fp):
                 p0, p1, p2 = _f32_project(P["A"], P["a"], i, j, z)
                 if not p2 > np.float32(0.01):
                     continue
-                r = np.float32(np.float32(1.0) / p2)
-                u, v = np.float32(p0 * r), np.float32(p1 * r)
-                mx = min(max(np.float32(np.float32(P["sx"] * z) * r), np.float32(1)), np.float32(max_fp))
-                my = min(max(np.float32(np.float32(P["sy"] * z) * r), np.float32(1)), np.float32(max_fp))
+                u, v = np.float32(p0 / p2), np.float32(p1 / p2)
+                mx = min(max(np.float32(np.float32(P["sx"] * z) / p2), np.float32(1)), np.float32(max_fp))
+                my = min(max(np.float32(np.float32(P["sy"] * z) / p2), np.float32(1)), np.float32(max_fp))
                 lo_u, hi_u = np.float32(u - np.float32(0.5) * mx), np.float32(u + np.float32(0.5) * mx)
                 lo_v, hi_v = np.float32(v - np.float32(0.5) * my), np.float32(v + np.float32(0.5) * my)
                 key = (f32bits(p2) << 32) | (c << 27) | (j * d.shape[1] + i)
@@ -395,14 +394,47 @@ def test_identity_view_reproduces_source(oracle_lib):
     assert kept.sum() > 0.6 * valid.size
     assert np.array_equal(r["blend_rgb"][kept], w.frames[0].rgb[kept])
     assert np.all(r["hole"][kept] == 0)
-    # no point lands where the source had no depth: such pixels are holes
-    # unless the filter closed a crack there (the backward fetch can then
-    # still find a depth-consistent tap with a tiny bilinear weight)
-    unfilled = ~valid & (r["z"] == r["zf"])
+    # no point lands where the source had no depth, and every such pixel is
+    # a hole, also where the filter closed a crack: the backward fetch of the
+    # identity view lands exactly on the pixel itself, whose tap has no depth
     assert np.all(r["z"][~valid] == EMPTY)
-    assert np.all(r["hole"][unfilled] == 1)
+    assert (r["zf"][~valid] != EMPTY).any(), "the case should include filter-closed cracks"
+    assert np.all(r["hole"][~valid] == 1)
     # with fill disabled the whole valid region is an exact copy
     assert np.array_equal(r["rgb"][kept], w.frames[0].rgb[kept])
+
+
+@pytest.mark.parametrize("cam", [0, 1, 2])
+def test_identity_view_reproduces_source_noisy_rig(oracle_lib, cam):
+    """Virtual camera = one camera of the three-camera rig with depth noise
+    and 5 % isolated invalid pixels: that camera alone is selected (weight
+    1), and every pixel with depth is an exact copy of the source unless the
+    speckle filter replaced its key.  The rig's float32 rotations are
+    orthonormal only to rounding, so the pair matrices of a camera with
+    itself differ from the identity by ~1e-5 px: a pixel without depth whose
+    crack the filter closed lands next to its own centre, and neighbour taps
+    with bilinear weights of that size can carry it.  Such a pixel then
+    holds a mix of its neighbours' source colours (each channel within their
+    range); every other pixel without depth is a hole."""
+    o = oracle_lib
+    w = sg.config2(0)
+    src = w.frames[cam]
+    r = o.synthesize(w.rig, w.frames, w.rig[cam], k_nearest=3, taps=True, fill_mode=1)
+    valid = src.depth_mm > 0
+    assert np.all(r["z"][~valid] == EMPTY)
+    assert np.all(o.key_cam(r["z"][valid]) == cam)
+    closed = ~valid & (r["zf"] != EMPTY)
+    assert closed.sum() > 1000
+    assert np.all(r["hole"][~valid & ~closed] == 1)
+    H, W = valid.shape
+    for y, x in zip(*np.nonzero(~valid & (r["hole"] == 0))):
+        nb = np.array([src.rgb[yy, xx] for yy in range(max(0, y - 1), min(H, y + 2))
+                       for xx in range(max(0, x - 1), min(W, x + 2)) if (yy, xx) != (y, x) and valid[yy, xx]])
+        assert len(nb) and np.all(nb.min(0) <= r["rgb"][y, x]) and np.all(r["rgb"][y, x] <= nb.max(0)), (y, x)
+    kept = valid & (r["z"] == r["zf"])
+    assert kept.sum() > 0.9 * valid.sum()
+    assert np.all(r["hole"][kept] == 0)
+    assert np.array_equal(r["rgb"][kept], src.rgb[kept])
 
 
 def test_integer_shift_view_is_shifted_source(oracle_lib):

@@ -1,7 +1,8 @@
 """Pins for the learned-path oracle (CPU): its convolutions against direct
 loops, its bfloat16 rounding against hand-worked bit patterns, its
-hand-written backward against central finite differences, and training
-against an overfit check."""
+hand-written backward against central finite differences, Adam against
+hand-worked moments over three steps, and training against an overfit
+check."""
 import numpy as np
 import pytest
 import torch
@@ -137,3 +138,46 @@ def test_adam_overfits_one_sample():
         losses.append(loss)
         unet.adam_step(master, g, m, v, step, lr=1e-2)
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_adam_three_steps_hand_worked():
+    """Three Adam steps with gradients 1, -2, 0.5 (and their negatives, and a
+    zero gradient) on a scalar weight and bias, beta = (0.9, 0.999), against
+    moments worked out by hand:
+      m1 = 0.1            v1 = 0.001             1 - b1^t = 0.1    1 - b2^t = 0.001
+      m2 = 0.09 - 0.2     v2 = 0.000999 + 0.004            0.19             0.001999
+         = -0.11             = 0.004999
+      m3 = -0.099 + 0.05  v3 = 0.004994001 + 0.00025       0.271            0.002997001
+         = -0.049            = 0.005244001
+    A wrong decay, a missing square, a bias correction off by one step or a
+    swapped beta changes the weights by far more than float32 rounding."""
+    lr, eps = 1e-3, 1e-8
+    gs = [1.0, -2.0, 0.5]
+    hand_m = [0.1, -0.11, -0.049]
+    hand_v = [0.001, 0.004999, 0.005244001]
+    hand_c1 = [0.1, 0.19, 0.271]
+    hand_c2 = [0.001, 0.001999, 0.002997001]
+    master = {"L": [np.float32([[0.25]]), np.float32([-0.5, 0.75])]}
+    m = {"L": [np.zeros((1, 1)), np.zeros(2)]}
+    v = {"L": [np.zeros((1, 1)), np.zeros(2)]}
+    w_want = np.float32(0.25)
+    b_want = np.float32([-0.5, 0.75])
+    for t in range(3):
+        grads = {"L": [np.float32([[gs[t]]]), np.float32([-gs[t], 0.0])]}
+        unet.adam_step(master, grads, m, v, t + 1, lr=lr)
+        assert m["L"][0][0, 0] == pytest.approx(hand_m[t], rel=1e-12)
+        assert v["L"][0][0, 0] == pytest.approx(hand_v[t], rel=1e-12)
+        assert m["L"][1][0] == pytest.approx(-hand_m[t], rel=1e-12)
+        assert v["L"][1][0] == pytest.approx(hand_v[t], rel=1e-12)
+        assert m["L"][1][1] == 0.0 and v["L"][1][1] == 0.0
+        step = lr * (hand_m[t] / hand_c1[t]) / (np.sqrt(hand_v[t] / hand_c2[t]) + eps)
+        w_want = np.float32(np.float64(w_want) - step)
+        b_want = np.float32(np.float64(b_want) - np.array([-step, 0.0]))
+        assert master["L"][0].dtype == np.float32
+        assert master["L"][0][0, 0] == w_want
+        assert np.array_equal(master["L"][1], b_want)
+    # net displacement: lr (1 - 0.5789474 / 1.5813761 - 0.1808118 / 1.3227810)
+    # (step 1 moves by lr: its corrected moments are g and g^2); the bias with
+    # zero gradient stays put (three float32 roundings near 0.25: 1e-7)
+    assert float(np.float32(0.25) - w_want) == pytest.approx(lr * 0.4972058, abs=1e-7)
+    assert b_want[1] == np.float32(0.75)
