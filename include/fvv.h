@@ -39,7 +39,7 @@
 extern "C" {
 #endif
 
-#define FVV_ABI_VERSION 7
+#define FVV_ABI_VERSION 8
 
 /* status codes */
 enum {
@@ -253,6 +253,30 @@ int32_t fvv_synthesize(fvv_ctx *ctx, const fvv_camera *virt, const fvv_synth_par
 int32_t fvv_synthesize_batch(fvv_ctx *ctx, const fvv_camera *virts, int32_t n_views,
                              const fvv_synth_params *params, void *const *outs,
                              const int64_t *pitches, int32_t mem_kind, void *stream);
+
+/* For callers that cannot allocate memory -- code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation: render one virtual
+ * camera exactly as fvv_synthesize does (device output, byte-identical
+ * result) with every temporary buffer of the synthesis (view descriptor,
+ * tile counters, bin lists and block ranges, splat records, slot plane,
+ * tile summaries, open-hole list) in one fixed device array of
+ * FVV_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs on
+ * until the process ends.  The call allocates no device and no pinned host
+ * memory (no hipMalloc, hipFree or hipHostMalloc).
+ *  - out_dev: device memory, height rows of width*3 bytes, pitch out_pitch;
+ *    enqueued on stream, returns at once.
+ *  - Paths FVV_PATH_PLAIN and FVV_PATH_LAYERED; FVV_PATH_LEARNED needs the
+ *    network's activation memory: FVV_E_UNSUPPORTED.
+ *  - FVV_E_NOMEM, with nothing enqueued, when the view's buffers exceed the
+ *    array (a 1920x1080 view drawing on three 1280x720 cameras needs about
+ *    34 MB, layered about 58 MB); other errors as fvv_synthesize.
+ *  - Every call on one GPU, from any context and on any stream, shares that
+ *    GPU's array and leaves its contents there; each call clears what must
+ *    start at zero itself.  Calls whose device work overlaps race: the
+ *    caller orders them (for example by issuing them on one stream). */
+#define FVV_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int32_t fvv_synthesize_noalloc(fvv_ctx *ctx, const fvv_camera *virt, const fvv_synth_params *params,
+                               void *out_dev, int64_t out_pitch, void *stream);
 
 /* Host-only helpers (no device, no context): the camera selection and the
  * float32 pair matrices the kernels use, exposed for inspection and tests.

@@ -82,6 +82,7 @@ def lib():
             "fvv_upload_mvd": (I32, [P, C.POINTER(View), I32, I32, P, C.POINTER(U64)]),
             "fvv_synthesize": (I32, [P, C.POINTER(Camera), C.POINTER(SynthParams), P, I64, I32, P]),
             "fvv_synthesize_batch": (I32, [P, C.POINTER(Camera), I32, C.POINTER(SynthParams), P, P, I32, P]),
+            "fvv_synthesize_noalloc": (I32, [P, C.POINTER(Camera), C.POINTER(SynthParams), P, I64, P]),
             "fvv_select_cameras": (I32, [C.POINTER(Camera), P, I32, C.POINTER(Camera), I32, P, P]),
             "fvv_pair_matrices": (I32, [C.POINTER(Camera), C.POINTER(Camera), P]),
             "fvv_set_debug": (I32, [P, I32]),
@@ -135,7 +136,7 @@ EXPORTED = ("fvv_abi_version", "fvv_create", "fvv_destroy", "fvv_last_error", "f
             "fvv_net_read_act", "fvv_net_device_bytes", "fvv_depth_encode_y12",
             "fvv_depth_decode_y12", "fvv_set_depth_format", "fvv_set_bg_model", "fvv_set_prefilter",
             "fvv_read_frame_depth", "fvv_tx_cameras", "fvv_server_tx_cameras",
-            "fvv_depth_encode_y12_batch", "fvv_depth_decode_y12_batch")
+            "fvv_depth_encode_y12_batch", "fvv_depth_decode_y12_batch", "fvv_synthesize_noalloc")
 DEPTH_MM16, DEPTH_Y12 = 0, 1
 NET_PARAMS, NET_GRADS = 0, 1
 NET_ALIGN = 8           # network inputs: multiples of 8 in both dimensions
@@ -428,6 +429,15 @@ class Context:
         else:
             self._check(self._L.fvv_synthesize(self._h, C.byref(vc), C.byref(p), out.data_ptr(),
                                                out.stride(0), MEM_DEVICE, _stream_handle(stream)))
+        return out
+
+    def synthesize_noalloc(self, virt, out, p: Optional[SynthParams] = None, stream=None):
+        """Render one view into the torch CUDA tensor ``out`` (H, W, 3) uint8
+        without any allocation (the library's fixed per-GPU scratch)."""
+        p = p or params()
+        vc = camera(virt)
+        self._check(self._L.fvv_synthesize_noalloc(self._h, C.byref(vc), C.byref(p), out.data_ptr(),
+                                                   out.stride(0), _stream_handle(stream)))
         return out
 
     def synthesize_batch(self, virts: Sequence, outs: Sequence, p: Optional[SynthParams] = None,

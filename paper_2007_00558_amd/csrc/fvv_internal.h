@@ -199,3 +199,8 @@ hipError_t fvv_launch_repack(const fvv_repack_batch &b, int max_w, int max_h, hi
 // descriptors, copied into d_views by the first kernel of the sequence.
 hipError_t fvv_launch_synthesis(const fvv_view_desc *h_views, fvv_view_desc *d_views,
                                 const fvv_batch_dims &dims, hipStream_t s, fvv_prof *prof);
+// One view whose descriptor travels in the kernel arguments: stored to
+// d_view, and the view's dims.total_tiles counters at `counts` cleared, by
+// the first kernel of the sequence (no host staging, nothing allocated).
+hipError_t fvv_launch_synthesis_one(const fvv_view_desc &view, fvv_view_desc *d_view, int32_t *counts,
+                                    const fvv_batch_dims &dims, hipStream_t s, fvv_prof *prof);

@@ -237,6 +237,16 @@ __global__ void __launch_bounds__(256) k_desc(const uint4 *__restrict__ src, uin
     if (e < n) dst[e] = src[e];
 }
 
+// One view's descriptor passed by value (calls that allocate nothing have
+// no pinned host copy to read): thread 0 stores it, and every thread clears
+// the view's tile counters, which the binning expects at zero.
+__global__ void __launch_bounds__(256) k_desc_one(const fvv_view_desc d, fvv_view_desc *__restrict__ dst,
+                                                  int32_t *__restrict__ counts, int n_counts)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *dst = d;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n_counts; e += gridDim.x * blockDim.x) counts[e] = 0;
+}
+
 // ---------------------------------------------------------------- binning
 // One wave per (view, camera slot, 8x8 source block), one lane per pixel:
 // the exact output bounds of the block's footprints (each pixel projected as
@@ -1052,17 +1062,12 @@ hipError_t fvv_launch_repack(const fvv_repack_batch &b, int max_w, int max_h, hi
     return hipGetLastError();
 }
 
-hipError_t fvv_launch_synthesis(const fvv_view_desc *h_views, fvv_view_desc *d_views, const fvv_batch_dims &b,
-                                hipStream_t s, fvv_prof *prof)
+namespace {
+
+// binning, tile kernel and open-hole pass over the descriptors at d_views
+hipError_t launch_stages(fvv_view_desc *d_views, const fvv_batch_dims &b, hipStream_t s, fvv_prof *prof)
 {
-    if (b.n_views <= 0) return hipSuccess;
-    static_assert(sizeof(fvv_view_desc) % 16 == 0, "descriptors are copied in 16-byte words");
-    const int words = (int)(b.n_views * sizeof(fvv_view_desc) / 16);
     hipEvent_t e0;
-    fvv_prof_begin(prof, s, e0);
-    hipLaunchKernelGGL(k_desc, dim3((words + 255) / 256), dim3(256), 0, s, (const uint4 *)h_views, (uint4 *)d_views,
-                       words);
-    fvv_prof_end(prof, s, FVV_ST_DESC, e0);
     fvv_prof_begin(prof, s, e0);
     const int bin_waves = (b.max_blocks + FVV_BIN_BPW - 1) / FVV_BIN_BPW;
     hipLaunchKernelGGL(k_bin, dim3((bin_waves + 3) / 4, b.max_k, b.n_views), dim3(256), 0, s, d_views);
@@ -1091,4 +1096,34 @@ hipError_t fvv_launch_synthesis(const fvv_view_desc *h_views, fvv_view_desc *d_v
         fvv_prof_end(prof, s, FVV_ST_FILL_OPEN, e0);
     }
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t fvv_launch_synthesis(const fvv_view_desc *h_views, fvv_view_desc *d_views, const fvv_batch_dims &b,
+                                hipStream_t s, fvv_prof *prof)
+{
+    if (b.n_views <= 0) return hipSuccess;
+    static_assert(sizeof(fvv_view_desc) % 16 == 0, "descriptors are copied in 16-byte words");
+    const int words = (int)(b.n_views * sizeof(fvv_view_desc) / 16);
+    hipEvent_t e0;
+    fvv_prof_begin(prof, s, e0);
+    hipLaunchKernelGGL(k_desc, dim3((words + 255) / 256), dim3(256), 0, s, (const uint4 *)h_views, (uint4 *)d_views,
+                       words);
+    fvv_prof_end(prof, s, FVV_ST_DESC, e0);
+    const hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : launch_stages(d_views, b, s, prof);
+}
+
+hipError_t fvv_launch_synthesis_one(const fvv_view_desc &view, fvv_view_desc *d_view, int32_t *counts,
+                                    const fvv_batch_dims &b, hipStream_t s, fvv_prof *prof)
+{
+    if (b.n_views != 1) return hipErrorInvalidValue;
+    hipEvent_t e0;
+    fvv_prof_begin(prof, s, e0);
+    const int grid = std::max(1, std::min(64, (b.total_tiles + 255) / 256));
+    hipLaunchKernelGGL(k_desc_one, dim3(grid), dim3(256), 0, s, view, d_view, counts, b.total_tiles);
+    fvv_prof_end(prof, s, FVV_ST_DESC, e0);
+    const hipError_t e = hipGetLastError();
+    return e != hipSuccess ? e : launch_stages(d_view, b, s, prof);
 }

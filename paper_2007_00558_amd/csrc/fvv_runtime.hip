@@ -163,6 +163,7 @@ struct fvv_ctx {
     size_t staging_bytes = 0;
     hipEvent_t staging_free = nullptr;
     Workspace user;          // workspace of direct synthesis calls
+    uint8_t *scratch = nullptr;   // device address of this device's no-allocation scratch
     // debug taps of view 0 of the last direct synthesis
     bool debug = false;
     unsigned long long *dbg_z = nullptr;
@@ -302,16 +303,21 @@ int select_k(const fvv_camera *rig, const int32_t *present, int n, const fvv_cam
 {
     double Cv[3];
     centre(v, Cv);
-    std::vector<std::pair<double, int>> d;
-    for (int c = 0; c < n; ++c) {
+    // insertion by distance into a fixed array (stable: a camera goes after
+    // every earlier one at the same distance; no heap use)
+    std::pair<double, int> d[FVV_MAX_CAMERAS];
+    int nd = 0;
+    for (int c = 0; c < n && c < FVV_MAX_CAMERAS; ++c) {
         if (present && !present[c]) continue;
         double Cc[3];
         centre(rig[c], Cc);
         const double dx = Cc[0] - Cv[0], dy = Cc[1] - Cv[1], dz = Cc[2] - Cv[2];
-        d.emplace_back(std::sqrt(dx * dx + dy * dy + dz * dz), c);
+        const double dist = std::sqrt(dx * dx + dy * dy + dz * dz);
+        int e = nd++;
+        for (; e > 0 && dist < d[e - 1].first; --e) d[e] = d[e - 1];
+        d[e] = {dist, c};
     }
-    std::stable_sort(d.begin(), d.end(), [](const auto &a, const auto &b) { return a.first < b.first; });
-    int K = std::min<int>({(int)d.size(), k, FVV_MAX_K});
+    int K = std::min<int>({nd, k, FVV_MAX_K});
     if (K > 0 && d[0].first < 1e-6) {
         idx[0] = d[0].second;
         w[0] = 1.0;
@@ -633,6 +639,88 @@ struct LearnedIO {
     bool scratch_out = false;          // RGB goes to workspace scratch (stack-only calls)
 };
 
+// Camera selection and tile layout of one view: the frame slot it reads
+// (si), its selected cameras and weights, tile grid and list sizes (L).
+int32_t plan_view(fvv_ctx *c, const fvv_camera &vc, const fvv_synth_params &P, int &si, ViewLayout &L)
+{
+    int32_t rc;
+    if ((rc = find_slot(c, P.frame_version, si))) return rc;
+    const FrameSlot &fs = c->slots[si];
+    const bool layered = P.path == FVV_PATH_LAYERED;
+    if (layered && !fs.layered)
+        return fail(c, FVV_E_STATE, "layered synthesis needs a frame set uploaded with background models");
+    const int n = (int)c->rig.size();
+    int32_t pres[FVV_MAX_CAMERAS];
+    for (int q = 0; q < n; ++q) pres[q] = ((P.exclude_mask >> q) & 1u) ? 0 : fs.present[q];
+    const int K = select_k(c->rig.data(), pres, n, vc, P.k_nearest, L.idx, L.w);
+    if (K < 1) return fail(c, FVV_E_STATE, "no camera present in the frame set");
+    int nb[FVV_MAX_K];
+    for (int k = 0; k < K; ++k) nb[k] = nblocks(c->rig[L.idx[k]]);
+    layout_sizes(L, vc.width, vc.height, nb, K, layered);
+    return FVV_OK;
+}
+
+// Descriptor of view `view` of a launch: geometry, parameters, the selected
+// cameras with their weights and float32 pair matrices, and the view's
+// buffers (slot plane, tile summaries, bin lists, block ranges, splat
+// records) carved from `cur`, tile counters from `cnt` (both advanced).
+// Output, stack, taps and the batch's open-tile list are the caller's.
+void fill_desc(fvv_ctx *c, fvv_view_desc &d, const fvv_camera &vc, const ViewLayout &L, const FrameSlot &fs,
+               const fvv_synth_params &P, int view, uint8_t *&cur, int32_t *&cnt)
+{
+    std::memset(&d, 0, sizeof d);
+    d.W = vc.width;
+    d.H = vc.height;
+    d.K = L.K;
+    d.fill_mode = P.fill_mode;
+    d.tau = P.tau_rel;
+    d.max_fp = P.max_footprint;
+    d.ntx = L.ntx;
+    d.nty = L.nty;
+    d.blk_stride = L.blk_stride;
+    d.tile_cap = L.tile_cap;
+    d.view = view;
+    d.layered = L.nsrc > L.K;
+    const size_t px = (size_t)vc.width * vc.height;
+    const size_t nt = (size_t)L.n_tiles;
+    auto carve = [&](size_t bytes) {
+        uint8_t *p = cur;
+        cur += align256(bytes);
+        return p;
+    };
+    d.slot = (uint32_t *)carve(px * 4);
+    d.rowsum = (int2 *)carve(nt * FVV_TILE * sizeof(int2));
+    d.colsum = (int2 *)carve(nt * FVV_TILE * sizeof(int2));
+    d.list = (int32_t *)carve(nt * (size_t)L.tile_cap * 4);
+    d.bbox = (int4 *)carve((size_t)L.nsrc * L.blk_stride * sizeof(int4));
+    d.spl = (unsigned long long *)carve((size_t)L.nsrc * L.blk_stride * 64 * 8);
+    d.counts = cnt;
+    cnt += nt;
+    for (int k = 0; k < L.K; ++k) {
+        const fvv_camera &sc = c->rig[L.idx[k]];
+        fvv_src_desc &sd = d.src[k];
+        sd.texel = fs.texel[L.idx[k]];
+        sd.depth = fs.depth[L.idx[k]];
+        sd.W = sc.width;
+        sd.H = sc.height;
+        sd.cam = L.idx[k];
+        sd.nbx = (sc.width + FVV_SBLK - 1) / FVV_SBLK;
+        sd.nblk = nblocks(sc);
+        sd.wgt = (float)L.w[k];
+        pair_dir(sc, vc, sd.A, sd.a);
+        pair_dir(vc, sc, sd.B, sd.b);
+        sd.sx = (float)((double)vc.fx / (double)sc.fx);
+        sd.sy = (float)((double)vc.fy / (double)sc.fy);
+        if (d.layered) {
+            // the camera's background layer: same geometry and weight
+            fvv_src_desc &bd = d.src[L.K + k];
+            bd = sd;
+            bd.texel = fs.bg_texel[L.idx[k]];
+            bd.depth = fs.bg_depth[L.idx[k]];
+        }
+    }
+}
+
 // One batched launch sequence over n views (caller holds c->mu, has checked
 // the arguments and resolved each view's parameters).  grow: the workspace
 // may be enlarged; otherwise the caller guarantees it fits.  Views on the
@@ -650,28 +738,16 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
         learned[v] = lio.stack_out || (have_net && Ps[v].path == FVV_PATH_LEARNED);
         if (learned[v] && !lio.stack_out) net_px = std::max(net_px, stack_w(virts[v].width) * stack_w(virts[v].height));
     }
-    const int n = (int)c->rig.size();
     std::vector<ViewLayout> lay(n_views);
     std::vector<int> slot_of(n_views);
     size_t total = 0, total_tiles = 0;
     fvv_batch_dims dims{n_views, 0, 0, 0, 0, 0, false, false, false};
     int32_t rc;
     for (int v = 0; v < n_views; ++v) {
-        if ((rc = find_slot(c, Ps[v].frame_version, slot_of[v]))) return rc;
-        const FrameSlot &fs = c->slots[slot_of[v]];
-        const bool layered = Ps[v].path == FVV_PATH_LAYERED;
-        if (layered && !fs.layered)
-            return fail(c, FVV_E_STATE, "layered synthesis needs a frame set uploaded with background models");
-        ViewLayout &L = lay[v];
+        if ((rc = plan_view(c, virts[v], Ps[v], slot_of[v], lay[v]))) return rc;
+        const ViewLayout &L = lay[v];
         const fvv_camera &vc = virts[v];
-        std::vector<int32_t> pres(fs.present);
-        for (int q = 0; q < n; ++q)
-            if (q < 32 && ((Ps[v].exclude_mask >> q) & 1u)) pres[q] = 0;
-        const int K = select_k(c->rig.data(), pres.data(), n, vc, Ps[v].k_nearest, L.idx, L.w);
-        if (K < 1) return fail(c, FVV_E_STATE, "no camera present in the frame set");
-        int nb[FVV_MAX_K];
-        for (int k = 0; k < K; ++k) nb[k] = nblocks(c->rig[L.idx[k]]);
-        layout_sizes(L, vc.width, vc.height, nb, K, layered);
+        const bool layered = Ps[v].path == FVV_PATH_LAYERED;
         total += view_ws_bytes(vc.width, vc.height, L, host_out || lio.scratch_out, learned[v] && !lio.stack_out);
         total_tiles += (size_t)L.n_tiles;
         dims.total_tiles += L.n_tiles;
@@ -721,39 +797,16 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
     std::vector<uint8_t *> host_stage(n_views, nullptr);
     for (int v = 0; v < n_views; ++v) {
         const fvv_camera &vc = virts[v];
-        const ViewLayout &L = lay[v];
-        const FrameSlot &fs = c->slots[slot_of[v]];
         fvv_view_desc &d = hd[v];
-        std::memset(&d, 0, sizeof d);
-        d.W = vc.width;
-        d.H = vc.height;
-        d.K = L.K;
-        d.fill_mode = Ps[v].fill_mode;
-        d.tau = Ps[v].tau_rel;
-        d.max_fp = Ps[v].max_footprint;
-        d.ntx = L.ntx;
-        d.nty = L.nty;
-        d.blk_stride = L.blk_stride;
-        d.tile_cap = L.tile_cap;
-        d.view = v;
-        d.layered = L.nsrc > L.K;
+        fill_desc(c, d, vc, lay[v], c->slots[slot_of[v]], Ps[v], v, cur, cnt);
+        d.open_list = Wk.open_list;
+        d.open_count = Wk.open_count;
         const size_t px = (size_t)vc.width * vc.height;
-        const size_t nt = (size_t)L.n_tiles;
         auto carve = [&](size_t bytes) {
             uint8_t *p = cur;
             cur += align256(bytes);
             return p;
         };
-        d.slot = (uint32_t *)carve(px * 4);
-        d.rowsum = (int2 *)carve(nt * FVV_TILE * sizeof(int2));
-        d.colsum = (int2 *)carve(nt * FVV_TILE * sizeof(int2));
-        d.list = (int32_t *)carve(nt * (size_t)L.tile_cap * 4);
-        d.bbox = (int4 *)carve((size_t)L.nsrc * L.blk_stride * sizeof(int4));
-        d.spl = (unsigned long long *)carve((size_t)L.nsrc * L.blk_stride * 64 * 8);
-        d.open_list = Wk.open_list;
-        d.open_count = Wk.open_count;
-        d.counts = cnt;
-        cnt += nt;
         if (host_out || lio.scratch_out) {
             host_stage[v] = carve(px * 3);
             d.out = host_stage[v];
@@ -777,29 +830,6 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
             }
             d.dbg_rgba = c->dbg_rgba;
             d.dbg_depth = c->dbg_depth;
-        }
-        for (int k = 0; k < L.K; ++k) {
-            const fvv_camera &sc = c->rig[L.idx[k]];
-            fvv_src_desc &sd = d.src[k];
-            sd.texel = fs.texel[L.idx[k]];
-            sd.depth = fs.depth[L.idx[k]];
-            sd.W = sc.width;
-            sd.H = sc.height;
-            sd.cam = L.idx[k];
-            sd.nbx = (sc.width + FVV_SBLK - 1) / FVV_SBLK;
-            sd.nblk = nblocks(sc);
-            sd.wgt = (float)L.w[k];
-            pair_dir(sc, vc, sd.A, sd.a);
-            pair_dir(vc, sc, sd.B, sd.b);
-            sd.sx = (float)((double)vc.fx / (double)sc.fx);
-            sd.sy = (float)((double)vc.fy / (double)sc.fy);
-            if (d.layered) {
-                // the camera's background layer: same geometry and weight
-                fvv_src_desc &bd = d.src[L.K + k];
-                bd = sd;
-                bd.texel = fs.bg_texel[L.idx[k]];
-                bd.depth = fs.bg_depth[L.idx[k]];
-            }
         }
     }
     bool waited[2] = {false, false};
@@ -1083,6 +1113,40 @@ void server_teardown(fvv_ctx *c)
 
 }  // namespace
 
+// Device scratch of fvv_synthesize_noalloc, one instance per GPU (each device
+// holds its own copy at its own address until the process ends).  In host
+// code `scratch` names a host-side stand-in: host code uses only the device
+// address hipGetSymbolAddress returns, kept per device below.
+static __device__ __align__(256) uint8_t scratch[FVV_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, looked up once per device with
+// that device current (at context creation).
+int32_t scratch_address(int dev, uint8_t **out)
+{
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        DeviceGuard g(dev);
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(nullptr, FVV_E_DEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                        hipGetErrorString(e));
+        }
+        g_scratch[dev] = (uint8_t *)p;
+    }
+    *out = g_scratch[dev];
+    return FVV_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int32_t fvv_abi_version(void) { return FVV_ABI_VERSION; }
@@ -1096,9 +1160,14 @@ int32_t fvv_create(int32_t hip_device, uint64_t mem_budget_bytes, fvv_ctx **out)
     if (e != hipSuccess) return fail(nullptr, FVV_E_DEVICE, "hipGetDeviceCount: %s", hipGetErrorString(e));
     if (hip_device < 0 || hip_device >= n)
         return fail(nullptr, FVV_E_ARG, "device %d outside 0..%d", hip_device, n - 1);
+    if (hip_device >= kMaxDevices) return fail(nullptr, FVV_E_UNSUPPORTED, "device %d beyond %d", hip_device, kMaxDevices);
+    uint8_t *scr = nullptr;
+    const int32_t rc = scratch_address(hip_device, &scr);
+    if (rc) return rc;
     fvv_ctx *c = new (std::nothrow) fvv_ctx();
     if (!c) return fail(nullptr, FVV_E_NOMEM, "out of host memory");
     c->device = hip_device;
+    c->scratch = scr;
     c->budget = mem_budget_bytes;
     *out = c;
     return FVV_OK;
@@ -1488,6 +1557,54 @@ int32_t fvv_synthesize_batch(fvv_ctx *c, const fvv_camera *virts, int32_t n_view
                              void *const *outs, const int64_t *pitches, int32_t mem_kind, void *stream)
 {
     return synthesize_impl(c, virts, n_views, params, outs, pitches, mem_kind, stream);
+}
+
+int32_t fvv_synthesize_noalloc(fvv_ctx *c, const fvv_camera *virt, const fvv_synth_params *params, void *out_dev,
+                               int64_t out_pitch, void *stream)
+{
+    if (!c) return FVV_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (!virt || !out_dev) return fail(c, FVV_E_ARG, "null argument");
+    if (c->rig.empty()) return fail(c, FVV_E_STATE, "no rig set");
+    fvv_synth_params P;
+    int32_t rc = resolve_params(c, params, P);
+    if (rc) return rc;
+    if (P.path == FVV_PATH_LEARNED)
+        return fail(c, FVV_E_UNSUPPORTED, "the learned path needs network activation memory: use fvv_synthesize");
+    if ((rc = check_camera(c, *virt, false, "virtual camera"))) return rc;
+    if (out_pitch < (int64_t)virt->width * 3) return fail(c, FVV_E_ARG, "out_pitch too small");
+    int si;
+    ViewLayout L;
+    if ((rc = plan_view(c, *virt, P, si, L))) return rc;
+    // scratch layout: open-tile count | descriptor | tile counters |
+    // open-tile list | the view's buffers (as a workspace carves them)
+    const size_t nt = (size_t)L.n_tiles;
+    const size_t off_desc = 256;
+    const size_t off_counts = off_desc + align256(sizeof(fvv_view_desc));
+    const size_t off_open = off_counts + align256(nt * 4);
+    const size_t off_view = off_open + align256(nt * sizeof(int2));
+    const size_t need = off_view + view_ws_bytes(virt->width, virt->height, L, false);
+    if (need > FVV_NOALLOC_SCRATCH_BYTES)
+        return fail(c, FVV_E_NOMEM, "the view needs %zu bytes of scratch, more than the %llu bytes of the "
+                    "no-allocation entry point", need, (unsigned long long)FVV_NOALLOC_SCRATCH_BYTES);
+    DeviceGuard g(c->device);
+    uint8_t *const base = c->scratch;
+    fvv_view_desc d;
+    uint8_t *cur = base + off_view;
+    int32_t *cnt = (int32_t *)(base + off_counts);
+    fill_desc(c, d, *virt, L, c->slots[si], P, 0, cur, cnt);
+    d.open_count = (int32_t *)base;
+    d.open_list = (int2 *)(base + off_open);
+    d.out = (uint8_t *)out_dev;
+    d.out_pitch = out_pitch;
+    const fvv_batch_dims dims{1, L.nsrc, L.blk_stride, L.ntx, L.nty, L.n_tiles, P.fill_mode == FVV_FILL_BG, false,
+                              P.path == FVV_PATH_LAYERED};
+    const hipStream_t s = (hipStream_t)stream;
+    HIPCHECK(c, hipStreamWaitEvent(s, c->slots[si].ready, 0));
+    const hipError_t le = fvv_launch_synthesis_one(d, (fvv_view_desc *)(base + off_desc),
+                                                   (int32_t *)(base + off_counts), dims, s, nullptr);
+    if (le != hipSuccess) return fail(c, FVV_E_DEVICE, "synthesis launch failed: %s", hipGetErrorString(le));
+    return note_reader(c, c->slots[si], s);
 }
 
 int32_t fvv_select_cameras(const fvv_camera *rig, const int32_t *present, int32_t n, const fvv_camera *virt,
