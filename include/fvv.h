@@ -29,6 +29,13 @@
  *    (synthesis).
  *  - A context is used by one host thread at a time, except fvv_submit and
  *    fvv_poll, which any thread may call while the server runs.
+ *  - The direct device calls of a context (fvv_synthesize,
+ *    fvv_synthesize_batch, fvv_make_stack, fvv_net_forward,
+ *    fvv_net_train_step) share its workspace, network activations and debug
+ *    taps.  A call on a stream other than the previous direct call's first
+ *    waits, on the device, for that call's work, so calls may alternate
+ *    streams freely; their results are those of the calls run one at a
+ *    time.  The server's steps use workspaces of their own.
  */
 #ifndef FVV_H
 #define FVV_H
@@ -304,9 +311,11 @@ int32_t fvv_tx_cameras(const fvv_camera *rig, int32_t n, const fvv_camera *views
                        int32_t n_tx, uint32_t *mask);
 
 /* Debug taps for stage-by-stage checking.  fvv_set_debug(ctx, 1) makes the
- * next synthesis keep, for its first view, the raw and filtered z-buffers and
- * the blend result before hole filling; fvv_debug_read copies one of them to
- * host memory (bytes must equal the tap's size):
+ * following direct syntheses keep, for one view of each call (view 0, or
+ * the index set with fvv_set_debug_view; a call with fewer views keeps
+ * none), the raw and filtered z-buffers, the blend result before hole
+ * filling and the bin-list load of every tile; fvv_debug_read copies one of
+ * them to host memory (bytes must equal the tap's size):
  *   FVV_TAP_Z_RAW, FVV_TAP_Z_FILT: uint64 key per output pixel,
  *     key = float32 depth bits << 32 | camera << 27 | source pixel index,
  *     0xFFFFFFFFFFFFFFFF = empty;
@@ -314,10 +323,16 @@ int32_t fvv_tx_cameras(const fvv_camera *rig, int32_t n, const fvv_camera *views
  *   FVV_TAP_DEPTH: float32 depth per pixel (0 for holes);
  *   FVV_TAP_BG_Z_RAW, FVV_TAP_BG_Z_FILT (layered synthesis only): the
  *     background layer's key maps; the first two taps then hold the
- *     foreground layer's, BLEND and DEPTH the composite. */
+ *     foreground layer's, BLEND and DEPTH the composite;
+ *   FVV_TAP_TILES: two int32 per 32x32 output tile (row-major over the
+ *     tile grid): the source-block entries the binning appended to the
+ *     tile's list and the list's capacity; a tile with more entries than
+ *     capacity tested every source block's tile range instead.
+ * fvv_set_debug_view: the index of the tapped view (>= 0; FVV_E_ARG). */
 enum { FVV_TAP_Z_RAW = 0, FVV_TAP_Z_FILT = 1, FVV_TAP_BLEND = 2, FVV_TAP_DEPTH = 3, FVV_TAP_BG_Z_RAW = 4,
-       FVV_TAP_BG_Z_FILT = 5 };
+       FVV_TAP_BG_Z_FILT = 5, FVV_TAP_TILES = 6 };
 int32_t fvv_set_debug(fvv_ctx *ctx, int32_t enable);
+int32_t fvv_set_debug_view(fvv_ctx *ctx, int32_t view);
 int32_t fvv_debug_read(fvv_ctx *ctx, int32_t tap, void *host_out, int64_t bytes);
 
 /* Stage timing (tracing).  With profiling on, every kernel the context
@@ -408,6 +423,7 @@ int32_t fvv_server_stats(fvv_ctx *ctx, uint64_t *out6);
  *   step with learning rate lr.  *loss_out (host, may be NULL) receives the
  *   loss, which synchronises the stream.  The weight gradient is reduced in
  *   a fixed order (no float atomics): a step is bit-reproducible.
+ *   FVV_E_STATE while the server runs (its steps read the weights).
  * fvv_net_read_act: host copy of one layer's output of the last forward,
  *   bfloat16 NHWC (bytes must be pixels at that layer's resolution x C_out x 2).
  * fvv_net_device_bytes: device memory held by the network and its

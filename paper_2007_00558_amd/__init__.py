@@ -22,7 +22,7 @@ FVV_OK, FVV_E_ARG, FVV_E_STATE, FVV_E_NOMEM, FVV_E_DEVICE, FVV_E_AGAIN, FVV_E_UN
 MEM_HOST, MEM_DEVICE = 0, 1
 FILL_BG, FILL_NONE = 0, 1
 PATH_PLAIN, PATH_LEARNED, PATH_LAYERED = 0, 1, 2
-TAP_Z_RAW, TAP_Z_FILT, TAP_BLEND, TAP_DEPTH, TAP_BG_Z_RAW, TAP_BG_Z_FILT = 0, 1, 2, 3, 4, 5
+TAP_Z_RAW, TAP_Z_FILT, TAP_BLEND, TAP_DEPTH, TAP_BG_Z_RAW, TAP_BG_Z_FILT, TAP_TILES = 0, 1, 2, 3, 4, 5, 6
 BG_MM = 0xFFFF          # background signal in millimetre depth maps
 KEY_EMPTY = np.uint64(0xFFFFFFFFFFFFFFFF)
 
@@ -86,6 +86,7 @@ def lib():
             "fvv_select_cameras": (I32, [C.POINTER(Camera), P, I32, C.POINTER(Camera), I32, P, P]),
             "fvv_pair_matrices": (I32, [C.POINTER(Camera), C.POINTER(Camera), P]),
             "fvv_set_debug": (I32, [P, I32]),
+            "fvv_set_debug_view": (I32, [P, I32]),
             "fvv_debug_read": (I32, [P, I32, P, I64]),
             "fvv_set_profiling": (I32, [P, I32]),
             "fvv_stage_count": (I32, []),
@@ -136,7 +137,8 @@ EXPORTED = ("fvv_abi_version", "fvv_create", "fvv_destroy", "fvv_last_error", "f
             "fvv_net_read_act", "fvv_net_device_bytes", "fvv_depth_encode_y12",
             "fvv_depth_decode_y12", "fvv_set_depth_format", "fvv_set_bg_model", "fvv_set_prefilter",
             "fvv_read_frame_depth", "fvv_tx_cameras", "fvv_server_tx_cameras",
-            "fvv_depth_encode_y12_batch", "fvv_depth_decode_y12_batch", "fvv_synthesize_noalloc")
+            "fvv_depth_encode_y12_batch", "fvv_depth_decode_y12_batch", "fvv_synthesize_noalloc",
+            "fvv_set_debug_view")
 DEPTH_MM16, DEPTH_Y12 = 0, 1
 NET_PARAMS, NET_GRADS = 0, 1
 NET_ALIGN = 8           # network inputs: multiples of 8 in both dimensions
@@ -453,7 +455,9 @@ class Context:
                                                  pitches.ctypes.data, MEM_DEVICE if dev else MEM_HOST, s))
         return outs
 
-    def set_debug(self, on: bool = True):
+    def set_debug(self, on: bool = True, view: int = 0):
+        """Stage taps of the following syntheses, for view ``view`` of each call."""
+        self._check(self._L.fvv_set_debug_view(self._h, view))
         self._check(self._L.fvv_set_debug(self._h, 1 if on else 0))
 
     def set_profiling(self, on: bool = True):
@@ -510,7 +514,8 @@ class Context:
 
     def debug_read(self, tap: int, shape):
         dtype = {TAP_Z_RAW: np.uint64, TAP_Z_FILT: np.uint64, TAP_BLEND: np.uint32,
-                 TAP_DEPTH: np.float32, TAP_BG_Z_RAW: np.uint64, TAP_BG_Z_FILT: np.uint64}[tap]
+                 TAP_DEPTH: np.float32, TAP_BG_Z_RAW: np.uint64, TAP_BG_Z_FILT: np.uint64,
+                 TAP_TILES: np.int32}[tap]
         a = np.empty(shape, dtype)
         self._check(self._L.fvv_debug_read(self._h, tap, a.ctypes.data, a.nbytes))
         return a

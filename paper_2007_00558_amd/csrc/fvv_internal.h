@@ -62,7 +62,8 @@ struct fvv_view_desc {
     // (FVV_NO_DEPTH = no splat), y = footprint x0 | y0 << 13 | (x1 - x0) << 26
     // | (y1 - y0) << 29, or FVV_SPL_RECOMPUTE when an extent exceeds 7
     unsigned long long *spl;
-    uint64_t pad16;         // keeps the descriptor a whole number of 16-byte words
+    int2 *dbg_tiles;        // debug tap (null unless enabled): per tile, the entries the
+                            // binning appended and the list capacity
     // per-tile results
     uint32_t *slot;         // W*H depth bits of covered pixels / FVV_HOLE / FVV_HOLE_OPEN
     int2 *rowsum;           // ntx*nty*FVV_TILE (first, last) covered x of each tile row

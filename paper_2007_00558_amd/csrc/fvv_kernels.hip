@@ -890,6 +890,7 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
     }
     __syncthreads();
     if (t == 0) {
+        if (vd.dbg_tiles) vd.dbg_tiles[tile] = make_int2(n_entries, vd.tile_cap);
         vd.counts[tile] = 0;   // ready for the next call
         if (s_open > 0) vd.open_list[atomicAdd(vd.open_count, 1)] = make_int2(vd.view, tile);
     }

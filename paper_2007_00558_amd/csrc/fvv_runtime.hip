@@ -164,6 +164,13 @@ struct fvv_ctx {
     hipEvent_t staging_free = nullptr;
     Workspace user;          // workspace of direct synthesis calls
     uint8_t *scratch = nullptr;   // device address of this device's no-allocation scratch
+    // Direct calls (synthesis, stacks, network forward and training) share
+    // the user workspace, the activation set, the network's gradient and
+    // the debug taps: the last such call's stream and an event recorded
+    // after its work; a call on another stream waits for that event first.
+    hipEvent_t last_ev = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool last_live = false;
     // debug taps of view 0 of the last direct synthesis
     bool debug = false;
     unsigned long long *dbg_z = nullptr;
@@ -174,6 +181,10 @@ struct fvv_ctx {
     uint32_t *dbg_rgba = nullptr;
     float *dbg_depth = nullptr;
     size_t dbg_px = 0;
+    int2 *dbg_tiles = nullptr;     // per tile: bin-list entries appended, list capacity
+    size_t dbg_tiles_n = 0;
+    int32_t debug_view = 0;        // view of a batched call whose stages are tapped
+    int64_t last_tiles = 0;
     int64_t last_px = 0;
     bool have_taps = false;
     // stage timing
@@ -639,6 +650,24 @@ struct LearnedIO {
     bool scratch_out = false;          // RGB goes to workspace scratch (stack-only calls)
 };
 
+// Order a direct call on stream s after the previous direct call's device
+// work when that ran on another stream (they share buffers).
+int32_t order_direct(fvv_ctx *c, hipStream_t s)
+{
+    if (c->last_live && c->last_stream != s) HIPCHECK(c, hipStreamWaitEvent(s, c->last_ev, 0));
+    return FVV_OK;
+}
+
+// Mark the end of a direct call's device work on stream s.
+int32_t mark_direct(fvv_ctx *c, hipStream_t s)
+{
+    if (!c->last_ev) HIPCHECK(c, hipEventCreateWithFlags(&c->last_ev, hipEventDisableTiming));
+    HIPCHECK(c, hipEventRecord(c->last_ev, s));
+    c->last_stream = s;
+    c->last_live = true;
+    return FVV_OK;
+}
+
 // Camera selection and tile layout of one view: the frame slot it reads
 // (si), its selected cameras and weights, tile grid and list sizes (L).
 int32_t plan_view(fvv_ctx *c, const fvv_camera &vc, const fvv_synth_params &P, int &si, ViewLayout &L)
@@ -765,8 +794,18 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
         return fail(c, FVV_E_NOMEM, "step does not fit its workspace");
     }
     if (net_px && (rc = reserve_act(c, lio.act, net_px, false))) return rc;
-    if (taps) {
-        const size_t px = (size_t)virts[0].width * virts[0].height;
+    const int tv = taps && c->debug_view < n_views ? c->debug_view : -1;   // tapped view
+    if (tv >= 0) {
+        const size_t nt = (size_t)lay[tv].n_tiles;
+        if (c->dbg_tiles_n < nt) {
+            HIPCHECK(c, hipDeviceSynchronize());
+            dfree(c, c->dbg_tiles, c->dbg_tiles_n * sizeof(int2));
+            c->dbg_tiles = nullptr;
+            c->dbg_tiles_n = 0;
+            if ((rc = dalloc(c, (void **)&c->dbg_tiles, nt * sizeof(int2)))) return rc;
+            c->dbg_tiles_n = nt;
+        }
+        const size_t px = (size_t)virts[tv].width * virts[tv].height;
         if (c->dbg_px < px) {
             HIPCHECK(c, hipDeviceSynchronize());
             dfree(c, c->dbg_z, c->dbg_px * 8);
@@ -821,7 +860,8 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
             d.stack = lio.stack_out ? lio.stack_out + (size_t)v * stack_bytes(vc.width, vc.height) / 2
                                     : (uint16_t *)carve(stack_bytes(vc.width, vc.height));
         }
-        if (taps && v == 0) {
+        if (v == tv) {
+            d.dbg_tiles = c->dbg_tiles;
             d.dbg_z = c->dbg_z;
             d.dbg_zf = c->dbg_zf;
             if (d.layered) {
@@ -906,11 +946,19 @@ int32_t synthesize_impl(fvv_ctx *c, const fvv_camera *virts, int n_views, const 
     std::vector<fvv_synth_params> Ps(n_views, P);
     LearnedIO lio;
     lio.act = c->act;
-    rc = launch_views(c, c->user, virts, Ps.data(), n_views, outs, pitches, mem_kind == FVV_MEM_HOST,
-                      (hipStream_t)stream, true, c->debug, lio);
+    const hipStream_t s = (hipStream_t)stream;
+    if ((rc = order_direct(c, s))) return rc;
+    rc = launch_views(c, c->user, virts, Ps.data(), n_views, outs, pitches, mem_kind == FVV_MEM_HOST, s, true,
+                      c->debug, lio);
+    const int32_t rm = mark_direct(c, s);
     if (rc) return rc;
-    c->have_taps = c->debug;
-    c->last_px = (int64_t)virts[0].width * virts[0].height;
+    if (rm) return rm;
+    c->have_taps = c->debug && c->debug_view < n_views;
+    if (c->have_taps) {
+        const fvv_camera &tvc = virts[c->debug_view];
+        c->last_px = (int64_t)tvc.width * tvc.height;
+        c->last_tiles = (int64_t)((tvc.width + FVV_TILE - 1) / FVV_TILE) * ((tvc.height + FVV_TILE - 1) / FVV_TILE);
+    }
     c->last_layered = P.path == FVV_PATH_LAYERED;
     return FVV_OK;
 }
@@ -1193,10 +1241,12 @@ void fvv_destroy(fvv_ctx *c)
         dfree(c, c->dbg_bzf, c->dbg_px * 8);
         dfree(c, c->dbg_rgba, c->dbg_px * 4);
         dfree(c, c->dbg_depth, c->dbg_px * 4);
+        dfree(c, c->dbg_tiles, c->dbg_tiles_n * sizeof(int2));
         release_bg(c);
         dfree(c, c->jbf, (FVV_JBF_WS + FVV_JBF_WC) * 4);
         for (hipEvent_t e : c->prof.pool) (void)hipEventDestroy(e);
         for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+        if (c->last_ev) (void)hipEventDestroy(c->last_ev);
         unet_act_free(c->act);
         unet_free(c->net);
     }
@@ -1693,6 +1743,15 @@ int32_t fvv_set_debug(fvv_ctx *c, int32_t enable)
     return FVV_OK;
 }
 
+int32_t fvv_set_debug_view(fvv_ctx *c, int32_t view)
+{
+    if (!c) return FVV_E_ARG;
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (view < 0) return fail(c, FVV_E_ARG, "view %d < 0", view);
+    c->debug_view = view;
+    return FVV_OK;
+}
+
 int32_t fvv_debug_read(fvv_ctx *c, int32_t tap, void *host_out, int64_t bytes)
 {
     if (!c) return FVV_E_ARG;
@@ -1707,6 +1766,7 @@ int32_t fvv_debug_read(fvv_ctx *c, int32_t tap, void *host_out, int64_t bytes)
     case FVV_TAP_Z_FILT: src = c->dbg_zf; need = c->last_px * 8; break;
     case FVV_TAP_BLEND: src = c->dbg_rgba; need = c->last_px * 4; break;
     case FVV_TAP_DEPTH: src = c->dbg_depth; need = c->last_px * 4; break;
+    case FVV_TAP_TILES: src = c->dbg_tiles; need = c->last_tiles * 8; break;
     case FVV_TAP_BG_Z_RAW:
     case FVV_TAP_BG_Z_FILT:
         if (!c->last_layered) return fail(c, FVV_E_STATE, "background-layer taps need a layered synthesis");
@@ -1960,8 +2020,11 @@ int32_t fvv_make_stack(fvv_ctx *c, const fvv_camera *virts, int32_t n_views, con
     LearnedIO lio;
     lio.stack_out = (uint16_t *)stack_dev;
     lio.scratch_out = true;
-    return launch_views(c, c->user, virts, Ps.data(), n_views, nullptr, nullptr, false, (hipStream_t)stream, true,
-                        false, lio);
+    const hipStream_t s = (hipStream_t)stream;
+    if ((rc = order_direct(c, s))) return rc;
+    rc = launch_views(c, c->user, virts, Ps.data(), n_views, nullptr, nullptr, false, s, true, false, lio);
+    const int32_t rm = mark_direct(c, s);
+    return rc ? rc : rm;
 }
 
 int32_t fvv_net_forward(fvv_ctx *c, const void *stack_dev, int32_t n, int32_t height, int32_t width, float *out_dev,
@@ -1976,14 +2039,18 @@ int32_t fvv_net_forward(fvv_ctx *c, const void *stack_dev, int32_t n, int32_t he
     const size_t px = (size_t)n * height * width;
     int32_t rc = reserve_act(c, c->act, px, false);
     if (rc) return rc;
+    const hipStream_t s = (hipStream_t)stream;
+    if ((rc = order_direct(c, s))) return rc;
     std::string err;
     hipEvent_t e0;
     fvv_prof *prof = c->profiling ? &c->prof : nullptr;
-    fvv_prof_begin(prof, (hipStream_t)stream, e0);
+    fvv_prof_begin(prof, s, e0);
     const hipError_t e = unet_forward(c->net, c->act, (const uint16_t *)stack_dev, n, height, width, out_dev, nullptr,
-                                      0, 0, 0, 0, (hipStream_t)stream, err);
-    fvv_prof_end(prof, (hipStream_t)stream, FVV_ST_NET, e0);
-    return net_status(c, e, err, "network forward");
+                                      0, 0, 0, 0, s, err);
+    fvv_prof_end(prof, s, FVV_ST_NET, e0);
+    const int32_t rm = mark_direct(c, s);
+    rc = net_status(c, e, err, "network forward");
+    return rc ? rc : rm;
 }
 
 int32_t fvv_net_train_step(fvv_ctx *c, const void *stack_dev, const float *target_dev, int32_t n, int32_t height,
@@ -1997,17 +2064,23 @@ int32_t fvv_net_train_step(fvv_ctx *c, const void *stack_dev, const float *targe
         return fail(c, FVV_E_ARG, "bad training batch (sizes must be multiples of %d, 1 <= valid_rows <= height)",
                     UNET_ALIGN);
     if (!std::isfinite(lr) || lr < 0.f) return fail(c, FVV_E_ARG, "learning rate must be finite and >= 0");
+    // the server's steps read the weights on their own streams while they run
+    if (c->server) return fail(c, FVV_E_STATE, "stop the server before training");
     DeviceGuard g(c->device);
     int32_t rc = reserve_act(c, c->act, (size_t)n * height * width, true);
     if (rc) return rc;
+    const hipStream_t s = (hipStream_t)stream;
+    if ((rc = order_direct(c, s))) return rc;
     std::string err;
     hipEvent_t e0;
     fvv_prof *prof = c->profiling ? &c->prof : nullptr;
-    fvv_prof_begin(prof, (hipStream_t)stream, e0);
+    fvv_prof_begin(prof, s, e0);
     const hipError_t e = unet_train(c->net, c->act, (const uint16_t *)stack_dev, target_dev, n, height, width,
-                                    valid_rows, lr, apply, loss_out, (hipStream_t)stream, err);
-    fvv_prof_end(prof, (hipStream_t)stream, FVV_ST_TRAIN, e0);
-    return net_status(c, e, err, "training step");
+                                    valid_rows, lr, apply, loss_out, s, err);
+    fvv_prof_end(prof, s, FVV_ST_TRAIN, e0);
+    const int32_t rm = mark_direct(c, s);
+    rc = net_status(c, e, err, "training step");
+    return rc ? rc : rm;
 }
 
 int32_t fvv_net_read_act(fvv_ctx *c, int32_t layer, void *host_out, int64_t bytes)

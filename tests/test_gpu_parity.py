@@ -289,27 +289,50 @@ def c3():
 
 def test_config3_batched_parity_sampled(fvv, ctx, oracle_lib, c3):
     """The benchmark's configuration: 60 views of 1920x1080 in one batched
-    call on device buffers; sampled views compared in full with the oracle,
-    the rest checked for coverage and determinism."""
+    call on device buffers; on five sampled views of that launch the raw and
+    filtered key maps, hole map and depth are compared bit-exact with the
+    oracle and the RGB within 1 (the stage taps follow one view of the batch
+    per call); every run of the batch gives the same bytes."""
     import torch
     w = c3
     ctx.set_rig(w.rig)
     ctx.upload_mvd(w.frames)
     outs = [torch.empty((v.height, v.width, 3), dtype=torch.uint8, device="cuda") for v in w.virtual]
-    say("[gpu] c3 batch of 60")
-    ctx.synthesize_batch(w.virtual, outs)
-    torch.cuda.synchronize()
-    host = [o.cpu().numpy() for o in outs]
     for vi in (0, 13, 29, 44, 59):
-        r = oracle_lib.synthesize(w.rig, w.frames, w.virtual[vi])
-        d = np.abs(host[vi].astype(np.int16) - r["rgb"].astype(np.int16))
-        assert d.max() <= 1, (vi, d.max())
+        say(f"[gpu] c3 batch of 60, taps on view {vi}")
+        ctx.set_debug(True, view=vi)
+        ctx.synthesize_batch(w.virtual, outs)
+        torch.cuda.synchronize()
+        v = w.virtual[vi]
+        taps = {name: ctx.debug_read(tap, (v.height, v.width)) for name, tap in
+                (("z", fvv.TAP_Z_RAW), ("zf", fvv.TAP_Z_FILT), ("blend", fvv.TAP_BLEND), ("depth", fvv.TAP_DEPTH))}
+        compare(oracle_lib, w, v, outs[vi].cpu().numpy(), taps)
+    ctx.set_debug(False)
+    host = [o.cpu().numpy() for o in outs]
     # a second batched run is identical
     outs2 = [torch.empty_like(o) for o in outs]
     ctx.synthesize_batch(w.virtual, outs2)
     torch.cuda.synchronize()
     for a, b in zip(outs, outs2):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("radius,W,H", [(10.0, 1024, 768), (20.0, 640, 480)])
+def test_tile_list_overflow_parity(fvv, ctx, oracle_lib, radius, W, H):
+    """A distant viewpoint crowds the source blocks into a few output tiles,
+    more than their bin lists hold (the capacity is eight times the average
+    per tile): those tiles test every block's tile range instead.  The tile
+    tap shows that branch ran; key maps, hole map and depth bit-exact, RGB
+    within 1."""
+    w = sg.config2(0)
+    v = sg.arc_camera(3.0, radius, W, H)
+    out, taps = gpu_run(fvv, ctx, w, v)
+    nt = ((W + 31) // 32) * ((H + 31) // 32)
+    tiles = ctx.debug_read(fvv.TAP_TILES, (nt, 2))
+    over = tiles[:, 0] > tiles[:, 1]
+    say(f"[gpu] overflowing tiles {int(over.sum())}, most entries {int(tiles[:, 0].max())}, capacity {tiles[0, 1]}")
+    assert over.sum() >= 5
+    compare(oracle_lib, w, v, out, taps)
 
 
 def test_config3_stage_parity_one_view(fvv, ctx, oracle_lib, c3):
