@@ -28,28 +28,50 @@ HBM_PEAK_GBS = 8000.0   # MI355X HBM3E peak, GB/s
 BF16_PEAK_TFLOPS = 2500.0   # MI355X dense bf16 matrix-core peak, TFLOP/s
 
 
+ROOT = os.path.dirname(os.path.abspath(__file__))
+
+
+def kernel_source_sha() -> str:
+    """Hash of the sources the plain path's kernels are compiled from (a
+    counter summary taken from other sources no longer describes them)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("fvv_kernels.hip", "fvv_internal.h"):
+        with open(os.path.join(ROOT, "paper_2007_00558_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def counted_traffic(kernel: str, n_views: int):
     """HBM bytes per launch of the tile kernel from the committed hardware-
-    counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None."""
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "plain_c3_60views_hbm_counters.md")
+    counter summary (FETCH_SIZE + WRITE_SIZE, copy-calibrated), or None when
+    there is none or it was taken from other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "plain_c3_60views_hbm_counters.md")
     if kernel != "tile" or n_views != 60 or not os.path.exists(path):
         return None
+    traffic, sha = None, None
     for line in open(path):
         if line.startswith("traffic_bytes_per_launch k_tile_plain 60 views:"):
-            return int(line.split(":")[1])
-    return None
+            traffic = int(line.split(":")[1])
+        if line.startswith("kernel_source_sha:"):
+            sha = line.split(":")[1].strip()
+    return traffic if sha == kernel_source_sha() else None
 
 
 def counted_valu_issue(kernel: str):
     """VALU issue utilisation of the tile kernel from the committed
-    instruction-issue counter summary (fraction of the issue slots), or None."""
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "tile_bin_fill_c3_issue_counters.md")
+    instruction-issue counter summary (fraction of the issue slots), or None
+    when there is none or it was taken from other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "tile_bin_fill_c3_issue_counters.md")
     if kernel != "tile" or not os.path.exists(path):
         return None
+    val, sha = None, None
     for line in open(path):
         if line.startswith("| `k_tile_plain` |"):
-            return float(line.split("|")[7])
-    return None
+            val = float(line.split("|")[7])
+        if line.startswith("kernel_source_sha:"):
+            sha = line.split(":")[1].strip()
+    return val if sha == kernel_source_sha() else None
 
 
 def net_flops(fvv, H: int, W: int) -> float:
@@ -80,6 +102,16 @@ def log(*a):
 #              (backward fetch) read once; per output pixel: RGB8 + 4-byte
 #              slot written (the z-buffer lives in LDS)
 #   desc, fill_open: descriptors, open holes only
+def method_bytes(n_views: int, n_out: int, n_src_sel: float) -> float:
+    """Compulsory HBM bytes of the method per batch (the per-output-pixel
+    model of the survey's measurement section): the selected cameras' RGB8 +
+    u16 depth read once (5 B per source pixel), a z-buffer cleared and read
+    (8 + 8 B per output pixel) and the RGB8 output (3 B per output pixel).
+    For three 1280x720 cameras into 1920x1080: 53.2 MB per view, 25.7 B per
+    output pixel."""
+    return n_views * (n_src_sel * 5.0 + n_out * (16.0 + 3.0))
+
+
 def stage_bytes(stage: str, n_views: int, n_out: int, n_src_sel: float, n_src_all: int) -> float:
     if stage == "repack":
         return n_src_all * (3 + 2 + 8 + 4)
@@ -90,24 +122,211 @@ def stage_bytes(stage: str, n_views: int, n_out: int, n_src_sel: float, n_src_al
     return float("nan")
 
 
-def run_serving(fvv, torch, sg, rig, raw, seconds: float, warmup_s: float, users: int = 64,
+def count_atomics(fvv, torch, ctx, rig, virts, k: int = 3) -> dict:
+    """Lane-level 64-bit atomics of one batched launch, counted from the
+    geometry (float32 projection of every valid source pixel of the selected
+    cameras, as the kernels project it):
+      tile: LDS atomicMin per output-tile window (the tile plus a 1-pixel
+        halo) that a point's footprint covers: sum over points of
+        sum over covered pixels of the number of windows holding the pixel;
+      bin: one list append (global atomic add) per (8x8 source block, output
+        tile whose window the block's footprints touch)."""
+    dev = torch.device("cuda:0")
+    planes = {}
+    lds = 0
+    glob = 0
+    for v in virts:
+        W, H = v.width, v.height
+        ntx, nty = (W + 31) // 32, (H + 31) // 32
+
+        def mult(n, nt):
+            x = torch.arange(n, device=dev)
+            m = 1 + ((x % 32 == 0) & (x >= 32)).long() + ((x % 32 == 31) & (x // 32 + 1 < nt)).long()
+            return torch.cat([torch.zeros(1, dtype=torch.long, device=dev), torch.cumsum(m, 0)])
+
+        cx, cy = mult(W, ntx), mult(H, nty)
+        idx, _ = fvv.select_cameras(rig, v, k)
+        for c in idx:
+            c = int(c)
+            if c not in planes:
+                planes[c] = torch.from_numpy(ctx.read_frame_depth(c)).to(dev)
+            z = planes[c]
+            Hs, Ws = z.shape
+            P = fvv.pair_matrices(rig[c], v)
+            A, a = torch.from_numpy(P["A"]).to(dev), torch.from_numpy(P["a"]).to(dev)
+            jj, ii = torch.meshgrid(torch.arange(Hs, device=dev, dtype=torch.float32),
+                                    torch.arange(Ws, device=dev, dtype=torch.float32), indexing="ij")
+            p = [((A[r, 0] * ii + A[r, 1] * jj) + A[r, 2]) * z + a[r] for r in range(3)]
+            ok = torch.isfinite(z) & (p[2] > 0.01)
+            u, vv = p[0] / p[2], p[1] / p[2]
+            mx = torch.clamp(float(P["sx"]) * z / p[2], 1.0, 4.0)
+            my = torch.clamp(float(P["sy"]) * z / p[2], 1.0, 4.0)
+            x0 = torch.clamp(torch.ceil(u - 0.5 * mx), min=0)
+            x1 = torch.clamp(torch.ceil(u + 0.5 * mx) - 1, max=W - 1)
+            y0 = torch.clamp(torch.ceil(vv - 0.5 * my), min=0)
+            y1 = torch.clamp(torch.ceil(vv + 0.5 * my) - 1, max=H - 1)
+            ok = ok & torch.isfinite(u) & torch.isfinite(vv) & (x0 <= x1) & (y0 <= y1)
+            x0 = torch.where(ok, x0, 0).long()
+            x1 = torch.where(ok, x1, 0).long()
+            y0 = torch.where(ok, y0, 0).long()
+            y1 = torch.where(ok, y1, 0).long()
+            per = (cx[x1 + 1] - cx[x0]) * (cy[y1 + 1] - cy[y0])
+            lds += int(torch.where(ok, per, 0).sum())
+            # per 8x8 block: footprint bounds -> tile range (as the binning)
+            hb, wb = (Hs + 7) // 8, (Ws + 7) // 8
+            pad = lambda t, fill: torch.nn.functional.pad(t, (0, wb * 8 - Ws, 0, hb * 8 - Hs), value=fill)
+            big = 1 << 30
+            blk = lambda t, fill: pad(torch.where(ok, t, fill), fill).reshape(hb, 8, wb, 8)
+            bx0 = blk(x0, big).amin(dim=(1, 3))
+            by0 = blk(y0, big).amin(dim=(1, 3))
+            bx1 = blk(x1, -1).amax(dim=(1, 3))
+            by1 = blk(y1, -1).amax(dim=(1, 3))
+            has = bx0 < big
+            tx0 = torch.clamp((bx0 + 31) // 32 - 1, min=0)
+            tx1 = torch.clamp((bx1 + 1) // 32, max=ntx - 1)
+            ty0 = torch.clamp((by0 + 31) // 32 - 1, min=0)
+            ty1 = torch.clamp((by1 + 1) // 32, max=nty - 1)
+            glob += int(torch.where(has, (tx1 - tx0 + 1) * (ty1 - ty0 + 1), 0).sum())
+    return {"tile_lds": lds, "bin_global": glob}
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def run_cpu_baseline(sg, w, n_views: int, n_out: int) -> dict:
+    """The oracle on the host's cores: timing mode (OpenMP over views, T =
+    OMP_NUM_THREADS or the core count) on the full 60-view batch, checked
+    equal to parity mode (one thread) on four views; the same for the
+    smaller configurations, one 960x544 network inference (torch CPU, T
+    threads) and a sample of the serving load's mixed-size requests."""
+    import oracle
+    import torch
+    oracle.lib()
+    T = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    res = {"kind": "oracle", "cores": T, "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    t = time.perf_counter()
+    outs = oracle.synthesize_views(w.rig, w.frames, w.virtual, T)
+    dt = time.perf_counter() - t
+    res["value"] = round(n_views * n_out / dt / 1e6, 3)
+    res["unit"] = "Mpixel/s"
+    check = list(range(0, n_views, max(1, n_views // 4)))[:4]
+    t = time.perf_counter()
+    same = all(np.array_equal(oracle.synthesize(w.rig, w.frames, w.virtual[q])["rgb"], outs[q]) for q in check)
+    dt1 = time.perf_counter() - t
+    assert same, "oracle timing mode differs from parity mode"
+    res["timing_equals_parity"] = same
+    res["single_thread_mpix_s"] = round(len(check) * n_out / dt1 / 1e6, 3)
+    res["sample"] = (f"all {n_views} swing views (9x1280x720 -> 1920x1080) in {dt:.1f} s at {T} threads, one view "
+                     f"per thread at a time; parity mode (1 thread) on views {check}")
+    cfg = {}
+    for name, wl in (("c1", sg.config1(0)), ("c2", sg.config2(0))):
+        vs = [wl.virtual[q % len(wl.virtual)] for q in range(4 * T)]
+        t = time.perf_counter()
+        oracle.synthesize_views(wl.rig, wl.frames, vs, T, k_nearest=wl.k_nearest)
+        dt = time.perf_counter() - t
+        npx = sum(v.width * v.height for v in vs)
+        cfg[name] = {"views": len(vs), "ms_per_view_per_thread": round(dt * T / len(vs) * 1e3, 3),
+                     "mpix_s": round(npx / dt / 1e6, 3)}
+    # serving mix: 3 output sizes on the arc
+    rng = np.random.default_rng(7)
+    sizes = [(640, 360), (1280, 720), (1920, 1080)]
+    vs = [sg.arc_camera(float(rng.uniform(-60, 60)), float(rng.uniform(2.0, 2.5)), *sizes[q % 3])
+          for q in range(2 * T)]
+    t = time.perf_counter()
+    oracle.synthesize_views(w.rig, w.frames, vs, T)
+    dt = time.perf_counter() - t
+    cfg["c5_mixed_sizes"] = {"requests": len(vs), "mpix_s": round(sum(v.width * v.height for v in vs) / dt / 1e6, 3)}
+    # one learned-path network inference at 960x544 (oracle.unet, float64)
+    from oracle import unet
+    from paper_2007_00558_amd import learned as L
+    flat = L.init_params(0)
+    P, o = {}, 0
+    for name, kind, ci, co in unet.LAYERS:
+        shp = unet.weight_shape(kind, ci, co)
+        k = int(np.prod(shp))
+        P[name] = (flat[o:o + k].reshape(shp), flat[o + k:o + k + co])
+        o += k + co
+    nthr = torch.get_num_threads()
+    torch.set_num_threads(T)
+    st = np.zeros((544, 960, 16))
+    t = time.perf_counter()
+    unet.forward(P, st)
+    cfg["c4_inference_s"] = round(time.perf_counter() - t, 3)
+    torch.set_num_threads(nthr)
+    res["configs"] = cfg
+    return res
+
+
+WEIGHTS = os.path.join(ROOT, "paper_2007_00558_amd", "weights", "unet_c4_loo.npy")
+
+
+def net_weights():
+    """Trained network parameters (float32 .npy, leave-one-camera-out on 500
+    seeded scenes) when committed, else a seeded initialisation."""
+    from paper_2007_00558_amd import learned as L
+    if os.path.exists(WEIGHTS):
+        return np.load(WEIGHTS, allow_pickle=False).astype(np.float32), "trained"
+    return L.init_params(0), "seeded initialisation"
+
+
+def make_sequence(sg, torch, w, n_frames: int = 30):
+    """A 30-frame dynamic sequence of the rig's scene (spheres moving, one
+    revolution per second, so the 30 Hz loop is seamless), captured on the
+    device with the rig's depth noise and invalid discs: n_frames frame sets
+    of device-resident (RGB8, u16 mm) buffers."""
+    from scenegen import gpu as sgg
+    seq = []
+    for f, scene in enumerate(sg.moving_scenes(w.scene, n_frames, amplitude=0.15, period_frames=n_frames)):
+        gen = torch.Generator().manual_seed(30_000 + f)
+        fs = []
+        for c in w.rig:
+            rgb, d = sgg.capture(scene, c, gen, noise_k=0.003, invalid_frac=0.10)
+            fs.append((rgb.contiguous(), d.to(torch.int16).contiguous()))
+        seq.append(fs)
+    torch.cuda.synchronize()
+    return seq
+
+
+def run_psnr(fvv, torch, flat, n_scenes: int) -> dict:
+    """PSNR of the plain and the learned path against the ray-cast truth on
+    held-out scenes (seeds never used in training), every camera of the rig
+    held out in turn at 960x540 and rendered from the three nearest others."""
+    from paper_2007_00558_amd import learned as L
+    ctx = fvv.Context(0)
+    ctx.set_rig(L.rig())
+    ctx.net_load(flat)
+    seeds = list(range(L.TEST_SEED0, L.TEST_SEED0 + n_scenes))
+    mean, per = L.evaluate(ctx, seeds)
+    ctx.close()
+    return {"test_scenes": n_scenes, "views": len(per["plain"]), "psnr_plain_db": round(mean["plain"], 3),
+            "psnr_learned_db": round(mean["learned"], 3), "gain_db": round(mean["learned"] - mean["plain"], 3),
+            "views_learned_better": int(sum(a > b for a, b in zip(per["learned"], per["plain"])))}
+
+
+def run_serving(fvv, torch, sg, rig, seq, seconds: float, warmup_s: float, users: int = 64,
                 rate: float = 30.0, seed: int = 0, path: int = 0) -> dict:
     """Continuous-batching load: `users` viewers, each with Poisson request
     arrivals at `rate` per second, output sizes 640x360 / 1280x720 / 1920x1080
     by user, a random walk of the viewpoint on the arc (angle in [-60, 60]
-    deg, radius in [2.0, 2.5] m); the frame set is re-ingested at 30 Hz from
-    device-resident raw buffers.  Latency = completion - submission, stamped
-    by the library's server."""
+    deg, radius in [2.0, 2.5] m); the frame sets of the dynamic sequence
+    `seq` are ingested in turn at 30 Hz from device-resident raw buffers.
+    Latency = completion - submission, stamped by the library's server."""
     from collections import deque
     dev = torch.device("cuda:0")
     sizes = [(640, 360), (1280, 720), (1920, 1080)]
     rng = np.random.default_rng(seed)
     ctx = fvv.Context(0)
     ctx.set_rig(rig)
-    ctx.upload_mvd(raw, mem=fvv.MEM_DEVICE)
+    ctx.upload_mvd(seq[0], mem=fvv.MEM_DEVICE)
     if path == fvv.PATH_LEARNED:
-        from paper_2007_00558_amd import learned as L
-        ctx.net_load(L.init_params(0))
+        ctx.net_load(net_weights()[0])
     torch.cuda.synchronize()
     srv = fvv.Server(ctx, max_slots=64)
     n_buf = 8
@@ -151,6 +370,7 @@ def run_serving(fvv, torch, sg, rig, raw, seconds: float, warmup_s: float, users
 
     t0 = time.perf_counter()
     next_refresh = 0.0
+    n_refresh = 0
     for i, (t, u) in enumerate(events):
         while True:
             now = time.perf_counter() - t0
@@ -159,8 +379,9 @@ def run_serving(fvv, torch, sg, rig, raw, seconds: float, warmup_s: float, users
             drain(False)
             if t - now > 0.001:
                 time.sleep(0.0005)
-        if t >= next_refresh:
-            ctx.upload_mvd(raw, mem=fvv.MEM_DEVICE, stream=refresh)
+        while t >= next_refresh:
+            n_refresh += 1
+            ctx.upload_mvd(seq[n_refresh % len(seq)], mem=fvv.MEM_DEVICE, stream=refresh)
             next_refresh += 1.0 / 30.0
         while all(busy[u]):
             drain(False)
@@ -181,7 +402,10 @@ def run_serving(fvv, torch, sg, rig, raw, seconds: float, warmup_s: float, users
     # (longer than the arrival window when the load exceeds the device)
     window = max(seconds, max(ts + lat for ts, lat, _ in meas) - warmup_s)
     return {"users": users, "rate_per_user": rate, "path": "learned" if path else "plain",
-            "offered_req_s": round(len(events) / horizon, 1), "completed": len(done),
+            "frame_sets": len(seq), "refreshes": n_refresh, "warmup_s": warmup_s,
+            "offered_req_s": round(len(events) / horizon, 1),
+            "offered_mpix_s": round(sum(sizes[u % 3][0] * sizes[u % 3][1] for _, u in events) / horizon / 1e6, 1),
+            "completed": len(done),
             "measured_requests": len(meas), "measured_s": seconds,
             "p50_ms": round(float(np.percentile(lats, 50)), 3),
             "p99_ms": round(float(np.percentile(lats, 99)), 3),
@@ -194,11 +418,10 @@ def run_serving(fvv, torch, sg, rig, raw, seconds: float, warmup_s: float, users
 
 def run_learned(fvv, torch, w, ctx, stream, args) -> dict:
     """Learned path at 960x540 (the swing views at half size): stack in the
-    tile kernel, network forward, RGB.  Weights are a seeded initialisation
-    (throughput does not depend on their values)."""
-    from paper_2007_00558_amd import learned as L
+    tile kernel, network forward, RGB, with the trained weights."""
     dev = torch.device("cuda:0")
-    ctx.net_load(L.init_params(0))
+    flat, kind = net_weights()
+    ctx.net_load(flat)
     virts = [v.with_size(960, 540, 0.5) for v in w.virtual[: args.learned_views]]
     outs = [torch.empty((540, 960, 3), dtype=torch.uint8, device=dev) for _ in virts]
     p = fvv.params(path=fvv.PATH_LEARNED)
@@ -222,7 +445,7 @@ def run_learned(fvv, torch, w, ctx, stream, args) -> dict:
     ctx.set_profiling(False)
     net_ms, net_n = prof["net"]
     fl = net_flops(fvv, fvv.pad8(540), 960)
-    tflops = fl / (net_ms / net_n * 1e-3) / 1e12
+    tflops = fl * len(virts) / (net_ms * 1e-3) / 1e12
     # plain at the same size and views, for comparison
     ctx.synthesize_batch(virts, outs, stream=stream)
     torch.cuda.synchronize()
@@ -242,7 +465,7 @@ def run_learned(fvv, torch, w, ctx, stream, args) -> dict:
     # plain renders; lr 0 keeps the weights) -> samples/s
     nb = min(4, len(virts))
     Hp, Wp = fvv.pad8(540), fvv.pad8(960)
-    stack = torch.empty((nb, Hp, Wp, 32), dtype=torch.int16, device=dev)
+    stack = torch.empty((nb, Hp, Wp, fvv.NET_IN), dtype=torch.int16, device=dev)
     ctx.make_stack(virts[:nb], [fvv.params()] * nb, stack, stream=stream)
     target = torch.zeros((nb, Hp, Wp, 3), dtype=torch.float32, device=dev)
     for q in range(nb):
@@ -258,9 +481,10 @@ def run_learned(fvv, torch, w, ctx, stream, args) -> dict:
     train_tflops = 3.0 * fl * nb / (ms_train * 1e-3) / 1e12
     npx = len(virts) * 960 * 540
     return {"config": "learned blend/inpaint, 9 cams 1280x720 -> 960x540 (stack 960x544x16 bf16), K=3",
-            "views": len(virts), "ms_per_batch": round(ms, 3), "mpix_s": round(npx / (ms * 1e-3) / 1e6, 1),
+            "weights": kind, "views": len(virts), "ms_per_batch": round(ms, 3), "mpix_s": round(npx / (ms * 1e-3) / 1e6, 1),
             "plain_same_views_mpix_s": round(npx / (ms_plain * 1e-3) / 1e6, 1),
-            "net_ms_per_view": round(net_ms / net_n, 4), "net_gflop_per_view": round(fl / 1e9, 2),
+            "net_ms_per_view": round(net_ms / len(virts), 4), "net_batches": net_n,
+            "net_gflop_per_view": round(fl / 1e9, 2),
             "roofline": {"bound": "mfma", "kernel": "network forward (all layers)",
                          "achieved": round(tflops, 1), "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                          "frac": round(tflops / BF16_PEAK_TFLOPS, 4), "traffic": None},
@@ -426,14 +650,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--views", type=int, default=60)
     ap.add_argument("--latency-reps", type=int, default=3)
-    ap.add_argument("--cpu-views", type=int, default=16,
-                    help="views of the oracle CPU baseline sample (0 = skip)")
-    ap.add_argument("--serve-seconds", type=float, default=5.0,
-                    help="measured seconds of the serving load (0 = skip)")
+    ap.add_argument("--cpu", type=int, default=1, help="time the oracle on the host's cores (0 = skip)")
+    ap.add_argument("--peaks", type=int, default=1,
+                    help="measure copy bandwidth and atomic rates, count the path's atomics (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="measured seconds of the serving load after 1 s of warm-up (0 = skip)")
+    ap.add_argument("--psnr-scenes", type=int, default=5,
+                    help="held-out scenes of the plain vs learned PSNR (0 = skip)")
     ap.add_argument("--learned-views", type=int, default=16,
                     help="views of the learned-path measurement at 960x540 (0 = skip)")
-    ap.add_argument("--serve-learned-seconds", type=float, default=3.0,
-                    help="measured seconds of the learned serving load (0 = skip)")
+    ap.add_argument("--serve-learned-seconds", type=float, default=10.0,
+                    help="measured seconds of the learned serving load after 1 s of warm-up (0 = skip)")
+    ap.add_argument("--serve-learned-24", type=float, default=3.0,
+                    help="measured seconds of a 24-user learned load (0 = skip)")
     ap.add_argument("--layered", type=int, default=1, help="measure the layered FG/BG step (0 = skip)")
     ap.add_argument("--codec-reps", type=int, default=20,
                     help="repetitions of the 12-bit depth codec timing (0 = skip)")
@@ -535,16 +764,48 @@ def main():
         stages[name] = {"avg_ms": round(avg_ms, 4), "launches_per_step": cnt / prof_steps}
         if b == b:
             stages[name]["alg_GBs"] = round(b / (avg_ms * 1e-3) / 1e9, 1)
-    dom = max(stages, key=lambda k: stages[k]["avg_ms"] * stages[k]["launches_per_step"])
-    if "alg_GBs" not in stages[dom]:
-        dom = "tile"
-    d = stages[dom]
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": d["alg_GBs"], "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(d["alg_GBs"] / HBM_PEAK_GBS, 4),
+    dom = "tile"
+    t_tile = stages[dom]["avg_ms"] * 1e-3
+    alg = method_bytes(n_views, n_out, n_src_sel)
+    achieved = alg / t_tile / 1e9
+    roofline = {"bound": "hbm", "kernel": "k_tile_plain", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": counted_traffic(dom, n_views),
+                "alg_bytes": round(alg), "alg_bytes_per_output_px": round(alg / (n_views * n_out), 2),
+                "design_bytes": round(stage_bytes(dom, n_views, n_out, n_src_sel, n_src_all)),
+                "step_frac": round(alg / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                 "valu_issue_vs_4cycle_model": counted_valu_issue(dom),
-                "alg_bytes": round(stage_bytes(dom, n_views, n_out, n_src_sel, n_src_all))}
+                "kernel_source_sha": kernel_source_sha()}
     log(f"[bench] stages: {json.dumps(stages)}")
+
+    # measured peaks and the atomics of the binning and the tile kernel
+    atomics = None
+    if args.peaks:
+        peaks = fvv.measure_peaks(0)
+        cnt = count_atomics(fvv, torch, ctx, w.rig, w.virtual)
+        t_bin = stages["bin"]["avg_ms"] * 1e-3
+        lds_rate, glob_rate = cnt["tile_lds"] / t_tile, cnt["bin_global"] / t_bin
+        # the binning's appends of one view, counted by the library's tile tap
+        vq = n_views // 3
+        ctx.set_debug(True, view=vq)
+        ctx.synthesize_batch(virt_c, outs, stream=stream)
+        torch.cuda.synchronize()
+        v = w.virtual[vq]
+        tiles = ctx.debug_read(fvv.TAP_TILES, (((v.width + 31) // 32) * ((v.height + 31) // 32), 2))
+        ctx.set_debug(False)
+        one = count_atomics(fvv, torch, ctx, w.rig, [v])
+        atomics = {"peaks": {k: round(v, 1) for k, v in peaks.items()},
+                   "bin_count_check": {"view": vq, "tap_entries": int(tiles[:, 0].sum()),
+                                       "counted": one["bin_global"]},
+                   "tile_lds_atomic_min_per_launch": cnt["tile_lds"],
+                   "tile_lds_atomic_min_per_s": round(lds_rate, 1),
+                   "tile_frac_of_lds_window_peak": round(lds_rate / peaks["lds_atomic_min_window_per_s"], 4),
+                   "bin_global_atomics_per_launch": cnt["bin_global"],
+                   "bin_global_atomics_per_s": round(glob_rate, 1),
+                   "bin_frac_of_global_distinct_peak": round(glob_rate / peaks["global_atomic_min_distinct_per_s"], 4),
+                   "hbm_copy_frac_of_spec": round(peaks["copy_GBs"] / HBM_PEAK_GBS, 4),
+                   "tile_frac_of_copy_bandwidth": round(achieved / peaks["copy_GBs"], 4)}
+        log(f"[bench] atomics {json.dumps(atomics)}")
 
     # single-view latency: one view per call, host clock to completion
     lat = []
@@ -558,19 +819,9 @@ def main():
     log(f"[bench] single-view latency p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms")
 
     cpu = None
-    if args.cpu_views > 0:
-        import oracle
-        oracle.lib()
-        sample = w.virtual[:: max(1, n_views // args.cpu_views)][: args.cpu_views]
-        t = time.perf_counter()
-        for v in sample:
-            oracle.synthesize(w.rig, w.frames, v)
-        dt = time.perf_counter() - t
-        cpu = {"value": round(len(sample) * n_out / dt / 1e6, 3), "unit": "Mpixel/s", "cores": 1,
-               "kind": "oracle",
-               "sample": f"{len(sample)} of the {n_views} swing views (9x1280x720 -> 1920x1080), "
-                         f"single-threaded, {dt:.1f} s on {platform.processor() or platform.machine()}"}
-        log(f"[bench] cpu oracle {cpu['value']} Mpix/s")
+    if args.cpu:
+        cpu = run_cpu_baseline(sg, w, n_views, n_out)
+        log(f"[bench] cpu oracle {json.dumps(cpu)}")
 
     tx = run_tx_policy(fvv, torch, w)
     log(f"[bench] transmission policy {json.dumps(tx)}")
@@ -591,24 +842,34 @@ def main():
         learned = run_learned(fvv, torch, w, ctx, stream, args)
         log(f"[bench] learned {json.dumps(learned)}")
 
+    psnr = None
+    if args.psnr_scenes > 0:
+        log(f"[bench] PSNR plain vs learned on {args.psnr_scenes} held-out scenes")
+        flat, kind = net_weights()
+        psnr = run_psnr(fvv, torch, flat, args.psnr_scenes)
+        psnr["weights"] = kind
+        log(f"[bench] psnr {json.dumps(psnr)}")
+
     serving = None
-    if args.serve_seconds > 0:
-        log("[bench] serving load: 64 users x 30 req/s, mixed 360p/720p/1080p")
-        serving = run_serving(fvv, torch, sg, w.rig, raw, args.serve_seconds, 1.0)
-        log(f"[bench] serving {json.dumps(serving)}")
     serving_learned = None
-    if args.serve_learned_seconds > 0:
-        # the plain load (64 users) needs about twice the network throughput
-        # of one GPU; reported as is, and at 24 users, a load it sustains
-        log("[bench] learned serving load: 64 users x 30 req/s, mixed 360p/720p/1080p")
-        serving_learned = run_serving(fvv, torch, sg, w.rig, raw, args.serve_learned_seconds, 1.0,
-                                      path=fvv.PATH_LEARNED)
-        log(f"[bench] learned serving {json.dumps(serving_learned)}")
-        log("[bench] learned serving load: 24 users x 30 req/s, mixed 360p/720p/1080p")
-        serving_learned24 = run_serving(fvv, torch, sg, w.rig, raw, args.serve_learned_seconds, 1.0, users=24,
-                                        path=fvv.PATH_LEARNED)
-        log(f"[bench] learned serving (24 users) {json.dumps(serving_learned24)}")
-        serving_learned = {"users64": serving_learned, "users24": serving_learned24}
+    if args.serve_seconds > 0 or args.serve_learned_seconds > 0:
+        log("[bench] dynamic sequence: 30 frame sets of the 9x1280x720 rig, spheres moving")
+        seq = make_sequence(sg, torch, w)
+        if args.serve_seconds > 0:
+            log("[bench] serving load: 64 users x 30 req/s, mixed 360p/720p/1080p")
+            serving = run_serving(fvv, torch, sg, w.rig, seq, args.serve_seconds, 1.0)
+            log(f"[bench] serving {json.dumps(serving)}")
+        if args.serve_learned_seconds > 0:
+            log("[bench] learned serving load: 64 users x 30 req/s, mixed 360p/720p/1080p")
+            serving_learned = {"users64": run_serving(fvv, torch, sg, w.rig, seq, args.serve_learned_seconds, 1.0,
+                                                      path=fvv.PATH_LEARNED)}
+            log(f"[bench] learned serving {json.dumps(serving_learned['users64'])}")
+            if args.serve_learned_24 > 0:
+                log("[bench] learned serving load: 24 users x 30 req/s, mixed 360p/720p/1080p")
+                serving_learned["users24"] = run_serving(fvv, torch, sg, w.rig, seq, args.serve_learned_24, 1.0,
+                                                         users=24, path=fvv.PATH_LEARNED)
+                log(f"[bench] learned serving (24 users) {json.dumps(serving_learned['users24'])}")
+        del seq
 
     res = {
         "metric": "virtual-view Mpixel/s (9-cam 720p MVD -> 1080p) + p99 latency, plain vs learned",
@@ -629,6 +890,7 @@ def main():
                                "(swing -60..+60 deg), K=3, hole fill; step = MVD re-ingest + batched synthesis",
                    "views_per_step": n_views, "out": "1920x1080", "sources": "9x1280x720", "k_nearest": 3},
         "roofline": roofline,
+        "atomics": atomics,
         "cpu_baseline": cpu,
         "latency_ms": {"single_view_p50": round(float(np.percentile(lat, 50)), 3),
                        "single_view_p99": round(float(np.percentile(lat, 99)), 3),
@@ -637,6 +899,7 @@ def main():
         "kernel_ms_per_step": round(sum(v["avg_ms"] * v["launches_per_step"] for v in stages.values()), 4),
         "serving": serving,
         "learned": learned,
+        "psnr": psnr,
         "serving_learned": serving_learned,
         "depth_codec": codec,
         "layered": layered,

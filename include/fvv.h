@@ -335,6 +335,21 @@ int32_t fvv_set_debug(fvv_ctx *ctx, int32_t enable);
 int32_t fvv_set_debug_view(fvv_ctx *ctx, int32_t view);
 int32_t fvv_debug_read(fvv_ctx *ctx, int32_t tap, void *host_out, int64_t bytes);
 
+/* Measured peaks of device hip_device for the roofline of the plain path
+ * (the operations the binning and the tile kernel are built from), each the
+ * best of five timed launches after a warm-up, on the null stream (the call
+ * synchronises the device and allocates 2 GiB for its duration):
+ *   out[0] HBM copy bandwidth, GB/s of bytes read plus written (1 GiB copy);
+ *   out[1] global 64-bit atomicMin per second, every lane its own word;
+ *   out[2] the same with the 64 lanes of a wave on one word;
+ *   out[3] LDS 64-bit atomicMin per second, conflict-free words;
+ *   out[4] LDS 64-bit atomicMin per second, pseudo-random words of a 34x34
+ *          window shared by eight waves (the splat's z-buffer).
+ * Returns FVV_PEAKS (the count written) or an error (text in
+ * fvv_last_error(NULL)); n must be >= FVV_PEAKS. */
+#define FVV_PEAKS 5
+int32_t fvv_measure_peaks(int32_t hip_device, double *out, int32_t n);
+
 /* Stage timing (tracing).  With profiling on, every kernel the context
  * launches is bracketed by HIP events on the caller's stream (this adds a
  * little launch overhead).  fvv_profile_read synchronises on the recorded
@@ -404,12 +419,12 @@ int32_t fvv_server_stats(fvv_ctx *ctx, uint64_t *out6);
  *  - Parameters: fvv_net_param_count() float32 values, layer by layer, each
  *    layer's weights (C_out, kh, kw, C_in) then its bias (C_out); a transposed
  *    convolution maps input (y, x) to output (2y+kh, 2x+kw).
- *  - Stack (network input): bfloat16 [n][Hp][Wp][32], Hp and Wp the output
+ *  - Stack (network input): bfloat16 [n][Hp][Wp][16], Hp and Wp the output
  *    height and width rounded up to multiples of 8.  Per pixel and for each
  *    of the first three selected cameras (selection order): the camera's
  *    depth-consistent bilinear colour R, G, B / 255, 0.5 / (its depth in that
  *    camera) capped at 1, and 1; zeros where the camera gives no sample, at
- *    pixels without a filtered point and in the padding; channels 15..31 zero.
+ *    pixels without a filtered point and in the padding; channel 15 zero.
  * fvv_net_load: host float32 parameters; resets the optimiser state.
  * fvv_net_read: host copy of the parameters (FVV_NET_PARAMS) or of the last
  *   training step's gradient (FVV_NET_GRADS).

@@ -29,7 +29,7 @@ def build(force: bool = True) -> str:
     """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
                                "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -112,6 +112,10 @@ def lib():
         L.fvv_ref_synthesize.argtypes = [C.POINTER(RefCamera), C.c_int32, P, P, P, P,
                                          C.POINTER(RefCamera), C.c_int32, C.c_float, C.c_float,
                                          C.c_int32, P, P, P, P, P, P, P, P]
+        L.fvv_ref_synthesize_views.restype = C.c_int32
+        L.fvv_ref_synthesize_views.argtypes = [C.POINTER(RefCamera), C.c_int32, P, P, P, P,
+                                               C.POINTER(RefCamera), C.c_int32, C.c_int32, C.c_float,
+                                               C.c_float, C.c_int32, P, C.c_int32]
         _lib = L
     return _lib
 
@@ -289,6 +293,31 @@ def synthesize(rig, frames, virt, k_nearest: int = 3, tau: float = 0.05, max_fp:
     res = dict(rgb=out, sel=sel[:K].copy(), weights=w[:K].copy())
     res.update(t)
     return res
+
+
+def synthesize_views(rig, frames, virts, threads: int, k_nearest: int = 3, tau: float = 0.05,
+                     max_fp: float = 4.0, fill_mode: int = 0):
+    """Timing mode: O1..O7 for many virtual cameras of one frame set on
+    `threads` OpenMP threads (one view per thread at a time); each view's
+    RGB8 equals :func:`synthesize` of that view alone."""
+    n = len(rig)
+    cams = (RefCamera * n)(*[ref_camera(c) for c in rig])
+    rgbs = [None if f is None else np.ascontiguousarray(f.rgb, np.uint8) for f in frames]
+    deps = [None if f is None else np.ascontiguousarray(f.depth_mm, np.uint16) for f in frames]
+    prgb = (C.c_void_p * n)(*[None if a is None else a.ctypes.data for a in rgbs])
+    pdep = (C.c_void_p * n)(*[None if a is None else a.ctypes.data for a in deps])
+    rp = np.array([0 if a is None else a.shape[1] * 3 for a in rgbs], np.int64)
+    dp = np.array([0 if a is None else a.shape[1] for a in deps], np.int64)
+    nv = len(virts)
+    va = (RefCamera * nv)(*[ref_camera(v) for v in virts])
+    outs = [np.empty((v.height, v.width, 3), np.uint8) for v in virts]
+    po = (C.c_void_p * nv)(*[o.ctypes.data for o in outs])
+    bad = lib().fvv_ref_synthesize_views(cams, n, C.cast(prgb, C.c_void_p), _ptr(rp), C.cast(pdep, C.c_void_p),
+                                         _ptr(dp), va, nv, k_nearest, tau, max_fp, fill_mode,
+                                         C.cast(po, C.c_void_p), threads)
+    if bad:
+        raise ValueError("oracle rejected the arguments of some views")
+    return outs
 
 
 def tx_cameras(rig, viewpoints, n_tx: int = 5):

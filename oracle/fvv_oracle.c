@@ -682,6 +682,30 @@ int32_t fvv_ref_synthesize(const ref_camera *rig, int32_t n,
     return K;
 }
 
+/* Timing mode (the benchmark's CPU baseline): fvv_ref_synthesize for
+ * n_views virtual cameras of one frame set, views spread over `threads`
+ * OpenMP threads (dynamic schedule).  Each view is computed exactly as a
+ * call of fvv_ref_synthesize alone computes it (the views share only
+ * read-only inputs), so the outputs equal those of the single-threaded
+ * calls; outs[v] receives view v's RGB8.  Returns the number of views whose
+ * arguments were rejected (0 on success). */
+int32_t fvv_ref_synthesize_views(const ref_camera *rig, int32_t n,
+                                 const uint8_t *const *views_rgb, const int64_t *rgb_pitch,
+                                 const uint16_t *const *views_depth, const int64_t *depth_pitch,
+                                 const ref_camera *virts, int32_t n_views, int32_t k_sel, float tau,
+                                 float max_fp, int32_t fill_mode, uint8_t *const *outs, int32_t threads)
+{
+    int32_t bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(threads) reduction(+ : bad)
+    for (int32_t v = 0; v < n_views; ++v) {
+        const int32_t K = fvv_ref_synthesize(rig, n, views_rgb, rgb_pitch, views_depth, depth_pitch, &virts[v],
+                                             k_sel, tau, max_fp, fill_mode, outs[v], NULL, NULL, NULL, NULL,
+                                             NULL, NULL, NULL);
+        bad += K < 0;
+    }
+    return bad;
+}
+
 /* ------------------------------------------------------------------------ */
 /* OC: 12-bit depth coding for 8-bit YUV420 codecs (Section V-A).
  * Quantisation, Eq. 2: Y = (2^12 - 3)(1/z - 1/z_far)/(1/z_near - 1/z_far) + 2

@@ -87,6 +87,7 @@ def lib():
             "fvv_pair_matrices": (I32, [C.POINTER(Camera), C.POINTER(Camera), P]),
             "fvv_set_debug": (I32, [P, I32]),
             "fvv_set_debug_view": (I32, [P, I32]),
+            "fvv_measure_peaks": (I32, [I32, P, I32]),
             "fvv_debug_read": (I32, [P, I32, P, I64]),
             "fvv_set_profiling": (I32, [P, I32]),
             "fvv_stage_count": (I32, []),
@@ -138,11 +139,11 @@ EXPORTED = ("fvv_abi_version", "fvv_create", "fvv_destroy", "fvv_last_error", "f
             "fvv_depth_decode_y12", "fvv_set_depth_format", "fvv_set_bg_model", "fvv_set_prefilter",
             "fvv_read_frame_depth", "fvv_tx_cameras", "fvv_server_tx_cameras",
             "fvv_depth_encode_y12_batch", "fvv_depth_decode_y12_batch", "fvv_synthesize_noalloc",
-            "fvv_set_debug_view")
+            "fvv_set_debug_view", "fvv_measure_peaks")
 DEPTH_MM16, DEPTH_Y12 = 0, 1
 NET_PARAMS, NET_GRADS = 0, 1
 NET_ALIGN = 8           # network inputs: multiples of 8 in both dimensions
-NET_IN = 32             # stack channels on the device (16 defined, zero padded)
+NET_IN = 16             # stack channels on the device (15 used, one zero channel)
 
 
 def camera(cam) -> Camera:
@@ -207,6 +208,17 @@ def _stream_handle(stream):
     if isinstance(stream, int):
         return stream
     return stream.cuda_stream
+
+
+def measure_peaks(device: int = 0) -> dict:
+    """Measured HBM copy bandwidth and 64-bit atomicMin rates of the device."""
+    out = np.zeros(5, np.float64)
+    rc = lib().fvv_measure_peaks(device, out.ctypes.data, out.size)
+    if rc < 0:
+        raise FvvError(rc, lib().fvv_last_error(None).decode())
+    return {"copy_GBs": float(out[0]), "global_atomic_min_distinct_per_s": float(out[1]),
+            "global_atomic_min_wave_contended_per_s": float(out[2]),
+            "lds_atomic_min_distinct_per_s": float(out[3]), "lds_atomic_min_window_per_s": float(out[4])}
 
 
 def select_cameras(rig: Sequence, virt, k: int, present=None):

@@ -7,6 +7,7 @@
 
 #include "fvv_y12.h"
 
+#include <string>
 #include <utility>
 #include <vector>
 
@@ -72,7 +73,7 @@ struct fvv_view_desc {
     int32_t *open_count;    // its length (cleared by the binning kernel)
     uint8_t *out;           // final RGB8, out_pitch bytes per row
     int64_t out_pitch;
-    // learned path: network input [stack_h][stack_w][32] bf16 (null = plain view)
+    // learned path: network input [stack_h][stack_w][16] bf16 (null = plain view)
     uint16_t *stack;
     int32_t stack_w, stack_h;   // W, H rounded up to multiples of 8
     // debug taps (null unless enabled); dbg_bz / dbg_bzf: background layer
@@ -197,11 +198,16 @@ hipError_t fvv_launch_y12(const fvv_y12_batch &b, bool encode, hipStream_t s);
 // Host-side launchers (fvv_kernels.hip).  All return hipError_t of the launch.
 hipError_t fvv_launch_repack(const fvv_repack_batch &b, int max_w, int max_h, hipStream_t s, fvv_prof *prof);
 // h_views: device-visible pointer to the coherent pinned host copy of the
-// descriptors, copied into d_views by the first kernel of the sequence.
+// descriptors and extra_bytes (a multiple of 16) that follow them, copied
+// into d_views by the first kernel of the sequence.
 hipError_t fvv_launch_synthesis(const fvv_view_desc *h_views, fvv_view_desc *d_views,
-                                const fvv_batch_dims &dims, hipStream_t s, fvv_prof *prof);
+                                const fvv_batch_dims &dims, size_t extra_bytes, hipStream_t s, fvv_prof *prof);
 // One view whose descriptor travels in the kernel arguments: stored to
 // d_view, and the view's dims.total_tiles counters at `counts` cleared, by
 // the first kernel of the sequence (no host staging, nothing allocated).
 hipError_t fvv_launch_synthesis_one(const fvv_view_desc &view, fvv_view_desc *d_view, int32_t *counts,
                                     const fvv_batch_dims &dims, hipStream_t s, fvv_prof *prof);
+
+// Measured machine peaks (fvv_peaks.hip) on the current device; see
+// fvv_measure_peaks in fvv.h for the five figures written to out.
+hipError_t fvv_measure_peaks_impl(double *out, std::string &err);

@@ -469,8 +469,8 @@ __device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int k0, int
 // selected cameras, the depth-consistent bilinear colour that blend_pixel
 // mixes (R, G, B / 255), the inverse source depth 0.5 / q_z capped at 1 and a
 // validity flag; zeros where a camera gives no sample, for pixels without a
-// filtered point and for the padding beyond the image.  16 bf16 channels and
-// 16 zero channels (64 bytes) per pixel.
+// filtered point and for the padding beyond the image.  16 bf16 channels (the
+// last one zero), 32 bytes per pixel.
 __device__ __forceinline__ void stack_pixel(const fvv_view_desc &vd, int x, int y, unsigned long long kf)
 {
     uint32_t ch[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // channel c in ch[c / 2], low half for even c
@@ -514,11 +514,9 @@ __device__ __forceinline__ void stack_pixel(const fvv_view_desc &vd, int x, int 
             put(5 * k + 4, 1.0f);
         }
     }
-    uint4 *o = (uint4 *)(vd.stack + ((int64_t)y * vd.stack_w + x) * 32);
+    uint4 *o = (uint4 *)(vd.stack + ((int64_t)y * vd.stack_w + x) * 16);
     o[0] = make_uint4(ch[0], ch[1], ch[2], ch[3]);
     o[1] = make_uint4(ch[4], ch[5], ch[6], ch[7]);
-    o[2] = make_uint4(0, 0, 0, 0);
-    o[3] = make_uint4(0, 0, 0, 0);
 }
 
 __device__ __forceinline__ void put_rgb(uint8_t *out, int64_t pitch, int x, int y, uint32_t c)
@@ -1102,11 +1100,12 @@ hipError_t launch_stages(fvv_view_desc *d_views, const fvv_batch_dims &b, hipStr
 }  // namespace
 
 hipError_t fvv_launch_synthesis(const fvv_view_desc *h_views, fvv_view_desc *d_views, const fvv_batch_dims &b,
-                                hipStream_t s, fvv_prof *prof)
+                                size_t extra_bytes, hipStream_t s, fvv_prof *prof)
 {
     if (b.n_views <= 0) return hipSuccess;
     static_assert(sizeof(fvv_view_desc) % 16 == 0, "descriptors are copied in 16-byte words");
-    const int words = (int)(b.n_views * sizeof(fvv_view_desc) / 16);
+    if (extra_bytes % 16) return hipErrorInvalidValue;
+    const int words = (int)((b.n_views * sizeof(fvv_view_desc) + extra_bytes) / 16);
     hipEvent_t e0;
     fvv_prof_begin(prof, s, e0);
     hipLaunchKernelGGL(k_desc, dim3((words + 255) / 256), dim3(256), 0, s, (const uint4 *)h_views, (uint4 *)d_views,

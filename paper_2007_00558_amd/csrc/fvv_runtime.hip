@@ -512,6 +512,16 @@ void release_frames(fvv_ctx *c)
     c->latest = -1;
 }
 
+// Per view of a launch: its descriptor and one entry of the network's output
+// table (learned views), both copied to the device by the first kernel.
+constexpr size_t kDescBytes = sizeof(fvv_view_desc) + sizeof(unet_out);
+static_assert(sizeof(unet_out) % 16 == 0, "output tables copy in 16-byte words");
+
+// Learned views of a launch batched through the network: views with one
+// stack size, at most this many pixels per forward (bounds the activation
+// set: about 420 bytes per pixel).
+constexpr size_t kNetBatchPixels = (size_t)8 << 20;
+
 // Grow a workspace (synchronising the device first) so it holds `bytes` of
 // per-view buffers, `tiles` tile counters and `n` view descriptors.
 int32_t ws_reserve(fvv_ctx *c, Workspace &W, size_t bytes, size_t tiles, size_t n)
@@ -543,10 +553,10 @@ int32_t ws_reserve(fvv_ctx *c, Workspace &W, size_t bytes, size_t tiles, size_t 
     }
     if (W.desc_cap < n) {
         HIPCHECK(c, hipDeviceSynchronize());
-        dfree(c, W.d_desc, W.desc_cap * sizeof(fvv_view_desc));
+        dfree(c, W.d_desc, W.desc_cap * kDescBytes);
         W.d_desc = nullptr;
         W.desc_cap = 0;
-        if ((rc = dalloc(c, (void **)&W.d_desc, n * sizeof(fvv_view_desc)))) return rc;
+        if ((rc = dalloc(c, (void **)&W.d_desc, n * kDescBytes))) return rc;
         W.desc_cap = n;
     }
     if (W.h_cap < n) {
@@ -556,7 +566,7 @@ int32_t ws_reserve(fvv_ctx *c, Workspace &W, size_t bytes, size_t tiles, size_t 
             if (W.h_desc[r]) (void)hipHostFree(W.h_desc[r]);
             W.h_desc[r] = nullptr;
             // fine-grained (coherent) so the copy kernel always sees this call's data
-            HIPCHECK(c, hipHostMalloc((void **)&W.h_desc[r], n * sizeof(fvv_view_desc),
+            HIPCHECK(c, hipHostMalloc((void **)&W.h_desc[r], n * kDescBytes,
                                       hipHostMallocMapped | hipHostMallocCoherent));
             HIPCHECK(c, hipHostGetDevicePointer((void **)&W.h_desc_dev[r], W.h_desc[r], 0));
             if (!W.h_ev[r]) HIPCHECK(c, hipEventCreateWithFlags(&W.h_ev[r], hipEventDisableTiming));
@@ -572,7 +582,7 @@ void ws_release(fvv_ctx *c, Workspace &W)
     dfree(c, W.counts, W.counts_cap * 4);
     dfree(c, W.open_list, W.counts_cap * sizeof(int2));
     dfree(c, W.open_count, 256);
-    dfree(c, W.d_desc, W.desc_cap * sizeof(fvv_view_desc));
+    dfree(c, W.d_desc, W.desc_cap * kDescBytes);
     for (int r = 0; r < Workspace::kRing; ++r) {
         if (W.h_desc[r]) (void)hipHostFree(W.h_desc[r]);
         if (W.h_ev[r]) (void)hipEventDestroy(W.h_ev[r]);
@@ -646,7 +656,7 @@ int32_t net_status(fvv_ctx *c, hipError_t e, const std::string &err, const char 
 // Learned-path inputs and outputs of one launch sequence.
 struct LearnedIO {
     unet_act *act = nullptr;           // activation set of the stream (null: the network does not run)
-    uint16_t *stack_out = nullptr;     // caller's stacks [n][stack_h][stack_w][32] (every view learned)
+    uint16_t *stack_out = nullptr;     // caller's stacks [n][stack_h][stack_w][16] (every view learned)
     bool scratch_out = false;          // RGB goes to workspace scratch (stack-only calls)
 };
 
@@ -762,10 +772,34 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
 {
     const bool have_net = lio.act && c->net && unet_loaded(c->net);
     std::vector<char> learned(n_views, 0);
+    for (int v = 0; v < n_views; ++v) learned[v] = lio.stack_out || (have_net && Ps[v].path == FVV_PATH_LEARNED);
+    // network batches: learned views grouped by stack size (first appearance
+    // order, views in call order), split at kNetBatchPixels; each batch's
+    // stacks are contiguous and its output-table entries consecutive
+    struct NetBatch {
+        int H, W;
+        std::vector<int> views;
+    };
+    std::vector<NetBatch> batches;
     size_t net_px = 0;
-    for (int v = 0; v < n_views; ++v) {
-        learned[v] = lio.stack_out || (have_net && Ps[v].path == FVV_PATH_LEARNED);
-        if (learned[v] && !lio.stack_out) net_px = std::max(net_px, stack_w(virts[v].width) * stack_w(virts[v].height));
+    if (!lio.stack_out) {
+        for (int v = 0; v < n_views; ++v) {
+            if (!learned[v]) continue;
+            const int sh = (int)stack_w(virts[v].height), sw = (int)stack_w(virts[v].width);
+            const size_t px = (size_t)sh * sw;
+            NetBatch *b = nullptr;
+            for (auto it = batches.rbegin(); it != batches.rend(); ++it)
+                if (it->H == sh && it->W == sw) {
+                    b = &*it;
+                    break;
+                }
+            if (!b || (b->views.size() + 1) * px > std::max(kNetBatchPixels, px)) {
+                batches.push_back(NetBatch{sh, sw, {}});
+                b = &batches.back();
+            }
+            b->views.push_back(v);
+            net_px = std::max(net_px, b->views.size() * px);
+        }
     }
     std::vector<ViewLayout> lay(n_views);
     std::vector<int> slot_of(n_views);
@@ -857,8 +891,7 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
         if (learned[v]) {
             d.stack_w = (int32_t)stack_w(vc.width);
             d.stack_h = (int32_t)stack_w(vc.height);
-            d.stack = lio.stack_out ? lio.stack_out + (size_t)v * stack_bytes(vc.width, vc.height) / 2
-                                    : (uint16_t *)carve(stack_bytes(vc.width, vc.height));
+            if (lio.stack_out) d.stack = lio.stack_out + (size_t)v * stack_bytes(vc.width, vc.height) / 2;
         }
         if (v == tv) {
             d.dbg_tiles = c->dbg_tiles;
@@ -872,6 +905,21 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
             d.dbg_depth = c->dbg_depth;
         }
     }
+    // network batches: contiguous stacks, output table after the descriptors
+    unet_out *ht = (unet_out *)(hd + n_views);
+    std::vector<int> batch_first;
+    int n_tab = 0;
+    for (const NetBatch &b : batches) {
+        batch_first.push_back(n_tab);
+        const size_t sb = stack_bytes(b.W, b.H);
+        uint8_t *base = cur;
+        cur += align256(sb * b.views.size());
+        for (size_t q = 0; q < b.views.size(); ++q) {
+            fvv_view_desc &d = hd[b.views[q]];
+            d.stack = (uint16_t *)(base + q * sb);
+            ht[n_tab++] = unet_out{d.out, d.out_pitch, d.H, d.W, 0};
+        }
+    }
     bool waited[2] = {false, false};
     for (int v = 0; v < n_views; ++v)
         if (!waited[slot_of[v]]) {
@@ -882,22 +930,22 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
         HIPCHECK(c, hipMemsetAsync(Wk.counts, 0, Wk.counts_cap * 4, s));
         Wk.dirty = false;
     }
-    const hipError_t le = fvv_launch_synthesis(Wk.h_desc_dev[r], Wk.d_desc, dims, s,
+    const hipError_t le = fvv_launch_synthesis(Wk.h_desc_dev[r], Wk.d_desc, dims, n_tab * sizeof(unet_out), s,
                                                c->profiling ? &c->prof : nullptr);
     if (le != hipSuccess) {
         Wk.dirty = true;
         return fail(c, FVV_E_DEVICE, "synthesis launch failed: %s", hipGetErrorString(le));
     }
-    if (net_px) {
+    if (!batches.empty()) {
         fvv_prof *prof = c->profiling ? &c->prof : nullptr;
-        for (int v = 0; v < n_views; ++v) {
-            if (!learned[v]) continue;
-            const fvv_view_desc &d = hd[v];
+        const unet_out *dt = (const unet_out *)(Wk.d_desc + n_views);
+        for (size_t bi = 0; bi < batches.size(); ++bi) {
+            const NetBatch &b = batches[bi];
             std::string err;
             hipEvent_t e0;
             fvv_prof_begin(prof, s, e0);
-            const hipError_t e = unet_forward(c->net, lio.act, d.stack, 1, d.stack_h, d.stack_w, nullptr, d.out,
-                                              d.out_pitch, 0, d.H, d.W, s, err);
+            const hipError_t e = unet_forward_batch(c->net, lio.act, hd[b.views[0]].stack, (int)b.views.size(), b.H,
+                                                    b.W, dt + batch_first[bi], s, err);
             fvv_prof_end(prof, s, FVV_ST_NET, e0);
             if ((rc = net_status(c, e, err, "network forward"))) return rc;
         }
@@ -1655,6 +1703,25 @@ int32_t fvv_synthesize_noalloc(fvv_ctx *c, const fvv_camera *virt, const fvv_syn
                                                    (int32_t *)(base + off_counts), dims, s, nullptr);
     if (le != hipSuccess) return fail(c, FVV_E_DEVICE, "synthesis launch failed: %s", hipGetErrorString(le));
     return note_reader(c, c->slots[si], s);
+}
+
+int32_t fvv_measure_peaks(int32_t hip_device, double *out, int32_t n)
+{
+    if (!out || n < FVV_PEAKS) return fail(nullptr, FVV_E_ARG, "out needs %d entries", FVV_PEAKS);
+    int nd = 0;
+    hipError_t e = hipGetDeviceCount(&nd);
+    if (e != hipSuccess) return fail(nullptr, FVV_E_DEVICE, "hipGetDeviceCount: %s", hipGetErrorString(e));
+    if (hip_device < 0 || hip_device >= nd) return fail(nullptr, FVV_E_ARG, "device %d outside 0..%d", hip_device, nd - 1);
+    DeviceGuard g(hip_device);
+    for (int k = 0; k < FVV_PEAKS; ++k) out[k] = 0.0;
+    std::string err;
+    e = fvv_measure_peaks_impl(out, err);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(nullptr, e == hipErrorOutOfMemory ? FVV_E_NOMEM : FVV_E_DEVICE, "peak measurement%s%s: %s",
+                    err.empty() ? "" : " ", err.c_str(), hipGetErrorString(e));
+    }
+    return FVV_PEAKS;
 }
 
 int32_t fvv_select_cameras(const fvv_camera *rig, const int32_t *present, int32_t n, const fvv_camera *virt,

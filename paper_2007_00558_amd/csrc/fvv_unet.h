@@ -13,8 +13,7 @@
 
 #include <string>
 
-#define UNET_IN 32          // stack channels on the device (16 used, zero padded to 32)
-#define UNET_IN_CANON 16    // stack channels of the network definition
+#define UNET_IN 16          // stack channels on the device (15 used, one zero channel)
 #define UNET_ALIGN 8        // network inputs are padded to multiples of 8 in both dimensions
 
 struct unet_layer {
@@ -52,7 +51,7 @@ hipError_t unet_get_grads(unet_state *n, float *host, hipStream_t s);
 // Make the activation set hold B*H*W pixels (grows only; synchronises the
 // device when it reallocates).
 hipError_t unet_act_reserve(unet_act *a, size_t pixels, bool train);
-// Forward over a stack [B][H][W][32] bf16 (H, W multiples of 8).  Writes
+// Forward over a stack [B][H][W][16] bf16 (H, W multiples of 8).  Writes
 // s = sigmoid output fp32 [B][H][W][3] to s_out if non-null and, if rgb is
 // non-null, RGB8 of the first valid_h rows and valid_w columns of image b at
 // rgb + b * img_stride (pitch bytes per row), for every pixel whose three
@@ -60,6 +59,21 @@ hipError_t unet_act_reserve(unet_act *a, size_t pixels, bool train);
 hipError_t unet_forward(unet_state *n, unet_act *a, const uint16_t *stack, int B, int H, int W, float *s_out,
                            uint8_t *rgb, int64_t pitch, int64_t img_stride, int valid_h, int valid_w,
                            hipStream_t s, std::string &err);
+// RGB8 destination of image b of a batched forward: its first h rows and w
+// columns at rgb, pitch bytes per row (32 bytes, so a table of them copies
+// in 16-byte words).
+struct unet_out {
+    uint8_t *rgb;
+    int64_t pitch;
+    int32_t h, w;
+    int64_t pad;
+};
+// Forward over B stacks of one size with per-image RGB8 destinations
+// (outs: B entries in device memory); pixels whose three outputs are not
+// finite keep what the destination held.  Each image's result is the same
+// for any B (the per-output accumulation order does not depend on the batch).
+hipError_t unet_forward_batch(unet_state *n, unet_act *a, const uint16_t *stack, int B, int H, int W,
+                              const unet_out *outs, hipStream_t s, std::string &err);
 // One training step: forward, L1 loss against target fp32 [B][H][W][3] over
 // rows < valid_h, backward into the gradient; apply != 0 then takes one Adam
 // step with learning rate lr (apply == 0 leaves the parameters unchanged).

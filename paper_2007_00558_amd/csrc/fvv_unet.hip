@@ -45,6 +45,7 @@ struct GemmArgs {
     int o_cs, o_off;
     int NB, H, W;            // column pixels: NB images of H x W
     int K;                   // channels per tap (multiple of 32)
+    int k_src;               // channels Bsrc holds at b_off (0 = K); staged channels beyond are zero
     int M;                   // rows (multiple of 16)
     int cout;                // EPI_CONVT_BF16: output channels (M = 4 cout)
 };
@@ -187,6 +188,7 @@ __global__ void __launch_bounds__(256) k_conv3(const GemmArgs g)
     const int b = t / tiles_y;
     const int x0 = txi * 16, y0 = tyi * TH;
     const int mbase = blockIdx.y * 32 * MT;
+    const int k_src = g.k_src ? g.k_src : g.K;
     const int lc = lane & 31, lh = lane >> 5;
     f32x16 acc[MT][NT];
 #pragma unroll
@@ -202,7 +204,7 @@ __global__ void __launch_bounds__(256) k_conv3(const GemmArgs g)
             const int pr = px / PW, pc = px - pr * PW;
             const int gy = y0 - 1 + pr, gx = x0 - 1 + pc;
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (gy >= 0 && gy < g.H && gx >= 0 && gx < g.W)
+            if (gy >= 0 && gy < g.H && gx >= 0 && gx < g.W && c0 + q * 8 < k_src)
                 v = *(const uint4 *)(g.Bsrc + (((int64_t)b * g.H + gy) * g.W + gx) * g.b_cs + g.b_off + c0 + q * 8);
             *(uint4 *)(patch + px * C3_PXS + q * 16) = v;
         }
@@ -368,6 +370,7 @@ struct WgradArgs {
     float *part;             // [chunks][M][taps*K] fp32 partial sums
     int NB, H, W;            // pixel grid of the contraction (the coarse grid for convT)
     int M, K;                // rows; input channels per tap (multiple of 32)
+    int x_src;               // channels X holds at x_off (0 = K); staged channels beyond are zero
     int chunk;               // pixels per workgroup (multiple of 32)
 };
 
@@ -424,7 +427,8 @@ __global__ void __launch_bounds__(256) k_wgrad(const WgradArgs a)
                 } else {
                     xp = p;
                 }
-                if (xp >= 0) v = *(const uint4 *)(a.X + xp * a.x_cs + a.x_off + cb * 32 + cg * 8);
+                if (xp >= 0 && cb * 32 + cg * 8 < (a.x_src ? a.x_src : a.K))
+                    v = *(const uint4 *)(a.X + xp * a.x_cs + a.x_off + cb * 32 + cg * 8);
             }
             const uint16_t *h = (const uint16_t *)&v;
 #pragma unroll
@@ -485,7 +489,7 @@ __global__ void __launch_bounds__(256) k_wgrad3(const WgradArgs a)
             if (p < p_end) {
                 const int b = p / HW, r = p - b * HW, y = r / a.W, x = r - y * a.W;
                 const int sy = y + t / 3 - 1, sx = x + t % 3 - 1;
-                if (sy >= 0 && sx >= 0 && sy < a.H && sx < a.W)
+                if (sy >= 0 && sx >= 0 && sy < a.H && sx < a.W && cb * 32 + cg * 8 < (a.x_src ? a.x_src : a.K))
                     v = *(const uint4 *)(a.X + (((int64_t)b * a.H + sy) * a.W + sx) * a.x_cs + a.x_off + cb * 32 +
                                          cg * 8);
             }
@@ -662,6 +666,7 @@ struct HeadArgs {
     float *s_out;            // [P][3] or null
     uint8_t *rgb;            // image b at rgb + b * img_stride, or null
     int64_t pitch, img_stride;
+    const unet_out *outs;    // or image b at outs[b] (device table), or null
     int NB, H, W, valid_h, valid_w;
     const float *target;     // [P][3] training
     float inv_n;             // 1 / (NB * valid_h * W * 3)
@@ -699,10 +704,16 @@ __global__ void __launch_bounds__(256) k_head(const HeadArgs h, int mode)
         if (!in) return;
         if (h.s_out)
             for (int c = 0; c < 3; ++c) h.s_out[p * 3 + c] = s[c];
-        if (h.rgb && y < h.valid_h && x < h.valid_w && isfinite(s[0]) && isfinite(s[1]) && isfinite(s[2])) {
-            uint8_t *o = h.rgb + b * h.img_stride + (int64_t)y * h.pitch + (int64_t)x * 3;
-            for (int c = 0; c < 3; ++c) o[c] = (uint8_t)fminf(floorf(s[c] * 255.f + 0.5f), 255.f);
+        const bool fin = isfinite(s[0]) && isfinite(s[1]) && isfinite(s[2]);
+        uint8_t *o = nullptr;
+        if (h.outs) {
+            const unet_out d = h.outs[b];
+            if (y < d.h && x < d.w) o = d.rgb + (int64_t)y * d.pitch + (int64_t)x * 3;
+        } else if (h.rgb && y < h.valid_h && x < h.valid_w) {
+            o = h.rgb + b * h.img_stride + (int64_t)y * h.pitch + (int64_t)x * 3;
         }
+        if (o && fin)
+            for (int c = 0; c < 3; ++c) o[c] = (uint8_t)fminf(floorf(s[c] * 255.f + 0.5f), 255.f);
         return;
     }
     // training
@@ -799,7 +810,7 @@ const struct {
     const char *name;
     int kind, cin, cout;
 } kLayers[] = {
-    {"enc0a", 0, UNET_IN_CANON, 32}, {"enc0b", 0, 32, 32},  {"enc1a", 0, 32, 64},   {"enc1b", 0, 64, 64},
+    {"enc0a", 0, UNET_IN, 32}, {"enc0b", 0, 32, 32},  {"enc1a", 0, 32, 64},   {"enc1b", 0, 64, 64},
     {"enc2a", 0, 64, 128},              {"enc2b", 0, 128, 128}, {"mid_a", 0, 128, 256}, {"mid_b", 0, 256, 256},
     {"up2", 1, 256, 128},               {"dec2a", 0, 256, 128}, {"dec2b", 0, 128, 128}, {"up1", 1, 128, 64},
     {"dec1a", 0, 128, 64},              {"dec1b", 0, 64, 64},   {"up0", 1, 64, 32},     {"dec0a", 0, 64, 32},
@@ -1092,6 +1103,7 @@ hipError_t conv_fwd(unet_state *n, int li, const uint16_t *in, int i_cs, int i_o
     g.H = H;
     g.W = W;
     g.K = l.cin_pad;
+    g.k_src = std::min(i_cs - i_off, l.cin_pad);
     g.M = l.cout;
     return conv3<EPI_RELU_BF16>(g, s);
 }
@@ -1198,6 +1210,7 @@ hipError_t wgrad(unet_state *n, unet_act *a, int li, const uint16_t *X, int x_cs
     w.W = W;
     w.M = l.cout;
     w.K = l.cin_pad;
+    w.x_src = l.cin;
     w.chunk = chunk;
     constexpr int taps = TAP == TAP_CONV3 ? 9 : (TAP == TAP_FINE4 ? 4 : 1);
     if (TAP == TAP_CONV3) {
@@ -1373,6 +1386,32 @@ hipError_t unet_forward(unet_state *n, unet_act *a, const uint16_t *stack, int N
     h.W = W;
     h.valid_h = valid_h;
     h.valid_w = valid_w;
+    const int P = NB * H * W;
+    hipLaunchKernelGGL(k_head, dim3((P + 255) / 256), dim3(256), 0, s, h, 0);
+    return hipGetLastError();
+}
+
+hipError_t unet_forward_batch(unet_state *n, unet_act *a, const uint16_t *stack, int NB, int H, int W,
+                              const unet_out *outs, hipStream_t s, std::string &err)
+{
+    if (!n->loaded) {
+        err = "no network parameters loaded";
+        return hipErrorInvalidValue;
+    }
+    if (!outs || !geometry_ok(a, NB, H, W)) {
+        err = "network input must be a multiple of 8 in both dimensions and fit the activation set";
+        return hipErrorInvalidValue;
+    }
+    NCHK(forward_all(n, a, stack, NB, H, W, s));
+    const unet_layer &hl = layers().L[L_HEAD];
+    HeadArgs h{};
+    h.a = a->d0b;
+    h.w = n->wf + hl.wf_off;
+    h.bias = n->w + hl.b_off;
+    h.outs = outs;
+    h.NB = NB;
+    h.H = H;
+    h.W = W;
     const int P = NB * H * W;
     hipLaunchKernelGGL(k_head, dim3((P + 255) / 256), dim3(256), 0, s, h, 0);
     return hipGetLastError();

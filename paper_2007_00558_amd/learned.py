@@ -22,7 +22,7 @@ import numpy as np
 
 import scenegen as sg
 
-from . import (MEM_DEVICE, NET_ALIGN, PATH_LEARNED, PATH_PLAIN, Context, net_layers, net_param_count,
+from . import (MEM_DEVICE, NET_ALIGN, NET_IN, PATH_LEARNED, PATH_PLAIN, Context, net_layers, net_param_count,
                pad8, params)
 
 ANGLES = [-60.0 + 15.0 * k for k in range(9)]
@@ -75,7 +75,7 @@ class SceneSet:
         self.ps = [params(exclude=(j,)) for j in range(len(self.cams))]
         self.Hp, self.Wp = pad8(OUT_H), pad8(OUT_W)
         n = len(self.views)
-        self.stack = torch.empty((n, self.Hp, self.Wp, 32), dtype=torch.int16, device=device)
+        self.stack = torch.empty((n, self.Hp, self.Wp, NET_IN), dtype=torch.int16, device=device)
         ctx.make_stack(self.views, self.ps, self.stack)
         self.target8 = torch.zeros((n, self.Hp, self.Wp, 3), dtype=torch.uint8, device=device)
         for j, v in enumerate(self.views):

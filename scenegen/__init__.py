@@ -33,7 +33,7 @@ import numpy as np
 __all__ = [
     "Camera", "look_at", "arc_camera", "Scene", "Frame", "Workload",
     "random_scene", "config1", "config2", "config3", "config_small",
-    "swing_trajectory", "BG_MM", "capture_layered", "background_model", "background_scene",
+    "swing_trajectory", "moving_scenes", "BG_MM", "capture_layered", "background_model", "background_scene",
 ]
 
 
@@ -293,6 +293,29 @@ def random_scene(rng: np.random.Generator, n_spheres=3, n_boxes=3, radius=0.8,
         c = np.array([rad * math.cos(ang), ground_y + half[1], rad * math.sin(ang)])
         box.append((c, half, rng.uniform(0, math.pi), rng.uniform(0.3, 1.0, 3)))
     return Scene(ground_y=ground_y, backdrop_radius=backdrop, spheres=sph, boxes=box, salt=salt)
+
+
+def moving_scenes(scene: Scene, n_frames: int, amplitude: float = 0.15, period_frames: int = 30) -> List[Scene]:
+    """A dynamic sequence of ``scene``: every sphere moves on a horizontal
+    circle of radius ``amplitude`` metres through its starting point, with a
+    small vertical bob (kept above the ground), one revolution every
+    ``period_frames`` frames, so a sequence of that many frames loops without
+    a jump; boxes and the background stay put.  Frame 0 is ``scene``."""
+    out = []
+    n = max(1, len(scene.spheres))
+    for f in range(n_frames):
+        a = 2.0 * math.pi * f / period_frames
+        sph = []
+        for k, (c0, r, col) in enumerate(scene.spheres):
+            ph = 2.0 * math.pi * k / n
+            d = amplitude * np.array([math.cos(a + ph) - math.cos(ph), 0.3 * math.sin(2.0 * a),
+                                      math.sin(a + ph) - math.sin(ph)])
+            c = np.asarray(c0, np.float64) + d
+            if scene.ground_y is not None:
+                c[1] = max(c[1], scene.ground_y + r)
+            sph.append((c, r, col))
+        out.append(replace(scene, spheres=sph))
+    return out
 
 
 # --------------------------------------------------------------------------

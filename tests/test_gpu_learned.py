@@ -79,11 +79,10 @@ def bf16_bits(x):
 
 
 def to_device_stack(st16):
-    """(N, H, W, 16) float64 -> device int16 tensor (N, H, W, 32) of bfloat16 bits."""
+    """(N, H, W, 16) float64 -> device int16 tensor (N, H, W, 16) of bfloat16 bits."""
     import torch
     N, H, W, _ = st16.shape
-    full = np.zeros((N, H, W, 32), np.uint16)
-    full[..., :16] = bf16_bits(st16)
+    full = bf16_bits(st16)
     return torch.from_numpy(full.view(np.int16)).cuda()
 
 
@@ -105,7 +104,7 @@ def test_stack_matches_oracle(fvv, ctx, oracle_lib, seed, W, H, exclude):
     ctx.upload_mvd(w.frames)
     views = w.virtual[:2]
     Hp, Wp = fvv.pad8(H), fvv.pad8(W)
-    st = torch.full((len(views), Hp, Wp, 32), 0x7F7F, dtype=torch.int16, device="cuda")
+    st = torch.full((len(views), Hp, Wp, 16), 0x7F7F, dtype=torch.int16, device="cuda")
     ctx.make_stack(views, [fvv.params(exclude=exclude)] * len(views), st)
     torch.cuda.synchronize()
     got = st.cpu().numpy().view(np.uint16)
@@ -116,7 +115,7 @@ def test_stack_matches_oracle(fvv, ctx, oracle_lib, seed, W, H, exclude):
         ref = oracle_lib.stack(r["zf"], w.rig, frames, v, r["sel"], r["weights"], 0.05, Hp - H, Wp - W)
         rb = bf16_bits(ref)
         g = got[q]
-        assert np.all(g[..., 16:] == 0) and np.all(g[..., 15] == 0)
+        assert g.shape[-1] == 16 and np.all(g[..., 15] == 0)
         K = len(r["sel"])
         for k in range(3):
             sl = slice(5 * k, 5 * k + 5)
@@ -205,6 +204,45 @@ def test_learned_batch_equals_single_and_plain_without_net(fvv, oracle_lib):
         assert np.array_equal(a, o.cpu().numpy())
     assert any(not np.array_equal(a, b) for a, b in zip(single, plain))
     c.close()
+
+
+def test_network_batch_invariance(fvv, ctx, oracle_lib):
+    """The network's output for an image does not depend on the batch it
+    runs in: stacks forwarded one at a time and four at a time give the same
+    bits, and learned views of two sizes rendered in one call (batched by
+    size through the network) equal the views rendered alone."""
+    import torch
+    H, W = 64, 96
+    ctx.net_load(flat(rand_params(90)))
+    st = np.stack([scene_stack(oracle_lib, 91 + q, W, H) for q in range(4)])
+    dst = to_device_stack(st)
+    four = torch.empty((4, H, W, 3), dtype=torch.float32, device="cuda")
+    ctx.net_forward(dst, 4, H, W, four)
+    ones = []
+    for q in range(4):
+        o = torch.empty((1, H, W, 3), dtype=torch.float32, device="cuda")
+        ctx.net_forward(dst[q:q + 1].contiguous(), 1, H, W, o)
+        ones.append(o)
+    torch.cuda.synchronize()
+    for q in range(4):
+        assert torch.equal(four[q], ones[q][0]), q
+    w = sg.config_small(92, n_cams=4, out_w=96, out_h=64)
+    ctx.set_rig(w.rig)
+    ctx.upload_mvd(w.frames)
+    views = [sg.arc_camera(a, 2.2, *((96, 64) if q % 2 else (130, 77))) for q, a in
+             enumerate(np.linspace(-12, 12, 7))]
+    p = fvv.params(path=fvv.PATH_LEARNED)
+    alone = [ctx.synthesize(v, p=p) for v in views]
+    outs = [torch.zeros((v.height, v.width, 3), dtype=torch.uint8, device="cuda") for v in views]
+    ctx.set_profiling(True)
+    ctx.profile(reset=True)
+    ctx.synthesize_batch(views, outs, p=p)
+    torch.cuda.synchronize()
+    prof = ctx.profile(reset=True)
+    ctx.set_profiling(False)
+    assert prof["net"][1] == 2, prof["net"]     # one forward per stack size
+    for a, o in zip(alone, outs):
+        assert np.array_equal(a, o.cpu().numpy())
 
 
 # ------------------------------------------------------------------ training
@@ -296,7 +334,7 @@ def test_learned_errors(fvv):
         c.net_load(np.zeros(10, np.float32))
     assert e.value.code == fvv.FVV_E_ARG
     c.net_load(np.zeros(fvv.net_param_count(), np.float32))
-    st = torch.zeros((1, 12, 16, 32), dtype=torch.int16, device="cuda")
+    st = torch.zeros((1, 12, 16, 16), dtype=torch.int16, device="cuda")
     out = torch.zeros((1, 12, 16, 3), device="cuda")
     with pytest.raises(fvv.FvvError) as e:
         c.net_forward(st, 1, 12, 16, out)    # 12 is not a multiple of 8

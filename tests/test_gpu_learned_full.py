@@ -81,9 +81,8 @@ def unflat(v):
 def to_device_stack(st16):
     import torch
     N, H, W, _ = st16.shape
-    full = np.zeros((N, H, W, 32), np.uint16)
-    full[..., :16] = torch.from_numpy(np.asarray(st16, np.float32)).to(torch.bfloat16).view(
-        torch.int16).numpy().view(np.uint16)
+    full = torch.from_numpy(np.asarray(st16, np.float32)).to(torch.bfloat16).view(torch.int16).numpy().view(
+        np.uint16)
     return torch.from_numpy(full.view(np.int16)).cuda()
 
 

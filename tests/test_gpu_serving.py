@@ -260,3 +260,62 @@ def test_layered_requests_in_mix_equal_alone(fvv):
     for a, o in zip(alone, outs):
         assert np.array_equal(a, o.cpu().numpy())
     ctx.close()
+
+
+def test_moving_scene_refreshes_mix_equals_alone(fvv):
+    """A moving scene refreshed while the server runs: each round uploads the
+    next frame set and submits plain and learned requests naming the new
+    version and the previous one (still resident), while requests of the
+    previous round may still be in flight; every result equals the same
+    request rendered alone on that frame set (bit-exact)."""
+    import torch
+    from paper_2007_00558_amd import learned as L
+    say("[gpu] serving across refreshes of a moving scene")
+    rng = np.random.default_rng(18)
+    base = sg.random_scene(rng, n_spheres=4, n_boxes=2, salt=18)
+    rig = [sg.arc_camera(a, 2.2, 120, 80) for a in (-15.0, 0.0, 15.0, 30.0)]
+    n_frames = 6
+    seq = [[sg.capture(s, c, 18, k, noise_k=0.002, invalid_frac=0.05) for k, c in enumerate(rig)]
+           for s in sg.moving_scenes(base, n_frames, amplitude=0.2, period_frames=n_frames)]
+    views = _mixed_views(None, 12, 6)
+    paths = [fvv.PATH_LEARNED if q % 3 == 1 else fvv.PATH_PLAIN for q in range(len(views))]
+    params = L.init_params(5)
+    # references: every view alone on every frame set
+    ref_ctx = fvv.Context(0)
+    ref_ctx.set_rig(rig)
+    ref_ctx.net_load(params)
+    ref = []
+    for fr in seq:
+        ref_ctx.upload_mvd(fr)
+        ref.append([ref_ctx.synthesize(v, p=fvv.params(path=pa)) for v, pa in zip(views, paths)])
+    ref_ctx.close()
+    assert not np.array_equal(ref[0][0], ref[n_frames // 2][0]), "the scene should move"
+    ctx = fvv.Context(0)
+    ctx.set_rig(rig)
+    ctx.net_load(params)
+    srv = fvv.Server(ctx, max_slots=6)
+    results = []          # (frame, view, output)
+    carry = []
+    ver = []
+    for k, fr in enumerate(seq):
+        ver.append(ctx.upload_mvd(fr))
+        cur, prev = [], []
+        for q, (v, pa) in enumerate(zip(views, paths)):
+            f = k if (q % 2 == 0 or k == 0) else k - 1
+            o = torch.zeros((v.height, v.width, 3), dtype=torch.uint8, device="cuda")
+            torch.cuda.synchronize()
+            t = srv.submit(v, o, fvv.params(path=pa, frame_version=ver[f]))
+            results.append((f, q, o))
+            (cur if f == k else prev).append(t)
+        # requests naming the previous version finish before the next
+        # upload evicts it; this round's requests may overlap that upload
+        _wait(srv, carry + prev)
+        carry = cur
+    _wait(srv, carry)
+    st = srv.stats()
+    srv.stop()
+    torch.cuda.synchronize()
+    assert st["failed"] == 0
+    for f, q, o in results:
+        assert np.array_equal(ref[f][q], o.cpu().numpy()), (f, q)
+    ctx.close()

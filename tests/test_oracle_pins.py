@@ -600,3 +600,14 @@ def test_stack_recombines_to_the_blend(oracle_lib, seed):
         mix = np.clip(np.floor(num[ok] / den[ok] + 0.5), 0, 255)
         diff = np.abs(mix - r["blend_rgb"][ok].astype(np.float64))
         assert diff.max() <= 1 and np.mean(diff > 0) < 1e-3
+
+
+def test_timing_mode_equals_parity_mode(oracle_lib):
+    """The benchmark's multi-threaded timing mode (views spread over OpenMP
+    threads) returns, view by view, exactly the single-threaded result."""
+    o = oracle_lib
+    w = sg.config_small(4, n_cams=4, w=96, h=64, out_w=120, out_h=72, n_virtual=6)
+    many = o.synthesize_views(w.rig, w.frames, w.virtual, 4)
+    for v, got in zip(w.virtual, many):
+        assert np.array_equal(got, o.synthesize(w.rig, w.frames, v)["rgb"])
+
