@@ -42,6 +42,7 @@ struct fvv_src_desc {
     float wgt;              // view weight, 1 / centre distance
     float A[9], a[3], B[9], b[3];
     float sx, sy;           // focal ratios virtual / source (footprint scale)
+    float umax, vmax;       // W - 0.5, H - 0.5: last sample coordinates on the image (exact in float32)
 };
 
 // One virtual view of a batched synthesis call.

@@ -373,24 +373,41 @@ __device__ __forceinline__ unsigned long long lower_median8(unsigned long long v
 }
 #undef CSWAP
 
-// Crack fill (empty key, >= 5 valid neighbours) and speckle removal (valid
-// key, >= 5 valid neighbours, none within tau z0) take the lower median.
-__device__ __forceinline__ unsigned long long filter_key(unsigned long long c, unsigned long long v[8], float tau)
+__device__ __forceinline__ int valid_count(const unsigned long long v[8])
 {
     int n = 0;
 #pragma unroll
     for (int e = 0; e < 8; ++e) n += v[e] != FVV_KEY_EMPTY;
-    if (n < 5) return c;
-    if (c != FVV_KEY_EMPTY) {
-        const float z0 = u2f((uint32_t)(c >> 32));
-        const float lim = __fmul_rn(tau, z0);
-        bool near = false;
+    return n;
+}
+
+// Crack fill (empty key, >= 5 valid neighbours) and speckle removal (valid
+// key, >= 5 valid neighbours, none within tau z0) take the lower median of
+// the valid neighbours; every other pixel keeps its key.
+__device__ __forceinline__ bool filter_needs_median(unsigned long long c, const unsigned long long v[8], float tau)
+{
+    // an empty key's depth word is all ones, a valid key's is the bit
+    // pattern of a positive float (sign bit clear): the sign bits count the
+    // empty neighbours
+    uint32_t empty = 0;
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
-            if (fabsf(__fsub_rn(u2f((uint32_t)(v[e] >> 32)), z0)) <= lim) near = true;   // empty: NaN, false
-        if (near) return c;
-    }
-    return lower_median8(v, n);
+    for (int e = 0; e < 8; ++e) empty += (uint32_t)(v[e] >> 63);
+    if (empty > 3) return false;   // fewer than five valid neighbours
+    if (c == FVV_KEY_EMPTY) return true;
+    const float z0 = u2f((uint32_t)(c >> 32));
+    const float lim = __fmul_rn(tau, z0);
+    // a neighbour within tau: the smallest |z_k - z0| is <= lim (an empty
+    // neighbour's depth is a NaN, which the minimum passes over; all NaN
+    // compares false)
+    float d = fabsf(__fsub_rn(u2f((uint32_t)(v[0] >> 32)), z0));
+#pragma unroll
+    for (int e = 1; e < 8; ++e) d = fminf(d, fabsf(__fsub_rn(u2f((uint32_t)(v[e] >> 32)), z0)));
+    return !(d <= lim);
+}
+
+__device__ __forceinline__ unsigned long long filter_key(unsigned long long c, unsigned long long v[8], float tau)
+{
+    return filter_needs_median(c, v, tau) ? lower_median8(v, valid_count(v)) : c;
 }
 
 // ---------------------------------------------------------------- blend
@@ -412,8 +429,8 @@ __device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int k0, int
         if (!(q2 > FVV_ZCLIP)) continue;
         const float r = __fdiv_rn(1.0f, q2);
         const float u = div_by(q0, q2, r), v = div_by(q1, q2, r);
-        if (!(u >= -0.5f && u <= __fsub_rn((float)s.W, 0.5f))) continue;
-        if (!(v >= -0.5f && v <= __fsub_rn((float)s.H, 0.5f))) continue;
+        if (!(u >= -0.5f && u <= s.umax)) continue;
+        if (!(v >= -0.5f && v <= s.vmax)) continue;
         const float fi0 = floorf(u), fj0 = floorf(v);
         const float fu = __fsub_rn(u, fi0), fv = __fsub_rn(v, fj0);
         const int i0 = (int)fi0, j0 = (int)fj0;
@@ -429,7 +446,8 @@ __device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int k0, int
         const int ic[2] = {max(i0, 0), min(i0 + 1, s.W - 1)};
         // 32-bit texel indices (a source has < 2^27 pixels): a uniform base
         // plus a 32-bit offset needs no 64-bit address arithmetic
-        const uint32_t jr[2] = {(uint32_t)(max(j0, 0) * s.W), (uint32_t)(min(j0 + 1, s.H - 1) * s.W)};
+        const uint32_t jr[2] = {(uint32_t)__umul24((uint32_t)max(j0, 0), (uint32_t)s.W),
+                                (uint32_t)__umul24((uint32_t)min(j0 + 1, s.H - 1), (uint32_t)s.W)};
         const gmem<unsigned long long> *tex = gptr((const unsigned long long *)s.texel);
         uint2 tx[4];
 #pragma unroll
@@ -485,8 +503,8 @@ __device__ __forceinline__ void stack_pixel(const fvv_view_desc &vd, int x, int 
             if (!(q2 > FVV_ZCLIP)) continue;
             const float r = __fdiv_rn(1.0f, q2);
             const float u = div_by(q0, q2, r), v = div_by(q1, q2, r);
-            if (!(u >= -0.5f && u <= __fsub_rn((float)s.W, 0.5f))) continue;
-            if (!(v >= -0.5f && v <= __fsub_rn((float)s.H, 0.5f))) continue;
+            if (!(u >= -0.5f && u <= s.umax)) continue;
+            if (!(v >= -0.5f && v <= s.vmax)) continue;
             const float fi0 = floorf(u), fj0 = floorf(v);
             const float fu = __fsub_rn(u, fi0), fv = __fsub_rn(v, fj0);
             const int i0 = (int)fi0, j0 = (int)fj0;
@@ -579,15 +597,22 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
     // first and the background layer in the second
     constexpr int NZ = LAYERED ? 2 * WN * WN : WN * WN;
     __shared__ unsigned long long zk[NZ];
-    __shared__ uint32_t s_slot[T * T];
-    __shared__ uint32_t s_rgb[T * T];
-    __shared__ int s_open, s_hole;
+    // the tile's filtered keys during the filter, then its slots and colours
+    __shared__ unsigned long long s_buf[T * T];
+    uint32_t *const s_slot = (uint32_t *)s_buf;
+    uint32_t *const s_rgb = s_slot + T * T;
+    unsigned long long *const s_kf = s_buf;
+    // pixels whose filtered key is a median (the two-window variant filters
+    // in place: its LDS budget has no room for the list)
+    __shared__ uint16_t s_med[LAYERED ? 2 : T * T];
+    __shared__ int s_open, s_hole, s_nmed;
     const int t = threadIdx.x;
     const int n_entries = vd.counts[tile];
     for (int e = t; e < NZ; e += TNT) zk[e] = FVV_KEY_EMPTY;
     if (t == 0) {
         s_open = 0;
         s_hole = 0;
+        s_nmed = 0;
     }
     __syncthreads();
 
@@ -693,24 +718,64 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
     }
     __syncthreads();
 
-    // ---- S2 + S3: filter and blend four horizontally adjacent pixels
+    // ---- S2: 3x3 filter of four horizontally adjacent pixels per thread.
+    // Most pixels keep their key (fewer than five valid neighbours, or a
+    // neighbour within tau); only the rest need the lower median, whose
+    // sorting network a wave would otherwise run whenever one of its lanes
+    // needs it.  Those pixels are listed and the list is spread over every
+    // thread of the tile.
     const int ly = t / TPR, lx0 = (t % TPR) * 4;
     const int y = Y0 + ly;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int x = X0 + lx0 + q;
+        unsigned long long kf = FVV_KEY_EMPTY;
+        bool need = false;
+        if (x < W && y < H) {
+            const unsigned long long *w3 = zk + ly * WN + lx0 + q;
+            const unsigned long long c = w3[WN + 1];
+            unsigned long long nb[8] = {w3[0], w3[1], w3[2], w3[WN], w3[WN + 2], w3[2 * WN], w3[2 * WN + 1],
+                                        w3[2 * WN + 2]};
+            if (LAYERED) {
+                kf = filter_key(c, nb, vd.tau);
+            } else {
+                kf = c;
+                need = filter_needs_median(c, nb, vd.tau);
+            }
+        }
+        s_kf[ly * T + lx0 + q] = kf;
+        const unsigned long long m = __ballot(need);
+        if (m) {
+            int base = 0;
+            if (lane == 0) base = atomicAdd(&s_nmed, __popcll(m));
+            base = __builtin_amdgcn_readfirstlane(base);   // every lane is active here: lane 0's value
+            const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0));
+            if (need) s_med[base + rank] = (uint16_t)(ly * T + lx0 + q);
+        }
+    }
+    __syncthreads();
+    for (int e = t; e < s_nmed; e += TNT) {
+        const int pix = s_med[e];
+        const unsigned long long *w3 = zk + (pix / T) * WN + (pix % T);
+        unsigned long long nb[8] = {w3[0], w3[1], w3[2], w3[WN], w3[WN + 2], w3[2 * WN], w3[2 * WN + 1],
+                                    w3[2 * WN + 2]};
+        s_kf[pix] = lower_median8(nb, valid_count(nb));
+    }
+    __syncthreads();
+    unsigned long long kfs[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) kfs[q] = s_kf[ly * T + lx0 + q];
+    __syncthreads();   // the key buffer becomes the slot and colour buffers
+
+    // ---- S3: backward fetch and blend
     uint32_t pslot[4], prgb[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int x = X0 + lx0 + q;
         pslot[q] = FVV_HOLE;
         prgb[q] = 0;
-        unsigned long long kf = FVV_KEY_EMPTY;
+        const unsigned long long kf = kfs[q];
         if (x < W && y < H) {
-            // the pixel's 3x3 window, read from LDS per pixel (holding the
-            // 3x6 window of all four would cost 36 registers)
-            const unsigned long long *w3 = zk + ly * WN + lx0 + q;
-            const unsigned long long c = w3[WN + 1];
-            unsigned long long nb[8] = {w3[0], w3[1], w3[2], w3[WN], w3[WN + 2], w3[2 * WN], w3[2 * WN + 1],
-                                        w3[2 * WN + 2]};
-            kf = filter_key(c, nb, vd.tau);
             if (kf != FVV_KEY_EMPTY) {
                 const float zf = u2f((uint32_t)(kf >> 32));
                 uint32_t col;
@@ -744,7 +809,7 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
                     }
                 }
             }
-            if (vd.dbg_z) vd.dbg_z[o] = c;
+            if (vd.dbg_z) vd.dbg_z[o] = zk[(ly + 1) * WN + lx0 + q + 1];
             if (vd.dbg_zf) vd.dbg_zf[o] = kf;
             if (vd.dbg_rgba) vd.dbg_rgba[o] = prgb[q];
             if (vd.dbg_depth) vd.dbg_depth[o] = (pslot[q] & FVV_HOLE) ? 0.0f : u2f(pslot[q]);

@@ -55,6 +55,7 @@ struct FrameSlot {
     bool layered = false;                 // holds background layers
     std::vector<int32_t> present;
     hipEvent_t ready = nullptr;           // recorded after the repack
+    hipStream_t ready_stream = nullptr;   // the stream it was recorded on
     std::vector<std::pair<hipStream_t, hipEvent_t>> readers;
 };
 
@@ -750,6 +751,8 @@ void fill_desc(fvv_ctx *c, fvv_view_desc &d, const fvv_camera &vc, const ViewLay
         pair_dir(vc, sc, sd.B, sd.b);
         sd.sx = (float)((double)vc.fx / (double)sc.fx);
         sd.sy = (float)((double)vc.fy / (double)sc.fy);
+        sd.umax = (float)sc.width - 0.5f;
+        sd.vmax = (float)sc.height - 0.5f;
         if (d.layered) {
             // the camera's background layer: same geometry and weight
             fvv_src_desc &bd = d.src[L.K + k];
@@ -923,7 +926,9 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
     bool waited[2] = {false, false};
     for (int v = 0; v < n_views; ++v)
         if (!waited[slot_of[v]]) {
-            HIPCHECK(c, hipStreamWaitEvent(s, c->slots[slot_of[v]].ready, 0));
+            // a stream's own earlier work is ordered already
+            if (c->slots[slot_of[v]].ready_stream != s)
+                HIPCHECK(c, hipStreamWaitEvent(s, c->slots[slot_of[v]].ready, 0));
             waited[slot_of[v]] = true;
         }
     if (Wk.dirty) {
@@ -1415,7 +1420,8 @@ int32_t fvv_upload_mvd(fvv_ctx *c, const fvv_view *views, int32_t n, int32_t mem
     }
     if (!c->staging_free) HIPCHECK(c, hipEventCreateWithFlags(&c->staging_free, hipEventDisableTiming));
     else if (host) HIPCHECK(c, hipStreamWaitEvent(s, c->staging_free, 0));
-    for (auto &r : fs.readers) HIPCHECK(c, hipStreamWaitEvent(s, r.second, 0));
+    for (auto &r : fs.readers)
+        if (r.first != s) HIPCHECK(c, hipStreamWaitEvent(s, r.second, 0));
     // device memory is read in place by the repack kernel; host memory is
     // first copied into the staging buffer, with blocking copies from the
     // caller's pageable memory once the stream is idle
@@ -1483,6 +1489,7 @@ int32_t fvv_upload_mvd(fvv_ctx *c, const fvv_view *views, int32_t n, int32_t mem
     HIPCHECK(c, fvv_launch_repack(b, max_w, max_h, s, c->profiling ? &c->prof : nullptr));
     if (host) HIPCHECK(c, hipEventRecord(c->staging_free, s));
     HIPCHECK(c, hipEventRecord(fs.ready, s));
+    fs.ready_stream = s;
     if (mem_kind == FVV_MEM_HOST) HIPCHECK(c, hipStreamSynchronize(s));
     fs.version = c->next_version++;
     c->latest = dst;
@@ -1698,7 +1705,7 @@ int32_t fvv_synthesize_noalloc(fvv_ctx *c, const fvv_camera *virt, const fvv_syn
     const fvv_batch_dims dims{1, L.nsrc, L.blk_stride, L.ntx, L.nty, L.n_tiles, P.fill_mode == FVV_FILL_BG, false,
                               P.path == FVV_PATH_LAYERED};
     const hipStream_t s = (hipStream_t)stream;
-    HIPCHECK(c, hipStreamWaitEvent(s, c->slots[si].ready, 0));
+    if (c->slots[si].ready_stream != s) HIPCHECK(c, hipStreamWaitEvent(s, c->slots[si].ready, 0));
     const hipError_t le = fvv_launch_synthesis_one(d, (fvv_view_desc *)(base + off_desc),
                                                    (int32_t *)(base + off_counts), dims, s, nullptr);
     if (le != hipSuccess) return fail(c, FVV_E_DEVICE, "synthesis launch failed: %s", hipGetErrorString(le));
