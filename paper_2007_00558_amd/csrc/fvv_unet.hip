@@ -197,26 +197,62 @@ __global__ void __launch_bounds__(256) k_conv3(const GemmArgs g)
         for (int n = 0; n < NT; ++n)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[i][n][r] = 0.f;
-    for (int c0 = 0; c0 < g.K; c0 += 32) {
-        // stage the input patch: PH x PW pixels x 4 quarters of 8 channels
-        for (int e = tid; e < PH * PW * 4; e += 256) {
-            const int px = e >> 2, q = e & 3;
-            const int pr = px / PW, pc = px - pr * PW;
-            const int gy = y0 - 1 + pr, gx = x0 - 1 + pc;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (gy >= 0 && gy < g.H && gx >= 0 && gx < g.W && c0 + q * 8 < k_src)
-                v = *(const uint4 *)(g.Bsrc + (((int64_t)b * g.H + gy) * g.W + gx) * g.b_cs + g.b_off + c0 + q * 8);
-            *(uint4 *)(patch + px * C3_PXS + q * 16) = v;
+    // Software pipeline over the 32-channel chunks: the next chunk's input
+    // patch (PH x PW pixels x 4 quarters of 8 channels) and weight slice
+    // (32*MT rows x 9 taps x 4 quarters) are fetched into registers while
+    // the current chunk's MFMAs run, then stored to LDS.
+    constexpr int NPF = (PH * PW * 4 + 255) / 256, NWF = (32 * MT * 36 + 255) / 256;
+    uint4 fp[NPF], fw[NWF];
+    // this thread's patch elements: 32-bit element offsets of their chunk-0
+    // channels (-1 outside the image); every element of a thread has the
+    // same quarter q = tid & 3
+    int32_t poff[NPF];
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) {
+        const int e = tid + k * 256;
+        const int px = e >> 2, pr = px / PW, pc = px - pr * PW;
+        const int gy = y0 - 1 + pr, gx = x0 - 1 + pc;
+        poff[k] = (e < PH * PW * 4 && gy >= 0 && gy < g.H && gx >= 0 && gx < g.W)
+                      ? ((b * g.H + gy) * g.W + gx) * g.b_cs + g.b_off + (tid & 3) * 8
+                      : -1;
+    }
+    // weights are stored chunk-major ([K/32][M][9][32]): a chunk's slice for
+    // this block's rows is one contiguous run, element e of it at 8 e
+    const uint16_t *wrows = g.A + (int64_t)mbase * 288;
+    auto fetch = [&](int c0) {
+        const bool qin = c0 + (tid & 3) * 8 < k_src;
+#pragma unroll
+        for (int k = 0; k < NPF; ++k) {
+            fp[k] = make_uint4(0, 0, 0, 0);
+            if (poff[k] >= 0 && qin) fp[k] = *(const uint4 *)(g.Bsrc + (uint32_t)(poff[k] + c0));
         }
-        // stage the weights: 32*MT rows x 9 taps x 4 quarters
-        for (int e = tid; e < 32 * MT * 36; e += 256) {
+        const uint16_t *wc = wrows + (int64_t)(c0 >> 5) * g.M * 288;
+#pragma unroll
+        for (int k = 0; k < NWF; ++k) {
+            const int e = tid + k * 256;
+            fw[k] = make_uint4(0, 0, 0, 0);
+            if (e < 32 * MT * 36 && mbase + e / 36 < g.M) fw[k] = *(const uint4 *)(wc + (uint32_t)e * 8);
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int k = 0; k < NPF; ++k) {
+            const int e = tid + k * 256;
+            if (e < PH * PW * 4) *(uint4 *)(patch + (e >> 2) * C3_PXS + (e & 3) * 16) = fp[k];
+        }
+#pragma unroll
+        for (int k = 0; k < NWF; ++k) {
+            const int e = tid + k * 256;
             const int r = e / 36, rem = e - r * 36, tap = rem >> 2, q = rem & 3;
-            const int m = mbase + r;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (m < g.M) v = *(const uint4 *)(g.A + ((int64_t)m * 9 + tap) * g.K + c0 + q * 8);
-            *(uint4 *)(wts + r * C3_RS + tap * 64 + q * 16) = v;
+            if (e < 32 * MT * 36) *(uint4 *)(wts + r * C3_RS + tap * 64 + q * 16) = fw[k];
         }
-        __syncthreads();
+    };
+    fetch(0);
+    stash();
+    __syncthreads();
+    for (int c0 = 0; c0 < g.K; c0 += 32) {
+        const bool more = c0 + 32 < g.K;
+        if (more) fetch(c0 + 32);
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int dy = tap / 3, dx = tap - dy * 3;
@@ -240,7 +276,11 @@ __global__ void __launch_bounds__(256) k_conv3(const GemmArgs g)
                         acc[i][n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i], bfr[n], acc[i][n], 0, 0, 0);
             }
         }
-        __syncthreads();
+        if (more) {
+            __syncthreads();   // every wave is done with this chunk
+            stash();
+            __syncthreads();
+        }
     }
     // epilogue: lane holds, for pixel lc of each tile, channels
     // 8*j + 4*lh + {0..3} (j = 0..3) of each 32-row tile
@@ -764,8 +804,11 @@ __global__ void __launch_bounds__(256) k_head(const HeadArgs h, int mode)
 }
 
 // Adam on the fp32 master parameters of one layer, and the bf16 copies in
-// the forward layout ([rows][taps][cin_pad]) and the data-gradient layout
-// ([cin][taps][cout], taps mirrored for 3x3).
+// the forward layout and the data-gradient layout (taps mirrored for 3x3):
+// 3x3 convolutions chunk-major, [cin_pad/32][cout][9][32] and
+// [cout/32][cin][9][32], so one 32-channel chunk of a block's rows is one
+// contiguous run; transposed convolutions [tap][cout][cin] and
+// [cin][tap][cout]; the head [cout][cin].
 struct AdamArgs {
     float *w, *m, *v;
     const float *g;
@@ -796,12 +839,17 @@ __global__ void __launch_bounds__(256) k_adam(const AdamArgs a)
     const uint16_t wb = f2bf(w);
     if (a.kind == 1) {   // convT: forward rows are (tap, cout)
         a.wf[((int64_t)(t * a.cout + co)) * a.cin_pad + ci] = wb;
+    } else if (a.kind == 0) {   // 3x3: chunk-major [cin_pad/32][cout][9][32]
+        a.wf[(((int64_t)(ci >> 5) * a.cout + co) * 9 + t) * 32 + (ci & 31)] = wb;
     } else {
         a.wf[((int64_t)co * a.taps + t) * a.cin_pad + ci] = wb;
     }
     if (a.wd) {
         const int td = a.kind == 0 ? a.taps - 1 - t : t;
-        a.wd[((int64_t)ci * a.taps + td) * a.cout + co] = wb;
+        if (a.kind == 0)   // data gradient, chunk-major over the output channels: [cout/32][cin][9][32]
+            a.wd[(((int64_t)(co >> 5) * a.cin + ci) * 9 + td) * 32 + (co & 31)] = wb;
+        else
+            a.wd[((int64_t)ci * a.taps + td) * a.cout + co] = wb;
     }
 }
 
@@ -1313,10 +1361,12 @@ hipError_t prep_weights(unet_state *n, float lr, int apply, hipStream_t s)
     return hipSuccess;
 }
 
+// The convolutions address activations with 32-bit element offsets: the
+// widest buffer holds 64 channels per full-resolution pixel.
 bool geometry_ok(unet_act *a, int NB, int H, int W)
 {
     return NB >= 1 && H >= UNET_ALIGN && W >= UNET_ALIGN && H % UNET_ALIGN == 0 && W % UNET_ALIGN == 0 &&
-           (size_t)NB * H * W <= a->cap;
+           (size_t)NB * H * W <= a->cap && (size_t)NB * H * W * 64 < ((size_t)1 << 31);
 }
 
 }  // namespace
