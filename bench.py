@@ -16,6 +16,7 @@ launches on, bracketed by synchronisation.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import platform
@@ -425,12 +426,14 @@ def run_learned(fvv, torch, w, ctx, stream, args) -> dict:
     virts = [v.with_size(960, 540, 0.5) for v in w.virtual[: args.learned_views]]
     outs = [torch.empty((540, 960, 3), dtype=torch.uint8, device=dev) for _ in virts]
     p = fvv.params(path=fvv.PATH_LEARNED)
-    for _ in range(2):
+    # warm-up long enough for the clocks to settle after the idle host-side
+    # blocks before this one (the first batches run up to 20 % slower)
+    for _ in range(10):
         ctx.synthesize_batch(virts, outs, p=p, stream=stream)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    reps = max(2, min(args.steps, 5))
+    reps = max(3, min(args.steps, 10))
     e0.record(stream)
     for _ in range(reps):
         ctx.synthesize_batch(virts, outs, p=p, stream=stream)
@@ -439,11 +442,13 @@ def run_learned(fvv, torch, w, ctx, stream, args) -> dict:
     ms = e0.elapsed_time(e1) / reps
     ctx.set_profiling(True)
     ctx.profile(reset=True)
-    ctx.synthesize_batch(virts, outs, p=p, stream=stream)
+    for _ in range(reps):
+        ctx.synthesize_batch(virts, outs, p=p, stream=stream)
     torch.cuda.synchronize()
     prof = ctx.profile(reset=True)
     ctx.set_profiling(False)
     net_ms, net_n = prof["net"]
+    net_ms, net_n = net_ms / reps, net_n / reps
     fl = net_flops(fvv, fvv.pad8(540), 960)
     tflops = fl * len(virts) / (net_ms * 1e-3) / 1e12
     # plain at the same size and views, for comparison
@@ -715,19 +720,36 @@ def main():
     while n_w < args.warmup or time.perf_counter() - t_w < 1.0:
         step()
         n_w += 1
-    torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    # no garbage-collector pass inside the timed region
+    gc.collect()
+    gc.disable()
+    torch.cuda.synchronize()
+    # timed region: synchronised on both sides, host clock (the whole job,
+    # the first step's enqueue included) and HIP events on the stream
+    t_wall = time.perf_counter()
     e0.record(stream)
-    t_host = time.perf_counter()
+    marks = []
     for _ in range(args.steps):
-        step()
-    t_host = (time.perf_counter() - t_host) * 1e3 / args.steps
+        t0 = time.perf_counter()
+        ctx.upload_mvd(raw, mem=fvv.MEM_DEVICE, stream=stream)
+        t1 = time.perf_counter()
+        ctx.synthesize_batch(virt_c, outs, stream=stream)
+        marks.append((t1 - t0, time.perf_counter() - t1))
+    t_host = (time.perf_counter() - t_wall) * 1e3 / args.steps
     e1.record(stream)
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / args.steps
+    ms_wall = (time.perf_counter() - t_wall) * 1e3 / args.steps
+    gc.enable()
+    ms_ev = e0.elapsed_time(e1) / args.steps
+    ms = max(ms_wall, ms_ev)
     mpix = n_views * n_out / (ms * 1e-3) / 1e6
-    log(f"[bench] {ms:.3f} ms/step, {mpix:.1f} Mpix/s (host enqueue {t_host:.3f} ms/step)")
+    log(f"[bench] {ms:.3f} ms/step (host clock {ms_wall:.3f}, events {ms_ev:.3f}), {mpix:.1f} Mpix/s "
+        f"(host enqueue {t_host:.3f} ms/step)")
+    worst = max(range(len(marks)), key=lambda q: sum(marks[q]))
+    log(f"[bench] host calls of the timed steps: first {[[round(x * 1e3, 2) for x in m] for m in marks[:3]]} ms, "
+        f"slowest step {worst}: upload {marks[worst][0] * 1e3:.2f} ms, synthesis {marks[worst][1] * 1e3:.2f} ms")
 
     # host time of one step's enqueue with the device idle
     host1 = []
@@ -879,6 +901,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(ms, 4),
+        "ms_per_step_host_clock": round(ms_wall, 4),
+        "ms_per_step_events": round(ms_ev, 4),
         "host_enqueue_ms_per_step": round(t_host, 4),
         "host_ms_per_step_idle_device": round(host1, 4),
         "higher_is_better": True,

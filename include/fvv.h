@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define FVV_ABI_VERSION 8
+#define FVV_ABI_VERSION 9
 
 /* status codes */
 enum {
@@ -349,6 +349,17 @@ int32_t fvv_debug_read(fvv_ctx *ctx, int32_t tap, void *host_out, int64_t bytes)
  * fvv_last_error(NULL)); n must be >= FVV_PEAKS. */
 #define FVV_PEAKS 5
 int32_t fvv_measure_peaks(int32_t hip_device, double *out, int32_t n);
+
+/* Self-check of the division the kernels use for every projected depth
+ * (Section VI: the warps divide by the projected depth; the float32 reading
+ * takes correctly rounded quotients): the reciprocal formed from the hardware
+ * estimate and one Newton step, and the quotients derived from it, against
+ * correctly rounded division, for every significand of the divisors
+ * 2^e (1 + m 2^-23), e_lo <= e <= e_hi (-125 <= e_lo <= e_hi <= 125), two
+ * dividends per divisor.  Writes the number of mismatching results to
+ * *mismatches (host memory; 0 expected).  Synchronous on hip_device; returns
+ * FVV_OK or an error (text in fvv_last_error(NULL)). */
+int32_t fvv_check_reciprocal(int32_t hip_device, int32_t e_lo, int32_t e_hi, uint64_t *mismatches);
 
 /* Stage timing (tracing).  With profiling on, every kernel the context
  * launches is bracketed by HIP events on the caller's stream (this adds a

@@ -88,6 +88,7 @@ def lib():
             "fvv_set_debug": (I32, [P, I32]),
             "fvv_set_debug_view": (I32, [P, I32]),
             "fvv_measure_peaks": (I32, [I32, P, I32]),
+            "fvv_check_reciprocal": (I32, [I32, I32, I32, P]),
             "fvv_debug_read": (I32, [P, I32, P, I64]),
             "fvv_set_profiling": (I32, [P, I32]),
             "fvv_stage_count": (I32, []),
@@ -139,7 +140,7 @@ EXPORTED = ("fvv_abi_version", "fvv_create", "fvv_destroy", "fvv_last_error", "f
             "fvv_depth_decode_y12", "fvv_set_depth_format", "fvv_set_bg_model", "fvv_set_prefilter",
             "fvv_read_frame_depth", "fvv_tx_cameras", "fvv_server_tx_cameras",
             "fvv_depth_encode_y12_batch", "fvv_depth_decode_y12_batch", "fvv_synthesize_noalloc",
-            "fvv_set_debug_view", "fvv_measure_peaks")
+            "fvv_set_debug_view", "fvv_measure_peaks", "fvv_check_reciprocal")
 DEPTH_MM16, DEPTH_Y12 = 0, 1
 NET_PARAMS, NET_GRADS = 0, 1
 NET_ALIGN = 8           # network inputs: multiples of 8 in both dimensions
@@ -219,6 +220,17 @@ def measure_peaks(device: int = 0) -> dict:
     return {"copy_GBs": float(out[0]), "global_atomic_min_distinct_per_s": float(out[1]),
             "global_atomic_min_wave_contended_per_s": float(out[2]),
             "lds_atomic_min_distinct_per_s": float(out[3]), "lds_atomic_min_window_per_s": float(out[4])}
+
+
+def check_reciprocal(device: int = 0, e_lo: int = -7, e_hi: int = 20) -> int:
+    """Mismatches of the kernels' reciprocal (and two quotients per divisor)
+    against correctly rounded division over every significand of the
+    binades 2^e_lo .. 2^e_hi, on the device."""
+    bad = np.zeros(1, np.uint64)
+    rc = lib().fvv_check_reciprocal(device, e_lo, e_hi, bad.ctypes.data)
+    if rc < 0:
+        raise FvvError(rc, lib().fvv_last_error(None).decode())
+    return int(bad[0])
 
 
 def select_cameras(rig: Sequence, virt, k: int, present=None):

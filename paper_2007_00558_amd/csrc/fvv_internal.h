@@ -212,3 +212,5 @@ hipError_t fvv_launch_synthesis_one(const fvv_view_desc &view, fvv_view_desc *d_
 // Measured machine peaks (fvv_peaks.hip) on the current device; see
 // fvv_measure_peaks in fvv.h for the five figures written to out.
 hipError_t fvv_measure_peaks_impl(double *out, std::string &err);
+// fvv_check_reciprocal's kernel: adds the mismatch count to *bad_dev
+hipError_t fvv_check_reciprocal_impl(int e_lo, int e_hi, unsigned long long *bad_dev, hipStream_t s);

@@ -79,6 +79,23 @@ __device__ __forceinline__ float div_by(float a, float b, float y)
     return __fmaf_rn(rem, y, q);
 }
 
+// RN(1/b) for a normal b with a normal reciprocal (every projected depth,
+// 0.01 < b < 2^126): the hardware reciprocal (within one ulp of 1/b) refined
+// by one Newton step in fused multiply-adds, y0 + y0 (1 - b y0), is the
+// correctly rounded reciprocal for every significand of b except all ones.
+// There the step can stay on the even neighbour one ulp below RN(1/b), whose
+// significand is odd (1/b lies just above the midpoint of the two), so that
+// significand gets its low bit set.  Three instructions fewer than the
+// correctly rounded division; fvv_check_reciprocal compares the two over
+// every significand of a range of binades on the device.
+__device__ __forceinline__ float rcp_rn(float b)
+{
+    const float y0 = __builtin_amdgcn_rcpf(b);
+    const float y1 = __fmaf_rn(__fmaf_rn(-b, y0, 1.0f), y0, y0);
+    const uint32_t ones = ((f2u(b) & 0x7FFFFFu) + 1u) >> 23;   // 1 iff the significand is all ones
+    return u2f(f2u(y1) | ones);
+}
+
 struct Footprint {
     int x0, x1, y0, y1;
     unsigned long long key;
@@ -95,7 +112,7 @@ __device__ __forceinline__ bool splat_point(const fvv_src_desc &s, int W, int H,
     float q0, q1, q2;
     project(s.A, s.a, (float)i, (float)j, z, q0, q1, q2);
     if (!(q2 > FVV_ZCLIP)) return false;
-    const float r = __fdiv_rn(1.0f, q2);   // one correctly rounded division per point
+    const float r = rcp_rn(q2);   // one correctly rounded reciprocal per point
     const float u = div_by(q0, q2, r), v = div_by(q1, q2, r);
     if (!isfinite(u) || !isfinite(v)) return false;
     float mx = div_by(__fmul_rn(s.sx, z), q2, r);
@@ -427,7 +444,7 @@ __device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int k0, int
         float q0, q1, q2;
         project(s.B, s.b, (float)x, (float)y, zf, q0, q1, q2);
         if (!(q2 > FVV_ZCLIP)) continue;
-        const float r = __fdiv_rn(1.0f, q2);
+        const float r = rcp_rn(q2);
         const float u = div_by(q0, q2, r), v = div_by(q1, q2, r);
         if (!(u >= -0.5f && u <= s.umax)) continue;
         if (!(v >= -0.5f && v <= s.vmax)) continue;
@@ -435,14 +452,15 @@ __device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int k0, int
         const float fu = __fsub_rn(u, fi0), fv = __fsub_rn(v, fj0);
         const int i0 = (int)fi0, j0 = (int)fj0;
         const float lim = __fmul_rn(vd.tau, q2);
-        const float gu = 1.0f - fu, gv = 1.0f - fv;
-        const float wt[4] = {gu * gv, fu * gv, gu * fv, fu * fv};
         // i0 >= -1 and i0 <= W - 1 (likewise j0): only the outer taps can fall
-        // off.  The four taps are read together from clamped coordinates and
-        // an invalid or inconsistent tap gets weight 0 (adding 0 * colour and
-        // 0 to the sums leaves them unchanged, as skipping it would).
-        const bool okc[2] = {i0 >= 0, i0 + 1 < s.W};
-        const bool okr[2] = {j0 >= 0, j0 + 1 < s.H};
+        // off.  The four taps are read together from clamped coordinates; a
+        // tap off the image or not depth-consistent gets weight 0 (adding
+        // 0 * colour and 0 to the sums leaves them unchanged, as skipping it
+        // would).
+        const float gu = 1.0f - fu, gv = 1.0f - fv;
+        const float wx0 = i0 >= 0 ? gu : 0.0f, wx1 = i0 + 1 < s.W ? fu : 0.0f;
+        const float wy0 = j0 >= 0 ? gv : 0.0f, wy1 = j0 + 1 < s.H ? fv : 0.0f;
+        const float wt[4] = {wx0 * wy0, wx1 * wy0, wx0 * wy1, wx1 * wy1};
         const int ic[2] = {max(i0, 0), min(i0 + 1, s.W - 1)};
         // 32-bit texel indices (a source has < 2^27 pixels): a uniform base
         // plus a 32-bit offset needs no 64-bit address arithmetic
@@ -460,19 +478,20 @@ __device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int k0, int
         for (int n = 0; n < 4; ++n) {
             // a texel without depth holds FVV_NO_DEPTH, a NaN as float32,
             // so the consistency test alone rejects it (NaN <= lim is false)
-            const bool ok = okc[n & 1] && okr[n >> 1] && fabsf(__fsub_rn(u2f(tx[n].y), q2)) <= lim;
-            const float w = ok ? wt[n] : 0.0f;
+            const float w = fabsf(__fsub_rn(u2f(tx[n].y), q2)) <= lim ? wt[n] : 0.0f;
             c0 = fmaf(w, (float)(tx[n].x & 0xFF), c0);
             c1 = fmaf(w, (float)((tx[n].x >> 8) & 0xFF), c1);
             c2 = fmaf(w, (float)((tx[n].x >> 16) & 0xFF), c2);
             csum += w;
         }
-        if (!(csum > 0.f)) continue;
-        const float inv = s.wgt * __builtin_amdgcn_rcpf(csum);
+        // a camera without a consistent tap adds nothing (no branch, so the
+        // colour words are read with the depths)
+        const bool any = csum > 0.f;
+        const float inv = any ? s.wgt * __builtin_amdgcn_rcpf(csum) : 0.0f;
         acc0 = fmaf(c0, inv, acc0);
         acc1 = fmaf(c1, inv, acc1);
         acc2 = fmaf(c2, inv, acc2);
-        wsum += s.wgt;
+        wsum += any ? s.wgt : 0.0f;
     }
     if (!(wsum > 0.f)) return false;
     const float iw = __builtin_amdgcn_rcpf(wsum);
@@ -501,7 +520,7 @@ __device__ __forceinline__ void stack_pixel(const fvv_view_desc &vd, int x, int 
             float q0, q1, q2;
             project(s.B, s.b, (float)x, (float)y, zf, q0, q1, q2);
             if (!(q2 > FVV_ZCLIP)) continue;
-            const float r = __fdiv_rn(1.0f, q2);
+            const float r = rcp_rn(q2);
             const float u = div_by(q0, q2, r), v = div_by(q1, q2, r);
             if (!(u >= -0.5f && u <= s.umax)) continue;
             if (!(v >= -0.5f && v <= s.vmax)) continue;
@@ -1178,6 +1197,39 @@ hipError_t fvv_launch_synthesis(const fvv_view_desc *h_views, fvv_view_desc *d_v
     fvv_prof_end(prof, s, FVV_ST_DESC, e0);
     const hipError_t e = hipGetLastError();
     return e != hipSuccess ? e : launch_stages(d_views, b, s, prof);
+}
+
+namespace {
+
+// Every significand m of b = 2^e (1 + m 2^-23), e_lo <= e <= e_hi: rcp_rn(b)
+// against the correctly rounded 1/b, and the quotients div_by(a, b, rcp_rn(b))
+// of two dividends per b against the correctly rounded a / b.
+__global__ void __launch_bounds__(256) k_check_rcp(int e_lo, int n_exp, unsigned long long *bad)
+{
+    const uint32_t n = (uint32_t)n_exp << 23;
+    uint32_t miss = 0;
+    for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) {
+        const uint32_t m = i & 0x7FFFFFu;
+        const int e = e_lo + (int)(i >> 23);
+        const float b = u2f(((uint32_t)(127 + e) << 23) | m);
+        const float y = rcp_rn(b);
+        miss += f2u(y) != f2u(__fdiv_rn(1.0f, b));
+        // dividends of both signs, image-coordinate-like magnitudes
+        const float a0 = u2f(((uint32_t)(118 + (m * 2654435761u >> 27) % 24u) << 23) | ((m * 40503u) & 0x7FFFFFu));
+        const float a1 = -u2f(((uint32_t)(118 + (m * 2246822519u >> 27) % 24u) << 23) | ((m * 69069u) & 0x7FFFFFu));
+        miss += f2u(div_by(a0, b, y)) != f2u(__fdiv_rn(a0, b));
+        miss += f2u(div_by(a1, b, y)) != f2u(__fdiv_rn(a1, b));
+    }
+    if (miss) atomicAdd(bad, (unsigned long long)miss);
+}
+
+}  // namespace
+
+hipError_t fvv_check_reciprocal_impl(int e_lo, int e_hi, unsigned long long *bad_dev, hipStream_t s)
+{
+    if (e_lo < -125 || e_hi > 125 || e_lo > e_hi) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_check_rcp, dim3(4096), dim3(256), 0, s, e_lo, e_hi - e_lo + 1, bad_dev);
+    return hipGetLastError();
 }
 
 hipError_t fvv_launch_synthesis_one(const fvv_view_desc &view, fvv_view_desc *d_view, int32_t *counts,

@@ -163,6 +163,10 @@ struct fvv_ctx {
     uint8_t *staging = nullptr;
     size_t staging_bytes = 0;
     hipEvent_t staging_free = nullptr;
+    // pinned bounce buffer (two halves) for copies into the caller's
+    // pageable host memory, and an event per half
+    uint8_t *bounce = nullptr;
+    hipEvent_t bounce_ev[2] = {nullptr, nullptr};
     Workspace user;          // workspace of direct synthesis calls
     uint8_t *scratch = nullptr;   // device address of this device's no-allocation scratch
     // Direct calls (synthesis, stacks, network forward and training) share
@@ -440,6 +444,47 @@ hipEvent_t take_event(fvv_ctx *c)
 }
 
 // record that `s` reads frame slot fs (an upload into the slot waits for it)
+constexpr size_t kBounceHalf = (size_t)8 << 20;   // bytes per half; holds a row of any output width
+
+// Copy `rows` rows of `row` bytes from device memory (src_pitch apart) into
+// the caller's host memory (dst_pitch apart) after the work already on
+// stream s: device -> pinned bounce half (asynchronous, on s) -> host
+// memcpy, two halves in flight.  Returns with the copy complete.
+int32_t to_host(fvv_ctx *c, uint8_t *dst, int64_t dst_pitch, const uint8_t *src, int64_t src_pitch, size_t row,
+                size_t rows, hipStream_t s)
+{
+    if (rows == 0 || row == 0) return FVV_OK;
+    if (row > kBounceHalf) return fail(c, FVV_E_ARG, "rows of %zu bytes exceed the %zu-byte host bounce buffer", row,
+                                       kBounceHalf);
+    if (!c->bounce) {
+        HIPCHECK(c, hipHostMalloc((void **)&c->bounce, 2 * kBounceHalf, hipHostMallocDefault));
+        for (auto &e : c->bounce_ev) HIPCHECK(c, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    const size_t per = kBounceHalf / row;          // rows per piece
+    const size_t n = (rows + per - 1) / per;
+    auto issue = [&](size_t i) -> int32_t {
+        const size_t r0 = i * per, nr = std::min(per, rows - r0);
+        uint8_t *b = c->bounce + (i & 1) * kBounceHalf;
+        HIPCHECK(c, hipMemcpy2DAsync(b, row, src + (int64_t)r0 * src_pitch, (size_t)src_pitch, row, nr,
+                                     hipMemcpyDeviceToHost, s));
+        HIPCHECK(c, hipEventRecord(c->bounce_ev[i & 1], s));
+        return FVV_OK;
+    };
+    int32_t rc = issue(0);
+    for (size_t i = 0; i < n && rc == FVV_OK; ++i) {
+        if (i + 1 < n && (rc = issue(i + 1))) break;   // the other half was consumed in the last iteration
+        HIPCHECK(c, hipEventSynchronize(c->bounce_ev[i & 1]));
+        const size_t r0 = i * per, nr = std::min(per, rows - r0);
+        const uint8_t *b = c->bounce + (i & 1) * kBounceHalf;
+        if (dst_pitch == (int64_t)row) {
+            std::memcpy(dst + r0 * row, b, nr * row);
+        } else {
+            for (size_t r = 0; r < nr; ++r) std::memcpy(dst + (int64_t)(r0 + r) * dst_pitch, b + r * row, row);
+        }
+    }
+    return rc;
+}
+
 int32_t note_reader(fvv_ctx *c, FrameSlot &fs, hipStream_t s)
 {
     for (auto &r : fs.readers)
@@ -960,18 +1005,12 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
     for (int q = 0; q < 2; ++q)
         if (waited[q] && (rc = note_reader(c, c->slots[q], s))) return rc;
     if (host_out && !lio.scratch_out) {
-        // caller's pageable host memory: blocking copies once the views are
-        // done (an asynchronous copy into pageable memory is not guaranteed
-        // to have landed by the stream synchronisation under every runtime
-        // configuration, e.g. with a tracing tool attached)
-        HIPCHECK(c, hipStreamSynchronize(s));
+        // caller's (pageable) host memory: through the pinned bounce buffer
         for (int v = 0; v < n_views; ++v) {
             const size_t row = (size_t)virts[v].width * 3;
-            if (pitches[v] == (int64_t)row)
-                HIPCHECK(c, hipMemcpy(outs[v], host_stage[v], row * virts[v].height, hipMemcpyDeviceToHost));
-            else
-                HIPCHECK(c, hipMemcpy2D(outs[v], pitches[v], host_stage[v], row, row, virts[v].height,
-                                        hipMemcpyDeviceToHost));
+            if ((rc = to_host(c, (uint8_t *)outs[v], pitches[v], host_stage[v], (int64_t)row, row,
+                              (size_t)virts[v].height, s)))
+                return rc;
         }
     }
     return FVV_OK;
@@ -1287,6 +1326,9 @@ void fvv_destroy(fvv_ctx *c)
             if (s.ready) (void)hipEventDestroy(s.ready);
         dfree(c, c->staging, c->staging_bytes);
         if (c->staging_free) (void)hipEventDestroy(c->staging_free);
+        if (c->bounce) (void)hipHostFree(c->bounce);
+        for (hipEvent_t e : c->bounce_ev)
+            if (e) (void)hipEventDestroy(e);
         ws_release(c, c->user);
         dfree(c, c->dbg_z, c->dbg_px * 8);
         dfree(c, c->dbg_zf, c->dbg_px * 8);
@@ -1553,8 +1595,9 @@ int32_t fvv_read_frame_depth(fvv_ctx *c, int32_t cam, int32_t layer, uint64_t ve
                                    (long long)bytes);
     DeviceGuard g(c->device);
     HIPCHECK(c, hipDeviceSynchronize());
-    HIPCHECK(c, hipMemcpy(host_out, layer ? fs.bg_depth[cam] : fs.depth[cam], (size_t)need, hipMemcpyDeviceToHost));
-    return FVV_OK;
+    const size_t row = (size_t)c->rig[cam].width * 4;
+    return to_host(c, (uint8_t *)host_out, (int64_t)row, (const uint8_t *)(layer ? fs.bg_depth[cam] : fs.depth[cam]),
+                   (int64_t)row, row, (size_t)c->rig[cam].height, nullptr);
 }
 
 int32_t fvv_set_depth_format(fvv_ctx *c, int32_t format, float z_near, float z_far)
@@ -1731,6 +1774,28 @@ int32_t fvv_measure_peaks(int32_t hip_device, double *out, int32_t n)
     return FVV_PEAKS;
 }
 
+int32_t fvv_check_reciprocal(int32_t hip_device, int32_t e_lo, int32_t e_hi, uint64_t *mismatches)
+{
+    if (!mismatches) return fail(nullptr, FVV_E_ARG, "mismatches is null");
+    if (e_lo < -125 || e_hi > 125 || e_lo > e_hi) return fail(nullptr, FVV_E_ARG, "binades %d..%d outside -125..125", e_lo, e_hi);
+    int nd = 0;
+    hipError_t e = hipGetDeviceCount(&nd);
+    if (e != hipSuccess) return fail(nullptr, FVV_E_DEVICE, "hipGetDeviceCount: %s", hipGetErrorString(e));
+    if (hip_device < 0 || hip_device >= nd) return fail(nullptr, FVV_E_ARG, "device %d outside 0..%d", hip_device, nd - 1);
+    DeviceGuard g(hip_device);
+    unsigned long long *bad = nullptr;
+    if ((e = hipMalloc((void **)&bad, sizeof *bad)) != hipSuccess)
+        return fail(nullptr, FVV_E_NOMEM, "hipMalloc: %s", hipGetErrorString(e));
+    unsigned long long h = 0;
+    e = hipMemcpy(bad, &h, sizeof h, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = fvv_check_reciprocal_impl(e_lo, e_hi, bad, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(&h, bad, sizeof h, hipMemcpyDeviceToHost);
+    (void)hipFree(bad);
+    if (e != hipSuccess) return fail(nullptr, FVV_E_DEVICE, "reciprocal check: %s", hipGetErrorString(e));
+    *mismatches = h;
+    return FVV_OK;
+}
+
 int32_t fvv_select_cameras(const fvv_camera *rig, const int32_t *present, int32_t n, const fvv_camera *virt,
                            int32_t k, int32_t *idx, float *w)
 {
@@ -1851,8 +1916,14 @@ int32_t fvv_debug_read(fvv_ctx *c, int32_t tap, void *host_out, int64_t bytes)
     }
     if (bytes != need) return fail(c, FVV_E_ARG, "tap %d holds %lld bytes, asked %lld", tap, (long long)need, (long long)bytes);
     HIPCHECK(c, hipDeviceSynchronize());
-    HIPCHECK(c, hipMemcpy(host_out, src, (size_t)need, hipMemcpyDeviceToHost));
-    return FVV_OK;
+    // as rows of at most 8 KB so any tap fits the bounce buffer's halves
+    const size_t row = std::min<size_t>((size_t)need, 8192);
+    const size_t rows = row ? (size_t)need / row : 0, tail = (size_t)need - rows * row;
+    int32_t rc = to_host(c, (uint8_t *)host_out, (int64_t)row, (const uint8_t *)src, (int64_t)row, row, rows, nullptr);
+    if (rc == FVV_OK && tail)
+        rc = to_host(c, (uint8_t *)host_out + rows * row, (int64_t)tail, (const uint8_t *)src + rows * row,
+                     (int64_t)tail, tail, 1, nullptr);
+    return rc;
 }
 
 int32_t fvv_server_start(fvv_ctx *c, int32_t max_slots, uint64_t step_bytes)

@@ -312,6 +312,145 @@ __global__ void __launch_bounds__(256) k_conv3(const GemmArgs g)
     }
 }
 
+// ---------------------------------------------------------------- 3x3 convolution, weights resident
+// The 32-output-channel layers with one or two input chunks (the full-
+// resolution level): the same implicit GEMM as k_conv3<1, TH>, but a block
+// stages the whole weight slice (KC chunks x 32 rows x 9 taps x 32 channels)
+// in LDS once and then walks over patches (TH x 16 pixels), so the weights
+// are not fetched again for every patch; the next patch (all KC chunks) is
+// fetched into registers while the current one's MFMAs and stores run.
+// Blocks take patches in steps of the grid; block b's patches in one step
+// are contiguous with those of the blocks on its XCD (b mod 8), so patches
+// whose halos overlap are read through the same L2.
+// A staged pixel holds its KC chunks side by side (KC x 64 bytes + 16 bytes
+// of padding: 80 or 144 bytes, both keep the 16-byte fragment reads of 8
+// consecutive lanes in distinct banks).
+template <int KC>
+constexpr int c3w_pxs() { return KC * 64 + 16; }
+template <int TH, int KC>
+constexpr int c3w_lds_bytes() { return (TH + 2) * 18 * c3w_pxs<KC>() + KC * 32 * C3_RS; }
+
+
+template <int TH, int KC, int EPI>
+__global__ void __launch_bounds__(256) k_conv3w(const GemmArgs g)
+{
+    static_assert(TH % 8 == 0, "each wave takes TH/4 rows, two per 32-pixel tile");
+    constexpr int NT = TH / 8;
+    constexpr int PW = 18;
+    constexpr int PH = TH + 2;
+    constexpr int PXS = c3w_pxs<KC>();
+    extern __shared__ __attribute__((aligned(16))) uint8_t c3w_smem[];
+    uint8_t *patch = c3w_smem;                    // PH x PW pixels, KC chunks each
+    uint8_t *wts = c3w_smem + PH * PW * PXS;      // KC weight slices
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tiles_x = (g.W + 15) / 16, tiles_y = (g.H + TH - 1) / TH;
+    const int tiles = tiles_x * tiles_y * g.NB;
+    const int k_src = g.k_src ? g.k_src : g.K;
+    const int lc = lane & 31, lh = lane >> 5;
+    // the weight slices, once: chunk-major [K/32][32][9][32]
+    for (int e = tid; e < KC * 32 * 36; e += 256) {
+        const int c = e / (32 * 36), r = (e / 36) % 32, rem = e % 36, tap = rem >> 2, q = rem & 3;
+        *(uint4 *)(wts + (c * 32 + r) * C3_RS + tap * 64 + q * 16) = *(const uint4 *)(g.A + (int64_t)e * 8);
+    }
+    // patch index of this block in step k (the grid is a multiple of 8)
+    const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8, per_xcd = gridDim.x / 8;
+    auto tile_of = [&](int k) { return k * gridDim.x + xcd * per_xcd + slot; };
+    constexpr int NPF = (PH * PW * 4 + 255) / 256;
+    uint4 fp[KC][NPF];
+    auto fetch = [&](int tl) {
+        int t = tl;
+        const int txi = t % tiles_x;
+        t /= tiles_x;
+        const int tyi = t % tiles_y;
+        const int b = t / tiles_y;
+#pragma unroll
+        for (int k = 0; k < NPF; ++k) {
+            const int e = tid + k * 256;
+            const int px = e >> 2, pr = px / PW, pc = px - pr * PW;
+            const int gy = tyi * TH - 1 + pr, gx = txi * 16 - 1 + pc;
+            const bool in = e < PH * PW * 4 && gy >= 0 && gy < g.H && gx >= 0 && gx < g.W;
+            const int32_t off = ((b * g.H + gy) * g.W + gx) * g.b_cs + g.b_off + (tid & 3) * 8;
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                fp[c][k] = make_uint4(0, 0, 0, 0);
+                if (in && c * 32 + (tid & 3) * 8 < k_src) fp[c][k] = *(const uint4 *)(g.Bsrc + (uint32_t)(off + c * 32));
+            }
+        }
+    };
+    auto stash = [&]() {
+#pragma unroll
+        for (int k = 0; k < NPF; ++k) {
+            const int e = tid + k * 256;
+            if (e < PH * PW * 4)
+#pragma unroll
+                for (int c = 0; c < KC; ++c) *(uint4 *)(patch + (e >> 2) * PXS + c * 64 + (e & 3) * 16) = fp[c][k];
+        }
+    };
+    int cur = tile_of(0);
+    if (cur < tiles) fetch(cur);
+    for (int k = 0; cur < tiles; ++k) {
+        __syncthreads();   // every wave is done with the previous patch (and the weights are staged)
+        stash();
+        __syncthreads();
+        const int nxt = tile_of(k + 1);
+        if (nxt < tiles) fetch(nxt);
+        f32x16 acc[NT];
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[n][r] = 0.f;
+#pragma unroll
+        for (int c = 0; c < KC; ++c)
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const int dy = tap / 3, dx = tap - dy * 3;
+#pragma unroll
+                for (int kk = 0; kk < 2; ++kk) {
+                    const int koff = (kk * 16 + 8 * lh) * 2;
+                    const bf16x8 af = __builtin_bit_cast(bf16x8, *(const uint4 *)(wts + (c * 32 + lc) * C3_RS + tap * 64 + koff));
+#pragma unroll
+                    for (int n = 0; n < NT; ++n) {
+                        const int pr = wave * (TH / 4) + 2 * n + (lc >> 4) + dy;
+                        const int pc = (lc & 15) + dx;
+                        const bf16x8 bfr = __builtin_bit_cast(bf16x8, *(const uint4 *)(patch + (pr * PW + pc) * PXS + c * 64 + koff));
+                        acc[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af, bfr, acc[n], 0, 0, 0);
+                    }
+                }
+            }
+        // epilogue: lane holds, for pixel lc of each 32-pixel tile, channels
+        // 8 j + 4 lh + {0..3} (j = 0..3)
+        int t = cur;
+        const int txi = t % tiles_x;
+        t /= tiles_x;
+        const int tyi = t % tiles_y;
+        const int b = t / tiles_y;
+#pragma unroll
+        for (int n = 0; n < NT; ++n) {
+            const int py = tyi * TH + wave * (TH / 4) + 2 * n + (lc >> 4), px = txi * 16 + (lc & 15);
+            if (py >= g.H || px >= g.W) continue;
+            const int64_t pix = ((int64_t)b * g.H + py) * g.W + px;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int m0 = 8 * j + 4 * lh;
+                float v0 = acc[n][4 * j + 0], v1 = acc[n][4 * j + 1];
+                float v2 = acc[n][4 * j + 2], v3 = acc[n][4 * j + 3];
+                if (EPI == EPI_F32) {
+                    *(float4 *)((float *)g.out + pix * g.o_cs + g.o_off + m0) = make_float4(v0, v1, v2, v3);
+                } else {
+                    v0 = fmaxf(v0 + g.bias[m0 + 0], 0.f);
+                    v1 = fmaxf(v1 + g.bias[m0 + 1], 0.f);
+                    v2 = fmaxf(v2 + g.bias[m0 + 2], 0.f);
+                    v3 = fmaxf(v3 + g.bias[m0 + 3], 0.f);
+                    *(uint2 *)((uint16_t *)g.out + pix * g.o_cs + g.o_off + m0) =
+                        make_uint2((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16),
+                                   (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16));
+                }
+            }
+        }
+        cur = nxt;
+    }
+}
+
 // ---------------------------------------------------------------- 1x1 GEMM, LDS-staged
 // out[p][m] = sum_k A[m][k] B[p][k] for the transposed convolutions (rows
 // m = tap * C_out + co, scattered to the four fine pixels by the epilogue):
@@ -398,6 +537,87 @@ __global__ void __launch_bounds__(256) k_gemm1(const GemmArgs g)
                     *(float4 *)((float *)g.out + (int64_t)p * g.o_cs + g.o_off + m0) = make_float4(v0, v1, v2, v3);
                 }
             }
+    }
+}
+
+// ---------------------------------------------------------------- 2x2 transposed convolution, registers only
+// The transposed convolution into the half-resolution level (M = 4 C_out =
+// 256 rows, K = C_in = 128; the kernel takes any M = 128 MTW): out[fine pixel of tap d][co] = sum_k A[d C_out + co][k] x[k]
+// + bias.  Wave w of a block owns rows [32 MTW w, 32 MTW (w + 1)) and keeps
+// their A fragments in registers for the whole launch; the block walks
+// 32-pixel column tiles (in steps of the grid), every wave reading the same
+// pixels' fragments straight from global memory (one 16-byte load per lane
+// and 16 channels, the next tile's in flight while the current one's MFMAs
+// and stores run).  Stores: the accumulator halves of lanes l and l + 32
+// (channels 8 j + 4 lh + {0..3}) are exchanged with v_permlane32_swap so that
+// each lane writes 8 consecutive channels, 16 bytes, and lanes l, l + 32
+// together 32 contiguous bytes of a fine pixel.
+template <int MTW, int KS>
+__global__ void __launch_bounds__(256) k_convT(const GemmArgs g)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lc = lane & 31, lh = lane >> 5;
+    const int P = g.NB * g.H * g.W;
+    const int HW = g.H * g.W;
+    bf16x8 af[MTW][KS];
+#pragma unroll
+    for (int i = 0; i < MTW; ++i)
+#pragma unroll
+        for (int k = 0; k < KS; ++k)
+            af[i][k] = ld8(g.A + (int64_t)((wave * MTW + i) * 32 + lc) * g.K + 16 * k + 8 * lh);
+    const bf16x8 zero8 = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+    auto fetch = [&](int p0, bf16x8 (&bf)[KS]) {
+        const int p = p0 + lc;
+        const uint16_t *row = g.Bsrc + (int64_t)(p < P ? p : 0) * g.b_cs + g.b_off + 8 * lh;
+#pragma unroll
+        for (int k = 0; k < KS; ++k) bf[k] = p < P ? ld8(row + 16 * k) : zero8;
+    };
+    bf16x8 bcur[KS], bnxt[KS];
+    int p0 = blockIdx.x * 32;
+    if (p0 < P) fetch(p0, bcur);
+    for (; p0 < P; p0 += gridDim.x * 32) {
+        const int pn = p0 + gridDim.x * 32;
+        if (pn < P) fetch(pn, bnxt);
+        f32x16 acc[MTW];
+#pragma unroll
+        for (int i = 0; i < MTW; ++i) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][r] = 0.f;
+#pragma unroll
+            for (int k = 0; k < KS; ++k) acc[i] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[i][k], bcur[k], acc[i], 0, 0, 0);
+        }
+        const int p = p0 + lc;
+        const int b = p / HW, rr = p - b * HW, y = rr / g.W, x = rr - y * g.W;
+#pragma unroll
+        for (int i = 0; i < MTW; ++i) {
+            const int m0 = (wave * MTW + i) * 32;
+            const int d = m0 / g.cout, co0 = m0 - d * g.cout;
+            // packed bf16 pairs: w[j][h] = channels 8 j + 4 lh + 2 h, + 1
+            uint32_t w[4][2];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float4 bj = *(const float4 *)(g.bias + co0 + 8 * j + 4 * lh);
+                w[j][0] = (uint32_t)f2bf(acc[i][4 * j + 0] + bj.x) | ((uint32_t)f2bf(acc[i][4 * j + 1] + bj.y) << 16);
+                w[j][1] = (uint32_t)f2bf(acc[i][4 * j + 2] + bj.z) | ((uint32_t)f2bf(acc[i][4 * j + 3] + bj.w) << 16);
+            }
+            // lanes < 32 end up with channels 16 q + 0..7, lanes >= 32 with
+            // 16 q + 8..15 (q = 0, 1)
+            uint4 o[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const auto s0 = __builtin_amdgcn_permlane32_swap(w[2 * q][0], w[2 * q + 1][0], false, false);
+                const auto s1 = __builtin_amdgcn_permlane32_swap(w[2 * q][1], w[2 * q + 1][1], false, false);
+                o[q] = make_uint4(s0[0], s1[0], s0[1], s1[1]);
+            }
+            if (p < P) {
+                const int64_t fp = ((int64_t)b * 2 * g.H + 2 * y + (d >> 1)) * (2 * g.W) + 2 * x + (d & 1);
+                uint16_t *dst = (uint16_t *)g.out + fp * g.o_cs + g.o_off + co0 + 8 * lh;
+                *(uint4 *)dst = o[0];
+                *(uint4 *)(dst + 16) = o[1];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KS; ++k) bcur[k] = bnxt[k];
     }
 }
 
@@ -1100,6 +1320,20 @@ hipError_t unet_act_reserve(unet_act *a, size_t pixels, bool train)
 
 namespace {
 
+// Blocks of a kernel that the device holds at once (its occupancy times the
+// compute units), for the kernels that walk their work in steps of the grid;
+// computed once per kernel.
+template <typename F>
+int resident_blocks(F kernel, size_t lds)
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, 256, lds) != hipSuccess)
+        return 256;
+    return std::max(1, per) * std::max(1, cus);
+}
+
 template <int MC, int NP, int TAP, int EPI>
 hipError_t gemm(const GemmArgs &g, hipStream_t s)
 {
@@ -1124,10 +1358,25 @@ hipError_t conv3_launch(const GemmArgs &g, hipStream_t s)
 // channels x 8-row patches for 32-channel outputs and for grids under 64 K
 // pixels (more blocks where there are few pixels), else 64 channels x
 // 16-row patches
+template <int TH, int KC, int EPI>
+hipError_t conv3w_launch(const GemmArgs &g, hipStream_t s)
+{
+    constexpr int lds = c3w_lds_bytes<TH, KC>();
+    static_assert(lds <= 65536, "staged patches and weights must fit 64 KB");
+    static const int grid = std::max(8, resident_blocks(k_conv3w<TH, KC, EPI>, lds) / 8 * 8);
+    hipLaunchKernelGGL((k_conv3w<TH, KC, EPI>), dim3(grid), dim3(256), lds, s, g);
+    return hipGetLastError();
+}
+
 template <int EPI>
 hipError_t conv3(const GemmArgs &g, hipStream_t s)
 {
     if (g.K % 32 != 0) return hipErrorInvalidValue;
+    // 32 output channels from one or two input chunks, with patches for
+    // every block several times over: weights resident, blocks walk patches
+    const int64_t tiles8 = (int64_t)((g.W + 15) / 16) * ((g.H + 7) / 8) * g.NB;
+    if (g.M == 32 && g.K == 32 && tiles8 >= 2048) return conv3w_launch<8, 1, EPI>(g, s);
+    if (g.M == 32 && g.K == 64 && tiles8 >= 2048) return conv3w_launch<8, 2, EPI>(g, s);
     if (g.M <= 32) return conv3_launch<1, 8, EPI>(g, s);
     if ((int64_t)g.NB * g.H * g.W >= 65536) return conv3_launch<2, 16, EPI>(g, s);
     return conv3_launch<1, 8, EPI>(g, s);
@@ -1174,6 +1423,16 @@ hipError_t convT_fwd(unet_state *n, int li, const uint16_t *in, int i_cs, int NB
     g.M = 4 * l.cout;
     g.cout = l.cout;
     const int P = NB * H * W;
+    // the half-resolution level with a thousand pixel tiles or more: A in
+    // registers, no LDS (at the finest level, with one 32-row tile per
+    // wave, the LDS-staged GEMM below is faster)
+    if (P >= 32768) {
+        if (g.M == 256 && g.K == 128) {
+            static const int rb = resident_blocks(k_convT<2, 8>, 0);
+            hipLaunchKernelGGL((k_convT<2, 8>), dim3(std::min(rb, (P + 31) / 32)), dim3(256), 0, s, g);
+            return hipGetLastError();
+        }
+    }
     // 128 x 128 blocks where they number a thousand or more, else 64 x 64
     // (small grids are latency-bound: more, shorter blocks)
     const int64_t big = (int64_t)((P + 127) / 128) * ((g.M + 127) / 128);

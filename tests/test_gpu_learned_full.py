@@ -11,6 +11,11 @@ the 9x1280x720 rig through the forward (every layer compared), one 960x540
 learned synthesis, a training step on four 256x256 crops (level 1 holds
 exactly 65,536 pixels) with every weight and bias gradient compared, and
 three Adam steps against the oracle's Adam.  Bars as in the smaller tests.
+The 32-channel full-resolution convolutions switch to a weights-resident
+kernel once a batch has 2,048 patches of 8 x 16 pixels or more; its output
+must be the bytes of the per-patch kernel (the same MFMA sequence per
+output), checked by running two 512x256 stacks together (resident kernel)
+and one at a time (per-patch kernel).
 """
 import sys
 
@@ -220,3 +225,33 @@ def test_adam_three_steps_vs_oracle(fvv, ctx, oracle_lib, rig9):
         # two updates may differ in the last place)
         for n in master:
             master[n] = [got[n][0].copy(), got[n][1].copy()]
+
+
+def test_weights_resident_conv_equals_per_patch_conv(fvv, ctx):
+    import torch
+    H, W = 256, 512       # 1,024 patches per image: one image per-patch, two resident
+    ctx.net_load(flat(rand_params(86)))
+    g = torch.Generator(device="cuda").manual_seed(87)
+    st = torch.rand((2, H, W, fvv.NET_IN), device="cuda", generator=g)
+    st[..., 15] = 0
+    st = st.to(torch.bfloat16).view(torch.int16).contiguous()
+    say("[gpu] learned-full: resident vs per-patch 3x3 convolutions")
+    two = torch.empty((2, H, W, 3), dtype=torch.float32, device="cuda")
+    ctx.net_forward(st, 2, H, W, two)
+    torch.cuda.synchronize()
+    layers = layer_list()[:-1]
+    px = {li: (H >> LEVEL[name]) * (W >> LEVEL[name]) for li, (name, *_) in enumerate(layers)}
+    acts_two = {li: ctx.net_read_act(li, (2 * px[li], co)) for li, (name, kind, ci, co) in enumerate(layers)}
+    for q in range(2):
+        one = torch.empty((1, H, W, 3), dtype=torch.float32, device="cuda")
+        ctx.net_forward(st[q:q + 1].contiguous(), 1, H, W, one)
+        torch.cuda.synchronize()
+        assert torch.equal(one[0], two[q]), q
+        for li, (name, kind, ci, co) in enumerate(layers):
+            a = ctx.net_read_act(li, (px[li], co))
+            assert np.array_equal(a, acts_two[li].reshape(2, px[li], co)[q]), (name, q)
+
+
+def layer_list():
+    from oracle import unet
+    return unet.LAYERS
