@@ -48,6 +48,22 @@ struct GemmArgs {
     int k_src;               // channels Bsrc holds at b_off (0 = K); staged channels beyond are zero
     int M;                   // rows (multiple of 16)
     int cout;                // EPI_CONVT_BF16: output channels (M = 4 cout)
+    uint16_t *pool;          // k_conv3w, EPI_RELU_BF16: also the 2x2 max-pooled output [NB][H/2][W/2][32] (or null)
+};
+
+struct HeadArgs {
+    const uint16_t *a;       // [P][32] bf16
+    const uint16_t *w;       // [3][32] bf16
+    const float *bias;       // [3]
+    float *s_out;            // [P][3] or null
+    uint8_t *rgb;            // image b at rgb + b * img_stride, or null
+    int64_t pitch, img_stride;
+    const unet_out *outs;    // or image b at outs[b] (device table), or null
+    int NB, H, W, valid_h, valid_w;
+    const float *target;     // [P][3] training
+    float inv_n;             // 1 / (NB * valid_h * W * 3)
+    float *g_a;              // [P][32] fp32 gradient at the head input
+    float *part;             // per workgroup: 3*32 weight + 3 bias partials + 1 loss partial
 };
 
 // Source pixel of tap t for column pixel (b, y, x); -1 outside.
@@ -331,7 +347,7 @@ template <int TH, int KC>
 constexpr int c3w_lds_bytes() { return (TH + 2) * 18 * c3w_pxs<KC>() + KC * 32 * C3_RS; }
 
 
-template <int TH, int KC, int EPI>
+template <int TH, int KC, int EPI, bool POOL>
 __global__ void __launch_bounds__(256) k_conv3w(const GemmArgs g)
 {
     static_assert(TH % 8 == 0, "each wave takes TH/4 rows, two per 32-pixel tile");
@@ -429,6 +445,7 @@ __global__ void __launch_bounds__(256) k_conv3w(const GemmArgs g)
             const int py = tyi * TH + wave * (TH / 4) + 2 * n + (lc >> 4), px = txi * 16 + (lc & 15);
             if (py >= g.H || px >= g.W) continue;
             const int64_t pix = ((int64_t)b * g.H + py) * g.W + px;
+            float v[16];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int m0 = 8 * j + 4 * lh;
@@ -444,7 +461,40 @@ __global__ void __launch_bounds__(256) k_conv3w(const GemmArgs g)
                     *(uint2 *)((uint16_t *)g.out + pix * g.o_cs + g.o_off + m0) =
                         make_uint2((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16),
                                    (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16));
+                    v[4 * j + 0] = v0;
+                    v[4 * j + 1] = v1;
+                    v[4 * j + 2] = v2;
+                    v[4 * j + 3] = v3;
                 }
+            }
+            if (EPI == EPI_RELU_BF16 && POOL) {
+                // 2x2 max-pool: the window of pooled pixel (py/2, px/2) is
+                // lanes lc, lc^1 (columns) and lc^16 (rows) of this wave
+                // (patch origins, rows and widths are even).  The max of the
+                // float32 values rounds to the max of their bfloat16 values.
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    float m = fmaxf(v[r], __int_as_float(__builtin_amdgcn_update_dpp(
+                                              0, __float_as_int(v[r]), 0xB1, 0xF, 0xF, false)));   // quad_perm 1,0,3,2
+                    const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(m), __float_as_uint(m), false, false);
+                    v[r] = fmaxf(__uint_as_float(sw[0]), __uint_as_float(sw[1]));
+                }
+                // the four lanes of a window share its 32 channels' maxima;
+                // lane (column bit a, row bit c) writes group j = 2 c + a
+                const int jsel = 2 * ((lc >> 4) & 1) + (lc & 1);
+                float q0 = v[0], q1 = v[1], q2 = v[2], q3 = v[3];
+#pragma unroll
+                for (int j = 1; j < 4; ++j)
+                    if (jsel == j) {
+                        q0 = v[4 * j + 0];
+                        q1 = v[4 * j + 1];
+                        q2 = v[4 * j + 2];
+                        q3 = v[4 * j + 3];
+                    }
+                const int64_t pp = ((int64_t)b * (g.H / 2) + (py >> 1)) * (g.W / 2) + (px >> 1);
+                *(uint2 *)(g.pool + pp * 32 + 8 * jsel + 4 * lh) =
+                    make_uint2((uint32_t)f2bf(q0) | ((uint32_t)f2bf(q1) << 16),
+                               (uint32_t)f2bf(q2) | ((uint32_t)f2bf(q3) << 16));
             }
         }
         cur = nxt;
@@ -919,20 +969,6 @@ __global__ void __launch_bounds__(256) k_reduce_rows(const float *part, int rows
 // Head: 1x1 conv 32->3 + bias, sigmoid.  mode 0: inference (s and/or RGB8
 // of finite pixels); mode 1: training (loss partials, d loss / d z, the
 // gradient at the head input and the head's weight/bias partials).
-struct HeadArgs {
-    const uint16_t *a;       // [P][32] bf16
-    const uint16_t *w;       // [3][32] bf16
-    const float *bias;       // [3]
-    float *s_out;            // [P][3] or null
-    uint8_t *rgb;            // image b at rgb + b * img_stride, or null
-    int64_t pitch, img_stride;
-    const unet_out *outs;    // or image b at outs[b] (device table), or null
-    int NB, H, W, valid_h, valid_w;
-    const float *target;     // [P][3] training
-    float inv_n;             // 1 / (NB * valid_h * W * 3)
-    float *g_a;              // [P][32] fp32 gradient at the head input
-    float *part;             // per workgroup: 3*32 weight + 3 bias partials + 1 loss partial
-};
 
 __global__ void __launch_bounds__(256) k_head(const HeadArgs h, int mode)
 {
@@ -1358,33 +1394,46 @@ hipError_t conv3_launch(const GemmArgs &g, hipStream_t s)
 // channels x 8-row patches for 32-channel outputs and for grids under 64 K
 // pixels (more blocks where there are few pixels), else 64 channels x
 // 16-row patches
-template <int TH, int KC, int EPI>
+template <int TH, int KC, int EPI, bool POOL>
 hipError_t conv3w_launch(const GemmArgs &g, hipStream_t s)
 {
     constexpr int lds = c3w_lds_bytes<TH, KC>();
     static_assert(lds <= 65536, "staged patches and weights must fit 64 KB");
-    static const int grid = std::max(8, resident_blocks(k_conv3w<TH, KC, EPI>, lds) / 8 * 8);
-    hipLaunchKernelGGL((k_conv3w<TH, KC, EPI>), dim3(grid), dim3(256), lds, s, g);
+    static const int grid = std::max(8, resident_blocks(k_conv3w<TH, KC, EPI, POOL>, lds) / 8 * 8);
+    hipLaunchKernelGGL((k_conv3w<TH, KC, EPI, POOL>), dim3(grid), dim3(256), lds, s, g);
     return hipGetLastError();
 }
 
+// *pooled (if given) tells whether the launch also wrote the 2x2 max-pool
+// of the output to g.pool: only the weights-resident kernel with one input
+// chunk does; g.pool is ignored otherwise.
 template <int EPI>
-hipError_t conv3(const GemmArgs &g, hipStream_t s)
+hipError_t conv3(GemmArgs g, hipStream_t s, bool *pooled = nullptr)
 {
     if (g.K % 32 != 0) return hipErrorInvalidValue;
+    if (pooled) *pooled = false;
     // 32 output channels from one or two input chunks, with patches for
     // every block several times over: weights resident, blocks walk patches
     const int64_t tiles8 = (int64_t)((g.W + 15) / 16) * ((g.H + 7) / 8) * g.NB;
-    if (g.M == 32 && g.K == 32 && tiles8 >= 2048) return conv3w_launch<8, 1, EPI>(g, s);
-    if (g.M == 32 && g.K == 64 && tiles8 >= 2048) return conv3w_launch<8, 2, EPI>(g, s);
+    if (g.M == 32 && g.K == 32 && tiles8 >= 2048 && g.H % 2 == 0 && g.W % 2 == 0) {
+        if constexpr (EPI == EPI_RELU_BF16) {
+            if (pooled && g.pool) {
+                *pooled = true;
+                return conv3w_launch<8, 1, EPI, true>(g, s);
+            }
+        }
+        return conv3w_launch<8, 1, EPI, false>(g, s);
+    }
+    if (g.M == 32 && g.K == 64 && tiles8 >= 2048) return conv3w_launch<8, 2, EPI, false>(g, s);
     if (g.M <= 32) return conv3_launch<1, 8, EPI>(g, s);
     if ((int64_t)g.NB * g.H * g.W >= 65536) return conv3_launch<2, 16, EPI>(g, s);
     return conv3_launch<1, 8, EPI>(g, s);
 }
 
-// 3x3 conv + bias + ReLU into (out, o_cs, o_off)
+// 3x3 conv + bias + ReLU into (out, o_cs, o_off); with pool_out, *pooled
+// tells whether the 2x2 max-pool of the output was written there as well
 hipError_t conv_fwd(unet_state *n, int li, const uint16_t *in, int i_cs, int i_off, uint16_t *out, int o_cs, int o_off,
-                    int NB, int H, int W, hipStream_t s)
+                    int NB, int H, int W, hipStream_t s, uint16_t *pool_out = nullptr, bool *pooled = nullptr)
 {
     const unet_layer &l = layers().L[li];
     GemmArgs g{};
@@ -1402,7 +1451,8 @@ hipError_t conv_fwd(unet_state *n, int li, const uint16_t *in, int i_cs, int i_o
     g.K = l.cin_pad;
     g.k_src = std::min(i_cs - i_off, l.cin_pad);
     g.M = l.cout;
-    return conv3<EPI_RELU_BF16>(g, s);
+    g.pool = pool_out;
+    return conv3<EPI_RELU_BF16>(g, s, pooled);
 }
 
 hipError_t convT_fwd(unet_state *n, int li, const uint16_t *in, int i_cs, int NB, int H, int W, uint16_t *out,
@@ -1460,8 +1510,9 @@ hipError_t forward_all(unet_state *n, unet_act *a, const uint16_t *stack, int NB
     a->W = W;
     const int H1 = H / 2, W1 = W / 2, H2 = H / 4, W2 = W / 4, H3 = H / 8, W3 = W / 8;
     NCHK(conv_fwd(n, L_E0A, stack, UNET_IN, 0, a->e0a, 32, 0, NB, H, W, s));
-    NCHK(conv_fwd(n, L_E0B, a->e0a, 32, 0, a->cat0, 64, 32, NB, H, W, s));
-    NCHK(pool(a->cat0, 64, 32, a->p1, NB, H, W, 32, s));
+    bool pooled = false;
+    NCHK(conv_fwd(n, L_E0B, a->e0a, 32, 0, a->cat0, 64, 32, NB, H, W, s, a->p1, &pooled));
+    if (!pooled) NCHK(pool(a->cat0, 64, 32, a->p1, NB, H, W, 32, s));
     NCHK(conv_fwd(n, L_E1A, a->p1, 32, 0, a->e1a, 64, 0, NB, H1, W1, s));
     NCHK(conv_fwd(n, L_E1B, a->e1a, 64, 0, a->cat1, 128, 64, NB, H1, W1, s));
     NCHK(pool(a->cat1, 128, 64, a->p2, NB, H1, W1, 64, s));
@@ -1680,7 +1731,6 @@ hipError_t unet_forward(unet_state *n, unet_act *a, const uint16_t *stack, int N
         err = "network input must be a multiple of 8 in both dimensions and fit the activation set";
         return hipErrorInvalidValue;
     }
-    NCHK(forward_all(n, a, stack, NB, H, W, s));
     const unet_layer &hl = layers().L[L_HEAD];
     HeadArgs h{};
     h.a = a->d0b;
@@ -1695,6 +1745,7 @@ hipError_t unet_forward(unet_state *n, unet_act *a, const uint16_t *stack, int N
     h.W = W;
     h.valid_h = valid_h;
     h.valid_w = valid_w;
+    NCHK(forward_all(n, a, stack, NB, H, W, s));
     const int P = NB * H * W;
     hipLaunchKernelGGL(k_head, dim3((P + 255) / 256), dim3(256), 0, s, h, 0);
     return hipGetLastError();
@@ -1711,7 +1762,6 @@ hipError_t unet_forward_batch(unet_state *n, unet_act *a, const uint16_t *stack,
         err = "network input must be a multiple of 8 in both dimensions and fit the activation set";
         return hipErrorInvalidValue;
     }
-    NCHK(forward_all(n, a, stack, NB, H, W, s));
     const unet_layer &hl = layers().L[L_HEAD];
     HeadArgs h{};
     h.a = a->d0b;
@@ -1721,6 +1771,7 @@ hipError_t unet_forward_batch(unet_state *n, unet_act *a, const uint16_t *stack,
     h.NB = NB;
     h.H = H;
     h.W = W;
+    NCHK(forward_all(n, a, stack, NB, H, W, s));
     const int P = NB * H * W;
     hipLaunchKernelGGL(k_head, dim3((P + 255) / 256), dim3(256), 0, s, h, 0);
     return hipGetLastError();
