@@ -995,7 +995,7 @@ int32_t launch_views(fvv_ctx *c, Workspace &Wk, const fvv_camera *virts, const f
             hipEvent_t e0;
             fvv_prof_begin(prof, s, e0);
             const hipError_t e = unet_forward_batch(c->net, lio.act, hd[b.views[0]].stack, (int)b.views.size(), b.H,
-                                                    b.W, dt + batch_first[bi], s, err);
+                                                    b.W, dt + batch_first[bi], s, err, taps);
             fvv_prof_end(prof, s, FVV_ST_NET, e0);
             if ((rc = net_status(c, e, err, "network forward"))) return rc;
         }
@@ -2191,7 +2191,7 @@ int32_t fvv_net_forward(fvv_ctx *c, const void *stack_dev, int32_t n, int32_t he
     fvv_prof *prof = c->profiling ? &c->prof : nullptr;
     fvv_prof_begin(prof, s, e0);
     const hipError_t e = unet_forward(c->net, c->act, (const uint16_t *)stack_dev, n, height, width, out_dev, nullptr,
-                                      0, 0, 0, 0, s, err);
+                                      0, 0, 0, 0, s, err, c->debug);
     fvv_prof_end(prof, s, FVV_ST_NET, e0);
     const int32_t rm = mark_direct(c, s);
     rc = net_status(c, e, err, "network forward");
@@ -2236,7 +2236,9 @@ int32_t fvv_net_read_act(fvv_ctx *c, int32_t layer, void *host_out, int64_t byte
     DeviceGuard g(c->device);
     HIPCHECK(c, hipDeviceSynchronize());
     const hipError_t e = unet_read_act(c->act, layer, host_out, (size_t)bytes, nullptr);
-    if (e != hipSuccess) return fail(c, FVV_E_ARG, "layer %d: wrong layer or byte count", layer);
+    if (e != hipSuccess)
+        return fail(c, FVV_E_ARG, "layer %d: wrong layer or byte count, or an output the last forward did not keep "
+                    "(debug taps off)", layer);
     return FVV_OK;
 }
 

@@ -56,9 +56,12 @@ hipError_t unet_act_reserve(unet_act *a, size_t pixels, bool train);
 // non-null, RGB8 of the first valid_h rows and valid_w columns of image b at
 // rgb + b * img_stride (pitch bytes per row), for every pixel whose three
 // outputs are finite (the others keep what the buffer held).
+// keep: store every layer's output (for unet_read_act); otherwise the
+// finest transposed convolution may run inside the convolution after it and
+// its output is not stored.
 hipError_t unet_forward(unet_state *n, unet_act *a, const uint16_t *stack, int B, int H, int W, float *s_out,
                            uint8_t *rgb, int64_t pitch, int64_t img_stride, int valid_h, int valid_w,
-                           hipStream_t s, std::string &err);
+                           hipStream_t s, std::string &err, bool keep = true);
 // RGB8 destination of image b of a batched forward: its first h rows and w
 // columns at rgb, pitch bytes per row (32 bytes, so a table of them copies
 // in 16-byte words).
@@ -73,7 +76,7 @@ struct unet_out {
 // finite keep what the destination held.  Each image's result is the same
 // for any B (the per-output accumulation order does not depend on the batch).
 hipError_t unet_forward_batch(unet_state *n, unet_act *a, const uint16_t *stack, int B, int H, int W,
-                              const unet_out *outs, hipStream_t s, std::string &err);
+                              const unet_out *outs, hipStream_t s, std::string &err, bool keep = true);
 // One training step: forward, L1 loss against target fp32 [B][H][W][3] over
 // rows < valid_h, backward into the gradient; apply != 0 then takes one Adam
 // step with learning rate lr (apply == 0 leaves the parameters unchanged).
@@ -82,5 +85,6 @@ hipError_t unet_train(unet_state *n, unet_act *a, const uint16_t *stack, const f
                          int W, int valid_h, float lr, int apply, float *loss_host, hipStream_t s,
                          std::string &err);
 // Copy one layer's stored output of the last forward (bf16 NHWC, that
-// layer's channels only) to host memory, for parity checks.
+// layer's channels only) to host memory, for parity checks; an error for
+// the finest transposed convolution when the last forward did not keep it.
 hipError_t unet_read_act(unet_act *a, int layer, void *host, size_t bytes, hipStream_t s);

@@ -49,6 +49,13 @@ struct GemmArgs {
     int M;                   // rows (multiple of 16)
     int cout;                // EPI_CONVT_BF16: output channels (M = 4 cout)
     uint16_t *pool;          // k_conv3w, EPI_RELU_BF16: also the 2x2 max-pooled output [NB][H/2][W/2][32] (or null)
+    // k_conv3w<.., 2, .., UPC>: input chunk 0 is the 2x2 transposed
+    // convolution (32 output channels, 64 input channels) of up_in
+    // [NB][H/2][W/2][64] with weights up_w [4 x 32][64] and bias up_b,
+    // computed per patch instead of read from Bsrc
+    const uint16_t *up_in;
+    const uint16_t *up_w;
+    const float *up_b;
 };
 
 struct HeadArgs {
@@ -347,10 +354,11 @@ template <int TH, int KC>
 constexpr int c3w_lds_bytes() { return (TH + 2) * 18 * c3w_pxs<KC>() + KC * 32 * C3_RS; }
 
 
-template <int TH, int KC, int EPI, bool POOL>
+template <int TH, int KC, int EPI, bool POOL, bool UPC = false>
 __global__ void __launch_bounds__(256) k_conv3w(const GemmArgs g)
 {
     static_assert(TH % 8 == 0, "each wave takes TH/4 rows, two per 32-pixel tile");
+    static_assert(!UPC || (KC == 2 && TH == 8), "the transposed convolution feeds chunk 0 of 8-row patches");
     constexpr int NT = TH / 8;
     constexpr int PW = 18;
     constexpr int PH = TH + 2;
@@ -371,6 +379,81 @@ __global__ void __launch_bounds__(256) k_conv3w(const GemmArgs g)
     // patch index of this block in step k (the grid is a multiple of 8)
     const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8, per_xcd = gridDim.x / 8;
     auto tile_of = [&](int k) { return k * gridDim.x + xcd * per_xcd + slot; };
+    // Transposed convolution feeding chunk 0 (UPC): the patch's fine rows
+    // y0 - 1 .. y0 + 8 and columns x0 - 1 .. x0 + 16 come from the coarse
+    // rows y0/2 - 1 .. y0/2 + 4 and columns x0/2 - 1 .. x0/2 + 8, 60 coarse
+    // pixels in two 32-column tiles.  Wave w computes tap w (rows 32 w ..
+    // 32 w + 31 of the weights, kept in registers) for all of them, in the
+    // k-step order of the LDS-staged GEMM, so every value is the bytes that
+    // GEMM would have stored; a fine pixel outside the image is 0 (the
+    // convolution's zero padding).
+    bf16x8 up_a[4], up_b[2][4];
+    float up_bias[16];
+    if constexpr (UPC) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) up_a[k] = ld8(g.up_w + (int64_t)(wave * 32 + lc) * 64 + 16 * k + 8 * lh);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) up_bias[4 * j + r] = g.up_b[8 * j + 4 * lh + r];
+    }
+    auto fetch_up = [&](int tl) {
+        int t = tl;
+        const int txi = t % tiles_x;
+        t /= tiles_x;
+        const int tyi = t % tiles_y;
+        const int b = t / tiles_y;
+        const int Hc = g.H / 2, Wc = g.W / 2;
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+            const int sl = 32 * n + lc, cr = sl / 10, cc = sl - cr * 10;
+            const int cy = tyi * 4 - 1 + cr, cx = txi * 8 - 1 + cc;
+            const bool in = sl < 60 && cy >= 0 && cy < Hc && cx >= 0 && cx < Wc;
+            const uint16_t *row = g.up_in + ((int64_t)(b * Hc + (in ? cy : 0)) * Wc + (in ? cx : 0)) * 64 + 8 * lh;
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                up_b[n][k] = in ? ld8(row + 16 * k) : __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+        }
+    };
+    // the MFMAs run after the previous patch's (their inputs have landed by
+    // then); their results wait in registers until the patch is staged
+    f32x16 up_u[2];
+    auto up_mfma = [&]() {
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r) up_u[n][r] = 0.f;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) up_u[n] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(up_a[k], up_b[n][k], up_u[n], 0, 0, 0);
+        }
+    };
+    auto up_store = [&](int tl) {
+        int t = tl;
+        const int txi = t % tiles_x;
+        t /= tiles_x;
+        const int tyi = t % tiles_y;
+        const int dy = wave >> 1, dx = wave & 1;
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+            const int sl = 32 * n + lc, cr = sl / 10, cc = sl - cr * 10;
+            const int pr = 2 * cr + dy - 1, pc = 2 * cc + dx - 1;       // patch row / column of this fine pixel
+            const int fy = tyi * TH - 1 + pr, fx = txi * 16 - 1 + pc;
+            if (sl < 60 && pr >= 0 && pr < PH && pc >= 0 && pc < PW) {
+                const bool in = fy >= 0 && fy < g.H && fx >= 0 && fx < g.W;
+                uint8_t *dst = patch + (pr * PW + pc) * PXS + 8 * lh;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    uint2 w2 = make_uint2(0, 0);
+                    if (in)
+                        w2 = make_uint2((uint32_t)f2bf(up_u[n][4 * j + 0] + up_bias[4 * j + 0]) |
+                                            ((uint32_t)f2bf(up_u[n][4 * j + 1] + up_bias[4 * j + 1]) << 16),
+                                        (uint32_t)f2bf(up_u[n][4 * j + 2] + up_bias[4 * j + 2]) |
+                                            ((uint32_t)f2bf(up_u[n][4 * j + 3] + up_bias[4 * j + 3]) << 16));
+                    *(uint2 *)(dst + 16 * j) = w2;
+                }
+            }
+        }
+    };
     constexpr int NPF = (PH * PW * 4 + 255) / 256;
     uint4 fp[KC][NPF];
     auto fetch = [&](int tl) {
@@ -387,11 +470,12 @@ __global__ void __launch_bounds__(256) k_conv3w(const GemmArgs g)
             const bool in = e < PH * PW * 4 && gy >= 0 && gy < g.H && gx >= 0 && gx < g.W;
             const int32_t off = ((b * g.H + gy) * g.W + gx) * g.b_cs + g.b_off + (tid & 3) * 8;
 #pragma unroll
-            for (int c = 0; c < KC; ++c) {
+            for (int c = UPC ? 1 : 0; c < KC; ++c) {
                 fp[c][k] = make_uint4(0, 0, 0, 0);
                 if (in && c * 32 + (tid & 3) * 8 < k_src) fp[c][k] = *(const uint4 *)(g.Bsrc + (uint32_t)(off + c * 32));
             }
         }
+        if constexpr (UPC) fetch_up(tl);
     };
     auto stash = [&]() {
 #pragma unroll
@@ -399,14 +483,18 @@ __global__ void __launch_bounds__(256) k_conv3w(const GemmArgs g)
             const int e = tid + k * 256;
             if (e < PH * PW * 4)
 #pragma unroll
-                for (int c = 0; c < KC; ++c) *(uint4 *)(patch + (e >> 2) * PXS + c * 64 + (e & 3) * 16) = fp[c][k];
+                for (int c = UPC ? 1 : 0; c < KC; ++c) *(uint4 *)(patch + (e >> 2) * PXS + c * 64 + (e & 3) * 16) = fp[c][k];
         }
     };
     int cur = tile_of(0);
-    if (cur < tiles) fetch(cur);
+    if (cur < tiles) {
+        fetch(cur);
+        if constexpr (UPC) up_mfma();
+    }
     for (int k = 0; cur < tiles; ++k) {
         __syncthreads();   // every wave is done with the previous patch (and the weights are staged)
         stash();
+        if constexpr (UPC) up_store(cur);
         __syncthreads();
         const int nxt = tile_of(k + 1);
         if (nxt < tiles) fetch(nxt);
@@ -433,6 +521,8 @@ __global__ void __launch_bounds__(256) k_conv3w(const GemmArgs g)
                     }
                 }
             }
+        if constexpr (UPC)
+            if (nxt < tiles) up_mfma();
         // epilogue: lane holds, for pixel lc of each 32-pixel tile, channels
         // 8 j + 4 lh + {0..3} (j = 0..3)
         int t = cur;
@@ -1214,6 +1304,7 @@ struct unet_state {
 struct unet_act {
     size_t cap = 0;          // pixels at full resolution
     bool train = false;
+    bool up0_stored = true;  // the last forward stored the finest transposed convolution's output
     size_t bytes = 0;
     int NB = 0, H = 0, W = 0;
     uint16_t *e0a = nullptr, *cat0 = nullptr, *p1 = nullptr, *e1a = nullptr, *cat1 = nullptr, *p2 = nullptr,
@@ -1394,13 +1485,13 @@ hipError_t conv3_launch(const GemmArgs &g, hipStream_t s)
 // channels x 8-row patches for 32-channel outputs and for grids under 64 K
 // pixels (more blocks where there are few pixels), else 64 channels x
 // 16-row patches
-template <int TH, int KC, int EPI, bool POOL>
+template <int TH, int KC, int EPI, bool POOL, bool UPC = false>
 hipError_t conv3w_launch(const GemmArgs &g, hipStream_t s)
 {
     constexpr int lds = c3w_lds_bytes<TH, KC>();
     static_assert(lds <= 65536, "staged patches and weights must fit 64 KB");
-    static const int grid = std::max(8, resident_blocks(k_conv3w<TH, KC, EPI, POOL>, lds) / 8 * 8);
-    hipLaunchKernelGGL((k_conv3w<TH, KC, EPI, POOL>), dim3(grid), dim3(256), lds, s, g);
+    static const int grid = std::max(8, resident_blocks(k_conv3w<TH, KC, EPI, POOL, UPC>, lds) / 8 * 8);
+    hipLaunchKernelGGL((k_conv3w<TH, KC, EPI, POOL, UPC>), dim3(grid), dim3(256), lds, s, g);
     return hipGetLastError();
 }
 
@@ -1503,7 +1594,42 @@ hipError_t pool(const uint16_t *in, int i_cs, int i_off, uint16_t *out, int NB, 
     return hipGetLastError();
 }
 
-hipError_t forward_all(unet_state *n, unet_act *a, const uint16_t *stack, int NB, int H, int W, hipStream_t s)
+// Whether the finest transposed convolution can run inside the next
+// convolution (weights-resident kernel with two input chunks).
+bool up0_fusable(int NB, int H, int W)
+{
+    return (int64_t)((W + 15) / 16) * ((H + 7) / 8) * NB >= 2048;
+}
+
+// dec0a with its input chunk 0 (the finest transposed convolution of d1b)
+// computed per patch: cat0's first 32 channels are neither written nor read
+hipError_t dec0a_fused(unet_state *n, unet_act *a, int NB, int H, int W, hipStream_t s)
+{
+    const unet_layer &l = layers().L[L_D0A], &u = layers().L[L_UP0];
+    GemmArgs g{};
+    g.A = n->wf + l.wf_off;
+    g.Bsrc = a->cat0;
+    g.b_cs = 64;
+    g.bias = n->w + l.b_off;
+    g.out = a->d0a;
+    g.o_cs = 32;
+    g.NB = NB;
+    g.H = H;
+    g.W = W;
+    g.K = l.cin_pad;
+    g.M = l.cout;
+    g.up_in = a->d1b;
+    g.up_w = n->wf + u.wf_off;
+    g.up_b = n->w + u.b_off;
+    if (g.K != 64 || g.M != 32 || u.cout != 32 || u.cin_pad != 64) return hipErrorInvalidValue;
+    return conv3w_launch<8, 2, EPI_RELU_BF16, false, true>(g, s);
+}
+
+// The forward pass up to the last 3x3 convolution.  fuse_up0 lets the
+// finest transposed convolution run inside dec0a (inference; its output is
+// then not stored).
+hipError_t forward_all(unet_state *n, unet_act *a, const uint16_t *stack, int NB, int H, int W, hipStream_t s,
+                       bool fuse_up0 = false)
 {
     a->NB = NB;
     a->H = H;
@@ -1527,8 +1653,13 @@ hipError_t forward_all(unet_state *n, unet_act *a, const uint16_t *stack, int NB
     NCHK(convT_fwd(n, L_UP1, a->d2b, 128, NB, H2, W2, a->cat1, 128, s));
     NCHK(conv_fwd(n, L_D1A, a->cat1, 128, 0, a->d1a, 64, 0, NB, H1, W1, s));
     NCHK(conv_fwd(n, L_D1B, a->d1a, 64, 0, a->d1b, 64, 0, NB, H1, W1, s));
-    NCHK(convT_fwd(n, L_UP0, a->d1b, 64, NB, H1, W1, a->cat0, 64, s));
-    NCHK(conv_fwd(n, L_D0A, a->cat0, 64, 0, a->d0a, 32, 0, NB, H, W, s));
+    a->up0_stored = !(fuse_up0 && up0_fusable(NB, H, W));
+    if (a->up0_stored) {
+        NCHK(convT_fwd(n, L_UP0, a->d1b, 64, NB, H1, W1, a->cat0, 64, s));
+        NCHK(conv_fwd(n, L_D0A, a->cat0, 64, 0, a->d0a, 32, 0, NB, H, W, s));
+    } else {
+        NCHK(dec0a_fused(n, a, NB, H, W, s));
+    }
     NCHK(conv_fwd(n, L_D0B, a->d0a, 32, 0, a->d0b, 32, 0, NB, H, W, s));
     return hipSuccess;
 }
@@ -1721,7 +1852,7 @@ hipError_t unet_get_grads(unet_state *n, float *host, hipStream_t s)
 
 hipError_t unet_forward(unet_state *n, unet_act *a, const uint16_t *stack, int NB, int H, int W, float *s_out,
                            uint8_t *rgb, int64_t pitch, int64_t img_stride, int valid_h, int valid_w,
-                           hipStream_t s, std::string &err)
+                           hipStream_t s, std::string &err, bool keep)
 {
     if (!n->loaded) {
         err = "no network parameters loaded";
@@ -1745,14 +1876,14 @@ hipError_t unet_forward(unet_state *n, unet_act *a, const uint16_t *stack, int N
     h.W = W;
     h.valid_h = valid_h;
     h.valid_w = valid_w;
-    NCHK(forward_all(n, a, stack, NB, H, W, s));
+    NCHK(forward_all(n, a, stack, NB, H, W, s, !keep));
     const int P = NB * H * W;
     hipLaunchKernelGGL(k_head, dim3((P + 255) / 256), dim3(256), 0, s, h, 0);
     return hipGetLastError();
 }
 
 hipError_t unet_forward_batch(unet_state *n, unet_act *a, const uint16_t *stack, int NB, int H, int W,
-                              const unet_out *outs, hipStream_t s, std::string &err)
+                              const unet_out *outs, hipStream_t s, std::string &err, bool keep)
 {
     if (!n->loaded) {
         err = "no network parameters loaded";
@@ -1771,7 +1902,7 @@ hipError_t unet_forward_batch(unet_state *n, unet_act *a, const uint16_t *stack,
     h.NB = NB;
     h.H = H;
     h.W = W;
-    NCHK(forward_all(n, a, stack, NB, H, W, s));
+    NCHK(forward_all(n, a, stack, NB, H, W, s, !keep));
     const int P = NB * H * W;
     hipLaunchKernelGGL(k_head, dim3((P + 255) / 256), dim3(256), 0, s, h, 0);
     return hipGetLastError();
@@ -1906,7 +2037,12 @@ hipError_t unet_read_act(unet_act *a, int layer, void *host, size_t bytes, hipSt
     case L_UP1: src = a->cat1; cs = 128; C = 64; break;
     case L_D1A: src = a->d1a; cs = 64; C = 64; break;
     case L_D1B: src = a->d1b; cs = 64; C = 64; break;
-    case L_UP0: src = a->cat0; cs = 64; C = 32; break;
+    case L_UP0:
+        if (!a->up0_stored) return hipErrorInvalidValue;
+        src = a->cat0;
+        cs = 64;
+        C = 32;
+        break;
     case L_D0A: src = a->d0a; cs = 32; C = 32; break;
     case L_D0B: src = a->d0b; cs = 32; C = 32; break;
     default: return hipErrorInvalidValue;

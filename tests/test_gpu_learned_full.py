@@ -119,8 +119,10 @@ def test_forward_two_960x544_views(fvv, ctx, oracle_lib, rig9):
     st = np.stack([view_stack(oracle_lib, rig9, a)[1] for a in (-22.0, 37.0)])
     out = torch.empty((N, H, W, 3), dtype=torch.float32, device="cuda")
     say("[gpu] learned-full: forward 2x960x544")
+    ctx.set_debug(True)        # keep every layer's output for the comparison
     ctx.net_forward(to_device_stack(st), N, H, W, out)
     torch.cuda.synchronize()
+    ctx.set_debug(False)
     s_gpu = out.cpu().numpy()
     for q in range(N):
         say(f"[gpu] learned-full: oracle forward of view {q}")
@@ -237,6 +239,7 @@ def test_weights_resident_conv_equals_per_patch_conv(fvv, ctx):
     st = st.to(torch.bfloat16).view(torch.int16).contiguous()
     say("[gpu] learned-full: resident vs per-patch 3x3 convolutions")
     two = torch.empty((2, H, W, 3), dtype=torch.float32, device="cuda")
+    ctx.set_debug(True)        # every layer kept (the finest transposed convolution on its own)
     ctx.net_forward(st, 2, H, W, two)
     torch.cuda.synchronize()
     layers = layer_list()[:-1]
@@ -250,6 +253,35 @@ def test_weights_resident_conv_equals_per_patch_conv(fvv, ctx):
         for li, (name, kind, ci, co) in enumerate(layers):
             a = ctx.net_read_act(li, (px[li], co))
             assert np.array_equal(a, acts_two[li].reshape(2, px[li], co)[q]), (name, q)
+    ctx.set_debug(False)
+
+
+def test_fused_transposed_convolution_equals_stored(fvv, ctx):
+    """Without debug taps a forward of 2,048 patches or more computes the
+    finest transposed convolution inside the convolution that reads it (its
+    output is never stored): the network's output must be the bytes of the
+    forward that stores every layer, for the production batch of 16 960x544
+    stacks and for two 512x256 stacks, and reading that layer must fail."""
+    import torch
+    ctx.net_load(flat(rand_params(88)))
+    g = torch.Generator(device="cuda").manual_seed(89)
+    for n, H, W in ((16, 544, 960), (2, 256, 512)):
+        st = torch.rand((n, H, W, fvv.NET_IN), device="cuda", generator=g)
+        st[..., 15] = 0
+        st = st.to(torch.bfloat16).view(torch.int16).contiguous()
+        say(f"[gpu] learned-full: fused vs stored finest transposed convolution, {n}x{W}x{H}")
+        fused = torch.empty((n, H, W, 3), dtype=torch.float32, device="cuda")
+        ctx.net_forward(st, n, H, W, fused)
+        torch.cuda.synchronize()
+        up0 = [li for li, (name, *_) in enumerate(layer_list()) if name == "up0"][0]
+        with pytest.raises(fvv.FvvError):
+            ctx.net_read_act(up0, (n * H * W, 32))
+        ctx.set_debug(True)
+        kept = torch.empty((n, H, W, 3), dtype=torch.float32, device="cuda")
+        ctx.net_forward(st, n, H, W, kept)
+        torch.cuda.synchronize()
+        ctx.set_debug(False)
+        assert torch.equal(fused, kept), (n, H, W)
 
 
 def layer_list():
