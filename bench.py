@@ -33,13 +33,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 
 
 def kernel_source_sha() -> str:
-    """Hash of the sources the plain path's kernels are compiled from (a
-    counter summary taken from other sources no longer describes them)."""
+    """Hash of the code the plain path's kernels are compiled from, comments
+    and blank space left out (a counter summary taken from other code no
+    longer describes them)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("fvv_kernels.hip", "fvv_internal.h"):
-        with open(os.path.join(ROOT, "paper_2007_00558_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_2007_00558_amd", "csrc", f), encoding="utf-8") as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", " ", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 

@@ -6,12 +6,13 @@
 //              decoded to millimetres) -> metres with the Eq. (1) correction
 //              (Section IV-A)
 //   desc       copy of the view descriptors from coherent pinned host memory
-//   bin        every 8x8 block of each selected source camera is bounded in
-//              the virtual image from the 8 corners of its pixel-and-depth
-//              frustum section and appended to the lists of the output tiles
-//              it may touch
+//   bin        every pixel of each selected source camera is warped into
+//              the virtual image once: its splat record (projected depth and
+//              packed footprint) is stored, and each 8x8 source block,
+//              bounded by the exact union of its pixels' footprints, is
+//              appended to the lists of the output tiles it touches
 //   tile       one workgroup per 32x32 output tile: splats its binned blocks
-//              (3D warping of each valid pixel) into an LDS z-buffer of packed
+//              (from their pixels' splat records) into an LDS z-buffer of packed
 //              (depth, camera, pixel) keys with 64-bit LDS atomicMin, 3x3
 //              crack/speckle filter in LDS, backward depth-consistent
 //              bilinear fetch from each selected camera mixed by camera
