@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define FVV_ABI_VERSION 9
+#define FVV_ABI_VERSION 10
 
 /* status codes */
 enum {
@@ -360,6 +360,14 @@ int32_t fvv_measure_peaks(int32_t hip_device, double *out, int32_t n);
  * *mismatches (host memory; 0 expected).  Synchronous on hip_device; returns
  * FVV_OK or an error (text in fvv_last_error(NULL)). */
 int32_t fvv_check_reciprocal(int32_t hip_device, int32_t e_lo, int32_t e_hi, uint64_t *mismatches);
+
+/* Self-check of the network's bfloat16 rounding (every stored tensor of the
+ * learned path is rounded to bfloat16, round to nearest even): the
+ * hardware conversion the kernels use against the rounding written out on
+ * the bit pattern, for all 2^32 float32 patterns but the NaNs.  Writes the
+ * number of mismatches to *mismatches (host memory; 0 expected).
+ * Synchronous on hip_device; returns FVV_OK or an error. */
+int32_t fvv_check_bf16(int32_t hip_device, uint64_t *mismatches);
 
 /* Stage timing (tracing).  With profiling on, every kernel the context
  * launches is bracketed by HIP events on the caller's stream (this adds a

@@ -89,6 +89,7 @@ def lib():
             "fvv_set_debug_view": (I32, [P, I32]),
             "fvv_measure_peaks": (I32, [I32, P, I32]),
             "fvv_check_reciprocal": (I32, [I32, I32, I32, P]),
+            "fvv_check_bf16": (I32, [I32, P]),
             "fvv_debug_read": (I32, [P, I32, P, I64]),
             "fvv_set_profiling": (I32, [P, I32]),
             "fvv_stage_count": (I32, []),
@@ -140,7 +141,8 @@ EXPORTED = ("fvv_abi_version", "fvv_create", "fvv_destroy", "fvv_last_error", "f
             "fvv_depth_decode_y12", "fvv_set_depth_format", "fvv_set_bg_model", "fvv_set_prefilter",
             "fvv_read_frame_depth", "fvv_tx_cameras", "fvv_server_tx_cameras",
             "fvv_depth_encode_y12_batch", "fvv_depth_decode_y12_batch", "fvv_synthesize_noalloc",
-            "fvv_set_debug_view", "fvv_measure_peaks", "fvv_check_reciprocal")
+            "fvv_set_debug_view", "fvv_measure_peaks", "fvv_check_reciprocal",
+            "fvv_check_bf16")
 DEPTH_MM16, DEPTH_Y12 = 0, 1
 NET_PARAMS, NET_GRADS = 0, 1
 NET_ALIGN = 8           # network inputs: multiples of 8 in both dimensions
@@ -228,6 +230,17 @@ def check_reciprocal(device: int = 0, e_lo: int = -7, e_hi: int = 20) -> int:
     binades 2^e_lo .. 2^e_hi, on the device."""
     bad = np.zeros(1, np.uint64)
     rc = lib().fvv_check_reciprocal(device, e_lo, e_hi, bad.ctypes.data)
+    if rc < 0:
+        raise FvvError(rc, lib().fvv_last_error(None).decode())
+    return int(bad[0])
+
+
+def check_bf16(device: int = 0) -> int:
+    """Mismatches of the network kernels' bfloat16 rounding (hardware
+    conversion) against round-to-nearest-even on the bits, over every
+    non-NaN float32, on the device."""
+    bad = np.zeros(1, np.uint64)
+    rc = lib().fvv_check_bf16(device, bad.ctypes.data)
     if rc < 0:
         raise FvvError(rc, lib().fvv_last_error(None).decode())
     return int(bad[0])

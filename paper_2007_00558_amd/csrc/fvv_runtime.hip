@@ -1796,6 +1796,27 @@ int32_t fvv_check_reciprocal(int32_t hip_device, int32_t e_lo, int32_t e_hi, uin
     return FVV_OK;
 }
 
+int32_t fvv_check_bf16(int32_t hip_device, uint64_t *mismatches)
+{
+    if (!mismatches) return fail(nullptr, FVV_E_ARG, "mismatches is null");
+    int nd = 0;
+    hipError_t e = hipGetDeviceCount(&nd);
+    if (e != hipSuccess) return fail(nullptr, FVV_E_DEVICE, "hipGetDeviceCount: %s", hipGetErrorString(e));
+    if (hip_device < 0 || hip_device >= nd) return fail(nullptr, FVV_E_ARG, "device %d outside 0..%d", hip_device, nd - 1);
+    DeviceGuard g(hip_device);
+    unsigned long long *bad = nullptr;
+    if ((e = hipMalloc((void **)&bad, sizeof *bad)) != hipSuccess)
+        return fail(nullptr, FVV_E_NOMEM, "hipMalloc: %s", hipGetErrorString(e));
+    unsigned long long h = 0;
+    e = hipMemcpy(bad, &h, sizeof h, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = unet_check_bf16(bad, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(&h, bad, sizeof h, hipMemcpyDeviceToHost);
+    (void)hipFree(bad);
+    if (e != hipSuccess) return fail(nullptr, FVV_E_DEVICE, "bfloat16 check: %s", hipGetErrorString(e));
+    *mismatches = h;
+    return FVV_OK;
+}
+
 int32_t fvv_select_cameras(const fvv_camera *rig, const int32_t *present, int32_t n, const fvv_camera *virt,
                            int32_t k, int32_t *idx, float *w)
 {

@@ -88,3 +88,7 @@ hipError_t unet_train(unet_state *n, unet_act *a, const uint16_t *stack, const f
 // layer's channels only) to host memory, for parity checks; an error for
 // the finest transposed convolution when the last forward did not keep it.
 hipError_t unet_read_act(unet_act *a, int layer, void *host, size_t bytes, hipStream_t s);
+// Adds to *bad_dev (device memory) the number of non-NaN float32 bit
+// patterns whose bfloat16 rounding by the hardware conversion the kernels
+// use differs from round-to-nearest-even written out on the bits.
+hipError_t unet_check_bf16(unsigned long long *bad_dev, hipStream_t s);

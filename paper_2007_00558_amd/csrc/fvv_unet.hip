@@ -25,13 +25,28 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 enum { TAP_CONV3 = 0, TAP_ONE = 1, TAP_FINE4 = 2 };
 enum { EPI_RELU_BF16 = 0, EPI_F32 = 1, EPI_CONVT_BF16 = 2 };
 
-__device__ __forceinline__ uint16_t f2bf(float f)
+// bfloat16 rounding to nearest even, written out on the bit pattern (the
+// definition the hardware conversion below is checked against)
+__device__ __forceinline__ uint16_t f2bf_ref(float f)
 {
     uint32_t u = __float_as_uint(f);
     if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);   // quiet NaN
     u += 0x7fffu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
 }
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// Two float32 values to packed bfloat16 (lo in the low half) with
+// v_cvt_pk_bf16_f32, round to nearest even: the bits of f2bf_ref for every
+// input but NaNs (fvv_check_bf16 compares the two over all 2^32 patterns).
+__device__ __forceinline__ uint32_t pack_bf16(float lo, float hi)
+{
+    const f32x2 v = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2));
+}
+__device__ __forceinline__ uint16_t f2bf(float f) { return (uint16_t)pack_bf16(f, 0.f); }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 __device__ __forceinline__ bf16x8 ld8(const uint16_t *p) { return __builtin_bit_cast(bf16x8, *(const uint4 *)p); }
@@ -159,8 +174,8 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
                 v2 = fmaxf(v2 + g.bias[m0 + 2], 0.f);
                 v3 = fmaxf(v3 + g.bias[m0 + 3], 0.f);
                 uint16_t *o = (uint16_t *)g.out + pix * g.o_cs + g.o_off + m0;
-                *(uint2 *)o = make_uint2((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16),
-                                         (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16));
+                *(uint2 *)o = make_uint2(pack_bf16(v0, v1),
+                                         pack_bf16(v2, v3));
             } else {
                 const int d = m0 / g.cout, co = m0 - d * g.cout;
                 const int64_t fp = ((int64_t)pb[n] * 2 * g.H + 2 * py[n] + (d >> 1)) * (2 * g.W) + 2 * px[n] + (d & 1);
@@ -169,8 +184,8 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
                 v2 += g.bias[co + 2];
                 v3 += g.bias[co + 3];
                 uint16_t *o = (uint16_t *)g.out + fp * g.o_cs + g.o_off + co;
-                *(uint2 *)o = make_uint2((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16),
-                                         (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16));
+                *(uint2 *)o = make_uint2(pack_bf16(v0, v1),
+                                         pack_bf16(v2, v3));
             }
         }
     }
@@ -328,8 +343,8 @@ __global__ void __launch_bounds__(256) k_conv3(const GemmArgs g)
                     v2 = fmaxf(v2 + g.bias[m0 + 2], 0.f);
                     v3 = fmaxf(v3 + g.bias[m0 + 3], 0.f);
                     *(uint2 *)((uint16_t *)g.out + pix * g.o_cs + g.o_off + m0) =
-                        make_uint2((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16),
-                                   (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16));
+                        make_uint2(pack_bf16(v0, v1),
+                                   pack_bf16(v2, v3));
                 }
             }
     }
@@ -445,10 +460,8 @@ __global__ void __launch_bounds__(256) k_conv3w(const GemmArgs g)
                 for (int j = 0; j < 4; ++j) {
                     uint2 w2 = make_uint2(0, 0);
                     if (in)
-                        w2 = make_uint2((uint32_t)f2bf(up_u[n][4 * j + 0] + up_bias[4 * j + 0]) |
-                                            ((uint32_t)f2bf(up_u[n][4 * j + 1] + up_bias[4 * j + 1]) << 16),
-                                        (uint32_t)f2bf(up_u[n][4 * j + 2] + up_bias[4 * j + 2]) |
-                                            ((uint32_t)f2bf(up_u[n][4 * j + 3] + up_bias[4 * j + 3]) << 16));
+                        w2 = make_uint2(pack_bf16(up_u[n][4 * j + 0] + up_bias[4 * j + 0], up_u[n][4 * j + 1] + up_bias[4 * j + 1]),
+                                        pack_bf16(up_u[n][4 * j + 2] + up_bias[4 * j + 2], up_u[n][4 * j + 3] + up_bias[4 * j + 3]));
                     *(uint2 *)(dst + 16 * j) = w2;
                 }
             }
@@ -549,8 +562,8 @@ __global__ void __launch_bounds__(256) k_conv3w(const GemmArgs g)
                     v2 = fmaxf(v2 + g.bias[m0 + 2], 0.f);
                     v3 = fmaxf(v3 + g.bias[m0 + 3], 0.f);
                     *(uint2 *)((uint16_t *)g.out + pix * g.o_cs + g.o_off + m0) =
-                        make_uint2((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16),
-                                   (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16));
+                        make_uint2(pack_bf16(v0, v1),
+                                   pack_bf16(v2, v3));
                     v[4 * j + 0] = v0;
                     v[4 * j + 1] = v1;
                     v[4 * j + 2] = v2;
@@ -583,8 +596,8 @@ __global__ void __launch_bounds__(256) k_conv3w(const GemmArgs g)
                     }
                 const int64_t pp = ((int64_t)b * (g.H / 2) + (py >> 1)) * (g.W / 2) + (px >> 1);
                 *(uint2 *)(g.pool + pp * 32 + 8 * jsel + 4 * lh) =
-                    make_uint2((uint32_t)f2bf(q0) | ((uint32_t)f2bf(q1) << 16),
-                               (uint32_t)f2bf(q2) | ((uint32_t)f2bf(q3) << 16));
+                    make_uint2(pack_bf16(q0, q1),
+                               pack_bf16(q2, q3));
             }
         }
         cur = nxt;
@@ -671,8 +684,8 @@ __global__ void __launch_bounds__(256) k_gemm1(const GemmArgs g)
                     v2 += g.bias[co + 2];
                     v3 += g.bias[co + 3];
                     *(uint2 *)((uint16_t *)g.out + fp * g.o_cs + g.o_off + co) =
-                        make_uint2((uint32_t)f2bf(v0) | ((uint32_t)f2bf(v1) << 16),
-                                   (uint32_t)f2bf(v2) | ((uint32_t)f2bf(v3) << 16));
+                        make_uint2(pack_bf16(v0, v1),
+                                   pack_bf16(v2, v3));
                 } else {
                     *(float4 *)((float *)g.out + (int64_t)p * g.o_cs + g.o_off + m0) = make_float4(v0, v1, v2, v3);
                 }
@@ -737,8 +750,8 @@ __global__ void __launch_bounds__(256) k_convT(const GemmArgs g)
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const float4 bj = *(const float4 *)(g.bias + co0 + 8 * j + 4 * lh);
-                w[j][0] = (uint32_t)f2bf(acc[i][4 * j + 0] + bj.x) | ((uint32_t)f2bf(acc[i][4 * j + 1] + bj.y) << 16);
-                w[j][1] = (uint32_t)f2bf(acc[i][4 * j + 2] + bj.z) | ((uint32_t)f2bf(acc[i][4 * j + 3] + bj.w) << 16);
+                w[j][0] = pack_bf16(acc[i][4 * j + 0] + bj.x, acc[i][4 * j + 1] + bj.y);
+                w[j][1] = pack_bf16(acc[i][4 * j + 2] + bj.z, acc[i][4 * j + 3] + bj.w);
             }
             // lanes < 32 end up with channels 16 q + 0..7, lanes >= 32 with
             // 16 q + 8..15 (q = 0, 1)
@@ -1197,6 +1210,20 @@ __global__ void __launch_bounds__(256) k_adam(const AdamArgs a)
         else
             a.wd[((int64_t)ci * a.taps + td) * a.cout + co] = wb;
     }
+}
+
+// Every float32 bit pattern but the NaNs: the hardware conversion against
+// the written-out rounding.
+__global__ void __launch_bounds__(256) k_check_bf16(unsigned long long *bad)
+{
+    uint32_t miss = 0;
+    const uint32_t stride = gridDim.x * 256u;
+    for (uint32_t u = blockIdx.x * 256u + threadIdx.x;; u += stride) {
+        const float f = __uint_as_float(u);
+        if (!((u & 0x7fffffffu) > 0x7f800000u)) miss += (uint16_t)pack_bf16(f, 0.f) != f2bf_ref(f);
+        if (u > 0xFFFFFFFFu - stride) break;
+    }
+    if (miss) atomicAdd(bad, (unsigned long long)miss);
 }
 
 // ---------------------------------------------------------------- host side
@@ -2052,4 +2079,10 @@ hipError_t unet_read_act(unet_act *a, int layer, void *host, size_t bytes, hipSt
     if (bytes != P * C * 2) return hipErrorInvalidValue;
     NCHK(hipStreamSynchronize(s));
     return hipMemcpy2D(host, (size_t)C * 2, src + off, (size_t)cs * 2, (size_t)C * 2, P, hipMemcpyDeviceToHost);
+}
+
+hipError_t unet_check_bf16(unsigned long long *bad_dev, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_check_bf16, dim3(4096), dim3(256), 0, s, bad_dev);
+    return hipGetLastError();
 }

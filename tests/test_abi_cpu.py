@@ -27,7 +27,7 @@ def test_library_exports_every_declared_function():
     for name in names:
         assert hasattr(L, name), name
     assert set(names) == set(fvv.EXPORTED)
-    assert L.fvv_abi_version() == 9
+    assert L.fvv_abi_version() == 10
 
 
 def test_header_struct_layouts_match_binding():
