@@ -207,7 +207,19 @@ constexpr int C3_RS = 9 * 64 + 16;     // bytes per staged weight row
 template <int MT, int TH>
 constexpr int c3_lds_bytes() { return (TH + 2) * 18 * C3_PXS + 32 * MT * C3_RS; }
 
-template <int MT, int TH, int EPI>
+// 2x2 max-pool in a convolution epilogue: the window of a pooled pixel is
+// lanes lc, lc^1 (columns) and lc^16 (rows) of the wave (patch origins, rows
+// and widths even); returns the window's maximum of v (float32 before the
+// bfloat16 rounding, whose maximum is the rounded maximum).
+__device__ __forceinline__ float pool_max4(float v)
+{
+    const float m = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF,
+                                                                         false)));   // quad_perm 1,0,3,2
+    const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(m), __float_as_uint(m), false, false);
+    return fmaxf(__uint_as_float(sw[0]), __uint_as_float(sw[1]));
+}
+
+template <int MT, int TH, int EPI, bool POOL = false>
 __global__ void __launch_bounds__(256) k_conv3(const GemmArgs g)
 {
     static_assert(TH % 8 == 0, "each wave takes TH/4 rows, two per 32-pixel tile");
@@ -345,6 +357,18 @@ __global__ void __launch_bounds__(256) k_conv3(const GemmArgs g)
                     *(uint2 *)((uint16_t *)g.out + pix * g.o_cs + g.o_off + m0) =
                         make_uint2(pack_bf16(v0, v1),
                                    pack_bf16(v2, v3));
+                    if (POOL) {
+                        // the window's four lanes share its maxima; lane
+                        // (column bit a, row bit c) writes group j = 2 c + a
+                        v0 = pool_max4(v0);
+                        v1 = pool_max4(v1);
+                        v2 = pool_max4(v2);
+                        v3 = pool_max4(v3);
+                        if (j == 2 * ((lc >> 4) & 1) + (lc & 1)) {
+                            const int64_t pp = ((int64_t)b * (g.H / 2) + (py >> 1)) * (g.W / 2) + (px >> 1);
+                            *(uint2 *)(g.pool + pp * g.M + m0) = make_uint2(pack_bf16(v0, v1), pack_bf16(v2, v3));
+                        }
+                    }
                 }
             }
     }
@@ -576,12 +600,7 @@ __global__ void __launch_bounds__(256) k_conv3w(const GemmArgs g)
                 // (patch origins, rows and widths are even).  The max of the
                 // float32 values rounds to the max of their bfloat16 values.
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    float m = fmaxf(v[r], __int_as_float(__builtin_amdgcn_update_dpp(
-                                              0, __float_as_int(v[r]), 0xB1, 0xF, 0xF, false)));   // quad_perm 1,0,3,2
-                    const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(m), __float_as_uint(m), false, false);
-                    v[r] = fmaxf(__uint_as_float(sw[0]), __uint_as_float(sw[1]));
-                }
+                for (int r = 0; r < 16; ++r) v[r] = pool_max4(v[r]);
                 // the four lanes of a window share its 32 channels' maxima;
                 // lane (column bit a, row bit c) writes group j = 2 c + a
                 const int jsel = 2 * ((lc >> 4) & 1) + (lc & 1);
@@ -1497,14 +1516,14 @@ hipError_t gemm(const GemmArgs &g, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int MT, int TH, int EPI>
+template <int MT, int TH, int EPI, bool POOL = false>
 hipError_t conv3_launch(const GemmArgs &g, hipStream_t s)
 {
     constexpr int lds = c3_lds_bytes<MT, TH>();
     static_assert(lds <= 65536, "staged patch and weights must fit 64 KB");
     const int tiles = ((g.W + 15) / 16) * ((g.H + TH - 1) / TH) * g.NB;
     dim3 grid(tiles, (g.M + 32 * MT - 1) / (32 * MT));
-    hipLaunchKernelGGL((k_conv3<MT, TH, EPI>), grid, dim3(256), lds, s, g);
+    hipLaunchKernelGGL((k_conv3<MT, TH, EPI, POOL>), grid, dim3(256), lds, s, g);
     return hipGetLastError();
 }
 
@@ -1543,9 +1562,14 @@ hipError_t conv3(GemmArgs g, hipStream_t s, bool *pooled = nullptr)
         return conv3w_launch<8, 1, EPI, false>(g, s);
     }
     if (g.M == 32 && g.K == 64 && tiles8 >= 2048) return conv3w_launch<8, 2, EPI, false>(g, s);
-    if (g.M <= 32) return conv3_launch<1, 8, EPI>(g, s);
-    if ((int64_t)g.NB * g.H * g.W >= 65536) return conv3_launch<2, 16, EPI>(g, s);
-    return conv3_launch<1, 8, EPI>(g, s);
+    const bool big = g.M > 32 && (int64_t)g.NB * g.H * g.W >= 65536;
+    if constexpr (EPI == EPI_RELU_BF16) {
+        if (pooled && g.pool && g.H % 2 == 0 && g.W % 2 == 0) {
+            *pooled = true;
+            return big ? conv3_launch<2, 16, EPI, true>(g, s) : conv3_launch<1, 8, EPI, true>(g, s);
+        }
+    }
+    return big ? conv3_launch<2, 16, EPI>(g, s) : conv3_launch<1, 8, EPI>(g, s);
 }
 
 // 3x3 conv + bias + ReLU into (out, o_cs, o_off); with pool_out, *pooled
@@ -1667,11 +1691,11 @@ hipError_t forward_all(unet_state *n, unet_act *a, const uint16_t *stack, int NB
     NCHK(conv_fwd(n, L_E0B, a->e0a, 32, 0, a->cat0, 64, 32, NB, H, W, s, a->p1, &pooled));
     if (!pooled) NCHK(pool(a->cat0, 64, 32, a->p1, NB, H, W, 32, s));
     NCHK(conv_fwd(n, L_E1A, a->p1, 32, 0, a->e1a, 64, 0, NB, H1, W1, s));
-    NCHK(conv_fwd(n, L_E1B, a->e1a, 64, 0, a->cat1, 128, 64, NB, H1, W1, s));
-    NCHK(pool(a->cat1, 128, 64, a->p2, NB, H1, W1, 64, s));
+    NCHK(conv_fwd(n, L_E1B, a->e1a, 64, 0, a->cat1, 128, 64, NB, H1, W1, s, a->p2, &pooled));
+    if (!pooled) NCHK(pool(a->cat1, 128, 64, a->p2, NB, H1, W1, 64, s));
     NCHK(conv_fwd(n, L_E2A, a->p2, 64, 0, a->e2a, 128, 0, NB, H2, W2, s));
-    NCHK(conv_fwd(n, L_E2B, a->e2a, 128, 0, a->cat2, 256, 128, NB, H2, W2, s));
-    NCHK(pool(a->cat2, 256, 128, a->p3, NB, H2, W2, 128, s));
+    NCHK(conv_fwd(n, L_E2B, a->e2a, 128, 0, a->cat2, 256, 128, NB, H2, W2, s, a->p3, &pooled));
+    if (!pooled) NCHK(pool(a->cat2, 256, 128, a->p3, NB, H2, W2, 128, s));
     NCHK(conv_fwd(n, L_MA, a->p3, 128, 0, a->ma, 256, 0, NB, H3, W3, s));
     NCHK(conv_fwd(n, L_MB, a->ma, 256, 0, a->mb, 256, 0, NB, H3, W3, s));
     NCHK(convT_fwd(n, L_UP2, a->mb, 256, NB, H3, W3, a->cat2, 256, s));
