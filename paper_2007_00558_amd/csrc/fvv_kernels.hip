@@ -51,11 +51,15 @@ static_assert(T % 4 == 0 && TNT % 64 == 0 && TNT >= 2 * T && TNT <= 1024, "tile 
 
 __device__ __forceinline__ uint32_t f2u(float f) { return __float_as_uint(f); }
 __device__ __forceinline__ float u2f(uint32_t u) { return __uint_as_float(u); }
-// float -> bfloat16 bits, round to nearest even (inputs here are finite)
-__device__ __forceinline__ uint32_t bf16_rne(float f)
+// two float32 values to packed bfloat16 bits (lo in the low half), round
+// to nearest even, by v_cvt_pk_bf16_f32 (fvv_check_bf16 compares it with
+// the rounding written out on the bits over every non-NaN float32)
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16_pack(float lo, float hi)
 {
-    const uint32_t u = __float_as_uint(f);
-    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    const f32x2_t v = {lo, hi};
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, bf16x2_t));
 }
 
 // p_r = ((M_r0 i + M_r1 j) + M_r2) z + m_r, each op rounded to float32
@@ -511,12 +515,15 @@ __device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int k0, int
 // last one zero), 32 bytes per pixel.
 __device__ __forceinline__ void stack_pixel(const fvv_view_desc &vd, int x, int y, unsigned long long kf)
 {
-    uint32_t ch[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // channel c in ch[c / 2], low half for even c
-    auto put = [&](int c, float v) { ch[c >> 1] |= (uint32_t)bf16_rne(v) << (16 * (c & 1)); };
+    float ch[16];   // channel values, rounded to bfloat16 at the end
+#pragma unroll
+    for (int c = 0; c < 16; ++c) ch[c] = 0.f;
     if (kf != FVV_KEY_EMPTY) {
         const float zf = u2f((uint32_t)(kf >> 32));
         const int K = min(vd.K, 3);
-        for (int k = 0; k < K; ++k) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (k >= K) break;
             const fvv_src_desc &s = vd.src[k];
             float q0, q1, q2;
             project(s.B, s.b, (float)x, (float)y, zf, q0, q1, q2);
@@ -544,17 +551,21 @@ __device__ __forceinline__ void stack_pixel(const fvv_view_desc &vd, int x, int 
                 csum += wt[n];
             }
             if (!(csum > 0.f)) continue;
-            put(5 * k + 0, __fdiv_rn(__fdiv_rn(c0, csum), 255.0f));
-            put(5 * k + 1, __fdiv_rn(__fdiv_rn(c1, csum), 255.0f));
-            put(5 * k + 2, __fdiv_rn(__fdiv_rn(c2, csum), 255.0f));
-            const float inv = __fdiv_rn(0.5f, q2);
-            put(5 * k + 3, inv < 1.0f ? inv : 1.0f);
-            put(5 * k + 4, 1.0f);
+            // colour / csum / 255: value arithmetic (within a bfloat16 step
+            // of the exact quotient); the inverse depth 0.5 / q2 is exact:
+            // half of the correctly rounded reciprocal
+            const float ic = __builtin_amdgcn_rcpf(csum) * (1.0f / 255.0f);
+            ch[5 * k + 0] = c0 * ic;
+            ch[5 * k + 1] = c1 * ic;
+            ch[5 * k + 2] = c2 * ic;
+            ch[5 * k + 3] = fminf(0.5f * r, 1.0f);
+            ch[5 * k + 4] = 1.0f;
         }
     }
     uint4 *o = (uint4 *)(vd.stack + ((int64_t)y * vd.stack_w + x) * 16);
-    o[0] = make_uint4(ch[0], ch[1], ch[2], ch[3]);
-    o[1] = make_uint4(ch[4], ch[5], ch[6], ch[7]);
+    o[0] = make_uint4(bf16_pack(ch[0], ch[1]), bf16_pack(ch[2], ch[3]), bf16_pack(ch[4], ch[5]), bf16_pack(ch[6], ch[7]));
+    o[1] = make_uint4(bf16_pack(ch[8], ch[9]), bf16_pack(ch[10], ch[11]), bf16_pack(ch[12], ch[13]),
+                      bf16_pack(ch[14], ch[15]));
 }
 
 __device__ __forceinline__ void put_rgb(uint8_t *out, int64_t pitch, int x, int y, uint32_t c)

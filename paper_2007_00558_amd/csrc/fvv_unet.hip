@@ -88,6 +88,48 @@ struct HeadArgs {
     float *part;             // per workgroup: 3*32 weight + 3 bias partials + 1 loss partial
 };
 
+// The head's 1x1 convolution (32 -> 3) of 32 pixels on one MFMA pair: A =
+// the head weights as rows 0..2 of a 32-row tile (the other rows zero),
+// B = the pixels' bfloat16 inputs, lane (lc, lh) holding channels 8 lh ..
+// 8 lh + 7 (b0) and 16 + 8 lh .. 23 + 8 lh (b1) of pixel lc.  Lane lc (< 32)
+// receives z_0..z_2 of pixel lc in d[0..2]; the result of a pixel depends
+// only on its own inputs.
+__device__ __forceinline__ f32x16 head_mfma(const uint16_t *w, bf16x8 b0, bf16x8 b1)
+{
+    const int lane = threadIdx.x & 63, lc = lane & 31, lh = lane >> 5;
+    const bf16x8 zero8 = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+    const bf16x8 a0 = lc < 3 ? ld8(w + lc * 32 + 8 * lh) : zero8;
+    const bf16x8 a1 = lc < 3 ? ld8(w + lc * 32 + 16 + 8 * lh) : zero8;
+    f32x16 d;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) d[r] = 0.f;
+    d = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a0, b0, d, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a1, b1, d, 0, 0, 0);
+}
+
+// Sigmoid outputs of the head for pixel p (image b, row y, column x): the
+// float32 outputs (if h.s_out) and the RGB8 pixel where the three are finite.
+__device__ __forceinline__ void head_store(const HeadArgs &h, const float z[3], int64_t p, int b, int y, int x)
+{
+    float s[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) s[c] = 1.0f / (1.0f + expf(-z[c]));
+    if (h.s_out)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) h.s_out[p * 3 + c] = s[c];
+    const bool fin = isfinite(s[0]) && isfinite(s[1]) && isfinite(s[2]);
+    uint8_t *o = nullptr;
+    if (h.outs) {
+        const unet_out d = h.outs[b];
+        if (y < d.h && x < d.w) o = d.rgb + (int64_t)y * d.pitch + (int64_t)x * 3;
+    } else if (h.rgb && y < h.valid_h && x < h.valid_w) {
+        o = h.rgb + b * h.img_stride + (int64_t)y * h.pitch + (int64_t)x * 3;
+    }
+    if (o && fin)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) o[c] = (uint8_t)fminf(floorf(s[c] * 255.f + 0.5f), 255.f);
+}
+
 // Source pixel of tap t for column pixel (b, y, x); -1 outside.
 template <int TAP>
 __device__ __forceinline__ int64_t tap_src(int b, int y, int x, int t, int H, int W)
@@ -393,9 +435,10 @@ template <int TH, int KC>
 constexpr int c3w_lds_bytes() { return (TH + 2) * 18 * c3w_pxs<KC>() + KC * 32 * C3_RS; }
 
 
-template <int TH, int KC, int EPI, bool POOL, bool UPC = false>
-__global__ void __launch_bounds__(256) k_conv3w(const GemmArgs g)
+template <int TH, int KC, int EPI, bool POOL, bool UPC = false, bool HEAD = false>
+__global__ void __launch_bounds__(256) k_conv3w(const GemmArgs g, const HeadArgs hd)
 {
+    static_assert(!HEAD || (EPI == EPI_RELU_BF16 && TH == 8), "the head follows a ReLU output, one tile per wave");
     static_assert(TH % 8 == 0, "each wave takes TH/4 rows, two per 32-pixel tile");
     static_assert(!UPC || (KC == 2 && TH == 8), "the transposed convolution feeds chunk 0 of 8-row patches");
     constexpr int NT = TH / 8;
@@ -567,6 +610,38 @@ __global__ void __launch_bounds__(256) k_conv3w(const GemmArgs g)
         t /= tiles_x;
         const int tyi = t % tiles_y;
         const int b = t / tiles_y;
+        if constexpr (HEAD) {
+            // the output as in the loop below, then the head on the matrix
+            // cores: the packed bfloat16 halves of lanes l and l + 32 swapped
+            // (v_permlane32_swap) into the B fragments of head_mfma
+            const int py = tyi * TH + wave * (TH / 4) + (lc >> 4), px = txi * 16 + (lc & 15);
+            const bool ok = py < g.H && px < g.W;
+            const int64_t pix = ((int64_t)b * g.H + py) * g.W + px;
+            uint32_t w[4][2];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int m0 = 8 * j + 4 * lh;
+                w[j][0] = pack_bf16(fmaxf(acc[0][4 * j + 0] + g.bias[m0 + 0], 0.f),
+                                    fmaxf(acc[0][4 * j + 1] + g.bias[m0 + 1], 0.f));
+                w[j][1] = pack_bf16(fmaxf(acc[0][4 * j + 2] + g.bias[m0 + 2], 0.f),
+                                    fmaxf(acc[0][4 * j + 3] + g.bias[m0 + 3], 0.f));
+                if (ok) *(uint2 *)((uint16_t *)g.out + pix * g.o_cs + g.o_off + m0) = make_uint2(w[j][0], w[j][1]);
+            }
+            uint4 o[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const auto s0 = __builtin_amdgcn_permlane32_swap(w[2 * q][0], w[2 * q + 1][0], false, false);
+                const auto s1 = __builtin_amdgcn_permlane32_swap(w[2 * q][1], w[2 * q + 1][1], false, false);
+                o[q] = make_uint4(s0[0], s1[0], s0[1], s1[1]);
+            }
+            const f32x16 dz = head_mfma(hd.w, __builtin_bit_cast(bf16x8, o[0]), __builtin_bit_cast(bf16x8, o[1]));
+            if (ok && !lh) {
+                const float z[3] = {dz[0] + hd.bias[0], dz[1] + hd.bias[1], dz[2] + hd.bias[2]};
+                head_store(hd, z, pix, b, py, px);
+            }
+            cur = nxt;
+            continue;
+        }
 #pragma unroll
         for (int n = 0; n < NT; ++n) {
             const int py = tyi * TH + wave * (TH / 4) + 2 * n + (lc >> 4), px = txi * 16 + (lc & 15);
@@ -1099,41 +1174,44 @@ __global__ void __launch_bounds__(256) k_head(const HeadArgs h, int mode)
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int P = h.NB * h.H * h.W;
     const bool in = p < P;
-    float a[32];
+    // z on the matrix cores: the wave's 64 pixels as two 32-pixel columns
+    // (head_mfma), pixel 32 t + lc of the wave in lane lc of column t; the
+    // second column's results move to lanes 32..63 (v_permlane32_swap)
+    const int lane = threadIdx.x & 63, lc = lane & 31, lh = lane >> 5;
+    const int64_t wbase = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63);
+    f32x16 d[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int64_t q = wbase + 32 * t + lc;
+        const bf16x8 zero8 = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
+        const bf16x8 b0 = q < P ? ld8(h.a + q * 32 + 8 * lh) : zero8;
+        const bf16x8 b1 = q < P ? ld8(h.a + q * 32 + 16 + 8 * lh) : zero8;
+        d[t] = head_mfma(h.w, b0, b1);
+    }
     float z[3] = {0.f, 0.f, 0.f};
-    if (in) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const auto sw = __builtin_amdgcn_permlane32_swap(__float_as_uint(d[1][c]), __float_as_uint(d[1][c]), false,
+                                                         false);
+        const float zc = lh ? __uint_as_float(sw[0]) : d[0][c];
+        if (in) z[c] = zc + h.bias[c];
+    }
+    float a[32];
+    if (in && mode != 0)
         for (int q = 0; q < 4; ++q) {
             const uint4 v = *(const uint4 *)(h.a + p * 32 + q * 8);
             const uint16_t *hv = (const uint16_t *)&v;
             for (int j = 0; j < 8; ++j) a[q * 8 + j] = bf2f(hv[j]);
         }
-        for (int c = 0; c < 3; ++c) {
-            float acc = 0.f;
-            for (int ci = 0; ci < 32; ++ci) acc += bf2f(h.w[c * 32 + ci]) * a[ci];
-            z[c] = acc + h.bias[c];
-        }
-    }
-    float s[3];
-    for (int c = 0; c < 3; ++c) s[c] = 1.0f / (1.0f + expf(-z[c]));
     const int b = in ? (int)(p / (h.H * h.W)) : 0;
     const int r = in ? (int)(p % (h.H * h.W)) : 0;
     const int y = r / h.W, x = r - y * h.W;
     if (mode == 0) {
-        if (!in) return;
-        if (h.s_out)
-            for (int c = 0; c < 3; ++c) h.s_out[p * 3 + c] = s[c];
-        const bool fin = isfinite(s[0]) && isfinite(s[1]) && isfinite(s[2]);
-        uint8_t *o = nullptr;
-        if (h.outs) {
-            const unet_out d = h.outs[b];
-            if (y < d.h && x < d.w) o = d.rgb + (int64_t)y * d.pitch + (int64_t)x * 3;
-        } else if (h.rgb && y < h.valid_h && x < h.valid_w) {
-            o = h.rgb + b * h.img_stride + (int64_t)y * h.pitch + (int64_t)x * 3;
-        }
-        if (o && fin)
-            for (int c = 0; c < 3; ++c) o[c] = (uint8_t)fminf(floorf(s[c] * 255.f + 0.5f), 255.f);
+        if (in) head_store(h, z, p, b, y, x);
         return;
     }
+    float s[3];
+    for (int c = 0; c < 3; ++c) s[c] = 1.0f / (1.0f + expf(-z[c]));
     // training
     float gz[3] = {0.f, 0.f, 0.f}, loss = 0.f;
     if (in && y < h.valid_h) {
@@ -1531,24 +1609,26 @@ hipError_t conv3_launch(const GemmArgs &g, hipStream_t s)
 // channels x 8-row patches for 32-channel outputs and for grids under 64 K
 // pixels (more blocks where there are few pixels), else 64 channels x
 // 16-row patches
-template <int TH, int KC, int EPI, bool POOL, bool UPC = false>
-hipError_t conv3w_launch(const GemmArgs &g, hipStream_t s)
+template <int TH, int KC, int EPI, bool POOL, bool UPC = false, bool HEAD = false>
+hipError_t conv3w_launch(const GemmArgs &g, hipStream_t s, const HeadArgs &h = HeadArgs{})
 {
     constexpr int lds = c3w_lds_bytes<TH, KC>();
     static_assert(lds <= 65536, "staged patches and weights must fit 64 KB");
-    static const int grid = std::max(8, resident_blocks(k_conv3w<TH, KC, EPI, POOL, UPC>, lds) / 8 * 8);
-    hipLaunchKernelGGL((k_conv3w<TH, KC, EPI, POOL, UPC>), dim3(grid), dim3(256), lds, s, g);
+    static const int grid = std::max(8, resident_blocks(k_conv3w<TH, KC, EPI, POOL, UPC, HEAD>, lds) / 8 * 8);
+    hipLaunchKernelGGL((k_conv3w<TH, KC, EPI, POOL, UPC, HEAD>), dim3(grid), dim3(256), lds, s, g, h);
     return hipGetLastError();
 }
 
 // *pooled (if given) tells whether the launch also wrote the 2x2 max-pool
-// of the output to g.pool: only the weights-resident kernel with one input
-// chunk does; g.pool is ignored otherwise.
+// of the output to g.pool; *headed (if given) whether it also ran the head
+// (only the weights-resident kernel with one input chunk runs it).
 template <int EPI>
-hipError_t conv3(GemmArgs g, hipStream_t s, bool *pooled = nullptr)
+hipError_t conv3(GemmArgs g, hipStream_t s, bool *pooled = nullptr, const HeadArgs *head = nullptr,
+                 bool *headed = nullptr)
 {
     if (g.K % 32 != 0) return hipErrorInvalidValue;
     if (pooled) *pooled = false;
+    if (headed) *headed = false;
     // 32 output channels from one or two input chunks, with patches for
     // every block several times over: weights resident, blocks walk patches
     const int64_t tiles8 = (int64_t)((g.W + 15) / 16) * ((g.H + 7) / 8) * g.NB;
@@ -1557,6 +1637,10 @@ hipError_t conv3(GemmArgs g, hipStream_t s, bool *pooled = nullptr)
             if (pooled && g.pool) {
                 *pooled = true;
                 return conv3w_launch<8, 1, EPI, true>(g, s);
+            }
+            if (headed && head) {
+                *headed = true;
+                return conv3w_launch<8, 1, EPI, false, false, true>(g, s, *head);
             }
         }
         return conv3w_launch<8, 1, EPI, false>(g, s);
@@ -1573,9 +1657,11 @@ hipError_t conv3(GemmArgs g, hipStream_t s, bool *pooled = nullptr)
 }
 
 // 3x3 conv + bias + ReLU into (out, o_cs, o_off); with pool_out, *pooled
-// tells whether the 2x2 max-pool of the output was written there as well
+// tells whether the 2x2 max-pool of the output was written there as well,
+// with head, *headed whether the head ran on the output as well
 hipError_t conv_fwd(unet_state *n, int li, const uint16_t *in, int i_cs, int i_off, uint16_t *out, int o_cs, int o_off,
-                    int NB, int H, int W, hipStream_t s, uint16_t *pool_out = nullptr, bool *pooled = nullptr)
+                    int NB, int H, int W, hipStream_t s, uint16_t *pool_out = nullptr, bool *pooled = nullptr,
+                    const HeadArgs *head = nullptr, bool *headed = nullptr)
 {
     const unet_layer &l = layers().L[li];
     GemmArgs g{};
@@ -1594,7 +1680,7 @@ hipError_t conv_fwd(unet_state *n, int li, const uint16_t *in, int i_cs, int i_o
     g.k_src = std::min(i_cs - i_off, l.cin_pad);
     g.M = l.cout;
     g.pool = pool_out;
-    return conv3<EPI_RELU_BF16>(g, s, pooled);
+    return conv3<EPI_RELU_BF16>(g, s, pooled, head, headed);
 }
 
 hipError_t convT_fwd(unet_state *n, int li, const uint16_t *in, int i_cs, int NB, int H, int W, uint16_t *out,
@@ -1678,9 +1764,10 @@ hipError_t dec0a_fused(unet_state *n, unet_act *a, int NB, int H, int W, hipStre
 
 // The forward pass up to the last 3x3 convolution.  fuse_up0 lets the
 // finest transposed convolution run inside dec0a (inference; its output is
-// then not stored).
+// then not stored); with head, *head_done tells whether the head ran in the
+// last convolution's epilogue.
 hipError_t forward_all(unet_state *n, unet_act *a, const uint16_t *stack, int NB, int H, int W, hipStream_t s,
-                       bool fuse_up0 = false)
+                       bool fuse_up0 = false, const HeadArgs *head = nullptr, bool *head_done = nullptr)
 {
     a->NB = NB;
     a->H = H;
@@ -1711,7 +1798,7 @@ hipError_t forward_all(unet_state *n, unet_act *a, const uint16_t *stack, int NB
     } else {
         NCHK(dec0a_fused(n, a, NB, H, W, s));
     }
-    NCHK(conv_fwd(n, L_D0B, a->d0a, 32, 0, a->d0b, 32, 0, NB, H, W, s));
+    NCHK(conv_fwd(n, L_D0B, a->d0a, 32, 0, a->d0b, 32, 0, NB, H, W, s, nullptr, nullptr, head, head_done));
     return hipSuccess;
 }
 
@@ -1927,7 +2014,9 @@ hipError_t unet_forward(unet_state *n, unet_act *a, const uint16_t *stack, int N
     h.W = W;
     h.valid_h = valid_h;
     h.valid_w = valid_w;
-    NCHK(forward_all(n, a, stack, NB, H, W, s, !keep));
+    bool done = false;
+    NCHK(forward_all(n, a, stack, NB, H, W, s, !keep, &h, &done));
+    if (done) return hipSuccess;
     const int P = NB * H * W;
     hipLaunchKernelGGL(k_head, dim3((P + 255) / 256), dim3(256), 0, s, h, 0);
     return hipGetLastError();
@@ -1953,7 +2042,9 @@ hipError_t unet_forward_batch(unet_state *n, unet_act *a, const uint16_t *stack,
     h.NB = NB;
     h.H = H;
     h.W = W;
-    NCHK(forward_all(n, a, stack, NB, H, W, s, !keep));
+    bool done = false;
+    NCHK(forward_all(n, a, stack, NB, H, W, s, !keep, &h, &done));
+    if (done) return hipSuccess;
     const int P = NB * H * W;
     hipLaunchKernelGGL(k_head, dim3((P + 255) / 256), dim3(256), 0, s, h, 0);
     return hipGetLastError();
