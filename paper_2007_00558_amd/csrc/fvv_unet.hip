@@ -418,7 +418,8 @@ __global__ void __launch_bounds__(256) k_conv3(const GemmArgs g)
 
 // ---------------------------------------------------------------- 3x3 convolution, weights resident
 // The 32-output-channel layers with one or two input chunks (the full-
-// resolution level): the same implicit GEMM as k_conv3<1, TH>, but a block
+// resolution level; 16-row patches with one chunk, 8-row ones with two, or
+// with the head): the same implicit GEMM as k_conv3<1, TH>, but a block
 // stages the whole weight slice (KC chunks x 32 rows x 9 taps x 32 channels)
 // in LDS once and then walks over patches (TH x 16 pixels), so the weights
 // are not fetched again for every patch; the next patch (all KC chunks) is
@@ -1636,14 +1637,14 @@ hipError_t conv3(GemmArgs g, hipStream_t s, bool *pooled = nullptr, const HeadAr
         if constexpr (EPI == EPI_RELU_BF16) {
             if (pooled && g.pool) {
                 *pooled = true;
-                return conv3w_launch<8, 1, EPI, true>(g, s);
+                return conv3w_launch<16, 1, EPI, true>(g, s);
             }
             if (headed && head) {
                 *headed = true;
                 return conv3w_launch<8, 1, EPI, false, false, true>(g, s, *head);
             }
         }
-        return conv3w_launch<8, 1, EPI, false>(g, s);
+        return conv3w_launch<16, 1, EPI, false>(g, s);
     }
     if (g.M == 32 && g.K == 64 && tiles8 >= 2048) return conv3w_launch<8, 2, EPI, false>(g, s);
     const bool big = g.M > 32 && (int64_t)g.NB * g.H * g.W >= 65536;
