@@ -462,9 +462,10 @@ int32_t fvv_server_stats(fvv_ctx *ctx, uint64_t *out6);
  *   bfloat16 NHWC (bytes must be pixels at that layer's resolution x C_out x 2).
  *   With debug taps on (fvv_set_debug) a forward keeps every layer's output;
  *   with them off it may compute the finest transposed convolution inside
- *   the convolution that reads it (large batches), and reading that layer
- *   then fails with FVV_E_ARG.  The network's results are the same bytes
- *   either way.
+ *   the convolution that reads it (large batches) and the head inside the
+ *   last convolution, whose output is then not stored either; reading such a
+ *   layer then fails with FVV_E_ARG.  The network's results are the same
+ *   bytes either way.
  * fvv_net_device_bytes: device memory held by the network and its
  *   activation sets (part of the context's budget). */
 enum { FVV_NET_PARAMS = 0, FVV_NET_GRADS = 1 };

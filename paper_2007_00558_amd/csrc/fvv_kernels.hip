@@ -438,21 +438,29 @@ __device__ __forceinline__ unsigned long long filter_key(unsigned long long c, u
 // the warped depth within tau are mixed bilinearly, cameras by their
 // distance weights.  Returns true and the RGBA8 colour if any camera
 // contributes.
-__device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int k0, int x, int y, float zf, uint32_t &rgba)
+//
+// ST (learned path): also the pixel's stack channels ch[0..14] from the
+// same per-camera samples: for each of the first three slots that
+// contributes, its bilinear colour (R, G, B / 255), the inverse source depth
+// 0.5 / q_z capped at 1 and a validity flag 1 (the caller zeroes ch first:
+// slots without a consistent tap stay zero).
+template <bool ST>
+__device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int k0, int x, int y, float zf, uint32_t &rgba,
+                                            float *ch = nullptr)
 {
     // Decisions (sample in range, tap valid and depth-consistent, camera
     // survives) in float32 op by op; the colour mix is value arithmetic and
     // uses fused multiply-adds and hardware reciprocals.
     float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, wsum = 0.f;
-    for (int k = k0; k < k0 + vd.K; ++k) {
+    auto camera = [&](int k, float *chk) {
         const fvv_src_desc &s = vd.src[k];
         float q0, q1, q2;
         project(s.B, s.b, (float)x, (float)y, zf, q0, q1, q2);
-        if (!(q2 > FVV_ZCLIP)) continue;
+        if (!(q2 > FVV_ZCLIP)) return;
         const float r = rcp_rn(q2);
         const float u = div_by(q0, q2, r), v = div_by(q1, q2, r);
-        if (!(u >= -0.5f && u <= s.umax)) continue;
-        if (!(v >= -0.5f && v <= s.vmax)) continue;
+        if (!(u >= -0.5f && u <= s.umax)) return;
+        if (!(v >= -0.5f && v <= s.vmax)) return;
         const float fi0 = floorf(u), fj0 = floorf(v);
         const float fu = __fsub_rn(u, fi0), fv = __fsub_rn(v, fj0);
         const int i0 = (int)fi0, j0 = (int)fj0;
@@ -497,6 +505,26 @@ __device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int k0, int
         acc1 = fmaf(c1, inv, acc1);
         acc2 = fmaf(c2, inv, acc2);
         wsum += any ? s.wgt : 0.0f;
+        if (ST && chk && any) {
+            // colour / csum / 255: value arithmetic (within a bfloat16 step
+            // of the exact quotient); the inverse depth 0.5 / q2 is exact:
+            // half of the correctly rounded reciprocal
+            const float icol = __builtin_amdgcn_rcpf(csum) * (1.0f / 255.0f);
+            chk[0] = c0 * icol;
+            chk[1] = c1 * icol;
+            chk[2] = c2 * icol;
+            chk[3] = fminf(0.5f * r, 1.0f);
+            chk[4] = 1.0f;
+        }
+    };
+    if (ST) {
+        // the stack's three slots unrolled, so their channels stay in registers
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (k < vd.K) camera(k0 + k, ch + 5 * k);
+        for (int k = 3; k < vd.K; ++k) camera(k0 + k, nullptr);
+    } else {
+        for (int k = 0; k < vd.K; ++k) camera(k0 + k, nullptr);
     }
     if (!(wsum > 0.f)) return false;
     const float iw = __builtin_amdgcn_rcpf(wsum);
@@ -507,65 +535,16 @@ __device__ __forceinline__ bool blend_pixel(const fvv_view_desc &vd, int k0, int
     return true;
 }
 
-// Learned-path input of output pixel (x, y): for each of the first three
-// selected cameras, the depth-consistent bilinear colour that blend_pixel
-// mixes (R, G, B / 255), the inverse source depth 0.5 / q_z capped at 1 and a
-// validity flag; zeros where a camera gives no sample, for pixels without a
-// filtered point and for the padding beyond the image.  16 bf16 channels (the
-// last one zero), 32 bytes per pixel.
-__device__ __forceinline__ void stack_pixel(const fvv_view_desc &vd, int x, int y, unsigned long long kf)
+// Learned-path input of output pixel (x, y): channels ch[0..14] from
+// blend_pixel (zeros for pixels without a filtered point and for the
+// padding beyond the image), the last of 16 bf16 channels zero, 32 bytes
+// per pixel.
+__device__ __forceinline__ void store_stack(const fvv_view_desc &vd, int x, int y, const float ch[16])
 {
-    float ch[16];   // channel values, rounded to bfloat16 at the end
-#pragma unroll
-    for (int c = 0; c < 16; ++c) ch[c] = 0.f;
-    if (kf != FVV_KEY_EMPTY) {
-        const float zf = u2f((uint32_t)(kf >> 32));
-        const int K = min(vd.K, 3);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            if (k >= K) break;
-            const fvv_src_desc &s = vd.src[k];
-            float q0, q1, q2;
-            project(s.B, s.b, (float)x, (float)y, zf, q0, q1, q2);
-            if (!(q2 > FVV_ZCLIP)) continue;
-            const float r = rcp_rn(q2);
-            const float u = div_by(q0, q2, r), v = div_by(q1, q2, r);
-            if (!(u >= -0.5f && u <= s.umax)) continue;
-            if (!(v >= -0.5f && v <= s.vmax)) continue;
-            const float fi0 = floorf(u), fj0 = floorf(v);
-            const float fu = __fsub_rn(u, fi0), fv = __fsub_rn(v, fj0);
-            const int i0 = (int)fi0, j0 = (int)fj0;
-            const float lim = __fmul_rn(vd.tau, q2);
-            const float gu = 1.0f - fu, gv = 1.0f - fv;
-            const float wt[4] = {gu * gv, fu * gv, gu * fv, fu * fv};
-            float c0 = 0.f, c1 = 0.f, c2 = 0.f, csum = 0.f;
-            for (int n = 0; n < 4; ++n) {
-                const int ti = i0 + (n & 1), tj = j0 + (n >> 1);
-                if (ti < 0 || tj < 0 || ti >= s.W || tj >= s.H) continue;
-                const uint2 tx = s.texel[(int64_t)tj * s.W + ti];
-                if (tx.y == FVV_NO_DEPTH) continue;
-                if (!(fabsf(__fsub_rn(u2f(tx.y), q2)) <= lim)) continue;
-                c0 += wt[n] * (float)(tx.x & 0xFF);
-                c1 += wt[n] * (float)((tx.x >> 8) & 0xFF);
-                c2 += wt[n] * (float)((tx.x >> 16) & 0xFF);
-                csum += wt[n];
-            }
-            if (!(csum > 0.f)) continue;
-            // colour / csum / 255: value arithmetic (within a bfloat16 step
-            // of the exact quotient); the inverse depth 0.5 / q2 is exact:
-            // half of the correctly rounded reciprocal
-            const float ic = __builtin_amdgcn_rcpf(csum) * (1.0f / 255.0f);
-            ch[5 * k + 0] = c0 * ic;
-            ch[5 * k + 1] = c1 * ic;
-            ch[5 * k + 2] = c2 * ic;
-            ch[5 * k + 3] = fminf(0.5f * r, 1.0f);
-            ch[5 * k + 4] = 1.0f;
-        }
-    }
     uint4 *o = (uint4 *)(vd.stack + ((int64_t)y * vd.stack_w + x) * 16);
     o[0] = make_uint4(bf16_pack(ch[0], ch[1]), bf16_pack(ch[2], ch[3]), bf16_pack(ch[4], ch[5]), bf16_pack(ch[6], ch[7]));
     o[1] = make_uint4(bf16_pack(ch[8], ch[9]), bf16_pack(ch[10], ch[11]), bf16_pack(ch[12], ch[13]),
-                      bf16_pack(ch[14], ch[15]));
+                      bf16_pack(ch[14], 0.f));
 }
 
 __device__ __forceinline__ void put_rgb(uint8_t *out, int64_t pitch, int x, int y, uint32_t c)
@@ -806,11 +785,14 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
         pslot[q] = FVV_HOLE;
         prgb[q] = 0;
         const unsigned long long kf = kfs[q];
+        float ch[STACK ? 16 : 1];   // the learned-path stack channels of the pixel
+#pragma unroll
+        for (int c = 0; c < (STACK ? 16 : 1); ++c) ch[c] = 0.f;
         if (x < W && y < H) {
             if (kf != FVV_KEY_EMPTY) {
                 const float zf = u2f((uint32_t)(kf >> 32));
                 uint32_t col;
-                if (blend_pixel(vd, 0, x, y, zf, col)) {
+                if (blend_pixel<STACK>(vd, 0, x, y, zf, col, ch)) {
                     pslot[q] = f2u(zf);
                     prgb[q] = col;
                 }
@@ -829,7 +811,7 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
                     if ((pslot[q] & FVV_HOLE) && kb != FVV_KEY_EMPTY) {
                         const float zf = u2f((uint32_t)(kb >> 32));
                         uint32_t col;
-                        if (blend_pixel(vd, vd.K, x, y, zf, col)) {
+                        if (blend_pixel<false>(vd, vd.K, x, y, zf, col)) {
                             pslot[q] = f2u(zf);
                             prgb[q] = col;
                         }
@@ -845,7 +827,7 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
             if (vd.dbg_rgba) vd.dbg_rgba[o] = prgb[q];
             if (vd.dbg_depth) vd.dbg_depth[o] = (pslot[q] & FVV_HOLE) ? 0.0f : u2f(pslot[q]);
         }
-        if (STACK && vd.stack && x < vd.stack_w && y < vd.stack_h) stack_pixel(vd, x, y, kf);
+        if (STACK && vd.stack && x < vd.stack_w && y < vd.stack_h) store_stack(vd, x, y, ch);
     }
     bool any_hole = false;
 #pragma unroll

@@ -57,8 +57,8 @@ hipError_t unet_act_reserve(unet_act *a, size_t pixels, bool train);
 // rgb + b * img_stride (pitch bytes per row), for every pixel whose three
 // outputs are finite (the others keep what the buffer held).
 // keep: store every layer's output (for unet_read_act); otherwise the
-// finest transposed convolution may run inside the convolution after it and
-// its output is not stored.
+// finest transposed convolution may run inside the convolution after it,
+// and the head inside the last convolution, neither of their inputs stored.
 hipError_t unet_forward(unet_state *n, unet_act *a, const uint16_t *stack, int B, int H, int W, float *s_out,
                            uint8_t *rgb, int64_t pitch, int64_t img_stride, int valid_h, int valid_w,
                            hipStream_t s, std::string &err, bool keep = true);
@@ -86,7 +86,8 @@ hipError_t unet_train(unet_state *n, unet_act *a, const uint16_t *stack, const f
                          std::string &err);
 // Copy one layer's stored output of the last forward (bf16 NHWC, that
 // layer's channels only) to host memory, for parity checks; an error for
-// the finest transposed convolution when the last forward did not keep it.
+// a layer (the finest transposed convolution, dec0b) whose output the last
+// forward did not store.
 hipError_t unet_read_act(unet_act *a, int layer, void *host, size_t bytes, hipStream_t s);
 // Adds to *bad_dev (device memory) the number of non-NaN float32 bit
 // patterns whose bfloat16 rounding by the hardware conversion the kernels

@@ -236,11 +236,15 @@ __global__ void __launch_bounds__(256) k_gemm(const GemmArgs g)
 // ---------------------------------------------------------------- 3x3 convolution, LDS-staged
 // 3x3 convolution (forward, or the data gradient with the mirrored weights)
 // as an implicit GEMM on v_mfma_f32_32x32x16_bf16.  A block computes 32*MT
-// output channels of a TH x 16 pixel patch of one image; for each 32-channel
-// chunk of the input it stages the (TH+2) x 18 input patch and the weight
-// slice (32*MT rows x 9 taps x 32 channels) in LDS once, and all nine taps
-// read them from there.  Four waves split the patch's rows; each wave holds
-// MT x NT tiles of 32 channels x 32 pixels (2 rows x 16 columns).
+// output channels of a TH x 16 pixel patch of one image (a work item); for
+// each 32-channel chunk of the input it stages the (TH+2) x 18 input patch
+// and the weight slice (32*MT rows x 9 taps x 32 channels) in LDS once, and
+// all nine taps read them from there.  Four waves split the patch's rows;
+// each wave holds MT x NT tiles of 32 channels x 32 pixels (2 rows x 16
+// columns).  The grid is the resident blocks; a block walks work items in
+// steps of the grid and fetches the next chunk into registers while the
+// current one's MFMAs run, across items too (the last chunk of an item
+// fetches the first of the next), so no item starts on an exposed fetch.
 // Per-pixel and per-row LDS strides are padded by 16 bytes so the 16-byte
 // fragment reads of 8 consecutive lanes fall in distinct banks.
 constexpr int C3_PXS = 80;             // bytes per staged pixel (32 bf16 + pad)
@@ -262,7 +266,7 @@ __device__ __forceinline__ float pool_max4(float v)
 }
 
 template <int MT, int TH, int EPI, bool POOL = false>
-__global__ void __launch_bounds__(256) k_conv3(const GemmArgs g)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_conv3(const GemmArgs g)
 {
     static_assert(TH % 8 == 0, "each wave takes TH/4 rows, two per 32-pixel tile");
     constexpr int NT = TH / 8;         // 32-pixel tiles per wave (TH/4 rows of 16)
@@ -273,52 +277,60 @@ __global__ void __launch_bounds__(256) k_conv3(const GemmArgs g)
     uint8_t *wts = c3_smem + PH * PW * C3_PXS;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int tiles_x = (g.W + 15) / 16, tiles_y = (g.H + TH - 1) / TH;
-    int t = blockIdx.x;
-    const int txi = t % tiles_x;
-    t /= tiles_x;
-    const int tyi = t % tiles_y;
-    const int b = t / tiles_y;
-    const int x0 = txi * 16, y0 = tyi * TH;
-    const int mbase = blockIdx.y * 32 * MT;
+    const int mgroups = (g.M + 32 * MT - 1) / (32 * MT);
+    const int items = tiles_x * tiles_y * g.NB * mgroups;
     const int k_src = g.k_src ? g.k_src : g.K;
     const int lc = lane & 31, lh = lane >> 5;
-    f32x16 acc[MT][NT];
-#pragma unroll
-    for (int i = 0; i < MT; ++i)
-#pragma unroll
-        for (int n = 0; n < NT; ++n)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[i][n][r] = 0.f;
-    // Software pipeline over the 32-channel chunks: the next chunk's input
-    // patch (PH x PW pixels x 4 quarters of 8 channels) and weight slice
-    // (32*MT rows x 9 taps x 4 quarters) are fetched into registers while
-    // the current chunk's MFMAs run, then stored to LDS.
+    // item of this block in step k (the grid is a multiple of 8): blocks on
+    // one XCD (b mod 8) take consecutive items, the output-channel groups of
+    // a patch and neighbouring patches, whose halos share that XCD's L2
+    const int xcd = blockIdx.x % 8, slot = blockIdx.x / 8, per_xcd = gridDim.x / 8;
+    auto item_of = [&](int k) { return k * gridDim.x + xcd * per_xcd + slot; };
+    struct Item {
+        int b, x0, y0, mbase;
+    };
+    auto decode = [&](int it) {
+        Item r;
+        const int mg = it % mgroups;
+        int t = it / mgroups;
+        const int txi = t % tiles_x;
+        t /= tiles_x;
+        const int tyi = t % tiles_y;
+        r.b = t / tiles_y;
+        r.x0 = txi * 16;
+        r.y0 = tyi * TH;
+        r.mbase = mg * 32 * MT;
+        return r;
+    };
+    // Chunks are fetched into registers (the input patch: PH x PW pixels x 4
+    // quarters of 8 channels; the weight slice: 32*MT rows x 9 taps x 4
+    // quarters) and stored to LDS once every wave is done with the previous.
     constexpr int NPF = (PH * PW * 4 + 255) / 256, NWF = (32 * MT * 36 + 255) / 256;
     uint4 fp[NPF], fw[NWF];
-    // this thread's patch elements: 32-bit element offsets of their chunk-0
-    // channels (-1 outside the image); every element of a thread has the
-    // same quarter q = tid & 3
-    int32_t poff[NPF];
+    // this thread's patch elements of an item: 32-bit element offsets of
+    // their chunk-0 channels (-1 outside the image); every element of a
+    // thread has the same quarter q = tid & 3
+    auto offsets = [&](const Item &it, int32_t *po) {
 #pragma unroll
-    for (int k = 0; k < NPF; ++k) {
-        const int e = tid + k * 256;
-        const int px = e >> 2, pr = px / PW, pc = px - pr * PW;
-        const int gy = y0 - 1 + pr, gx = x0 - 1 + pc;
-        poff[k] = (e < PH * PW * 4 && gy >= 0 && gy < g.H && gx >= 0 && gx < g.W)
-                      ? ((b * g.H + gy) * g.W + gx) * g.b_cs + g.b_off + (tid & 3) * 8
-                      : -1;
-    }
+        for (int k = 0; k < NPF; ++k) {
+            const int e = tid + k * 256;
+            const int px = e >> 2, pr = px / PW, pc = px - pr * PW;
+            const int gy = it.y0 - 1 + pr, gx = it.x0 - 1 + pc;
+            po[k] = (e < PH * PW * 4 && gy >= 0 && gy < g.H && gx >= 0 && gx < g.W)
+                        ? ((it.b * g.H + gy) * g.W + gx) * g.b_cs + g.b_off + (tid & 3) * 8
+                        : -1;
+        }
+    };
     // weights are stored chunk-major ([K/32][M][9][32]): a chunk's slice for
-    // this block's rows is one contiguous run, element e of it at 8 e
-    const uint16_t *wrows = g.A + (int64_t)mbase * 288;
-    auto fetch = [&](int c0) {
+    // an item's rows is one contiguous run, element e of it at 8 e
+    auto fetch = [&](const int32_t *po, int mbase, int c0) {
         const bool qin = c0 + (tid & 3) * 8 < k_src;
 #pragma unroll
         for (int k = 0; k < NPF; ++k) {
             fp[k] = make_uint4(0, 0, 0, 0);
-            if (poff[k] >= 0 && qin) fp[k] = *(const uint4 *)(g.Bsrc + (uint32_t)(poff[k] + c0));
+            if (po[k] >= 0 && qin) fp[k] = *(const uint4 *)(g.Bsrc + (uint32_t)(po[k] + c0));
         }
-        const uint16_t *wc = wrows + (int64_t)(c0 >> 5) * g.M * 288;
+        const uint16_t *wc = g.A + (int64_t)mbase * 288 + (int64_t)(c0 >> 5) * g.M * 288;
 #pragma unroll
         for (int k = 0; k < NWF; ++k) {
             const int e = tid + k * 256;
@@ -339,12 +351,42 @@ __global__ void __launch_bounds__(256) k_conv3(const GemmArgs g)
             if (e < 32 * MT * 36) *(uint4 *)(wts + r * C3_RS + tap * 64 + q * 16) = fw[k];
         }
     };
-    fetch(0);
+    // poff holds the offsets of the item whose chunks are being fetched: the
+    // current one's, then (from its last chunk on) the next one's
+    int cur = item_of(0);
+    if (cur >= items) return;
+    int32_t poff[NPF];
+    {
+        const Item it = decode(cur);
+        offsets(it, poff);
+        fetch(poff, it.mbase, 0);
+    }
     stash();
     __syncthreads();
-    for (int c0 = 0; c0 < g.K; c0 += 32) {
-        const bool more = c0 + 32 < g.K;
-        if (more) fetch(c0 + 32);
+    // one loop over (item, chunk) steps, so the accumulators are carried
+    // through a single loop
+    int step = 1, nxt = item_of(1);
+    int mbase = (cur % mgroups) * 32 * MT;
+    f32x16 acc[MT][NT];
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int n = 0; n < NT; ++n)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[i][n][r] = 0.f;
+    for (int c0 = 0;;) {
+        // the next chunk: this item's, else the next item's first
+        const bool last = c0 + 32 >= g.K;
+        bool more = true;
+        if (!last) {
+            fetch(poff, mbase, c0 + 32);
+        } else if (nxt < items) {
+            const Item n = decode(nxt);
+            offsets(n, poff);
+            fetch(poff, n.mbase, 0);
+        } else {
+            more = false;
+        }
 #pragma unroll
         for (int tap = 0; tap < 9; ++tap) {
             const int dy = tap / 3, dx = tap - dy * 3;
@@ -373,46 +415,60 @@ __global__ void __launch_bounds__(256) k_conv3(const GemmArgs g)
             stash();
             __syncthreads();
         }
-    }
-    // epilogue: lane holds, for pixel lc of each tile, channels
-    // 8*j + 4*lh + {0..3} (j = 0..3) of each 32-row tile
+        if (!last) {
+            c0 += 32;
+            continue;
+        }
+        const Item it = decode(cur);
 #pragma unroll
-    for (int n = 0; n < NT; ++n) {
-        const int py = y0 + wave * (TH / 4) + 2 * n + (lc >> 4), px = x0 + (lc & 15);
-        if (py >= g.H || px >= g.W) continue;
-        const int64_t pix = ((int64_t)b * g.H + py) * g.W + px;
+        for (int n = 0; n < NT; ++n) {
+            const int py = it.y0 + wave * (TH / 4) + 2 * n + (lc >> 4), px = it.x0 + (lc & 15);
+            if (py >= g.H || px >= g.W) continue;
+            const int64_t pix = ((int64_t)it.b * g.H + py) * g.W + px;
 #pragma unroll
-        for (int i = 0; i < MT; ++i)
+            for (int i = 0; i < MT; ++i)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int m0 = mbase + i * 32 + 8 * j + 4 * lh;
-                if (m0 >= g.M) continue;
-                float v0 = acc[i][n][4 * j + 0], v1 = acc[i][n][4 * j + 1];
-                float v2 = acc[i][n][4 * j + 2], v3 = acc[i][n][4 * j + 3];
-                if (EPI == EPI_F32) {
-                    *(float4 *)((float *)g.out + pix * g.o_cs + g.o_off + m0) = make_float4(v0, v1, v2, v3);
-                } else {
-                    v0 = fmaxf(v0 + g.bias[m0 + 0], 0.f);
-                    v1 = fmaxf(v1 + g.bias[m0 + 1], 0.f);
-                    v2 = fmaxf(v2 + g.bias[m0 + 2], 0.f);
-                    v3 = fmaxf(v3 + g.bias[m0 + 3], 0.f);
-                    *(uint2 *)((uint16_t *)g.out + pix * g.o_cs + g.o_off + m0) =
-                        make_uint2(pack_bf16(v0, v1),
-                                   pack_bf16(v2, v3));
-                    if (POOL) {
-                        // the window's four lanes share its maxima; lane
-                        // (column bit a, row bit c) writes group j = 2 c + a
-                        v0 = pool_max4(v0);
-                        v1 = pool_max4(v1);
-                        v2 = pool_max4(v2);
-                        v3 = pool_max4(v3);
-                        if (j == 2 * ((lc >> 4) & 1) + (lc & 1)) {
-                            const int64_t pp = ((int64_t)b * (g.H / 2) + (py >> 1)) * (g.W / 2) + (px >> 1);
-                            *(uint2 *)(g.pool + pp * g.M + m0) = make_uint2(pack_bf16(v0, v1), pack_bf16(v2, v3));
+                for (int j = 0; j < 4; ++j) {
+                    const int m0 = it.mbase + i * 32 + 8 * j + 4 * lh;
+                    if (m0 >= g.M) continue;
+                    float v0 = acc[i][n][4 * j + 0], v1 = acc[i][n][4 * j + 1];
+                    float v2 = acc[i][n][4 * j + 2], v3 = acc[i][n][4 * j + 3];
+                    if (EPI == EPI_F32) {
+                        *(float4 *)((float *)g.out + pix * g.o_cs + g.o_off + m0) = make_float4(v0, v1, v2, v3);
+                    } else {
+                        v0 = fmaxf(v0 + g.bias[m0 + 0], 0.f);
+                        v1 = fmaxf(v1 + g.bias[m0 + 1], 0.f);
+                        v2 = fmaxf(v2 + g.bias[m0 + 2], 0.f);
+                        v3 = fmaxf(v3 + g.bias[m0 + 3], 0.f);
+                        *(uint2 *)((uint16_t *)g.out + pix * g.o_cs + g.o_off + m0) =
+                            make_uint2(pack_bf16(v0, v1),
+                                       pack_bf16(v2, v3));
+                        if (POOL) {
+                            // the window's four lanes share its maxima; lane
+                            // (column bit a, row bit c) writes group j = 2 c + a
+                            v0 = pool_max4(v0);
+                            v1 = pool_max4(v1);
+                            v2 = pool_max4(v2);
+                            v3 = pool_max4(v3);
+                            if (j == 2 * ((lc >> 4) & 1) + (lc & 1)) {
+                                const int64_t pp = ((int64_t)it.b * (g.H / 2) + (py >> 1)) * (g.W / 2) + (px >> 1);
+                                *(uint2 *)(g.pool + pp * g.M + m0) = make_uint2(pack_bf16(v0, v1), pack_bf16(v2, v3));
+                            }
                         }
                     }
                 }
-            }
+        }
+        if (!more) break;
+        cur = nxt;
+        nxt = item_of(++step);
+        mbase = (cur % mgroups) * 32 * MT;
+        c0 = 0;
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+#pragma unroll
+            for (int n = 0; n < NT; ++n)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) acc[i][n][r] = 0.f;
     }
 }
 
@@ -439,7 +495,7 @@ constexpr int c3w_lds_bytes() { return (TH + 2) * 18 * c3w_pxs<KC>() + KC * 32 *
 template <int TH, int KC, int EPI, bool POOL, bool UPC = false, bool HEAD = false>
 __global__ void __launch_bounds__(256) k_conv3w(const GemmArgs g, const HeadArgs hd)
 {
-    static_assert(!HEAD || (EPI == EPI_RELU_BF16 && TH == 8), "the head follows a ReLU output, one tile per wave");
+    static_assert(!HEAD || EPI == EPI_RELU_BF16, "the head follows a ReLU output");
     static_assert(TH % 8 == 0, "each wave takes TH/4 rows, two per 32-pixel tile");
     static_assert(!UPC || (KC == 2 && TH == 8), "the transposed convolution feeds chunk 0 of 8-row patches");
     constexpr int NT = TH / 8;
@@ -612,33 +668,38 @@ __global__ void __launch_bounds__(256) k_conv3w(const GemmArgs g, const HeadArgs
         const int tyi = t % tiles_y;
         const int b = t / tiles_y;
         if constexpr (HEAD) {
-            // the output as in the loop below, then the head on the matrix
-            // cores: the packed bfloat16 halves of lanes l and l + 32 swapped
+            // the output as in the loop below (stored unless g.out is null:
+            // only the head reads it), then the head on the matrix cores: the
+            // packed bfloat16 halves of lanes l and l + 32 swapped
             // (v_permlane32_swap) into the B fragments of head_mfma
-            const int py = tyi * TH + wave * (TH / 4) + (lc >> 4), px = txi * 16 + (lc & 15);
-            const bool ok = py < g.H && px < g.W;
-            const int64_t pix = ((int64_t)b * g.H + py) * g.W + px;
-            uint32_t w[4][2];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int m0 = 8 * j + 4 * lh;
-                w[j][0] = pack_bf16(fmaxf(acc[0][4 * j + 0] + g.bias[m0 + 0], 0.f),
-                                    fmaxf(acc[0][4 * j + 1] + g.bias[m0 + 1], 0.f));
-                w[j][1] = pack_bf16(fmaxf(acc[0][4 * j + 2] + g.bias[m0 + 2], 0.f),
-                                    fmaxf(acc[0][4 * j + 3] + g.bias[m0 + 3], 0.f));
-                if (ok) *(uint2 *)((uint16_t *)g.out + pix * g.o_cs + g.o_off + m0) = make_uint2(w[j][0], w[j][1]);
-            }
-            uint4 o[2];
+            for (int n = 0; n < NT; ++n) {
+                const int py = tyi * TH + wave * (TH / 4) + 2 * n + (lc >> 4), px = txi * 16 + (lc & 15);
+                const bool ok = py < g.H && px < g.W;
+                const int64_t pix = ((int64_t)b * g.H + py) * g.W + px;
+                uint32_t w[4][2];
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const auto s0 = __builtin_amdgcn_permlane32_swap(w[2 * q][0], w[2 * q + 1][0], false, false);
-                const auto s1 = __builtin_amdgcn_permlane32_swap(w[2 * q][1], w[2 * q + 1][1], false, false);
-                o[q] = make_uint4(s0[0], s1[0], s0[1], s1[1]);
-            }
-            const f32x16 dz = head_mfma(hd.w, __builtin_bit_cast(bf16x8, o[0]), __builtin_bit_cast(bf16x8, o[1]));
-            if (ok && !lh) {
-                const float z[3] = {dz[0] + hd.bias[0], dz[1] + hd.bias[1], dz[2] + hd.bias[2]};
-                head_store(hd, z, pix, b, py, px);
+                for (int j = 0; j < 4; ++j) {
+                    const int m0 = 8 * j + 4 * lh;
+                    w[j][0] = pack_bf16(fmaxf(acc[n][4 * j + 0] + g.bias[m0 + 0], 0.f),
+                                        fmaxf(acc[n][4 * j + 1] + g.bias[m0 + 1], 0.f));
+                    w[j][1] = pack_bf16(fmaxf(acc[n][4 * j + 2] + g.bias[m0 + 2], 0.f),
+                                        fmaxf(acc[n][4 * j + 3] + g.bias[m0 + 3], 0.f));
+                    if (ok && g.out)
+                        *(uint2 *)((uint16_t *)g.out + pix * g.o_cs + g.o_off + m0) = make_uint2(w[j][0], w[j][1]);
+                }
+                uint4 o[2];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const auto s0 = __builtin_amdgcn_permlane32_swap(w[2 * q][0], w[2 * q + 1][0], false, false);
+                    const auto s1 = __builtin_amdgcn_permlane32_swap(w[2 * q][1], w[2 * q + 1][1], false, false);
+                    o[q] = make_uint4(s0[0], s1[0], s0[1], s1[1]);
+                }
+                const f32x16 dz = head_mfma(hd.w, __builtin_bit_cast(bf16x8, o[0]), __builtin_bit_cast(bf16x8, o[1]));
+                if (ok && !lh) {
+                    const float z[3] = {dz[0] + hd.bias[0], dz[1] + hd.bias[1], dz[2] + hd.bias[2]};
+                    head_store(hd, z, pix, b, py, px);
+                }
             }
             cur = nxt;
             continue;
@@ -1430,6 +1491,7 @@ struct unet_act {
     size_t cap = 0;          // pixels at full resolution
     bool train = false;
     bool up0_stored = true;  // the last forward stored the finest transposed convolution's output
+    bool d0b_stored = true;  // ... and dec0b's output
     size_t bytes = 0;
     int NB = 0, H = 0, W = 0;
     uint16_t *e0a = nullptr, *cat0 = nullptr, *p1 = nullptr, *e1a = nullptr, *cat1 = nullptr, *p2 = nullptr,
@@ -1600,9 +1662,10 @@ hipError_t conv3_launch(const GemmArgs &g, hipStream_t s)
 {
     constexpr int lds = c3_lds_bytes<MT, TH>();
     static_assert(lds <= 65536, "staged patch and weights must fit 64 KB");
-    const int tiles = ((g.W + 15) / 16) * ((g.H + TH - 1) / TH) * g.NB;
-    dim3 grid(tiles, (g.M + 32 * MT - 1) / (32 * MT));
-    hipLaunchKernelGGL((k_conv3<MT, TH, EPI, POOL>), grid, dim3(256), lds, s, g);
+    const int64_t items = (int64_t)((g.W + 15) / 16) * ((g.H + TH - 1) / TH) * g.NB * ((g.M + 32 * MT - 1) / (32 * MT));
+    static const int rb = std::max(8, resident_blocks(k_conv3<MT, TH, EPI, POOL>, lds) / 8 * 8);
+    const int grid = (int)std::min<int64_t>(rb, (items + 7) / 8 * 8);
+    hipLaunchKernelGGL((k_conv3<MT, TH, EPI, POOL>), dim3(grid), dim3(256), lds, s, g);
     return hipGetLastError();
 }
 
@@ -1622,10 +1685,11 @@ hipError_t conv3w_launch(const GemmArgs &g, hipStream_t s, const HeadArgs &h = H
 
 // *pooled (if given) tells whether the launch also wrote the 2x2 max-pool
 // of the output to g.pool; *headed (if given) whether it also ran the head
-// (only the weights-resident kernel with one input chunk runs it).
+// (only the weights-resident kernel with one input chunk runs it), and then
+// head_only leaves the output itself unstored.
 template <int EPI>
 hipError_t conv3(GemmArgs g, hipStream_t s, bool *pooled = nullptr, const HeadArgs *head = nullptr,
-                 bool *headed = nullptr)
+                 bool *headed = nullptr, bool head_only = false)
 {
     if (g.K % 32 != 0) return hipErrorInvalidValue;
     if (pooled) *pooled = false;
@@ -1641,7 +1705,8 @@ hipError_t conv3(GemmArgs g, hipStream_t s, bool *pooled = nullptr, const HeadAr
             }
             if (headed && head) {
                 *headed = true;
-                return conv3w_launch<8, 1, EPI, false, false, true>(g, s, *head);
+                if (head_only) g.out = nullptr;
+                return conv3w_launch<16, 1, EPI, false, false, true>(g, s, *head);
             }
         }
         return conv3w_launch<16, 1, EPI, false>(g, s);
@@ -1659,10 +1724,11 @@ hipError_t conv3(GemmArgs g, hipStream_t s, bool *pooled = nullptr, const HeadAr
 
 // 3x3 conv + bias + ReLU into (out, o_cs, o_off); with pool_out, *pooled
 // tells whether the 2x2 max-pool of the output was written there as well,
-// with head, *headed whether the head ran on the output as well
+// with head, *headed whether the head ran on the output as well (and
+// head_only then leaves out unwritten)
 hipError_t conv_fwd(unet_state *n, int li, const uint16_t *in, int i_cs, int i_off, uint16_t *out, int o_cs, int o_off,
                     int NB, int H, int W, hipStream_t s, uint16_t *pool_out = nullptr, bool *pooled = nullptr,
-                    const HeadArgs *head = nullptr, bool *headed = nullptr)
+                    const HeadArgs *head = nullptr, bool *headed = nullptr, bool head_only = false)
 {
     const unet_layer &l = layers().L[li];
     GemmArgs g{};
@@ -1681,7 +1747,7 @@ hipError_t conv_fwd(unet_state *n, int li, const uint16_t *in, int i_cs, int i_o
     g.k_src = std::min(i_cs - i_off, l.cin_pad);
     g.M = l.cout;
     g.pool = pool_out;
-    return conv3<EPI_RELU_BF16>(g, s, pooled, head, headed);
+    return conv3<EPI_RELU_BF16>(g, s, pooled, head, headed, head_only);
 }
 
 hipError_t convT_fwd(unet_state *n, int li, const uint16_t *in, int i_cs, int NB, int H, int W, uint16_t *out,
@@ -1763,12 +1829,12 @@ hipError_t dec0a_fused(unet_state *n, unet_act *a, int NB, int H, int W, hipStre
     return conv3w_launch<8, 2, EPI_RELU_BF16, false, true>(g, s);
 }
 
-// The forward pass up to the last 3x3 convolution.  fuse_up0 lets the
-// finest transposed convolution run inside dec0a (inference; its output is
-// then not stored); with head, *head_done tells whether the head ran in the
-// last convolution's epilogue.
+// The forward pass up to the last 3x3 convolution.  lean (inference) stores
+// only what a later launch reads: the finest transposed convolution may run
+// inside dec0a, and dec0b's output, when the head runs in its epilogue, is
+// not stored.  With head, *head_done tells whether the head ran there.
 hipError_t forward_all(unet_state *n, unet_act *a, const uint16_t *stack, int NB, int H, int W, hipStream_t s,
-                       bool fuse_up0 = false, const HeadArgs *head = nullptr, bool *head_done = nullptr)
+                       bool lean = false, const HeadArgs *head = nullptr, bool *head_done = nullptr)
 {
     a->NB = NB;
     a->H = H;
@@ -1792,14 +1858,17 @@ hipError_t forward_all(unet_state *n, unet_act *a, const uint16_t *stack, int NB
     NCHK(convT_fwd(n, L_UP1, a->d2b, 128, NB, H2, W2, a->cat1, 128, s));
     NCHK(conv_fwd(n, L_D1A, a->cat1, 128, 0, a->d1a, 64, 0, NB, H1, W1, s));
     NCHK(conv_fwd(n, L_D1B, a->d1a, 64, 0, a->d1b, 64, 0, NB, H1, W1, s));
-    a->up0_stored = !(fuse_up0 && up0_fusable(NB, H, W));
+    a->up0_stored = !(lean && up0_fusable(NB, H, W));
     if (a->up0_stored) {
         NCHK(convT_fwd(n, L_UP0, a->d1b, 64, NB, H1, W1, a->cat0, 64, s));
         NCHK(conv_fwd(n, L_D0A, a->cat0, 64, 0, a->d0a, 32, 0, NB, H, W, s));
     } else {
         NCHK(dec0a_fused(n, a, NB, H, W, s));
     }
-    NCHK(conv_fwd(n, L_D0B, a->d0a, 32, 0, a->d0b, 32, 0, NB, H, W, s, nullptr, nullptr, head, head_done));
+    bool headed = false;
+    NCHK(conv_fwd(n, L_D0B, a->d0a, 32, 0, a->d0b, 32, 0, NB, H, W, s, nullptr, nullptr, head, &headed, lean));
+    a->d0b_stored = !(lean && headed);
+    if (head_done) *head_done = headed;
     return hipSuccess;
 }
 
@@ -2187,7 +2256,12 @@ hipError_t unet_read_act(unet_act *a, int layer, void *host, size_t bytes, hipSt
         C = 32;
         break;
     case L_D0A: src = a->d0a; cs = 32; C = 32; break;
-    case L_D0B: src = a->d0b; cs = 32; C = 32; break;
+    case L_D0B:
+        if (!a->d0b_stored) return hipErrorInvalidValue;
+        src = a->d0b;
+        cs = 32;
+        C = 32;
+        break;
     default: return hipErrorInvalidValue;
     }
     if (!src || a->NB == 0) return hipErrorInvalidValue;

@@ -258,10 +258,11 @@ def test_weights_resident_conv_equals_per_patch_conv(fvv, ctx):
 
 def test_fused_transposed_convolution_equals_stored(fvv, ctx):
     """Without debug taps a forward of 2,048 patches or more computes the
-    finest transposed convolution inside the convolution that reads it (its
-    output is never stored): the network's output must be the bytes of the
-    forward that stores every layer, for the production batch of 16 960x544
-    stacks and for two 512x256 stacks, and reading that layer must fail."""
+    finest transposed convolution inside the convolution that reads it and
+    the head inside dec0b (neither's input is stored): the network's output
+    must be the bytes of the forward that stores every layer, for the
+    production batch of 16 960x544 stacks and for two 512x256 stacks, and
+    reading those two layers must fail."""
     import torch
     ctx.net_load(flat(rand_params(88)))
     g = torch.Generator(device="cuda").manual_seed(89)
@@ -273,9 +274,10 @@ def test_fused_transposed_convolution_equals_stored(fvv, ctx):
         fused = torch.empty((n, H, W, 3), dtype=torch.float32, device="cuda")
         ctx.net_forward(st, n, H, W, fused)
         torch.cuda.synchronize()
-        up0 = [li for li, (name, *_) in enumerate(layer_list()) if name == "up0"][0]
-        with pytest.raises(fvv.FvvError):
-            ctx.net_read_act(up0, (n * H * W, 32))
+        for lname in ("up0", "dec0b"):
+            li = [li for li, (name, *_) in enumerate(layer_list()) if name == lname][0]
+            with pytest.raises(fvv.FvvError):
+                ctx.net_read_act(li, (n * H * W, 32))
         ctx.set_debug(True)
         kept = torch.empty((n, H, W, 3), dtype=torch.float32, device="cuda")
         ctx.net_forward(st, n, H, W, kept)
