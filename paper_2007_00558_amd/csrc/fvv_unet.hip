@@ -492,12 +492,13 @@ template <int TH, int KC>
 constexpr int c3w_lds_bytes() { return (TH + 2) * 18 * c3w_pxs<KC>() + KC * 32 * C3_RS; }
 
 
-template <int TH, int KC, int EPI, bool POOL, bool UPC = false, bool HEAD = false>
+template <int TH, int KC, int EPI, bool POOL, bool UPC = false, bool HEAD = false, bool K16 = false>
 __global__ void __launch_bounds__(256) k_conv3w(const GemmArgs g, const HeadArgs hd)
 {
     static_assert(!HEAD || EPI == EPI_RELU_BF16, "the head follows a ReLU output");
     static_assert(TH % 8 == 0, "each wave takes TH/4 rows, two per 32-pixel tile");
     static_assert(!UPC || (KC == 2 && TH == 8), "the transposed convolution feeds chunk 0 of 8-row patches");
+    static_assert(!K16 || KC == 1, "K16: one chunk whose channels 16..31 are zero (not staged, not multiplied)");
     constexpr int NT = TH / 8;
     constexpr int PW = 18;
     constexpr int PH = TH + 2;
@@ -618,7 +619,7 @@ __global__ void __launch_bounds__(256) k_conv3w(const GemmArgs g, const HeadArgs
 #pragma unroll
         for (int k = 0; k < NPF; ++k) {
             const int e = tid + k * 256;
-            if (e < PH * PW * 4)
+            if (e < PH * PW * 4 && !(K16 && (e & 3) >= 2))
 #pragma unroll
                 for (int c = UPC ? 1 : 0; c < KC; ++c) *(uint4 *)(patch + (e >> 2) * PXS + c * 64 + (e & 3) * 16) = fp[c][k];
         }
@@ -646,7 +647,7 @@ __global__ void __launch_bounds__(256) k_conv3w(const GemmArgs g, const HeadArgs
             for (int tap = 0; tap < 9; ++tap) {
                 const int dy = tap / 3, dx = tap - dy * 3;
 #pragma unroll
-                for (int kk = 0; kk < 2; ++kk) {
+                for (int kk = 0; kk < (K16 ? 1 : 2); ++kk) {
                     const int koff = (kk * 16 + 8 * lh) * 2;
                     const bf16x8 af = __builtin_bit_cast(bf16x8, *(const uint4 *)(wts + (c * 32 + lc) * C3_RS + tap * 64 + koff));
 #pragma unroll
@@ -1673,13 +1674,13 @@ hipError_t conv3_launch(const GemmArgs &g, hipStream_t s)
 // channels x 8-row patches for 32-channel outputs and for grids under 64 K
 // pixels (more blocks where there are few pixels), else 64 channels x
 // 16-row patches
-template <int TH, int KC, int EPI, bool POOL, bool UPC = false, bool HEAD = false>
+template <int TH, int KC, int EPI, bool POOL, bool UPC = false, bool HEAD = false, bool K16 = false>
 hipError_t conv3w_launch(const GemmArgs &g, hipStream_t s, const HeadArgs &h = HeadArgs{})
 {
     constexpr int lds = c3w_lds_bytes<TH, KC>();
     static_assert(lds <= 65536, "staged patches and weights must fit 64 KB");
-    static const int grid = std::max(8, resident_blocks(k_conv3w<TH, KC, EPI, POOL, UPC, HEAD>, lds) / 8 * 8);
-    hipLaunchKernelGGL((k_conv3w<TH, KC, EPI, POOL, UPC, HEAD>), dim3(grid), dim3(256), lds, s, g, h);
+    static const int grid = std::max(8, resident_blocks(k_conv3w<TH, KC, EPI, POOL, UPC, HEAD, K16>, lds) / 8 * 8);
+    hipLaunchKernelGGL((k_conv3w<TH, KC, EPI, POOL, UPC, HEAD, K16>), dim3(grid), dim3(256), lds, s, g, h);
     return hipGetLastError();
 }
 
@@ -1709,6 +1710,9 @@ hipError_t conv3(GemmArgs g, hipStream_t s, bool *pooled = nullptr, const HeadAr
                 return conv3w_launch<16, 1, EPI, false, false, true>(g, s, *head);
             }
         }
+        // an input of 16 channels or fewer (the stack): the zero half of the
+        // chunk is neither staged nor multiplied
+        if (g.k_src > 0 && g.k_src <= 16) return conv3w_launch<16, 1, EPI, false, false, false, true>(g, s);
         return conv3w_launch<16, 1, EPI, false>(g, s);
     }
     if (g.M == 32 && g.K == 64 && tiles8 >= 2048) return conv3w_launch<8, 2, EPI, false>(g, s);
