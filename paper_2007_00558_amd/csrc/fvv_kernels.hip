@@ -679,41 +679,38 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
         }
     };
     if (!scan_all) {
-        // The wave's entries are e = wave + TNW q.  They are read 64 at a time
-        // (one per lane) and the splat records of the next two entries are
-        // in flight while the current one is splatted, so the dependent
-        // loads of consecutive entries overlap instead of queueing.
-        const int32_t *lst = vd.list + (int64_t)tile * vd.tile_cap;
-        const int nq = n_entries > wave ? (n_entries - wave + TNW - 1) / TNW : 0;
-        int base = 0;
-        int ents = lane < nq ? lst[wave + TNW * lane] : 0;
-        auto entry = [&](int q) -> int {
-            if (q - base >= 64) {
-                base = q;
-                ents = q + lane < nq ? lst[wave + TNW * (q + lane)] : 0;
-            }
-            return __builtin_amdgcn_readlane(ents, q - base);
-        };
-        int e0 = 0, e1 = 0;
-        unsigned long long z0 = 0, z1 = 0;
+        // The wave's entries are e = wave + TNW q; the splat records of the
+        // next two entries are in flight while the current one is splatted,
+        // so the dependent loads of consecutive entries overlap instead of
+        // queueing.
+        // the list was written by the binning and is only read here: wave-
+        // uniform entries come through the scalar cache (constant address
+        // space), straight into scalar registers
+        const __attribute__((address_space(4))) int32_t *lst =
+            (const __attribute__((address_space(4))) int32_t *)(vd.list + (int64_t)tile * vd.tile_cap);
+        const int nq = __builtin_amdgcn_readfirstlane(n_entries > wave ? (n_entries - wave + TNW - 1) / TNW : 0);
+        auto entry = [&](int q) -> int { return lst[wave + TNW * q]; };
+        // Two records in flight, in two registers that alternate (the loop
+        // takes two entries per trip): a register is reloaded only after its
+        // record has been taken, so taking one waits for that load alone.
+        // Past the last entry the last record is loaded again (unused), so
+        // the loads need no branches.
         if (nq > 0) {
-            e0 = entry(0);
-            z0 = block_rec(e0);
-        }
-        if (nq > 1) {
-            e1 = entry(1);
-            z1 = block_rec(e1);
-        }
-        for (int q = 0; q < nq; ++q) {
-            const int ec = e0;
-            const unsigned long long zc = z0;
-            e0 = e1;
-            z0 = z1;
-            if (q + 2 < nq) {
-                e1 = entry(q + 2);
+            int e0 = entry(0), e1 = entry(min(1, nq - 1));
+            unsigned long long z0 = block_rec(e0), z1 = block_rec(e1);
+            for (int q = 0; q < nq; q += 2) {
+                const int ec0 = e0;
+                const unsigned long long zc0 = z0;
+                e0 = entry(min(q + 2, nq - 1));
+                z0 = block_rec(e0);
+                splat_entry(ec0, zc0);
+                if (q + 1 >= nq) break;
+                const int ec1 = e1;
+                const unsigned long long zc1 = z1;
+                e1 = entry(min(q + 3, nq - 1));
                 z1 = block_rec(e1);
+                splat_entry(ec1, zc1);
             }
-            splat_entry(ec, zc);
         }
     } else {
         // more entries than the list holds: test every block's tile range
