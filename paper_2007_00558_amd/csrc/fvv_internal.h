@@ -39,6 +39,7 @@ struct fvv_src_desc {
     int32_t cam;            // rig index (key bits 27..31)
     int32_t nbx;            // source blocks per row: ceil(W / FVV_SBLK)
     int32_t nblk;           // source blocks: nbx * ceil(H / FVV_SBLK)
+    uint64_t nbx_magic;     // ceil(2^40 / nbx): blk / nbx = (blk nbx_magic) >> 40 (blk < 2^24)
     float wgt;              // view weight, 1 / centre distance
     float A[9], a[3], B[9], b[3];
     float sx, sy;           // focal ratios virtual / source (footprint scale)

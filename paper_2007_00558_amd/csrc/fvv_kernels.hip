@@ -101,6 +101,15 @@ __device__ __forceinline__ float rcp_rn(float b)
     return u2f(f2u(y1) | ones);
 }
 
+// Row of source block blk (< 2^24; nbx <= 8192): with m = ceil(2^40 / nbx),
+// blk m / 2^40 exceeds blk / nbx by less than blk / 2^40 < 2^-16 <= 1 / nbx,
+// too little to reach the next integer, so its floor is the quotient: a
+// 64-bit multiply on the scalar unit instead of an integer division.
+__device__ __forceinline__ int block_row(int blk, const fvv_src_desc &s)
+{
+    return (int)(((uint64_t)(uint32_t)blk * s.nbx_magic) >> 40);
+}
+
 struct Footprint {
     int x0, x1, y0, y1;
     unsigned long long key;
@@ -296,7 +305,7 @@ __global__ void __launch_bounds__(256) k_bin(const fvv_view_desc *__restrict__ v
     int pi[FVV_BIN_BPW], pj[FVV_BIN_BPW];
 #pragma unroll
     for (int q = 0; q < FVV_BIN_BPW; ++q) {
-        const int by = (blk0 + q) / s.nbx, bx = blk0 + q - by * s.nbx;
+        const int by = block_row(blk0 + q, s), bx = blk0 + q - by * s.nbx;
         pi[q] = bx * FVV_SBLK + (lane & (FVV_SBLK - 1));
         pj[q] = by * FVV_SBLK + lane / FVV_SBLK;
         zb[q] = FVV_NO_DEPTH;
@@ -647,7 +656,7 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
         if (rz == FVV_NO_DEPTH) return;
         const fvv_src_desc &s = vd.src[ent >> 24];
         const int blk = ent & 0xFFFFFF;
-        const int by = blk / s.nbx, bx = blk - by * s.nbx;
+        const int by = block_row(blk, s), bx = blk - by * s.nbx;
         const int i = bx * FVV_SBLK + si, j = by * FVV_SBLK + sj;
         Footprint f;
         if (rf != FVV_SPL_RECOMPUTE) {

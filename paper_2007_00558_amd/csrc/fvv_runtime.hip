@@ -790,6 +790,7 @@ void fill_desc(fvv_ctx *c, fvv_view_desc &d, const fvv_camera &vc, const ViewLay
         sd.H = sc.height;
         sd.cam = L.idx[k];
         sd.nbx = (sc.width + FVV_SBLK - 1) / FVV_SBLK;
+        sd.nbx_magic = ((1ULL << 40) + (uint64_t)sd.nbx - 1) / (uint64_t)sd.nbx;
         sd.nblk = nblocks(sc);
         sd.wgt = (float)L.w[k];
         pair_dir(sc, vc, sd.A, sd.a);

@@ -159,3 +159,24 @@ def test_tx_cameras_bit_exact_vs_oracle(oracle_lib):
     assert L.fvv_tx_cameras(arr, 1, arr, 1, 0, C.byref(m)) == fvv.FVV_E_ARG
     assert L.fvv_tx_cameras(arr, 0, arr, 1, 1, C.byref(m)) == fvv.FVV_E_ARG
     assert L.fvv_tx_cameras(arr, 1, None, 0, 1, C.byref(m)) == 0 and m.value == 0
+
+
+def test_block_row_multiply_equals_division():
+    """The kernels find a source block's row as (blk * m) >> 40 with
+    m = ceil(2^40 / nbx) (the runtime's formula) instead of blk // nbx: exact
+    for every block index below 2^24 and every row length a source camera
+    can have (width <= 65535, so nbx <= 8192).  Checked here at the
+    quotient boundaries (q nbx - 1, q nbx), where a too-large multiplier
+    would first show, for every nbx and quotients spread over the range."""
+    import numpy as np
+    nbx = np.arange(1, 8193, dtype=np.uint64)
+    m = ((np.uint64(1) << np.uint64(40)) + nbx - np.uint64(1)) // nbx
+    rng = np.random.default_rng(7)
+    for _ in range(64):
+        q = (rng.random(nbx.shape) * ((1 << 24) // nbx.astype(np.float64))).astype(np.uint64)
+        for n in (q * nbx, q * nbx + nbx - np.uint64(1)):
+            ok = n < np.uint64(1 << 24)
+            got = (n * m) >> np.uint64(40)
+            assert np.array_equal(got[ok], (n // nbx)[ok])
+    top = np.uint64((1 << 24) - 1)
+    assert np.array_equal((top * m) >> np.uint64(40), top // nbx)
