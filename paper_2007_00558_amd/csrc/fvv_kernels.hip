@@ -653,8 +653,10 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
     auto splat_entry = [&](int ent, unsigned long long rec) {
         ent = __builtin_amdgcn_readfirstlane(ent);   // uniform; the pipeline's copies lose that
         const uint32_t rz = (uint32_t)rec, rf = (uint32_t)(rec >> 32);
-        if (rz == FVV_NO_DEPTH) return;
-        const fvv_src_desc &s = vd.src[ent >> 24];
+        // a point without depth (its record's footprint is 0) is dropped
+        // with the empty footprints below: one lane branch per entry, not two
+        const bool live = rz != FVV_NO_DEPTH;
+        const fvv_src_desc &s = vd.src[(uint32_t)ent >> 24];
         const int blk = ent & 0xFFFFFF;
         const int by = block_row(blk, s), bx = blk - by * s.nbx;
         const int i = bx * FVV_SBLK + si, j = by * FVV_SBLK + sj;
@@ -669,7 +671,7 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
         } else if (!splat_point(s, W, H, vd.max_fp, i, j, gptr(s.depth)[(uint32_t)(j * s.W + i)], f)) {
             return;
         }
-        const int xa = max(f.x0, WX0), xb = min(f.x1, WX0 + WN - 1);
+        const int xa = max(f.x0, WX0), xb = live ? min(f.x1, WX0 + WN - 1) : xa - 1;
         const int ya = max(f.y0, WY0), yb = min(f.y1, WY0 + WN - 1);
         unsigned long long *zl = (LAYERED && (ent >> 24) >= vd.K) ? zk + WN * WN : zk;
         if (xa > xb || ya > yb) return;
@@ -696,9 +698,9 @@ __device__ __forceinline__ void tile_body(const fvv_view_desc *__restrict__ view
         // uniform entries come through the scalar cache (constant address
         // space), straight into scalar registers
         const __attribute__((address_space(4))) int32_t *lst =
-            (const __attribute__((address_space(4))) int32_t *)(vd.list + (int64_t)tile * vd.tile_cap);
+            (const __attribute__((address_space(4))) int32_t *)(vd.list + (int64_t)tile * vd.tile_cap + wave);
         const int nq = __builtin_amdgcn_readfirstlane(n_entries > wave ? (n_entries - wave + TNW - 1) / TNW : 0);
-        auto entry = [&](int q) -> int { return lst[wave + TNW * q]; };
+        auto entry = [&](int q) -> int { return lst[(uint32_t)(TNW * q)]; };
         // Two records in flight, in two registers that alternate (the loop
         // takes two entries per trip): a register is reloaded only after its
         // record has been taken, so taking one waits for that load alone.
