@@ -1670,10 +1670,11 @@ hipError_t conv3_launch(const GemmArgs &g, hipStream_t s)
     return hipGetLastError();
 }
 
-// 3x3 convolution shapes (measured on the 960x544 network): 32 output
-// channels x 8-row patches for 32-channel outputs and for grids under 64 K
-// pixels (more blocks where there are few pixels), else 64 channels x
-// 16-row patches
+// 3x3 convolution shapes (measured on the 960x544 network): the
+// 32-output-channel layers of large grids with their weights resident
+// (16-row patches with one input chunk, 8-row ones with two); otherwise 32
+// output channels x 8-row patches for grids under 64 K pixels (more blocks
+// where there are few pixels), else 64 channels x 16-row patches
 template <int TH, int KC, int EPI, bool POOL, bool UPC = false, bool HEAD = false, bool K16 = false>
 hipError_t conv3w_launch(const GemmArgs &g, hipStream_t s, const HeadArgs &h = HeadArgs{})
 {
